@@ -1,0 +1,161 @@
+"""Sketched least squares and CP-ALS (STS-CP) in plain float64.
+
+* :class:`SparseTensor` -- COO tensor with duplicates summed; per mode the
+  entries are grouped into mode-``j`` fibers (all entries sharing the other
+  modes' indices), the rows of ``mat(T, j)^T`` that a sampled Khatri-Rao
+  row selects (Appendix A.9, matricisation; Appendix A.13, the sampled
+  spMTTKRP reduces to an SpMM).
+* :func:`normal_equations` / :func:`sketched_solve` -- one sampled solve of
+  ``min_X || S U_{!=j} X^T - S mat(T, j)^T ||_F`` with the sampling matrix
+  ``S`` of Section 2.1 (weights ``1/sqrt(J q_d)``), by the normal equations
+  ``U_j = Y M^+`` with ``M = (SA)^T SA`` and ``Y = (SB)^T SA``; then the
+  column norms become ``sigma`` and the columns are renormalised
+  (Algorithm 6, lines 6-8).
+* :func:`fit` -- ``1 - ||T~ - T||_F / ||T||_F`` (Section 4.3) through
+  ``||T~||^2 = sigma^T ((*)_k G_k) sigma`` and ``<T, T~>`` over the nonzeros.
+* :func:`cp_als` -- Algorithm 6 with the sampled solve.
+
+The solve method is not fixed by the paper; the reading used is the normal
+equations with a float64 eigen-pseudo-inverse (no regularisation).  A column
+of zero norm keeps ``sigma = 0`` and stays zero.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+from .definition import pinv_psd, hadamard_all
+from .sampler import KRPSampler
+
+__all__ = ["SparseTensor", "normal_equations", "sketched_solve", "fit",
+           "cp_als", "normalize_columns"]
+
+
+class SparseTensor:
+    def __init__(self, dims, idx, val):
+        self.dims = tuple(int(d) for d in dims)
+        self.N = len(self.dims)
+        self.idx = np.asarray(idx, dtype=np.int64)
+        self.val = np.asarray(val, dtype=np.float64)
+        self.nnz = self.val.shape[0]
+        self._fib = {}
+        # ||T||^2 of the tensor with duplicates summed
+        key = self._key(self.idx, list(range(self.N)))
+        uk, inv = np.unique(key, return_inverse=True)
+        summed = np.bincount(inv.reshape(-1), weights=self.val, minlength=len(uk))
+        self.norm2 = float(summed @ summed)
+
+    def _key(self, cols_idx, modes):
+        """Mixed-radix key of the columns ``modes`` (int64 when it fits,
+        else Python integers)."""
+        bits = sum(int(self.dims[m] - 1).bit_length() for m in modes)
+        if bits <= 62:
+            key = np.zeros(cols_idx.shape[0], dtype=np.int64)
+            for c, m in enumerate(modes):
+                key = key * self.dims[m] + cols_idx[:, c if cols_idx.shape[1] == len(modes) else m]
+            return key
+        key = np.zeros(cols_idx.shape[0], dtype=object)
+        for c, m in enumerate(modes):
+            col = cols_idx[:, c if cols_idx.shape[1] == len(modes) else m]
+            key = key * self.dims[m] + col.astype(object)
+        return key
+
+    def others(self, j):
+        return [k for k in range(self.N) if k != j]
+
+    def fibers(self, j):
+        """Entries sorted by the other modes' indices: ``(keys_sorted,
+        order)`` where ``order`` permutes the COO entries."""
+        if j not in self._fib:
+            oth = self.others(j)
+            key = self._key(self.idx[:, oth], oth)
+            order = np.argsort(key, kind="stable")
+            self._fib[j] = (key[order], order)
+        return self._fib[j]
+
+    def lookup(self, j, sample_idx):
+        """``[lo, hi)`` ranges (into the mode-``j`` sorted order) of the fiber
+        selected by each sampled multi-index ``sample_idx[J, N]``."""
+        oth = self.others(j)
+        keys, _ = self.fibers(j)
+        q = self._key(np.asarray(sample_idx)[:, oth], oth)
+        lo = np.searchsorted(keys, q, side="left")
+        hi = np.searchsorted(keys, q, side="right")
+        return lo, hi
+
+
+def normal_equations(tensor, j, idx, rows, w2):
+    """``M = sum_d w_d^2 a_d a_d^T`` and ``Y = sum_d w_d^2 b_d a_d^T`` where
+    ``b_d`` is the mode-``j`` fiber of sample ``d`` (a sparse ``I_j`` vector).
+    """
+    rows = np.asarray(rows, dtype=np.float64)
+    M = (rows * w2[:, None]).T @ rows
+    lo, hi = tensor.lookup(j, idx)
+    cnt = hi - lo
+    _, order = tensor.fibers(j)
+    sid = np.repeat(np.arange(len(cnt)), cnt)
+    starts = np.repeat(lo - np.concatenate(([0], np.cumsum(cnt)[:-1])), cnt)
+    ent = order[starts + np.arange(cnt.sum())]
+    ij = tensor.idx[ent, j]
+    coef = w2[sid] * tensor.val[ent]
+    Y = np.zeros((tensor.dims[j], rows.shape[1]))
+    for r in range(rows.shape[1]):
+        Y[:, r] = np.bincount(ij, weights=coef * rows[sid, r], minlength=tensor.dims[j])
+    return M, Y
+
+
+def normalize_columns(U):
+    """Column norms ``sigma`` and the renormalised copy (zero columns stay)."""
+    U = np.asarray(U, dtype=np.float64)
+    sigma = np.sqrt(np.einsum("ir,ir->r", U, U))
+    out = U.copy()
+    nz = sigma > 0
+    out[:, nz] /= sigma[nz]
+    return out, sigma
+
+
+def sketched_solve(sampler: KRPSampler, tensor: SparseTensor, j, u01):
+    """One STS-CP solve for mode ``j``; returns ``(U_j, sigma, draw, M, Y)``.
+
+    The sampler is refreshed with the new ``U_j`` (Algorithm 6 line 8 and
+    Theorem 1.1 part 1)."""
+    draw = sampler.draw(j, u01)
+    J = draw.prob.shape[0]
+    w2 = 1.0 / (J * draw.prob)
+    M, Y = normal_equations(tensor, j, draw.idx, draw.rows, w2)
+    Mp, _ = pinv_psd(M)
+    Unew, sigma = normalize_columns(Y @ Mp)
+    sampler.refresh(j, Unew)
+    return Unew, sigma, draw, M, Y
+
+
+def fit(tensor: SparseTensor, Us, sigma, chunk=1 << 20):
+    """``1 - ||T~ - T||_F / ||T||_F`` with ``T~ = [sigma; U_1..U_N]``."""
+    Us = [np.asarray(U, dtype=np.float64) for U in Us]
+    sigma = np.asarray(sigma, dtype=np.float64)
+    inner = 0.0
+    for s in range(0, tensor.nnz, chunk):
+        e = min(tensor.nnz, s + chunk)
+        p = np.ones((e - s, sigma.shape[0]))
+        for k, U in enumerate(Us):
+            p *= U[tensor.idx[s:e, k]]
+        inner += float(tensor.val[s:e] @ (p @ sigma))
+    G = hadamard_all([U.T @ U for U in Us])
+    model2 = float(sigma @ G @ sigma)
+    resid2 = max(0.0, tensor.norm2 + model2 - 2.0 * inner)
+    return 1.0 - np.sqrt(resid2) / np.sqrt(tensor.norm2)
+
+
+def cp_als(tensor: SparseTensor, U0, sweeps, u01_of, F=None):
+    """Algorithm 6 with the sampled solve.  ``U0``: initial factors (their
+    columns are normalised here, ``sigma = 1``); ``u01_of(sweep, j)`` gives
+    the uniforms of each solve.  Returns ``(Us, sigma, fits)`` with the fit
+    after every sweep."""
+    Us = [normalize_columns(U)[0] for U in U0]
+    sigma = np.ones(Us[0].shape[1])
+    sampler = KRPSampler(Us, F)
+    fits = []
+    for s in range(sweeps):
+        for j in range(tensor.N):
+            Us[j], sigma, _, _, _ = sketched_solve(sampler, tensor, j, u01_of(s, j))
+        fits.append(fit(tensor, Us, sigma))
+    return Us, sigma, fits
