@@ -1,0 +1,185 @@
+/*
+ * krps.h -- C ABI of libkrps: exact Khatri-Rao-product leverage-score
+ * sampling and sketched CP-ALS on one AMD Instinct MI355X (gfx950).
+ *
+ * The operations follow Bharadwaj et al., "Fast Exact Leverage Score
+ * Sampling from Khatri-Rao Products with Applications to Tensor
+ * Decomposition" (NeurIPS 2023):
+ *   - build a sampler over factors U_j in R^{I_j x R}             (Thm 1.1 part 1, Alg. 1)
+ *   - refresh it after a factor changed                            (Thm 1.1 part 1)
+ *   - draw J rows of U_1 (.) ... (.) U_N, optionally without one
+ *     factor, with probability proportional to their leverage      (Thm 1.1 part 2, Alg. 2)
+ *   - solve the sampled problem min ||S A X - S B||_F inside CP-ALS
+ *     on a sparse tensor                                           (Sec. 2.1, Sec. 3.3, Alg. 6)
+ *
+ * General conventions
+ *   - Every function returns a krps_status; KRPS_OK is 0, errors are
+ *     negative.  krps_last_error() gives a thread-local message for the
+ *     last failing call of the calling thread.  No C++ exception crosses
+ *     this boundary and nothing aborts.
+ *   - Pointers named U, uniforms, idx, prob, rows, ws, sigma, vals are
+ *     DEVICE pointers; arrays of sizes/dims are HOST pointers.  Every
+ *     device buffer is owned by the caller; the library keeps non-owning
+ *     references where stated and never frees them.
+ *   - All device memory the library needs beyond its inputs and outputs
+ *     comes from caller-provided workspaces (size queries below); the
+ *     library itself does not allocate device memory.
+ *   - All work is enqueued on the context's HIP stream and is asynchronous;
+ *     results are valid after the stream is synchronised.  Host-side
+ *     validation happens before anything is enqueued.
+ *   - Indices are 0-based int32 (I_j < 2^31).  Matrices are row-major.
+ *   - Limits: 1 <= N <= KRPS_MAX_MODES, 1 <= R <= KRPS_MAX_R.
+ */
+#ifndef KRPS_H
+#define KRPS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define KRPS_MAX_MODES 8
+#define KRPS_MAX_R 128
+
+typedef enum {
+  KRPS_OK = 0,
+  KRPS_EINVAL = -1,      /* bad shape, null pointer, index out of range, R outside [1,128] */
+  KRPS_EWORKSPACE = -2,  /* workspace smaller than the size query returned */
+  KRPS_EDEVICE = -3,     /* a HIP runtime call failed (message has the HIP error) */
+  KRPS_EZERO = -4,       /* the Khatri-Rao product is the zero matrix (C = 0, Sec. 3) */
+  KRPS_ENUMERIC = -5,    /* NaN/Inf met on the device */
+  KRPS_EUNSUPPORTED = -6 /* valid request this build does not implement */
+} krps_status;
+
+/* Arithmetic of the sampler.  Factor storage is float64 for KRPS_FP64 and
+ * float32 for the other two.  KRPS_BF16X2 computes the Gram builds as
+ * bf16 hi/lo split products on the matrix cores accumulated in float32;
+ * the tree walk then runs in float32 as in KRPS_FP32. */
+typedef enum { KRPS_FP64 = 0, KRPS_FP32 = 1, KRPS_BF16X2 = 2 } krps_precision;
+
+typedef struct krps_ctx_s* krps_ctx;
+typedef struct krps_sampler_s* krps_sampler;
+typedef struct krps_tensor_s* krps_tensor;
+
+/* ------------------------------------------------------------------ */
+/* Context                                                             */
+/* ------------------------------------------------------------------ */
+
+/* Creates a context on HIP device `device` that enqueues on `hip_stream`
+ * (a hipStream_t; NULL = the device's null stream).  The stream is not
+ * owned.  Does not initialise the GPU beyond selecting the device. */
+krps_status krps_ctx_create(int device, void* hip_stream, krps_ctx* out);
+krps_status krps_ctx_destroy(krps_ctx ctx);
+/* Synchronises the context stream and reports device-side errors. */
+krps_status krps_ctx_sync(krps_ctx ctx);
+/* Thread-local message of the last error (never NULL). */
+const char* krps_last_error(void);
+/* Library version string. */
+const char* krps_version(void);
+
+/* ------------------------------------------------------------------ */
+/* Sampler: Algorithm 1 (ConstructKRPSampler) and Theorem 1.1 part 1   */
+/* ------------------------------------------------------------------ */
+
+/* Bytes of persistent workspace for a sampler over N factors of heights
+ * I[0..N-1] and R columns with leaf size F (F = 0 picks R, the paper's
+ * choice for the factor trees Z_j, Sec. 3.2).  The workspace holds, per
+ * factor, the segment tree T_{I_j,F} of partial Gram matrices (root and
+ * left children, packed upper triangles, Appendix A.5) and G_j in float64. */
+krps_status krps_sampler_workspace_bytes(int N, const int64_t* I, int R, int F,
+                                         krps_precision p, size_t* bytes);
+
+/* Builds the sampler (Algorithm 1): for each j, Z_j = BuildSampler(U_j,
+ * F, [1]) (Algorithm 3) and G_j = U_j^T U_j.
+ *   U[j]   device pointer, row-major I[j] x R, float64 for KRPS_FP64 and
+ *          float32 otherwise.  NON-OWNING: the caller keeps every U[j]
+ *          alive and unmodified, or calls krps_sampler_refresh after
+ *          changing it.  krps_sketched_solve writes U[j] in place.
+ *   ws     device workspace of at least krps_sampler_workspace_bytes().
+ * The sampler handle is host memory owned by the library until
+ * krps_sampler_destroy. */
+krps_status krps_sampler_create(krps_ctx ctx, int N, const int64_t* I, int R, int F,
+                                void* const* U, krps_precision p, void* ws,
+                                size_t ws_bytes, krps_sampler* out);
+
+/* U[j] changed in place: rebuild Z_j and G_j (O(I_j R^2), Thm 1.1 part 1). */
+krps_status krps_sampler_refresh(krps_sampler s, int j);
+krps_status krps_sampler_destroy(krps_sampler s);
+
+/* ------------------------------------------------------------------ */
+/* Sampling: Algorithm 2 (KRPSample)                                   */
+/* ------------------------------------------------------------------ */
+
+/* Bytes of per-draw scratch for krps_sample / krps_row_prob: G^+, every
+ * G_{>k} with its eigendecomposition, and the eigen-trees E_k (O(N R^3)). */
+krps_status krps_sample_workspace_bytes(krps_sampler s, size_t* bytes);
+
+/* Draws J samples from the Khatri-Rao product of all factors
+ * (exclude = -1) or of all but factor `exclude` (Algorithm 2).
+ *   uniforms  device float64 [J][N][2] in (0,1): uniforms[d][k][0] drives
+ *             the eigen-component draw of mode k for sample d (Sec. 3.2,
+ *             first-stage distribution), [d][k][1] its row draw
+ *             (second-stage distribution).  Entries of the excluded mode
+ *             are ignored.
+ *   idx       device int32 [J][N] out: the sampled multi-index, -1 in the
+ *             excluded column.
+ *   prob      device float64 [J] out or NULL: q_d = l(a_d) / rank(A), the
+ *             probability of the sampled row (Sec. 2.1).
+ *   rows      device [J][R] out or NULL: the sampled Khatri-Rao rows
+ *             a_d = (*)_{k != exclude} U_k[idx[d][k]] in the factor
+ *             storage type.
+ *   ws        per-draw scratch (krps_sample_workspace_bytes).
+ * Returns KRPS_EZERO if the Khatri-Rao product is zero (detected on the
+ * device; reported by this call after a stream synchronisation only when
+ * `check` is nonzero, else at the next krps_ctx_sync). */
+krps_status krps_sample(krps_sampler s, int exclude, int64_t J, const double* uniforms,
+                        int32_t* idx, double* prob, void* rows, void* ws, size_t ws_bytes,
+                        int check);
+
+/* Probability q of M given multi-indices (idx [M][N], the excluded column
+ * is ignored) under the leverage distribution of the (excluded) product. */
+krps_status krps_row_prob(krps_sampler s, int exclude, int64_t M, const int32_t* idx,
+                          double* prob, void* ws, size_t ws_bytes);
+
+/* ------------------------------------------------------------------ */
+/* Introspection (tests and benchmarks)                                */
+/* ------------------------------------------------------------------ */
+
+typedef struct {
+  int64_t I;          /* rows of the factor */
+  int64_t L;          /* leaves, ceil(I / F) */
+  int32_t F;          /* leaf size */
+  int32_t D;          /* depth, ceil(log2 L) (0 for one leaf) */
+  int64_t n_nodes;    /* stored nodes: root + left children */
+  int64_t tri;        /* R (R + 1) / 2, elements per stored node */
+  void* nodes;        /* device: n_nodes x tri, packed upper triangle, row-major
+                         (entry (a, b), a <= b, at a*R - a*(a-1)/2 + b - a);
+                         node 0 is the root, then for level l = 1..D the left
+                         children in position order (position 2m stored at m) */
+  double* gram;       /* device: G_j = U_j^T U_j, R x R float64 */
+  int elem_bytes;     /* 8 (FP64) or 4 */
+} krps_tree_info;
+
+krps_status krps_sampler_tree_info(krps_sampler s, int j, krps_tree_info* out);
+
+/* Offsets (bytes into the per-draw workspace) of what krps_sample prepares
+ * for exclusion `exclude`; valid after a krps_sample / krps_row_prob call
+ * with that workspace. */
+typedef struct {
+  size_t gplus;       /* float64 R x R, G^+ of G = (*)_{k != exclude} G_k */
+  size_t rank;        /* int32, rank of G */
+  size_t ggt;         /* float64 [N][R][R]: G_{>k} */
+  size_t lam;         /* float64 [N][R]: eigenvalues of G_{>k}, ascending */
+  size_t vecs;        /* factor type [N][R][R]: eigenvector u of mode k at [k][u][:] */
+  size_t etree;       /* factor type [N][n_enodes][tri]: E_k trees, same layout as Z */
+  int64_t n_enodes;   /* stored nodes per E_k (F = 1, L = R) */
+} krps_draw_layout;
+
+krps_status krps_draw_layout_query(krps_sampler s, krps_draw_layout* out);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* KRPS_H */

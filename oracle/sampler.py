@@ -72,7 +72,7 @@ class SegmentTree:
         pad[: self.I] = U
         blocks = pad.reshape(L, F, R)
         levels = [None] * (D + 1)
-        levels[D] = np.einsum("lfa,lfb->lab", blocks, blocks)
+        levels[D] = np.matmul(blocks.transpose(0, 2, 1), blocks)
         # internal nodes, level by level from the one above the leaves
         for lev in range(D - 1, -1, -1):
             child = levels[lev + 1]
@@ -192,6 +192,10 @@ def _row_sample_chunk(tree, H, Y, dvec):
         low = np.where(go_left, low, cut)
     F = tree.F
     s0 = pos * F
+    if F == 1:
+        # a one-row leaf: the scan can only return that row, and its right
+        # edge is a boundary already compared above
+        return s0, margin
     offs = np.arange(F)
     ridx = s0[:, None] + offs[None, :]
     valid = ridx < tree.I
@@ -215,6 +219,10 @@ def _row_sample_chunk(tree, H, Y, dvec):
     return s0 + chosen, margin
 
 
+def _round(a, dtype):
+    return np.asarray(a).astype(dtype).astype(np.float64)
+
+
 class Draw:
     """Result of one ``KRPSample`` call."""
 
@@ -234,13 +242,22 @@ class KRPSampler:
 
     ``F`` is the leaf size of the factor trees ``Z_j`` (the paper uses
     ``F = R``; any positive ``F`` gives the same rows under the tie rule).
+
+    ``store`` (None or a NumPy float type) takes the integer decisions in a
+    storage precision: the cached partial Gram matrices, the eigen-tree
+    nodes ``P^v (*) G_k`` and the eigenvectors are rounded to ``store``
+    before the walks, while every operation stays float64.  With
+    ``np.float32`` this is the precision in which a float32-storage
+    implementation decides its indices, so both sides compare the same
+    decision.
     """
 
-    def __init__(self, Us, F=None):
+    def __init__(self, Us, F=None, store=None):
         self.U = [np.asarray(U, dtype=np.float64) for U in Us]
         self.N = len(self.U)
         self.R = self.U[0].shape[1]
         self.F = self.R if F is None else int(F)
+        self.store = store
         self.Z = [None] * self.N
         self.G = [None] * self.N
         for j in range(self.N):
@@ -252,6 +269,8 @@ class KRPSampler:
         if U is not None:
             self.U[j] = np.asarray(U, dtype=np.float64)
         self.Z[j] = SegmentTree(self.U[j], self.F)
+        if self.store is not None:
+            self.Z[j].levels = [_round(lv, self.store) for lv in self.Z[j].levels]
         self.G[j] = self.U[j].T @ self.U[j]
 
     def modes(self, exclude):
@@ -278,6 +297,11 @@ class KRPSampler:
             eig[k] = (lam, V)
             B = np.sqrt(lam)[:, None] * V.T          # rows sqrt(lam_u) V[:, u]^T
             E[k] = SegmentTree(B, 1)
+            if self.store is not None:
+                # node masses <h h^T, P^v, G_k> = h^T (P^v (*) G_k) h with the
+                # Hadamard product stored in the storage precision
+                E[k].levels = [_round(lv * self.G[k], self.store) for lv in E[k].levels]
+                E[k].folded = True
         return Gp, rank, eig, E, degenerate
 
     def draw(self, exclude, u01):
@@ -296,8 +320,10 @@ class KRPSampler:
         margin = np.full(J, np.inf)
         for k in modes:
             lam, V = eig[k]
-            u, m1 = row_sample_batch(E[k], h, self.G[k], u01[:, k, 0])
-            ht = h * V[:, u].T
+            folded = getattr(E[k], "folded", False)
+            u, m1 = row_sample_batch(E[k], h, None if folded else self.G[k], u01[:, k, 0])
+            Vs = V if self.store is None else _round(V, self.store)
+            ht = h * Vs[:, u].T
             t, m2 = row_sample_batch(self.Z[k], ht, None, u01[:, k, 1])
             h = h * self.U[k][t]
             idx[:, k] = t

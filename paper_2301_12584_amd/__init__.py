@@ -1,0 +1,233 @@
+"""Python binding of libkrps (exact Khatri-Rao leverage-score sampling and
+sketched CP-ALS on MI355X).
+
+Argument marshalling only: device memory comes from torch tensors, every
+computation runs in the library's HIP kernels.  Loading fails loudly when
+the compiled library is missing; there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libkrps.so")
+HEADER = os.path.join(os.path.dirname(HERE), "include", "krps.h")
+
+KRPS_OK = 0
+STATUS = {0: "KRPS_OK", -1: "KRPS_EINVAL", -2: "KRPS_EWORKSPACE", -3: "KRPS_EDEVICE",
+          -4: "KRPS_EZERO", -5: "KRPS_ENUMERIC", -6: "KRPS_EUNSUPPORTED"}
+PRECISION = {"fp64": 0, "fp32": 1, "bf16x2": 2}
+
+_lib = None
+
+
+class KrpsError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{STATUS.get(code, code)}: {msg}")
+        self.code = code
+
+
+class TreeInfo(ctypes.Structure):
+    _fields_ = [("I", ctypes.c_int64), ("L", ctypes.c_int64), ("F", ctypes.c_int32),
+                ("D", ctypes.c_int32), ("n_nodes", ctypes.c_int64), ("tri", ctypes.c_int64),
+                ("nodes", ctypes.c_void_p), ("gram", ctypes.c_void_p),
+                ("elem_bytes", ctypes.c_int)]
+
+
+class DrawLayout(ctypes.Structure):
+    _fields_ = [("gplus", ctypes.c_size_t), ("rank", ctypes.c_size_t), ("ggt", ctypes.c_size_t),
+                ("lam", ctypes.c_size_t), ("vecs", ctypes.c_size_t), ("etree", ctypes.c_size_t),
+                ("n_enodes", ctypes.c_int64)]
+
+
+def declared_symbols():
+    """Function names declared in include/krps.h."""
+    text = open(HEADER).read()
+    return sorted(set(re.findall(r"\b(krps_[a-z0-9_]+)\s*\(", text)))
+
+
+def lib():
+    """The loaded libkrps (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"libkrps.so not built ({LIB_PATH}); run __graft_entry__.build()")
+    L = ctypes.CDLL(LIB_PATH)
+    c = ctypes
+    P = c.c_void_p
+    sig = {
+        "krps_last_error": (c.c_char_p, []),
+        "krps_version": (c.c_char_p, []),
+        "krps_ctx_create": (c.c_int, [c.c_int, P, c.POINTER(P)]),
+        "krps_ctx_destroy": (c.c_int, [P]),
+        "krps_ctx_sync": (c.c_int, [P]),
+        "krps_sampler_workspace_bytes": (c.c_int, [c.c_int, c.POINTER(c.c_int64), c.c_int, c.c_int,
+                                                   c.c_int, c.POINTER(c.c_size_t)]),
+        "krps_sampler_create": (c.c_int, [P, c.c_int, c.POINTER(c.c_int64), c.c_int, c.c_int,
+                                          c.POINTER(P), c.c_int, P, c.c_size_t, c.POINTER(P)]),
+        "krps_sampler_refresh": (c.c_int, [P, c.c_int]),
+        "krps_sampler_destroy": (c.c_int, [P]),
+        "krps_sample_workspace_bytes": (c.c_int, [P, c.POINTER(c.c_size_t)]),
+        "krps_sample": (c.c_int, [P, c.c_int, c.c_int64, P, P, P, P, P, c.c_size_t, c.c_int]),
+        "krps_row_prob": (c.c_int, [P, c.c_int, c.c_int64, P, P, P, c.c_size_t]),
+        "krps_sampler_tree_info": (c.c_int, [P, c.c_int, c.POINTER(TreeInfo)]),
+        "krps_draw_layout_query": (c.c_int, [P, c.POINTER(DrawLayout)]),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(L, name)
+        f.restype = res
+        f.argtypes = args
+    _lib = L
+    return L
+
+
+def check(code):
+    if code != KRPS_OK:
+        raise KrpsError(code, lib().krps_last_error().decode())
+
+
+def _ptr(t):
+    return ctypes.c_void_p(0 if t is None else t.data_ptr())
+
+
+class Context:
+    """Device + HIP stream (torch's current stream unless given)."""
+
+    def __init__(self, device=0, stream=None):
+        import torch
+        self.torch = torch
+        self.device = torch.device("cuda", device)
+        if stream is None:
+            stream = torch.cuda.current_stream(self.device)
+        self.stream = stream
+        h = ctypes.c_void_p()
+        check(lib().krps_ctx_create(device, ctypes.c_void_p(stream.cuda_stream), ctypes.byref(h)))
+        self.handle = h
+
+    def sync(self):
+        check(lib().krps_ctx_sync(self.handle))
+
+    def __del__(self):
+        if getattr(self, "handle", None) is not None and _lib is not None:
+            _lib.krps_ctx_destroy(self.handle)
+            self.handle = None
+
+
+def sampler_workspace_bytes(dims, R, F=0, precision="fp32"):
+    n = len(dims)
+    arr = (ctypes.c_int64 * n)(*[int(d) for d in dims])
+    out = ctypes.c_size_t()
+    check(lib().krps_sampler_workspace_bytes(n, arr, int(R), int(F), PRECISION[precision],
+                                             ctypes.byref(out)))
+    return out.value
+
+
+class Sampler:
+    """Sampler over device factors (Algorithm 1).  ``factors``: list of
+    contiguous CUDA tensors ``[I_j, R]`` (float64 for ``fp64``, float32
+    otherwise).  The tensors are referenced, not copied."""
+
+    def __init__(self, ctx: Context, factors, precision="fp32", F=0):
+        torch = ctx.torch
+        self.ctx = ctx
+        self.precision = precision
+        self.factors = list(factors)
+        self.N = len(self.factors)
+        self.R = int(self.factors[0].shape[1])
+        self.dims = [int(U.shape[0]) for U in self.factors]
+        want = torch.float64 if precision == "fp64" else torch.float32
+        for U in self.factors:
+            if U.dtype != want or not U.is_contiguous() or U.device != ctx.device:
+                raise ValueError(f"factors must be contiguous {want} tensors on {ctx.device}")
+        nbytes = sampler_workspace_bytes(self.dims, self.R, F, precision)
+        self.ws = torch.empty(nbytes, dtype=torch.uint8, device=ctx.device)
+        arr = (ctypes.c_int64 * self.N)(*self.dims)
+        ptrs = (ctypes.c_void_p * self.N)(*[U.data_ptr() for U in self.factors])
+        h = ctypes.c_void_p()
+        check(lib().krps_sampler_create(ctx.handle, self.N, arr, self.R, int(F), ptrs,
+                                        PRECISION[precision], _ptr(self.ws), nbytes,
+                                        ctypes.byref(h)))
+        self.handle = h
+        sz = ctypes.c_size_t()
+        check(lib().krps_sample_workspace_bytes(self.handle, ctypes.byref(sz)))
+        self.draw_ws = torch.empty(sz.value, dtype=torch.uint8, device=ctx.device)
+
+    def refresh(self, j):
+        check(lib().krps_sampler_refresh(self.handle, int(j)))
+
+    def sample(self, exclude, uniforms, prob=True, rows=False, check_status=False):
+        """Draws ``J = uniforms.shape[0]`` samples; returns ``(idx, prob, rows)``."""
+        torch = self.ctx.torch
+        J = int(uniforms.shape[0])
+        dev = self.ctx.device
+        idx = torch.empty((J, self.N), dtype=torch.int32, device=dev)
+        p = torch.empty(J, dtype=torch.float64, device=dev) if prob else None
+        rdt = torch.float64 if self.precision == "fp64" else torch.float32
+        r = torch.empty((J, self.R), dtype=rdt, device=dev) if rows else None
+        check(lib().krps_sample(self.handle, int(exclude), J, _ptr(uniforms), _ptr(idx), _ptr(p),
+                                _ptr(r), _ptr(self.draw_ws), self.draw_ws.numel(),
+                                1 if check_status else 0))
+        return idx, p, r
+
+    def row_prob(self, exclude, idx):
+        torch = self.ctx.torch
+        M = int(idx.shape[0])
+        p = torch.empty(M, dtype=torch.float64, device=self.ctx.device)
+        check(lib().krps_row_prob(self.handle, int(exclude), M, _ptr(idx), _ptr(p),
+                                  _ptr(self.draw_ws), self.draw_ws.numel()))
+        return p
+
+    def tree_info(self, j):
+        ti = TreeInfo()
+        check(lib().krps_sampler_tree_info(self.handle, int(j), ctypes.byref(ti)))
+        return ti
+
+    def tree_nodes(self, j):
+        """Copy of the stored nodes of factor tree ``j`` as ``[n_nodes, tri]``."""
+        torch = self.ctx.torch
+        ti = self.tree_info(j)
+        off = ti.nodes - self.ws.data_ptr()
+        n = ti.n_nodes * ti.tri * ti.elem_bytes
+        dt = torch.float64 if ti.elem_bytes == 8 else torch.float32
+        return self.ws[off:off + n].view(dt).view(ti.n_nodes, ti.tri).clone()
+
+    def gram(self, j):
+        torch = self.ctx.torch
+        ti = self.tree_info(j)
+        off = ti.gram - self.ws.data_ptr()
+        return self.ws[off:off + self.R * self.R * 8].view(torch.float64).view(self.R, self.R).clone()
+
+    def draw_layout(self):
+        dl = DrawLayout()
+        check(lib().krps_draw_layout_query(self.handle, ctypes.byref(dl)))
+        return dl
+
+    def draw_parts(self):
+        """Views of what the last sample()/row_prob() prepared."""
+        torch = self.ctx.torch
+        dl = self.draw_layout()
+        R, N = self.R, self.N
+        ws = self.draw_ws
+        tri = R * (R + 1) // 2
+        es = 8 if self.precision == "fp64" else 4
+        dt = torch.float64 if es == 8 else torch.float32
+
+        def view(off, n, dtype, nb):
+            return ws[off:off + n * nb].view(dtype)
+
+        return {
+            "gplus": view(dl.gplus, R * R, torch.float64, 8).view(R, R).clone(),
+            "rank": int(view(dl.rank, 1, torch.int32, 4).item()),
+            "ggt": view(dl.ggt, N * R * R, torch.float64, 8).view(N, R, R).clone(),
+            "lam": view(dl.lam, N * R, torch.float64, 8).view(N, R).clone(),
+            "vecs": view(dl.vecs, N * R * R, dt, es).view(N, R, R).clone(),
+            "etree": view(dl.etree, N * dl.n_enodes * tri, dt, es).view(N, dl.n_enodes, tri).clone(),
+        }
+
+    def __del__(self):
+        if getattr(self, "handle", None) is not None and _lib is not None:
+            _lib.krps_sampler_destroy(self.handle)
+            self.handle = None

@@ -1,0 +1,107 @@
+// Internal declarations shared by the libkrps translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <string>
+
+#include "../../include/krps.h"
+
+namespace krps {
+
+// ---------------------------------------------------------------- errors
+void set_error(const std::string& msg);
+krps_status fail(krps_status st, const std::string& msg);
+krps_status hip_fail(hipError_t e, const char* what);
+
+#define KRPS_HIP(call)                                   \
+  do {                                                   \
+    hipError_t e_ = (call);                              \
+    if (e_ != hipSuccess) return ::krps::hip_fail(e_, #call); \
+  } while (0)
+
+// ---------------------------------------------------------------- layout
+inline int64_t tri(int R) { return (int64_t)R * (R + 1) / 2; }
+inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
+inline int ceil_log2(int64_t x) {
+  int d = 0;
+  while ((int64_t(1) << d) < x) ++d;
+  return d;
+}
+inline size_t align_up(size_t x, size_t a = 256) { return (x + a - 1) / a * a; }
+
+// Segment tree T_{I,F}: L leaves padded to 2^D; nodes stored: the root,
+// then for each level l = 1..D the left children of the real nodes.
+// real(l) = ceil(L / 2^(D-l)); stored left children at level l:
+// ceil(L / 2^(D-l+1)).
+struct TreeShape {
+  int64_t I = 0, L = 0;
+  int F = 0, D = 0;
+  int64_t n_nodes = 0;
+  void init(int64_t I_, int F_) {
+    I = I_;
+    F = F_;
+    L = ceil_div(I, F);
+    D = L > 1 ? ceil_log2(L) : 0;
+    n_nodes = 1;
+    for (int l = 1; l <= D; ++l) n_nodes += ((L - 1) >> (D - l + 1)) + 1;
+  }
+};
+
+// Per-mode descriptor read by the descent kernel.
+struct ModeDesc {
+  const void* U;      // factor, row-major I x R
+  const void* Z;      // factor tree nodes
+  const void* E;      // eigen tree nodes (per draw)
+  const void* V;      // eigenvectors, [u][R] (per draw)
+  int64_t I, L;
+  int32_t F, D;
+  int32_t DE, pad;
+};
+
+struct DescentArgs {
+  ModeDesc mode[KRPS_MAX_MODES];
+  int N, R, exclude, nsteps;      // nsteps: number of drawn modes
+  int order[KRPS_MAX_MODES];      // drawn modes in increasing order
+  int64_t J;
+  const double* u01;              // [J][N][2]
+  int32_t* idx;                   // [J][N]
+  double* prob;                   // [J] or null
+  void* rows;                     // [J][R] or null
+  const double* gplus;            // packed upper G^+ (tri) float64
+  const int32_t* rank;            // device rank of G
+  double* wout;                   // [J] sampling weights 1/sqrt(J q) or null
+  int scale_rows;                 // rows <- a_d / sqrt(J q_d)
+  int32_t* status;                // device status word
+};
+
+// Status word bits set by kernels.
+enum : int32_t { ST_ZERO = 1, ST_NUMERIC = 2 };
+
+// ------------------------------------------------------------- launchers
+// tree_build.hip
+size_t tree_build_scratch_bytes(int64_t L, int R);
+hipError_t launch_tree_build(hipStream_t st, krps_precision p, const void* U, int64_t I, int R,
+                             const TreeShape& ts, void* nodes, double* gram_full,
+                             double* scratch, size_t scratch_bytes);
+
+// eig.hip
+size_t prep_lds_bytes(int R);
+// G = (*) mats[0..nmat-1] -> G^+ (full, and packed if non-null), rank;
+// for nsteps > 0 also G_{>k} for the drawn modes order[0..nsteps-1] (host array)
+// (mats must then be those modes' Grams in the same order).
+hipError_t launch_prep_gplus2(hipStream_t st, int R, int nmat, const double* const* mats,
+                              int nsteps, const int* order, double* gplus_full,
+                              double* gplus_packed, int32_t* rank, double* ggt, int32_t* status);
+hipError_t launch_prep_eig2(hipStream_t st, krps_precision p, int R, int nsteps,
+                            const double* const* Gsteps, const int* order, const double* ggt,
+                            double* lam, void* vecs, void* etree, int64_t enodes);
+hipError_t launch_pinv(hipStream_t st, int R, const double* M, double* Mp_full, int32_t* rank);
+
+// descent.hip
+hipError_t launch_descent(hipStream_t st, krps_precision p, const DescentArgs& a);
+hipError_t launch_row_prob(hipStream_t st, krps_precision p, const DescentArgs& a);
+
+}  // namespace krps

@@ -1,0 +1,296 @@
+// Segment-tree construction on the matrix cores (BuildSampler, Appendix A.5
+// Algorithm 3): leaf partial Gram matrices G^v = U[S(v)]^T U[S(v)] and the
+// level-by-level sums G^v = G^{L(v)} + G^{R(v)} up to the root G = U^T U.
+//
+// Storage (space halving of Appendix A.5): the root and the left children
+// only, each as a packed upper triangle.  Pad leaves (the tree is padded to
+// 2^D leaves) are implicit zeros and never stored.
+//
+// Kernel 1 (leaf_run_kernel): a team of TW waves owns a run of 2^s
+// consecutive leaves.  Each leaf's Gram is a SYRK on the matrix cores; the
+// upper-triangle 16x16 tiles are split across the team's waves.  The run's
+// subtree is summed in registers with a binary counter (leaf u of the run
+// merges with the saved left siblings of its trailing one-bits), left
+// children are written as they complete, and the run root goes to a float64
+// scratch array.
+// Kernel 2 (node_upsweep_kernel): the levels above the runs, one thread per
+// packed entry, the same binary counter over groups of 2^s2 nodes in float64,
+// down to the root (also written as the full float64 R x R Gram G_j).
+#include "device_common.h"
+#include "krps_internal.h"
+
+namespace krps {
+
+namespace {
+
+enum { M_F64 = 0, M_F32 = 1, M_SPLIT = 2 };
+
+__device__ __forceinline__ f64x4 mfma_f64(double a, double b, f64x4 c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+__device__ __forceinline__ f32x4 mfma_bf16(bf16x8 a, bf16x8 b, f32x4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+}
+
+// Writes the 16x16 accumulator tile (ta, tb) of one node.  Column l%16 of
+// the tile is in lane l; the row of register i is 4*(l/16)+i for the
+// float32-accumulating instructions and 4*i+l/16 for the float64 one.
+template <typename OUT, typename ACC>
+__device__ __forceinline__ void write_tile(OUT* dst, const ACC& v, int ta, int tb, int R,
+                                           int lane) {
+  constexpr bool F64 = std::is_same_v<ACC, f64x4>;
+  const int b = 16 * tb + (lane & 15);
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int a = 16 * ta + (F64 ? 4 * i + (lane >> 4) : 4 * (lane >> 4) + i);
+    if (a < R && b < R && a <= b) dst[packed_index(a, b, R)] = (OUT)v[i];
+  }
+}
+
+template <int MODE, int NT, int TW, int S>
+__global__ __launch_bounds__(64 * TW) void leaf_run_kernel(const void* __restrict__ Uv, int64_t I,
+                                                           int R, int F, int64_t L, int D,
+                                                           int s_eff, void* __restrict__ nodes_v,
+                                                           double* __restrict__ tops) {
+  // storage type of the factor and the nodes; float64 accumulation on the
+  // matrix cores except for the bf16 split
+  using T = std::conditional_t<MODE == M_F64, double, float>;
+  using ACC = std::conditional_t<MODE == M_SPLIT, f32x4, f64x4>;
+  constexpr int NPAIRS = NT * (NT + 1) / 2;
+  constexpr int NPW = (NPAIRS + TW - 1) / TW;
+  const T* __restrict__ U = (const T*)Uv;
+  T* __restrict__ nodes = (T*)nodes_v;
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int64_t TR = (int64_t)R * (R + 1) / 2;
+  const int64_t run = blockIdx.x;
+  const int nrun = 1 << s_eff;
+
+  ACC node[NPW];
+  ACC stack[S > 0 ? S : 1][NPW];
+
+  for (int u = 0; u < nrun; ++u) {
+    const int64_t c = (run << s_eff) + u;
+#pragma unroll
+    for (int q = 0; q < NPW; ++q) node[q] = ACC{0, 0, 0, 0};
+    if (c < L) {
+      const int64_t r0 = c * F;
+      const int64_t r1 = r0 + F < I ? r0 + F : I;
+      if constexpr (MODE != M_SPLIT) {
+        for (int64_t rb = r0; rb < r1; rb += 4) {
+          const int64_t row = rb + (lane >> 4);
+          const bool rv = row < r1;
+          double vals[NT];
+          static_for<0, NT>([&](auto tt) {
+            constexpr int t = decltype(tt)::value;
+            const int col = 16 * t + (lane & 15);
+            vals[t] = (rv && col < R) ? (double)U[row * R + col] : 0.0;
+          });
+          static_for<0, NPAIRS>([&](auto pp) {
+            constexpr int pr = decltype(pp)::value;
+            constexpr int ta = pair_ta(NT, pr);
+            constexpr int tb = pair_tb(NT, pr);
+            if (pr % TW == wave) node[pr / TW] = mfma_f64(vals[ta], vals[tb], node[pr / TW]);
+          });
+        }
+      } else {
+        for (int64_t rb = r0; rb < r1; rb += 32) {
+          bf16x8 hi[NT], lo[NT];
+          static_for<0, NT>([&](auto tt) {
+            constexpr int t = decltype(tt)::value;
+            const int col = 16 * t + (lane & 15);
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+              const int64_t row = rb + 8 * (lane >> 4) + j;
+              const float x = (row < r1 && col < R) ? U[row * R + col] : 0.f;
+              const __bf16 h = (__bf16)x;
+              hi[t][j] = h;
+              lo[t][j] = (__bf16)(x - (float)h);
+            }
+          });
+          static_for<0, NPAIRS>([&](auto pp) {
+            constexpr int pr = decltype(pp)::value;
+            constexpr int ta = pair_ta(NT, pr);
+            constexpr int tb = pair_tb(NT, pr);
+            if (pr % TW == wave) {
+              ACC a = node[pr / TW];
+              a = mfma_bf16(hi[ta], hi[tb], a);
+              a = mfma_bf16(hi[ta], lo[tb], a);
+              a = mfma_bf16(lo[ta], hi[tb], a);
+              node[pr / TW] = a;
+            }
+          });
+        }
+      }
+    }
+    // binary counter: merge with the saved left siblings
+    int t = __builtin_ctz(~(unsigned)u);
+    if (t > s_eff) t = s_eff;
+    static_for<0, S>([&](auto mm) {
+      constexpr int m = decltype(mm)::value;
+      if (m < t) {
+#pragma unroll
+        for (int q = 0; q < NPW; ++q) node[q] += stack[m][q];
+      }
+    });
+    const int lev = D - t;
+    const int64_t pos = c >> t;
+    if (t == s_eff) {
+      double* dst = tops + run * TR;
+      static_for<0, NPAIRS>([&](auto pp) {
+        constexpr int pr = decltype(pp)::value;
+        if (pr % TW == wave) write_tile(dst, node[pr / TW], pair_ta(NT, pr), pair_tb(NT, pr), R, lane);
+      });
+    } else {
+      if (nodes != nullptr && pos < ((L - 1) >> (D - lev)) + 1) {
+        T* dst = nodes + (level_offset(L, D, lev) + (pos >> 1)) * TR;
+        static_for<0, NPAIRS>([&](auto pp) {
+          constexpr int pr = decltype(pp)::value;
+          if (pr % TW == wave) write_tile(dst, node[pr / TW], pair_ta(NT, pr), pair_tb(NT, pr), R, lane);
+        });
+      }
+      static_for<0, S>([&](auto mm) {
+        constexpr int m = decltype(mm)::value;
+        if (m == t) {
+#pragma unroll
+          for (int q = 0; q < NPW; ++q) stack[m][q] = node[q];
+        }
+      });
+    }
+  }
+}
+
+__device__ __forceinline__ void unpack_index(int64_t p, int R, int& a, int& b) {
+  const double q = (double)(2 * R + 1);
+  int aa = (int)((q - sqrt(q * q - 8.0 * (double)p)) * 0.5);
+  if (aa < 0) aa = 0;
+  if (aa > R - 1) aa = R - 1;
+  while (aa > 0 && packed_index(aa, aa, R) > p) --aa;
+  while (aa < R - 1 && packed_index(aa + 1, aa + 1, R) <= p) ++aa;
+  a = aa;
+  b = aa + (int)(p - packed_index(aa, aa, R));
+}
+
+constexpr int S2MAX = 6;
+
+template <typename T>
+__global__ __launch_bounds__(256) void node_upsweep_kernel(const double* __restrict__ in,
+                                                           int64_t n_in, int lev_in, int s2, int R,
+                                                           int64_t L, int D, T* __restrict__ nodes,
+                                                           double* __restrict__ out,
+                                                           double* __restrict__ gram_full) {
+  const int64_t TR = (int64_t)R * (R + 1) / 2;
+  const int64_t g = blockIdx.x;
+  for (int64_t p = threadIdx.x; p < TR; p += blockDim.x) {
+    double stack[S2MAX];
+    for (int u = 0; u < (1 << s2); ++u) {
+      int64_t pos = (g << s2) + u;
+      double v = pos < n_in ? in[pos * TR + p] : 0.0;
+      int t = __builtin_ctz(~(unsigned)u);
+      if (t > s2) t = s2;
+      for (int m = 0; m < t; ++m) v += stack[m];
+      const int lev = lev_in - t;
+      pos >>= t;
+      if (t == s2) {
+        if (lev == 0) {
+          if (nodes != nullptr) nodes[p] = (T)v;
+          int a, b;
+          unpack_index(p, R, a, b);
+          gram_full[(int64_t)a * R + b] = v;
+          gram_full[(int64_t)b * R + a] = v;
+        } else {
+          out[g * TR + p] = v;
+        }
+      } else {
+        if (nodes != nullptr && pos < ((L - 1) >> (D - lev)) + 1)
+          nodes[(level_offset(L, D, lev) + (pos >> 1)) * TR + p] = (T)v;
+        stack[t] = v;
+      }
+    }
+  }
+}
+
+struct LeafCfg {
+  int NT, TW, S;
+};
+
+template <int MODE, int NT, int TW, int S>
+hipError_t run_leaf(hipStream_t st, const void* U, int64_t I, int R, int F, int64_t L, int D,
+                    void* nodes, double* tops, int& s_eff) {
+  s_eff = S < D ? S : D;
+  const int64_t nrun = ceil_div(L, int64_t(1) << s_eff);
+  hipLaunchKernelGGL((leaf_run_kernel<MODE, NT, TW, S>), dim3((unsigned)nrun), dim3(64 * TW), 0,
+                     st, U, I, R, F, L, D, s_eff, nodes, tops);
+  return hipGetLastError();
+}
+
+// Team shape and register-run depth per precision and tile count.
+template <int MODE>
+hipError_t dispatch_leaf(hipStream_t st, const void* U, int64_t I, int R, int F, int64_t L, int D,
+                         void* nodes, double* tops, int& s_eff) {
+  if constexpr (MODE == M_SPLIT) {
+    if (R <= 16) return run_leaf<MODE, 1, 1, 4>(st, U, I, R, F, L, D, nodes, tops, s_eff);
+    if (R <= 32) return run_leaf<MODE, 2, 1, 4>(st, U, I, R, F, L, D, nodes, tops, s_eff);
+    if (R <= 64) return run_leaf<MODE, 4, 2, 3>(st, U, I, R, F, L, D, nodes, tops, s_eff);
+    return run_leaf<MODE, 8, 4, 2>(st, U, I, R, F, L, D, nodes, tops, s_eff);
+  } else {
+    if (R <= 16) return run_leaf<MODE, 1, 1, 3>(st, U, I, R, F, L, D, nodes, tops, s_eff);
+    if (R <= 32) return run_leaf<MODE, 2, 1, 3>(st, U, I, R, F, L, D, nodes, tops, s_eff);
+    if (R <= 64) return run_leaf<MODE, 4, 4, 2>(st, U, I, R, F, L, D, nodes, tops, s_eff);
+    return run_leaf<MODE, 8, 8, 2>(st, U, I, R, F, L, D, nodes, tops, s_eff);
+  }
+}
+
+constexpr int MIN_S = 2;  // smallest register-run depth used above
+
+}  // namespace
+
+size_t tree_build_scratch_bytes(int64_t L, int R) {
+  const int64_t a = ceil_div(L, int64_t(1) << MIN_S);
+  const int64_t b = ceil_div(a, 2);
+  return align_up((size_t)a * tri(R) * 8) + align_up((size_t)b * tri(R) * 8);
+}
+
+hipError_t launch_tree_build(hipStream_t st, krps_precision p, const void* U, int64_t I, int R,
+                             const TreeShape& ts, void* nodes, double* gram_full, double* scratch,
+                             size_t scratch_bytes) {
+  const int64_t TR = tri(R);
+  const int64_t a_nodes = ceil_div(ts.L, int64_t(1) << MIN_S);
+  double* bufA = scratch;
+  double* bufB = (double*)((char*)scratch + align_up((size_t)a_nodes * TR * 8));
+  if (scratch_bytes < tree_build_scratch_bytes(ts.L, R)) return hipErrorInvalidValue;
+  int s_eff = 0;
+  hipError_t e;
+  if (p == KRPS_FP64)
+    e = dispatch_leaf<M_F64>(st, U, I, R, ts.F, ts.L, ts.D, nodes, bufA, s_eff);
+  else if (p == KRPS_FP32)
+    e = dispatch_leaf<M_F32>(st, U, I, R, ts.F, ts.L, ts.D, nodes, bufA, s_eff);
+  else
+    e = dispatch_leaf<M_SPLIT>(st, U, I, R, ts.F, ts.L, ts.D, nodes, bufA, s_eff);
+  if (e != hipSuccess) return e;
+  int lev = ts.D - s_eff;
+  int64_t n = ceil_div(ts.L, int64_t(1) << s_eff);
+  double* cur = bufA;
+  double* nxt = bufB;
+  for (;;) {
+    const int s2 = lev < S2MAX ? lev : S2MAX;
+    const int64_t ng = ceil_div(n, int64_t(1) << s2);
+    if (p == KRPS_FP64)
+      hipLaunchKernelGGL(node_upsweep_kernel<double>, dim3((unsigned)ng), dim3(256), 0, st, cur, n,
+                         lev, s2, R, ts.L, ts.D, (double*)nodes, nxt, gram_full);
+    else
+      hipLaunchKernelGGL(node_upsweep_kernel<float>, dim3((unsigned)ng), dim3(256), 0, st, cur, n,
+                         lev, s2, R, ts.L, ts.D, (float*)nodes, nxt, gram_full);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    if (lev - s2 == 0) break;
+    lev -= s2;
+    n = ng;
+    double* tmp = cur;
+    cur = nxt;
+    nxt = tmp;
+  }
+  return hipSuccess;
+}
+
+}  // namespace krps

@@ -236,3 +236,15 @@ def test_two_stage_draw_equals_bruteforce_inversion(exclude):
     u = synth.uniforms(500, 3, 61 + exclude)
     assert check_two_stage_vs_bruteforce(smp.KRPSampler(Us), Us, exclude, u) == 0.0
     assert check_two_stage_vs_bruteforce(smp.KRPSampler(Us, F=2), Us, exclude, u) == 0.0
+
+
+def test_storage_precision_changes_only_near_boundary_draws():
+    # rounding the cached nodes to float32 may move only draws whose uniform
+    # sits near a bucket edge; probabilities of the drawn rows are unchanged
+    Us = synth.gaussian_factors((300, 200, 100), 16, seed=70, heavy_rows_frac=0.01)
+    u = synth.uniforms(3000, 3, 71)
+    a = smp.KRPSampler(Us).draw(0, u)
+    b = smp.KRPSampler(Us, store=np.float32).draw(0, u)
+    same = (a.idx == b.idx).all(axis=1)
+    assert np.all(same | (a.margin < 1e-5))
+    np.testing.assert_allclose(b.prob[same], a.prob[same], rtol=1e-12)
