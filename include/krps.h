@@ -54,9 +54,11 @@ typedef enum {
 } krps_status;
 
 /* Arithmetic of the sampler.  Factor storage is float64 for KRPS_FP64 and
- * float32 for the other two.  KRPS_BF16X2 computes the Gram builds as
- * bf16 hi/lo split products on the matrix cores accumulated in float32;
- * the tree walk then runs in float32 as in KRPS_FP32. */
+ * float32 for the other two.  KRPS_FP32 builds the Gram matrices with
+ * float64 matrix-core products and stores them rounded to float32;
+ * KRPS_BF16X2 builds them as bf16 hi/lo split products accumulated in
+ * float32.  In every precision the walk's arithmetic (node masses, the
+ * running offsets, probabilities) is float64 over the stored values. */
 typedef enum { KRPS_FP64 = 0, KRPS_FP32 = 1, KRPS_BF16X2 = 2 } krps_precision;
 
 typedef struct krps_ctx_s* krps_ctx;
@@ -138,6 +140,16 @@ krps_status krps_sample(krps_sampler s, int exclude, int64_t J, const double* un
                         int32_t* idx, double* prob, void* rows, void* ws, size_t ws_bytes,
                         int check);
 
+/* The two halves of krps_sample, for callers that reuse one preparation or
+ * time the walk alone.  krps_sample_prepare enqueues lines 1-5 of
+ * Algorithm 2 (G^+, the G_{>k}, their eigendecompositions and the eigen-
+ * trees E_k) into ws for exclusion `exclude`; krps_sample_draw enqueues the
+ * walk of lines 6-12 and must be given the same ws and exclude after a
+ * prepare (KRPS_EINVAL otherwise).  Arguments as for krps_sample. */
+krps_status krps_sample_prepare(krps_sampler s, int exclude, void* ws, size_t ws_bytes);
+krps_status krps_sample_draw(krps_sampler s, int exclude, int64_t J, const double* uniforms,
+                             int32_t* idx, double* prob, void* rows, void* ws, size_t ws_bytes);
+
 /* Probability q of M given multi-indices (idx [M][N], the excluded column
  * is ignored) under the leverage distribution of the (excluded) product. */
 krps_status krps_row_prob(krps_sampler s, int exclude, int64_t M, const int32_t* idx,
@@ -169,7 +181,8 @@ krps_status krps_sampler_tree_info(krps_sampler s, int j, krps_tree_info* out);
  * with that workspace. */
 typedef struct {
   size_t gplus;       /* float64 R x R, G^+ of G = (*)_{k != exclude} G_k */
-  size_t rank;        /* int32, rank of G */
+  size_t rank;        /* int32 [2 + N]: rank of G, then the Jacobi sweep count of
+                         G and of each drawn mode's G_{>k} (diagnostics) */
   size_t ggt;         /* float64 [N][R][R]: G_{>k} */
   size_t lam;         /* float64 [N][R]: eigenvalues of G_{>k}, ascending */
   size_t vecs;        /* factor type [N][R][R]: eigenvector u of mode k at [k][u][:] */

@@ -72,6 +72,8 @@ def lib():
         "krps_sampler_destroy": (c.c_int, [P]),
         "krps_sample_workspace_bytes": (c.c_int, [P, c.POINTER(c.c_size_t)]),
         "krps_sample": (c.c_int, [P, c.c_int, c.c_int64, P, P, P, P, P, c.c_size_t, c.c_int]),
+        "krps_sample_prepare": (c.c_int, [P, c.c_int, P, c.c_size_t]),
+        "krps_sample_draw": (c.c_int, [P, c.c_int, c.c_int64, P, P, P, P, P, c.c_size_t]),
         "krps_row_prob": (c.c_int, [P, c.c_int, c.c_int64, P, P, P, c.c_size_t]),
         "krps_sampler_tree_info": (c.c_int, [P, c.c_int, c.POINTER(TreeInfo)]),
         "krps_draw_layout_query": (c.c_int, [P, c.POINTER(DrawLayout)]),
@@ -172,6 +174,19 @@ class Sampler:
                                 1 if check_status else 0))
         return idx, p, r
 
+    def prepare(self, exclude):
+        """Lines 1-5 of Algorithm 2 for ``exclude`` into this sampler's draw
+        workspace."""
+        check(lib().krps_sample_prepare(self.handle, int(exclude), _ptr(self.draw_ws),
+                                        self.draw_ws.numel()))
+
+    def draw(self, exclude, uniforms, idx, prob=None, rows=None):
+        """The walk alone (after :meth:`prepare` with the same ``exclude``),
+        into caller-provided output tensors."""
+        check(lib().krps_sample_draw(self.handle, int(exclude), int(uniforms.shape[0]),
+                                     _ptr(uniforms), _ptr(idx), _ptr(prob), _ptr(rows),
+                                     _ptr(self.draw_ws), self.draw_ws.numel()))
+
     def row_prob(self, exclude, idx):
         torch = self.ctx.torch
         M = int(idx.shape[0])
@@ -221,6 +236,7 @@ class Sampler:
         return {
             "gplus": view(dl.gplus, R * R, torch.float64, 8).view(R, R).clone(),
             "rank": int(view(dl.rank, 1, torch.int32, 4).item()),
+            "sweeps": view(dl.rank, 2 + N, torch.int32, 4).cpu().numpy()[1:].tolist(),
             "ggt": view(dl.ggt, N * R * R, torch.float64, 8).view(N, R, R).clone(),
             "lam": view(dl.lam, N * R, torch.float64, 8).view(N, R).clone(),
             "vecs": view(dl.vecs, N * R * R, dt, es).view(N, R, R).clone(),

@@ -26,49 +26,71 @@ namespace {
 
 constexpr int DESC_WAVES = 4;  // waves per block
 
-// Packed outer product h h^T of the float64 vector in hb (LDS), off-diagonal
-// terms doubled, lane l holding entries l + 64 m.
-template <int NP>
+// Sum over the LPS lanes of one lane group (groups are aligned, LPS a
+// power of two <= 64); every lane of the group gets the result.
+template <int LPS>
+__device__ __forceinline__ double group_sum(double v) {
+#pragma unroll
+  for (int o = LPS / 2; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+template <int LPS>
+__device__ __forceinline__ double group_inclusive_scan(double v, int sl) {
+#pragma unroll
+  for (int o = 1; o < LPS; o <<= 1) {
+    const double t = __shfl_up(v, o, LPS);
+    if (sl >= o) v += t;
+  }
+  return v;
+}
+
+// Packed outer product h h^T of the group's float64 vector in hb (LDS),
+// off-diagonal terms doubled; lane sl of the group holds entries sl + LPS m.
+template <int LPS, int NP>
 struct Packed {
   double v[NP];
 };
 
-template <int NP>
-__device__ __forceinline__ void build_packed(Packed<NP>& P, const double* hb,
-                                             const uint16_t* __restrict__ tab, int TR, int lane) {
+// Branch-free: entries past the triangle read entry tri-1 and get weight 0.
+template <int LPS, int NP>
+__device__ __forceinline__ void build_packed(Packed<LPS, NP>& P, const double* hb,
+                                             const uint16_t* __restrict__ tab, int TR, int sl) {
 #pragma unroll
   for (int m = 0; m < NP; ++m) {
-    const int p = lane + 64 * m;
-    double val = 0;
-    if (p < TR) {
-      const uint16_t ab = tab[p];
-      const int a = ab & 0xff, b = ab >> 8;
-      val = hb[a] * hb[b];
-      if (a != b) val += val;
-    }
-    P.v[m] = val;
+    const int p = sl + LPS * m;
+    const uint16_t ab = tab[p < TR ? p : TR - 1];
+    const int a = ab & 0xff, b = ab >> 8;
+    const double w = p < TR ? (a != b ? 2.0 : 1.0) : 0.0;
+    P.v[m] = w * hb[a] * hb[b];
   }
 }
 
-// Node mass <h h^T, G^v> = h^T G^v h in float64 whatever the storage type.
-// R <= 64: dot product of the stored packed triangle with the packed outer
-// product kept in registers (each lane reads tri(R)/64 coalesced entries).
-template <typename T, int NP>
-__device__ __forceinline__ double node_mass(const Packed<NP>& P, const double*,
-                                            const T* __restrict__ node, int R, int TR, int lane) {
+// Node mass <h h^T, G^v> = h^T G^v h in float64 whatever the storage type:
+// the stored packed triangle (tri(R) entries, read by the group's lanes in
+// coalesced strides) dotted with the packed outer product in registers.
+template <typename T, int LPS, int NP>
+__device__ __forceinline__ double node_mass(const Packed<LPS, NP>& P, const double*,
+                                            const T* __restrict__ node, int R, int TR, int sl) {
+  // all loads first (in bounds: past-the-end entries re-read entry tri-1,
+  // whose packed weight is 0), then the float64 products
+  T g[NP];
+#pragma unroll
+  for (int m = 0; m < NP; ++m) {
+    const int p = sl + LPS * m;
+    g[m] = node[p < TR ? p : TR - 1];
+  }
   double acc = 0;
 #pragma unroll
-  for (int m = 0; m < NP; ++m) {
-    const int p = lane + 64 * m;
-    if (p < TR) acc += P.v[m] * (double)node[p];
-  }
-  return wave_sum(acc);
+  for (int m = 0; m < NP; ++m) acc += P.v[m] * (double)g[m];
+  return group_sum<LPS>(acc);
 }
 
-// R > 64: row by row; lane l owns columns l and l + 64, the row's h_a is a
-// broadcast LDS read, so no outer product has to be held in registers.
+// R > 64 (one sample per wavefront, NP == 0): row by row; lane l owns
+// columns l and l + 64 and the row's h_a is a broadcast LDS read, so no
+// outer product is held in registers.
 template <typename T>
-__device__ __forceinline__ double node_mass(const Packed<1>&, const double* hb,
+__device__ __forceinline__ double node_mass(const Packed<64, 0>&, const double* hb,
                                             const T* __restrict__ node, int R, int TR, int lane) {
   double acc0 = 0, acc1 = 0;
   int64_t start = 0;
@@ -85,24 +107,26 @@ __device__ __forceinline__ double node_mass(const Packed<1>&, const double* hb,
     }
     start += R - a;
   }
-  double v = (b0 < R ? acc0 * hb[b0] : 0.0) + (b1 < R ? acc1 * hb[b1] : 0.0);
+  const double v = (b0 < R ? acc0 * hb[b0] : 0.0) + (b1 < R ? acc1 * hb[b1] : 0.0);
   (void)TR;
-  return wave_sum(v);
+  return group_sum<64>(v);
 }
 
-// Inversion walk down a stored tree (root + left children): returns the
-// leaf position and the offset `low` of its segment.
-template <typename T, typename PK>
-__device__ __forceinline__ int64_t walk(const T* __restrict__ nodes, int64_t L, int D, const PK& P,
-                                        const double* hb, int R, int TR, int lane, double x,
-                                        double C, double& low_out) {
+// Inversion walk down a stored tree (root + left children) for each group's
+// sample: returns the leaf position and the offset `low` of its segment.
+// All groups of a wavefront walk the same tree, so the loop is uniform and
+// only the positions differ.
+template <typename T, int LPS, int NP>
+__device__ __forceinline__ int64_t walk(const T* __restrict__ nodes, int64_t L, int D,
+                                        const Packed<LPS, NP>& P, const double* hb, int R, int TR,
+                                        int sl, double x, double C, double& low_out) {
   double low = 0.0, high = C;
   int64_t pos = 0;
   int64_t off = 1;
   for (int lev = 1; lev <= D; ++lev) {
     const int64_t cnt_left = ((L - 1) >> (D - lev + 1)) + 1;
     const int64_t real = ((L - 1) >> (D - lev)) + 1;
-    double mL = node_mass<T>(P, hb, nodes + (off + pos) * (int64_t)TR, R, TR, lane);
+    double mL = node_mass<T>(P, hb, nodes + (off + pos) * (int64_t)TR, R, TR, sl);
     mL = mL > 0.0 ? mL : 0.0;
     const double cut = low + mL;
     const bool right_exists = 2 * pos + 1 < real;
@@ -119,35 +143,84 @@ __device__ __forceinline__ int64_t walk(const T* __restrict__ nodes, int64_t L, 
   return pos;
 }
 
-// Leaf scan: first row i of [s0, s1) with low + sum_{m <= i} r_m >= x.
-template <typename T>
-__device__ __forceinline__ int64_t leaf_scan(const T* __restrict__ U, int R, int64_t s0, int64_t s1,
-                                             const double* hb, double low, double x, int lane) {
-  int64_t last_pos = -1;
-  for (int64_t base = s0; base < s1; base += 64) {
-    const int64_t row = base + lane;
-    const bool valid = row < s1;
-    double r = 0.0;
-    if (valid) {
-      const T* __restrict__ ur = U + row * R;
-      double acc = 0;
-      for (int e = 0; e < R; ++e) acc += (double)ur[e] * hb[e];
-      r = acc * acc;
+// Dot product of the factor row `ur` (R contiguous values) with hb.  The
+// loads of each chunk of up to 32 values are issued together.
+template <int RMAX, typename T>
+__device__ __forceinline__ double row_dot(const T* __restrict__ ur, const double* hb, int R) {
+  constexpr int CH = RMAX < 32 ? RMAX : 32;
+  double acc = 0;
+  if constexpr (std::is_same_v<T, float>) {
+    if ((R & 3) == 0) {
+      for (int c0 = 0; c0 < R; c0 += CH) {
+        const float4* __restrict__ u4 = (const float4*)(ur + c0);
+        float4 v[CH / 4];
+#pragma unroll
+        for (int q = 0; q < CH / 4; ++q)
+          if (c0 + 4 * q < R) v[q] = u4[q];
+#pragma unroll
+        for (int q = 0; q < CH / 4; ++q)
+          if (c0 + 4 * q < R) {
+            const double* hh = hb + c0 + 4 * q;
+            acc += (double)v[q].x * hh[0] + (double)v[q].y * hh[1] + (double)v[q].z * hh[2] +
+                   (double)v[q].w * hh[3];
+          }
+      }
+      return acc;
     }
-    const double incl = wave_inclusive_scan(r, lane);
-    const bool hit = valid && (low + incl >= x);
-    const unsigned long long m = __ballot(hit);
-    if (m != 0ull) return base + (__ffsll((long long)m) - 1);
-    const unsigned long long pm = __ballot(valid && r > 0.0);
-    if (pm != 0ull) last_pos = base + (63 - __clzll((long long)pm));
-    low += __shfl(incl, 63, 64);
+  } else {
+    if ((R & 1) == 0) {
+      for (int c0 = 0; c0 < R; c0 += CH) {
+        const double2* __restrict__ u2 = (const double2*)(ur + c0);
+        double2 v[CH / 2];
+#pragma unroll
+        for (int q = 0; q < CH / 2; ++q)
+          if (c0 + 2 * q < R) v[q] = u2[q];
+#pragma unroll
+        for (int q = 0; q < CH / 2; ++q)
+          if (c0 + 2 * q < R) acc += v[q].x * hb[c0 + 2 * q] + v[q].y * hb[c0 + 2 * q + 1];
+      }
+      return acc;
+    }
   }
+  for (int e = 0; e < R; ++e) acc += (double)ur[e] * hb[e];
+  return acc;
+}
+
+// Leaf scan of each group's leaf [s0, s1): first row i with
+// low + sum_{m <= i} r_m >= x, r_m = (U[m] . h~)^2; one row per lane of the
+// group, LPS rows at a time.  `nchunk` (uniform) bounds the chunks.
+template <int LPS, int RMAX, typename T>
+__device__ __forceinline__ int64_t leaf_scan(const T* __restrict__ U, int R, int64_t s0, int64_t s1,
+                                             int nchunk, const double* hb, double low, double x,
+                                             int sl, int sub) {
+  const unsigned long long gmask = LPS == 64 ? ~0ull : ((1ull << LPS) - 1ull);
+  int64_t found = -1, last_pos = -1;
+  for (int ch = 0; ch < nchunk; ++ch) {
+    const int64_t base = s0 + (int64_t)ch * LPS;
+    const int64_t row = base + sl;
+    const bool valid = row < s1;
+    // rows past the leaf re-read its last row and count 0
+    const double acc = row_dot<RMAX>(U + (valid ? row : s1 - 1) * R, hb, R);
+    const double r = valid ? acc * acc : 0.0;
+    const double incl = group_inclusive_scan<LPS>(r, sl);
+    const bool hit = valid && found < 0 && (low + incl >= x);
+    const unsigned long long m = (__ballot(hit) >> (sub * LPS)) & gmask;
+    if (found < 0 && m != 0ull) found = base + (__ffsll((long long)m) - 1);
+    const unsigned long long pm = (__ballot(valid && r > 0.0) >> (sub * LPS)) & gmask;
+    if (pm != 0ull) last_pos = base + (63 - __clzll((long long)pm));
+    low += __shfl(incl, LPS - 1, LPS);
+  }
+  if (found >= 0) return found;
   return last_pos >= 0 ? last_pos : s1 - 1;
 }
 
-// NP > 1: packed outer product in registers; NP == 1: row-broadcast masses.
-template <typename T, int NP>
+// One wavefront walks 64 / LPS samples at once, LPS lanes per sample
+// (persistent grid-stride loop).  NP == 0 selects the row-broadcast masses
+// (R > 64, LPS == 64).
+template <typename T, int LPS, int NP, int RMAX>
 __global__ __launch_bounds__(64 * DESC_WAVES) void descent_kernel(DescentArgs a) {
+  constexpr int G = 64 / LPS;
+  constexpr int HE = (RMAX + LPS - 1) / LPS;  // history entries per lane
   extern __shared__ unsigned char smem_raw[];
   const int R = a.R;
   const int TR = R * (R + 1) / 2;
@@ -155,7 +228,9 @@ __global__ __launch_bounds__(64 * DESC_WAVES) void descent_kernel(DescentArgs a)
   double* hb_all = (double*)(smem_raw + ((TR * 2 + 15) / 16) * 16);
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
-  double* hb = hb_all + wave * 128;
+  const int sub = lane / LPS;
+  const int sl = lane % LPS;
+  double* hb = hb_all + (wave * G + sub) * 128;
   for (int p = threadIdx.x; p < TR; p += blockDim.x) {
     int aa = 0;
     while (aa < R - 1 && packed_index(aa + 1, aa + 1, R) <= p) ++aa;
@@ -167,75 +242,89 @@ __global__ __launch_bounds__(64 * DESC_WAVES) void descent_kernel(DescentArgs a)
   const int N = a.N;
   const int64_t J = a.J;
   const double inv_rank = a.rank ? 1.0 / (double)a.rank[0] : 1.0;
-  const int64_t stride = (int64_t)gridDim.x * DESC_WAVES;
-  for (int64_t d = (int64_t)blockIdx.x * DESC_WAVES + wave; d < J; d += stride) {
-    // history h = (*) of the rows drawn so far, float64 (lanes e, e + 64)
-    double h0 = 1, h1 = 1;
-    Packed<NP> P;
+  const int64_t stride = (int64_t)gridDim.x * DESC_WAVES * G;
+  for (int64_t base = ((int64_t)blockIdx.x * DESC_WAVES + wave) * G; base < J; base += stride) {
+    const int64_t d = base + sub;
+    const bool active = d < J;
+    // history h = (*) of the rows drawn so far, float64; entry e = sl + LPS i
+    double h[HE];
+#pragma unroll
+    for (int i = 0; i < HE; ++i) h[i] = 1.0;
+    Packed<LPS, NP> P;
     for (int st = 0; st < a.nsteps; ++st) {
       const int k = a.order[st];
       const ModeDesc& md = a.mode[k];
-      const double d1 = a.u01[(d * N + k) * 2 + 0];
-      const double d2 = a.u01[(d * N + k) * 2 + 1];
+      const double d1 = active ? a.u01[(d * N + k) * 2 + 0] : 0.5;
+      const double d2 = active ? a.u01[(d * N + k) * 2 + 1] : 0.5;
       // ---- stage 1: eigen-component u from E_k
-      if (lane < R) hb[lane] = h0;
-      if (lane + 64 < R) hb[lane + 64] = h1;
+#pragma unroll
+      for (int i = 0; i < HE; ++i)
+        if (sl + LPS * i < R) hb[sl + LPS * i] = h[i];
       wave_lds_sync();
-      if constexpr (NP > 1) build_packed(P, hb, tab, TR, lane);
+      if constexpr (NP > 0) build_packed(P, hb, tab, TR, sl);
       const T* __restrict__ E = (const T*)md.E;
-      const double C1 = node_mass<T>(P, hb, E, R, TR, lane);
+      const double C1 = node_mass<T>(P, hb, E, R, TR, sl);
       double low;
-      int u = (int)walk(E, (int64_t)R, md.DE, P, hb, R, TR, lane, d1 * C1, C1, low);
+      int u = (int)walk(E, (int64_t)R, md.DE, P, hb, R, TR, sl, d1 * C1, C1, low);
       if (u >= R) u = R - 1;
       // ---- stage 2: row t from Z_k with h~ = h (*) V[:, u]
       const T* __restrict__ V = (const T*)md.V + (int64_t)u * R;
-      const double ht0 = lane < R ? h0 * (double)V[lane] : 0.0;
-      const double ht1 = lane + 64 < R ? h1 * (double)V[lane + 64] : 0.0;
+      double ht[HE];
+#pragma unroll
+      for (int i = 0; i < HE; ++i) {
+        const int e = sl + LPS * i;
+        ht[i] = e < R ? h[i] * (double)V[e] : 0.0;
+      }
       wave_lds_sync();
-      if (lane < R) hb[lane] = ht0;
-      if (lane + 64 < R) hb[lane + 64] = ht1;
+#pragma unroll
+      for (int i = 0; i < HE; ++i)
+        if (sl + LPS * i < R) hb[sl + LPS * i] = ht[i];
       wave_lds_sync();
-      if constexpr (NP > 1) build_packed(P, hb, tab, TR, lane);
+      if constexpr (NP > 0) build_packed(P, hb, tab, TR, sl);
       const T* __restrict__ Z = (const T*)md.Z;
-      const double C2 = node_mass<T>(P, hb, Z, R, TR, lane);
+      const double C2 = node_mass<T>(P, hb, Z, R, TR, sl);
       const double x2 = d2 * C2;
-      const int64_t c = walk(Z, md.L, md.D, P, hb, R, TR, lane, x2, C2, low);
+      const int64_t c = walk(Z, md.L, md.D, P, hb, R, TR, sl, x2, C2, low);
       const int64_t s0 = c * md.F;
       const int64_t s1 = s0 + md.F < md.I ? s0 + md.F : md.I;
       const T* __restrict__ U = (const T*)md.U;
-      int64_t t = leaf_scan(U, R, s0, s1, hb, low, x2, lane);
+      const int nchunk = (md.F + LPS - 1) / LPS;
+      int64_t t = leaf_scan<LPS, RMAX>(U, R, s0, s1, nchunk, hb, low, x2, sl, sub);
       if (t < 0) t = 0;
       if (t >= md.I) t = md.I - 1;
-      if (lane == 0) a.idx[d * N + k] = (int32_t)t;
-      if (lane < R) h0 *= (double)U[t * R + lane];
-      if (lane + 64 < R) h1 *= (double)U[t * R + lane + 64];
-      if (!(C1 > 0.0) || !(C2 > 0.0)) {
-        if (lane == 0) atomicOr(a.status, ST_NUMERIC);
+      if (sl == 0 && active) a.idx[d * N + k] = (int32_t)t;
+#pragma unroll
+      for (int i = 0; i < HE; ++i) {
+        const int e = sl + LPS * i;
+        if (e < R) h[i] *= (double)U[t * R + e];
+      }
+      if (active && (!(C1 > 0.0) || !(C2 > 0.0))) {
+        if (sl == 0) atomicOr(a.status, ST_NUMERIC);
       }
       wave_lds_sync();
     }
-    if (a.exclude >= 0 && lane == 0) a.idx[d * N + a.exclude] = -1;
+    if (a.exclude >= 0 && sl == 0 && active) a.idx[d * N + a.exclude] = -1;
     // ---- probability of the sampled row: q = a G^+ a^T / rank
     if (a.prob != nullptr || a.rows != nullptr || a.wout != nullptr) {
-      if (lane < R) hb[lane] = h0;
-      if (lane + 64 < R) hb[lane + 64] = h1;
+#pragma unroll
+      for (int i = 0; i < HE; ++i)
+        if (sl + LPS * i < R) hb[sl + LPS * i] = h[i];
       wave_lds_sync();
-      double acc = 0.0;
-      for (int p = lane; p < TR; p += 64) {
-        const uint16_t ab = tab[p];
-        const int ia = ab & 0xff, ib = ab >> 8;
-        const double v = hb[ia] * hb[ib] * a.gplus[p];
-        acc += ia == ib ? v : 2.0 * v;
-      }
-      const double q = wave_sum(acc) * inv_rank;
-      if (lane == 0 && a.prob != nullptr) a.prob[d] = q;
-      const double w = 1.0 / sqrt((double)J * q);
-      if (lane == 0 && a.wout != nullptr) a.wout[d] = w;
-      if (a.rows != nullptr) {
-        T* rows = (T*)a.rows + d * R;
-        const double sc = a.scale_rows ? w : 1.0;
-        if (lane < R) rows[lane] = (T)(h0 * sc);
-        if (lane + 64 < R) rows[lane + 64] = (T)(h1 * sc);
+      if constexpr (NP > 0) build_packed(P, hb, tab, TR, sl);
+      const double q = node_mass<double>(P, hb, a.gplus, R, TR, sl) * inv_rank;
+      if (active) {
+        if (sl == 0 && a.prob != nullptr) a.prob[d] = q;
+        const double w = 1.0 / sqrt((double)J * q);
+        if (sl == 0 && a.wout != nullptr) a.wout[d] = w;
+        if (a.rows != nullptr) {
+          T* rows = (T*)a.rows + d * R;
+          const double sc = a.scale_rows ? w : 1.0;
+#pragma unroll
+          for (int i = 0; i < HE; ++i) {
+            const int e = sl + LPS * i;
+            if (e < R) rows[e] = (T)(h[i] * sc);
+          }
+        }
       }
       wave_lds_sync();
     }
@@ -289,32 +378,41 @@ __global__ __launch_bounds__(64 * DESC_WAVES) void row_prob_kernel(DescentArgs a
   }
 }
 
-template <typename T, int NP>
+template <typename T, int LPS, int NP, int RMAX>
 hipError_t run_descent(hipStream_t st, const DescentArgs& a) {
+  constexpr int G = 64 / LPS;
   const int TR = a.R * (a.R + 1) / 2;
-  const size_t lds = ((TR * 2 + 15) / 16) * 16 + DESC_WAVES * 128 * sizeof(double);
-  int64_t blocks = (a.J + DESC_WAVES - 1) / DESC_WAVES;
+  const size_t lds = ((TR * 2 + 15) / 16) * 16 + DESC_WAVES * G * 128 * sizeof(double);
+  int64_t blocks = (a.J + DESC_WAVES * G - 1) / (DESC_WAVES * G);
   if (blocks > 256 * 8) blocks = 256 * 8;
   if (blocks < 1) blocks = 1;
-  hipLaunchKernelGGL((descent_kernel<T, NP>), dim3((unsigned)blocks), dim3(64 * DESC_WAVES), lds, st,
-                     a);
+  hipLaunchKernelGGL((descent_kernel<T, LPS, NP, RMAX>), dim3((unsigned)blocks),
+                     dim3(64 * DESC_WAVES), lds, st, a);
   return hipGetLastError();
 }
 
+// Lanes per sample (LPS) and packed entries per lane (NP = ceil(tri/LPS));
+// `lps` (0 = default) selects among the compiled variants.
 template <typename T>
-hipError_t dispatch_descent(hipStream_t st, const DescentArgs& a) {
-  if (a.R <= 16) return run_descent<T, 3>(st, a);
-  if (a.R <= 32) return run_descent<T, 9>(st, a);
-  if (a.R <= 64) return run_descent<T, 33>(st, a);
-  return run_descent<T, 1>(st, a);
+hipError_t dispatch_descent(hipStream_t st, const DescentArgs& a, int lps) {
+  if (a.R <= 8) return lps == 8 ? run_descent<T, 8, 5, 8>(st, a) : run_descent<T, 4, 9, 8>(st, a);
+  if (a.R <= 16)
+    return lps == 16 ? run_descent<T, 16, 9, 16>(st, a) : run_descent<T, 8, 17, 16>(st, a);
+  if (a.R <= 32) {
+    if (lps == 64) return run_descent<T, 64, 9, 32>(st, a);
+    if (lps == 16) return run_descent<T, 16, 33, 32>(st, a);
+    return run_descent<T, 32, 17, 32>(st, a);
+  }
+  if (a.R <= 64) return run_descent<T, 64, 33, 64>(st, a);
+  return run_descent<T, 64, 0, 128>(st, a);
 }
 
 }  // namespace
 
 hipError_t launch_descent(hipStream_t st, krps_precision p, const DescentArgs& a) {
   if (a.J <= 0) return hipSuccess;
-  if (p == KRPS_FP64) return dispatch_descent<double>(st, a);
-  return dispatch_descent<float>(st, a);
+  if (p == KRPS_FP64) return dispatch_descent<double>(st, a, a.lps);
+  return dispatch_descent<float>(st, a, a.lps);
 }
 
 hipError_t launch_row_prob(hipStream_t st, krps_precision p, const DescentArgs& a) {

@@ -20,90 +20,146 @@ namespace krps {
 
 namespace {
 
-constexpr int PREP_THREADS = 1024;
+constexpr int PREP_THREADS = 1024;  // upper bound; launches use prep_threads(R)
+constexpr int jacobi_team(int R);
+
+// Block size of the one-workgroup eigensolver: one team per column pair.
+int prep_threads(int R) {
+  const int npairs = (R + (R & 1)) / 2;
+  int t = npairs * jacobi_team(R);
+  if (t < 64) t = 64;
+  if (t > PREP_THREADS) t = PREP_THREADS;
+  return (t + 63) / 64 * 64;
+}
 
 struct GList {
   const double* G[KRPS_MAX_MODES];
   int order[KRPS_MAX_MODES];
 };
 
-__device__ __forceinline__ double team_sum(double v, int team) {
-  for (int o = team >> 1; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+// Lane-exchange of a double through the data-parallel primitives (DPP).
+template <int CTRL>
+__device__ __forceinline__ double dpp_d(double v) {
+  const int lo = __builtin_amdgcn_mov_dpp(__double2loint(v), CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(v), CTRL, 0xF, 0xF, false);
+  return __hiloint2double(hi, lo);
+}
+
+// Sum over an aligned team of TEAM (1, 2, 4, 8 or 16) lanes: quad swaps,
+// then half-row and row mirrors.
+template <int TEAM>
+__device__ __forceinline__ double team_sum(double v) {
+  if constexpr (TEAM >= 2) v += dpp_d<0xB1>(v);   // quad_perm [1,0,3,2]
+  if constexpr (TEAM >= 4) v += dpp_d<0x4E>(v);   // quad_perm [2,3,0,1]
+  if constexpr (TEAM >= 8) v += dpp_d<0x141>(v);  // row_half_mirror
+  if constexpr (TEAM >= 16) v += dpp_d<0x140>(v); // row_mirror
   return v;
 }
 
-// One-sided Jacobi on the columns of A (column c at A + c*R), all threads
-// of the block.  `flag` is an int in LDS.
-__device__ void jacobi_columns(double* A, int R, int* flag) {
+// Team of lanes per column pair for a given R (RPL rows per lane at most).
+constexpr int jacobi_team(int R) { return R <= 32 ? 4 : (R <= 64 ? 8 : 16); }
+constexpr int JACOBI_RPL = 8;
+
+// One-sided Jacobi on the columns of A (column c at A + c*RS, RS = R + 1 so
+// that the columns of a step fall in different LDS banks).  Each step
+// rotates the R/2 disjoint column pairs of the round-robin (circle)
+// schedule in parallel, one team of TEAM lanes per pair; a lane keeps its
+// <= RPL rows of both columns in registers between the dot products and
+// the rotation.  `flag` is an int in LDS.  Returns the number of sweeps.
+template <int TEAM>
+__device__ int jacobi_columns_t(double* A, int R, int* flag) {
+  constexpr int RPL = JACOBI_RPL;
+  const int RS = R + 1;
   const int tid = threadIdx.x;
   const int n = R + (R & 1);
   const int npairs = n / 2;
-  int team = blockDim.x / npairs;
-  if (team > 64) team = 64;
-  int t2 = 1;
-  while (t2 * 2 <= team) t2 *= 2;
-  team = t2;
-  const int s = tid / team;
-  const int li = tid % team;
-  const double tol = (double)R * DBL_EPSILON;
-  for (int sweep = 0; sweep < 40; ++sweep) {
+  const int s = tid / TEAM;
+  const int li = tid % TEAM;
+  // a pair counts as orthogonal below tol * |a_p| |a_q|; rounding keeps the
+  // computed cosine of ill-separated columns near eps * kappa, so a tighter
+  // tol would only spin until the sweep cap
+  const double tol = 1e-13;
+  int sweep = 0;
+  for (; sweep < 24; ++sweep) {
     __syncthreads();
     if (tid == 0) *flag = 0;
     __syncthreads();
+    // circle schedule: position 0 is fixed, the others rotate by one per
+    // step; pair s holds positions s and n-1-s
+    int cp = s == 0 ? 0 : (s - 1) % (n - 1);
+    int cq = (n - 2 - s) % (n - 1);
     for (int step = 0; step < n - 1; ++step) {
-      if (s < npairs) {
-        const int i0 = s, i1 = n - 1 - s;
-        const int p = (i0 == 0) ? 0 : 1 + ((i0 - 1 + step) % (n - 1));
-        const int q = 1 + ((i1 - 1 + step) % (n - 1));
-        if (p < R && q < R) {
-          double al = 0, be = 0, ga = 0;
-          for (int r = li; r < R; r += team) {
-            const double x = A[p * R + r], y = A[q * R + r];
-            al += x * x;
-            be += y * y;
-            ga += x * y;
-          }
-          al = team_sum(al, team);
-          be = team_sum(be, team);
-          ga = team_sum(ga, team);
-          if (al > 0 && be > 0 && fabs(ga) > tol * sqrt(al * be)) {
-            const double zeta = (be - al) / (2.0 * ga);
-            double t;
-            if (fabs(zeta) > 1e150)
-              t = 0.5 / zeta;
-            else
-              t = (zeta >= 0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
-            const double c = 1.0 / sqrt(1.0 + t * t);
-            const double sn = c * t;
-            for (int r = li; r < R; r += team) {
-              const double x = A[p * R + r], y = A[q * R + r];
-              A[p * R + r] = c * x - sn * y;
-              A[q * R + r] = sn * x + c * y;
-            }
-            if (li == 0) *flag = 1;
+      int p = 0, q = 0;
+      bool act = s < npairs;
+      if (act) {
+        p = (s == 0) ? 0 : 1 + cp;
+        q = 1 + cq;
+        act = p < R && q < R;
+      }
+      cp = cp + 1 == n - 1 ? 0 : cp + 1;
+      cq = cq + 1 == n - 1 ? 0 : cq + 1;
+      double x[RPL], y[RPL];
+      double al = 0, be = 0, ga = 0;
+#pragma unroll
+      for (int i = 0; i < RPL; ++i) {
+        const int r = li + TEAM * i;
+        const bool ok = act && r < R;
+        x[i] = ok ? A[p * RS + r] : 0.0;
+        y[i] = ok ? A[q * RS + r] : 0.0;
+        al += x[i] * x[i];
+        be += y[i] * y[i];
+        ga += x[i] * y[i];
+      }
+      al = team_sum<TEAM>(al);
+      be = team_sum<TEAM>(be);
+      ga = team_sum<TEAM>(ga);
+      if (act && al > 0 && be > 0 && fabs(ga) > tol * sqrt(al * be)) {
+        // tangent of the rotation angle, the root of t^2 + 2 zeta t - 1 = 0
+        // of smaller magnitude (zeta = (be - al) / (2 ga))
+        const double dd = be - al, g2 = 2.0 * ga;
+        const double rr = sqrt(dd * dd + g2 * g2);
+        const double t = g2 / (dd + (dd >= 0 ? rr : -rr));
+        const double c = rsqrt(1.0 + t * t);
+        const double sn = c * t;
+#pragma unroll
+        for (int i = 0; i < RPL; ++i) {
+          const int r = li + TEAM * i;
+          if (r < R) {
+            A[p * RS + r] = c * x[i] - sn * y[i];
+            A[q * RS + r] = sn * x[i] + c * y[i];
           }
         }
+        if (li == 0) *flag = 1;
       }
       __syncthreads();
     }
     if (*flag == 0) break;
   }
   __syncthreads();
+  return sweep + 1;
+}
+
+__device__ int jacobi_columns(double* A, int R, int* flag) {
+  if (R <= 32) return jacobi_columns_t<jacobi_team(32)>(A, R, flag);
+  if (R <= 64) return jacobi_columns_t<jacobi_team(64)>(A, R, flag);
+  return jacobi_columns_t<jacobi_team(128)>(A, R, flag);
 }
 
 // Column norms into lam[], columns normalised in place (zero columns stay).
 __device__ void norms_and_normalise(double* A, int R, double* lam) {
+  const int RS = R + 1;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
   for (int c = wave; c < R; c += nw) {
     double ss = 0;
-    for (int r = lane; r < R; r += 64) ss += A[c * R + r] * A[c * R + r];
+    for (int r = lane; r < R; r += 64) ss += A[c * RS + r] * A[c * RS + r];
     ss = wave_sum(ss);
     if (lane == 0) lam[c] = sqrt(ss);
   }
   __syncthreads();
   for (int i = threadIdx.x; i < R * R; i += blockDim.x) {
-    const double l = lam[i / R];
-    A[i] = l > 0 ? A[i] / l : 0.0;
+    const int c = i / R, r = i % R;
+    const double l = lam[c];
+    A[c * RS + r] = l > 0 ? A[c * RS + r] / l : 0.0;
   }
   __syncthreads();
 }
@@ -115,18 +171,20 @@ __global__ __launch_bounds__(PREP_THREADS) void prep_gplus_kernel(
     double* __restrict__ gplus_full, double* __restrict__ gplus_packed, int32_t* __restrict__ rank,
     double* __restrict__ ggt, int32_t* __restrict__ status) {
   extern __shared__ double smem[];
-  double* A = smem;                 // R*R
-  double* lam = A + R * R;          // R
+  const int RS = R + 1;
+  double* A = smem;                 // R*RS
+  double* lam = A + R * RS;         // R
   double* red = lam + R;            // 2
   int* flag = (int*)(red + 2);
   const int tid = threadIdx.x;
   for (int i = tid; i < R * R; i += blockDim.x) {
     double v = 1.0;
     for (int m = 0; m < nmat; ++m) v *= gl.G[m][i];
-    A[i] = v;
+    A[(i / R) * RS + i % R] = v;
   }
   __syncthreads();
-  jacobi_columns(A, R, flag);
+  const int sweeps = jacobi_columns(A, R, flag);
+  if (tid == 0) rank[1] = sweeps;
   norms_and_normalise(A, R, lam);
   if (tid == 0) {
     double lmax = 0;
@@ -141,11 +199,12 @@ __global__ __launch_bounds__(PREP_THREADS) void prep_gplus_kernel(
   }
   __syncthreads();
   const double tau = red[0];
+  for (int c = tid; c < R; c += blockDim.x) lam[c] = lam[c] > tau ? 1.0 / lam[c] : 0.0;
+  __syncthreads();
   for (int i = tid; i < R * R; i += blockDim.x) {
     const int a = i / R, b = i % R;
     double v = 0;
-    for (int c = 0; c < R; ++c)
-      if (lam[c] > tau) v += A[c * R + a] * A[c * R + b] / lam[c];
+    for (int c = 0; c < R; ++c) v += A[c * RS + a] * A[c * RS + b] * lam[c];
     gplus_full[i] = v;
     if (gplus_packed != nullptr && a <= b) gplus_packed[packed_index(a, b, R)] = v;
     // G_{>k}: later drawn modes' Grams multiplied in
@@ -162,19 +221,22 @@ __global__ __launch_bounds__(PREP_THREADS) void prep_gplus_kernel(
 template <typename T>
 __global__ __launch_bounds__(PREP_THREADS) void prep_eig_kernel(
     GList gk, int R, const double* __restrict__ ggt,
-    double* __restrict__ lam_out, T* __restrict__ vecs, T* __restrict__ etree, int64_t enodes) {
+    double* __restrict__ lam_out, T* __restrict__ vecs, T* __restrict__ etree, int64_t enodes,
+    int32_t* __restrict__ sweep_out) {
   extern __shared__ double smem[];
+  const int RS = R + 1;
   double* A = smem;
-  double* lam = A + R * R;
+  double* lam = A + R * RS;
   int* perm = (int*)(lam + R);
   int* flag = perm + R;
   const int st = blockIdx.x;
   const int k = gk.order[st];
   const double* __restrict__ Gk = gk.G[st];
   const int tid = threadIdx.x;
-  for (int i = tid; i < R * R; i += blockDim.x) A[i] = ggt[(int64_t)k * R * R + i];
+  for (int i = tid; i < R * R; i += blockDim.x) A[(i / R) * RS + i % R] = ggt[(int64_t)k * R * R + i];
   __syncthreads();
-  jacobi_columns(A, R, flag);
+  const int sweeps = jacobi_columns(A, R, flag);
+  if (tid == 0 && sweep_out != nullptr) sweep_out[2 + st] = sweeps;
   norms_and_normalise(A, R, lam);
   // ascending order, ties by column index
   for (int c = tid; c < R; c += blockDim.x) {
@@ -186,7 +248,7 @@ __global__ __launch_bounds__(PREP_THREADS) void prep_eig_kernel(
   __syncthreads();
   for (int i = tid; i < R * R; i += blockDim.x) {
     const int u = i / R, e = i % R;
-    vecs[(int64_t)k * R * R + i] = (T)A[perm[u] * R + e];
+    vecs[(int64_t)k * R * R + i] = (T)A[perm[u] * RS + e];
     if (e == 0) lam_out[(int64_t)k * R + u] = lam[perm[u]];
   }
   // eigen-tree over the R rows sqrt(lam_u) v_u^T with Y = G_k: node masses
@@ -207,7 +269,7 @@ __global__ __launch_bounds__(PREP_THREADS) void prep_eig_kernel(
       double v = 0;
       if (u < R) {
         const int c = perm[u];
-        v = lam[c] * A[c * R + a] * A[c * R + b] * g;
+        v = lam[c] * A[c * RS + a] * A[c * RS + b] * g;
       }
       int t = __builtin_ctzll(~(unsigned long long)u);
       if (t > DE) t = DE;
@@ -231,7 +293,9 @@ hipError_t set_lds(const void* fn, size_t bytes) {
 
 }  // namespace
 
-size_t prep_lds_bytes(int R) { return (size_t)R * R * 8 + (size_t)R * 8 + 64 + (size_t)R * 4 + 64; }
+size_t prep_lds_bytes(int R) {
+  return (size_t)R * (R + 1) * 8 + (size_t)R * 8 + 64 + (size_t)R * 4 + 64;
+}
 
 hipError_t launch_prep_gplus2(hipStream_t st, int R, int nmat, const double* const* mats,
                               int nsteps, const int* order, double* gplus_full,
@@ -242,14 +306,15 @@ hipError_t launch_prep_gplus2(hipStream_t st, int R, int nmat, const double* con
   const size_t lds = prep_lds_bytes(R);
   hipError_t e = set_lds((const void*)prep_gplus_kernel, lds);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(prep_gplus_kernel, dim3(1), dim3(PREP_THREADS), lds, st, gl, nmat, R, nsteps,
+  hipLaunchKernelGGL(prep_gplus_kernel, dim3(1), dim3(prep_threads(R)), lds, st, gl, nmat, R, nsteps,
                      gplus_full, gplus_packed, rank, ggt, status);
   return hipGetLastError();
 }
 
 hipError_t launch_prep_eig2(hipStream_t st, krps_precision p, int R, int nsteps,
                             const double* const* Gsteps, const int* order, const double* ggt,
-                            double* lam, void* vecs, void* etree, int64_t enodes) {
+                            double* lam, void* vecs, void* etree, int64_t enodes,
+                            int32_t* sweep_out) {
   GList gl{};
   for (int m = 0; m < nsteps; ++m) {
     gl.G[m] = Gsteps[m];
@@ -260,13 +325,13 @@ hipError_t launch_prep_eig2(hipStream_t st, krps_precision p, int R, int nsteps,
   if (p == KRPS_FP64) {
     e = set_lds((const void*)prep_eig_kernel<double>, lds);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(prep_eig_kernel<double>, dim3(nsteps), dim3(PREP_THREADS), lds, st, gl,
-                       R, ggt, lam, (double*)vecs, (double*)etree, enodes);
+    hipLaunchKernelGGL(prep_eig_kernel<double>, dim3(nsteps), dim3(prep_threads(R)), lds, st, gl,
+                       R, ggt, lam, (double*)vecs, (double*)etree, enodes, sweep_out);
   } else {
     e = set_lds((const void*)prep_eig_kernel<float>, lds);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(prep_eig_kernel<float>, dim3(nsteps), dim3(PREP_THREADS), lds, st, gl,
-                       R, ggt, lam, (float*)vecs, (float*)etree, enodes);
+    hipLaunchKernelGGL(prep_eig_kernel<float>, dim3(nsteps), dim3(prep_threads(R)), lds, st, gl,
+                       R, ggt, lam, (float*)vecs, (float*)etree, enodes, sweep_out);
   }
   return hipGetLastError();
 }

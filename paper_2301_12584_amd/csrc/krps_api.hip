@@ -2,6 +2,7 @@
 // launches of the sampler kernels.  Host code only; every computation runs
 // in the kernels of tree_build.hip, eig.hip and descent.hip.
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <new>
 #include <string>
@@ -47,6 +48,9 @@ struct krps_sampler_s {
   int32_t* status;
   // per-draw workspace layout
   krps_draw_layout lay;
+  const void* prepared_ws = nullptr;  // ws of the last preparation
+  int prepared_exclude = -2;
+  int lps = 0;                         // descent lanes per sample (0 = default)
   size_t draw_bytes;
   int64_t enodes;
   int DE;
@@ -134,6 +138,8 @@ krps_status build_tree(krps_sampler s, int j) {
   return KRPS_OK;
 }
 
+void fill_descent_args(krps_sampler s, int exclude, void* ws, DescentArgs& a);
+
 // Enqueues lines 1-5 of Algorithm 2 for exclusion `exclude` into ws and
 // fills the descent arguments.
 krps_status prepare_draw(krps_sampler s, int exclude, void* ws, DescentArgs& a) {
@@ -159,8 +165,23 @@ krps_status prepare_draw(krps_sampler s, int exclude, void* ws, DescentArgs& a) 
   hipError_t e = launch_prep_gplus2(st, R, nsteps, mats, nsteps, order, gplus_full, gplus_packed,
                                     rank, ggt, s->status);
   if (e != hipSuccess) return hip_fail(e, "prep G+ launch");
-  e = launch_prep_eig2(st, s->prec, R, nsteps, mats, order, ggt, lam, vecs, etree, s->enodes);
+  e = launch_prep_eig2(st, s->prec, R, nsteps, mats, order, ggt, lam, vecs, etree, s->enodes,
+                       rank);
   if (e != hipSuccess) return hip_fail(e, "prep eig launch");
+  fill_descent_args(s, exclude, ws, a);
+  return KRPS_OK;
+}
+
+// Descent arguments for a preparation of `exclude` held in ws.
+void fill_descent_args(krps_sampler s, int exclude, void* ws, DescentArgs& a) {
+  char* w = (char*)ws;
+  const int R = s->R;
+  int order[KRPS_MAX_MODES];
+  int nsteps = 0;
+  for (int k = 0; k < s->N; ++k)
+    if (k != exclude) order[nsteps++] = k;
+  double* gplus_packed = (double*)(w + gpacked_off(s));
+  int32_t* rank = (int32_t*)(w + s->lay.rank);
   memset(&a, 0, sizeof(a));
   a.N = s->N;
   a.R = R;
@@ -183,7 +204,7 @@ krps_status prepare_draw(krps_sampler s, int exclude, void* ws, DescentArgs& a) 
   a.gplus = gplus_packed;
   a.rank = rank;
   a.status = s->status;
-  return KRPS_OK;
+  a.lps = s->lps;
 }
 
 }  // namespace
@@ -263,6 +284,7 @@ krps_status krps_sampler_create(krps_ctx ctx, int N, const int64_t* I, int R, in
   s->scratch = (double*)(w + pl.scratch_off);
   s->scratch_bytes = pl.scratch_bytes;
   s->status = (int32_t*)(w + pl.status_off);
+  if (const char* e = getenv("KRPS_DESCENT_LPS")) s->lps = atoi(e);
   plan_draw(s);
   hipError_t e = hipSetDevice(ctx->device);
   if (e != hipSuccess) {
@@ -302,20 +324,37 @@ krps_status krps_sample_workspace_bytes(krps_sampler s, size_t* bytes) {
   return KRPS_OK;
 }
 
-krps_status krps_sample(krps_sampler s, int exclude, int64_t J, const double* uniforms,
-                        int32_t* idx, double* prob, void* rows, void* ws, size_t ws_bytes,
-                        int check) {
+static krps_status check_draw_args(krps_sampler s, int exclude, void* ws, size_t ws_bytes) {
   if (s == nullptr) return fail(KRPS_EINVAL, "sampler is NULL");
   if (exclude < -1 || exclude >= s->N) return fail(KRPS_EINVAL, "exclude out of range");
   if (exclude >= 0 && s->N == 1) return fail(KRPS_EINVAL, "cannot exclude the only factor");
+  if (ws == nullptr) return fail(KRPS_EINVAL, "workspace is NULL");
+  if (ws_bytes < s->draw_bytes) return fail(KRPS_EWORKSPACE, "draw workspace too small");
+  return KRPS_OK;
+}
+
+krps_status krps_sample_prepare(krps_sampler s, int exclude, void* ws, size_t ws_bytes) {
+  krps_status st = check_draw_args(s, exclude, ws, ws_bytes);
+  if (st != KRPS_OK) return st;
+  DescentArgs a;
+  st = prepare_draw(s, exclude, ws, a);
+  if (st != KRPS_OK) return st;
+  s->prepared_ws = ws;
+  s->prepared_exclude = exclude;
+  return KRPS_OK;
+}
+
+krps_status krps_sample_draw(krps_sampler s, int exclude, int64_t J, const double* uniforms,
+                             int32_t* idx, double* prob, void* rows, void* ws, size_t ws_bytes) {
+  krps_status st = check_draw_args(s, exclude, ws, ws_bytes);
+  if (st != KRPS_OK) return st;
   if (J < 0) return fail(KRPS_EINVAL, "J < 0");
   if (J > 0 && (uniforms == nullptr || idx == nullptr))
     return fail(KRPS_EINVAL, "uniforms/idx is NULL");
-  if (ws == nullptr) return fail(KRPS_EINVAL, "workspace is NULL");
-  if (ws_bytes < s->draw_bytes) return fail(KRPS_EWORKSPACE, "draw workspace too small");
+  if (s->prepared_ws != ws || s->prepared_exclude != exclude)
+    return fail(KRPS_EINVAL, "krps_sample_draw without a matching krps_sample_prepare");
   DescentArgs a;
-  krps_status st = prepare_draw(s, exclude, ws, a);
-  if (st != KRPS_OK) return st;
+  fill_descent_args(s, exclude, ws, a);
   a.J = J;
   a.u01 = uniforms;
   a.idx = idx;
@@ -323,6 +362,16 @@ krps_status krps_sample(krps_sampler s, int exclude, int64_t J, const double* un
   a.rows = rows;
   hipError_t e = launch_descent(s->ctx->stream, s->prec, a);
   if (e != hipSuccess) return hip_fail(e, "descent launch");
+  return KRPS_OK;
+}
+
+krps_status krps_sample(krps_sampler s, int exclude, int64_t J, const double* uniforms,
+                        int32_t* idx, double* prob, void* rows, void* ws, size_t ws_bytes,
+                        int check) {
+  krps_status st = krps_sample_prepare(s, exclude, ws, ws_bytes);
+  if (st != KRPS_OK) return st;
+  st = krps_sample_draw(s, exclude, J, uniforms, idx, prob, rows, ws, ws_bytes);
+  if (st != KRPS_OK) return st;
   if (check) {
     int32_t flag = 0;
     KRPS_HIP(hipMemcpyAsync(&flag, s->status, 4, hipMemcpyDeviceToHost, s->ctx->stream));

@@ -74,6 +74,7 @@ struct DescentArgs {
   const int32_t* rank;            // device rank of G
   double* wout;                   // [J] sampling weights 1/sqrt(J q) or null
   int scale_rows;                 // rows <- a_d / sqrt(J q_d)
+  int lps;                        // lanes per sample of the walk (0 = default)
   int32_t* status;                // device status word
 };
 
@@ -97,7 +98,9 @@ hipError_t launch_prep_gplus2(hipStream_t st, int R, int nmat, const double* con
                               double* gplus_packed, int32_t* rank, double* ggt, int32_t* status);
 hipError_t launch_prep_eig2(hipStream_t st, krps_precision p, int R, int nsteps,
                             const double* const* Gsteps, const int* order, const double* ggt,
-                            double* lam, void* vecs, void* etree, int64_t enodes);
+                            double* lam, void* vecs, void* etree, int64_t enodes,
+                            int32_t* sweep_out);
+// rank points at two int32: the rank and the Jacobi sweep count.
 hipError_t launch_pinv(hipStream_t st, int R, const double* M, double* Mp_full, int32_t* rank);
 
 // descent.hip

@@ -77,32 +77,63 @@ __global__ __launch_bounds__(64 * TW) void leaf_run_kernel(const void* __restric
       const int64_t r0 = c * F;
       const int64_t r1 = r0 + F < I ? r0 + F : I;
       if constexpr (MODE != M_SPLIT) {
-        for (int64_t rb = r0; rb < r1; rb += 4) {
-          const int64_t row = rb + (lane >> 4);
-          const bool rv = row < r1;
-          double vals[NT];
-          static_for<0, NT>([&](auto tt) {
-            constexpr int t = decltype(tt)::value;
-            const int col = 16 * t + (lane & 15);
-            vals[t] = (rv && col < R) ? (double)U[row * R + col] : 0.0;
-          });
-          static_for<0, NPAIRS>([&](auto pp) {
-            constexpr int pr = decltype(pp)::value;
-            constexpr int ta = pair_ta(NT, pr);
-            constexpr int tb = pair_tb(NT, pr);
-            if (pr % TW == wave) node[pr / TW] = mfma_f64(vals[ta], vals[tb], node[pr / TW]);
-          });
+        // chunks of KS steps of 4 rows: all loads of a chunk are issued
+        // before its products
+        constexpr int KS = NT <= 2 ? 8 : 4;
+        for (int64_t rc = r0; rc < r1; rc += 4 * KS) {
+          // unconditional loads from clamped (in-bounds) addresses, zeroed
+          // afterwards, so that they are all issued back to back
+          T raw[KS][NT];
+#pragma unroll
+          for (int ks = 0; ks < KS; ++ks) {
+            const int64_t row = rc + 4 * ks + (lane >> 4);
+            const int64_t rowc = row < r1 ? row : r1 - 1;
+            static_for<0, NT>([&](auto tt) {
+              constexpr int t = decltype(tt)::value;
+              const int col = 16 * t + (lane & 15);
+              raw[ks][t] = U[rowc * R + (col < R ? col : R - 1)];
+            });
+          }
+#pragma unroll
+          for (int ks = 0; ks < KS; ++ks) {
+            const bool rv = rc + 4 * ks + (lane >> 4) < r1;
+            static_for<0, NT>([&](auto tt) {
+              constexpr int t = decltype(tt)::value;
+              if (!rv || 16 * t + (lane & 15) >= R) raw[ks][t] = T(0);
+            });
+          }
+#pragma unroll
+          for (int ks = 0; ks < KS; ++ks) {
+            static_for<0, NPAIRS>([&](auto pp) {
+              constexpr int pr = decltype(pp)::value;
+              constexpr int ta = pair_ta(NT, pr);
+              constexpr int tb = pair_tb(NT, pr);
+              if (pr % TW == wave)
+                node[pr / TW] = mfma_f64((double)raw[ks][ta], (double)raw[ks][tb], node[pr / TW]);
+            });
+          }
         }
       } else {
         for (int64_t rb = r0; rb < r1; rb += 32) {
           bf16x8 hi[NT], lo[NT];
+          float xs[NT][8];
           static_for<0, NT>([&](auto tt) {
             constexpr int t = decltype(tt)::value;
             const int col = 16 * t + (lane & 15);
+            const int colc = col < R ? col : R - 1;
 #pragma unroll
             for (int j = 0; j < 8; ++j) {
               const int64_t row = rb + 8 * (lane >> 4) + j;
-              const float x = (row < r1 && col < R) ? U[row * R + col] : 0.f;
+              xs[t][j] = U[(row < r1 ? row : r1 - 1) * R + colc];
+            }
+          });
+          static_for<0, NT>([&](auto tt) {
+            constexpr int t = decltype(tt)::value;
+            const bool cv = 16 * t + (lane & 15) < R;
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+              const int64_t row = rb + 8 * (lane >> 4) + j;
+              const float x = (cv && row < r1) ? xs[t][j] : 0.f;
               const __bf16 h = (__bf16)x;
               hi[t][j] = h;
               lo[t][j] = (__bf16)(x - (float)h);
@@ -171,8 +202,11 @@ __device__ __forceinline__ void unpack_index(int64_t p, int R, int& a, int& b) {
   b = aa + (int)(p - packed_index(aa, aa, R));
 }
 
-constexpr int S2MAX = 6;
+constexpr int S2 = 3;  // levels summed per upsweep pass
 
+// One thread per packed entry and per group of 2^S2 consecutive nodes of
+// level lev_in; the group's subtree is summed with a binary counter whose
+// saved left siblings sit in registers (the loop is unrolled).
 template <typename T>
 __global__ __launch_bounds__(256) void node_upsweep_kernel(const double* __restrict__ in,
                                                            int64_t n_in, int lev_in, int s2, int R,
@@ -180,15 +214,23 @@ __global__ __launch_bounds__(256) void node_upsweep_kernel(const double* __restr
                                                            double* __restrict__ out,
                                                            double* __restrict__ gram_full) {
   const int64_t TR = (int64_t)R * (R + 1) / 2;
-  const int64_t g = blockIdx.x;
-  for (int64_t p = threadIdx.x; p < TR; p += blockDim.x) {
-    double stack[S2MAX];
-    for (int u = 0; u < (1 << s2); ++u) {
+  const int64_t ng = (n_in + (int64_t(1) << s2) - 1) >> s2;
+  const int64_t total = ng * TR;
+  for (int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; gid < total;
+       gid += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t g = gid / TR;
+    const int64_t p = gid % TR;
+    double stack[S2];
+#pragma unroll
+    for (int u = 0; u < (1 << S2); ++u) {
+      if (u >= (1 << s2)) break;
       int64_t pos = (g << s2) + u;
       double v = pos < n_in ? in[pos * TR + p] : 0.0;
       int t = __builtin_ctz(~(unsigned)u);
       if (t > s2) t = s2;
-      for (int m = 0; m < t; ++m) v += stack[m];
+#pragma unroll
+      for (int m = 0; m < S2; ++m)
+        if (m < t) v += stack[m];
       const int lev = lev_in - t;
       pos >>= t;
       if (t == s2) {
@@ -204,7 +246,9 @@ __global__ __launch_bounds__(256) void node_upsweep_kernel(const double* __restr
       } else {
         if (nodes != nullptr && pos < ((L - 1) >> (D - lev)) + 1)
           nodes[(level_offset(L, D, lev) + (pos >> 1)) * TR + p] = (T)v;
-        stack[t] = v;
+#pragma unroll
+        for (int m = 0; m < S2; ++m)
+          if (m == t) stack[m] = v;
       }
     }
   }
@@ -234,10 +278,12 @@ hipError_t dispatch_leaf(hipStream_t st, const void* U, int64_t I, int R, int F,
     if (R <= 64) return run_leaf<MODE, 4, 2, 3>(st, U, I, R, F, L, D, nodes, tops, s_eff);
     return run_leaf<MODE, 8, 4, 2>(st, U, I, R, F, L, D, nodes, tops, s_eff);
   } else {
-    if (R <= 16) return run_leaf<MODE, 1, 1, 3>(st, U, I, R, F, L, D, nodes, tops, s_eff);
-    if (R <= 32) return run_leaf<MODE, 2, 1, 3>(st, U, I, R, F, L, D, nodes, tops, s_eff);
-    if (R <= 64) return run_leaf<MODE, 4, 4, 2>(st, U, I, R, F, L, D, nodes, tops, s_eff);
-    return run_leaf<MODE, 8, 8, 2>(st, U, I, R, F, L, D, nodes, tops, s_eff);
+    // one or two float64 accumulator tiles per wave keep the register run
+    // (binary-counter stack) small enough for several waves per SIMD
+    if (R <= 16) return run_leaf<MODE, 1, 1, 4>(st, U, I, R, F, L, D, nodes, tops, s_eff);
+    if (R <= 32) return run_leaf<MODE, 2, 3, 4>(st, U, I, R, F, L, D, nodes, tops, s_eff);
+    if (R <= 64) return run_leaf<MODE, 4, 5, 3>(st, U, I, R, F, L, D, nodes, tops, s_eff);
+    return run_leaf<MODE, 8, 12, 2>(st, U, I, R, F, L, D, nodes, tops, s_eff);
   }
 }
 
@@ -273,14 +319,16 @@ hipError_t launch_tree_build(hipStream_t st, krps_precision p, const void* U, in
   double* cur = bufA;
   double* nxt = bufB;
   for (;;) {
-    const int s2 = lev < S2MAX ? lev : S2MAX;
+    const int s2 = lev < S2 ? lev : S2;
     const int64_t ng = ceil_div(n, int64_t(1) << s2);
+    int64_t blocks = ceil_div(ng * TR, 256);
+    if (blocks > 4096) blocks = 4096;
     if (p == KRPS_FP64)
-      hipLaunchKernelGGL(node_upsweep_kernel<double>, dim3((unsigned)ng), dim3(256), 0, st, cur, n,
-                         lev, s2, R, ts.L, ts.D, (double*)nodes, nxt, gram_full);
+      hipLaunchKernelGGL(node_upsweep_kernel<double>, dim3((unsigned)blocks), dim3(256), 0, st, cur,
+                         n, lev, s2, R, ts.L, ts.D, (double*)nodes, nxt, gram_full);
     else
-      hipLaunchKernelGGL(node_upsweep_kernel<float>, dim3((unsigned)ng), dim3(256), 0, st, cur, n,
-                         lev, s2, R, ts.L, ts.D, (float*)nodes, nxt, gram_full);
+      hipLaunchKernelGGL(node_upsweep_kernel<float>, dim3((unsigned)blocks), dim3(256), 0, st, cur,
+                         n, lev, s2, R, ts.L, ts.D, (float*)nodes, nxt, gram_full);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
     if (lev - s2 == 0) break;
