@@ -156,6 +156,81 @@ krps_status krps_row_prob(krps_sampler s, int exclude, int64_t M, const int32_t*
                           double* prob, void* ws, size_t ws_bytes);
 
 /* ------------------------------------------------------------------ */
+/* Sparse tensor and sketched CP-ALS (Sec. 3.3, Alg. 6, Appendix A.9)  */
+/* ------------------------------------------------------------------ */
+
+/* Bytes of persistent workspace for a sparse tensor of N modes with the
+ * given dims and nnz stored entries: per mode j the entries sorted by the
+ * other modes' indices (increasing mode order, then i_j), i.e. grouped into
+ * the mode-j fibers that rows of mat(T, j)^T select, plus an offset table
+ * over the leading other mode; and the sort's scratch. */
+krps_status krps_tensor_workspace_bytes(int N, const int64_t* dims, int64_t nnz, size_t* bytes);
+
+/* Builds the per-mode fiber index of a COO tensor on the device.
+ *   idx  device int32 [nnz][N], 0 <= idx[e][k] < dims[k] (not checked on
+ *        the device; out-of-range indices give undefined results)
+ *   val  device float32 [nnz]; duplicate coordinates are allowed and mean
+ *        the sum of their values.
+ * idx and val are read during this call only (the workspace keeps sorted
+ * copies).  Synchronises the stream once (sort sizing) and computes
+ * ||T||_F^2 of the tensor with duplicates summed. */
+krps_status krps_tensor_create(krps_ctx ctx, int N, const int64_t* dims, int64_t nnz,
+                               const int32_t* idx, const float* val, void* ws, size_t ws_bytes,
+                               krps_tensor* out);
+krps_status krps_tensor_destroy(krps_tensor t);
+/* ||T||_F^2 (host value; valid after krps_tensor_create returned). */
+krps_status krps_tensor_norm2(krps_tensor t, double* out);
+
+/* Bytes of scratch for one sketched solve / sweep / fit with J samples. */
+krps_status krps_solve_workspace_bytes(krps_sampler s, krps_tensor t, int64_t J, size_t* bytes);
+
+/* Algorithm 6 lines 1-3 for factor j: sigma = column norms of U_j, then
+ * U_j[:, i] /= sigma[i] (zero columns stay zero) and Z_j, G_j are rebuilt.
+ * sigma: device float64 [R] out (may be NULL). */
+krps_status krps_normalize_factor(krps_sampler s, int j, double* sigma, void* ws, size_t ws_bytes);
+
+/* One STS-CP solve (Sec. 3.3; Algorithm 6 lines 6-8 with the sampled
+ * solve): draw J rows of U_{!=j} by leverage (uniforms as in krps_sample),
+ * form M = (SA)^T SA and Y = (SB)^T SA with S's weights 1/sqrt(J q_d)
+ * (Sec. 2.1) and the sampled mode-j fibers of T, set
+ * U_j = Y M^+ (float64 eigen-pseudo-inverse), sigma = its column norms,
+ * renormalise U_j in place and rebuild Z_j and G_j.
+ *   sigma  device float64 [R] out.
+ * The sampler's U[j] buffer is overwritten. */
+krps_status krps_sketched_solve(krps_sampler s, krps_tensor t, int j, int64_t J,
+                                const double* uniforms, double* sigma, void* ws, size_t ws_bytes);
+
+/* One ALS sweep: krps_sketched_solve for j = 0..N-1 in order (Alg. 6
+ * lines 5-9).  uniforms: device float64 [N][J][N][2], block j for solve j.
+ * With use_graph != 0 the sweep is captured once into a HIP graph (keyed by
+ * the argument pointers) and replayed on later calls with the same
+ * arguments; a null context stream is captured on a stream of the
+ * context's own and replayed on the null stream. */
+krps_status krps_als_sweep(krps_sampler s, krps_tensor t, int64_t J, const double* uniforms,
+                           double* sigma, void* ws, size_t ws_bytes, int use_graph);
+
+/* fit = 1 - ||T~ - T||_F / ||T||_F for T~ = [sigma; U_1..U_N] (Sec. 4.3),
+ * with ||T~||^2 = sigma^T ((*)_k G_k) sigma and <T, T~> over the stored
+ * entries.  sigma: device float64 [R].  fit: host out (synchronises). */
+krps_status krps_fit(krps_sampler s, krps_tensor t, const double* sigma, double* fit, void* ws,
+                     size_t ws_bytes);
+
+/* Offsets (bytes into the solve workspace) of the last solve's pieces. */
+typedef struct {
+  size_t idx;      /* int32 [J][N] sampled multi-indices */
+  size_t prob;     /* float64 [J] q_d */
+  size_t w;        /* float64 [J] 1/sqrt(J q_d) */
+  size_t rows;     /* [J][R] w_d a_d (rows of S A): float64, float32 for KRPS_BF16X2 */
+  size_t M;        /* float64 [R][R] (S A)^T S A */
+  size_t Mp;       /* float64 [R][R] its pseudo-inverse */
+  size_t Y;        /* float64 [I_j][R] (S B)^T S A */
+  size_t draw;     /* per-draw scratch (krps_draw_layout offsets are relative to this) */
+} krps_solve_layout;
+
+krps_status krps_solve_layout_query(krps_sampler s, krps_tensor t, int64_t J,
+                                    krps_solve_layout* out);
+
+/* ------------------------------------------------------------------ */
 /* Introspection (tests and benchmarks)                                */
 /* ------------------------------------------------------------------ */
 

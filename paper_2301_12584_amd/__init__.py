@@ -42,6 +42,10 @@ class DrawLayout(ctypes.Structure):
                 ("n_enodes", ctypes.c_int64)]
 
 
+class SolveLayout(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_size_t) for n in ("idx", "prob", "w", "rows", "M", "Mp", "Y", "draw")]
+
+
 def declared_symbols():
     """Function names declared in include/krps.h."""
     text = open(HEADER).read()
@@ -75,6 +79,18 @@ def lib():
         "krps_sample_prepare": (c.c_int, [P, c.c_int, P, c.c_size_t]),
         "krps_sample_draw": (c.c_int, [P, c.c_int, c.c_int64, P, P, P, P, P, c.c_size_t]),
         "krps_row_prob": (c.c_int, [P, c.c_int, c.c_int64, P, P, P, c.c_size_t]),
+        "krps_tensor_workspace_bytes": (c.c_int, [c.c_int, c.POINTER(c.c_int64), c.c_int64,
+                                                  c.POINTER(c.c_size_t)]),
+        "krps_tensor_create": (c.c_int, [P, c.c_int, c.POINTER(c.c_int64), c.c_int64, P, P, P,
+                                         c.c_size_t, c.POINTER(P)]),
+        "krps_tensor_destroy": (c.c_int, [P]),
+        "krps_tensor_norm2": (c.c_int, [P, c.POINTER(c.c_double)]),
+        "krps_solve_workspace_bytes": (c.c_int, [P, P, c.c_int64, c.POINTER(c.c_size_t)]),
+        "krps_solve_layout_query": (c.c_int, [P, P, c.c_int64, c.POINTER(SolveLayout)]),
+        "krps_normalize_factor": (c.c_int, [P, c.c_int, P, P, c.c_size_t]),
+        "krps_sketched_solve": (c.c_int, [P, P, c.c_int, c.c_int64, P, P, P, c.c_size_t]),
+        "krps_als_sweep": (c.c_int, [P, P, c.c_int64, P, P, P, c.c_size_t, c.c_int]),
+        "krps_fit": (c.c_int, [P, P, P, c.POINTER(c.c_double), P, c.c_size_t]),
         "krps_sampler_tree_info": (c.c_int, [P, c.c_int, c.POINTER(TreeInfo)]),
         "krps_draw_layout_query": (c.c_int, [P, c.POINTER(DrawLayout)]),
     }
@@ -247,3 +263,98 @@ class Sampler:
         if getattr(self, "handle", None) is not None and _lib is not None:
             _lib.krps_sampler_destroy(self.handle)
             self.handle = None
+
+
+class Tensor:
+    """Sparse COO tensor with its per-mode fiber index on the device.
+    ``idx``: int32 CUDA tensor ``[nnz, N]``, ``val``: float32 ``[nnz]``."""
+
+    def __init__(self, ctx: Context, dims, idx, val):
+        torch = ctx.torch
+        self.ctx = ctx
+        self.dims = [int(d) for d in dims]
+        self.N = len(self.dims)
+        self.nnz = int(val.shape[0])
+        if idx.dtype != torch.int32 or val.dtype != torch.float32:
+            raise ValueError("idx must be int32 and val float32")
+        idx = idx.contiguous()
+        val = val.contiguous()
+        arr = (ctypes.c_int64 * self.N)(*self.dims)
+        nb = ctypes.c_size_t()
+        check(lib().krps_tensor_workspace_bytes(self.N, arr, self.nnz, ctypes.byref(nb)))
+        self.ws = torch.empty(nb.value, dtype=torch.uint8, device=ctx.device)
+        h = ctypes.c_void_p()
+        check(lib().krps_tensor_create(ctx.handle, self.N, arr, self.nnz, _ptr(idx), _ptr(val),
+                                       _ptr(self.ws), nb.value, ctypes.byref(h)))
+        self.handle = h
+
+    @property
+    def norm2(self):
+        v = ctypes.c_double()
+        check(lib().krps_tensor_norm2(self.handle, ctypes.byref(v)))
+        return v.value
+
+    def __del__(self):
+        if getattr(self, "handle", None) is not None and _lib is not None:
+            _lib.krps_tensor_destroy(self.handle)
+            self.handle = None
+
+
+class CPALS:
+    """Sketched CP-ALS state: a sampler over the factors, a tensor and the
+    solve workspace for J samples per solve."""
+
+    def __init__(self, sampler: Sampler, tensor: Tensor, J):
+        torch = sampler.ctx.torch
+        self.S, self.T, self.J = sampler, tensor, int(J)
+        nb = ctypes.c_size_t()
+        check(lib().krps_solve_workspace_bytes(sampler.handle, tensor.handle, self.J,
+                                               ctypes.byref(nb)))
+        self.ws = torch.empty(nb.value, dtype=torch.uint8, device=sampler.ctx.device)
+        self.sigma = torch.ones(sampler.R, dtype=torch.float64, device=sampler.ctx.device)
+        lay = SolveLayout()
+        check(lib().krps_solve_layout_query(sampler.handle, tensor.handle, self.J,
+                                            ctypes.byref(lay)))
+        self.layout = lay
+
+    def normalize(self, j):
+        check(lib().krps_normalize_factor(self.S.handle, int(j), _ptr(self.sigma), _ptr(self.ws),
+                                          self.ws.numel()))
+
+    def solve(self, j, uniforms):
+        check(lib().krps_sketched_solve(self.S.handle, self.T.handle, int(j), self.J,
+                                        _ptr(uniforms), _ptr(self.sigma), _ptr(self.ws),
+                                        self.ws.numel()))
+
+    def sweep(self, uniforms, use_graph=False):
+        check(lib().krps_als_sweep(self.S.handle, self.T.handle, self.J, _ptr(uniforms),
+                                   _ptr(self.sigma), _ptr(self.ws), self.ws.numel(),
+                                   1 if use_graph else 0))
+
+    def fit(self):
+        v = ctypes.c_double()
+        check(lib().krps_fit(self.S.handle, self.T.handle, _ptr(self.sigma), ctypes.byref(v),
+                             _ptr(self.ws), self.ws.numel()))
+        return v.value
+
+    def parts(self, j):
+        """Views of the last solve's pieces (for mode ``j``'s Y height)."""
+        torch = self.S.ctx.torch
+        l, R, N, J = self.layout, self.S.R, self.S.N, self.J
+        ws = self.ws
+        es = 8 if self.S.precision == "fp64" else 4
+        dt = torch.float64 if es == 8 else torch.float32
+
+        def view(off, n, dtype, nb):
+            return ws[off:off + n * nb].view(dtype)
+
+        return {
+            "idx": view(l.idx, J * N, torch.int32, 4).view(J, N).clone(),
+            "prob": view(l.prob, J, torch.float64, 8).clone(),
+            "w": view(l.w, J, torch.float64, 8).clone(),
+            "rows": (view(l.rows, J * R, torch.float32, 4) if self.S.precision == "bf16x2"
+                     else view(l.rows, J * R, torch.float64, 8)).view(J, R).clone(),
+            "M": view(l.M, R * R, torch.float64, 8).view(R, R).clone(),
+            "Mp": view(l.Mp, R * R, torch.float64, 8).view(R, R).clone(),
+            "Y": view(l.Y, self.S.dims[j] * R, torch.float64, 8).view(self.S.dims[j], R).clone(),
+        }

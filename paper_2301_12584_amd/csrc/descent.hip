@@ -305,7 +305,7 @@ __global__ __launch_bounds__(64 * DESC_WAVES) void descent_kernel(DescentArgs a)
     }
     if (a.exclude >= 0 && sl == 0 && active) a.idx[d * N + a.exclude] = -1;
     // ---- probability of the sampled row: q = a G^+ a^T / rank
-    if (a.prob != nullptr || a.rows != nullptr || a.wout != nullptr) {
+    if (a.prob != nullptr || a.rows != nullptr || a.rows64 != nullptr || a.wout != nullptr) {
 #pragma unroll
       for (int i = 0; i < HE; ++i)
         if (sl + LPS * i < R) hb[sl + LPS * i] = h[i];
@@ -316,13 +316,21 @@ __global__ __launch_bounds__(64 * DESC_WAVES) void descent_kernel(DescentArgs a)
         if (sl == 0 && a.prob != nullptr) a.prob[d] = q;
         const double w = 1.0 / sqrt((double)J * q);
         if (sl == 0 && a.wout != nullptr) a.wout[d] = w;
+        const double sc = a.scale_rows ? w : 1.0;
         if (a.rows != nullptr) {
           T* rows = (T*)a.rows + d * R;
-          const double sc = a.scale_rows ? w : 1.0;
 #pragma unroll
           for (int i = 0; i < HE; ++i) {
             const int e = sl + LPS * i;
             if (e < R) rows[e] = (T)(h[i] * sc);
+          }
+        }
+        if (a.rows64 != nullptr) {
+          double* rows = a.rows64 + d * R;
+#pragma unroll
+          for (int i = 0; i < HE; ++i) {
+            const int e = sl + LPS * i;
+            if (e < R) rows[e] = h[i] * sc;
           }
         }
       }

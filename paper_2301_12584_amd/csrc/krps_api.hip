@@ -2,6 +2,7 @@
 // launches of the sampler kernels.  Host code only; every computation runs
 // in the kernels of tree_build.hip, eig.hip and descent.hip.
 #include <cstdio>
+#include <cmath>
 #include <cstdlib>
 #include <cstring>
 #include <new>
@@ -31,6 +32,7 @@ using namespace krps;
 struct krps_ctx_s {
   int device;
   hipStream_t stream;
+  hipStream_t capture = nullptr;  // own stream for graph capture when `stream` is null
 };
 
 struct krps_sampler_s {
@@ -51,9 +53,25 @@ struct krps_sampler_s {
   const void* prepared_ws = nullptr;  // ws of the last preparation
   int prepared_exclude = -2;
   int lps = 0;                         // descent lanes per sample (0 = default)
+  // captured ALS sweep
+  hipGraphExec_t sweep_exec = nullptr;
+  const void* g_key[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
+  int64_t g_J = -1;
   size_t draw_bytes;
   int64_t enodes;
   int DE;
+};
+
+struct krps_tensor_s {
+  krps_ctx ctx;
+  int N;
+  int64_t nnz;
+  std::vector<int64_t> dims;
+  std::vector<int32_t*> cols;  // per mode: [N][nnz]
+  std::vector<float*> vals;    // per mode: [nnz]
+  std::vector<int64_t*> off;   // per mode: [dims[lead] + 1]
+  std::vector<int> lead;
+  double norm2 = 0;
 };
 
 namespace {
@@ -207,6 +225,174 @@ void fill_descent_args(krps_sampler s, int exclude, void* ws, DescentArgs& a) {
   a.lps = s->lps;
 }
 
+// ------------------------------------------------------------ tensor plan
+
+struct TensorPlan {
+  std::vector<size_t> cols_off, vals_off, off_off;
+  std::vector<int> lead;
+  size_t k0 = 0, k1 = 0, p0 = 0, p1 = 0, temp = 0, temp_bytes = 0, acc = 0, total = 0;
+};
+
+TensorPlan plan_tensor(int N, const int64_t* dims, int64_t nnz) {
+  TensorPlan pl;
+  size_t off = 0;
+  for (int j = 0; j < N; ++j) {
+    const int lead = N == 1 ? 0 : (j == 0 ? 1 : 0);
+    pl.lead.push_back(lead);
+    pl.cols_off.push_back(off);
+    off += align_up((size_t)N * nnz * 4);
+    pl.vals_off.push_back(off);
+    off += align_up((size_t)nnz * 4);
+    pl.off_off.push_back(off);
+    off += align_up((size_t)(dims[lead] + 1) * 8);
+  }
+  pl.k0 = off;
+  off += align_up((size_t)nnz * 4);
+  pl.k1 = off;
+  off += align_up((size_t)nnz * 4);
+  pl.p0 = off;
+  off += align_up((size_t)nnz * 4);
+  pl.p1 = off;
+  off += align_up((size_t)nnz * 4);
+  pl.temp = off;
+  pl.temp_bytes = sort_temp_bytes(nnz);
+  off += align_up(pl.temp_bytes);
+  pl.acc = off;
+  off += 256;
+  pl.total = off;
+  return pl;
+}
+
+// ------------------------------------------------------------- solve plan
+
+struct SolvePlan {
+  krps_solve_layout lay;
+  size_t lo, hi, cnt, start, rank, partial, gscratch, gscratch_bytes, fitp, fitout, sig;
+  size_t total;
+  int64_t Imax;
+};
+
+SolvePlan plan_solve(krps_sampler s, int64_t J) {
+  SolvePlan pl;
+  const int R = s->R, N = s->N;
+  const int es = s->elem;
+  int64_t Imax = 0;
+  for (int j = 0; j < N; ++j) Imax = s->I[j] > Imax ? s->I[j] : Imax;
+  pl.Imax = Imax;
+  size_t off = 0;
+  krps_solve_layout& l = pl.lay;
+  l.draw = off;
+  off += align_up(s->draw_bytes);
+  l.idx = off;
+  off += align_up((size_t)J * N * 4);
+  l.prob = off;
+  off += align_up((size_t)J * 8);
+  l.w = off;
+  off += align_up((size_t)J * 8);
+  l.rows = off;
+  off += align_up((size_t)J * R * 8);
+  pl.lo = off;
+  off += align_up((size_t)J * 8);
+  pl.hi = off;
+  off += align_up((size_t)J * 8);
+  pl.cnt = off;
+  off += align_up((size_t)J * 8);
+  pl.start = off;
+  off += align_up((size_t)(J + 1) * 8);
+  l.M = off;
+  off += align_up((size_t)R * R * 8);
+  l.Mp = off;
+  off += align_up((size_t)R * R * 8);
+  pl.rank = off;
+  off += 256;
+  l.Y = off;
+  off += align_up((size_t)Imax * R * 8);
+  pl.partial = off;
+  off += align_up(solve_partial_bytes(R));
+  TreeShape tm;
+  tm.init(J > 0 ? J : 1, R);
+  pl.gscratch = off;
+  pl.gscratch_bytes = tree_build_scratch_bytes(tm.L, R);
+  off += align_up(pl.gscratch_bytes);
+  pl.fitp = off;
+  off += align_up(fit_partial_bytes());
+  pl.fitout = off;
+  off += 256;
+  pl.sig = off;
+  off += align_up((size_t)R * 8);
+  pl.total = off;
+  return pl;
+}
+
+krps_status check_pair(krps_sampler s, krps_tensor t) {
+  if (s == nullptr || t == nullptr) return fail(KRPS_EINVAL, "sampler/tensor is NULL");
+  if (s->N != t->N) return fail(KRPS_EINVAL, "sampler and tensor have different N");
+  for (int k = 0; k < s->N; ++k)
+    if (s->I[k] != t->dims[k]) return fail(KRPS_EINVAL, "factor heights differ from tensor dims");
+  return KRPS_OK;
+}
+
+// Enqueues one sketched solve of mode j.
+krps_status enqueue_solve(krps_sampler s, krps_tensor t, int j, int64_t J, const double* uniforms,
+                          double* sigma, char* w, const SolvePlan& pl) {
+  const int R = s->R, N = s->N;
+  hipStream_t st = s->ctx->stream;
+  const krps_solve_layout& l = pl.lay;
+  DescentArgs a;
+  krps_status rs = prepare_draw(s, j, w + l.draw, a);
+  if (rs != KRPS_OK) return rs;
+  // rows of S A = w_d a_d: float64 for the float64 and float32 paths (the
+  // Gram M and Y are then formed in float64), float32 for the bf16 split
+  const bool split = s->prec == KRPS_BF16X2;
+  a.J = J;
+  a.u01 = uniforms;
+  a.idx = (int32_t*)(w + l.idx);
+  a.prob = (double*)(w + l.prob);
+  if (split)
+    a.rows = w + l.rows;
+  else
+    a.rows64 = (double*)(w + l.rows);
+  a.wout = (double*)(w + l.w);
+  a.scale_rows = 1;
+  hipError_t e = launch_descent(st, s->prec, a);
+  if (e != hipSuccess) return hip_fail(e, "descent launch");
+  // M = (S A)^T (S A): the Gram of the scaled sampled rows, by the tree
+  // builder without stored nodes
+  TreeShape tm;
+  tm.init(J, R);
+  e = launch_tree_build(st, split ? KRPS_BF16X2 : KRPS_FP64, w + l.rows, J, R, tm, nullptr,
+                        (double*)(w + l.M), (double*)(w + pl.gscratch), pl.gscratch_bytes);
+  if (e != hipSuccess) return hip_fail(e, "Gram of sampled rows");
+  e = launch_pinv(st, R, (double*)(w + l.M), (double*)(w + l.Mp), (int32_t*)(w + pl.rank));
+  if (e != hipSuccess) return hip_fail(e, "pseudo-inverse");
+  e = launch_fill_f64(st, (double*)(w + l.Y), s->I[j] * R);
+  if (e != hipSuccess) return hip_fail(e, "Y clear");
+  FiberArgs fa;
+  fa.N = N;
+  fa.j = j;
+  fa.lead = t->lead[j];
+  fa.R = R;
+  fa.nnz = t->nnz;
+  fa.J = J;
+  fa.cols = t->cols[j];
+  fa.vals = t->vals[j];
+  fa.off = t->off[j];
+  fa.sample_idx = (const int32_t*)(w + l.idx);
+  fa.lo = (int64_t*)(w + pl.lo);
+  fa.hi = (int64_t*)(w + pl.hi);
+  fa.cnt = (int64_t*)(w + pl.cnt);
+  fa.start = (int64_t*)(w + pl.start);
+  e = launch_lookup(st, fa);
+  if (e != hipSuccess) return hip_fail(e, "fiber lookup");
+  e = launch_spmm(st, split ? KRPS_BF16X2 : KRPS_FP64, fa, w + l.rows, (const double*)(w + l.w),
+                  w + l.Y);
+  if (e != hipSuccess) return hip_fail(e, "SpMM");
+  e = launch_solve_gemm(st, s->prec, w + l.Y, (const double*)(w + l.Mp), s->U[j], s->I[j], R,
+                        (double*)(w + pl.partial), sigma);
+  if (e != hipSuccess) return hip_fail(e, "solve GEMM");
+  return build_tree(s, j);
+}
+
 }  // namespace
 
 extern "C" {
@@ -229,6 +415,7 @@ krps_status krps_ctx_create(int device, void* hip_stream, krps_ctx* out) {
 }
 
 krps_status krps_ctx_destroy(krps_ctx ctx) {
+  if (ctx != nullptr && ctx->capture != nullptr) (void)hipStreamDestroy(ctx->capture);
   delete ctx;
   return KRPS_OK;
 }
@@ -314,6 +501,7 @@ krps_status krps_sampler_refresh(krps_sampler s, int j) {
 }
 
 krps_status krps_sampler_destroy(krps_sampler s) {
+  if (s != nullptr && s->sweep_exec != nullptr) (void)hipGraphExecDestroy(s->sweep_exec);
   delete s;
   return KRPS_OK;
 }
@@ -420,6 +608,219 @@ krps_status krps_sampler_tree_info(krps_sampler s, int j, krps_tree_info* out) {
 krps_status krps_draw_layout_query(krps_sampler s, krps_draw_layout* out) {
   if (s == nullptr || out == nullptr) return fail(KRPS_EINVAL, "sampler/out is NULL");
   *out = s->lay;
+  return KRPS_OK;
+}
+
+krps_status krps_tensor_workspace_bytes(int N, const int64_t* dims, int64_t nnz, size_t* bytes) {
+  krps_status st = check_dims(N, dims, 1);
+  if (st != KRPS_OK) return st;
+  if (nnz < 1 || nnz > (int64_t)UINT32_MAX) return fail(KRPS_EINVAL, "nnz must be in [1, 2^32)");
+  if (bytes == nullptr) return fail(KRPS_EINVAL, "bytes is NULL");
+  *bytes = plan_tensor(N, dims, nnz).total;
+  return KRPS_OK;
+}
+
+krps_status krps_tensor_create(krps_ctx ctx, int N, const int64_t* dims, int64_t nnz,
+                               const int32_t* idx, const float* val, void* ws, size_t ws_bytes,
+                               krps_tensor* out) {
+  if (ctx == nullptr || out == nullptr) return fail(KRPS_EINVAL, "ctx/out is NULL");
+  krps_status st = check_dims(N, dims, 1);
+  if (st != KRPS_OK) return st;
+  if (nnz < 1 || nnz > (int64_t)UINT32_MAX) return fail(KRPS_EINVAL, "nnz must be in [1, 2^32)");
+  if (idx == nullptr || val == nullptr || ws == nullptr)
+    return fail(KRPS_EINVAL, "idx/val/workspace is NULL");
+  TensorPlan pl = plan_tensor(N, dims, nnz);
+  if (ws_bytes < pl.total) return fail(KRPS_EWORKSPACE, "tensor workspace too small");
+  krps_tensor t = new (std::nothrow) krps_tensor_s;
+  if (t == nullptr) return fail(KRPS_EINVAL, "out of host memory");
+  t->ctx = ctx;
+  t->N = N;
+  t->nnz = nnz;
+  char* w = (char*)ws;
+  for (int j = 0; j < N; ++j) {
+    t->dims.push_back(dims[j]);
+    t->cols.push_back((int32_t*)(w + pl.cols_off[j]));
+    t->vals.push_back((float*)(w + pl.vals_off[j]));
+    t->off.push_back((int64_t*)(w + pl.off_off[j]));
+    t->lead.push_back(pl.lead[j]);
+  }
+  hipStream_t s = ctx->stream;
+  for (int j = 0; j < N; ++j) {
+    hipError_t e = build_fiber_index(s, N, dims, nnz, idx, val, j, t->cols[j], t->vals[j],
+                                     t->off[j], (uint32_t*)(w + pl.k0), (uint32_t*)(w + pl.k1),
+                                     (uint32_t*)(w + pl.p0), (uint32_t*)(w + pl.p1), w + pl.temp,
+                                     pl.temp_bytes);
+    if (e != hipSuccess) {
+      delete t;
+      return hip_fail(e, "fiber index build");
+    }
+  }
+  double* acc = (double*)(w + pl.acc);
+  hipError_t e = launch_fill_f64(s, acc, 1);
+  if (e == hipSuccess) e = launch_norm2(s, t->cols[0], t->vals[0], N, nnz, acc);
+  if (e == hipSuccess) e = hipMemcpyAsync(&t->norm2, acc, 8, hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) {
+    delete t;
+    return hip_fail(e, "tensor norm");
+  }
+  *out = t;
+  return KRPS_OK;
+}
+
+krps_status krps_tensor_destroy(krps_tensor t) {
+  delete t;
+  return KRPS_OK;
+}
+
+krps_status krps_tensor_norm2(krps_tensor t, double* out) {
+  if (t == nullptr || out == nullptr) return fail(KRPS_EINVAL, "tensor/out is NULL");
+  *out = t->norm2;
+  return KRPS_OK;
+}
+
+krps_status krps_solve_workspace_bytes(krps_sampler s, krps_tensor t, int64_t J, size_t* bytes) {
+  krps_status st = check_pair(s, t);
+  if (st != KRPS_OK) return st;
+  if (J < 1) return fail(KRPS_EINVAL, "J must be >= 1");
+  if (bytes == nullptr) return fail(KRPS_EINVAL, "bytes is NULL");
+  *bytes = plan_solve(s, J).total;
+  return KRPS_OK;
+}
+
+krps_status krps_solve_layout_query(krps_sampler s, krps_tensor t, int64_t J,
+                                    krps_solve_layout* out) {
+  krps_status st = check_pair(s, t);
+  if (st != KRPS_OK) return st;
+  if (J < 1 || out == nullptr) return fail(KRPS_EINVAL, "J < 1 or out is NULL");
+  *out = plan_solve(s, J).lay;
+  return KRPS_OK;
+}
+
+krps_status krps_normalize_factor(krps_sampler s, int j, double* sigma, void* ws, size_t ws_bytes) {
+  if (s == nullptr) return fail(KRPS_EINVAL, "sampler is NULL");
+  if (j < 0 || j >= s->N) return fail(KRPS_EINVAL, "j out of range");
+  if (ws == nullptr || ws_bytes < solve_partial_bytes(s->R) + align_up((size_t)s->R * 8))
+    return fail(KRPS_EWORKSPACE, "workspace too small");
+  double* partial = (double*)ws;
+  double* sg = sigma != nullptr ? sigma : (double*)((char*)ws + align_up(solve_partial_bytes(s->R)));
+  hipStream_t st = s->ctx->stream;
+  hipError_t e = launch_colnorm(st, s->prec, s->U[j], s->I[j], s->R, partial, sg);
+  if (e == hipSuccess) e = launch_normalize(st, s->prec, s->U[j], s->I[j], s->R, sg);
+  if (e != hipSuccess) return hip_fail(e, "normalise factor");
+  return build_tree(s, j);
+}
+
+krps_status krps_sketched_solve(krps_sampler s, krps_tensor t, int j, int64_t J,
+                                const double* uniforms, double* sigma, void* ws, size_t ws_bytes) {
+  krps_status st = check_pair(s, t);
+  if (st != KRPS_OK) return st;
+  if (s->N < 2) return fail(KRPS_EINVAL, "a solve needs N >= 2");
+  if (j < 0 || j >= s->N) return fail(KRPS_EINVAL, "j out of range");
+  if (J < 1) return fail(KRPS_EINVAL, "J must be >= 1");
+  if (uniforms == nullptr || sigma == nullptr || ws == nullptr)
+    return fail(KRPS_EINVAL, "uniforms/sigma/workspace is NULL");
+  SolvePlan pl = plan_solve(s, J);
+  if (ws_bytes < pl.total) return fail(KRPS_EWORKSPACE, "solve workspace too small");
+  st = enqueue_solve(s, t, j, J, uniforms, sigma, (char*)ws, pl);
+  s->prepared_ws = nullptr;
+  return st;
+}
+
+krps_status krps_als_sweep(krps_sampler s, krps_tensor t, int64_t J, const double* uniforms,
+                           double* sigma, void* ws, size_t ws_bytes, int use_graph) {
+  krps_status st = check_pair(s, t);
+  if (st != KRPS_OK) return st;
+  if (s->N < 2) return fail(KRPS_EINVAL, "a sweep needs N >= 2");
+  if (J < 1) return fail(KRPS_EINVAL, "J must be >= 1");
+  if (uniforms == nullptr || sigma == nullptr || ws == nullptr)
+    return fail(KRPS_EINVAL, "uniforms/sigma/workspace is NULL");
+  SolvePlan pl = plan_solve(s, J);
+  if (ws_bytes < pl.total) return fail(KRPS_EWORKSPACE, "solve workspace too small");
+  hipStream_t stream = s->ctx->stream;
+  const size_t ublock = (size_t)J * s->N * 2;
+  auto enqueue_all = [&]() -> krps_status {
+    for (int j = 0; j < s->N; ++j) {
+      krps_status r = enqueue_solve(s, t, j, J, uniforms + j * ublock, sigma, (char*)ws, pl);
+      if (r != KRPS_OK) return r;
+    }
+    return KRPS_OK;
+  };
+  if (!use_graph) {
+    st = enqueue_all();
+    s->prepared_ws = nullptr;
+    return st;
+  }
+  const void* key[5] = {t, uniforms, sigma, ws, (const void*)(intptr_t)J};
+  bool same = s->sweep_exec != nullptr && s->g_J == J;
+  for (int i = 0; i < 5 && same; ++i) same = s->g_key[i] == key[i];
+  if (!same) {
+    if (s->sweep_exec != nullptr) {
+      (void)hipGraphExecDestroy(s->sweep_exec);
+      s->sweep_exec = nullptr;
+    }
+    // the null stream cannot be captured: capture on the context's own
+    // stream, replay on the caller's
+    hipStream_t cap = stream;
+    if (cap == nullptr) {
+      if (s->ctx->capture == nullptr)
+        KRPS_HIP(hipStreamCreateWithFlags(&s->ctx->capture, hipStreamNonBlocking));
+      cap = s->ctx->capture;
+    }
+    KRPS_HIP(hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal));
+    s->ctx->stream = cap;
+    st = enqueue_all();
+    s->ctx->stream = stream;
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamEndCapture(cap, &g);
+    if (st != KRPS_OK) {
+      if (g) (void)hipGraphDestroy(g);
+      return st;
+    }
+    if (e != hipSuccess) return hip_fail(e, "end capture");
+    e = hipGraphInstantiate(&s->sweep_exec, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) return hip_fail(e, "graph instantiate");
+    for (int i = 0; i < 5; ++i) s->g_key[i] = key[i];
+    s->g_J = J;
+  }
+  KRPS_HIP(hipGraphLaunch(s->sweep_exec, stream));
+  s->prepared_ws = nullptr;
+  return KRPS_OK;
+}
+
+krps_status krps_fit(krps_sampler s, krps_tensor t, const double* sigma, double* fit, void* ws,
+                     size_t ws_bytes) {
+  krps_status st = check_pair(s, t);
+  if (st != KRPS_OK) return st;
+  if (sigma == nullptr || fit == nullptr || ws == nullptr)
+    return fail(KRPS_EINVAL, "sigma/fit/workspace is NULL");
+  SolvePlan pl = plan_solve(s, 1);
+  const size_t need = align_up(fit_partial_bytes()) + 256;
+  if (ws_bytes < need) return fail(KRPS_EWORKSPACE, "workspace too small for the fit");
+  char* w = (char*)ws;
+  FitArgs fa;
+  memset(&fa, 0, sizeof(fa));
+  fa.N = s->N;
+  fa.R = s->R;
+  fa.nnz = t->nnz;
+  fa.cols = t->cols[0];
+  fa.vals = t->vals[0];
+  for (int k = 0; k < s->N; ++k) {
+    fa.U[k] = s->U[k];
+    fa.G[k] = s->gram[k];
+  }
+  fa.sigma = sigma;
+  double* partial = (double*)w;
+  double* out = (double*)(w + align_up(fit_partial_bytes()));
+  hipError_t e = launch_fit(s->ctx->stream, s->prec, fa, partial, out);
+  if (e != hipSuccess) return hip_fail(e, "fit");
+  double h[2];
+  KRPS_HIP(hipMemcpyAsync(h, out, 16, hipMemcpyDeviceToHost, s->ctx->stream));
+  KRPS_HIP(hipStreamSynchronize(s->ctx->stream));
+  const double r2 = t->norm2 + h[1] - 2.0 * h[0];
+  *fit = 1.0 - sqrt(r2 > 0 ? r2 : 0.0) / sqrt(t->norm2);
+  (void)pl;
   return KRPS_OK;
 }
 

@@ -69,13 +69,38 @@ struct DescentArgs {
   const double* u01;              // [J][N][2]
   int32_t* idx;                   // [J][N]
   double* prob;                   // [J] or null
-  void* rows;                     // [J][R] or null
+  void* rows;                     // [J][R] or null (factor type)
+  double* rows64;                 // [J][R] float64 rows or null
   const double* gplus;            // packed upper G^+ (tri) float64
   const int32_t* rank;            // device rank of G
   double* wout;                   // [J] sampling weights 1/sqrt(J q) or null
   int scale_rows;                 // rows <- a_d / sqrt(J q_d)
   int lps;                        // lanes per sample of the walk (0 = default)
   int32_t* status;                // device status word
+};
+
+// Fiber lookup / SpMM arguments for one solve of mode j.
+struct FiberArgs {
+  int N, j, lead, R;
+  int64_t nnz, J;
+  const int32_t* cols;        // [N][nnz] columns of mode j's sorted entries
+  const float* vals;          // [nnz]
+  const int64_t* off;         // [dims[lead] + 1] offsets over the leading other mode
+  const int32_t* sample_idx;  // [J][N]
+  int64_t* lo;                // [J] fiber entry range
+  int64_t* hi;                // [J]
+  int64_t* cnt;               // [J] work items per sample
+  int64_t* start;             // [J + 1] exclusive prefix of cnt
+};
+
+struct FitArgs {
+  int N, R;
+  int64_t nnz;
+  const int32_t* cols;  // [N][nnz] stored entries (any mode's order)
+  const float* vals;
+  const void* U[KRPS_MAX_MODES];
+  const double* G[KRPS_MAX_MODES];
+  const double* sigma;
 };
 
 // Status word bits set by kernels.
@@ -102,6 +127,30 @@ hipError_t launch_prep_eig2(hipStream_t st, krps_precision p, int R, int nsteps,
                             int32_t* sweep_out);
 // rank points at two int32: the rank and the Jacobi sweep count.
 hipError_t launch_pinv(hipStream_t st, int R, const double* M, double* Mp_full, int32_t* rank);
+
+// lstsq.hip
+size_t sort_temp_bytes(int64_t nnz);
+hipError_t build_fiber_index(hipStream_t st, int N, const int64_t* dims, int64_t nnz,
+                             const int32_t* idx, const float* val, int j, int32_t* cols,
+                             float* vals, int64_t* off, uint32_t* k0, uint32_t* k1, uint32_t* p0,
+                             uint32_t* p1, void* temp, size_t temp_bytes);
+hipError_t launch_norm2(hipStream_t st, const int32_t* cols, const float* vals, int N, int64_t nnz,
+                        double* out);
+hipError_t launch_lookup(hipStream_t st, const FiberArgs& a);
+hipError_t launch_spmm(hipStream_t st, krps_precision p, const FiberArgs& a, const void* rows,
+                       const double* w, void* Y);
+size_t solve_partial_bytes(int R);
+hipError_t launch_fill(hipStream_t st, krps_precision p, void* ptr, int64_t n);
+hipError_t launch_fill_f64(hipStream_t st, double* ptr, int64_t n);
+hipError_t launch_solve_gemm(hipStream_t st, krps_precision p, const void* Y, const double* Mp,
+                             void* U, int64_t I, int R, double* partial, double* sigma);
+hipError_t launch_colnorm(hipStream_t st, krps_precision p, const void* U, int64_t I, int R,
+                          double* partial, double* sigma);
+hipError_t launch_normalize(hipStream_t st, krps_precision p, void* U, int64_t I, int R,
+                            const double* sigma);
+size_t fit_partial_bytes();
+hipError_t launch_fit(hipStream_t st, krps_precision p, const FitArgs& a, double* partial,
+                      double* out);
 
 // descent.hip
 hipError_t launch_descent(hipStream_t st, krps_precision p, const DescentArgs& a);

@@ -1,0 +1,550 @@
+// The sketched least-squares assembly of STS-CP (Section 3.3; Appendix A.9
+// for the solve's pieces; Appendix A.13 for the reduction of the sampled
+// spMTTKRP to an SpMM) and the exact fit (Section 4.3).
+//
+//   fiber index : per mode j the COO entries sorted by the other modes'
+//                 indices (increasing mode order), then i_j -- the mode-j
+//                 fibers, i.e. the rows of mat(T, j)^T, are contiguous; an
+//                 offset table over the leading other mode narrows lookups.
+//   lookup      : per sample, the entry range of its fiber (offset table,
+//                 then binary search on the remaining modes).
+//   SpMM        : Y[i_j(e), :] += w_d x_e (w_d a_d) over the fiber entries,
+//                 split into chunks of CH entries so that heavy fibers
+//                 spread over many wavefronts (float atomics on Y).
+//   solve       : U_j = Y M^+ (M^+ in LDS, float64 products), per-column
+//                 sums of squares reduced deterministically, sigma, and the
+//                 renormalisation of U_j.
+//   fit         : <T, T~> over the stored entries and sigma^T (*G_k) sigma.
+#include <rocprim/device/device_radix_sort.hpp>
+
+#include "device_common.h"
+#include "krps_internal.h"
+
+namespace krps {
+
+namespace {
+
+constexpr int CH = 64;  // fiber entries per SpMM work item
+
+__global__ void iota_kernel(uint32_t* __restrict__ p, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = (uint32_t)i;
+}
+
+__global__ void gather_key_kernel(uint32_t* __restrict__ keys, const int32_t* __restrict__ idx,
+                                  const uint32_t* __restrict__ perm, int N, int col, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    keys[i] = (uint32_t)idx[(int64_t)perm[i] * N + col];
+}
+
+// Sorted copy of the tensor for one mode: cols[k][e] = idx[perm[e]][k].
+__global__ void materialize_kernel(int32_t* __restrict__ cols, float* __restrict__ vals,
+                                   const int32_t* __restrict__ idx, const float* __restrict__ val,
+                                   const uint32_t* __restrict__ perm, int N, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t p = perm[i];
+    for (int k = 0; k < N; ++k) cols[(int64_t)k * n + i] = idx[p * N + k];
+    vals[i] = val[p];
+  }
+}
+
+// off[v] = first entry whose leading key is >= v, for v in [0, dim].
+__global__ void offsets_kernel(int64_t* __restrict__ off, const int32_t* __restrict__ key,
+                               int64_t n, int64_t dim) {
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e <= n;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t prev = e == 0 ? -1 : key[e - 1];
+    const int64_t cur = e == n ? dim : key[e];
+    for (int64_t v = prev + 1; v <= cur; ++v) off[v] = e;
+  }
+}
+
+// ||T||^2 with duplicates summed: entries are sorted by all N columns, so
+// equal coordinates are adjacent; the first entry of each run adds the
+// square of the run's sum.
+__global__ void norm2_kernel(const int32_t* __restrict__ cols, const float* __restrict__ vals,
+                             int N, int64_t n, double* __restrict__ out) {
+  __shared__ double red[256];
+  double acc = 0;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    bool head = e == 0;
+    for (int k = 0; k < N && !head; ++k) head = cols[(int64_t)k * n + e] != cols[(int64_t)k * n + e - 1];
+    if (!head) continue;
+    double s = vals[e];
+    for (int64_t f = e + 1; f < n; ++f) {
+      bool same = true;
+      for (int k = 0; k < N && same; ++k) same = cols[(int64_t)k * n + f] == cols[(int64_t)k * n + e];
+      if (!same) break;
+      s += vals[f];
+    }
+    acc += s * s;
+  }
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int o = blockDim.x / 2; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) atomicAdd(out, red[0]);
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------ tensor
+
+size_t sort_temp_bytes(int64_t nnz) {
+  size_t bytes = 0;
+  (void)rocprim::radix_sort_pairs(nullptr, bytes, (uint32_t*)nullptr, (uint32_t*)nullptr,
+                                  (uint32_t*)nullptr, (uint32_t*)nullptr, (uint32_t)nnz, 0, 32);
+  return bytes;
+}
+
+static int bits_of(int64_t dim) {
+  int b = 1;
+  while ((int64_t(1) << b) < dim) ++b;
+  return b;
+}
+
+hipError_t build_fiber_index(hipStream_t st, int N, const int64_t* dims, int64_t nnz,
+                             const int32_t* idx, const float* val, int j, int32_t* cols,
+                             float* vals, int64_t* off, uint32_t* k0, uint32_t* k1, uint32_t* p0,
+                             uint32_t* p1, void* temp, size_t temp_bytes) {
+  const int grid = 4096, block = 256;
+  hipLaunchKernelGGL(iota_kernel, dim3(grid), dim3(block), 0, st, p0, nnz);
+  // LSD: least significant key first (i_j), then the other modes from the
+  // last to the first; each pass is a stable sort of the current order
+  int order[KRPS_MAX_MODES + 1];
+  int no = 0;
+  order[no++] = j;
+  for (int k = N - 1; k >= 0; --k)
+    if (k != j) order[no++] = k;
+  for (int pass = 0; pass < no; ++pass) {
+    const int col = order[pass];
+    hipLaunchKernelGGL(gather_key_kernel, dim3(grid), dim3(block), 0, st, k0, idx, p0, N, col, nnz);
+    size_t tb = temp_bytes;
+    hipError_t e = rocprim::radix_sort_pairs(temp, tb, k0, k1, p0, p1, (uint32_t)nnz, 0,
+                                             bits_of(dims[col]), st);
+    if (e != hipSuccess) return e;
+    uint32_t* t = p0;
+    p0 = p1;
+    p1 = t;
+  }
+  hipLaunchKernelGGL(materialize_kernel, dim3(grid), dim3(block), 0, st, cols, vals, idx, val, p0,
+                     N, nnz);
+  int lead = j == 0 ? 1 : 0;
+  if (N == 1) lead = 0;
+  hipLaunchKernelGGL(offsets_kernel, dim3(grid), dim3(block), 0, st, off,
+                     cols + (int64_t)lead * nnz, nnz, dims[lead]);
+  return hipGetLastError();
+}
+
+hipError_t launch_norm2(hipStream_t st, const int32_t* cols, const float* vals, int N, int64_t nnz,
+                        double* out) {
+  hipLaunchKernelGGL(norm2_kernel, dim3(1024), dim3(256), 0, st, cols, vals, N, nnz, out);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ lookup
+
+namespace {
+
+// Entry range of the fiber of sample d in the mode-j index: offsets over
+// the leading other mode, then lexicographic binary search on the rest.
+__global__ void lookup_kernel(FiberArgs a) {
+  const int N = a.N;
+  for (int64_t d = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; d < a.J;
+       d += (int64_t)gridDim.x * blockDim.x) {
+    const int32_t* __restrict__ sidx = a.sample_idx + d * N;
+    int64_t lo = 0, hi = 0;
+    if (N > 1) {
+      const int v = sidx[a.lead];
+      lo = a.off[v];
+      hi = a.off[v + 1];
+      // remaining other modes, in increasing order
+      for (int k = a.lead + 1; k < N; ++k) {
+        if (k == a.j) continue;
+        const int32_t* __restrict__ c = a.cols + (int64_t)k * a.nnz;
+        const int key = sidx[k];
+        int64_t l = lo, r = hi;
+        while (l < r) {  // first >= key
+          const int64_t m = (l + r) >> 1;
+          if (c[m] < key) l = m + 1; else r = m;
+        }
+        int64_t l2 = l, r2 = hi;
+        while (l2 < r2) {  // first > key
+          const int64_t m = (l2 + r2) >> 1;
+          if (c[m] <= key) l2 = m + 1; else r2 = m;
+        }
+        lo = l;
+        hi = l2;
+      }
+    } else {
+      lo = 0;
+      hi = a.nnz;
+    }
+    a.lo[d] = lo;
+    a.hi[d] = hi;
+    a.cnt[d] = (hi - lo + CH - 1) / CH;
+  }
+}
+
+// Exclusive scan of cnt[0..J) into start[0..J], one block.
+__global__ __launch_bounds__(1024) void scan_kernel(const int64_t* __restrict__ cnt,
+                                                    int64_t* __restrict__ start, int64_t J) {
+  __shared__ int64_t part[1024];
+  const int t = threadIdx.x;
+  const int64_t per = (J + 1023) / 1024;
+  const int64_t b = t * per, e = b + per < J ? b + per : J;
+  int64_t s = 0;
+  for (int64_t i = b; i < e; ++i) s += cnt[i];
+  part[t] = s;
+  __syncthreads();
+  for (int o = 1; o < 1024; o <<= 1) {
+    const int64_t v = t >= o ? part[t - o] : 0;
+    __syncthreads();
+    part[t] += v;
+    __syncthreads();
+  }
+  int64_t run = t == 0 ? 0 : part[t - 1];
+  for (int64_t i = b; i < e; ++i) {
+    start[i] = run;
+    run += cnt[i];
+  }
+  if (t == 1023) start[J] = part[1023];
+}
+
+// Y[i_j(e), :] += coef_e * rows[d, :] with coef_e = w_d x_e: one wavefront
+// per work item (a chunk of <= CH entries of one fiber), lanes over columns.
+template <typename T>
+__global__ __launch_bounds__(256) void spmm_kernel(FiberArgs a, const T* __restrict__ rows,
+                                                   const double* __restrict__ w,
+                                                   double* __restrict__ Y) {
+  const int lane = threadIdx.x & 63;
+  const int R = a.R;
+  const int64_t total = a.start[a.J];
+  const int64_t nw = (int64_t)gridDim.x * (blockDim.x >> 6);
+  const int32_t* __restrict__ ij = a.cols + (int64_t)a.j * a.nnz;
+  for (int64_t c = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); c < total;
+       c += nw) {
+    // sample of work item c: last d with start[d] <= c
+    int64_t l = 0, r = a.J;
+    while (r - l > 1) {
+      const int64_t m = (l + r) >> 1;
+      if (a.start[m] <= c) l = m; else r = m;
+    }
+    const int64_t d = l;
+    const int64_t e0 = a.lo[d] + (c - a.start[d]) * CH;
+    const int64_t e1 = e0 + CH < a.hi[d] ? e0 + CH : a.hi[d];
+    const double wd = w[d];
+    const T r0 = lane < R ? rows[d * R + lane] : T(0);
+    const T r1 = lane + 64 < R ? rows[d * R + lane + 64] : T(0);
+    for (int64_t e = e0; e < e1; ++e) {
+      const double coef = wd * (double)a.vals[e];
+      const int64_t i = ij[e];
+      if (lane < R) atomicAdd(&Y[i * R + lane], coef * (double)r0);
+      if (lane + 64 < R) atomicAdd(&Y[i * R + lane + 64], coef * (double)r1);
+    }
+  }
+}
+
+}  // namespace
+
+hipError_t launch_lookup(hipStream_t st, const FiberArgs& a) {
+  int64_t blocks = (a.J + 255) / 256;
+  if (blocks > 4096) blocks = 4096;
+  if (blocks < 1) blocks = 1;
+  hipLaunchKernelGGL(lookup_kernel, dim3((unsigned)blocks), dim3(256), 0, st, a);
+  hipLaunchKernelGGL(scan_kernel, dim3(1), dim3(1024), 0, st, a.cnt, a.start, a.J);
+  return hipGetLastError();
+}
+
+hipError_t launch_spmm(hipStream_t st, krps_precision p, const FiberArgs& a, const void* rows,
+                       const double* w, void* Y) {
+  if (p == KRPS_FP64)
+    hipLaunchKernelGGL(spmm_kernel<double>, dim3(2048), dim3(256), 0, st, a,
+                       (const double*)rows, w, (double*)Y);
+  else
+    hipLaunchKernelGGL(spmm_kernel<float>, dim3(2048), dim3(256), 0, st, a, (const float*)rows,
+                       w, (double*)Y);
+  return hipGetLastError();
+}
+
+// --------------------------------------------------------- fills and solve
+
+namespace {
+
+template <typename T>
+__global__ void fill_kernel(T* __restrict__ p, int64_t n, T v) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = v;
+}
+
+// Y M^+ for a persistent sweep of row groups; thread (row slot, c) with
+// c < RB columns.  Pass 1 (sigma == nullptr) only accumulates the per-column
+// sums of squares of the float64 products in registers and reduces them per
+// block into partial[block][c]; pass 2 recomputes the products and writes
+// U = (Y M^+)[:, c] / sigma[c], rounded once to the factor type.
+template <typename T, int RB>
+__global__ __launch_bounds__(256) void gemm_colsum_kernel(const double* __restrict__ Y,
+                                                          const double* __restrict__ Mp,
+                                                          T* __restrict__ out, int64_t I, int R,
+                                                          double* __restrict__ partial,
+                                                          const double* __restrict__ sigma) {
+  extern __shared__ double sm[];
+  double* Ms = sm;                 // R x R
+  double* red = sm + R * R;        // 256
+  for (int i = threadIdx.x; i < R * R; i += blockDim.x) Ms[i] = Mp[i];
+  __syncthreads();
+  constexpr int ROWS = 256 / RB;
+  const int c = threadIdx.x % RB;
+  const int rs = threadIdx.x / RB;
+  const double inv = (sigma != nullptr && c < R && sigma[c] > 0) ? 1.0 / sigma[c] : 0.0;
+  double sq = 0;
+  for (int64_t r = (int64_t)blockIdx.x * ROWS + rs; r < I; r += (int64_t)gridDim.x * ROWS) {
+    if (c < R) {
+      const double* __restrict__ yr = Y + r * R;
+      double acc = 0;
+      for (int k = 0; k < R; ++k) acc += yr[k] * Ms[k * R + c];
+      if (sigma == nullptr)
+        sq += acc * acc;
+      else
+        out[r * R + c] = (T)(acc * inv);
+    }
+  }
+  if (sigma != nullptr) return;
+  red[threadIdx.x] = sq;
+  __syncthreads();
+  if (rs == 0 && c < R) {
+    double s = 0;
+    for (int q = 0; q < ROWS; ++q) s += red[q * RB + c];
+    partial[(int64_t)blockIdx.x * R + c] = s;
+  }
+}
+
+// Column sums of squares of a factor (for the initial normalisation).
+template <typename T, int RB>
+__global__ __launch_bounds__(256) void colsum_kernel(const T* __restrict__ U, int64_t I, int R,
+                                                     double* __restrict__ partial) {
+  __shared__ double red[256];
+  constexpr int ROWS = 256 / RB;
+  const int c = threadIdx.x % RB;
+  const int rs = threadIdx.x / RB;
+  double sq = 0;
+  for (int64_t r = (int64_t)blockIdx.x * ROWS + rs; r < I; r += (int64_t)gridDim.x * ROWS)
+    if (c < R) {
+      const double v = (double)U[r * R + c];
+      sq += v * v;
+    }
+  red[threadIdx.x] = sq;
+  __syncthreads();
+  if (rs == 0 && c < R) {
+    double s = 0;
+    for (int q = 0; q < ROWS; ++q) s += red[q * RB + c];
+    partial[(int64_t)blockIdx.x * R + c] = s;
+  }
+}
+
+// sigma[c] = sqrt(sum_b partial[b][c]); one block per column.
+__global__ __launch_bounds__(256) void sigma_kernel(const double* __restrict__ partial, int nb,
+                                                    int R, double* __restrict__ sigma) {
+  __shared__ double red[256];
+  const int c = blockIdx.x;
+  double s = 0;
+  for (int b = threadIdx.x; b < nb; b += blockDim.x) s += partial[(int64_t)b * R + c];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int o = blockDim.x / 2; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) sigma[c] = sqrt(red[0]);
+}
+
+template <typename T>
+__global__ void normalize_kernel(T* __restrict__ U, int64_t I, int R,
+                                 const double* __restrict__ sigma) {
+  const int64_t n = I * R;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const double s = sigma[i % R];
+    U[i] = s > 0 ? (T)((double)U[i] / s) : T(0);
+  }
+}
+
+}  // namespace
+
+constexpr int SOLVE_BLOCKS = 2048;
+
+size_t solve_partial_bytes(int R) { return (size_t)SOLVE_BLOCKS * R * 8; }
+
+hipError_t launch_fill(hipStream_t st, krps_precision p, void* ptr, int64_t n) {
+  if (n <= 0) return hipSuccess;
+  int64_t blocks = (n + 255) / 256;
+  if (blocks > 8192) blocks = 8192;
+  if (p == KRPS_FP64)
+    hipLaunchKernelGGL(fill_kernel<double>, dim3((unsigned)blocks), dim3(256), 0, st, (double*)ptr,
+                       n, 0.0);
+  else
+    hipLaunchKernelGGL(fill_kernel<float>, dim3((unsigned)blocks), dim3(256), 0, st, (float*)ptr,
+                       n, 0.0f);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill_f64(hipStream_t st, double* ptr, int64_t n) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(fill_kernel<double>, dim3(64), dim3(256), 0, st, ptr, n, 0.0);
+  return hipGetLastError();
+}
+
+template <typename T, int RB>
+static hipError_t run_gemm(hipStream_t st, const double* Y, const double* Mp, void* out, int64_t I,
+                           int R, double* partial, double* sigma) {
+  const size_t lds = (size_t)R * R * 8 + 256 * 8;
+  hipError_t e = hipFuncSetAttribute((const void*)gemm_colsum_kernel<T, RB>,
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL((gemm_colsum_kernel<T, RB>), dim3(SOLVE_BLOCKS), dim3(256), lds, st, Y, Mp,
+                     (T*)out, I, R, partial, (const double*)nullptr);
+  hipLaunchKernelGGL(sigma_kernel, dim3(R), dim3(256), 0, st, partial, SOLVE_BLOCKS, R, sigma);
+  hipLaunchKernelGGL((gemm_colsum_kernel<T, RB>), dim3(SOLVE_BLOCKS), dim3(256), lds, st, Y, Mp,
+                     (T*)out, I, R, partial, (const double*)sigma);
+  return hipGetLastError();
+}
+
+// U = Y M^+ with its column norms sigma taken out: two passes over Y (norms,
+// then the normalised write) so that U is rounded once.
+hipError_t launch_solve_gemm(hipStream_t st, krps_precision p, const void* Y, const double* Mp,
+                             void* U, int64_t I, int R, double* partial, double* sigma) {
+  const double* Yd = (const double*)Y;
+  if (p == KRPS_FP64)
+    return R <= 64 ? run_gemm<double, 64>(st, Yd, Mp, U, I, R, partial, sigma)
+                   : run_gemm<double, 128>(st, Yd, Mp, U, I, R, partial, sigma);
+  return R <= 64 ? run_gemm<float, 64>(st, Yd, Mp, U, I, R, partial, sigma)
+                 : run_gemm<float, 128>(st, Yd, Mp, U, I, R, partial, sigma);
+}
+
+hipError_t launch_colnorm(hipStream_t st, krps_precision p, const void* U, int64_t I, int R,
+                          double* partial, double* sigma) {
+  if (p == KRPS_FP64) {
+    if (R <= 64)
+      hipLaunchKernelGGL((colsum_kernel<double, 64>), dim3(SOLVE_BLOCKS), dim3(256), 0, st,
+                         (const double*)U, I, R, partial);
+    else
+      hipLaunchKernelGGL((colsum_kernel<double, 128>), dim3(SOLVE_BLOCKS), dim3(256), 0, st,
+                         (const double*)U, I, R, partial);
+  } else {
+    if (R <= 64)
+      hipLaunchKernelGGL((colsum_kernel<float, 64>), dim3(SOLVE_BLOCKS), dim3(256), 0, st,
+                         (const float*)U, I, R, partial);
+    else
+      hipLaunchKernelGGL((colsum_kernel<float, 128>), dim3(SOLVE_BLOCKS), dim3(256), 0, st,
+                         (const float*)U, I, R, partial);
+  }
+  hipLaunchKernelGGL(sigma_kernel, dim3(R), dim3(256), 0, st, partial, SOLVE_BLOCKS, R, sigma);
+  return hipGetLastError();
+}
+
+hipError_t launch_normalize(hipStream_t st, krps_precision p, void* U, int64_t I, int R,
+                            const double* sigma) {
+  int64_t blocks = (I * R + 255) / 256;
+  if (blocks > 8192) blocks = 8192;
+  if (p == KRPS_FP64)
+    hipLaunchKernelGGL(normalize_kernel<double>, dim3((unsigned)blocks), dim3(256), 0, st,
+                       (double*)U, I, R, sigma);
+  else
+    hipLaunchKernelGGL(normalize_kernel<float>, dim3((unsigned)blocks), dim3(256), 0, st,
+                       (float*)U, I, R, sigma);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------- fit
+
+namespace {
+
+// <T, T~> partial sums: thread per stored entry, sum_r sigma_r prod_k U_k[i_k, r].
+template <typename T>
+__global__ __launch_bounds__(256) void fit_inner_kernel(FitArgs a, double* __restrict__ partial) {
+  __shared__ double red[256];
+  double acc = 0;
+  const int R = a.R;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < a.nnz;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    double rowsum = 0;
+    for (int r0 = 0; r0 < R; r0 += 16) {
+      double pr[16];
+#pragma unroll
+      for (int q = 0; q < 16; ++q) pr[q] = r0 + q < R ? a.sigma[r0 + q] : 0.0;
+      for (int k = 0; k < a.N; ++k) {
+        const T* __restrict__ u = (const T*)a.U[k] + (int64_t)a.cols[(int64_t)k * a.nnz + e] * R + r0;
+#pragma unroll
+        for (int q = 0; q < 16; ++q)
+          if (r0 + q < R) pr[q] *= (double)u[q];
+      }
+#pragma unroll
+      for (int q = 0; q < 16; ++q) rowsum += pr[q];
+    }
+    acc += (double)a.vals[e] * rowsum;
+  }
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int o = blockDim.x / 2; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) partial[blockIdx.x] = red[0];
+}
+
+// out[0] = sum of partials (<T, T~>), out[1] = sigma^T ((*)_k G_k) sigma.
+__global__ __launch_bounds__(256) void fit_final_kernel(FitArgs a, const double* __restrict__ partial,
+                                                        int nb, double* __restrict__ out) {
+  __shared__ double red[256];
+  double s = 0;
+  for (int b = threadIdx.x; b < nb; b += blockDim.x) s += partial[b];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int o = blockDim.x / 2; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+    __syncthreads();
+  }
+  const double inner = red[0];
+  __syncthreads();
+  const int R = a.R;
+  double m = 0;
+  for (int i = threadIdx.x; i < R * R; i += blockDim.x) {
+    double g = 1.0;
+    for (int k = 0; k < a.N; ++k) g *= a.G[k][i];
+    m += a.sigma[i / R] * g * a.sigma[i % R];
+  }
+  red[threadIdx.x] = m;
+  __syncthreads();
+  for (int o = blockDim.x / 2; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    out[0] = inner;
+    out[1] = red[0];
+  }
+}
+
+}  // namespace
+
+constexpr int FIT_BLOCKS = 2048;
+size_t fit_partial_bytes() { return FIT_BLOCKS * 8; }
+
+hipError_t launch_fit(hipStream_t st, krps_precision p, const FitArgs& a, double* partial,
+                      double* out) {
+  if (p == KRPS_FP64)
+    hipLaunchKernelGGL(fit_inner_kernel<double>, dim3(FIT_BLOCKS), dim3(256), 0, st, a, partial);
+  else
+    hipLaunchKernelGGL(fit_inner_kernel<float>, dim3(FIT_BLOCKS), dim3(256), 0, st, a, partial);
+  hipLaunchKernelGGL(fit_final_kernel, dim3(1), dim3(256), 0, st, a, partial, FIT_BLOCKS, out);
+  return hipGetLastError();
+}
+
+}  // namespace krps
