@@ -10,7 +10,7 @@
   ``S`` of Section 2.1 (weights ``1/sqrt(J q_d)``), by the normal equations
   ``U_j = Y M^+`` with ``M = (SA)^T SA`` and ``Y = (SB)^T SA``; then the
   column norms become ``sigma`` and the columns are renormalised
-  (Algorithm 6, lines 6-8).
+  (the factor update of Algorithm 6).
 * :func:`fit` -- ``1 - ||T~ - T||_F / ||T||_F`` (Section 4.3) through
   ``||T~||^2 = sigma^T ((*)_k G_k) sigma`` and ``<T, T~>`` over the nonzeros.
 * :func:`cp_als` -- Algorithm 6 with the sampled solve.
@@ -22,6 +22,7 @@ of zero norm keeps ``sigma = 0`` and stays zero.
 from __future__ import annotations
 
 import numpy as np
+from scipy import sparse
 
 from .definition import pinv_psd, hadamard_all
 from .sampler import KRPSampler
@@ -86,20 +87,32 @@ class SparseTensor:
 def normal_equations(tensor, j, idx, rows, w2):
     """``M = sum_d w_d^2 a_d a_d^T`` and ``Y = sum_d w_d^2 b_d a_d^T`` where
     ``b_d`` is the mode-``j`` fiber of sample ``d`` (a sparse ``I_j`` vector).
+
+    Samples drawn more than once (the same multi-index) select the same row
+    ``a_d`` and the same fiber ``b_d``, so their terms of ``Y`` are gathered
+    first: each distinct sampled fiber is expanded once with the summed
+    weight ``sum w_d^2`` of its samples (the rows of the sampling matrix of
+    Section 2.1 are i.i.d. draws; repeated rows add).  This bounds the
+    expansion by the number of stored entries.
     """
     rows = np.asarray(rows, dtype=np.float64)
     M = (rows * w2[:, None]).T @ rows
-    lo, hi = tensor.lookup(j, idx)
+    oth = tensor.others(j)
+    idx = np.asarray(idx, dtype=np.int64)
+    _, first, inv = np.unique(idx[:, oth], axis=0, return_index=True, return_inverse=True)
+    inv = inv.reshape(-1)
+    W = np.bincount(inv, weights=w2, minlength=len(first))       # summed w_d^2
+    A = rows[first]                                              # a_u, one per fiber
+    lo, hi = tensor.lookup(j, idx[first])
     cnt = hi - lo
     _, order = tensor.fibers(j)
-    sid = np.repeat(np.arange(len(cnt)), cnt)
+    uid = np.repeat(np.arange(len(cnt)), cnt)
     starts = np.repeat(lo - np.concatenate(([0], np.cumsum(cnt)[:-1])), cnt)
     ent = order[starts + np.arange(cnt.sum())]
-    ij = tensor.idx[ent, j]
-    coef = w2[sid] * tensor.val[ent]
-    Y = np.zeros((tensor.dims[j], rows.shape[1]))
-    for r in range(rows.shape[1]):
-        Y[:, r] = np.bincount(ij, weights=coef * rows[sid, r], minlength=tensor.dims[j])
+    # P[i, u] = W_u * sum of x_e over the entries of fiber u with i_j(e) = i
+    P = sparse.coo_matrix((W[uid] * tensor.val[ent], (tensor.idx[ent, j], uid)),
+                          shape=(tensor.dims[j], len(first))).tocsr()
+    Y = np.asarray(P @ A)
     return M, Y
 
 
@@ -116,8 +129,8 @@ def normalize_columns(U):
 def sketched_solve(sampler: KRPSampler, tensor: SparseTensor, j, u01):
     """One STS-CP solve for mode ``j``; returns ``(U_j, sigma, draw, M, Y)``.
 
-    The sampler is refreshed with the new ``U_j`` (Algorithm 6 line 8 and
-    Theorem 1.1 part 1)."""
+    The sampler is refreshed with the new ``U_j`` (the factor update of
+    Algorithm 6 and Theorem 1.1 part 1)."""
     draw = sampler.draw(j, u01)
     J = draw.prob.shape[0]
     w2 = 1.0 / (J * draw.prob)
