@@ -1,13 +1,21 @@
-"""Benchmark of the exact Khatri-Rao leverage sampler (and, when built, the
-sketched CP-ALS sweep) on one MI355X.
+"""Benchmark of the exact Khatri-Rao leverage sampler and the sketched
+CP-ALS sweep on one MI355X.
 
-Workload of the headline number: N = 3 factors of 2^20 x 32 (float32,
-N(0,1) with 1% of the rows scaled by 100), J = 65,536 samples drawn from
-the Khatri-Rao product of the other two factors for each excluded mode
-k in {0, 1, 2}.  One step = rebuild the three segment trees + prepare and
-draw the three exclusions (with the probability of every sample).
+Headline number (``value``, samples/s): N = 3 factors of 2^20 x 32
+(float32, N(0,1) with 1% of the rows scaled by 100), J = 65,536 samples
+drawn from the Khatri-Rao product of the other two factors for each
+excluded mode k in {0, 1, 2}.  One step = rebuild the three segment trees +
+prepare and draw the three exclusions (with the probability of every
+sample).
 
-Prints one JSON line (see README / DESIGN for the fields).
+Second half of the metric (``als``): sketched CP-ALS on a sparse
+1e6 x 1e6 x 1e5 tensor with 1e8 Zipf(1.2) nonzeros, R = 64, J = 65,536
+samples per solve, 10 sweeps, each sweep replayed from a HIP graph; sweep
+time (fit excluded) and the fit after every sweep, BF16 hi/lo split Grams
+against the plain float64 path, with the float64 oracle's fits when they
+have been stored.
+
+Prints one JSON line.
 """
 from __future__ import annotations
 
@@ -38,6 +46,16 @@ def parse():
     ap.add_argument("--precisions", default="fp32,fp64,bf16x2")
     ap.add_argument("--calib-copy", action="store_true",
                     help="only run a 1 GiB device copy (counter calibration)")
+    ap.add_argument("--als", default="bf16x2,fp64",
+                    help="precisions of the CP-ALS leg ('' skips it)")
+    ap.add_argument("--als-nnz", type=float, default=None,
+                    help="nonzeros of the CP-ALS tensor (default: the workload's 1e8)")
+    ap.add_argument("--als-sweeps", type=int, default=None)
+    ap.add_argument("--als-seeds", type=int, default=4,
+                    help="uniform seeds of the CP-ALS leg (mean/std of the final fit)")
+    ap.add_argument("--batched", default="fp32",
+                    help="precision of the batched-samplers leg ('' skips it)")
+    ap.add_argument("--batched-reps", type=int, default=3)
     return ap.parse_args()
 
 
@@ -170,6 +188,179 @@ def cpu_baseline(Us, u01, J_full, budget_s=20.0):
                       f"{t_draw * 1e6:.1f} us/draw), scaled to one step of 3 x {J_full} draws"}
 
 
+GOLDEN = os.path.join(ROOT, "tests", "golden")
+
+
+def oracle_fits(config, store, nnz):
+    tag = f"_nnz{int(nnz)}" if nnz is not None else ""
+    try:
+        return json.load(open(os.path.join(GOLDEN, f"als_fits_c{config}{tag}_{store}.json")))["fits"]
+    except (OSError, ValueError, KeyError):
+        return None
+
+
+def run_als(torch, krps, ctx, precs, nnz, sweeps_arg, seeds):
+    """Sketched CP-ALS: one untimed sweep captures the graph, the factors
+    are reset, then every sweep is replayed and timed with HIP events on
+    the context stream; the fit is taken between sweeps, outside the
+    timed region."""
+    import numpy as np
+    import synth
+    t0 = time.perf_counter()
+    dims, idx, val, U0, R, J, sweeps, useed = synth.als_problem(3, None if nnz is None else int(nnz))
+    if sweeps_arg is not None:
+        sweeps = sweeps_arg
+    N = len(dims)
+    gen_s = time.perf_counter() - t0
+    print(f"# als inputs: {len(val)} nnz generated in {gen_s:.1f} s", file=sys.stderr, flush=True)
+    t0 = time.perf_counter()
+    T = krps.Tensor(ctx, dims, torch.from_numpy(idx).to(ctx.device),
+                    torch.from_numpy(val).to(ctx.device))
+    del idx, val
+    print(f"# als tensor: {T.stored_entries} distinct coordinates, index built in "
+          f"{time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
+    u_all = [torch.from_numpy(synth.sweep_uniforms(useed, s, N, J)).to(ctx.device)
+             for s in range(sweeps)]
+    ubuf = torch.empty_like(u_all[0])
+    out = {}
+    for prec in precs:
+        dt = torch.float64 if prec == "fp64" else torch.float32
+        Ud = [torch.from_numpy(U).to(ctx.device).to(dt).contiguous() for U in U0]
+        S = krps.Sampler(ctx, Ud, precision=prec)
+        A = krps.CPALS(S, T, J)
+
+        def reset():
+            for k in range(N):
+                S.factors[k].copy_(Ud0[k])
+                S.refresh(k)
+            A.sigma.fill_(1.0)
+
+        for k in range(N):
+            A.normalize(k)
+        Ud0 = [U.clone() for U in S.factors]
+        # capture (first call with these pointers), then start over
+        ubuf.copy_(u_all[0])
+        A.sweep(ubuf, use_graph=True)
+        torch.cuda.synchronize()
+        print(f"# als {prec}: graph captured", file=sys.stderr, flush=True)
+        reset()
+        torch.cuda.synchronize()
+        stream = torch.cuda.current_stream()
+        ms, fits = [], []
+        for s in range(sweeps):
+            ubuf.copy_(u_all[s])
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            A.sweep(ubuf, use_graph=True)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            ms.append(e0.elapsed_time(e1))
+            fits.append(A.fit())
+            print(f"# als {prec} sweep {s}: {ms[-1]:.3f} ms fit {fits[-1]:.6f}", file=sys.stderr,
+                  flush=True)
+        # more uniform seeds: the spread of the final fit over sketches
+        finals = [fits[-1]]
+        for extra in range(1, seeds):
+            reset()
+            for s in range(sweeps):
+                ubuf.copy_(torch.from_numpy(synth.sweep_uniforms(useed + 7919 * extra, s, N, J)))
+                A.sweep(ubuf, use_graph=True)
+            torch.cuda.synchronize()
+            finals.append(A.fit())
+            print(f"# als {prec} seed {extra}: final fit {finals[-1]:.6f}", file=sys.stderr,
+                  flush=True)
+        ref = oracle_fits(3, "f64" if prec == "fp64" else "f32", nnz)
+        rec = {"sweep_ms": ms, "sweep_ms_mean": float(np.mean(ms)),
+               "als_s_total": float(np.sum(ms)) / 1e3, "fits": fits,
+               "final_fit_over_seeds": finals, "final_fit_mean": float(np.mean(finals)),
+               "final_fit_std": float(np.std(finals)),
+               "samples_per_s_in_sweep": N * J / (float(np.mean(ms)) / 1e3)}
+        if ref is not None and len(ref) == len(fits):
+            rec["oracle_fits"] = ref
+            rec["max_abs_fit_diff"] = float(np.max(np.abs(np.array(fits) - np.array(ref))))
+        out[prec] = rec
+        print(f"# als {prec}: sweep {rec['sweep_ms_mean']:.3f} ms, fits {np.round(fits, 6)}",
+              file=sys.stderr, flush=True)
+        del A, S
+        torch.cuda.synchronize()
+    cfg = {"workload": f"sketched CP-ALS {dims[0]:.0e}x{dims[1]:.0e}x{dims[2]:.0e}, "
+                       f"nnz={T.nnz}, Zipf(1.2), R={R}, J={J}, {sweeps} sweeps, graph replay",
+           "dims": list(dims), "nnz": T.nnz, "R": R, "J": J, "sweeps": sweeps}
+    return {"config": cfg, "precisions": out}
+
+
+def run_batched(torch, krps, ctx, prec, reps):
+    """64 independent samplers (N in {3,4,5}, I_j log-uniform in
+    [2^10, 2^22], R in {16,32,64,128}, N(0,1) factors), J = 16,384 samples
+    each over all modes: one batched call (batched preparations + one
+    persistent walk launch) against one krps_sample call per problem.
+    Factors are drawn on the device from a seeded generator."""
+    import numpy as np
+    import synth
+    probs = synth.batched_problems(64, synth.config_seed(4))
+    J = synth.CONFIGS[4]["J"]
+    g = torch.Generator(device=ctx.device)
+    g.manual_seed(synth.config_seed(4))
+    dt = torch.float64 if prec == "fp64" else torch.float32
+    samplers, unis = [], []
+    fbytes = 0
+    for p, (dims, R) in enumerate(probs):
+        Ud = [torch.randn((I, R), generator=g, device=ctx.device, dtype=torch.float32).to(dt)
+              for I in dims]
+        fbytes += sum(U.numel() * U.element_size() for U in Ud)
+        samplers.append(krps.Sampler(ctx, Ud, precision=prec))
+        unis.append(torch.from_numpy(synth.uniforms(J, len(dims), synth.uniform_seed(4) + p))
+                    .to(ctx.device))
+    torch.cuda.synchronize()
+    print(f"# batched: {len(probs)} samplers built, {fbytes / 1e9:.1f} GB of factors",
+          file=sys.stderr, flush=True)
+    excl = [-1] * len(probs)
+    ws = None
+    ev = lambda: torch.cuda.Event(enable_timing=True)  # noqa: E731
+    idx_b, _ = krps.sample_batched(ctx, samplers, excl, unis)
+    torch.cuda.synchronize()
+    tb = []
+    for _ in range(reps):
+        e0, e1 = ev(), ev()
+        e0.record()
+        idx_b, prob_b = krps.sample_batched(ctx, samplers, excl, unis, ws=ws)
+        e1.record()
+        torch.cuda.synchronize()
+        tb.append(e0.elapsed_time(e1))
+    ts = []
+    for _ in range(reps):
+        e0, e1 = ev(), ev()
+        e0.record()
+        outs = [S.sample(-1, u) for S, u in zip(samplers, unis)]
+        e1.record()
+        torch.cuda.synchronize()
+        ts.append(e0.elapsed_time(e1))
+    same = all(torch.equal(a, o[0]) for a, o in zip(idx_b, outs))
+    e0, e1 = ev(), ev()
+    e0.record()
+    for S in samplers:
+        for j in range(S.N):
+            S.refresh(j)
+    e1.record()
+    torch.cuda.synchronize()
+    total = J * len(probs)
+    rec = {"config": {"workload": "64 samplers, N in {3,4,5}, I_j log-uniform [2^10, 2^22], "
+                                  "R in {16,32,64,128}, J=16384 each, all modes",
+                      "problems": [[list(d), R] for d, R in probs], "precision": prec,
+                      "factor_bytes": fbytes},
+           "samples": total,
+           "batched_ms": float(np.median(tb)), "per_problem_ms": float(np.median(ts)),
+           "batched_samples_per_s": total / (float(np.median(tb)) / 1e3),
+           "per_problem_samples_per_s": total / (float(np.median(ts)) / 1e3),
+           "build_all_ms": e0.elapsed_time(e1), "identical_to_per_problem": bool(same)}
+    print(f"# batched {prec}: {rec['batched_ms']:.2f} ms ({rec['batched_samples_per_s'] / 1e6:.1f}"
+          f" M samples/s) vs per-problem {rec['per_problem_ms']:.2f} ms; identical {same}",
+          file=sys.stderr, flush=True)
+    del samplers
+    torch.cuda.synchronize()
+    return rec
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -242,6 +433,13 @@ def main():
                            "build_ms": v["build_ms"], "descent_ms": v["descent_ms"]}
                        for p, v in results.items()},
     }
+    del results
+    torch.cuda.synchronize()
+    if args.als:
+        line["als"] = run_als(torch, krps, ctx, args.als.split(","), args.als_nnz,
+                              args.als_sweeps, args.als_seeds)
+    if args.batched:
+        line["batched"] = run_batched(torch, krps, ctx, args.batched, args.batched_reps)
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(Us, u01, J)
     else:

@@ -141,14 +141,43 @@ krps_status krps_sample(krps_sampler s, int exclude, int64_t J, const double* un
                         int check);
 
 /* The two halves of krps_sample, for callers that reuse one preparation or
- * time the walk alone.  krps_sample_prepare enqueues lines 1-5 of
+ * time the walk alone.  krps_sample_prepare enqueues the set-up part of
  * Algorithm 2 (G^+, the G_{>k}, their eigendecompositions and the eigen-
  * trees E_k) into ws for exclusion `exclude`; krps_sample_draw enqueues the
- * walk of lines 6-12 and must be given the same ws and exclude after a
+ * per-sample walk and must be given the same ws and exclude after a
  * prepare (KRPS_EINVAL otherwise).  Arguments as for krps_sample. */
 krps_status krps_sample_prepare(krps_sampler s, int exclude, void* ws, size_t ws_bytes);
 krps_status krps_sample_draw(krps_sampler s, int exclude, int64_t J, const double* uniforms,
                              int32_t* idx, double* prob, void* rows, void* ws, size_t ws_bytes);
+
+/* Bytes of workspace for krps_sample_batched over the P samplers s[] with
+ * exclusions exclude[] (per problem its per-draw scratch and a table of
+ * tri(R) packed indices, plus the job and problem descriptors). */
+krps_status krps_sample_batched_workspace_bytes(krps_ctx ctx, int P, const krps_sampler* s,
+                                                const int* exclude, size_t* bytes);
+
+/* Algorithm 2 for P independent problems at once (Appendix A.10: many
+ * samplers batched): the P preparations run as batched one-block jobs, and
+ * the walks of all problems of one storage type and shape class (R <= 8,
+ * 16, 32, 64, 128) run in ONE persistent launch, in which each wavefront
+ * takes the next task (problem, group of samples) from a device counter;
+ * problems are ordered by decreasing cost.  The problems may differ in N,
+ * I_j, R and precision.
+ *   s[p], exclude[p]  sampler and exclusion of problem p (host arrays;
+ *                     every sampler on ctx's device)
+ *   J[p]              samples of problem p (host array)
+ *   uniforms[p]       device float64 [J[p]][N_p][2], as for krps_sample
+ *   idx[p]            device int32 [J[p]][N_p] out (excluded column -1)
+ *   prob[p]           device float64 [J[p]] out (NULL array or entry: no q)
+ *   ws                workspace (krps_sample_batched_workspace_bytes)
+ * The results equal P calls of krps_sample with the same arguments.  The
+ * descriptors are staged through a pinned host buffer owned by ctx (the
+ * call waits for the previous batched call's copy out of it).  Device-side
+ * status (EZERO, ENUMERIC) goes to each sampler's status word. */
+krps_status krps_sample_batched(krps_ctx ctx, int P, const krps_sampler* s, const int* exclude,
+                                const int64_t* J, const double* const* uniforms,
+                                int32_t* const* idx, double* const* prob, void* ws,
+                                size_t ws_bytes);
 
 /* Probability q of M given multi-indices (idx [M][N], the excluded column
  * is ignored) under the leverage distribution of the (excluded) product. */
@@ -160,10 +189,11 @@ krps_status krps_row_prob(krps_sampler s, int exclude, int64_t M, const int32_t*
 /* ------------------------------------------------------------------ */
 
 /* Bytes of persistent workspace for a sparse tensor of N modes with the
- * given dims and nnz stored entries: per mode j the entries sorted by the
+ * given dims and nnz given entries: per mode j the entries sorted by the
  * other modes' indices (increasing mode order, then i_j), i.e. grouped into
- * the mode-j fibers that rows of mat(T, j)^T select, plus an offset table
- * over the leading other mode; and the sort's scratch. */
+ * the mode-j fibers that rows of mat(T, j)^T select, with entries of equal
+ * coordinates merged into one float64 value (their sum), plus an offset
+ * table over the leading other mode; and the sort's scratch. */
 krps_status krps_tensor_workspace_bytes(int N, const int64_t* dims, int64_t nnz, size_t* bytes);
 
 /* Builds the per-mode fiber index of a COO tensor on the device.
@@ -171,28 +201,33 @@ krps_status krps_tensor_workspace_bytes(int N, const int64_t* dims, int64_t nnz,
  *        the device; out-of-range indices give undefined results)
  *   val  device float32 [nnz]; duplicate coordinates are allowed and mean
  *        the sum of their values.
- * idx and val are read during this call only (the workspace keeps sorted
- * copies).  Synchronises the stream once (sort sizing) and computes
- * ||T||_F^2 of the tensor with duplicates summed. */
+ * idx and val are read during this call only (the workspace keeps sorted,
+ * merged copies).  Synchronises the stream (to read back the number of
+ * distinct coordinates and ||T||_F^2 of the tensor with duplicates
+ * summed).  nnz must be in [1, 2^32). */
 krps_status krps_tensor_create(krps_ctx ctx, int N, const int64_t* dims, int64_t nnz,
                                const int32_t* idx, const float* val, void* ws, size_t ws_bytes,
                                krps_tensor* out);
 krps_status krps_tensor_destroy(krps_tensor t);
 /* ||T||_F^2 (host value; valid after krps_tensor_create returned). */
 krps_status krps_tensor_norm2(krps_tensor t, double* out);
+/* Number of stored entries: distinct coordinates after merging duplicates. */
+krps_status krps_tensor_stored_entries(krps_tensor t, int64_t* out);
 
 /* Bytes of scratch for one sketched solve / sweep / fit with J samples. */
 krps_status krps_solve_workspace_bytes(krps_sampler s, krps_tensor t, int64_t J, size_t* bytes);
 
-/* Algorithm 6 lines 1-3 for factor j: sigma = column norms of U_j, then
+/* The initial normalisation of Algorithm 6 for factor j: sigma = column norms of U_j, then
  * U_j[:, i] /= sigma[i] (zero columns stay zero) and Z_j, G_j are rebuilt.
  * sigma: device float64 [R] out (may be NULL). */
 krps_status krps_normalize_factor(krps_sampler s, int j, double* sigma, void* ws, size_t ws_bytes);
 
-/* One STS-CP solve (Sec. 3.3; Algorithm 6 lines 6-8 with the sampled
+/* One STS-CP solve (Sec. 3.3; the factor update of Algorithm 6 with the sampled
  * solve): draw J rows of U_{!=j} by leverage (uniforms as in krps_sample),
  * form M = (SA)^T SA and Y = (SB)^T SA with S's weights 1/sqrt(J q_d)
- * (Sec. 2.1) and the sampled mode-j fibers of T, set
+ * (Sec. 2.1) and the sampled mode-j fibers of T (samples drawn more than
+ * once select the same fiber; each distinct fiber is expanded once with
+ * the summed weight w^2 of its samples), set
  * U_j = Y M^+ (float64 eigen-pseudo-inverse), sigma = its column norms,
  * renormalise U_j in place and rebuild Z_j and G_j.
  *   sigma  device float64 [R] out.
@@ -200,8 +235,8 @@ krps_status krps_normalize_factor(krps_sampler s, int j, double* sigma, void* ws
 krps_status krps_sketched_solve(krps_sampler s, krps_tensor t, int j, int64_t J,
                                 const double* uniforms, double* sigma, void* ws, size_t ws_bytes);
 
-/* One ALS sweep: krps_sketched_solve for j = 0..N-1 in order (Alg. 6
- * lines 5-9).  uniforms: device float64 [N][J][N][2], block j for solve j.
+/* One ALS sweep: krps_sketched_solve for j = 0..N-1 in order (the inner
+ * loop of Algorithm 6).  uniforms: device float64 [N][J][N][2], block j for solve j.
  * With use_graph != 0 the sweep is captured once into a HIP graph (keyed by
  * the argument pointers) and replayed on later calls with the same
  * arguments; a null context stream is captured on a stream of the
@@ -241,7 +276,7 @@ typedef struct {
   int32_t D;          /* depth, ceil(log2 L) (0 for one leaf) */
   int64_t n_nodes;    /* stored nodes: root + left children */
   int64_t tri;        /* R (R + 1) / 2, elements per stored node */
-  void* nodes;        /* device: n_nodes x tri, packed upper triangle, row-major
+  void* nodes;        /* device: n_nodes x tri (then 64 zero elements), packed upper triangle, row-major
                          (entry (a, b), a <= b, at a*R - a*(a-1)/2 + b - a);
                          node 0 is the root, then for level l = 1..D the left
                          children in position order (position 2m stored at m) */
@@ -261,8 +296,10 @@ typedef struct {
   size_t ggt;         /* float64 [N][R][R]: G_{>k} */
   size_t lam;         /* float64 [N][R]: eigenvalues of G_{>k}, ascending */
   size_t vecs;        /* factor type [N][R][R]: eigenvector u of mode k at [k][u][:] */
-  size_t etree;       /* factor type [N][n_enodes][tri]: E_k trees, same layout as Z */
+  size_t etree;       /* factor type: E_k at etree + k * etree_stride elements, n_enodes
+                         nodes of tri entries in the layout of Z, then zero padding */
   int64_t n_enodes;   /* stored nodes per E_k (F = 1, L = R) */
+  int64_t etree_stride; /* elements from E_k to E_{k+1} */
 } krps_draw_layout;
 
 krps_status krps_draw_layout_query(krps_sampler s, krps_draw_layout* out);

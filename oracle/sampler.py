@@ -277,7 +277,7 @@ class KRPSampler:
         return [k for k in range(self.N) if k != exclude]
 
     def prepare(self, exclude):
-        """Lines 1-5 of Algorithm 2: ``G``, ``G^+``, every ``G_{>k}`` and its
+        """The set-up part of Algorithm 2 (before its per-sample loop): ``G``, ``G^+``, every ``G_{>k}`` and its
         eigendecomposition, and the trees ``E_k``."""
         modes = self.modes(exclude)
         G = hadamard_all([self.G[k] for k in modes])

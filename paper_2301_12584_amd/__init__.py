@@ -39,7 +39,7 @@ class TreeInfo(ctypes.Structure):
 class DrawLayout(ctypes.Structure):
     _fields_ = [("gplus", ctypes.c_size_t), ("rank", ctypes.c_size_t), ("ggt", ctypes.c_size_t),
                 ("lam", ctypes.c_size_t), ("vecs", ctypes.c_size_t), ("etree", ctypes.c_size_t),
-                ("n_enodes", ctypes.c_int64)]
+                ("n_enodes", ctypes.c_int64), ("etree_stride", ctypes.c_int64)]
 
 
 class SolveLayout(ctypes.Structure):
@@ -77,6 +77,9 @@ def lib():
         "krps_sample_workspace_bytes": (c.c_int, [P, c.POINTER(c.c_size_t)]),
         "krps_sample": (c.c_int, [P, c.c_int, c.c_int64, P, P, P, P, P, c.c_size_t, c.c_int]),
         "krps_sample_prepare": (c.c_int, [P, c.c_int, P, c.c_size_t]),
+        "krps_sample_batched_workspace_bytes": (c.c_int, [P, c.c_int, P, P,
+                                                          c.POINTER(c.c_size_t)]),
+        "krps_sample_batched": (c.c_int, [P, c.c_int, P, P, P, P, P, P, P, c.c_size_t]),
         "krps_sample_draw": (c.c_int, [P, c.c_int, c.c_int64, P, P, P, P, P, c.c_size_t]),
         "krps_row_prob": (c.c_int, [P, c.c_int, c.c_int64, P, P, P, c.c_size_t]),
         "krps_tensor_workspace_bytes": (c.c_int, [c.c_int, c.POINTER(c.c_int64), c.c_int64,
@@ -85,6 +88,7 @@ def lib():
                                          c.c_size_t, c.POINTER(P)]),
         "krps_tensor_destroy": (c.c_int, [P]),
         "krps_tensor_norm2": (c.c_int, [P, c.POINTER(c.c_double)]),
+        "krps_tensor_stored_entries": (c.c_int, [P, c.POINTER(c.c_int64)]),
         "krps_solve_workspace_bytes": (c.c_int, [P, P, c.c_int64, c.POINTER(c.c_size_t)]),
         "krps_solve_layout_query": (c.c_int, [P, P, c.c_int64, c.POINTER(SolveLayout)]),
         "krps_normalize_factor": (c.c_int, [P, c.c_int, P, P, c.c_size_t]),
@@ -191,8 +195,8 @@ class Sampler:
         return idx, p, r
 
     def prepare(self, exclude):
-        """Lines 1-5 of Algorithm 2 for ``exclude`` into this sampler's draw
-        workspace."""
+        """The set-up part of Algorithm 2 (before its per-sample loop) for
+        ``exclude`` into this sampler's draw workspace."""
         check(lib().krps_sample_prepare(self.handle, int(exclude), _ptr(self.draw_ws),
                                         self.draw_ws.numel()))
 
@@ -256,13 +260,41 @@ class Sampler:
             "ggt": view(dl.ggt, N * R * R, torch.float64, 8).view(N, R, R).clone(),
             "lam": view(dl.lam, N * R, torch.float64, 8).view(N, R).clone(),
             "vecs": view(dl.vecs, N * R * R, dt, es).view(N, R, R).clone(),
-            "etree": view(dl.etree, N * dl.n_enodes * tri, dt, es).view(N, dl.n_enodes, tri).clone(),
+            "etree": view(dl.etree, N * dl.etree_stride, dt, es).view(N, dl.etree_stride)
+                     [:, :dl.n_enodes * tri].reshape(N, dl.n_enodes, tri).clone(),
         }
 
     def __del__(self):
         if getattr(self, "handle", None) is not None and _lib is not None:
             _lib.krps_sampler_destroy(self.handle)
             self.handle = None
+
+
+def sample_batched(ctx: "Context", samplers, excludes, uniforms, with_prob=True, ws=None):
+    """Algorithm 2 for many samplers in one batched call (one persistent walk
+    launch per storage type).  ``uniforms[p]``: CUDA float64
+    ``[J_p, N_p, 2]``.  Returns ``(idx_list, prob_list)`` (prob entries are
+    None without ``with_prob``).  ``ws``: optional uint8 workspace tensor."""
+    torch = ctx.torch
+    P = len(samplers)
+    hs = (ctypes.c_void_p * P)(*[sp.handle.value for sp in samplers])
+    ex = (ctypes.c_int * P)(*[int(e) for e in excludes])
+    nb = ctypes.c_size_t()
+    check(lib().krps_sample_batched_workspace_bytes(ctx.handle, P, hs, ex, ctypes.byref(nb)))
+    if ws is None or ws.numel() < nb.value:
+        ws = torch.empty(nb.value, dtype=torch.uint8, device=ctx.device)
+    Js = [int(u.shape[0]) for u in uniforms]
+    idx = [torch.empty((J, sp.N), dtype=torch.int32, device=ctx.device)
+           for J, sp in zip(Js, samplers)]
+    prob = [torch.empty(J, dtype=torch.float64, device=ctx.device) if with_prob else None
+            for J in Js]
+    Ja = (ctypes.c_int64 * P)(*Js)
+    ua = (ctypes.c_void_p * P)(*[u.data_ptr() for u in uniforms])
+    ia = (ctypes.c_void_p * P)(*[i.data_ptr() for i in idx])
+    pa = (ctypes.c_void_p * P)(*[(q.data_ptr() if q is not None else 0) for q in prob])
+    check(lib().krps_sample_batched(ctx.handle, P, hs, ex, Ja, ua, ia,
+                                    pa if with_prob else None, _ptr(ws), ws.numel()))
+    return idx, prob
 
 
 class Tensor:
@@ -292,6 +324,13 @@ class Tensor:
     def norm2(self):
         v = ctypes.c_double()
         check(lib().krps_tensor_norm2(self.handle, ctypes.byref(v)))
+        return v.value
+
+    @property
+    def stored_entries(self):
+        """Distinct coordinates (duplicates are merged into one entry)."""
+        v = ctypes.c_int64()
+        check(lib().krps_tensor_stored_entries(self.handle, ctypes.byref(v)))
         return v.value
 
     def __del__(self):

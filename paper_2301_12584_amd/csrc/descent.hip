@@ -1,7 +1,8 @@
-// The batched root-to-leaf descent (KRPSample, Section 3.2 Algorithm 2,
-// lines 6-12; RowSample, Appendix A.5 Algorithm 4).
+// The batched root-to-leaf descent (the per-sample walk of KRPSample,
+// Section 3.2 Algorithm 2; RowSample, Appendix A.5 Algorithm 4).
 //
-// One wavefront per sample (persistent grid-stride loop over samples).
+// A group of LPS lanes per sample, 64 / LPS samples per wavefront
+// (persistent grid-stride loop over samples).
 // For each drawn mode k (increasing k != exclude):
 //   stage 1: walk E_k with the history h: node mass <h h^T, P^v (*) G_k>,
 //            target x1 = u01[d][k][0] * C1  -> eigen-index u
@@ -12,7 +13,8 @@
 // A node mass is a dot product of the stored packed upper triangle with
 // the packed outer product of h (off-diagonal terms doubled), built once
 // per stage and kept in registers: each level is one coalesced read of the
-// node (tri(R) elements, 64 lanes) and a wavefront sum.  Branch decisions
+// node (tri(R) elements over the group's lanes) and a butterfly sum over
+// the group.  Branch decisions
 // and the running offsets low/high are float64 in every precision.
 // After the last mode h is the sampled Khatri-Rao row a_d; its probability
 // q_d = a_d G^+ a_d^T / rank (Section 2.1) is the same kind of dot product
@@ -25,6 +27,12 @@ namespace krps {
 namespace {
 
 constexpr int DESC_WAVES = 4;  // waves per block
+// Waves per SIMD the register allocation of the walk kernels must allow
+// (the walk is bound by the latency of its dependent node reads, so
+// occupancy matters more than registers).
+#ifndef KRPS_DESC_MIN_WAVES
+#define KRPS_DESC_MIN_WAVES 1
+#endif
 
 // Sum over the LPS lanes of one lane group (groups are aligned, LPS a
 // power of two <= 64); every lane of the group gets the result.
@@ -53,11 +61,14 @@ struct Packed {
 };
 
 // Branch-free: entries past the triangle read entry tri-1 and get weight 0.
+// The LDS reads go in batches of 8 entries (a compiler barrier between
+// batches) so that at most 8 entries' operands are in flight in registers.
 template <int LPS, int NP>
 __device__ __forceinline__ void build_packed(Packed<LPS, NP>& P, const double* hb,
                                              const uint16_t* __restrict__ tab, int TR, int sl) {
 #pragma unroll
   for (int m = 0; m < NP; ++m) {
+    if (m % 8 == 0) asm volatile("" ::: "memory");
     const int p = sl + LPS * m;
     const uint16_t ab = tab[p < TR ? p : TR - 1];
     const int a = ab & 0xff, b = ab >> 8;
@@ -72,13 +83,18 @@ __device__ __forceinline__ void build_packed(Packed<LPS, NP>& P, const double* h
 template <typename T, int LPS, int NP>
 __device__ __forceinline__ double node_mass(const Packed<LPS, NP>& P, const double*,
                                             const T* __restrict__ node, int R, int TR, int sl) {
-  // all loads first (in bounds: past-the-end entries re-read entry tri-1,
-  // whose packed weight is 0), then the float64 products
+  // all loads first, then the float64 products.  Only the npr strides
+  // that reach into the triangle are read (npr is uniform); the last may
+  // run up to LPS - 1 entries past the node, into the next node or the
+  // zero padding that follows every node array, with packed weight 0.
+  const int npr = (TR + LPS - 1) / LPS;
   T g[NP];
+  if (npr >= NP) {
 #pragma unroll
-  for (int m = 0; m < NP; ++m) {
-    const int p = sl + LPS * m;
-    g[m] = node[p < TR ? p : TR - 1];
+    for (int m = 0; m < NP; ++m) g[m] = node[sl + LPS * m];
+  } else {
+#pragma unroll
+    for (int m = 0; m < NP; ++m) g[m] = m < npr ? node[sl + LPS * m] : T(0);
   }
   double acc = 0;
 #pragma unroll
@@ -196,6 +212,9 @@ __device__ __forceinline__ int64_t leaf_scan(const T* __restrict__ U, int R, int
   const unsigned long long gmask = LPS == 64 ? ~0ull : ((1ull << LPS) - 1ull);
   int64_t found = -1, last_pos = -1;
   for (int ch = 0; ch < nchunk; ++ch) {
+    // h~ is re-read from LDS in every chunk rather than held in registers
+    // across the scan (RMAX doubles per lane would cost occupancy)
+    asm volatile("" ::: "memory");
     const int64_t base = s0 + (int64_t)ch * LPS;
     const int64_t row = base + sl;
     const bool valid = row < s1;
@@ -214,13 +233,131 @@ __device__ __forceinline__ int64_t leaf_scan(const T* __restrict__ U, int R, int
   return last_pos >= 0 ? last_pos : s1 - 1;
 }
 
-// One wavefront walks 64 / LPS samples at once, LPS lanes per sample
-// (persistent grid-stride loop).  NP == 0 selects the row-broadcast masses
-// (R > 64, LPS == 64).
+// The walk of the samples base + (lane group) of one wavefront: 64 / LPS
+// samples at once, LPS lanes per sample.  `tab` maps packed entry p to its
+// (a, b) pair (LDS or global); `hb` is this group's RMAX doubles of LDS.
+// NP == 0 selects the row-broadcast masses (R > 64, LPS == 64).
 template <typename T, int LPS, int NP, int RMAX>
-__global__ __launch_bounds__(64 * DESC_WAVES) void descent_kernel(DescentArgs a) {
-  constexpr int G = 64 / LPS;
+__device__ __forceinline__ void descend(const DescentArgs& a, int64_t base,
+                                        const uint16_t* __restrict__ tab, double* hb, int lane) {
   constexpr int HE = (RMAX + LPS - 1) / LPS;  // history entries per lane
+  const int R = a.R;
+  const int TR = R * (R + 1) / 2;
+  const int sub = lane / LPS;
+  const int sl = lane % LPS;
+  const int N = a.N;
+  const int64_t J = a.J;
+  const double inv_rank = a.rank ? 1.0 / (double)a.rank[0] : 1.0;
+  const int64_t d = base + sub;
+  const bool active = d < J;
+  // history h = (*) of the rows drawn so far, float64; entry e = sl + LPS i
+  double h[HE];
+#pragma unroll
+  for (int i = 0; i < HE; ++i) h[i] = 1.0;
+  Packed<LPS, NP> P;
+  for (int st = 0; st < a.nsteps; ++st) {
+    const int k = a.order[st];
+    const ModeDesc& md = a.mode[k];
+    const double d1 = active ? a.u01[(d * N + k) * 2 + 0] : 0.5;
+    const double d2 = active ? a.u01[(d * N + k) * 2 + 1] : 0.5;
+    // ---- stage 1: eigen-component u from E_k
+#pragma unroll
+    for (int i = 0; i < HE; ++i)
+      if (sl + LPS * i < R) hb[sl + LPS * i] = h[i];
+    wave_lds_sync();
+    if constexpr (NP > 0) build_packed(P, hb, tab, TR, sl);
+    const T* __restrict__ E = (const T*)md.E;
+    const double C1 = node_mass<T>(P, hb, E, R, TR, sl);
+    double low;
+    int u = (int)walk(E, (int64_t)R, md.DE, P, hb, R, TR, sl, d1 * C1, C1, low);
+    if (u >= R) u = R - 1;
+    // ---- stage 2: row t from Z_k with h~ = h (*) V[:, u]
+    const T* __restrict__ V = (const T*)md.V + (int64_t)u * R;
+    double ht[HE];
+#pragma unroll
+    for (int i = 0; i < HE; ++i) {
+      const int e = sl + LPS * i;
+      ht[i] = e < R ? h[i] * (double)V[e] : 0.0;
+    }
+    wave_lds_sync();
+#pragma unroll
+    for (int i = 0; i < HE; ++i)
+      if (sl + LPS * i < R) hb[sl + LPS * i] = ht[i];
+    wave_lds_sync();
+    if constexpr (NP > 0) build_packed(P, hb, tab, TR, sl);
+    const T* __restrict__ Z = (const T*)md.Z;
+    const double C2 = node_mass<T>(P, hb, Z, R, TR, sl);
+    const double x2 = d2 * C2;
+    const int64_t c = walk(Z, md.L, md.D, P, hb, R, TR, sl, x2, C2, low);
+    const int64_t s0 = c * md.F;
+    const int64_t s1 = s0 + md.F < md.I ? s0 + md.F : md.I;
+    const T* __restrict__ U = (const T*)md.U;
+    const int nchunk = (md.F + LPS - 1) / LPS;
+    int64_t t = leaf_scan<LPS, RMAX>(U, R, s0, s1, nchunk, hb, low, x2, sl, sub);
+    if (t < 0) t = 0;
+    if (t >= md.I) t = md.I - 1;
+    if (sl == 0 && active) a.idx[d * N + k] = (int32_t)t;
+#pragma unroll
+    for (int i = 0; i < HE; ++i) {
+      const int e = sl + LPS * i;
+      if (e < R) h[i] *= (double)U[t * R + e];
+    }
+    if (active && (!(C1 > 0.0) || !(C2 > 0.0))) {
+      if (sl == 0) atomicOr(a.status, ST_NUMERIC);
+    }
+    wave_lds_sync();
+  }
+  if (a.exclude >= 0 && sl == 0 && active) a.idx[d * N + a.exclude] = -1;
+  // ---- probability of the sampled row: q = a G^+ a^T / rank
+  if (a.prob != nullptr || a.rows != nullptr || a.rows64 != nullptr || a.wout != nullptr) {
+#pragma unroll
+    for (int i = 0; i < HE; ++i)
+      if (sl + LPS * i < R) hb[sl + LPS * i] = h[i];
+    wave_lds_sync();
+    if constexpr (NP > 0) build_packed(P, hb, tab, TR, sl);
+    const double q = node_mass<double>(P, hb, a.gplus, R, TR, sl) * inv_rank;
+    if (active) {
+      if (sl == 0 && a.prob != nullptr) a.prob[d] = q;
+      const double w = 1.0 / sqrt((double)J * q);
+      if (sl == 0 && a.wout != nullptr) a.wout[d] = w;
+      const double sc = a.scale_rows ? w : 1.0;
+      if (a.rows != nullptr) {
+        T* rows = (T*)a.rows + d * R;
+#pragma unroll
+        for (int i = 0; i < HE; ++i) {
+          const int e = sl + LPS * i;
+          if (e < R) rows[e] = (T)(h[i] * sc);
+        }
+      }
+      if (a.rows64 != nullptr) {
+        double* rows = a.rows64 + d * R;
+#pragma unroll
+        for (int i = 0; i < HE; ++i) {
+          const int e = sl + LPS * i;
+          if (e < R) rows[e] = h[i] * sc;
+        }
+      }
+    }
+    wave_lds_sync();
+  }
+}
+
+// (a, b) of every packed entry p of an R x R upper triangle.
+__device__ __forceinline__ void fill_tab(uint16_t* tab, int R, int t0, int nt) {
+  const int TR = R * (R + 1) / 2;
+  for (int p = t0; p < TR; p += nt) {
+    int aa = 0;
+    while (aa < R - 1 && packed_index(aa + 1, aa + 1, R) <= p) ++aa;
+    const int bb = aa + (int)(p - packed_index(aa, aa, R));
+    tab[p] = (uint16_t)(aa | (bb << 8));
+  }
+}
+
+// One problem: persistent grid-stride loop of the wavefronts over groups
+// of 64 / LPS samples.
+template <typename T, int LPS, int NP, int RMAX>
+__global__ __launch_bounds__(64 * DESC_WAVES, KRPS_DESC_MIN_WAVES) void descent_kernel(DescentArgs a) {
+  constexpr int G = 64 / LPS;
   extern __shared__ unsigned char smem_raw[];
   const int R = a.R;
   const int TR = R * (R + 1) / 2;
@@ -228,115 +365,58 @@ __global__ __launch_bounds__(64 * DESC_WAVES) void descent_kernel(DescentArgs a)
   double* hb_all = (double*)(smem_raw + ((TR * 2 + 15) / 16) * 16);
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
-  const int sub = lane / LPS;
-  const int sl = lane % LPS;
-  double* hb = hb_all + (wave * G + sub) * 128;
-  for (int p = threadIdx.x; p < TR; p += blockDim.x) {
-    int aa = 0;
-    while (aa < R - 1 && packed_index(aa + 1, aa + 1, R) <= p) ++aa;
-    const int bb = aa + (int)(p - packed_index(aa, aa, R));
-    tab[p] = (uint16_t)(aa | (bb << 8));
-  }
+  double* hb = hb_all + wave * 128 + (lane / LPS) * RMAX;
+  fill_tab(tab, R, threadIdx.x, blockDim.x);
   __syncthreads();
-
-  const int N = a.N;
-  const int64_t J = a.J;
-  const double inv_rank = a.rank ? 1.0 / (double)a.rank[0] : 1.0;
   const int64_t stride = (int64_t)gridDim.x * DESC_WAVES * G;
-  for (int64_t base = ((int64_t)blockIdx.x * DESC_WAVES + wave) * G; base < J; base += stride) {
-    const int64_t d = base + sub;
-    const bool active = d < J;
-    // history h = (*) of the rows drawn so far, float64; entry e = sl + LPS i
-    double h[HE];
-#pragma unroll
-    for (int i = 0; i < HE; ++i) h[i] = 1.0;
-    Packed<LPS, NP> P;
-    for (int st = 0; st < a.nsteps; ++st) {
-      const int k = a.order[st];
-      const ModeDesc& md = a.mode[k];
-      const double d1 = active ? a.u01[(d * N + k) * 2 + 0] : 0.5;
-      const double d2 = active ? a.u01[(d * N + k) * 2 + 1] : 0.5;
-      // ---- stage 1: eigen-component u from E_k
-#pragma unroll
-      for (int i = 0; i < HE; ++i)
-        if (sl + LPS * i < R) hb[sl + LPS * i] = h[i];
-      wave_lds_sync();
-      if constexpr (NP > 0) build_packed(P, hb, tab, TR, sl);
-      const T* __restrict__ E = (const T*)md.E;
-      const double C1 = node_mass<T>(P, hb, E, R, TR, sl);
-      double low;
-      int u = (int)walk(E, (int64_t)R, md.DE, P, hb, R, TR, sl, d1 * C1, C1, low);
-      if (u >= R) u = R - 1;
-      // ---- stage 2: row t from Z_k with h~ = h (*) V[:, u]
-      const T* __restrict__ V = (const T*)md.V + (int64_t)u * R;
-      double ht[HE];
-#pragma unroll
-      for (int i = 0; i < HE; ++i) {
-        const int e = sl + LPS * i;
-        ht[i] = e < R ? h[i] * (double)V[e] : 0.0;
-      }
-      wave_lds_sync();
-#pragma unroll
-      for (int i = 0; i < HE; ++i)
-        if (sl + LPS * i < R) hb[sl + LPS * i] = ht[i];
-      wave_lds_sync();
-      if constexpr (NP > 0) build_packed(P, hb, tab, TR, sl);
-      const T* __restrict__ Z = (const T*)md.Z;
-      const double C2 = node_mass<T>(P, hb, Z, R, TR, sl);
-      const double x2 = d2 * C2;
-      const int64_t c = walk(Z, md.L, md.D, P, hb, R, TR, sl, x2, C2, low);
-      const int64_t s0 = c * md.F;
-      const int64_t s1 = s0 + md.F < md.I ? s0 + md.F : md.I;
-      const T* __restrict__ U = (const T*)md.U;
-      const int nchunk = (md.F + LPS - 1) / LPS;
-      int64_t t = leaf_scan<LPS, RMAX>(U, R, s0, s1, nchunk, hb, low, x2, sl, sub);
-      if (t < 0) t = 0;
-      if (t >= md.I) t = md.I - 1;
-      if (sl == 0 && active) a.idx[d * N + k] = (int32_t)t;
-#pragma unroll
-      for (int i = 0; i < HE; ++i) {
-        const int e = sl + LPS * i;
-        if (e < R) h[i] *= (double)U[t * R + e];
-      }
-      if (active && (!(C1 > 0.0) || !(C2 > 0.0))) {
-        if (sl == 0) atomicOr(a.status, ST_NUMERIC);
-      }
-      wave_lds_sync();
+  for (int64_t base = ((int64_t)blockIdx.x * DESC_WAVES + wave) * G; base < a.J; base += stride)
+    descend<T, LPS, NP, RMAX>(a, base, tab, hb, lane);
+}
+
+// Shape classes of the batched walk (lanes per sample, packed entries per
+// lane, largest R): R <= 8, 16, 32, 64, 128.
+template <int CLS> struct Cls;
+template <> struct Cls<0> { static constexpr int LPS = 4, NP = 9, RMAX = 8; };
+template <> struct Cls<1> { static constexpr int LPS = 8, NP = 17, RMAX = 16; };
+template <> struct Cls<2> { static constexpr int LPS = 32, NP = 17, RMAX = 32; };
+template <> struct Cls<3> { static constexpr int LPS = 64, NP = 33, RMAX = 64; };
+template <> struct Cls<4> { static constexpr int LPS = 64, NP = 0, RMAX = 128; };
+
+// Many problems of one shape class in one persistent launch (Appendix
+// A.10 batching): every wavefront takes the next task -- (problem, group
+// of 64 / LPS samples) -- from a device counter until all tasks are taken;
+// problems are ordered by decreasing cost on the host, so the largest
+// start first.  One kernel per class keeps each class's register budget
+// (and so its occupancy) instead of the largest class's.
+template <typename T, int CLS>
+__global__ __launch_bounds__(64 * DESC_WAVES, KRPS_DESC_MIN_WAVES) void descent_batched_kernel(
+    const BatchProblem* __restrict__ probs, int P, int64_t ntask,
+    unsigned long long* __restrict__ counter) {
+  using C = Cls<CLS>;
+  __shared__ double hb_all[DESC_WAVES * 128];
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  double* hb = hb_all + wave * 128 + (lane / C::LPS) * C::RMAX;
+  for (;;) {
+    long long t = 0;
+    if (lane == 0) t = (long long)atomicAdd(counter, 1ull);
+    t = __shfl(t, 0);
+    if (t >= ntask) break;
+    int lo = 0, hi = P;  // last problem with task0 <= t
+    while (hi - lo > 1) {
+      const int mid = (lo + hi) >> 1;
+      if (probs[mid].task0 <= t) lo = mid; else hi = mid;
     }
-    if (a.exclude >= 0 && sl == 0 && active) a.idx[d * N + a.exclude] = -1;
-    // ---- probability of the sampled row: q = a G^+ a^T / rank
-    if (a.prob != nullptr || a.rows != nullptr || a.rows64 != nullptr || a.wout != nullptr) {
-#pragma unroll
-      for (int i = 0; i < HE; ++i)
-        if (sl + LPS * i < R) hb[sl + LPS * i] = h[i];
-      wave_lds_sync();
-      if constexpr (NP > 0) build_packed(P, hb, tab, TR, sl);
-      const double q = node_mass<double>(P, hb, a.gplus, R, TR, sl) * inv_rank;
-      if (active) {
-        if (sl == 0 && a.prob != nullptr) a.prob[d] = q;
-        const double w = 1.0 / sqrt((double)J * q);
-        if (sl == 0 && a.wout != nullptr) a.wout[d] = w;
-        const double sc = a.scale_rows ? w : 1.0;
-        if (a.rows != nullptr) {
-          T* rows = (T*)a.rows + d * R;
-#pragma unroll
-          for (int i = 0; i < HE; ++i) {
-            const int e = sl + LPS * i;
-            if (e < R) rows[e] = (T)(h[i] * sc);
-          }
-        }
-        if (a.rows64 != nullptr) {
-          double* rows = a.rows64 + d * R;
-#pragma unroll
-          for (int i = 0; i < HE; ++i) {
-            const int e = sl + LPS * i;
-            if (e < R) rows[e] = h[i] * sc;
-          }
-        }
-      }
-      wave_lds_sync();
-    }
+    const BatchProblem& b = probs[lo];
+    const int64_t base = (t - b.task0) * (int64_t)(64 / C::LPS);
+    descend<T, C::LPS, C::NP, C::RMAX>(b.a, base, b.tab, hb, lane);
   }
+}
+
+// Packed-index table of each problem's R (one block per problem).
+__global__ void batch_tab_kernel(const BatchProblem* __restrict__ probs) {
+  const BatchProblem& b = probs[blockIdx.x];
+  if (b.cls < 4) fill_tab((uint16_t*)b.tab, b.a.R, threadIdx.x, blockDim.x);
 }
 
 // q of given multi-indices: a = (*)_k U_k[idx[d][k]], q = a G^+ a^T / rank.
@@ -390,7 +470,7 @@ template <typename T, int LPS, int NP, int RMAX>
 hipError_t run_descent(hipStream_t st, const DescentArgs& a) {
   constexpr int G = 64 / LPS;
   const int TR = a.R * (a.R + 1) / 2;
-  const size_t lds = ((TR * 2 + 15) / 16) * 16 + DESC_WAVES * G * 128 * sizeof(double);
+  const size_t lds = ((TR * 2 + 15) / 16) * 16 + DESC_WAVES * 128 * sizeof(double);
   int64_t blocks = (a.J + DESC_WAVES * G - 1) / (DESC_WAVES * G);
   if (blocks > 256 * 8) blocks = 256 * 8;
   if (blocks < 1) blocks = 1;
@@ -421,6 +501,41 @@ hipError_t launch_descent(hipStream_t st, krps_precision p, const DescentArgs& a
   if (a.J <= 0) return hipSuccess;
   if (p == KRPS_FP64) return dispatch_descent<double>(st, a, a.lps);
   return dispatch_descent<float>(st, a, a.lps);
+}
+
+int batch_class(int R) { return R <= 8 ? 0 : R <= 16 ? 1 : R <= 32 ? 2 : R <= 64 ? 3 : 4; }
+int batch_group(int cls) { return cls == 0 ? 16 : cls == 1 ? 8 : cls == 2 ? 2 : 1; }
+
+template <typename T, int CLS>
+void launch_cls(hipStream_t st, int64_t blocks, const BatchProblem* probs, int P, int64_t ntask,
+                unsigned long long* counter) {
+  hipLaunchKernelGGL((descent_batched_kernel<T, CLS>), dim3((unsigned)blocks),
+                     dim3(64 * DESC_WAVES), 0, st, probs, P, ntask, counter);
+}
+
+template <typename T>
+void launch_batched_t(hipStream_t st, int cls, int64_t blocks, const BatchProblem* probs, int P,
+                      int64_t ntask, unsigned long long* counter) {
+  switch (cls) {
+    case 0: launch_cls<T, 0>(st, blocks, probs, P, ntask, counter); break;
+    case 1: launch_cls<T, 1>(st, blocks, probs, P, ntask, counter); break;
+    case 2: launch_cls<T, 2>(st, blocks, probs, P, ntask, counter); break;
+    case 3: launch_cls<T, 3>(st, blocks, probs, P, ntask, counter); break;
+    default: launch_cls<T, 4>(st, blocks, probs, P, ntask, counter); break;
+  }
+}
+
+hipError_t launch_descent_batched(hipStream_t st, bool f64, int cls, const BatchProblem* probs,
+                                  int P, int64_t ntask, unsigned long long* counter) {
+  hipLaunchKernelGGL(batch_tab_kernel, dim3((unsigned)P), dim3(256), 0, st, probs);
+  if (ntask <= 0) return hipGetLastError();
+  int64_t blocks = (ntask + DESC_WAVES - 1) / DESC_WAVES;
+  if (blocks > 256 * 8) blocks = 256 * 8;
+  if (f64)
+    launch_batched_t<double>(st, cls, blocks, probs, P, ntask, counter);
+  else
+    launch_batched_t<float>(st, cls, blocks, probs, P, ntask, counter);
+  return hipGetLastError();
 }
 
 hipError_t launch_row_prob(hipStream_t st, krps_precision p, const DescentArgs& a) {

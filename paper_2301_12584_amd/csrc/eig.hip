@@ -1,5 +1,5 @@
-// Per-draw preparation in float64 (KRPSample, Section 3.2 Algorithm 2,
-// lines 1-5): G = (*)_{k != j} G_k, its pseudo-inverse and rank, every
+// Per-draw preparation in float64 (the set-up part of KRPSample, Section
+// 3.2 Algorithm 2, before the per-sample loop): G = (*)_{k != j} G_k, its pseudo-inverse and rank, every
 // G_{>k} = G^+ (*) prod_{m > k, m != j} G_m, their eigendecompositions
 // G_{>k} = V_k Lambda_k V_k^T, and the eigen-trees E_k =
 // BuildSampler(sqrt(Lambda_k) V_k^T, F = 1, G_k).
@@ -31,11 +31,6 @@ int prep_threads(int R) {
   if (t > PREP_THREADS) t = PREP_THREADS;
   return (t + 63) / 64 * 64;
 }
-
-struct GList {
-  const double* G[KRPS_MAX_MODES];
-  int order[KRPS_MAX_MODES];
-};
 
 // Lane-exchange of a double through the data-parallel primitives (DPP).
 template <int CTRL>
@@ -165,17 +160,16 @@ __device__ void norms_and_normalise(double* A, int R, double* lam) {
 }
 
 // G = (*) of the listed Grams -> G^+ (full and packed), rank, and G_{>k}
-// for the drawn modes order[0..nsteps-1] (nsteps may be 0).
-__global__ __launch_bounds__(PREP_THREADS) void prep_gplus_kernel(
-    GList gl, int nmat, int R, int nsteps,
-    double* __restrict__ gplus_full, double* __restrict__ gplus_packed, int32_t* __restrict__ rank,
-    double* __restrict__ ggt, int32_t* __restrict__ status) {
-  extern __shared__ double smem[];
-  const int RS = R + 1;
+// for the drawn modes order[0..nsteps-1] (nsteps may be 0).  One block.
+__device__ void prep_gplus_body(const GList& gl, int nmat, int R, int nsteps,
+                                double* __restrict__ gplus_full, double* __restrict__ gplus_packed,
+                                int32_t* __restrict__ rank, double* __restrict__ ggt,
+                                int32_t* __restrict__ status, double* smem) {
   double* A = smem;                 // R*RS
-  double* lam = A + R * RS;         // R
+  double* lam = A + R * (R + 1);    // R
   double* red = lam + R;            // 2
   int* flag = (int*)(red + 2);
+  const int RS = R + 1;
   const int tid = threadIdx.x;
   for (int i = tid; i < R * R; i += blockDim.x) {
     double v = 1.0;
@@ -201,6 +195,9 @@ __global__ __launch_bounds__(PREP_THREADS) void prep_gplus_kernel(
   const double tau = red[0];
   for (int c = tid; c < R; c += blockDim.x) lam[c] = lam[c] > tau ? 1.0 / lam[c] : 0.0;
   __syncthreads();
+  if (gplus_packed != nullptr)
+    for (int i = tid; i < NODE_SLACK; i += blockDim.x)
+      gplus_packed[(int64_t)R * (R + 1) / 2 + i] = 0.0;
   for (int i = tid; i < R * R; i += blockDim.x) {
     const int a = i / R, b = i % R;
     double v = 0;
@@ -216,20 +213,35 @@ __global__ __launch_bounds__(PREP_THREADS) void prep_gplus_kernel(
   }
 }
 
-// One block per drawn mode: eigendecomposition of G_{>k} (ascending), the
-// eigenvectors in the factor type and the eigen-tree E_k.
-template <typename T>
-__global__ __launch_bounds__(PREP_THREADS) void prep_eig_kernel(
-    GList gk, int R, const double* __restrict__ ggt,
-    double* __restrict__ lam_out, T* __restrict__ vecs, T* __restrict__ etree, int64_t enodes,
-    int32_t* __restrict__ sweep_out) {
+__global__ __launch_bounds__(PREP_THREADS) void prep_gplus_kernel(
+    GList gl, int nmat, int R, int nsteps,
+    double* __restrict__ gplus_full, double* __restrict__ gplus_packed, int32_t* __restrict__ rank,
+    double* __restrict__ ggt, int32_t* __restrict__ status) {
   extern __shared__ double smem[];
+  prep_gplus_body(gl, nmat, R, nsteps, gplus_full, gplus_packed, rank, ggt, status, smem);
+}
+
+// One block per job of a batch.
+__global__ __launch_bounds__(PREP_THREADS) void prep_gplus_batched_kernel(
+    const PrepJob* __restrict__ jobs) {
+  extern __shared__ double smem[];
+  const PrepJob& j = jobs[blockIdx.x];
+  prep_gplus_body(j.gl, j.nmat, j.R, j.nsteps, j.gplus_full, j.gplus_packed, j.rank, j.ggt,
+                  j.status, smem);
+}
+
+// Drawn mode `st` of gk: eigendecomposition of G_{>k} (ascending), the
+// eigenvectors in the factor type and the eigen-tree E_k.  One block.
+template <typename T>
+__device__ void prep_eig_body(const GList& gk, int st, int R, const double* __restrict__ ggt,
+                              double* __restrict__ lam_out, T* __restrict__ vecs,
+                              T* __restrict__ etree, int64_t estride,
+                              int32_t* __restrict__ sweep_out, double* smem) {
   const int RS = R + 1;
   double* A = smem;
   double* lam = A + R * RS;
   int* perm = (int*)(lam + R);
   int* flag = perm + R;
-  const int st = blockIdx.x;
   const int k = gk.order[st];
   const double* __restrict__ Gk = gk.G[st];
   const int tid = threadIdx.x;
@@ -257,7 +269,8 @@ __global__ __launch_bounds__(PREP_THREADS) void prep_eig_kernel(
   const int64_t TR = (int64_t)R * (R + 1) / 2;
   const int DE = R > 1 ? 32 - __builtin_clz((unsigned)(R - 1)) : 0;
   const int64_t Lp = int64_t(1) << DE;
-  T* __restrict__ E = etree + (int64_t)k * enodes * TR;
+  T* __restrict__ E = etree + (int64_t)k * estride;
+  for (int64_t i = tid; i < NODE_SLACK; i += blockDim.x) E[estride - NODE_SLACK + i] = T(0);
   for (int64_t p = tid; p < TR; p += blockDim.x) {
     // (a, b) of packed entry p
     int a = 0;
@@ -287,6 +300,24 @@ __global__ __launch_bounds__(PREP_THREADS) void prep_eig_kernel(
   }
 }
 
+template <typename T>
+__global__ __launch_bounds__(PREP_THREADS) void prep_eig_kernel(
+    GList gk, int R, const double* __restrict__ ggt,
+    double* __restrict__ lam_out, T* __restrict__ vecs, T* __restrict__ etree, int64_t estride,
+    int32_t* __restrict__ sweep_out) {
+  extern __shared__ double smem[];
+  prep_eig_body<T>(gk, blockIdx.x, R, ggt, lam_out, vecs, etree, estride, sweep_out, smem);
+}
+
+template <typename T>
+__global__ __launch_bounds__(PREP_THREADS) void prep_eig_batched_kernel(
+    const EigJob* __restrict__ jobs) {
+  extern __shared__ double smem[];
+  const EigJob& j = jobs[blockIdx.x];
+  prep_eig_body<T>(j.gl, j.st, j.R, j.ggt, j.lam, (T*)j.vecs, (T*)j.etree, j.estride,
+                   j.sweep_out, smem);
+}
+
 hipError_t set_lds(const void* fn, size_t bytes) {
   return hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
 }
@@ -313,7 +344,7 @@ hipError_t launch_prep_gplus2(hipStream_t st, int R, int nmat, const double* con
 
 hipError_t launch_prep_eig2(hipStream_t st, krps_precision p, int R, int nsteps,
                             const double* const* Gsteps, const int* order, const double* ggt,
-                            double* lam, void* vecs, void* etree, int64_t enodes,
+                            double* lam, void* vecs, void* etree, int64_t estride,
                             int32_t* sweep_out) {
   GList gl{};
   for (int m = 0; m < nsteps; ++m) {
@@ -326,12 +357,42 @@ hipError_t launch_prep_eig2(hipStream_t st, krps_precision p, int R, int nsteps,
     e = set_lds((const void*)prep_eig_kernel<double>, lds);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(prep_eig_kernel<double>, dim3(nsteps), dim3(prep_threads(R)), lds, st, gl,
-                       R, ggt, lam, (double*)vecs, (double*)etree, enodes, sweep_out);
+                       R, ggt, lam, (double*)vecs, (double*)etree, estride, sweep_out);
   } else {
     e = set_lds((const void*)prep_eig_kernel<float>, lds);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(prep_eig_kernel<float>, dim3(nsteps), dim3(prep_threads(R)), lds, st, gl,
-                       R, ggt, lam, (float*)vecs, (float*)etree, enodes, sweep_out);
+                       R, ggt, lam, (float*)vecs, (float*)etree, estride, sweep_out);
+  }
+  return hipGetLastError();
+}
+
+int prep_block_threads(int R) { return prep_threads(R); }
+
+hipError_t launch_prep_batched(hipStream_t st, const PrepJob* jobs, int njobs, int Rmax) {
+  if (njobs <= 0) return hipSuccess;
+  const size_t lds = prep_lds_bytes(Rmax);
+  hipError_t e = set_lds((const void*)prep_gplus_batched_kernel, lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(prep_gplus_batched_kernel, dim3((unsigned)njobs), dim3(prep_threads(Rmax)),
+                     lds, st, jobs);
+  return hipGetLastError();
+}
+
+hipError_t launch_eig_batched(hipStream_t st, bool f64, const EigJob* jobs, int njobs, int Rmax) {
+  if (njobs <= 0) return hipSuccess;
+  const size_t lds = prep_lds_bytes(Rmax);
+  hipError_t e;
+  if (f64) {
+    e = set_lds((const void*)prep_eig_batched_kernel<double>, lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(prep_eig_batched_kernel<double>, dim3((unsigned)njobs),
+                       dim3(prep_threads(Rmax)), lds, st, jobs);
+  } else {
+    e = set_lds((const void*)prep_eig_batched_kernel<float>, lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(prep_eig_batched_kernel<float>, dim3((unsigned)njobs),
+                       dim3(prep_threads(Rmax)), lds, st, jobs);
   }
   return hipGetLastError();
 }

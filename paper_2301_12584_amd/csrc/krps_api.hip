@@ -1,6 +1,7 @@
 // libkrps C ABI: argument validation, workspace planning and stream-ordered
 // launches of the sampler kernels.  Host code only; every computation runs
 // in the kernels of tree_build.hip, eig.hip and descent.hip.
+#include <algorithm>
 #include <cstdio>
 #include <cmath>
 #include <cstdlib>
@@ -33,6 +34,12 @@ struct krps_ctx_s {
   int device;
   hipStream_t stream;
   hipStream_t capture = nullptr;  // own stream for graph capture when `stream` is null
+  // pinned host staging of batched-draw descriptors; `staged` marks the
+  // copy out of it that must finish before the buffer is rewritten
+  void* pinned = nullptr;
+  size_t pinned_bytes = 0;
+  hipEvent_t staged = nullptr;
+  bool staged_pending = false;
 };
 
 struct krps_sampler_s {
@@ -59,16 +66,18 @@ struct krps_sampler_s {
   int64_t g_J = -1;
   size_t draw_bytes;
   int64_t enodes;
+  int64_t estride;  // elements per mode of the eigen-tree region (nodes + zero padding)
   int DE;
 };
 
 struct krps_tensor_s {
   krps_ctx ctx;
   int N;
-  int64_t nnz;
+  int64_t nnz;                 // entries given
+  int64_t nu = -1;             // stored entries (distinct coordinates)
   std::vector<int64_t> dims;
-  std::vector<int32_t*> cols;  // per mode: [N][nnz]
-  std::vector<float*> vals;    // per mode: [nnz]
+  std::vector<int32_t*> cols;  // per mode: [N][nu]
+  std::vector<double*> vals;   // per mode: [nu], duplicates summed
   std::vector<int64_t*> off;   // per mode: [dims[lead] + 1]
   std::vector<int> lead;
   double norm2 = 0;
@@ -104,7 +113,7 @@ SamplerPlan plan_sampler(int N, const int64_t* I, int R, int F, krps_precision p
     ts.init(I[j], F);
     pl.shape.push_back(ts);
     pl.node_off.push_back(off);
-    off += align_up((size_t)ts.n_nodes * TR * elem_bytes(p));
+    off += align_up((size_t)(ts.n_nodes * TR + NODE_SLACK) * elem_bytes(p));
     pl.gram_off.push_back(off);
     off += align_up((size_t)R * R * 8);
     const size_t sb = tree_build_scratch_bytes(ts.L, R);
@@ -126,12 +135,13 @@ void plan_draw(krps_sampler s) {
   TreeShape es;
   es.init(R, 1);
   s->enodes = es.n_nodes;
+  s->estride = s->enodes * TR + NODE_SLACK;
   size_t off = 0;
   krps_draw_layout& l = s->lay;
   l.gplus = off;
   off += align_up((size_t)R * R * 8);
   const size_t gpacked = off;
-  off += align_up((size_t)TR * 8);
+  off += align_up((size_t)(TR + NODE_SLACK) * 8);
   l.rank = off;
   off += 256;
   l.ggt = off;
@@ -141,8 +151,9 @@ void plan_draw(krps_sampler s) {
   l.vecs = off;
   off += align_up((size_t)N * R * R * s->elem);
   l.etree = off;
-  off += align_up((size_t)N * s->enodes * TR * s->elem);
+  off += align_up((size_t)N * s->estride * s->elem);
   l.n_enodes = s->enodes;
+  l.etree_stride = s->estride;
   s->draw_bytes = off;
   (void)gpacked;
 }
@@ -158,7 +169,7 @@ krps_status build_tree(krps_sampler s, int j) {
 
 void fill_descent_args(krps_sampler s, int exclude, void* ws, DescentArgs& a);
 
-// Enqueues lines 1-5 of Algorithm 2 for exclusion `exclude` into ws and
+// Enqueues the set-up part of Algorithm 2 (before its per-sample loop) for exclusion `exclude` into ws and
 // fills the descent arguments.
 krps_status prepare_draw(krps_sampler s, int exclude, void* ws, DescentArgs& a) {
   char* w = (char*)ws;
@@ -183,7 +194,7 @@ krps_status prepare_draw(krps_sampler s, int exclude, void* ws, DescentArgs& a) 
   hipError_t e = launch_prep_gplus2(st, R, nsteps, mats, nsteps, order, gplus_full, gplus_packed,
                                     rank, ggt, s->status);
   if (e != hipSuccess) return hip_fail(e, "prep G+ launch");
-  e = launch_prep_eig2(st, s->prec, R, nsteps, mats, order, ggt, lam, vecs, etree, s->enodes,
+  e = launch_prep_eig2(st, s->prec, R, nsteps, mats, order, ggt, lam, vecs, etree, s->estride,
                        rank);
   if (e != hipSuccess) return hip_fail(e, "prep eig launch");
   fill_descent_args(s, exclude, ws, a);
@@ -211,7 +222,7 @@ void fill_descent_args(krps_sampler s, int exclude, void* ws, DescentArgs& a) {
     ModeDesc& m = a.mode[k];
     m.U = s->U[k];
     m.Z = s->nodes[k];
-    m.E = w + s->lay.etree + (size_t)k * s->enodes * TR * s->elem;
+    m.E = w + s->lay.etree + (size_t)k * s->estride * s->elem;
     m.V = w + s->lay.vecs + (size_t)k * R * R * s->elem;
     m.I = s->I[k];
     m.L = s->shape[k].L;
@@ -242,7 +253,7 @@ TensorPlan plan_tensor(int N, const int64_t* dims, int64_t nnz) {
     pl.cols_off.push_back(off);
     off += align_up((size_t)N * nnz * 4);
     pl.vals_off.push_back(off);
-    off += align_up((size_t)nnz * 4);
+    off += align_up((size_t)nnz * 8);
     pl.off_off.push_back(off);
     off += align_up((size_t)(dims[lead] + 1) * 8);
   }
@@ -268,6 +279,9 @@ TensorPlan plan_tensor(int N, const int64_t* dims, int64_t nnz) {
 struct SolvePlan {
   krps_solve_layout lay;
   size_t lo, hi, cnt, start, rank, partial, gscratch, gscratch_bytes, fitp, fitout, sig;
+  size_t coef, slot, hkey, hW, hrep;
+  int64_t H;
+  int hbits;
   size_t total;
   int64_t Imax;
 };
@@ -299,6 +313,20 @@ SolvePlan plan_solve(krps_sampler s, int64_t J) {
   off += align_up((size_t)J * 8);
   pl.start = off;
   off += align_up((size_t)(J + 1) * 8);
+  // fiber merge: per-sample coefficient and slot, hash table of H >= 2J slots
+  pl.hbits = 6;
+  while ((int64_t(1) << pl.hbits) < 2 * J) ++pl.hbits;
+  pl.H = int64_t(1) << pl.hbits;
+  pl.coef = off;
+  off += align_up((size_t)J * 8);
+  pl.slot = off;
+  off += align_up((size_t)J * 4);
+  pl.hkey = off;
+  off += align_up((size_t)pl.H * 8);
+  pl.hW = off;
+  off += align_up((size_t)pl.H * 8);
+  pl.hrep = off;
+  off += align_up((size_t)pl.H * 4);
   l.M = off;
   off += align_up((size_t)R * R * 8);
   l.Mp = off;
@@ -361,7 +389,7 @@ krps_status enqueue_solve(krps_sampler s, krps_tensor t, int j, int64_t J, const
   TreeShape tm;
   tm.init(J, R);
   e = launch_tree_build(st, split ? KRPS_BF16X2 : KRPS_FP64, w + l.rows, J, R, tm, nullptr,
-                        (double*)(w + l.M), (double*)(w + pl.gscratch), pl.gscratch_bytes);
+                        (double*)(w + l.M), (double*)(w + pl.gscratch), pl.gscratch_bytes, 3);
   if (e != hipSuccess) return hip_fail(e, "Gram of sampled rows");
   e = launch_pinv(st, R, (double*)(w + l.M), (double*)(w + l.Mp), (int32_t*)(w + pl.rank));
   if (e != hipSuccess) return hip_fail(e, "pseudo-inverse");
@@ -372,20 +400,27 @@ krps_status enqueue_solve(krps_sampler s, krps_tensor t, int j, int64_t J, const
   fa.j = j;
   fa.lead = t->lead[j];
   fa.R = R;
-  fa.nnz = t->nnz;
+  fa.nnz = t->nu;
   fa.J = J;
   fa.cols = t->cols[j];
   fa.vals = t->vals[j];
   fa.off = t->off[j];
   fa.sample_idx = (const int32_t*)(w + l.idx);
+  fa.w = (const double*)(w + l.w);
   fa.lo = (int64_t*)(w + pl.lo);
   fa.hi = (int64_t*)(w + pl.hi);
   fa.cnt = (int64_t*)(w + pl.cnt);
   fa.start = (int64_t*)(w + pl.start);
+  fa.coef = (double*)(w + pl.coef);
+  fa.slot = (int32_t*)(w + pl.slot);
+  fa.hkey = (unsigned long long*)(w + pl.hkey);
+  fa.hW = (double*)(w + pl.hW);
+  fa.hrep = (int32_t*)(w + pl.hrep);
+  fa.H = pl.H;
+  fa.hbits = pl.hbits;
   e = launch_lookup(st, fa);
   if (e != hipSuccess) return hip_fail(e, "fiber lookup");
-  e = launch_spmm(st, split ? KRPS_BF16X2 : KRPS_FP64, fa, w + l.rows, (const double*)(w + l.w),
-                  w + l.Y);
+  e = launch_spmm(st, split ? KRPS_BF16X2 : KRPS_FP64, fa, w + l.rows, w + l.Y);
   if (e != hipSuccess) return hip_fail(e, "SpMM");
   e = launch_solve_gemm(st, s->prec, w + l.Y, (const double*)(w + l.Mp), s->U[j], s->I[j], R,
                         (double*)(w + pl.partial), sigma);
@@ -415,6 +450,11 @@ krps_status krps_ctx_create(int device, void* hip_stream, krps_ctx* out) {
 }
 
 krps_status krps_ctx_destroy(krps_ctx ctx) {
+  if (ctx != nullptr && ctx->staged != nullptr) {
+    (void)hipEventSynchronize(ctx->staged);
+    (void)hipEventDestroy(ctx->staged);
+  }
+  if (ctx != nullptr && ctx->pinned != nullptr) (void)hipHostFree(ctx->pinned);
   if (ctx != nullptr && ctx->capture != nullptr) (void)hipStreamDestroy(ctx->capture);
   delete ctx;
   return KRPS_OK;
@@ -479,9 +519,12 @@ krps_status krps_sampler_create(krps_ctx ctx, int N, const int64_t* I, int R, in
     return hip_fail(e, "hipSetDevice");
   }
   e = hipMemsetAsync(s->status, 0, 4, ctx->stream);
+  for (int j = 0; j < N && e == hipSuccess; ++j)
+    e = launch_fill(ctx->stream, p, (char*)s->nodes[j] + (size_t)pl.shape[j].n_nodes * tri(R) * s->elem,
+                    NODE_SLACK);
   if (e != hipSuccess) {
     delete s;
-    return hip_fail(e, "status clear");
+    return hip_fail(e, "status and padding clear");
   }
   for (int j = 0; j < N; ++j) {
     st = build_tree(s, j);
@@ -570,6 +613,258 @@ krps_status krps_sample(krps_sampler s, int exclude, int64_t J, const double* un
   return KRPS_OK;
 }
 
+}  // extern "C"
+
+namespace {
+
+// Workspace of a batched draw: per problem its draw scratch and packed-
+// index table, then the job and problem descriptors and two task counters.
+struct BatchPlan {
+  std::vector<size_t> draw_off, tab_off;
+  size_t desc = 0, prep = 0, eig = 0, probs = 0, counters = 0, total = 0;
+  int n_eig = 0;
+};
+
+int drawn_modes(krps_sampler s, int exclude) { return exclude >= 0 ? s->N - 1 : s->N; }
+
+BatchPlan plan_batch(int P, const krps_sampler* s, const int* exclude) {
+  BatchPlan pl;
+  size_t off = 0;
+  for (int p = 0; p < P; ++p) {
+    pl.draw_off.push_back(off);
+    off += align_up(s[p]->draw_bytes);
+    pl.tab_off.push_back(off);
+    off += align_up((size_t)tri(s[p]->R) * 2);
+    pl.n_eig += drawn_modes(s[p], exclude[p]);
+  }
+  pl.desc = off;
+  pl.prep = off;
+  off += align_up((size_t)P * sizeof(PrepJob));
+  pl.eig = off;
+  off += align_up((size_t)pl.n_eig * sizeof(EigJob));
+  pl.probs = off;
+  off += align_up((size_t)P * sizeof(BatchProblem));
+  pl.counters = off;
+  off += 256;
+  pl.total = off;
+  return pl;
+}
+
+krps_status check_batch(krps_ctx ctx, int P, const krps_sampler* s, const int* exclude) {
+  if (ctx == nullptr) return fail(KRPS_EINVAL, "ctx is NULL");
+  if (P < 1) return fail(KRPS_EINVAL, "P must be >= 1");
+  if (s == nullptr || exclude == nullptr) return fail(KRPS_EINVAL, "samplers/exclude is NULL");
+  for (int p = 0; p < P; ++p) {
+    if (s[p] == nullptr) return fail(KRPS_EINVAL, "a sampler is NULL");
+    if (s[p]->ctx->device != ctx->device) return fail(KRPS_EINVAL, "sampler on another device");
+    if (exclude[p] < -1 || exclude[p] >= s[p]->N) return fail(KRPS_EINVAL, "exclude out of range");
+  }
+  return KRPS_OK;
+}
+
+// Walk cost of one sample (float64 FMAs), for ordering the tasks.
+double sample_cost(krps_sampler s, int exclude) {
+  const double TR = (double)tri(s->R);
+  double c = 0;
+  for (int k = 0; k < s->N; ++k)
+    if (k != exclude) c += TR * (s->DE + s->shape[k].D + 2) + (double)s->shape[k].F * s->R;
+  return c;
+}
+
+}  // namespace
+
+extern "C" {
+
+krps_status krps_sample_batched_workspace_bytes(krps_ctx ctx, int P, const krps_sampler* s,
+                                                const int* exclude, size_t* bytes) {
+  krps_status st = check_batch(ctx, P, s, exclude);
+  if (st != KRPS_OK) return st;
+  if (bytes == nullptr) return fail(KRPS_EINVAL, "bytes is NULL");
+  *bytes = plan_batch(P, s, exclude).total;
+  return KRPS_OK;
+}
+
+krps_status krps_sample_batched(krps_ctx ctx, int P, const krps_sampler* s, const int* exclude,
+                                const int64_t* J, const double* const* uniforms,
+                                int32_t* const* idx, double* const* prob, void* ws,
+                                size_t ws_bytes) {
+  krps_status st = check_batch(ctx, P, s, exclude);
+  if (st != KRPS_OK) return st;
+  if (J == nullptr || uniforms == nullptr || idx == nullptr)
+    return fail(KRPS_EINVAL, "J/uniforms/idx is NULL");
+  for (int p = 0; p < P; ++p) {
+    if (J[p] < 0) return fail(KRPS_EINVAL, "J < 0");
+    if (J[p] > 0 && (uniforms[p] == nullptr || idx[p] == nullptr))
+      return fail(KRPS_EINVAL, "uniforms/idx of a problem is NULL");
+  }
+  if (ws == nullptr) return fail(KRPS_EINVAL, "workspace is NULL");
+  const BatchPlan pl = plan_batch(P, s, exclude);
+  if (ws_bytes < pl.total) return fail(KRPS_EWORKSPACE, "batched workspace too small");
+  char* w = (char*)ws;
+  KRPS_HIP(hipSetDevice(ctx->device));
+  hipStream_t stream = ctx->stream;
+
+  // host descriptors: preparations (sorted by block size), eigen jobs per
+  // storage type and block size, problems per storage type by falling cost
+  std::vector<int> ord(P);
+  for (int p = 0; p < P; ++p) ord[p] = p;
+  std::vector<double> cost(P);
+  for (int p = 0; p < P; ++p) cost[p] = sample_cost(s[p], exclude[p]) * (double)J[p];
+  // walk groups: (storage type, shape class), each one persistent launch
+  auto group_of = [&](int p) { return (s[p]->prec == KRPS_FP64 ? 0 : 5) + batch_class(s[p]->R); };
+  std::sort(ord.begin(), ord.end(), [&](int x, int y) {
+    const int gx = group_of(x), gy = group_of(y);
+    if (gx != gy) return gx < gy;
+    return cost[x] > cost[y];
+  });
+  std::vector<PrepJob> prep(P);
+  std::vector<EigJob> eig;
+  std::vector<BatchProblem> probs(P);
+  for (int p = 0; p < P; ++p) {
+    krps_sampler sp = s[p];
+    char* dw = w + pl.draw_off[p];
+    const int R = sp->R;
+    PrepJob& pj = prep[p];
+    memset(&pj, 0, sizeof(pj));
+    int nsteps = 0;
+    for (int k = 0; k < sp->N; ++k)
+      if (k != exclude[p]) {
+        pj.gl.order[nsteps] = k;
+        pj.gl.G[nsteps] = sp->gram[k];
+        ++nsteps;
+      }
+    pj.nmat = nsteps;
+    pj.R = R;
+    pj.nsteps = nsteps;
+    pj.gplus_full = (double*)(dw + sp->lay.gplus);
+    pj.gplus_packed = (double*)(dw + gpacked_off(sp));
+    pj.rank = (int32_t*)(dw + sp->lay.rank);
+    pj.ggt = (double*)(dw + sp->lay.ggt);
+    pj.status = sp->status;
+    for (int t = 0; t < nsteps; ++t) {
+      EigJob ej;
+      memset(&ej, 0, sizeof(ej));
+      ej.gl = pj.gl;
+      ej.st = t;
+      ej.R = R;
+      ej.ggt = pj.ggt;
+      ej.lam = (double*)(dw + sp->lay.lam);
+      ej.vecs = dw + sp->lay.vecs;
+      ej.etree = dw + sp->lay.etree;
+      ej.estride = sp->estride;
+      ej.sweep_out = pj.rank;
+      eig.push_back(ej);
+    }
+  }
+  // eigen jobs: float64 storage first, each type by block size
+  std::vector<int> eprob;  // problem of each eigen job (same order as built)
+  for (int p = 0; p < P; ++p)
+    for (int t = 0; t < drawn_modes(s[p], exclude[p]); ++t) eprob.push_back(p);
+  std::vector<int> eord(eig.size());
+  for (size_t i = 0; i < eig.size(); ++i) eord[i] = (int)i;
+  std::stable_sort(eord.begin(), eord.end(), [&](int x, int y) {
+    const bool fx = s[eprob[x]]->prec == KRPS_FP64, fy = s[eprob[y]]->prec == KRPS_FP64;
+    if (fx != fy) return fx;
+    return prep_block_threads(eig[x].R) > prep_block_threads(eig[y].R);
+  });
+  std::vector<EigJob> eig_sorted;
+  for (int i : eord) eig_sorted.push_back(eig[i]);
+  std::vector<int> pord(P);
+  for (int p = 0; p < P; ++p) pord[p] = p;
+  std::stable_sort(pord.begin(), pord.end(), [&](int x, int y) {
+    return prep_block_threads(prep[x].R) > prep_block_threads(prep[y].R);
+  });
+  std::vector<PrepJob> prep_sorted;
+  for (int p : pord) prep_sorted.push_back(prep[p]);
+  // problems
+  int64_t task[10] = {0};
+  int nprob[10] = {0};
+  for (int i = 0; i < P; ++i) {
+    const int p = ord[i];
+    krps_sampler sp = s[p];
+    const int g = group_of(p);
+    BatchProblem& b = probs[i];
+    memset(&b, 0, sizeof(b));
+    fill_descent_args(sp, exclude[p], w + pl.draw_off[p], b.a);
+    b.a.J = J[p];
+    b.a.u01 = uniforms[p];
+    b.a.idx = idx[p];
+    b.a.prob = prob != nullptr ? prob[p] : nullptr;
+    b.tab = (const uint16_t*)(w + pl.tab_off[p]);
+    b.cls = batch_class(sp->R);
+    b.G = batch_group(b.cls);
+    b.task0 = task[g];
+    task[g] += (J[p] + b.G - 1) / b.G;
+    ++nprob[g];
+  }
+  // stage and copy the descriptors
+  const size_t nb = pl.counters - pl.desc;
+  if (ctx->staged_pending) {
+    KRPS_HIP(hipEventSynchronize(ctx->staged));
+    ctx->staged_pending = false;
+  }
+  if (ctx->pinned_bytes < nb) {
+    if (ctx->pinned != nullptr) KRPS_HIP(hipHostFree(ctx->pinned));
+    ctx->pinned = nullptr;
+    ctx->pinned_bytes = 0;
+    KRPS_HIP(hipHostMalloc(&ctx->pinned, nb, hipHostMallocDefault));
+    ctx->pinned_bytes = nb;
+  }
+  if (ctx->staged == nullptr) KRPS_HIP(hipEventCreateWithFlags(&ctx->staged, hipEventDisableTiming));
+  char* hp = (char*)ctx->pinned;
+  memcpy(hp + (pl.prep - pl.desc), prep_sorted.data(), (size_t)P * sizeof(PrepJob));
+  if (!eig_sorted.empty())
+    memcpy(hp + (pl.eig - pl.desc), eig_sorted.data(), eig_sorted.size() * sizeof(EigJob));
+  memcpy(hp + (pl.probs - pl.desc), probs.data(), (size_t)P * sizeof(BatchProblem));
+  KRPS_HIP(hipMemcpyAsync(w + pl.desc, hp, nb, hipMemcpyHostToDevice, stream));
+  KRPS_HIP(hipEventRecord(ctx->staged, stream));
+  ctx->staged_pending = true;
+
+  // preparations, grouped by block size
+  const PrepJob* dprep = (const PrepJob*)(w + pl.prep);
+  for (int i = 0; i < P;) {
+    const int bt = prep_block_threads(prep_sorted[i].R);
+    int j = i, Rmax = 0;
+    while (j < P && prep_block_threads(prep_sorted[j].R) == bt) {
+      Rmax = prep_sorted[j].R > Rmax ? prep_sorted[j].R : Rmax;
+      ++j;
+    }
+    hipError_t e = launch_prep_batched(stream, dprep + i, j - i, Rmax);
+    if (e != hipSuccess) return hip_fail(e, "batched preparation");
+    i = j;
+  }
+  const EigJob* deig = (const EigJob*)(w + pl.eig);
+  const int ne = (int)eig_sorted.size();
+  for (int i = 0; i < ne;) {
+    const bool f64 = s[eprob[eord[i]]]->prec == KRPS_FP64;
+    const int bt = prep_block_threads(eig_sorted[i].R);
+    int j = i, Rmax = 0;
+    while (j < ne && (s[eprob[eord[j]]]->prec == KRPS_FP64) == f64 &&
+           prep_block_threads(eig_sorted[j].R) == bt) {
+      Rmax = eig_sorted[j].R > Rmax ? eig_sorted[j].R : Rmax;
+      ++j;
+    }
+    hipError_t e = launch_eig_batched(stream, f64, deig + i, j - i, Rmax);
+    if (e != hipSuccess) return hip_fail(e, "batched eigen-trees");
+    i = j;
+  }
+  // the walks: one persistent launch per (storage type, shape class) present
+  unsigned long long* counters = (unsigned long long*)(w + pl.counters);
+  hipError_t e = launch_fill_f64(stream, (double*)counters, 10);
+  if (e != hipSuccess) return hip_fail(e, "counter clear");
+  const BatchProblem* dprobs = (const BatchProblem*)(w + pl.probs);
+  int first = 0;
+  for (int g = 0; g < 10; ++g) {
+    if (nprob[g] > 0) {
+      e = launch_descent_batched(stream, g < 5, g % 5, dprobs + first, nprob[g], task[g],
+                                 counters + g);
+      if (e != hipSuccess) return hip_fail(e, "batched walk");
+    }
+    first += nprob[g];
+  }
+  return KRPS_OK;
+}
+
 krps_status krps_row_prob(krps_sampler s, int exclude, int64_t M, const int32_t* idx,
                           double* prob, void* ws, size_t ws_bytes) {
   if (s == nullptr) return fail(KRPS_EINVAL, "sampler is NULL");
@@ -640,7 +935,7 @@ krps_status krps_tensor_create(krps_ctx ctx, int N, const int64_t* dims, int64_t
   for (int j = 0; j < N; ++j) {
     t->dims.push_back(dims[j]);
     t->cols.push_back((int32_t*)(w + pl.cols_off[j]));
-    t->vals.push_back((float*)(w + pl.vals_off[j]));
+    t->vals.push_back((double*)(w + pl.vals_off[j]));
     t->off.push_back((int64_t*)(w + pl.off_off[j]));
     t->lead.push_back(pl.lead[j]);
   }
@@ -649,7 +944,7 @@ krps_status krps_tensor_create(krps_ctx ctx, int N, const int64_t* dims, int64_t
     hipError_t e = build_fiber_index(s, N, dims, nnz, idx, val, j, t->cols[j], t->vals[j],
                                      t->off[j], (uint32_t*)(w + pl.k0), (uint32_t*)(w + pl.k1),
                                      (uint32_t*)(w + pl.p0), (uint32_t*)(w + pl.p1), w + pl.temp,
-                                     pl.temp_bytes);
+                                     pl.temp_bytes, &t->nu);
     if (e != hipSuccess) {
       delete t;
       return hip_fail(e, "fiber index build");
@@ -657,7 +952,7 @@ krps_status krps_tensor_create(krps_ctx ctx, int N, const int64_t* dims, int64_t
   }
   double* acc = (double*)(w + pl.acc);
   hipError_t e = launch_fill_f64(s, acc, 1);
-  if (e == hipSuccess) e = launch_norm2(s, t->cols[0], t->vals[0], N, nnz, acc);
+  if (e == hipSuccess) e = launch_norm2(s, t->vals[0], t->nu, acc);
   if (e == hipSuccess) e = hipMemcpyAsync(&t->norm2, acc, 8, hipMemcpyDeviceToHost, s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);
   if (e != hipSuccess) {
@@ -670,6 +965,12 @@ krps_status krps_tensor_create(krps_ctx ctx, int N, const int64_t* dims, int64_t
 
 krps_status krps_tensor_destroy(krps_tensor t) {
   delete t;
+  return KRPS_OK;
+}
+
+krps_status krps_tensor_stored_entries(krps_tensor t, int64_t* out) {
+  if (t == nullptr || out == nullptr) return fail(KRPS_EINVAL, "tensor/out is NULL");
+  *out = t->nu;
   return KRPS_OK;
 }
 
@@ -803,7 +1104,7 @@ krps_status krps_fit(krps_sampler s, krps_tensor t, const double* sigma, double*
   memset(&fa, 0, sizeof(fa));
   fa.N = s->N;
   fa.R = s->R;
-  fa.nnz = t->nnz;
+  fa.nnz = t->nu;
   fa.cols = t->cols[0];
   fa.vals = t->vals[0];
   for (int k = 0; k < s->N; ++k) {

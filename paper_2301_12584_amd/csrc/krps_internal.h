@@ -79,25 +79,78 @@ struct DescentArgs {
   int32_t* status;                // device status word
 };
 
+// Zero elements that follow every array of stored tree nodes (factor
+// trees, eigen-trees, packed G^+): the walk reads each node in strides of
+// its lane group without clamping, so it may read up to 63 elements past
+// the node's end; they are finite and carry weight 0.
+constexpr int64_t NODE_SLACK = 64;
+
+// Grams multiplied into a preparation, and the drawn modes in order.
+struct GList {
+  const double* G[KRPS_MAX_MODES];
+  int order[KRPS_MAX_MODES];
+};
+
+// One G^+ preparation of a batch (one block each).
+struct PrepJob {
+  GList gl;
+  int nmat, R, nsteps, pad;
+  double* gplus_full;
+  double* gplus_packed;
+  int32_t* rank;
+  double* ggt;
+  int32_t* status;
+};
+
+// One eigen-tree preparation (drawn mode st of a problem) of a batch.
+struct EigJob {
+  GList gl;
+  int st, R;
+  const double* ggt;
+  double* lam;
+  void* vecs;
+  void* etree;
+  int64_t estride;  // elements from one mode's eigen-tree to the next
+  int32_t* sweep_out;
+};
+
+// One problem of a batched draw: its walk arguments, its packed-index
+// table (device, tri(R) uint16; unused for R > 64), its shape class and
+// samples per task, and its first task in the batch's task numbering.
+struct BatchProblem {
+  DescentArgs a;
+  const uint16_t* tab;
+  int cls, G;
+  int64_t task0;
+};
+
 // Fiber lookup / SpMM arguments for one solve of mode j.
 struct FiberArgs {
   int N, j, lead, R;
-  int64_t nnz, J;
+  int64_t nnz, J;             // stored (merged) entries; samples
   const int32_t* cols;        // [N][nnz] columns of mode j's sorted entries
-  const float* vals;          // [nnz]
+  const double* vals;         // [nnz] merged values
   const int64_t* off;         // [dims[lead] + 1] offsets over the leading other mode
   const int32_t* sample_idx;  // [J][N]
+  const double* w;            // [J] 1/sqrt(J q_d)
   int64_t* lo;                // [J] fiber entry range
   int64_t* hi;                // [J]
-  int64_t* cnt;               // [J] work items per sample
+  int64_t* cnt;               // [J] work items per sample (0 unless first of its fiber)
   int64_t* start;             // [J + 1] exclusive prefix of cnt
+  double* coef;               // [J] (sum of w^2 over the fiber's samples) / w_d
+  int32_t* slot;              // [J] hash slot of the sample's fiber (-1: empty fiber)
+  unsigned long long* hkey;   // [H] fiber keys (first entry), all-ones = empty
+  double* hW;                 // [H] summed w^2
+  int32_t* hrep;              // [H] smallest sample index of the fiber
+  int64_t H;                  // power of two >= 2 J
+  int hbits;                  // log2 H
 };
 
 struct FitArgs {
   int N, R;
   int64_t nnz;
   const int32_t* cols;  // [N][nnz] stored entries (any mode's order)
-  const float* vals;
+  const double* vals;
   const void* U[KRPS_MAX_MODES];
   const double* G[KRPS_MAX_MODES];
   const double* sigma;
@@ -111,7 +164,7 @@ enum : int32_t { ST_ZERO = 1, ST_NUMERIC = 2 };
 size_t tree_build_scratch_bytes(int64_t L, int R);
 hipError_t launch_tree_build(hipStream_t st, krps_precision p, const void* U, int64_t I, int R,
                              const TreeShape& ts, void* nodes, double* gram_full,
-                             double* scratch, size_t scratch_bytes);
+                             double* scratch, size_t scratch_bytes, int split_terms = 2);
 
 // eig.hip
 size_t prep_lds_bytes(int R);
@@ -123,22 +176,24 @@ hipError_t launch_prep_gplus2(hipStream_t st, int R, int nmat, const double* con
                               double* gplus_packed, int32_t* rank, double* ggt, int32_t* status);
 hipError_t launch_prep_eig2(hipStream_t st, krps_precision p, int R, int nsteps,
                             const double* const* Gsteps, const int* order, const double* ggt,
-                            double* lam, void* vecs, void* etree, int64_t enodes,
+                            double* lam, void* vecs, void* etree, int64_t estride,
                             int32_t* sweep_out);
 // rank points at two int32: the rank and the Jacobi sweep count.
 hipError_t launch_pinv(hipStream_t st, int R, const double* M, double* Mp_full, int32_t* rank);
 
 // lstsq.hip
 size_t sort_temp_bytes(int64_t nnz);
+// Sorted, merged copy of the tensor for mode j.  *nu < 0 on entry: the
+// count of distinct coordinates is read back (one stream synchronisation)
+// and stored in *nu; otherwise *nu is used as that count.
 hipError_t build_fiber_index(hipStream_t st, int N, const int64_t* dims, int64_t nnz,
                              const int32_t* idx, const float* val, int j, int32_t* cols,
-                             float* vals, int64_t* off, uint32_t* k0, uint32_t* k1, uint32_t* p0,
-                             uint32_t* p1, void* temp, size_t temp_bytes);
-hipError_t launch_norm2(hipStream_t st, const int32_t* cols, const float* vals, int N, int64_t nnz,
-                        double* out);
+                             double* vals, int64_t* off, uint32_t* k0, uint32_t* k1, uint32_t* p0,
+                             uint32_t* p1, void* temp, size_t temp_bytes, int64_t* nu);
+hipError_t launch_norm2(hipStream_t st, const double* vals, int64_t n, double* out);
 hipError_t launch_lookup(hipStream_t st, const FiberArgs& a);
 hipError_t launch_spmm(hipStream_t st, krps_precision p, const FiberArgs& a, const void* rows,
-                       const double* w, void* Y);
+                       void* Y);
 size_t solve_partial_bytes(int R);
 hipError_t launch_fill(hipStream_t st, krps_precision p, void* ptr, int64_t n);
 hipError_t launch_fill_f64(hipStream_t st, double* ptr, int64_t n);
@@ -154,6 +209,14 @@ hipError_t launch_fit(hipStream_t st, krps_precision p, const FitArgs& a, double
 
 // descent.hip
 hipError_t launch_descent(hipStream_t st, krps_precision p, const DescentArgs& a);
+// Batched preparation and walk (jobs and problems in device memory).
+int prep_block_threads(int R);
+hipError_t launch_prep_batched(hipStream_t st, const PrepJob* jobs, int njobs, int Rmax);
+hipError_t launch_eig_batched(hipStream_t st, bool f64, const EigJob* jobs, int njobs, int Rmax);
+int batch_class(int R);
+int batch_group(int cls);
+hipError_t launch_descent_batched(hipStream_t st, bool f64, int cls, const BatchProblem* probs,
+                                  int P, int64_t ntask, unsigned long long* counter);
 hipError_t launch_row_prob(hipStream_t st, krps_precision p, const DescentArgs& a);
 
 }  // namespace krps

@@ -6,16 +6,31 @@
 //                 indices (increasing mode order), then i_j -- the mode-j
 //                 fibers, i.e. the rows of mat(T, j)^T, are contiguous; an
 //                 offset table over the leading other mode narrows lookups.
+//                 Entries with equal coordinates are merged into one stored
+//                 entry whose float64 value is their sum (duplicates mean a
+//                 sum), so a fiber holds each i_j at most once.
 //   lookup      : per sample, the entry range of its fiber (offset table,
 //                 then binary search on the remaining modes).
-//   SpMM        : Y[i_j(e), :] += w_d x_e (w_d a_d) over the fiber entries,
-//                 split into chunks of CH entries so that heavy fibers
-//                 spread over many wavefronts (float atomics on Y).
+//   merge       : samples drawn more than once select the same fiber and
+//                 the same row a_d; their weights w_d^2 are summed in a
+//                 hash table keyed by the fiber, and only the first such
+//                 sample expands the fiber (the rows of the sampling matrix
+//                 are i.i.d. draws, Section 2.1; repeated rows add).  This
+//                 bounds the SpMM by the stored entries.
+//   SpMM        : Y[i_j(e), :] += (sum w^2 / w_d) x_e (w_d a_d) over the
+//                 entries of each distinct sampled fiber, split into chunks
+//                 of CH entries so that heavy fibers spread over many
+//                 wavefronts (float64 atomics on Y).
 //   solve       : U_j = Y M^+ (M^+ in LDS, float64 products), per-column
 //                 sums of squares reduced deterministically, sigma, and the
 //                 renormalisation of U_j.
 //   fit         : <T, T~> over the stored entries and sigma^T (*G_k) sigma.
 #include <rocprim/device/device_radix_sort.hpp>
+#include <rocprim/device/device_reduce_by_key.hpp>
+#include <rocprim/device/device_scan.hpp>
+#include <rocprim/iterator/counting_iterator.hpp>
+#include <rocprim/iterator/discard_iterator.hpp>
+#include <rocprim/iterator/transform_iterator.hpp>
 
 #include "device_common.h"
 #include "krps_internal.h"
@@ -39,17 +54,43 @@ __global__ void gather_key_kernel(uint32_t* __restrict__ keys, const int32_t* __
     keys[i] = (uint32_t)idx[(int64_t)perm[i] * N + col];
 }
 
-// Sorted copy of the tensor for one mode: cols[k][e] = idx[perm[e]][k].
-__global__ void materialize_kernel(int32_t* __restrict__ cols, float* __restrict__ vals,
-                                   const int32_t* __restrict__ idx, const float* __restrict__ val,
-                                   const uint32_t* __restrict__ perm, int N, int64_t n) {
+// head[e] = 1 where the sorted entry e starts a run of equal coordinates.
+__global__ void head_kernel(uint32_t* __restrict__ head, const int32_t* __restrict__ idx,
+                            const uint32_t* __restrict__ perm, int N, int64_t n) {
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
        i += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t p = perm[i];
-    for (int k = 0; k < N; ++k) cols[(int64_t)k * n + i] = idx[p * N + k];
-    vals[i] = val[p];
+    bool h = i == 0;
+    if (!h) {
+      const int32_t* __restrict__ a = idx + (int64_t)perm[i] * N;
+      const int32_t* __restrict__ b = idx + (int64_t)perm[i - 1] * N;
+      for (int k = 0; k < N; ++k) h = h || a[k] != b[k];
+    }
+    head[i] = h ? 1u : 0u;
   }
 }
+
+// Columns of the merged sorted copy for one mode: the head of each run of
+// equal coordinates (run number rid[e] - 1) writes its indices.
+__global__ void coalesce_cols_kernel(int32_t* __restrict__ cols, const int32_t* __restrict__ idx,
+                                     const uint32_t* __restrict__ perm,
+                                     const uint32_t* __restrict__ head,
+                                     const uint32_t* __restrict__ rid, int N, int64_t n,
+                                     int64_t nu) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    if (head[i] == 0) continue;
+    const int64_t q = (int64_t)rid[i] - 1;
+    const int64_t p = perm[i];
+    for (int k = 0; k < N; ++k) cols[(int64_t)k * nu + q] = idx[p * N + k];
+  }
+}
+
+// Value of sorted entry i as float64 (the input of the run sums).
+struct SortedValue {
+  const float* val;
+  const uint32_t* perm;
+  __host__ __device__ double operator()(uint32_t i) const { return (double)val[perm[i]]; }
+};
 
 // off[v] = first entry whose leading key is >= v, for v in [0, dim].
 __global__ void offsets_kernel(int64_t* __restrict__ off, const int32_t* __restrict__ key,
@@ -62,27 +103,14 @@ __global__ void offsets_kernel(int64_t* __restrict__ off, const int32_t* __restr
   }
 }
 
-// ||T||^2 with duplicates summed: entries are sorted by all N columns, so
-// equal coordinates are adjacent; the first entry of each run adds the
-// square of the run's sum.
-__global__ void norm2_kernel(const int32_t* __restrict__ cols, const float* __restrict__ vals,
-                             int N, int64_t n, double* __restrict__ out) {
+// ||T||^2 over the merged entries (each coordinate stored once).
+__global__ void norm2_kernel(const double* __restrict__ vals, int64_t n,
+                             double* __restrict__ out) {
   __shared__ double red[256];
   double acc = 0;
   for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n;
-       e += (int64_t)gridDim.x * blockDim.x) {
-    bool head = e == 0;
-    for (int k = 0; k < N && !head; ++k) head = cols[(int64_t)k * n + e] != cols[(int64_t)k * n + e - 1];
-    if (!head) continue;
-    double s = vals[e];
-    for (int64_t f = e + 1; f < n; ++f) {
-      bool same = true;
-      for (int k = 0; k < N && same; ++k) same = cols[(int64_t)k * n + f] == cols[(int64_t)k * n + e];
-      if (!same) break;
-      s += vals[f];
-    }
-    acc += s * s;
-  }
+       e += (int64_t)gridDim.x * blockDim.x)
+    acc += vals[e] * vals[e];
   red[threadIdx.x] = acc;
   __syncthreads();
   for (int o = blockDim.x / 2; o > 0; o >>= 1) {
@@ -97,10 +125,19 @@ __global__ void norm2_kernel(const int32_t* __restrict__ cols, const float* __re
 // ------------------------------------------------------------------ tensor
 
 size_t sort_temp_bytes(int64_t nnz) {
-  size_t bytes = 0;
+  size_t bytes = 0, sb = 0, rb = 0;
   (void)rocprim::radix_sort_pairs(nullptr, bytes, (uint32_t*)nullptr, (uint32_t*)nullptr,
                                   (uint32_t*)nullptr, (uint32_t*)nullptr, (uint32_t)nnz, 0, 32);
-  return bytes;
+  (void)rocprim::inclusive_scan(nullptr, sb, (const uint32_t*)nullptr, (uint32_t*)nullptr,
+                                (size_t)nnz, rocprim::plus<uint32_t>());
+  auto vin = rocprim::make_transform_iterator(rocprim::make_counting_iterator<uint32_t>(0),
+                                              SortedValue{nullptr, nullptr});
+  (void)rocprim::reduce_by_key(nullptr, rb, (const uint32_t*)nullptr, vin, (size_t)nnz,
+                               rocprim::make_discard_iterator(), (double*)nullptr,
+                               rocprim::make_discard_iterator(), rocprim::plus<double>(),
+                               rocprim::equal_to<uint32_t>());
+  size_t m = bytes > sb ? bytes : sb;
+  return m > rb ? m : rb;
 }
 
 static int bits_of(int64_t dim) {
@@ -111,8 +148,8 @@ static int bits_of(int64_t dim) {
 
 hipError_t build_fiber_index(hipStream_t st, int N, const int64_t* dims, int64_t nnz,
                              const int32_t* idx, const float* val, int j, int32_t* cols,
-                             float* vals, int64_t* off, uint32_t* k0, uint32_t* k1, uint32_t* p0,
-                             uint32_t* p1, void* temp, size_t temp_bytes) {
+                             double* vals, int64_t* off, uint32_t* k0, uint32_t* k1, uint32_t* p0,
+                             uint32_t* p1, void* temp, size_t temp_bytes, int64_t* nu) {
   const int grid = 4096, block = 256;
   hipLaunchKernelGGL(iota_kernel, dim3(grid), dim3(block), 0, st, p0, nnz);
   // LSD: least significant key first (i_j), then the other modes from the
@@ -133,18 +170,39 @@ hipError_t build_fiber_index(hipStream_t st, int N, const int64_t* dims, int64_t
     p0 = p1;
     p1 = t;
   }
-  hipLaunchKernelGGL(materialize_kernel, dim3(grid), dim3(block), 0, st, cols, vals, idx, val, p0,
-                     N, nnz);
+  // runs of equal coordinates -> one stored entry each (k0: heads, k1: run
+  // number, 1-based); each run's value is its float64 sum in sorted order
+  hipLaunchKernelGGL(head_kernel, dim3(grid), dim3(block), 0, st, k0, idx, p0, N, nnz);
+  size_t tb = temp_bytes;
+  hipError_t e = rocprim::inclusive_scan(temp, tb, k0, k1, (size_t)nnz,
+                                         rocprim::plus<uint32_t>(), st);
+  if (e != hipSuccess) return e;
+  if (*nu < 0) {  // the count of distinct coordinates is the same in every mode
+    uint32_t last = 0;
+    e = hipMemcpyAsync(&last, k1 + nnz - 1, 4, hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return e;
+    *nu = (int64_t)last;
+  }
+  auto vin = rocprim::make_transform_iterator(rocprim::make_counting_iterator<uint32_t>(0),
+                                              SortedValue{val, p0});
+  tb = temp_bytes;
+  e = rocprim::reduce_by_key(temp, tb, (const uint32_t*)k1, vin, (size_t)nnz,
+                             rocprim::make_discard_iterator(), vals,
+                             rocprim::make_discard_iterator(), rocprim::plus<double>(),
+                             rocprim::equal_to<uint32_t>(), st);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(coalesce_cols_kernel, dim3(grid), dim3(block), 0, st, cols, idx, p0, k0, k1,
+                     N, nnz, *nu);
   int lead = j == 0 ? 1 : 0;
   if (N == 1) lead = 0;
   hipLaunchKernelGGL(offsets_kernel, dim3(grid), dim3(block), 0, st, off,
-                     cols + (int64_t)lead * nnz, nnz, dims[lead]);
+                     cols + (int64_t)lead * *nu, *nu, dims[lead]);
   return hipGetLastError();
 }
 
-hipError_t launch_norm2(hipStream_t st, const int32_t* cols, const float* vals, int N, int64_t nnz,
-                        double* out) {
-  hipLaunchKernelGGL(norm2_kernel, dim3(1024), dim3(256), 0, st, cols, vals, N, nnz, out);
+hipError_t launch_norm2(hipStream_t st, const double* vals, int64_t n, double* out) {
+  hipLaunchKernelGGL(norm2_kernel, dim3(1024), dim3(256), 0, st, vals, n, out);
   return hipGetLastError();
 }
 
@@ -188,7 +246,96 @@ __global__ void lookup_kernel(FiberArgs a) {
     }
     a.lo[d] = lo;
     a.hi[d] = hi;
-    a.cnt[d] = (hi - lo + CH - 1) / CH;
+  }
+}
+
+constexpr unsigned long long EMPTY_KEY = ~0ull;
+
+__global__ void merge_clear_kernel(FiberArgs a) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < a.H;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    a.hkey[i] = EMPTY_KEY;
+    a.hW[i] = 0.0;
+    a.hrep[i] = INT32_MAX;
+  }
+}
+
+__device__ __forceinline__ int wave_min(int v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    const int u = __shfl_xor(v, o);
+    v = u < v ? u : v;
+  }
+  return v;
+}
+
+// Inserts every sample with a nonempty fiber into the hash table keyed by
+// the fiber's first entry: the slot accumulates sum w_d^2 and the smallest
+// d.  Lanes of a wavefront holding the same key are combined first (one
+// leader per key), so a fiber drawn thousands of times costs few atomics.
+// H >= 2 J, so an empty slot is always found within H probes.
+__global__ __launch_bounds__(256) void merge_insert_kernel(FiberArgs a) {
+  const int lane = threadIdx.x & 63;
+  const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
+  for (int64_t base = wave * 64; base < a.J; base += nwaves * 64) {
+    const int64_t d = base + lane;
+    bool active = false;
+    int64_t key = 0;
+    double w2 = 0.0;
+    if (d < a.J) {
+      key = a.lo[d];
+      active = a.hi[d] > key;
+      const double wd = a.w[d];
+      w2 = wd * wd;
+    }
+    int myslot = -1;
+    for (;;) {
+      const unsigned long long m = __ballot(active);
+      if (m == 0) break;
+      const int leader = __ffsll((long long)m) - 1;
+      const int64_t lkey = __shfl(key, leader);
+      const bool mine = active && key == lkey;
+      const double v = wave_sum(mine ? w2 : 0.0);
+      const int dmin = wave_min(mine ? (int)d : INT32_MAX);
+      int slot = 0;
+      if (lane == leader) {
+        uint64_t h = ((uint64_t)lkey * 0x9E3779B97F4A7C15ull) >> (64 - a.hbits);
+        for (int64_t probe = 0; probe < a.H; ++probe) {
+          const unsigned long long prev =
+              atomicCAS(&a.hkey[h], EMPTY_KEY, (unsigned long long)lkey);
+          if (prev == EMPTY_KEY || prev == (unsigned long long)lkey) break;
+          h = (h + 1) & (uint64_t)(a.H - 1);
+        }
+        slot = (int)h;
+        atomicAdd(&a.hW[slot], v);
+        atomicMin(&a.hrep[slot], dmin);
+      }
+      slot = __shfl(slot, leader);
+      if (mine) {
+        myslot = slot;
+        active = false;
+      }
+    }
+    if (d < a.J) a.slot[d] = myslot;
+  }
+}
+
+// The first sample of each distinct fiber expands it with coefficient
+// (sum w^2) / w_d applied to its stored row w_d a_d; the others expand
+// nothing.
+__global__ void merge_finish_kernel(FiberArgs a) {
+  for (int64_t d = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; d < a.J;
+       d += (int64_t)gridDim.x * blockDim.x) {
+    const int s = a.slot[d];
+    int64_t c = 0;
+    double coef = 0.0;
+    if (s >= 0 && a.hrep[s] == (int)d) {
+      c = (a.hi[d] - a.lo[d] + CH - 1) / CH;
+      coef = a.hW[s] / a.w[d];
+    }
+    a.cnt[d] = c;
+    a.coef[d] = coef;
   }
 }
 
@@ -217,11 +364,10 @@ __global__ __launch_bounds__(1024) void scan_kernel(const int64_t* __restrict__ 
   if (t == 1023) start[J] = part[1023];
 }
 
-// Y[i_j(e), :] += coef_e * rows[d, :] with coef_e = w_d x_e: one wavefront
-// per work item (a chunk of <= CH entries of one fiber), lanes over columns.
+// Y[i_j(e), :] += coef_d x_e rows[d, :]: one wavefront per work item (a
+// chunk of <= CH entries of one distinct sampled fiber), lanes over columns.
 template <typename T>
 __global__ __launch_bounds__(256) void spmm_kernel(FiberArgs a, const T* __restrict__ rows,
-                                                   const double* __restrict__ w,
                                                    double* __restrict__ Y) {
   const int lane = threadIdx.x & 63;
   const int R = a.R;
@@ -239,11 +385,11 @@ __global__ __launch_bounds__(256) void spmm_kernel(FiberArgs a, const T* __restr
     const int64_t d = l;
     const int64_t e0 = a.lo[d] + (c - a.start[d]) * CH;
     const int64_t e1 = e0 + CH < a.hi[d] ? e0 + CH : a.hi[d];
-    const double wd = w[d];
+    const double cd = a.coef[d];
     const T r0 = lane < R ? rows[d * R + lane] : T(0);
     const T r1 = lane + 64 < R ? rows[d * R + lane + 64] : T(0);
     for (int64_t e = e0; e < e1; ++e) {
-      const double coef = wd * (double)a.vals[e];
+      const double coef = cd * a.vals[e];
       const int64_t i = ij[e];
       if (lane < R) atomicAdd(&Y[i * R + lane], coef * (double)r0);
       if (lane + 64 < R) atomicAdd(&Y[i * R + lane + 64], coef * (double)r1);
@@ -258,18 +404,23 @@ hipError_t launch_lookup(hipStream_t st, const FiberArgs& a) {
   if (blocks > 4096) blocks = 4096;
   if (blocks < 1) blocks = 1;
   hipLaunchKernelGGL(lookup_kernel, dim3((unsigned)blocks), dim3(256), 0, st, a);
+  int64_t hb = (a.H + 255) / 256;
+  if (hb > 4096) hb = 4096;
+  hipLaunchKernelGGL(merge_clear_kernel, dim3((unsigned)hb), dim3(256), 0, st, a);
+  hipLaunchKernelGGL(merge_insert_kernel, dim3((unsigned)blocks), dim3(256), 0, st, a);
+  hipLaunchKernelGGL(merge_finish_kernel, dim3((unsigned)blocks), dim3(256), 0, st, a);
   hipLaunchKernelGGL(scan_kernel, dim3(1), dim3(1024), 0, st, a.cnt, a.start, a.J);
   return hipGetLastError();
 }
 
 hipError_t launch_spmm(hipStream_t st, krps_precision p, const FiberArgs& a, const void* rows,
-                       const double* w, void* Y) {
+                       void* Y) {
   if (p == KRPS_FP64)
     hipLaunchKernelGGL(spmm_kernel<double>, dim3(2048), dim3(256), 0, st, a,
-                       (const double*)rows, w, (double*)Y);
+                       (const double*)rows, (double*)Y);
   else
     hipLaunchKernelGGL(spmm_kernel<float>, dim3(2048), dim3(256), 0, st, a, (const float*)rows,
-                       w, (double*)Y);
+                       (double*)Y);
   return hipGetLastError();
 }
 
@@ -488,7 +639,7 @@ __global__ __launch_bounds__(256) void fit_inner_kernel(FitArgs a, double* __res
 #pragma unroll
       for (int q = 0; q < 16; ++q) rowsum += pr[q];
     }
-    acc += (double)a.vals[e] * rowsum;
+    acc += a.vals[e] * rowsum;
   }
   red[threadIdx.x] = acc;
   __syncthreads();

@@ -23,7 +23,10 @@ namespace krps {
 
 namespace {
 
-enum { M_F64 = 0, M_F32 = 1, M_SPLIT = 2 };
+// M_SPLIT: x = hi + lo (bf16 each), products hi hi + hi lo + lo hi (about
+// 2^-16 relative error).  M_SPLIT3: x = hi + mid + lo, the six products
+// whose parts' orders sum to at most 2 (about 2^-24, float32-like).
+enum { M_F64 = 0, M_F32 = 1, M_SPLIT = 2, M_SPLIT3 = 3 };
 
 __device__ __forceinline__ f64x4 mfma_f64(double a, double b, f64x4 c) {
   return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
@@ -55,7 +58,8 @@ __global__ __launch_bounds__(64 * TW) void leaf_run_kernel(const void* __restric
   // storage type of the factor and the nodes; float64 accumulation on the
   // matrix cores except for the bf16 split
   using T = std::conditional_t<MODE == M_F64, double, float>;
-  using ACC = std::conditional_t<MODE == M_SPLIT, f32x4, f64x4>;
+  constexpr bool SPLIT = MODE == M_SPLIT || MODE == M_SPLIT3;
+  using ACC = std::conditional_t<SPLIT, f32x4, f64x4>;
   constexpr int NPAIRS = NT * (NT + 1) / 2;
   constexpr int NPW = (NPAIRS + TW - 1) / TW;
   const T* __restrict__ U = (const T*)Uv;
@@ -76,7 +80,7 @@ __global__ __launch_bounds__(64 * TW) void leaf_run_kernel(const void* __restric
     if (c < L) {
       const int64_t r0 = c * F;
       const int64_t r1 = r0 + F < I ? r0 + F : I;
-      if constexpr (MODE != M_SPLIT) {
+      if constexpr (!SPLIT) {
         // chunks of KS steps of 4 rows: all loads of a chunk are issued
         // before its products
         constexpr int KS = NT <= 2 ? 8 : 4;
@@ -115,7 +119,7 @@ __global__ __launch_bounds__(64 * TW) void leaf_run_kernel(const void* __restric
         }
       } else {
         for (int64_t rb = r0; rb < r1; rb += 32) {
-          bf16x8 hi[NT], lo[NT];
+          bf16x8 hi[NT], lo[NT], mid[NT];
           float xs[NT][8];
           static_for<0, NT>([&](auto tt) {
             constexpr int t = decltype(tt)::value;
@@ -136,7 +140,14 @@ __global__ __launch_bounds__(64 * TW) void leaf_run_kernel(const void* __restric
               const float x = (cv && row < r1) ? xs[t][j] : 0.f;
               const __bf16 h = (__bf16)x;
               hi[t][j] = h;
-              lo[t][j] = (__bf16)(x - (float)h);
+              if constexpr (MODE == M_SPLIT3) {
+                const float r = x - (float)h;
+                const __bf16 m = (__bf16)r;
+                mid[t][j] = m;
+                lo[t][j] = (__bf16)(r - (float)m);
+              } else {
+                lo[t][j] = (__bf16)(x - (float)h);
+              }
             }
           });
           static_for<0, NPAIRS>([&](auto pp) {
@@ -145,9 +156,19 @@ __global__ __launch_bounds__(64 * TW) void leaf_run_kernel(const void* __restric
             constexpr int tb = pair_tb(NT, pr);
             if (pr % TW == wave) {
               ACC a = node[pr / TW];
-              a = mfma_bf16(hi[ta], hi[tb], a);
-              a = mfma_bf16(hi[ta], lo[tb], a);
-              a = mfma_bf16(lo[ta], hi[tb], a);
+              if constexpr (MODE == M_SPLIT3) {
+                // smallest terms first
+                a = mfma_bf16(mid[ta], mid[tb], a);
+                a = mfma_bf16(hi[ta], lo[tb], a);
+                a = mfma_bf16(lo[ta], hi[tb], a);
+                a = mfma_bf16(hi[ta], mid[tb], a);
+                a = mfma_bf16(mid[ta], hi[tb], a);
+                a = mfma_bf16(hi[ta], hi[tb], a);
+              } else {
+                a = mfma_bf16(hi[ta], hi[tb], a);
+                a = mfma_bf16(hi[ta], lo[tb], a);
+                a = mfma_bf16(lo[ta], hi[tb], a);
+              }
               node[pr / TW] = a;
             }
           });
@@ -272,7 +293,7 @@ hipError_t run_leaf(hipStream_t st, const void* U, int64_t I, int R, int F, int6
 template <int MODE>
 hipError_t dispatch_leaf(hipStream_t st, const void* U, int64_t I, int R, int F, int64_t L, int D,
                          void* nodes, double* tops, int& s_eff) {
-  if constexpr (MODE == M_SPLIT) {
+  if constexpr (MODE == M_SPLIT || MODE == M_SPLIT3) {
     if (R <= 16) return run_leaf<MODE, 1, 1, 4>(st, U, I, R, F, L, D, nodes, tops, s_eff);
     if (R <= 32) return run_leaf<MODE, 2, 1, 4>(st, U, I, R, F, L, D, nodes, tops, s_eff);
     if (R <= 64) return run_leaf<MODE, 4, 2, 3>(st, U, I, R, F, L, D, nodes, tops, s_eff);
@@ -299,7 +320,7 @@ size_t tree_build_scratch_bytes(int64_t L, int R) {
 
 hipError_t launch_tree_build(hipStream_t st, krps_precision p, const void* U, int64_t I, int R,
                              const TreeShape& ts, void* nodes, double* gram_full, double* scratch,
-                             size_t scratch_bytes) {
+                             size_t scratch_bytes, int split_terms) {
   const int64_t TR = tri(R);
   const int64_t a_nodes = ceil_div(ts.L, int64_t(1) << MIN_S);
   double* bufA = scratch;
@@ -311,6 +332,8 @@ hipError_t launch_tree_build(hipStream_t st, krps_precision p, const void* U, in
     e = dispatch_leaf<M_F64>(st, U, I, R, ts.F, ts.L, ts.D, nodes, bufA, s_eff);
   else if (p == KRPS_FP32)
     e = dispatch_leaf<M_F32>(st, U, I, R, ts.F, ts.L, ts.D, nodes, bufA, s_eff);
+  else if (split_terms == 3)
+    e = dispatch_leaf<M_SPLIT3>(st, U, I, R, ts.F, ts.L, ts.D, nodes, bufA, s_eff);
   else
     e = dispatch_leaf<M_SPLIT>(st, U, I, R, ts.F, ts.L, ts.D, nodes, bufA, s_eff);
   if (e != hipSuccess) return e;

@@ -32,6 +32,10 @@ __all__ = [
     "planted_cp_tensor",
     "CONFIGS",
     "config_seed",
+    "uniform_seed",
+    "sweep_uniforms",
+    "als_problem",
+    "batched_problems",
 ]
 
 
@@ -78,6 +82,12 @@ def uniforms(J, N, seed):
     words = rng.integers(0, np.iinfo(np.uint64).max, size=(int(J), int(N), 2),
                          dtype=np.uint64, endpoint=True)
     return ((words >> np.uint64(11)).astype(np.float64) + 0.5) * (2.0 ** -53)
+
+
+def sweep_uniforms(seed, sweep, N, J):
+    """Uniforms of one ALS sweep: float64 ``[N][J][N][2]``, block ``j`` for
+    the solve of mode ``j`` (seeded by ``seed + 1000 * sweep + j``)."""
+    return np.stack([uniforms(J, N, int(seed) + 1000 * int(sweep) + j) for j in range(int(N))])
 
 
 def zipf_indices(rng, n, dim, alpha, chunk=1 << 24):
@@ -160,6 +170,19 @@ CONFIGS = {
             dims=(20_000_000, 20_000_000, 20_000_000, 1_000_000),
             nnz=500_000_000, alpha=1.1, R=128, J=131072, sweeps=10),
 }
+
+
+def als_problem(config_no, nnz=None):
+    """Inputs of a sketched CP-ALS workload: ``(dims, idx, val, U0, R, J,
+    sweeps, useed)`` with the COO tensor, the N(0,1) initial factors and
+    the uniform seed (pass it to :func:`sweep_uniforms`).  ``nnz`` overrides
+    the workload's nonzero count (smaller tests of the same recipe)."""
+    cfg = CONFIGS[int(config_no)]
+    dims = cfg["dims"]
+    n = cfg["nnz"] if nnz is None else int(nnz)
+    idx, val = sparse_tensor(dims, n, cfg["alpha"], config_seed(config_no))
+    U0 = gaussian_factors(dims, cfg["R"], config_seed(config_no) + 100)
+    return dims, idx, val, U0, cfg["R"], cfg["J"], cfg["sweeps"], uniform_seed(config_no)
 
 
 def batched_problems(P, seed):

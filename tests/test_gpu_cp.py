@@ -61,6 +61,54 @@ def test_tensor_norm_with_duplicates(env, seed):
     assert abs(T2.norm2 - ref2) <= 1e-9 * ref2
 
 
+def test_duplicates_are_merged_into_stored_entries(env):
+    krps, torch, ctx = env
+    dims = (12, 10, 8)
+    idx, val = dense_coo(dims, 3, dup=500)
+    T = krps.Tensor(ctx, dims, torch.from_numpy(idx).to(ctx.device),
+                    torch.from_numpy(val).to(ctx.device))
+    assert T.stored_entries == len(np.unique(idx, axis=0))
+    zidx, zval = synth.sparse_tensor((50, 40, 30), 100_000, 1.2, seed=8)
+    T2 = krps.Tensor(ctx, (50, 40, 30), torch.from_numpy(zidx).to(ctx.device),
+                     torch.from_numpy(zval).to(ctx.device))
+    assert T2.stored_entries == len(np.unique(zidx, axis=0))
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_repeated_samples_share_one_fiber(env, prec):
+    """A factor with one dominant row makes most samples repeat a few
+    multi-indices; M and Y must still equal the oracle's normal equations
+    on the GPU's own draw (each distinct fiber expanded once with the summed
+    weight of its samples)."""
+    krps, torch, ctx = env
+    dims, R, J = (60, 50, 40), 4, 5000
+    idx, val = synth.sparse_tensor(dims, 30_000, 1.1, seed=12)
+    Us = synth.gaussian_factors(dims, R, seed=13)
+    for U in Us:
+        U[:2] *= 50.0
+    S, T, A = make(krps, torch, ctx, dims, idx, val, Us, prec, J)
+    for k in range(3):
+        A.normalize(k)
+    Un = [S.factors[k].cpu().numpy().astype(np.float64) for k in range(3)]
+    j = 1
+    u01 = synth.uniforms(J, 3, 77)
+    A.solve(j, torch.from_numpy(u01).to(ctx.device))
+    torch.cuda.synchronize()
+    got = {k: v.cpu().numpy() for k, v in A.parts(j).items()}
+    oth = [k for k in range(3) if k != j]
+    n_distinct = len(np.unique(got["idx"][:, oth], axis=0))
+    assert n_distinct < J // 4, n_distinct          # the draw really repeats
+    Tor = ocp.SparseTensor(dims, idx, val)
+    w2 = 1.0 / (J * got["prob"])
+    rows = np.ones((J, R))
+    for k in oth:
+        rows *= Un[k][got["idx"][:, k]]
+    M2, Y2 = ocp.normal_equations(Tor, j, got["idx"].astype(np.int64), rows, w2)
+    tol = 1e-11 if prec == "fp64" else 1e-6
+    assert np.abs(got["M"] - M2).max() <= tol * np.abs(M2).max()
+    assert np.abs(got["Y"] - Y2).max() <= tol * np.abs(Y2).max()
+
+
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
 @pytest.mark.parametrize("j", [0, 1, 2])
 def test_one_solve_matches_oracle(env, prec, j):
