@@ -171,13 +171,25 @@ krps_status krps_sample_batched_workspace_bytes(krps_ctx ctx, int P, const krps_
  *   prob[p]           device float64 [J[p]] out (NULL array or entry: no q)
  *   ws                workspace (krps_sample_batched_workspace_bytes)
  * The results equal P calls of krps_sample with the same arguments.  The
- * descriptors are staged through a pinned host buffer owned by ctx (the
- * call waits for the previous batched call's copy out of it).  Device-side
+ * descriptors are staged through pinned host buffers owned by ctx (a call
+ * waits for the previous batched call's copy out of the same buffer).  Device-side
  * status (EZERO, ENUMERIC) goes to each sampler's status word. */
 krps_status krps_sample_batched(krps_ctx ctx, int P, const krps_sampler* s, const int* exclude,
                                 const int64_t* J, const double* const* uniforms,
                                 int32_t* const* idx, double* const* prob, void* ws,
                                 size_t ws_bytes);
+
+/* The two halves of krps_sample_batched, for callers that time or reuse
+ * them: krps_sample_batched_prepare enqueues the P preparations into ws;
+ * krps_sample_batched_draw enqueues the walks and must follow a prepare
+ * with the same s[], exclude[] and ws (the samplers unchanged since).
+ * Each half stages its descriptors through its own pinned buffer of ctx. */
+krps_status krps_sample_batched_prepare(krps_ctx ctx, int P, const krps_sampler* s,
+                                        const int* exclude, void* ws, size_t ws_bytes);
+krps_status krps_sample_batched_draw(krps_ctx ctx, int P, const krps_sampler* s,
+                                     const int* exclude, const int64_t* J,
+                                     const double* const* uniforms, int32_t* const* idx,
+                                     double* const* prob, void* ws, size_t ws_bytes);
 
 /* Probability q of M given multi-indices (idx [M][N], the excluded column
  * is ignored) under the leverage distribution of the (excluded) product. */

@@ -80,6 +80,8 @@ def lib():
         "krps_sample_batched_workspace_bytes": (c.c_int, [P, c.c_int, P, P,
                                                           c.POINTER(c.c_size_t)]),
         "krps_sample_batched": (c.c_int, [P, c.c_int, P, P, P, P, P, P, P, c.c_size_t]),
+        "krps_sample_batched_prepare": (c.c_int, [P, c.c_int, P, P, P, c.c_size_t]),
+        "krps_sample_batched_draw": (c.c_int, [P, c.c_int, P, P, P, P, P, P, P, c.c_size_t]),
         "krps_sample_draw": (c.c_int, [P, c.c_int, c.c_int64, P, P, P, P, P, c.c_size_t]),
         "krps_row_prob": (c.c_int, [P, c.c_int, c.c_int64, P, P, P, c.c_size_t]),
         "krps_tensor_workspace_bytes": (c.c_int, [c.c_int, c.POINTER(c.c_int64), c.c_int64,
@@ -270,31 +272,63 @@ class Sampler:
             self.handle = None
 
 
-def sample_batched(ctx: "Context", samplers, excludes, uniforms, with_prob=True, ws=None):
-    """Algorithm 2 for many samplers in one batched call (one persistent walk
-    launch per storage type).  ``uniforms[p]``: CUDA float64
-    ``[J_p, N_p, 2]``.  Returns ``(idx_list, prob_list)`` (prob entries are
-    None without ``with_prob``).  ``ws``: optional uint8 workspace tensor."""
-    torch = ctx.torch
-    P = len(samplers)
-    hs = (ctypes.c_void_p * P)(*[sp.handle.value for sp in samplers])
-    ex = (ctypes.c_int * P)(*[int(e) for e in excludes])
-    nb = ctypes.c_size_t()
-    check(lib().krps_sample_batched_workspace_bytes(ctx.handle, P, hs, ex, ctypes.byref(nb)))
-    if ws is None or ws.numel() < nb.value:
-        ws = torch.empty(nb.value, dtype=torch.uint8, device=ctx.device)
-    Js = [int(u.shape[0]) for u in uniforms]
-    idx = [torch.empty((J, sp.N), dtype=torch.int32, device=ctx.device)
-           for J, sp in zip(Js, samplers)]
-    prob = [torch.empty(J, dtype=torch.float64, device=ctx.device) if with_prob else None
-            for J in Js]
-    Ja = (ctypes.c_int64 * P)(*Js)
-    ua = (ctypes.c_void_p * P)(*[u.data_ptr() for u in uniforms])
-    ia = (ctypes.c_void_p * P)(*[i.data_ptr() for i in idx])
-    pa = (ctypes.c_void_p * P)(*[(q.data_ptr() if q is not None else 0) for q in prob])
-    check(lib().krps_sample_batched(ctx.handle, P, hs, ex, Ja, ua, ia,
-                                    pa if with_prob else None, _ptr(ws), ws.numel()))
-    return idx, prob
+class Batch:
+    """Many samplers drawn together (Appendix A.10 batching): batched
+    preparations and one persistent walk launch per storage type and shape
+    class.  ``excludes[p]`` is the exclusion of ``samplers[p]`` (a sampler
+    may appear several times with different exclusions)."""
+
+    def __init__(self, ctx: "Context", samplers, excludes):
+        torch = ctx.torch
+        self.ctx = ctx
+        self.samplers = list(samplers)
+        self.P = len(self.samplers)
+        self._h = (ctypes.c_void_p * self.P)(*[sp.handle.value for sp in self.samplers])
+        self._ex = (ctypes.c_int * self.P)(*[int(e) for e in excludes])
+        nb = ctypes.c_size_t()
+        check(lib().krps_sample_batched_workspace_bytes(ctx.handle, self.P, self._h, self._ex,
+                                                        ctypes.byref(nb)))
+        self.ws = torch.empty(nb.value, dtype=torch.uint8, device=ctx.device)
+
+    def prepare(self):
+        check(lib().krps_sample_batched_prepare(self.ctx.handle, self.P, self._h, self._ex,
+                                                _ptr(self.ws), self.ws.numel()))
+
+    def draw(self, uniforms, idx, prob=None):
+        """Walks into caller tensors: ``uniforms[p]`` float64 ``[J_p, N_p, 2]``,
+        ``idx[p]`` int32 ``[J_p, N_p]``, ``prob[p]`` float64 ``[J_p]`` or None."""
+        P = self.P
+        Ja = (ctypes.c_int64 * P)(*[int(u.shape[0]) for u in uniforms])
+        ua = (ctypes.c_void_p * P)(*[u.data_ptr() for u in uniforms])
+        ia = (ctypes.c_void_p * P)(*[i.data_ptr() for i in idx])
+        pa = None
+        if prob is not None:
+            pa = (ctypes.c_void_p * P)(*[(q.data_ptr() if q is not None else 0) for q in prob])
+        check(lib().krps_sample_batched_draw(self.ctx.handle, P, self._h, self._ex, Ja, ua, ia,
+                                             pa, _ptr(self.ws), self.ws.numel()))
+
+    def sample(self, uniforms, with_prob=True):
+        """One krps_sample_batched call; returns ``(idx_list, prob_list)``."""
+        torch = self.ctx.torch
+        dev = self.ctx.device
+        idx = [torch.empty((int(u.shape[0]), sp.N), dtype=torch.int32, device=dev)
+               for u, sp in zip(uniforms, self.samplers)]
+        prob = [torch.empty(int(u.shape[0]), dtype=torch.float64, device=dev) if with_prob
+                else None for u in uniforms]
+        P = self.P
+        Ja = (ctypes.c_int64 * P)(*[int(u.shape[0]) for u in uniforms])
+        ua = (ctypes.c_void_p * P)(*[u.data_ptr() for u in uniforms])
+        ia = (ctypes.c_void_p * P)(*[i.data_ptr() for i in idx])
+        pa = (ctypes.c_void_p * P)(*[(q.data_ptr() if q is not None else 0) for q in prob])
+        check(lib().krps_sample_batched(self.ctx.handle, P, self._h, self._ex, Ja, ua, ia,
+                                        pa if with_prob else None, _ptr(self.ws), self.ws.numel()))
+        return idx, prob
+
+
+def sample_batched(ctx: "Context", samplers, excludes, uniforms, with_prob=True):
+    """Algorithm 2 for many samplers in one batched call.  ``uniforms[p]``:
+    CUDA float64 ``[J_p, N_p, 2]``.  Returns ``(idx_list, prob_list)``."""
+    return Batch(ctx, samplers, excludes).sample(uniforms, with_prob)
 
 
 class Tensor:

@@ -397,11 +397,17 @@ __global__ __launch_bounds__(64 * DESC_WAVES, KRPS_DESC_MIN_WAVES) void descent_
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
   double* hb = hb_all + wave * 128 + (lane / C::LPS) * C::RMAX;
+  // task numbers are wave-uniform (scalar registers), so the problem's
+  // descriptor is read with scalar loads; the next task is claimed before
+  // the current one is walked, which hides the counter's latency
+  unsigned int claim = 0;
+  if (lane == 0) claim = (unsigned int)atomicAdd(counter, 1ull);
+  unsigned int next = __builtin_amdgcn_readfirstlane(claim);
   for (;;) {
-    long long t = 0;
-    if (lane == 0) t = (long long)atomicAdd(counter, 1ull);
-    t = __shfl(t, 0);
+    const long long t = (long long)next;
     if (t >= ntask) break;
+    claim = 0;
+    if (lane == 0) claim = (unsigned int)atomicAdd(counter, 1ull);
     int lo = 0, hi = P;  // last problem with task0 <= t
     while (hi - lo > 1) {
       const int mid = (lo + hi) >> 1;
@@ -410,6 +416,7 @@ __global__ __launch_bounds__(64 * DESC_WAVES, KRPS_DESC_MIN_WAVES) void descent_
     const BatchProblem& b = probs[lo];
     const int64_t base = (t - b.task0) * (int64_t)(64 / C::LPS);
     descend<T, C::LPS, C::NP, C::RMAX>(b.a, base, b.tab, hb, lane);
+    next = __builtin_amdgcn_readfirstlane(claim);
   }
 }
 

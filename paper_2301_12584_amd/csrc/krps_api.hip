@@ -34,12 +34,13 @@ struct krps_ctx_s {
   int device;
   hipStream_t stream;
   hipStream_t capture = nullptr;  // own stream for graph capture when `stream` is null
-  // pinned host staging of batched-draw descriptors; `staged` marks the
-  // copy out of it that must finish before the buffer is rewritten
-  void* pinned = nullptr;
-  size_t pinned_bytes = 0;
-  hipEvent_t staged = nullptr;
-  bool staged_pending = false;
+  // pinned host staging of batched-draw descriptors (slot 0: preparation
+  // jobs, slot 1: walk problems); `staged` marks the copy out of a slot
+  // that must finish before the slot is rewritten
+  void* pinned[2] = {nullptr, nullptr};
+  size_t pinned_bytes[2] = {0, 0};
+  hipEvent_t staged[2] = {nullptr, nullptr};
+  bool staged_pending[2] = {false, false};
 };
 
 struct krps_sampler_s {
@@ -450,11 +451,13 @@ krps_status krps_ctx_create(int device, void* hip_stream, krps_ctx* out) {
 }
 
 krps_status krps_ctx_destroy(krps_ctx ctx) {
-  if (ctx != nullptr && ctx->staged != nullptr) {
-    (void)hipEventSynchronize(ctx->staged);
-    (void)hipEventDestroy(ctx->staged);
+  for (int i = 0; ctx != nullptr && i < 2; ++i) {
+    if (ctx->staged[i] != nullptr) {
+      (void)hipEventSynchronize(ctx->staged[i]);
+      (void)hipEventDestroy(ctx->staged[i]);
+    }
+    if (ctx->pinned[i] != nullptr) (void)hipHostFree(ctx->pinned[i]);
   }
-  if (ctx != nullptr && ctx->pinned != nullptr) (void)hipHostFree(ctx->pinned);
   if (ctx != nullptr && ctx->capture != nullptr) (void)hipStreamDestroy(ctx->capture);
   delete ctx;
   return KRPS_OK;
@@ -662,6 +665,31 @@ krps_status check_batch(krps_ctx ctx, int P, const krps_sampler* s, const int* e
   return KRPS_OK;
 }
 
+// Copies `bytes` of host descriptors to device memory `dst` on the context
+// stream through pinned staging slot `slot` (waits for that slot's
+// previous copy first).
+krps_status stage_copy(krps_ctx ctx, int slot, const void* src, size_t bytes, void* dst) {
+  if (bytes == 0) return KRPS_OK;
+  if (ctx->staged_pending[slot]) {
+    KRPS_HIP(hipEventSynchronize(ctx->staged[slot]));
+    ctx->staged_pending[slot] = false;
+  }
+  if (ctx->pinned_bytes[slot] < bytes) {
+    if (ctx->pinned[slot] != nullptr) KRPS_HIP(hipHostFree(ctx->pinned[slot]));
+    ctx->pinned[slot] = nullptr;
+    ctx->pinned_bytes[slot] = 0;
+    KRPS_HIP(hipHostMalloc(&ctx->pinned[slot], bytes, hipHostMallocDefault));
+    ctx->pinned_bytes[slot] = bytes;
+  }
+  if (ctx->staged[slot] == nullptr)
+    KRPS_HIP(hipEventCreateWithFlags(&ctx->staged[slot], hipEventDisableTiming));
+  memcpy(ctx->pinned[slot], src, bytes);
+  KRPS_HIP(hipMemcpyAsync(dst, ctx->pinned[slot], bytes, hipMemcpyHostToDevice, ctx->stream));
+  KRPS_HIP(hipEventRecord(ctx->staged[slot], ctx->stream));
+  ctx->staged_pending[slot] = true;
+  return KRPS_OK;
+}
+
 // Walk cost of one sample (float64 FMAs), for ordering the tasks.
 double sample_cost(krps_sampler s, int exclude) {
   const double TR = (double)tri(s->R);
@@ -684,10 +712,115 @@ krps_status krps_sample_batched_workspace_bytes(krps_ctx ctx, int P, const krps_
   return KRPS_OK;
 }
 
-krps_status krps_sample_batched(krps_ctx ctx, int P, const krps_sampler* s, const int* exclude,
-                                const int64_t* J, const double* const* uniforms,
-                                int32_t* const* idx, double* const* prob, void* ws,
-                                size_t ws_bytes) {
+krps_status krps_sample_batched_prepare(krps_ctx ctx, int P, const krps_sampler* s,
+                                        const int* exclude, void* ws, size_t ws_bytes) {
+  krps_status st = check_batch(ctx, P, s, exclude);
+  if (st != KRPS_OK) return st;
+  if (ws == nullptr) return fail(KRPS_EINVAL, "workspace is NULL");
+  const BatchPlan pl = plan_batch(P, s, exclude);
+  if (ws_bytes < pl.total) return fail(KRPS_EWORKSPACE, "batched workspace too small");
+  char* w = (char*)ws;
+  KRPS_HIP(hipSetDevice(ctx->device));
+  hipStream_t stream = ctx->stream;
+  // preparation jobs sorted by block size; eigen jobs by storage type, then
+  // block size
+  std::vector<PrepJob> prep(P);
+  std::vector<EigJob> eig;
+  std::vector<int> eprob;  // problem of each eigen job
+  for (int p = 0; p < P; ++p) {
+    krps_sampler sp = s[p];
+    char* dw = w + pl.draw_off[p];
+    PrepJob& pj = prep[p];
+    memset(&pj, 0, sizeof(pj));
+    int nsteps = 0;
+    for (int k = 0; k < sp->N; ++k)
+      if (k != exclude[p]) {
+        pj.gl.order[nsteps] = k;
+        pj.gl.G[nsteps] = sp->gram[k];
+        ++nsteps;
+      }
+    pj.nmat = nsteps;
+    pj.R = sp->R;
+    pj.nsteps = nsteps;
+    pj.gplus_full = (double*)(dw + sp->lay.gplus);
+    pj.gplus_packed = (double*)(dw + gpacked_off(sp));
+    pj.rank = (int32_t*)(dw + sp->lay.rank);
+    pj.ggt = (double*)(dw + sp->lay.ggt);
+    pj.status = sp->status;
+    for (int t = 0; t < nsteps; ++t) {
+      EigJob ej;
+      memset(&ej, 0, sizeof(ej));
+      ej.gl = pj.gl;
+      ej.st = t;
+      ej.R = sp->R;
+      ej.ggt = pj.ggt;
+      ej.lam = (double*)(dw + sp->lay.lam);
+      ej.vecs = dw + sp->lay.vecs;
+      ej.etree = dw + sp->lay.etree;
+      ej.estride = sp->estride;
+      ej.sweep_out = pj.rank;
+      eig.push_back(ej);
+      eprob.push_back(p);
+    }
+  }
+  std::vector<int> pord(P);
+  for (int p = 0; p < P; ++p) pord[p] = p;
+  std::stable_sort(pord.begin(), pord.end(), [&](int x, int y) {
+    return prep_block_threads(prep[x].R) > prep_block_threads(prep[y].R);
+  });
+  std::vector<PrepJob> prep_sorted;
+  for (int p : pord) prep_sorted.push_back(prep[p]);
+  std::vector<int> eord(eig.size());
+  for (size_t i = 0; i < eig.size(); ++i) eord[i] = (int)i;
+  auto ef64 = [&](int i) { return s[eprob[i]]->prec == KRPS_FP64; };
+  std::stable_sort(eord.begin(), eord.end(), [&](int x, int y) {
+    if (ef64(x) != ef64(y)) return ef64(x);
+    return prep_block_threads(eig[x].R) > prep_block_threads(eig[y].R);
+  });
+  std::vector<EigJob> eig_sorted;
+  for (int i : eord) eig_sorted.push_back(eig[i]);
+  // stage and copy the job descriptors
+  std::vector<char> host(pl.probs - pl.prep);
+  memcpy(host.data(), prep_sorted.data(), (size_t)P * sizeof(PrepJob));
+  if (!eig_sorted.empty())
+    memcpy(host.data() + (pl.eig - pl.prep), eig_sorted.data(),
+           eig_sorted.size() * sizeof(EigJob));
+  st = stage_copy(ctx, 0, host.data(), host.size(), w + pl.prep);
+  if (st != KRPS_OK) return st;
+  // preparations, grouped by block size
+  const PrepJob* dprep = (const PrepJob*)(w + pl.prep);
+  for (int i = 0; i < P;) {
+    const int bt = prep_block_threads(prep_sorted[i].R);
+    int j = i, Rmax = 0;
+    while (j < P && prep_block_threads(prep_sorted[j].R) == bt) {
+      Rmax = prep_sorted[j].R > Rmax ? prep_sorted[j].R : Rmax;
+      ++j;
+    }
+    hipError_t e = launch_prep_batched(stream, dprep + i, j - i, Rmax);
+    if (e != hipSuccess) return hip_fail(e, "batched preparation");
+    i = j;
+  }
+  const EigJob* deig = (const EigJob*)(w + pl.eig);
+  const int ne = (int)eig_sorted.size();
+  for (int i = 0; i < ne;) {
+    const bool f64 = ef64(eord[i]);
+    const int bt = prep_block_threads(eig_sorted[i].R);
+    int j = i, Rmax = 0;
+    while (j < ne && ef64(eord[j]) == f64 && prep_block_threads(eig_sorted[j].R) == bt) {
+      Rmax = eig_sorted[j].R > Rmax ? eig_sorted[j].R : Rmax;
+      ++j;
+    }
+    hipError_t e = launch_eig_batched(stream, f64, deig + i, j - i, Rmax);
+    if (e != hipSuccess) return hip_fail(e, "batched eigen-trees");
+    i = j;
+  }
+  return KRPS_OK;
+}
+
+krps_status krps_sample_batched_draw(krps_ctx ctx, int P, const krps_sampler* s,
+                                     const int* exclude, const int64_t* J,
+                                     const double* const* uniforms, int32_t* const* idx,
+                                     double* const* prob, void* ws, size_t ws_bytes) {
   krps_status st = check_batch(ctx, P, s, exclude);
   if (st != KRPS_OK) return st;
   if (J == nullptr || uniforms == nullptr || idx == nullptr)
@@ -703,80 +836,19 @@ krps_status krps_sample_batched(krps_ctx ctx, int P, const krps_sampler* s, cons
   char* w = (char*)ws;
   KRPS_HIP(hipSetDevice(ctx->device));
   hipStream_t stream = ctx->stream;
-
-  // host descriptors: preparations (sorted by block size), eigen jobs per
-  // storage type and block size, problems per storage type by falling cost
-  std::vector<int> ord(P);
-  for (int p = 0; p < P; ++p) ord[p] = p;
+  // walk groups: (storage type, shape class), each one persistent launch,
+  // problems in a group by falling cost
   std::vector<double> cost(P);
   for (int p = 0; p < P; ++p) cost[p] = sample_cost(s[p], exclude[p]) * (double)J[p];
-  // walk groups: (storage type, shape class), each one persistent launch
   auto group_of = [&](int p) { return (s[p]->prec == KRPS_FP64 ? 0 : 5) + batch_class(s[p]->R); };
+  std::vector<int> ord(P);
+  for (int p = 0; p < P; ++p) ord[p] = p;
   std::sort(ord.begin(), ord.end(), [&](int x, int y) {
     const int gx = group_of(x), gy = group_of(y);
     if (gx != gy) return gx < gy;
     return cost[x] > cost[y];
   });
-  std::vector<PrepJob> prep(P);
-  std::vector<EigJob> eig;
   std::vector<BatchProblem> probs(P);
-  for (int p = 0; p < P; ++p) {
-    krps_sampler sp = s[p];
-    char* dw = w + pl.draw_off[p];
-    const int R = sp->R;
-    PrepJob& pj = prep[p];
-    memset(&pj, 0, sizeof(pj));
-    int nsteps = 0;
-    for (int k = 0; k < sp->N; ++k)
-      if (k != exclude[p]) {
-        pj.gl.order[nsteps] = k;
-        pj.gl.G[nsteps] = sp->gram[k];
-        ++nsteps;
-      }
-    pj.nmat = nsteps;
-    pj.R = R;
-    pj.nsteps = nsteps;
-    pj.gplus_full = (double*)(dw + sp->lay.gplus);
-    pj.gplus_packed = (double*)(dw + gpacked_off(sp));
-    pj.rank = (int32_t*)(dw + sp->lay.rank);
-    pj.ggt = (double*)(dw + sp->lay.ggt);
-    pj.status = sp->status;
-    for (int t = 0; t < nsteps; ++t) {
-      EigJob ej;
-      memset(&ej, 0, sizeof(ej));
-      ej.gl = pj.gl;
-      ej.st = t;
-      ej.R = R;
-      ej.ggt = pj.ggt;
-      ej.lam = (double*)(dw + sp->lay.lam);
-      ej.vecs = dw + sp->lay.vecs;
-      ej.etree = dw + sp->lay.etree;
-      ej.estride = sp->estride;
-      ej.sweep_out = pj.rank;
-      eig.push_back(ej);
-    }
-  }
-  // eigen jobs: float64 storage first, each type by block size
-  std::vector<int> eprob;  // problem of each eigen job (same order as built)
-  for (int p = 0; p < P; ++p)
-    for (int t = 0; t < drawn_modes(s[p], exclude[p]); ++t) eprob.push_back(p);
-  std::vector<int> eord(eig.size());
-  for (size_t i = 0; i < eig.size(); ++i) eord[i] = (int)i;
-  std::stable_sort(eord.begin(), eord.end(), [&](int x, int y) {
-    const bool fx = s[eprob[x]]->prec == KRPS_FP64, fy = s[eprob[y]]->prec == KRPS_FP64;
-    if (fx != fy) return fx;
-    return prep_block_threads(eig[x].R) > prep_block_threads(eig[y].R);
-  });
-  std::vector<EigJob> eig_sorted;
-  for (int i : eord) eig_sorted.push_back(eig[i]);
-  std::vector<int> pord(P);
-  for (int p = 0; p < P; ++p) pord[p] = p;
-  std::stable_sort(pord.begin(), pord.end(), [&](int x, int y) {
-    return prep_block_threads(prep[x].R) > prep_block_threads(prep[y].R);
-  });
-  std::vector<PrepJob> prep_sorted;
-  for (int p : pord) prep_sorted.push_back(prep[p]);
-  // problems
   int64_t task[10] = {0};
   int nprob[10] = {0};
   for (int i = 0; i < P; ++i) {
@@ -797,58 +869,8 @@ krps_status krps_sample_batched(krps_ctx ctx, int P, const krps_sampler* s, cons
     task[g] += (J[p] + b.G - 1) / b.G;
     ++nprob[g];
   }
-  // stage and copy the descriptors
-  const size_t nb = pl.counters - pl.desc;
-  if (ctx->staged_pending) {
-    KRPS_HIP(hipEventSynchronize(ctx->staged));
-    ctx->staged_pending = false;
-  }
-  if (ctx->pinned_bytes < nb) {
-    if (ctx->pinned != nullptr) KRPS_HIP(hipHostFree(ctx->pinned));
-    ctx->pinned = nullptr;
-    ctx->pinned_bytes = 0;
-    KRPS_HIP(hipHostMalloc(&ctx->pinned, nb, hipHostMallocDefault));
-    ctx->pinned_bytes = nb;
-  }
-  if (ctx->staged == nullptr) KRPS_HIP(hipEventCreateWithFlags(&ctx->staged, hipEventDisableTiming));
-  char* hp = (char*)ctx->pinned;
-  memcpy(hp + (pl.prep - pl.desc), prep_sorted.data(), (size_t)P * sizeof(PrepJob));
-  if (!eig_sorted.empty())
-    memcpy(hp + (pl.eig - pl.desc), eig_sorted.data(), eig_sorted.size() * sizeof(EigJob));
-  memcpy(hp + (pl.probs - pl.desc), probs.data(), (size_t)P * sizeof(BatchProblem));
-  KRPS_HIP(hipMemcpyAsync(w + pl.desc, hp, nb, hipMemcpyHostToDevice, stream));
-  KRPS_HIP(hipEventRecord(ctx->staged, stream));
-  ctx->staged_pending = true;
-
-  // preparations, grouped by block size
-  const PrepJob* dprep = (const PrepJob*)(w + pl.prep);
-  for (int i = 0; i < P;) {
-    const int bt = prep_block_threads(prep_sorted[i].R);
-    int j = i, Rmax = 0;
-    while (j < P && prep_block_threads(prep_sorted[j].R) == bt) {
-      Rmax = prep_sorted[j].R > Rmax ? prep_sorted[j].R : Rmax;
-      ++j;
-    }
-    hipError_t e = launch_prep_batched(stream, dprep + i, j - i, Rmax);
-    if (e != hipSuccess) return hip_fail(e, "batched preparation");
-    i = j;
-  }
-  const EigJob* deig = (const EigJob*)(w + pl.eig);
-  const int ne = (int)eig_sorted.size();
-  for (int i = 0; i < ne;) {
-    const bool f64 = s[eprob[eord[i]]]->prec == KRPS_FP64;
-    const int bt = prep_block_threads(eig_sorted[i].R);
-    int j = i, Rmax = 0;
-    while (j < ne && (s[eprob[eord[j]]]->prec == KRPS_FP64) == f64 &&
-           prep_block_threads(eig_sorted[j].R) == bt) {
-      Rmax = eig_sorted[j].R > Rmax ? eig_sorted[j].R : Rmax;
-      ++j;
-    }
-    hipError_t e = launch_eig_batched(stream, f64, deig + i, j - i, Rmax);
-    if (e != hipSuccess) return hip_fail(e, "batched eigen-trees");
-    i = j;
-  }
-  // the walks: one persistent launch per (storage type, shape class) present
+  st = stage_copy(ctx, 1, probs.data(), (size_t)P * sizeof(BatchProblem), w + pl.probs);
+  if (st != KRPS_OK) return st;
   unsigned long long* counters = (unsigned long long*)(w + pl.counters);
   hipError_t e = launch_fill_f64(stream, (double*)counters, 10);
   if (e != hipSuccess) return hip_fail(e, "counter clear");
@@ -863,6 +885,17 @@ krps_status krps_sample_batched(krps_ctx ctx, int P, const krps_sampler* s, cons
     first += nprob[g];
   }
   return KRPS_OK;
+}
+
+krps_status krps_sample_batched(krps_ctx ctx, int P, const krps_sampler* s, const int* exclude,
+                                const int64_t* J, const double* const* uniforms,
+                                int32_t* const* idx, double* const* prob, void* ws,
+                                size_t ws_bytes) {
+  if (J == nullptr || uniforms == nullptr || idx == nullptr)
+    return fail(KRPS_EINVAL, "J/uniforms/idx is NULL");
+  krps_status st = krps_sample_batched_prepare(ctx, P, s, exclude, ws, ws_bytes);
+  if (st != KRPS_OK) return st;
+  return krps_sample_batched_draw(ctx, P, s, exclude, J, uniforms, idx, prob, ws, ws_bytes);
 }
 
 krps_status krps_row_prob(krps_sampler s, int exclude, int64_t M, const int32_t* idx,

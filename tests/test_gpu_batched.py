@@ -111,3 +111,24 @@ def test_batched_empty_problem_and_no_prob(env):
     idx2, _ = krps.sample_batched(ctx, [S2], [0], [u2])
     torch.cuda.synchronize()
     assert torch.equal(idx2[0], ref)
+
+
+def test_one_sampler_all_exclusions_prepare_then_draw(env):
+    """The same sampler listed once per exclusion; the walk is drawn twice
+    after one preparation and equals one krps_sample per exclusion."""
+    krps, torch, ctx = env
+    _, S = make(krps, torch, ctx, (4000, 3000, 2000), 32, "fp32", 5)
+    J = 4096
+    unis = [torch.from_numpy(synth.uniforms(J, 3, 60 + k)).to(ctx.device) for k in range(3)]
+    batch = krps.Batch(ctx, [S, S, S], [0, 1, 2])
+    batch.prepare()
+    idx = [torch.empty((J, 3), dtype=torch.int32, device=ctx.device) for _ in range(3)]
+    prob = [torch.empty(J, dtype=torch.float64, device=ctx.device) for _ in range(3)]
+    for rep in range(2):
+        batch.draw(unis, idx, prob)
+        torch.cuda.synchronize()
+        for k in range(3):
+            ref_i, ref_p, _ = S.sample(k, unis[k])
+            torch.cuda.synchronize()
+            assert torch.equal(idx[k], ref_i), (rep, k)
+            assert torch.equal(prob[k], ref_p), (rep, k)
