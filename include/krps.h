@@ -262,6 +262,62 @@ krps_status krps_als_sweep(krps_sampler s, krps_tensor t, int64_t J, const doubl
 krps_status krps_fit(krps_sampler s, krps_tensor t, const double* sigma, double* fit, void* ws,
                      size_t ws_bytes);
 
+/* Bytes of workspace for krps_sketched_lstsq with R columns, J sampled
+ * rows and n right-hand sides. */
+krps_status krps_lstsq_workspace_bytes(int R, int64_t J, int64_t n, size_t* bytes);
+
+/* The sampled least-squares problem min_X || S A X - S B ||_F on its own
+ * (Section 2.1), from rows already drawn: S has one row per sample d with
+ * weight w_d = 1/sqrt(J q_d) at the sampled row of A.  Normal equations
+ * with a float64 eigen-pseudo-inverse: X = M^+ Z, M = sum_d w_d^2 a_d a_d^T,
+ * Z = sum_d w_d^2 a_d b_d^T.
+ *   rows     device [J][R]: a_d, the sampled rows of A (unscaled), float64
+ *            for KRPS_FP64 and float32 otherwise
+ *   prob     device float64 [J]: q_d of each sample (> 0)
+ *   SB_rows  device [J][n]: b_d, the rows of B at the sampled indices
+ *            (unscaled), same type as rows
+ *   X        device float64 [R][n] out
+ *   ws       workspace (krps_lstsq_workspace_bytes)
+ * The arithmetic is float64 in every precision. */
+krps_status krps_sketched_lstsq(krps_ctx ctx, int R, int64_t J, const void* rows,
+                                const double* prob, int64_t n, const void* SB_rows, double* X,
+                                krps_precision p, void* ws, size_t ws_bytes);
+
+/* ------------------------------------------------------------------ */
+/* Autotuning of the walk (leaf size F of the factor trees, lanes per   */
+/* sample of the walk kernel)                                          */
+/* ------------------------------------------------------------------ */
+
+typedef struct {
+  int32_t F;          /* leaf size of the factor trees (krps_sampler_create's F) */
+  int32_t lps;        /* lanes per sample of the walk (krps_sampler_set_lps) */
+  double build_ms;    /* measured: rebuild of all N trees */
+  double draw_ms;     /* measured: prepare + draw of J samples over all modes */
+  int32_t from_cache; /* 1 if read from the cache file, 0 if measured now */
+} krps_tune;
+
+/* Selects the walk shape of a sampler: lanes per sample (0 = default;
+ * 4 or 8 for R <= 8, 8 or 16 for R <= 16, 16, 32 or 64 for R <= 32, 64
+ * above).  The index and probability of every draw do not depend on it. */
+krps_status krps_sampler_set_lps(krps_sampler s, int lps);
+
+/* Bytes of workspace for krps_autotune (a sampler with the smallest leaf
+ * size tried, its draw scratch and J outputs). */
+krps_status krps_autotune_workspace_bytes(int N, const int64_t* I, int R, krps_precision p,
+                                          int64_t J, size_t* bytes);
+
+/* Times a rebuild of the N trees plus a draw of J samples (no exclusion,
+ * uniforms device float64 [J][N][2]) over the caller's factors U for leaf
+ * sizes F in {R/2, R, 2R, 4R} and every lanes-per-sample choice of R, and
+ * returns the fastest.  Results are keyed by (gfx950, precision, R, J, I_1..I_N)
+ * in the JSON-lines file cache_path (NULL: no cache): a key present there
+ * is returned without timing; a new result is appended.  The leaf size
+ * does not change any drawn index (ties go to the lower row, so the index
+ * depends only on the row order).  Synchronises the stream. */
+krps_status krps_autotune(krps_ctx ctx, int N, const int64_t* I, int R, krps_precision p,
+                          void* const* U, int64_t J, const double* uniforms, void* ws,
+                          size_t ws_bytes, const char* cache_path, krps_tune* out);
+
 /* Offsets (bytes into the solve workspace) of the last solve's pieces. */
 typedef struct {
   size_t idx;      /* int32 [J][N] sampled multi-indices */

@@ -28,7 +28,7 @@ from .definition import pinv_psd, hadamard_all
 from .sampler import KRPSampler
 
 __all__ = ["SparseTensor", "normal_equations", "sketched_solve", "fit",
-           "cp_als", "normalize_columns"]
+           "cp_als", "normalize_columns", "sketched_lstsq"]
 
 
 class SparseTensor:
@@ -114,6 +114,21 @@ def normal_equations(tensor, j, idx, rows, w2):
                           shape=(tensor.dims[j], len(first))).tocsr()
     Y = np.asarray(P @ A)
     return M, Y
+
+
+def sketched_lstsq(rows, prob, sb_rows):
+    """``argmin_X ||S A X - S B||_F`` from sampled rows ``a_d`` of ``A``,
+    their probabilities ``q_d`` and the rows ``b_d`` of ``B`` at the same
+    indices (Section 2.1: weights ``w_d = 1/sqrt(J q_d)``), by the normal
+    equations ``X = M^+ (SA)^T SB`` with the float64 eigen-pseudo-inverse."""
+    rows = np.asarray(rows, dtype=np.float64)
+    sb_rows = np.asarray(sb_rows, dtype=np.float64)
+    J = rows.shape[0]
+    w2 = 1.0 / (J * np.asarray(prob, dtype=np.float64))
+    M = (rows * w2[:, None]).T @ rows
+    Z = (rows * w2[:, None]).T @ sb_rows
+    Mp, _ = pinv_psd(M)
+    return Mp @ Z
 
 
 def normalize_columns(U):

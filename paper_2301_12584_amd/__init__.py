@@ -42,6 +42,11 @@ class DrawLayout(ctypes.Structure):
                 ("n_enodes", ctypes.c_int64), ("etree_stride", ctypes.c_int64)]
 
 
+class Tune(ctypes.Structure):
+    _fields_ = [("F", ctypes.c_int32), ("lps", ctypes.c_int32), ("build_ms", ctypes.c_double),
+                ("draw_ms", ctypes.c_double), ("from_cache", ctypes.c_int32)]
+
+
 class SolveLayout(ctypes.Structure):
     _fields_ = [(n, ctypes.c_size_t) for n in ("idx", "prob", "w", "rows", "M", "Mp", "Y", "draw")]
 
@@ -90,6 +95,16 @@ def lib():
                                          c.c_size_t, c.POINTER(P)]),
         "krps_tensor_destroy": (c.c_int, [P]),
         "krps_tensor_norm2": (c.c_int, [P, c.POINTER(c.c_double)]),
+        "krps_sampler_set_lps": (c.c_int, [P, c.c_int]),
+        "krps_autotune_workspace_bytes": (c.c_int, [c.c_int, c.POINTER(c.c_int64), c.c_int,
+                                                    c.c_int, c.c_int64, c.POINTER(c.c_size_t)]),
+        "krps_autotune": (c.c_int, [P, c.c_int, c.POINTER(c.c_int64), c.c_int, c.c_int,
+                                    c.POINTER(P), c.c_int64, P, P, c.c_size_t, c.c_char_p,
+                                    c.POINTER(Tune)]),
+        "krps_lstsq_workspace_bytes": (c.c_int, [c.c_int, c.c_int64, c.c_int64,
+                                                 c.POINTER(c.c_size_t)]),
+        "krps_sketched_lstsq": (c.c_int, [P, c.c_int, c.c_int64, P, P, c.c_int64, P, P, c.c_int,
+                                          P, c.c_size_t]),
         "krps_tensor_stored_entries": (c.c_int, [P, c.POINTER(c.c_int64)]),
         "krps_solve_workspace_bytes": (c.c_int, [P, P, c.c_int64, c.POINTER(c.c_size_t)]),
         "krps_solve_layout_query": (c.c_int, [P, P, c.c_int64, c.POINTER(SolveLayout)]),
@@ -154,7 +169,7 @@ class Sampler:
     contiguous CUDA tensors ``[I_j, R]`` (float64 for ``fp64``, float32
     otherwise).  The tensors are referenced, not copied."""
 
-    def __init__(self, ctx: Context, factors, precision="fp32", F=0):
+    def __init__(self, ctx: Context, factors, precision="fp32", F=0, lps=0):
         torch = ctx.torch
         self.ctx = ctx
         self.precision = precision
@@ -175,6 +190,8 @@ class Sampler:
                                         PRECISION[precision], _ptr(self.ws), nbytes,
                                         ctypes.byref(h)))
         self.handle = h
+        if lps:
+            check(lib().krps_sampler_set_lps(self.handle, int(lps)))
         sz = ctypes.c_size_t()
         check(lib().krps_sample_workspace_bytes(self.handle, ctypes.byref(sz)))
         self.draw_ws = torch.empty(sz.value, dtype=torch.uint8, device=ctx.device)
@@ -329,6 +346,50 @@ def sample_batched(ctx: "Context", samplers, excludes, uniforms, with_prob=True)
     """Algorithm 2 for many samplers in one batched call.  ``uniforms[p]``:
     CUDA float64 ``[J_p, N_p, 2]``.  Returns ``(idx_list, prob_list)``."""
     return Batch(ctx, samplers, excludes).sample(uniforms, with_prob)
+
+
+def autotune(ctx: "Context", factors, uniforms, precision="fp32", cache_path=None):
+    """Leaf size F and walk lanes per sample for these factors: measured
+    (rebuild + draw of J = uniforms.shape[0] samples; uniforms float64
+    ``[J, N, 2]`` on the device) or read from the JSON-lines cache.
+    Returns a dict with F, lps, build_ms, draw_ms, from_cache."""
+    torch = ctx.torch
+    N = len(factors)
+    R = int(factors[0].shape[1])
+    dims = [int(U.shape[0]) for U in factors]
+    J = int(uniforms.shape[0])
+    arr = (ctypes.c_int64 * N)(*dims)
+    nb = ctypes.c_size_t()
+    check(lib().krps_autotune_workspace_bytes(N, arr, R, PRECISION[precision], J,
+                                              ctypes.byref(nb)))
+    ws = torch.empty(nb.value, dtype=torch.uint8, device=ctx.device)
+    ptrs = (ctypes.c_void_p * N)(*[U.data_ptr() for U in factors])
+    t = Tune()
+    check(lib().krps_autotune(ctx.handle, N, arr, R, PRECISION[precision], ptrs, J,
+                              _ptr(uniforms), _ptr(ws), ws.numel(),
+                              None if cache_path is None else str(cache_path).encode(),
+                              ctypes.byref(t)))
+    return {"F": t.F, "lps": t.lps, "build_ms": t.build_ms, "draw_ms": t.draw_ms,
+            "from_cache": bool(t.from_cache)}
+
+
+def sketched_lstsq(ctx: "Context", rows, prob, sb_rows, precision=None):
+    """min_X ||S A X - S B||_F from sampled rows ``rows`` [J, R], their
+    probabilities ``prob`` [J] (float64) and the sampled rows of B
+    ``sb_rows`` [J, n]; returns X [R, n] (float64)."""
+    torch = ctx.torch
+    J, R = int(rows.shape[0]), int(rows.shape[1])
+    n = int(sb_rows.shape[1])
+    if precision is None:
+        precision = "fp64" if rows.dtype == torch.float64 else "fp32"
+    nb = ctypes.c_size_t()
+    check(lib().krps_lstsq_workspace_bytes(R, J, n, ctypes.byref(nb)))
+    ws = torch.empty(nb.value, dtype=torch.uint8, device=ctx.device)
+    X = torch.empty((R, n), dtype=torch.float64, device=ctx.device)
+    rows, prob, sb_rows = rows.contiguous(), prob.contiguous(), sb_rows.contiguous()
+    check(lib().krps_sketched_lstsq(ctx.handle, R, J, _ptr(rows), _ptr(prob), n, _ptr(sb_rows),
+                                    _ptr(X), PRECISION[precision], _ptr(ws), ws.numel()))
+    return X
 
 
 class Tensor:

@@ -89,6 +89,21 @@ namespace {
 bool valid_prec(krps_precision p) { return p == KRPS_FP64 || p == KRPS_FP32 || p == KRPS_BF16X2; }
 int elem_bytes(krps_precision p) { return p == KRPS_FP64 ? 8 : 4; }
 
+// Walk shapes compiled for each R (lanes per sample; 0 = the default).
+bool lps_supported(int R, int lps) {
+  if (lps == 0) return true;
+  if (R <= 8) return lps == 4 || lps == 8;
+  if (R <= 16) return lps == 8 || lps == 16;
+  if (R <= 32) return lps == 16 || lps == 32 || lps == 64;
+  return lps == 64;
+}
+std::vector<int> lps_choices(int R) {
+  if (R <= 8) return {4, 8};
+  if (R <= 16) return {8, 16};
+  if (R <= 32) return {16, 32, 64};
+  return {64};
+}
+
 krps_status check_dims(int N, const int64_t* I, int R) {
   if (N < 1 || N > KRPS_MAX_MODES) return fail(KRPS_EINVAL, "N must be in [1, 8]");
   if (R < 1 || R > KRPS_MAX_R) return fail(KRPS_EINVAL, "R must be in [1, 128]");
@@ -549,6 +564,13 @@ krps_status krps_sampler_refresh(krps_sampler s, int j) {
 krps_status krps_sampler_destroy(krps_sampler s) {
   if (s != nullptr && s->sweep_exec != nullptr) (void)hipGraphExecDestroy(s->sweep_exec);
   delete s;
+  return KRPS_OK;
+}
+
+krps_status krps_sampler_set_lps(krps_sampler s, int lps) {
+  if (s == nullptr) return fail(KRPS_EINVAL, "sampler is NULL");
+  if (!lps_supported(s->R, lps)) return fail(KRPS_EINVAL, "lanes per sample not available for R");
+  s->lps = lps;
   return KRPS_OK;
 }
 
@@ -1120,6 +1142,239 @@ krps_status krps_als_sweep(krps_sampler s, krps_tensor t, int64_t J, const doubl
   }
   KRPS_HIP(hipGraphLaunch(s->sweep_exec, stream));
   s->prepared_ws = nullptr;
+  return KRPS_OK;
+}
+
+namespace {
+
+struct LsPlan {
+  size_t SA, SBw, M, Mp, rank, partial, Z, scratch, scratch_bytes, total;
+};
+
+LsPlan plan_lstsq(int R, int64_t J, int64_t n) {
+  LsPlan pl;
+  size_t off = 0;
+  pl.SA = off;
+  off += align_up((size_t)J * R * 8);
+  pl.SBw = off;
+  off += align_up((size_t)J * n * 8);
+  pl.M = off;
+  off += align_up((size_t)R * R * 8);
+  pl.Mp = off;
+  off += align_up((size_t)R * R * 8);
+  pl.rank = off;
+  off += 256;
+  pl.partial = off;
+  off += align_up(lstsq_partial_bytes(R, n));
+  pl.Z = off;
+  off += align_up((size_t)R * n * 8);
+  TreeShape tm;
+  tm.init(J, R);
+  pl.scratch = off;
+  pl.scratch_bytes = tree_build_scratch_bytes(tm.L, R);
+  off += align_up(pl.scratch_bytes);
+  pl.total = off;
+  return pl;
+}
+
+}  // namespace
+
+krps_status krps_lstsq_workspace_bytes(int R, int64_t J, int64_t n, size_t* bytes) {
+  if (R < 1 || R > KRPS_MAX_R) return fail(KRPS_EINVAL, "R outside [1, 128]");
+  if (J < 1 || n < 1) return fail(KRPS_EINVAL, "J and n must be >= 1");
+  if (bytes == nullptr) return fail(KRPS_EINVAL, "bytes is NULL");
+  *bytes = plan_lstsq(R, J, n).total;
+  return KRPS_OK;
+}
+
+krps_status krps_sketched_lstsq(krps_ctx ctx, int R, int64_t J, const void* rows,
+                                const double* prob, int64_t n, const void* SB_rows, double* X,
+                                krps_precision p, void* ws, size_t ws_bytes) {
+  if (ctx == nullptr) return fail(KRPS_EINVAL, "ctx is NULL");
+  if (!valid_prec(p)) return fail(KRPS_EINVAL, "unknown precision");
+  if (R < 1 || R > KRPS_MAX_R) return fail(KRPS_EINVAL, "R outside [1, 128]");
+  if (J < 1 || n < 1) return fail(KRPS_EINVAL, "J and n must be >= 1");
+  if (rows == nullptr || prob == nullptr || SB_rows == nullptr || X == nullptr || ws == nullptr)
+    return fail(KRPS_EINVAL, "rows/prob/SB_rows/X/workspace is NULL");
+  const LsPlan pl = plan_lstsq(R, J, n);
+  if (ws_bytes < pl.total) return fail(KRPS_EWORKSPACE, "least-squares workspace too small");
+  KRPS_HIP(hipSetDevice(ctx->device));
+  hipStream_t st = ctx->stream;
+  char* w = (char*)ws;
+  double* SA = (double*)(w + pl.SA);
+  double* SBw = (double*)(w + pl.SBw);
+  hipError_t e = launch_ls_scale(st, p, rows, SB_rows, prob, J, R, n, SA, SBw);
+  if (e != hipSuccess) return hip_fail(e, "row scaling");
+  TreeShape tm;
+  tm.init(J, R);
+  e = launch_tree_build(st, KRPS_FP64, SA, J, R, tm, nullptr, (double*)(w + pl.M),
+                        (double*)(w + pl.scratch), pl.scratch_bytes);
+  if (e != hipSuccess) return hip_fail(e, "Gram of sampled rows");
+  e = launch_pinv(st, R, (double*)(w + pl.M), (double*)(w + pl.Mp), (int32_t*)(w + pl.rank));
+  if (e != hipSuccess) return hip_fail(e, "pseudo-inverse");
+  e = launch_ls_solve(st, SA, SBw, J, R, n, (const double*)(w + pl.Mp), (double*)(w + pl.partial),
+                      (double*)(w + pl.Z), X);
+  if (e != hipSuccess) return hip_fail(e, "solve");
+  return KRPS_OK;
+}
+
+namespace {
+
+struct TunePlan {
+  size_t sampler, draw, idx, prob, total;
+  int Fmin;
+};
+
+TunePlan plan_tune(int N, const int64_t* I, int R, krps_precision p, int64_t J) {
+  TunePlan pl;
+  pl.Fmin = R / 2 > 0 ? R / 2 : 1;
+  size_t off = 0;
+  pl.sampler = off;
+  off += align_up(plan_sampler(N, I, R, pl.Fmin, p).total);
+  krps_sampler_s tmp;
+  tmp.N = N;
+  tmp.R = R;
+  tmp.elem = elem_bytes(p);
+  plan_draw(&tmp);
+  pl.draw = off;
+  off += align_up(tmp.draw_bytes);
+  pl.idx = off;
+  off += align_up((size_t)J * N * 4);
+  pl.prob = off;
+  off += align_up((size_t)J * 8);
+  pl.total = off;
+  return pl;
+}
+
+std::string tune_key(int N, const int64_t* I, int R, krps_precision p, int64_t J) {
+  std::string k = "gfx950 p=" + std::to_string((int)p) + " R=" + std::to_string(R) +
+                  " J=" + std::to_string(J) + " I=";
+  for (int j = 0; j < N; ++j) k += (j ? "," : "") + std::to_string(I[j]);
+  return k;
+}
+
+// One line per entry: {"key": "...", "F": f, "lps": l, "build_ms": b, "draw_ms": d}
+bool tune_lookup(const char* path, const std::string& key, krps_tune* out) {
+  if (path == nullptr) return false;
+  FILE* f = fopen(path, "r");
+  if (f == nullptr) return false;
+  char line[1024];
+  bool found = false;
+  const std::string pat = "\"key\": \"" + key + "\"";
+  while (fgets(line, sizeof(line), f) != nullptr) {
+    const char* at = strstr(line, pat.c_str());
+    if (at == nullptr) continue;
+    const char* q = strstr(line, "\"F\": ");
+    const char* l = strstr(line, "\"lps\": ");
+    const char* b = strstr(line, "\"build_ms\": ");
+    const char* d = strstr(line, "\"draw_ms\": ");
+    if (q && l && b && d) {
+      out->F = atoi(q + 5);
+      out->lps = atoi(l + 7);
+      out->build_ms = atof(b + 12);
+      out->draw_ms = atof(d + 11);
+      out->from_cache = 1;
+      found = true;  // the last entry for a key wins
+    }
+  }
+  fclose(f);
+  return found;
+}
+
+void tune_store(const char* path, const std::string& key, const krps_tune& t) {
+  if (path == nullptr) return;
+  FILE* f = fopen(path, "a");
+  if (f == nullptr) return;
+  fprintf(f, "{\"key\": \"%s\", \"F\": %d, \"lps\": %d, \"build_ms\": %.6f, \"draw_ms\": %.6f}\n",
+          key.c_str(), t.F, t.lps, t.build_ms, t.draw_ms);
+  fclose(f);
+}
+
+}  // namespace
+
+krps_status krps_autotune_workspace_bytes(int N, const int64_t* I, int R, krps_precision p,
+                                          int64_t J, size_t* bytes) {
+  krps_status st = check_dims(N, I, R);
+  if (st != KRPS_OK) return st;
+  if (!valid_prec(p)) return fail(KRPS_EINVAL, "unknown precision");
+  if (J < 1) return fail(KRPS_EINVAL, "J must be >= 1");
+  if (bytes == nullptr) return fail(KRPS_EINVAL, "bytes is NULL");
+  *bytes = plan_tune(N, I, R, p, J).total;
+  return KRPS_OK;
+}
+
+krps_status krps_autotune(krps_ctx ctx, int N, const int64_t* I, int R, krps_precision p,
+                          void* const* U, int64_t J, const double* uniforms, void* ws,
+                          size_t ws_bytes, const char* cache_path, krps_tune* out) {
+  if (ctx == nullptr || out == nullptr) return fail(KRPS_EINVAL, "ctx/out is NULL");
+  krps_status st = check_dims(N, I, R);
+  if (st != KRPS_OK) return st;
+  if (!valid_prec(p)) return fail(KRPS_EINVAL, "unknown precision");
+  if (J < 1 || uniforms == nullptr || U == nullptr || ws == nullptr)
+    return fail(KRPS_EINVAL, "J/uniforms/U/workspace invalid");
+  const std::string key = tune_key(N, I, R, p, J);
+  memset(out, 0, sizeof(*out));
+  if (tune_lookup(cache_path, key, out)) return KRPS_OK;
+  const TunePlan pl = plan_tune(N, I, R, p, J);
+  if (ws_bytes < pl.total) return fail(KRPS_EWORKSPACE, "autotune workspace too small");
+  char* w = (char*)ws;
+  KRPS_HIP(hipSetDevice(ctx->device));
+  hipEvent_t ev[3];
+  for (int i = 0; i < 3; ++i) KRPS_HIP(hipEventCreate(&ev[i]));
+  std::vector<int> Fs;
+  for (int f : {pl.Fmin, R, 2 * R, 4 * R})
+    if (std::find(Fs.begin(), Fs.end(), f) == Fs.end()) Fs.push_back(f);
+  double best = 1e300;
+  krps_status result = KRPS_OK;
+  for (int F : Fs) {
+    krps_sampler s = nullptr;
+    result = krps_sampler_create(ctx, N, I, R, F, U, p, w + pl.sampler, pl.draw - pl.sampler, &s);
+    if (result != KRPS_OK) break;
+    for (int lps : lps_choices(R)) {
+      s->lps = lps;
+      float bmin = 1e30f, dmin = 1e30f;
+      for (int rep = 0; rep < 4 && result == KRPS_OK; ++rep) {
+        hipError_t e = hipEventRecord(ev[0], ctx->stream);
+        for (int j = 0; j < N && e == hipSuccess; ++j)
+          if (build_tree(s, j) != KRPS_OK) e = hipErrorUnknown;
+        if (e == hipSuccess) e = hipEventRecord(ev[1], ctx->stream);
+        if (e != hipSuccess) {
+          result = hip_fail(e, "autotune build");
+          break;
+        }
+        result = krps_sample(s, -1, J, uniforms, (int32_t*)(w + pl.idx), (double*)(w + pl.prob),
+                             nullptr, w + pl.draw, pl.idx - pl.draw, 0);
+        if (result != KRPS_OK) break;
+        e = hipEventRecord(ev[2], ctx->stream);
+        if (e == hipSuccess) e = hipEventSynchronize(ev[2]);
+        float b = 0, d = 0;
+        if (e == hipSuccess) e = hipEventElapsedTime(&b, ev[0], ev[1]);
+        if (e == hipSuccess) e = hipEventElapsedTime(&d, ev[1], ev[2]);
+        if (e != hipSuccess) {
+          result = hip_fail(e, "autotune timing");
+          break;
+        }
+        if (rep > 0) {  // the first repetition warms up
+          bmin = b < bmin ? b : bmin;
+          dmin = d < dmin ? d : dmin;
+        }
+      }
+      if (result != KRPS_OK) break;
+      if (bmin + dmin < best) {
+        best = bmin + dmin;
+        out->F = F;
+        out->lps = lps;
+        out->build_ms = bmin;
+        out->draw_ms = dmin;
+      }
+    }
+    krps_sampler_destroy(s);
+    if (result != KRPS_OK) break;
+  }
+  for (int i = 0; i < 3; ++i) (void)hipEventDestroy(ev[i]);
+  if (result != KRPS_OK) return result;
+  out->from_cache = 0;
+  tune_store(cache_path, key, *out);
   return KRPS_OK;
 }
 

@@ -195,6 +195,13 @@ hipError_t launch_lookup(hipStream_t st, const FiberArgs& a);
 hipError_t launch_spmm(hipStream_t st, krps_precision p, const FiberArgs& a, const void* rows,
                        void* Y);
 size_t solve_partial_bytes(int R);
+// Generic sketched least squares (scaled rows, Z = (SA)^T S B, X = M^+ Z).
+size_t lstsq_partial_bytes(int R, int64_t n);
+hipError_t launch_ls_scale(hipStream_t st, krps_precision p, const void* rows, const void* sb,
+                           const double* prob, int64_t J, int R, int64_t n, double* SA,
+                           double* SBw);
+hipError_t launch_ls_solve(hipStream_t st, const double* SA, const double* SBw, int64_t J, int R,
+                           int64_t n, const double* Mp, double* partial, double* Z, double* X);
 hipError_t launch_fill(hipStream_t st, krps_precision p, void* ptr, int64_t n);
 hipError_t launch_fill_f64(hipStream_t st, double* ptr, int64_t n);
 hipError_t launch_solve_gemm(hipStream_t st, krps_precision p, const void* Y, const double* Mp,

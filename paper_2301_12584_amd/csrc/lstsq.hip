@@ -699,3 +699,103 @@ hipError_t launch_fit(hipStream_t st, krps_precision p, const FitArgs& a, double
 }
 
 }  // namespace krps
+
+// ------------------------------------------------- generic sketched solve
+//
+// min_X || S A X - S B ||_F from the sampled rows a_d of A, their
+// probabilities q_d and the sampled rows b_d of B (Section 2.1): with
+// w_d = 1/sqrt(J q_d), X = M^+ Z, M = sum_d w_d^2 a_d a_d^T (R x R) and
+// Z = sum_d w_d^2 a_d b_d^T (R x n).
+
+namespace krps {
+
+namespace {
+
+constexpr int LS_CHUNKS = 64;  // J chunks of the Z partial sums
+
+// SA[d] = w_d a_d and SBw[d] = w_d b_d in float64.
+template <typename T>
+__global__ void ls_scale_kernel(const T* __restrict__ rows, const T* __restrict__ sb,
+                                const double* __restrict__ prob, int64_t J, int R, int64_t n,
+                                double* __restrict__ SA, double* __restrict__ SBw) {
+  const int64_t w = R + n;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < J * w;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t d = i / w, c = i % w;
+    const double wd = 1.0 / sqrt((double)J * prob[d]);
+    if (c < R)
+      SA[d * R + c] = wd * (double)rows[d * R + c];
+    else
+      SBw[d * n + (c - R)] = wd * (double)sb[d * n + (c - R)];
+  }
+}
+
+// partial[chunk][r][c] = sum over the chunk's samples of SA[d][r] SBw[d][c].
+__global__ void ls_atb_kernel(const double* __restrict__ SA, const double* __restrict__ SBw,
+                              int64_t J, int R, int64_t n, double* __restrict__ partial) {
+  const int64_t per = (J + LS_CHUNKS - 1) / LS_CHUNKS;
+  const int chunk = blockIdx.y;
+  const int64_t d0 = chunk * per, d1 = d0 + per < J ? d0 + per : J;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < (int64_t)R * n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t r = i / n, c = i % n;
+    double acc = 0;
+    for (int64_t d = d0; d < d1; ++d) acc += SA[d * R + r] * SBw[d * n + c];
+    partial[(int64_t)chunk * R * n + i] = acc;
+  }
+}
+
+// Z = the sum of the chunk partials, in chunk order.
+__global__ void ls_z_kernel(const double* __restrict__ partial, int R, int64_t n,
+                            double* __restrict__ Z) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < (int64_t)R * n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    double z = 0;
+    for (int ch = 0; ch < LS_CHUNKS; ++ch) z += partial[(int64_t)ch * R * n + i];
+    Z[i] = z;
+  }
+}
+
+// X = M^+ Z.
+__global__ void ls_mul_kernel(const double* __restrict__ Mp, const double* __restrict__ Z, int R,
+                              int64_t n, double* __restrict__ X) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < (int64_t)R * n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t r = i / n, c = i % n;
+    double x = 0;
+    for (int k = 0; k < R; ++k) x += Mp[(int64_t)r * R + k] * Z[(int64_t)k * n + c];
+    X[i] = x;
+  }
+}
+
+}  // namespace
+
+size_t lstsq_partial_bytes(int R, int64_t n) { return (size_t)LS_CHUNKS * R * n * 8; }
+
+hipError_t launch_ls_scale(hipStream_t st, krps_precision p, const void* rows, const void* sb,
+                           const double* prob, int64_t J, int R, int64_t n, double* SA,
+                           double* SBw) {
+  int64_t blocks = (J * (R + n) + 255) / 256;
+  if (blocks > 8192) blocks = 8192;
+  if (blocks < 1) blocks = 1;
+  if (p == KRPS_FP64)
+    hipLaunchKernelGGL(ls_scale_kernel<double>, dim3((unsigned)blocks), dim3(256), 0, st,
+                       (const double*)rows, (const double*)sb, prob, J, R, n, SA, SBw);
+  else
+    hipLaunchKernelGGL(ls_scale_kernel<float>, dim3((unsigned)blocks), dim3(256), 0, st,
+                       (const float*)rows, (const float*)sb, prob, J, R, n, SA, SBw);
+  return hipGetLastError();
+}
+
+hipError_t launch_ls_solve(hipStream_t st, const double* SA, const double* SBw, int64_t J, int R,
+                           int64_t n, const double* Mp, double* partial, double* Z, double* X) {
+  int64_t bx = ((int64_t)R * n + 255) / 256;
+  if (bx > 1024) bx = 1024;
+  hipLaunchKernelGGL(ls_atb_kernel, dim3((unsigned)bx, LS_CHUNKS), dim3(256), 0, st, SA, SBw, J, R,
+                     n, partial);
+  hipLaunchKernelGGL(ls_z_kernel, dim3((unsigned)bx), dim3(256), 0, st, partial, R, n, Z);
+  hipLaunchKernelGGL(ls_mul_kernel, dim3((unsigned)bx), dim3(256), 0, st, Mp, Z, R, n, X);
+  return hipGetLastError();
+}
+
+}  // namespace krps

@@ -264,3 +264,28 @@ def test_graph_replays_equal_eager_sweeps(env):
         assert torch.allclose(A.sigma, eager_sig, rtol=1e-10)
         # eager work between replays
         _ = (S.factors[0] * 2).sum().item()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_generic_sketched_lstsq_matches_oracle(env, prec):
+    """krps_sketched_lstsq on leverage-sampled rows of a dense A (drawn by
+    the sampler over A itself, N = 1) and the rows of B at those indices."""
+    krps, torch, ctx = env
+    rng = np.random.default_rng(11)
+    I, R, n, J = 3000, 24, 7, 5000
+    A = synth.gaussian_factors((I,), R, seed=12, heavy_rows_frac=0.02)[0]
+    B = rng.standard_normal((I, n)).astype(np.float32)
+    dt = torch.float64 if prec == "fp64" else torch.float32
+    Ad = torch.from_numpy(A).to(ctx.device).to(dt).contiguous()
+    S = krps.Sampler(ctx, [Ad], precision=prec)
+    u = torch.from_numpy(synth.uniforms(J, 1, 13)).to(ctx.device)
+    idx, prob, _ = S.sample(-1, u)
+    rows = Ad[idx[:, 0].long()]
+    sb = torch.from_numpy(B).to(ctx.device).to(dt)[idx[:, 0].long()]
+    X = krps.sketched_lstsq(ctx, rows, prob, sb).cpu().numpy()
+    ref = ocp.sketched_lstsq(rows.cpu().numpy(), prob.cpu().numpy(), sb.cpu().numpy())
+    np.testing.assert_allclose(X, ref, rtol=1e-9, atol=1e-10 * np.abs(ref).max())
+    # and close to the exact solution (a leverage sketch with J >> R)
+    exact = np.linalg.lstsq(A.astype(np.float64), B.astype(np.float64), rcond=None)[0]
+    res = np.linalg.norm(A @ X - B) / np.linalg.norm(A @ exact - B)
+    assert res < 1.05, res

@@ -226,3 +226,26 @@ def test_split_precision_reports_mismatch_rate(env):
           f"prob rel err max {rel.max():.2e}", flush=True)
     assert same.mean() > 0.9
     assert rel.max() <= TOL_PROB["bf16x2"]
+
+
+def test_autotune_measures_then_reads_the_cache(tmp_path):
+    import torch
+    import paper_2301_12584_amd as krps
+    ctx = krps.Context(0)
+    Us = synth.gaussian_factors((20000, 15000, 9000), 16, seed=77, heavy_rows_frac=0.01)
+    Ud = [torch.from_numpy(U).to(ctx.device).contiguous() for U in Us]
+    u = torch.from_numpy(synth.uniforms(4096, 3, 78)).to(ctx.device)
+    cache = tmp_path / "tune.jsonl"
+    t1 = krps.autotune(ctx, Ud, u, "fp32", cache_path=cache)
+    assert not t1["from_cache"] and t1["F"] in (8, 16, 32, 64) and t1["lps"] in (8, 16)
+    t2 = krps.autotune(ctx, Ud, u, "fp32", cache_path=cache)
+    assert t2["from_cache"] and (t2["F"], t2["lps"]) == (t1["F"], t1["lps"])
+    # the tuned shape draws the same indices as the default one
+    S0 = krps.Sampler(ctx, Ud, precision="fp32")
+    S1 = krps.Sampler(ctx, Ud, precision="fp32", F=t1["F"], lps=t1["lps"])
+    i0, p0, _ = S0.sample(-1, u)
+    i1, p1, _ = S1.sample(-1, u)
+    torch.cuda.synchronize()
+    same = (i0 == i1).all(dim=1).cpu().numpy()
+    assert same.mean() >= 0.999, same.mean()
+    np.testing.assert_allclose(p1.cpu().numpy()[same], p0.cpu().numpy()[same], rtol=1e-5)

@@ -131,3 +131,31 @@ def test_leverage_sketch_meets_the_residual_guarantee():
         x = np.linalg.lstsq(A[r] * w[:, None], b[r] * w, rcond=None)[0]
         eps.append(np.linalg.norm(A @ x - b) / r_opt - 1)
     assert np.mean(eps) < 0.05, eps
+
+
+def test_sketched_lstsq_full_enumeration_is_exact_least_squares():
+    """Every row of A once with q = 1/I (so w = 1): the sketched normal
+    equations are the exact ones, and X equals the textbook least-squares
+    solution; listing every row twice with q = 1/(2I) changes nothing."""
+    rng = np.random.default_rng(3)
+    A = rng.standard_normal((60, 5))
+    B = rng.standard_normal((60, 3))
+    X = cp.sketched_lstsq(A, np.full(60, 1 / 60), B)
+    ref = np.linalg.lstsq(A, B, rcond=None)[0]
+    np.testing.assert_allclose(X, ref, rtol=1e-10, atol=1e-12)
+    X2 = cp.sketched_lstsq(np.vstack([A, A]), np.full(120, 1 / 120), np.vstack([B, B]))
+    np.testing.assert_allclose(X2, ref, rtol=1e-10, atol=1e-12)
+
+
+def test_sketched_lstsq_weights_follow_the_probabilities():
+    """Halving one sample's probability doubles its weight w^2: the result
+    equals the exact weighted least-squares solution with those weights."""
+    rng = np.random.default_rng(4)
+    A = rng.standard_normal((40, 4))
+    B = rng.standard_normal((40, 2))
+    q = rng.uniform(0.5, 1.5, 40)
+    q /= q.sum()
+    X = cp.sketched_lstsq(A, q, B)
+    w = np.sqrt(1.0 / (40 * q))
+    ref = np.linalg.lstsq(A * w[:, None], B * w[:, None], rcond=None)[0]
+    np.testing.assert_allclose(X, ref, rtol=1e-10, atol=1e-12)
