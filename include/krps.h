@@ -205,7 +205,9 @@ krps_status krps_row_prob(krps_sampler s, int exclude, int64_t M, const int32_t*
  * other modes' indices (increasing mode order, then i_j), i.e. grouped into
  * the mode-j fibers that rows of mat(T, j)^T select, with entries of equal
  * coordinates merged into one float64 value (their sum), plus an offset
- * table over the leading other mode; and the sort's scratch. */
+ * table over the leading other mode; per mode the 32 rows with the most
+ * entries (the SpMM accumulates them per workgroup); and the sort's
+ * scratch. */
 krps_status krps_tensor_workspace_bytes(int N, const int64_t* dims, int64_t nnz, size_t* bytes);
 
 /* Builds the per-mode fiber index of a COO tensor on the device.

@@ -52,7 +52,7 @@ __device__ __forceinline__ double team_sum(double v) {
 }
 
 // Team of lanes per column pair for a given R (RPL rows per lane at most).
-constexpr int jacobi_team(int R) { return R <= 32 ? 4 : (R <= 64 ? 8 : 16); }
+constexpr int jacobi_team(int R) { return R <= 32 ? 4 : 16; }
 constexpr int JACOBI_RPL = 8;
 
 // One-sided Jacobi on the columns of A (column c at A + c*RS, RS = R + 1 so

@@ -81,6 +81,9 @@ struct krps_tensor_s {
   std::vector<double*> vals;   // per mode: [nu], duplicates summed
   std::vector<int64_t*> off;   // per mode: [dims[lead] + 1]
   std::vector<int> lead;
+  std::vector<int8_t*> hot_slot;   // per mode: [dims[j]]
+  std::vector<int32_t*> hot_rows;  // per mode: [nhot]
+  int nhot = 0;
   double norm2 = 0;
 };
 
@@ -255,8 +258,10 @@ void fill_descent_args(krps_sampler s, int exclude, void* ws, DescentArgs& a) {
 // ------------------------------------------------------------ tensor plan
 
 struct TensorPlan {
-  std::vector<size_t> cols_off, vals_off, off_off;
+  std::vector<size_t> cols_off, vals_off, off_off, hslot_off, hrows_off;
   std::vector<int> lead;
+  size_t hc0 = 0, hc1 = 0, hi0 = 0, hi1 = 0;
+  int nhot = 0;
   size_t k0 = 0, k1 = 0, p0 = 0, p1 = 0, temp = 0, temp_bytes = 0, acc = 0, total = 0;
 };
 
@@ -281,8 +286,31 @@ TensorPlan plan_tensor(int N, const int64_t* dims, int64_t nnz) {
   off += align_up((size_t)nnz * 4);
   pl.p1 = off;
   off += align_up((size_t)nnz * 4);
-  pl.temp = off;
+  // hot rows: per mode a slot byte per row and the rows; temporaries sized
+  // for the largest mode
+  int64_t dmax = 1;
+  for (int j = 0; j < N; ++j) {
+    dmax = dims[j] > dmax ? dims[j] : dmax;
+    pl.hslot_off.push_back(off);
+    off += align_up((size_t)dims[j]);
+    pl.hrows_off.push_back(off);
+    off += align_up((size_t)HOT_ROWS * 4);
+  }
+  pl.nhot = HOT_ROWS;
+  pl.hc0 = off;
+  off += align_up((size_t)dmax * 4);
+  pl.hc1 = off;
+  off += align_up((size_t)dmax * 4);
+  pl.hi0 = off;
+  off += align_up((size_t)dmax * 4);
+  pl.hi1 = off;
+  off += align_up((size_t)dmax * 4);
   pl.temp_bytes = sort_temp_bytes(nnz);
+  {
+    const size_t hb = hot_temp_bytes(dmax);
+    if (hb > pl.temp_bytes) pl.temp_bytes = hb;
+  }
+  pl.temp = off;
   off += align_up(pl.temp_bytes);
   pl.acc = off;
   off += 256;
@@ -295,7 +323,7 @@ TensorPlan plan_tensor(int N, const int64_t* dims, int64_t nnz) {
 struct SolvePlan {
   krps_solve_layout lay;
   size_t lo, hi, cnt, start, rank, partial, gscratch, gscratch_bytes, fitp, fitout, sig;
-  size_t coef, slot, hkey, hW, hrep;
+  size_t coef, slot, hkey, hW, hrep, rflag, rpos, rep, rstart, bsum;
   int64_t H;
   int hbits;
   size_t total;
@@ -343,6 +371,16 @@ SolvePlan plan_solve(krps_sampler s, int64_t J) {
   off += align_up((size_t)pl.H * 8);
   pl.hrep = off;
   off += align_up((size_t)pl.H * 4);
+  pl.rflag = off;
+  off += align_up((size_t)J * 8);
+  pl.rpos = off;
+  off += align_up((size_t)(J + 1) * 8);
+  pl.rep = off;
+  off += align_up((size_t)J * 4);
+  pl.rstart = off;
+  off += align_up((size_t)(J + 1) * 8);
+  pl.bsum = off;
+  off += align_up((size_t)((J + 1023) / 1024 + 2) * 8);
   l.M = off;
   off += align_up((size_t)R * R * 8);
   l.Mp = off;
@@ -434,6 +472,14 @@ krps_status enqueue_solve(krps_sampler s, krps_tensor t, int j, int64_t J, const
   fa.hrep = (int32_t*)(w + pl.hrep);
   fa.H = pl.H;
   fa.hbits = pl.hbits;
+  fa.rflag = (int64_t*)(w + pl.rflag);
+  fa.rpos = (int64_t*)(w + pl.rpos);
+  fa.rep = (int32_t*)(w + pl.rep);
+  fa.rstart = (int64_t*)(w + pl.rstart);
+  fa.bsum = (int64_t*)(w + pl.bsum);
+  fa.hot_slot = t->hot_slot[j];
+  fa.hot_rows = t->hot_rows[j];
+  fa.nhot = (int)std::min<int64_t>(t->nhot, t->dims[j]);
   e = launch_lookup(st, fa);
   if (e != hipSuccess) return hip_fail(e, "fiber lookup");
   e = launch_spmm(st, split ? KRPS_BF16X2 : KRPS_FP64, fa, w + l.rows, w + l.Y);
@@ -1003,6 +1049,22 @@ krps_status krps_tensor_create(krps_ctx ctx, int N, const int64_t* dims, int64_t
     if (e != hipSuccess) {
       delete t;
       return hip_fail(e, "fiber index build");
+    }
+  }
+  // hot rows of each mode: the i_j column of mode j's merged copy
+  const int nhot = (int)std::min<int64_t>(pl.nhot, 1 << 20);
+  t->nhot = nhot;
+  for (int j = 0; j < N; ++j) {
+    t->hot_slot.push_back((int8_t*)(w + pl.hslot_off[j]));
+    t->hot_rows.push_back((int32_t*)(w + pl.hrows_off[j]));
+    const int nh = (int)std::min<int64_t>(nhot, dims[j]);
+    hipError_t e = build_hot_rows(s, t->cols[j] + (int64_t)j * t->nu, t->nu, dims[j], nh,
+                                  (uint32_t*)(w + pl.hc0), (uint32_t*)(w + pl.hc1),
+                                  (uint32_t*)(w + pl.hi0), (uint32_t*)(w + pl.hi1), w + pl.temp,
+                                  pl.temp_bytes, t->hot_rows[j], t->hot_slot[j]);
+    if (e != hipSuccess) {
+      delete t;
+      return hip_fail(e, "hot rows");
     }
   }
   double* acc = (double*)(w + pl.acc);

@@ -144,7 +144,19 @@ struct FiberArgs {
   int32_t* hrep;              // [H] smallest sample index of the fiber
   int64_t H;                  // power of two >= 2 J
   int hbits;                  // log2 H
+  int64_t* rflag;             // [J] 1 if the sample expands its fiber
+  int64_t* rpos;              // [J + 1] exclusive prefix of rflag (rpos[J] = count)
+  int32_t* rep;               // [J] expanding samples in sample order
+  int64_t* rstart;            // [J + 1] first work item of each of them, then the total
+  int64_t* bsum;              // [ceil(J / 1024) + 1] scan tile totals
+  const int8_t* hot_slot;     // [dims[j]] slot of a hot row of mode j, -1 otherwise
+  const int32_t* hot_rows;    // [nhot] the hot rows
+  int nhot;
 };
+
+// Rows of a mode with the most stored entries (kept per workgroup in LDS by
+// the SpMM).
+constexpr int HOT_ROWS = 32;
 
 struct FitArgs {
   int N, R;
@@ -191,6 +203,10 @@ hipError_t build_fiber_index(hipStream_t st, int N, const int64_t* dims, int64_t
                              double* vals, int64_t* off, uint32_t* k0, uint32_t* k1, uint32_t* p0,
                              uint32_t* p1, void* temp, size_t temp_bytes, int64_t* nu);
 hipError_t launch_norm2(hipStream_t st, const double* vals, int64_t n, double* out);
+size_t hot_temp_bytes(int64_t dim);
+hipError_t build_hot_rows(hipStream_t st, const int32_t* col, int64_t n, int64_t dim, int nhot,
+                          uint32_t* c0, uint32_t* c1, uint32_t* i0, uint32_t* i1, void* temp,
+                          size_t temp_bytes, int32_t* rows, int8_t* slot);
 hipError_t launch_lookup(hipStream_t st, const FiberArgs& a);
 hipError_t launch_spmm(hipStream_t st, krps_precision p, const FiberArgs& a, const void* rows,
                        void* Y);

@@ -39,7 +39,7 @@ namespace krps {
 
 namespace {
 
-constexpr int CH = 64;  // fiber entries per SpMM work item
+constexpr int CH = 64;  // fiber entries per SpMM work item (one per lane)
 
 __global__ void iota_kernel(uint32_t* __restrict__ p, int64_t n) {
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
@@ -206,6 +206,65 @@ hipError_t launch_norm2(hipStream_t st, const double* vals, int64_t n, double* o
   return hipGetLastError();
 }
 
+// ---------------------------------------------------------------- hot rows
+//
+// The HOT_ROWS rows of each mode that hold the most stored entries: the
+// SpMM accumulates their updates in LDS per workgroup and adds them to Y
+// once per workgroup, so the most popular rows of a power-law mode do not
+// serialise the float64 atomics on a few addresses.
+
+namespace {
+
+__global__ void hot_count_kernel(const int32_t* __restrict__ col, int64_t n,
+                                 uint32_t* __restrict__ count) {
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n;
+       e += (int64_t)gridDim.x * blockDim.x)
+    atomicAdd(&count[col[e]], 1u);
+}
+
+__global__ void hot_clear_kernel(uint32_t* __restrict__ count, uint32_t* __restrict__ index,
+                                 int8_t* __restrict__ slot, int64_t dim) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < dim;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    count[i] = 0;
+    index[i] = (uint32_t)i;
+    slot[i] = -1;
+  }
+}
+
+__global__ void hot_pick_kernel(const uint32_t* __restrict__ sorted_index, int nhot,
+                                int32_t* __restrict__ rows, int8_t* __restrict__ slot) {
+  const int s = threadIdx.x;
+  if (s < nhot) {
+    const uint32_t i = sorted_index[s];
+    rows[s] = (int32_t)i;
+    slot[i] = (int8_t)s;
+  }
+}
+
+}  // namespace
+
+size_t hot_temp_bytes(int64_t dim) {
+  size_t bytes = 0;
+  (void)rocprim::radix_sort_pairs_desc(nullptr, bytes, (uint32_t*)nullptr, (uint32_t*)nullptr,
+                                       (uint32_t*)nullptr, (uint32_t*)nullptr, (uint32_t)dim, 0,
+                                       32);
+  return bytes;
+}
+
+hipError_t build_hot_rows(hipStream_t st, const int32_t* col, int64_t n, int64_t dim, int nhot,
+                          uint32_t* c0, uint32_t* c1, uint32_t* i0, uint32_t* i1, void* temp,
+                          size_t temp_bytes, int32_t* rows, int8_t* slot) {
+  hipLaunchKernelGGL(hot_clear_kernel, dim3(1024), dim3(256), 0, st, c0, i0, slot, dim);
+  hipLaunchKernelGGL(hot_count_kernel, dim3(4096), dim3(256), 0, st, col, n, c0);
+  size_t tb = temp_bytes;
+  hipError_t e = rocprim::radix_sort_pairs_desc(temp, tb, c0, c1, i0, i1, (uint32_t)dim, 0, 32,
+                                                st);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(hot_pick_kernel, dim3(1), dim3(64), 0, st, i1, nhot, rows, slot);
+  return hipGetLastError();
+}
+
 // ------------------------------------------------------------------ lookup
 
 namespace {
@@ -336,18 +395,69 @@ __global__ void merge_finish_kernel(FiberArgs a) {
     }
     a.cnt[d] = c;
     a.coef[d] = coef;
+    a.rflag[d] = c > 0 ? 1 : 0;
   }
 }
 
-// Exclusive scan of cnt[0..J) into start[0..J], one block.
-__global__ __launch_bounds__(1024) void scan_kernel(const int64_t* __restrict__ cnt,
-                                                    int64_t* __restrict__ start, int64_t J) {
+// The samples that expand a fiber, in sample order: rep[k] and the first
+// work item rstart[k] of the k-th of them (rstart[nrep] = all items).
+__global__ void compact_kernel(FiberArgs a) {
+  for (int64_t d = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; d <= a.J;
+       d += (int64_t)gridDim.x * blockDim.x) {
+    if (d == a.J) {
+      a.rstart[a.rpos[a.J]] = a.start[a.J];
+    } else if (a.cnt[d] > 0) {
+      const int64_t k = a.rpos[d];
+      a.rep[k] = (int32_t)d;
+      a.rstart[k] = a.start[d];
+    }
+  }
+}
+
+// Exclusive scan of cnt[0..J) into start[0..J] (start[J] = the total) in
+// three launches: tiles of 1024 (wave scans, then the 16 wave totals),
+// the tile totals, and the tile offsets added back.
+constexpr int SCAN_TILE = 1024;
+
+__device__ __forceinline__ int64_t wave_incl_scan_i64(int64_t x, int lane) {
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const int64_t y = __shfl_up(x, o, 64);
+    if (lane >= o) x += y;
+  }
+  return x;
+}
+
+__global__ __launch_bounds__(SCAN_TILE) void scan_tiles_kernel(const int64_t* __restrict__ cnt,
+                                                               int64_t* __restrict__ start,
+                                                               int64_t* __restrict__ bsum,
+                                                               int64_t J) {
+  __shared__ int64_t wsum[SCAN_TILE / 64];
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  const int64_t i = (int64_t)blockIdx.x * SCAN_TILE + t;
+  const int64_t v = i < J ? cnt[i] : 0;
+  int64_t x = wave_incl_scan_i64(v, lane);
+  if (lane == 63) wsum[wave] = x;
+  __syncthreads();
+  if (wave == 0) {
+    const int64_t w = lane < SCAN_TILE / 64 ? wsum[lane] : 0;
+    const int64_t wi = wave_incl_scan_i64(w, lane);
+    if (lane < SCAN_TILE / 64) wsum[lane] = wi - w;  // exclusive
+    if (lane == SCAN_TILE / 64 - 1) bsum[blockIdx.x] = wi;
+  }
+  __syncthreads();
+  x += wsum[wave];
+  if (i < J) start[i] = x - v;
+}
+
+// Exclusive scan of the nb tile totals in place; bsum[nb] = the total.
+__global__ __launch_bounds__(1024) void scan_bsum_kernel(int64_t* __restrict__ bsum, int64_t nb) {
   __shared__ int64_t part[1024];
   const int t = threadIdx.x;
-  const int64_t per = (J + 1023) / 1024;
-  const int64_t b = t * per, e = b + per < J ? b + per : J;
+  const int64_t per = (nb + 1023) / 1024;
+  const int64_t b = t * per, e = b + per < nb ? b + per : nb;
   int64_t s = 0;
-  for (int64_t i = b; i < e; ++i) s += cnt[i];
+  for (int64_t i = b; i < e; ++i) s += bsum[i];
   part[t] = s;
   __syncthreads();
   for (int o = 1; o < 1024; o <<= 1) {
@@ -358,42 +468,90 @@ __global__ __launch_bounds__(1024) void scan_kernel(const int64_t* __restrict__ 
   }
   int64_t run = t == 0 ? 0 : part[t - 1];
   for (int64_t i = b; i < e; ++i) {
-    start[i] = run;
-    run += cnt[i];
+    const int64_t c = bsum[i];
+    bsum[i] = run;
+    run += c;
   }
-  if (t == 1023) start[J] = part[1023];
+  if (t == 1023) bsum[nb] = part[1023];
 }
 
-// Y[i_j(e), :] += coef_d x_e rows[d, :]: one wavefront per work item (a
-// chunk of <= CH entries of one distinct sampled fiber), lanes over columns.
+__global__ __launch_bounds__(SCAN_TILE) void scan_add_kernel(int64_t* __restrict__ start,
+                                                             const int64_t* __restrict__ bsum,
+                                                             int64_t J, int64_t nb) {
+  const int64_t i = (int64_t)blockIdx.x * SCAN_TILE + threadIdx.x;
+  if (i < J) start[i] += bsum[blockIdx.x];
+  if (i == 0) start[J] = bsum[nb];
+}
+
+void launch_scan(hipStream_t st, const int64_t* cnt, int64_t* start, int64_t* bsum, int64_t J) {
+  const int64_t nb = J > 0 ? (J + SCAN_TILE - 1) / SCAN_TILE : 1;
+  hipLaunchKernelGGL(scan_tiles_kernel, dim3((unsigned)nb), dim3(SCAN_TILE), 0, st, cnt, start,
+                     bsum, J);
+  hipLaunchKernelGGL(scan_bsum_kernel, dim3(1), dim3(1024), 0, st, bsum, nb);
+  hipLaunchKernelGGL(scan_add_kernel, dim3((unsigned)nb), dim3(SCAN_TILE), 0, st, start, bsum, J,
+                     nb);
+}
+
+// Y[i_j(e), :] += coef_d x_e rows[d, :].  A wavefront takes SPMM_IPW
+// consecutive work items (chunks of <= CH entries of one distinct sampled
+// fiber): one binary search over the compacted item starts for the first,
+// then a linear advance.  The chunk's entries are read by the lanes in one
+// go and broadcast one by one; lanes run over the R columns.
+constexpr int SPMM_IPW = 4;
+
 template <typename T>
 __global__ __launch_bounds__(256) void spmm_kernel(FiberArgs a, const T* __restrict__ rows,
                                                    double* __restrict__ Y) {
+  extern __shared__ double hot_acc[];  // [nhot][R]
   const int lane = threadIdx.x & 63;
   const int R = a.R;
-  const int64_t total = a.start[a.J];
+  for (int q = threadIdx.x; q < a.nhot * R; q += blockDim.x) hot_acc[q] = 0.0;
+  __syncthreads();
+  const int64_t nrep = a.rpos[a.J];
+  const int64_t total = a.rstart[nrep];
   const int64_t nw = (int64_t)gridDim.x * (blockDim.x >> 6);
   const int32_t* __restrict__ ij = a.cols + (int64_t)a.j * a.nnz;
-  for (int64_t c = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); c < total;
-       c += nw) {
-    // sample of work item c: last d with start[d] <= c
-    int64_t l = 0, r = a.J;
+  for (int64_t c0 = ((int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6)) * SPMM_IPW;
+       c0 < total; c0 += nw * SPMM_IPW) {
+    int64_t l = 0, r = nrep;  // last k with rstart[k] <= c0
     while (r - l > 1) {
       const int64_t m = (l + r) >> 1;
-      if (a.start[m] <= c) l = m; else r = m;
+      if (a.rstart[m] <= c0) l = m; else r = m;
     }
-    const int64_t d = l;
-    const int64_t e0 = a.lo[d] + (c - a.start[d]) * CH;
-    const int64_t e1 = e0 + CH < a.hi[d] ? e0 + CH : a.hi[d];
-    const double cd = a.coef[d];
-    const T r0 = lane < R ? rows[d * R + lane] : T(0);
-    const T r1 = lane + 64 < R ? rows[d * R + lane + 64] : T(0);
-    for (int64_t e = e0; e < e1; ++e) {
-      const double coef = cd * a.vals[e];
-      const int64_t i = ij[e];
-      if (lane < R) atomicAdd(&Y[i * R + lane], coef * (double)r0);
-      if (lane + 64 < R) atomicAdd(&Y[i * R + lane + 64], coef * (double)r1);
+    int64_t k = l;
+    const int64_t c1 = c0 + SPMM_IPW < total ? c0 + SPMM_IPW : total;
+    for (int64_t c = c0; c < c1; ++c) {
+      while (k + 1 < nrep && a.rstart[k + 1] <= c) ++k;
+      const int64_t d = a.rep[k];
+      const int64_t e0 = a.lo[d] + (c - a.rstart[k]) * CH;
+      const int64_t e1 = e0 + CH < a.hi[d] ? e0 + CH : a.hi[d];
+      const double cd = a.coef[d];
+      const T r0 = lane < R ? rows[d * R + lane] : T(0);
+      const T r1 = lane + 64 < R ? rows[d * R + lane + 64] : T(0);
+      // lane t holds entry e0 + t (CH == 64)
+      const int64_t et = e0 + lane < e1 ? e0 + lane : e1 - 1;
+      const double xv = cd * a.vals[et];
+      const int iv = ij[et];
+      const int n = (int)(e1 - e0);
+      for (int t = 0; t < n; ++t) {
+        const double coef = __shfl(xv, t);
+        const int64_t i = __builtin_amdgcn_readfirstlane(__shfl(iv, t));
+        const int hs = a.hot_slot[i];
+        if (hs >= 0) {
+          double* acc = hot_acc + hs * R;
+          if (lane < R) atomicAdd(&acc[lane], coef * (double)r0);
+          if (lane + 64 < R) atomicAdd(&acc[lane + 64], coef * (double)r1);
+        } else {
+          if (lane < R) atomicAdd(&Y[i * R + lane], coef * (double)r0);
+          if (lane + 64 < R) atomicAdd(&Y[i * R + lane + 64], coef * (double)r1);
+        }
+      }
     }
+  }
+  __syncthreads();
+  for (int q = threadIdx.x; q < a.nhot * R; q += blockDim.x) {
+    const double v = hot_acc[q];
+    if (v != 0.0) atomicAdd(&Y[(int64_t)a.hot_rows[q / R] * R + q % R], v);
   }
 }
 
@@ -409,17 +567,22 @@ hipError_t launch_lookup(hipStream_t st, const FiberArgs& a) {
   hipLaunchKernelGGL(merge_clear_kernel, dim3((unsigned)hb), dim3(256), 0, st, a);
   hipLaunchKernelGGL(merge_insert_kernel, dim3((unsigned)blocks), dim3(256), 0, st, a);
   hipLaunchKernelGGL(merge_finish_kernel, dim3((unsigned)blocks), dim3(256), 0, st, a);
-  hipLaunchKernelGGL(scan_kernel, dim3(1), dim3(1024), 0, st, a.cnt, a.start, a.J);
+  launch_scan(st, a.cnt, a.start, a.bsum, a.J);
+  launch_scan(st, a.rflag, a.rpos, a.bsum, a.J);
+  int64_t cb = (a.J + 1 + 255) / 256;
+  if (cb > 4096) cb = 4096;
+  hipLaunchKernelGGL(compact_kernel, dim3((unsigned)cb), dim3(256), 0, st, a);
   return hipGetLastError();
 }
 
 hipError_t launch_spmm(hipStream_t st, krps_precision p, const FiberArgs& a, const void* rows,
                        void* Y) {
+  const size_t lds = (size_t)a.nhot * a.R * 8;
   if (p == KRPS_FP64)
-    hipLaunchKernelGGL(spmm_kernel<double>, dim3(2048), dim3(256), 0, st, a,
+    hipLaunchKernelGGL(spmm_kernel<double>, dim3(2048), dim3(256), lds, st, a,
                        (const double*)rows, (double*)Y);
   else
-    hipLaunchKernelGGL(spmm_kernel<float>, dim3(2048), dim3(256), 0, st, a, (const float*)rows,
+    hipLaunchKernelGGL(spmm_kernel<float>, dim3(2048), dim3(256), lds, st, a, (const float*)rows,
                        (double*)Y);
   return hipGetLastError();
 }
@@ -435,45 +598,92 @@ __global__ void fill_kernel(T* __restrict__ p, int64_t n, T v) {
     p[i] = v;
 }
 
-// Y M^+ for a persistent sweep of row groups; thread (row slot, c) with
-// c < RB columns.  Pass 1 (sigma == nullptr) only accumulates the per-column
-// sums of squares of the float64 products in registers and reduces them per
-// block into partial[block][c]; pass 2 recomputes the products and writes
-// U = (Y M^+)[:, c] / sigma[c], rounded once to the factor type.
-template <typename T, int RB>
+// Y M^+ for a persistent sweep of 64-row tiles.  The block's 256 threads
+// are 16 row groups x 16 column groups; a thread accumulates 4 rows x
+// RC/16 columns (columns tc + 16 j) in float64 registers, with K taken in
+// chunks of 32 through LDS (Y tile [64][33], M^+ chunk [32][RC]).
+// Pass 1 (sigma == nullptr) only keeps the per-column sums of squares of
+// the products and reduces them per block into partial[block][c]; pass 2
+// recomputes the products and writes U = (Y M^+)[:, c] / sigma[c],
+// rounded once to the factor type.
+constexpr int GT_ROWS = 64, GT_KC = 32;
+
+template <typename T, int RC>
 __global__ __launch_bounds__(256) void gemm_colsum_kernel(const double* __restrict__ Y,
                                                           const double* __restrict__ Mp,
                                                           T* __restrict__ out, int64_t I, int R,
                                                           double* __restrict__ partial,
                                                           const double* __restrict__ sigma) {
-  extern __shared__ double sm[];
-  double* Ms = sm;                 // R x R
-  double* red = sm + R * R;        // 256
-  for (int i = threadIdx.x; i < R * R; i += blockDim.x) Ms[i] = Mp[i];
-  __syncthreads();
-  constexpr int ROWS = 256 / RB;
-  const int c = threadIdx.x % RB;
-  const int rs = threadIdx.x / RB;
-  const double inv = (sigma != nullptr && c < R && sigma[c] > 0) ? 1.0 / sigma[c] : 0.0;
-  double sq = 0;
-  for (int64_t r = (int64_t)blockIdx.x * ROWS + rs; r < I; r += (int64_t)gridDim.x * ROWS) {
-    if (c < R) {
-      const double* __restrict__ yr = Y + r * R;
-      double acc = 0;
-      for (int k = 0; k < R; ++k) acc += yr[k] * Ms[k * R + c];
-      if (sigma == nullptr)
-        sq += acc * acc;
-      else
-        out[r * R + c] = (T)(acc * inv);
+  constexpr int TCW = RC / 16;
+  __shared__ double Ys[GT_ROWS][GT_KC + 1];
+  __shared__ double Ms[GT_KC][RC];
+  __shared__ double red[16][RC];
+  const int tc = threadIdx.x % 16;
+  const int tr = threadIdx.x / 16;
+  double inv[TCW], sq[TCW];
+#pragma unroll
+  for (int j = 0; j < TCW; ++j) {
+    const int c = tc + 16 * j;
+    inv[j] = (sigma != nullptr && c < R && sigma[c] > 0) ? 1.0 / sigma[c] : 0.0;
+    sq[j] = 0.0;
+  }
+  const int64_t ntile = (I + GT_ROWS - 1) / GT_ROWS;
+  for (int64_t tile = blockIdx.x; tile < ntile; tile += gridDim.x) {
+    const int64_t r0 = tile * GT_ROWS;
+    double acc[4][TCW];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int j = 0; j < TCW; ++j) acc[i][j] = 0.0;
+    for (int k0 = 0; k0 < R; k0 += GT_KC) {
+      __syncthreads();
+      for (int e = threadIdx.x; e < GT_ROWS * GT_KC; e += 256) {
+        const int i = e / GT_KC, kk = e % GT_KC;
+        const int64_t r = r0 + i;
+        Ys[i][kk] = (r < I && k0 + kk < R) ? Y[r * R + k0 + kk] : 0.0;
+      }
+      for (int e = threadIdx.x; e < GT_KC * RC; e += 256) {
+        const int kk = e / RC, c = e % RC;
+        Ms[kk][c] = (k0 + kk < R && c < R) ? Mp[(int64_t)(k0 + kk) * R + c] : 0.0;
+      }
+      __syncthreads();
+#pragma unroll 4
+      for (int kk = 0; kk < GT_KC; ++kk) {
+        double a[4], b[TCW];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) a[i] = Ys[tr * 4 + i][kk];
+#pragma unroll
+        for (int j = 0; j < TCW; ++j) b[j] = Ms[kk][tc + 16 * j];
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+          for (int j = 0; j < TCW; ++j) acc[i][j] += a[i] * b[j];
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int64_t r = r0 + tr * 4 + i;
+      if (r >= I) continue;
+#pragma unroll
+      for (int j = 0; j < TCW; ++j) {
+        const int c = tc + 16 * j;
+        if (c >= R) continue;
+        if (sigma == nullptr)
+          sq[j] += acc[i][j] * acc[i][j];
+        else
+          out[r * R + c] = (T)(acc[i][j] * inv[j]);
+      }
     }
   }
   if (sigma != nullptr) return;
-  red[threadIdx.x] = sq;
   __syncthreads();
-  if (rs == 0 && c < R) {
-    double s = 0;
-    for (int q = 0; q < ROWS; ++q) s += red[q * RB + c];
-    partial[(int64_t)blockIdx.x * R + c] = s;
+#pragma unroll
+  for (int j = 0; j < TCW; ++j) red[tr][tc + 16 * j] = sq[j];
+  __syncthreads();
+  for (int c = threadIdx.x; c < R; c += 256) {
+    double t = 0;
+    for (int q = 0; q < 16; ++q) t += red[q][c];
+    partial[(int64_t)blockIdx.x * R + c] = t;
   }
 }
 
@@ -552,17 +762,13 @@ hipError_t launch_fill_f64(hipStream_t st, double* ptr, int64_t n) {
   return hipGetLastError();
 }
 
-template <typename T, int RB>
+template <typename T, int RC>
 static hipError_t run_gemm(hipStream_t st, const double* Y, const double* Mp, void* out, int64_t I,
                            int R, double* partial, double* sigma) {
-  const size_t lds = (size_t)R * R * 8 + 256 * 8;
-  hipError_t e = hipFuncSetAttribute((const void*)gemm_colsum_kernel<T, RB>,
-                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((gemm_colsum_kernel<T, RB>), dim3(SOLVE_BLOCKS), dim3(256), lds, st, Y, Mp,
+  hipLaunchKernelGGL((gemm_colsum_kernel<T, RC>), dim3(SOLVE_BLOCKS), dim3(256), 0, st, Y, Mp,
                      (T*)out, I, R, partial, (const double*)nullptr);
   hipLaunchKernelGGL(sigma_kernel, dim3(R), dim3(256), 0, st, partial, SOLVE_BLOCKS, R, sigma);
-  hipLaunchKernelGGL((gemm_colsum_kernel<T, RB>), dim3(SOLVE_BLOCKS), dim3(256), lds, st, Y, Mp,
+  hipLaunchKernelGGL((gemm_colsum_kernel<T, RC>), dim3(SOLVE_BLOCKS), dim3(256), 0, st, Y, Mp,
                      (T*)out, I, R, partial, (const double*)sigma);
   return hipGetLastError();
 }
@@ -572,11 +778,14 @@ static hipError_t run_gemm(hipStream_t st, const double* Y, const double* Mp, vo
 hipError_t launch_solve_gemm(hipStream_t st, krps_precision p, const void* Y, const double* Mp,
                              void* U, int64_t I, int R, double* partial, double* sigma) {
   const double* Yd = (const double*)Y;
-  if (p == KRPS_FP64)
-    return R <= 64 ? run_gemm<double, 64>(st, Yd, Mp, U, I, R, partial, sigma)
-                   : run_gemm<double, 128>(st, Yd, Mp, U, I, R, partial, sigma);
-  return R <= 64 ? run_gemm<float, 64>(st, Yd, Mp, U, I, R, partial, sigma)
-                 : run_gemm<float, 128>(st, Yd, Mp, U, I, R, partial, sigma);
+  if (p == KRPS_FP64) {
+    if (R <= 32) return run_gemm<double, 32>(st, Yd, Mp, U, I, R, partial, sigma);
+    if (R <= 64) return run_gemm<double, 64>(st, Yd, Mp, U, I, R, partial, sigma);
+    return run_gemm<double, 128>(st, Yd, Mp, U, I, R, partial, sigma);
+  }
+  if (R <= 32) return run_gemm<float, 32>(st, Yd, Mp, U, I, R, partial, sigma);
+  if (R <= 64) return run_gemm<float, 64>(st, Yd, Mp, U, I, R, partial, sigma);
+  return run_gemm<float, 128>(st, Yd, Mp, U, I, R, partial, sigma);
 }
 
 hipError_t launch_colnorm(hipStream_t st, krps_precision p, const void* U, int64_t I, int R,
