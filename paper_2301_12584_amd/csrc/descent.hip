@@ -82,7 +82,8 @@ __device__ __forceinline__ void build_packed(Packed<LPS, NP>& P, const double* h
 // coalesced strides) dotted with the packed outer product in registers.
 template <typename T, int LPS, int NP>
 __device__ __forceinline__ double node_mass(const Packed<LPS, NP>& P, const double*,
-                                            const T* __restrict__ node, int R, int TR, int sl) {
+                                            const T* __restrict__ node, int R, int TR, int sl,
+                                            const uint16_t* __restrict__ = nullptr) {
   // all loads first, then the float64 products.  Only the npr strides
   // that reach into the triangle are read (npr is uniform); the last may
   // run up to LPS - 1 entries past the node, into the next node or the
@@ -102,30 +103,36 @@ __device__ __forceinline__ double node_mass(const Packed<LPS, NP>& P, const doub
   return group_sum<LPS>(acc);
 }
 
-// R > 64 (one sample per wavefront, NP == 0): row by row; lane l owns
-// columns l and l + 64 and the row's h_a is a broadcast LDS read, so no
-// outer product is held in registers.
+// R > 64 (one sample per wavefront, NP == 0): the packed outer product is
+// not held in registers; each lane forms w h_a h_b for its packed entries
+// (lane + 64 m) from the (a, b) table and h in LDS, eight entries at a
+// time with their loads issued together.
 template <typename T>
 __device__ __forceinline__ double node_mass(const Packed<64, 0>&, const double* hb,
-                                            const T* __restrict__ node, int R, int TR, int lane) {
-  double acc0 = 0, acc1 = 0;
-  int64_t start = 0;
-  const int b0 = lane, b1 = lane + 64;
-  for (int a = 0; a < R; ++a) {
-    const double ha = hb[a];
-    if (b0 >= a && b0 < R) {
-      const double g = (double)node[start + (b0 - a)];
-      acc0 += (b0 == a ? ha : 2.0 * ha) * g;
+                                            const T* __restrict__ node, int R, int TR, int lane,
+                                            const uint16_t* __restrict__ tab) {
+  double acc = 0;
+  const int npr = (TR + 63) / 64;
+  for (int m0 = 0; m0 < npr; m0 += 8) {
+    T g[8];
+    uint16_t ab[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const int p = lane + 64 * (m0 + q);
+      const int pc = p < TR ? p : TR - 1;
+      g[q] = node[pc];
+      ab[q] = tab[pc];
     }
-    if (b1 >= a && b1 < R) {
-      const double g = (double)node[start + (b1 - a)];
-      acc1 += (b1 == a ? ha : 2.0 * ha) * g;
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const int p = lane + 64 * (m0 + q);
+      const int a = ab[q] & 0xff, b = ab[q] >> 8;
+      const double w = p < TR ? (a != b ? 2.0 : 1.0) : 0.0;
+      acc += w * hb[a] * hb[b] * (double)g[q];
     }
-    start += R - a;
   }
-  const double v = (b0 < R ? acc0 * hb[b0] : 0.0) + (b1 < R ? acc1 * hb[b1] : 0.0);
-  (void)TR;
-  return group_sum<64>(v);
+  (void)R;
+  return group_sum<64>(acc);
 }
 
 // Inversion walk down a stored tree (root + left children) for each group's
@@ -135,14 +142,15 @@ __device__ __forceinline__ double node_mass(const Packed<64, 0>&, const double* 
 template <typename T, int LPS, int NP>
 __device__ __forceinline__ int64_t walk(const T* __restrict__ nodes, int64_t L, int D,
                                         const Packed<LPS, NP>& P, const double* hb, int R, int TR,
-                                        int sl, double x, double C, double& low_out) {
+                                        int sl, double x, double C, double& low_out,
+                                        const uint16_t* __restrict__ tab) {
   double low = 0.0, high = C;
   int64_t pos = 0;
   int64_t off = 1;
   for (int lev = 1; lev <= D; ++lev) {
     const int64_t cnt_left = ((L - 1) >> (D - lev + 1)) + 1;
     const int64_t real = ((L - 1) >> (D - lev)) + 1;
-    double mL = node_mass<T>(P, hb, nodes + (off + pos) * (int64_t)TR, R, TR, sl);
+    double mL = node_mass<T>(P, hb, nodes + (off + pos) * (int64_t)TR, R, TR, sl, tab);
     mL = mL > 0.0 ? mL : 0.0;
     const double cut = low + mL;
     const bool right_exists = 2 * pos + 1 < real;
@@ -236,7 +244,8 @@ __device__ __forceinline__ int64_t leaf_scan(const T* __restrict__ U, int R, int
 // The walk of the samples base + (lane group) of one wavefront: 64 / LPS
 // samples at once, LPS lanes per sample.  `tab` maps packed entry p to its
 // (a, b) pair (LDS or global); `hb` is this group's RMAX doubles of LDS.
-// NP == 0 selects the row-broadcast masses (R > 64, LPS == 64).
+// NP == 0 selects the masses formed entry by entry from h in LDS (R > 64,
+// LPS == 64).
 template <typename T, int LPS, int NP, int RMAX>
 __device__ __forceinline__ void descend(const DescentArgs& a, int64_t base,
                                         const uint16_t* __restrict__ tab, double* hb, int lane) {
@@ -267,9 +276,9 @@ __device__ __forceinline__ void descend(const DescentArgs& a, int64_t base,
     wave_lds_sync();
     if constexpr (NP > 0) build_packed(P, hb, tab, TR, sl);
     const T* __restrict__ E = (const T*)md.E;
-    const double C1 = node_mass<T>(P, hb, E, R, TR, sl);
+    const double C1 = node_mass<T>(P, hb, E, R, TR, sl, tab);
     double low;
-    int u = (int)walk(E, (int64_t)R, md.DE, P, hb, R, TR, sl, d1 * C1, C1, low);
+    int u = (int)walk(E, (int64_t)R, md.DE, P, hb, R, TR, sl, d1 * C1, C1, low, tab);
     if (u >= R) u = R - 1;
     // ---- stage 2: row t from Z_k with h~ = h (*) V[:, u]
     const T* __restrict__ V = (const T*)md.V + (int64_t)u * R;
@@ -286,9 +295,9 @@ __device__ __forceinline__ void descend(const DescentArgs& a, int64_t base,
     wave_lds_sync();
     if constexpr (NP > 0) build_packed(P, hb, tab, TR, sl);
     const T* __restrict__ Z = (const T*)md.Z;
-    const double C2 = node_mass<T>(P, hb, Z, R, TR, sl);
+    const double C2 = node_mass<T>(P, hb, Z, R, TR, sl, tab);
     const double x2 = d2 * C2;
-    const int64_t c = walk(Z, md.L, md.D, P, hb, R, TR, sl, x2, C2, low);
+    const int64_t c = walk(Z, md.L, md.D, P, hb, R, TR, sl, x2, C2, low, tab);
     const int64_t s0 = c * md.F;
     const int64_t s1 = s0 + md.F < md.I ? s0 + md.F : md.I;
     const T* __restrict__ U = (const T*)md.U;
@@ -315,7 +324,7 @@ __device__ __forceinline__ void descend(const DescentArgs& a, int64_t base,
       if (sl + LPS * i < R) hb[sl + LPS * i] = h[i];
     wave_lds_sync();
     if constexpr (NP > 0) build_packed(P, hb, tab, TR, sl);
-    const double q = node_mass<double>(P, hb, a.gplus, R, TR, sl) * inv_rank;
+    const double q = node_mass<double>(P, hb, a.gplus, R, TR, sl, tab) * inv_rank;
     if (active) {
       if (sl == 0 && a.prob != nullptr) a.prob[d] = q;
       const double w = 1.0 / sqrt((double)J * q);
@@ -423,7 +432,7 @@ __global__ __launch_bounds__(64 * DESC_WAVES, KRPS_DESC_MIN_WAVES) void descent_
 // Packed-index table of each problem's R (one block per problem).
 __global__ void batch_tab_kernel(const BatchProblem* __restrict__ probs) {
   const BatchProblem& b = probs[blockIdx.x];
-  if (b.cls < 4) fill_tab((uint16_t*)b.tab, b.a.R, threadIdx.x, blockDim.x);
+  fill_tab((uint16_t*)b.tab, b.a.R, threadIdx.x, blockDim.x);
 }
 
 // q of given multi-indices: a = (*)_k U_k[idx[d][k]], q = a G^+ a^T / rank.
