@@ -54,6 +54,10 @@ def parse():
     ap.add_argument("--als-sweeps", type=int, default=None)
     ap.add_argument("--als-seeds", type=int, default=4,
                     help="uniform seeds of the CP-ALS leg (mean/std of the final fit)")
+    ap.add_argument("--large", action="store_true",
+                    help="also run the large 4-mode CP-ALS workload (2e7^3 x 1e6, 5e8 Zipf(1.1) "
+                         "entries, R=128, J=131072; several minutes)")
+    ap.add_argument("--large-sweeps", type=int, default=None)
     ap.add_argument("--batched", default="fp32",
                     help="precision of the batched-samplers leg ('' skips it)")
     ap.add_argument("--batched-reps", type=int, default=3)
@@ -200,7 +204,7 @@ def oracle_fits(config, store, nnz):
         return None
 
 
-def run_als(torch, krps, ctx, precs, nnz, sweeps_arg, seeds):
+def run_als(torch, krps, ctx, precs, nnz, sweeps_arg, seeds, config=3, init="gaussian"):
     """Sketched CP-ALS: one untimed sweep captures the graph, the factors
     are reset, then every sweep is replayed and timed with HIP events on
     the context stream; the fit is taken between sweeps, outside the
@@ -208,16 +212,23 @@ def run_als(torch, krps, ctx, precs, nnz, sweeps_arg, seeds):
     import numpy as np
     import synth
     t0 = time.perf_counter()
-    dims, idx, val, U0, R, J, sweeps, useed = synth.als_problem(3, None if nnz is None else int(nnz))
+    dims, idx, val, U0, R, J, sweeps, useed = synth.als_problem(
+        config, None if nnz is None else int(nnz),
+        progress=lambda j: print(f"# als inputs: mode {j} drawn", file=sys.stderr, flush=True))
     if sweeps_arg is not None:
         sweeps = sweeps_arg
     N = len(dims)
     gen_s = time.perf_counter() - t0
-    print(f"# als inputs: {len(val)} nnz generated in {gen_s:.1f} s", file=sys.stderr, flush=True)
+    len_nnz = int(len(val))
+    print(f"# als inputs: {len_nnz} nnz generated in {gen_s:.1f} s", file=sys.stderr, flush=True)
     t0 = time.perf_counter()
-    T = krps.Tensor(ctx, dims, torch.from_numpy(idx).to(ctx.device),
-                    torch.from_numpy(val).to(ctx.device))
+    idx_d = torch.from_numpy(idx).to(ctx.device)
+    val_d = torch.from_numpy(val).to(ctx.device)
     del idx, val
+    T = krps.Tensor(ctx, dims, idx_d, val_d)
+    del idx_d, val_d
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
     print(f"# als tensor: {T.stored_entries} distinct coordinates, index built in "
           f"{time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
     u_all = [torch.from_numpy(synth.sweep_uniforms(useed, s, N, J)).to(ctx.device)
@@ -237,8 +248,12 @@ def run_als(torch, krps, ctx, precs, nnz, sweeps_arg, seeds):
             A.sigma.fill_(1.0)
 
         for k in range(N):
-            A.normalize(k)
-        Ud0 = [U.clone() for U in S.factors]
+            if init == "range_finder":
+                A.init_range_finder(k, synth.config_seed(config))
+            else:
+                A.normalize(k)
+        Ud0 = [U.cpu() for U in S.factors]  # host copies: the large workload's
+        # float64 factors alone take 61 GB of device memory
         # capture (first call with these pointers), then start over
         ubuf.copy_(u_all[0])
         A.sweep(ubuf, use_graph=True)
@@ -270,7 +285,7 @@ def run_als(torch, krps, ctx, precs, nnz, sweeps_arg, seeds):
             finals.append(A.fit())
             print(f"# als {prec} seed {extra}: final fit {finals[-1]:.6f}", file=sys.stderr,
                   flush=True)
-        ref = oracle_fits(3, "f64" if prec == "fp64" else "f32", nnz)
+        ref = oracle_fits(config, "f64" if prec == "fp64" else "f32", nnz)
         rec = {"sweep_ms": ms, "sweep_ms_mean": float(np.mean(ms)),
                "als_s_total": float(np.sum(ms)) / 1e3, "fits": fits,
                "final_fit_over_seeds": finals, "final_fit_mean": float(np.mean(finals)),
@@ -282,11 +297,14 @@ def run_als(torch, krps, ctx, precs, nnz, sweeps_arg, seeds):
         out[prec] = rec
         print(f"# als {prec}: sweep {rec['sweep_ms_mean']:.3f} ms, fits {np.round(fits, 6)}",
               file=sys.stderr, flush=True)
-        del A, S
+        del A, S, Ud, Ud0
         torch.cuda.synchronize()
-    cfg = {"workload": f"sketched CP-ALS {dims[0]:.0e}x{dims[1]:.0e}x{dims[2]:.0e}, "
-                       f"nnz={T.nnz}, Zipf(1.2), R={R}, J={J}, {sweeps} sweeps, graph replay",
-           "dims": list(dims), "nnz": T.nnz, "R": R, "J": J, "sweeps": sweeps}
+        torch.cuda.empty_cache()
+    shape = "x".join(f"{d:.0e}" for d in dims)
+    cfg = {"workload": f"sketched CP-ALS {shape}, nnz={len_nnz}, "
+                       f"Zipf({synth.CONFIGS[config]['alpha']}), R={R}, J={J}, {sweeps} sweeps, "
+                       "graph replay",
+           "dims": list(dims), "nnz": len_nnz, "R": R, "J": J, "sweeps": sweeps, "init": init}
     return {"config": cfg, "precisions": out}
 
 
@@ -440,6 +458,12 @@ def main():
                               args.als_sweeps, args.als_seeds)
     if args.batched:
         line["batched"] = run_batched(torch, krps, ctx, args.batched, args.batched_reps)
+    if args.large:
+        # the N(0,1) start draws only empty fibers of this tensor (5e8 entries
+        # among 4e20 fibers per mode), so the first solve is zero; the range
+        # finder (the paper's start for its sparsest tensor) is used instead
+        line["als_large"] = run_als(torch, krps, ctx, ["bf16x2", "fp64"], None, args.large_sweeps,
+                                    1, config=5, init="range_finder")
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(Us, u01, J)
     else:

@@ -140,6 +140,17 @@ krps_status krps_sample(krps_sampler s, int exclude, int64_t J, const double* un
                         int32_t* idx, double* prob, void* rows, void* ws, size_t ws_bytes,
                         int check);
 
+/* krps_sample with uniforms generated in the walk instead of read: for
+ * sample d and mode k, the words x0, x1 of Philox4x64-10 (Salmon et al.,
+ * SC'11) of counter (ctr_base + d, k, 0, 0) under key (seed, 0) give
+ * uniforms[d][k][0] = ((x0 >> 11) + 0.5) 2^-53 (first stage) and
+ * uniforms[d][k][1] from x1 (second stage).  Disjoint ctr_base ranges give
+ * independent draws.  Other arguments as for krps_sample (no status
+ * check). */
+krps_status krps_sample_seeded(krps_sampler s, int exclude, int64_t J, uint64_t seed,
+                               uint64_t ctr_base, int32_t* idx, double* prob, void* rows,
+                               void* ws, size_t ws_bytes);
+
 /* The two halves of krps_sample, for callers that reuse one preparation or
  * time the walk alone.  krps_sample_prepare enqueues the set-up part of
  * Algorithm 2 (G^+, the G_{>k}, their eigendecompositions and the eigen-
@@ -319,6 +330,21 @@ krps_status krps_autotune_workspace_bytes(int N, const int64_t* I, int R, krps_p
 krps_status krps_autotune(krps_ctx ctx, int N, const int64_t* I, int R, krps_precision p,
                           void* const* U, int64_t J, const double* uniforms, void* ws,
                           size_t ws_bytes, const char* cache_path, krps_tune* out);
+
+/* Randomized range-finder initialisation of factor j (the initialisation
+ * the paper uses for its sparsest tensor, Section 4.3): U_j = mat(T, j) S
+ * with an i.i.d. N(0,1) sketch S of prod_{k != j} I_k rows and R columns
+ * that is generated only for fibers holding entries and never stored.
+ * Row of S for the fiber with other-mode indices (i_a, i_b, i_c, i_d)
+ * (increasing mode order, missing ones 0), column pair q: Philox4x64-10 of
+ * counter (i_a | i_b << 32, i_c | i_d << 32, q, 0) under key (seed, j);
+ * the first two output words x give uniforms ((x >> 11) + 0.5) 2^-53 and
+ * the Box-Muller pair (cosine, sine) gives columns 2q and 2q + 1.  Then
+ * the columns are normalised as krps_normalize_factor does (sigma out,
+ * may be NULL) and Z_j is rebuilt.  U[j] is overwritten.  N <= 5
+ * (KRPS_EUNSUPPORTED otherwise).  ws: a solve workspace (any J). */
+krps_status krps_init_range_finder(krps_sampler s, krps_tensor t, int j, uint64_t seed,
+                                   double* sigma, void* ws, size_t ws_bytes);
 
 /* Offsets (bytes into the solve workspace) of the last solve's pieces. */
 typedef struct {

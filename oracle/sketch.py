@@ -24,7 +24,7 @@ from __future__ import annotations
 
 import numpy as np
 
-__all__ = ["philox4x64", "sketch_rows", "range_finder"]
+__all__ = ["philox4x64", "sketch_rows", "range_finder", "philox_uniforms"]
 
 _M0 = np.uint64(0xD2E7470EE14C6C93)
 _M1 = np.uint64(0xCA5A826395121157)
@@ -96,4 +96,19 @@ def range_finder(tensor, j, R, seed):
     for r in range(R):
         out[:, r] = np.bincount(tensor.idx[:, j], weights=tensor.val * S[inv, r],
                                 minlength=tensor.dims[j])
+    return out
+
+
+def philox_uniforms(J, N, seed, ctr_base=0):
+    """Sampler uniforms generated from (seed, ctr_base): float64 [J][N][2]
+    with [d][k][s] from word s of Philox4x64-10 of counter
+    (ctr_base + d, k, 0, 0) under key (seed, 0)."""
+    d = np.arange(J, dtype=np.uint64) + np.uint64(ctr_base)
+    out = np.empty((J, N, 2))
+    for k in range(N):
+        ctr = np.stack([d, np.full(J, k, dtype=np.uint64), np.zeros(J, dtype=np.uint64),
+                        np.zeros(J, dtype=np.uint64)], 1)
+        x = philox4x64(ctr, [seed, 0])
+        for s in range(2):
+            out[:, k, s] = ((x[:, s] >> np.uint64(11)).astype(np.float64) + 0.5) * 2.0 ** -53
     return out

@@ -82,6 +82,8 @@ def lib():
         "krps_sample_workspace_bytes": (c.c_int, [P, c.POINTER(c.c_size_t)]),
         "krps_sample": (c.c_int, [P, c.c_int, c.c_int64, P, P, P, P, P, c.c_size_t, c.c_int]),
         "krps_sample_prepare": (c.c_int, [P, c.c_int, P, c.c_size_t]),
+        "krps_sample_seeded": (c.c_int, [P, c.c_int, c.c_int64, c.c_uint64, c.c_uint64, P, P, P,
+                                         P, c.c_size_t]),
         "krps_sample_batched_workspace_bytes": (c.c_int, [P, c.c_int, P, P,
                                                           c.POINTER(c.c_size_t)]),
         "krps_sample_batched": (c.c_int, [P, c.c_int, P, P, P, P, P, P, P, c.c_size_t]),
@@ -96,6 +98,7 @@ def lib():
         "krps_tensor_destroy": (c.c_int, [P]),
         "krps_tensor_norm2": (c.c_int, [P, c.POINTER(c.c_double)]),
         "krps_sampler_set_lps": (c.c_int, [P, c.c_int]),
+        "krps_init_range_finder": (c.c_int, [P, P, c.c_int, c.c_uint64, P, P, c.c_size_t]),
         "krps_autotune_workspace_bytes": (c.c_int, [c.c_int, c.POINTER(c.c_int64), c.c_int,
                                                     c.c_int, c.c_int64, c.POINTER(c.c_size_t)]),
         "krps_autotune": (c.c_int, [P, c.c_int, c.POINTER(c.c_int64), c.c_int, c.c_int,
@@ -212,6 +215,18 @@ class Sampler:
                                 _ptr(r), _ptr(self.draw_ws), self.draw_ws.numel(),
                                 1 if check_status else 0))
         return idx, p, r
+
+    def sample_seeded(self, exclude, J, seed, ctr_base=0, prob=True):
+        """Draws J samples with uniforms generated in the walk (Philox4x64-10
+        of (ctr_base + d, k, 0, 0) under (seed, 0)); returns ``(idx, prob)``."""
+        torch = self.ctx.torch
+        dev = self.ctx.device
+        idx = torch.empty((int(J), self.N), dtype=torch.int32, device=dev)
+        p = torch.empty(int(J), dtype=torch.float64, device=dev) if prob else None
+        check(lib().krps_sample_seeded(self.handle, int(exclude), int(J), ctypes.c_uint64(int(seed)),
+                                       ctypes.c_uint64(int(ctr_base)), _ptr(idx), _ptr(p), None,
+                                       _ptr(self.draw_ws), self.draw_ws.numel()))
+        return idx, p
 
     def prepare(self, exclude):
         """The set-up part of Algorithm 2 (before its per-sample loop) for
@@ -454,6 +469,13 @@ class CPALS:
     def normalize(self, j):
         check(lib().krps_normalize_factor(self.S.handle, int(j), _ptr(self.sigma), _ptr(self.ws),
                                           self.ws.numel()))
+
+    def init_range_finder(self, j, seed):
+        """U_j = mat(T, j) S with a generated Gaussian sketch, normalised
+        (sigma of mode j into self.sigma); Z_j rebuilt."""
+        check(lib().krps_init_range_finder(self.S.handle, self.T.handle, int(j),
+                                           ctypes.c_uint64(int(seed)), _ptr(self.sigma),
+                                           _ptr(self.ws), self.ws.numel()))
 
     def solve(self, j, uniforms):
         check(lib().krps_sketched_solve(self.S.handle, self.T.handle, int(j), self.J,

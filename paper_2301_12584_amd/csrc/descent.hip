@@ -267,8 +267,22 @@ __device__ __forceinline__ void descend(const DescentArgs& a, int64_t base,
   for (int st = 0; st < a.nsteps; ++st) {
     const int k = a.order[st];
     const ModeDesc& md = a.mode[k];
-    const double d1 = active ? a.u01[(d * N + k) * 2 + 0] : 0.5;
-    const double d2 = active ? a.u01[(d * N + k) * 2 + 1] : 0.5;
+    double d1 = 0.5, d2 = 0.5;
+    if (a.u01 != nullptr) {
+      if (active) {
+        d1 = a.u01[(d * N + k) * 2 + 0];
+        d2 = a.u01[(d * N + k) * 2 + 1];
+      }
+    } else {
+      // in-kernel uniforms: Philox4x64-10 of (ctr_base + d, k, 0, 0) under
+      // (seed, 0); word 0 drives stage 1, word 1 stage 2
+      uint64_t c[4] = {a.ctr_base + (uint64_t)d, (uint64_t)k, 0, 0};
+      philox4x64_10(c, a.seed, 0);
+      if (active) {
+        d1 = u01_of_word(c[0]);
+        d2 = u01_of_word(c[1]);
+      }
+    }
     // ---- stage 1: eigen-component u from E_k
 #pragma unroll
     for (int i = 0; i < HE; ++i)

@@ -73,6 +73,30 @@ __device__ __forceinline__ double wave_inclusive_scan(double v, int lane) {
   return v;
 }
 
+// Philox4x64-10 (Salmon, Moraes, Dror, Shaw, SC'11): ten rounds of the
+// 4 x 64-bit S-box on counter c under key (k0, k1), in place.
+__device__ __forceinline__ void philox4x64_10(uint64_t c[4], uint64_t k0, uint64_t k1) {
+  const uint64_t M0 = 0xD2E7470EE14C6C93ull, M1 = 0xCA5A826395121157ull;
+  const uint64_t W0 = 0x9E3779B97F4A7C15ull, W1 = 0xBB67AE8584CAA73Bull;
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    const uint64_t h0 = __umul64hi(M0, c[0]), l0 = M0 * c[0];
+    const uint64_t h1 = __umul64hi(M1, c[2]), l1 = M1 * c[2];
+    const uint64_t n0 = h1 ^ c[1] ^ k0, n2 = h0 ^ c[3] ^ k1;
+    c[0] = n0;
+    c[1] = l1;
+    c[2] = n2;
+    c[3] = l0;
+    k0 += W0;
+    k1 += W1;
+  }
+}
+
+// Open-interval uniform from a 64-bit word: ((x >> 11) + 0.5) 2^-53.
+__device__ __forceinline__ double u01_of_word(uint64_t x) {
+  return ((double)(x >> 11) + 0.5) * 0x1.0p-53;
+}
+
 // Orders the LDS traffic of one wave (all lanes see the others' writes).
 __device__ __forceinline__ void wave_lds_sync() {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");

@@ -667,6 +667,27 @@ krps_status krps_sample_draw(krps_sampler s, int exclude, int64_t J, const doubl
   return KRPS_OK;
 }
 
+krps_status krps_sample_seeded(krps_sampler s, int exclude, int64_t J, uint64_t seed,
+                               uint64_t ctr_base, int32_t* idx, double* prob, void* rows,
+                               void* ws, size_t ws_bytes) {
+  krps_status st = krps_sample_prepare(s, exclude, ws, ws_bytes);
+  if (st != KRPS_OK) return st;
+  if (J < 0) return fail(KRPS_EINVAL, "J < 0");
+  if (J > 0 && idx == nullptr) return fail(KRPS_EINVAL, "idx is NULL");
+  DescentArgs a;
+  fill_descent_args(s, exclude, ws, a);
+  a.J = J;
+  a.u01 = nullptr;
+  a.seed = seed;
+  a.ctr_base = ctr_base;
+  a.idx = idx;
+  a.prob = prob;
+  a.rows = rows;
+  hipError_t e = launch_descent(s->ctx->stream, s->prec, a);
+  if (e != hipSuccess) return hip_fail(e, "descent launch");
+  return KRPS_OK;
+}
+
 krps_status krps_sample(krps_sampler s, int exclude, int64_t J, const double* uniforms,
                         int32_t* idx, double* prob, void* rows, void* ws, size_t ws_bytes,
                         int check) {
@@ -1438,6 +1459,22 @@ krps_status krps_autotune(krps_ctx ctx, int N, const int64_t* I, int R, krps_pre
   out->from_cache = 0;
   tune_store(cache_path, key, *out);
   return KRPS_OK;
+}
+
+krps_status krps_init_range_finder(krps_sampler s, krps_tensor t, int j, uint64_t seed,
+                                   double* sigma, void* ws, size_t ws_bytes) {
+  krps_status st = check_pair(s, t);
+  if (st != KRPS_OK) return st;
+  if (j < 0 || j >= s->N) return fail(KRPS_EINVAL, "j out of range");
+  if (s->N > 5) return fail(KRPS_EUNSUPPORTED, "range finder supports at most 5 modes");
+  if (ws == nullptr) return fail(KRPS_EINVAL, "workspace is NULL");
+  SolvePlan pl = plan_solve(s, 1);
+  if (ws_bytes < pl.total) return fail(KRPS_EWORKSPACE, "workspace too small");
+  char* w = (char*)ws;
+  hipError_t e = launch_range_finder(s->ctx->stream, s->prec, t->cols[j], t->vals[j], t->nu, s->N,
+                                     j, s->R, seed, s->I[j], (double*)(w + pl.lay.Y), s->U[j]);
+  if (e != hipSuccess) return hip_fail(e, "range finder");
+  return krps_normalize_factor(s, j, sigma, ws, ws_bytes);
 }
 
 krps_status krps_fit(krps_sampler s, krps_tensor t, const double* sigma, double* fit, void* ws,

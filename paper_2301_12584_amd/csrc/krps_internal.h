@@ -66,7 +66,8 @@ struct DescentArgs {
   int N, R, exclude, nsteps;      // nsteps: number of drawn modes
   int order[KRPS_MAX_MODES];      // drawn modes in increasing order
   int64_t J;
-  const double* u01;              // [J][N][2]
+  const double* u01;              // [J][N][2], or null: generated from seed / ctr_base
+  uint64_t seed, ctr_base;        // in-kernel uniforms (Philox4x64-10)
   int32_t* idx;                   // [J][N]
   double* prob;                   // [J] or null
   void* rows;                     // [J][R] or null (factor type)
@@ -203,6 +204,11 @@ hipError_t build_fiber_index(hipStream_t st, int N, const int64_t* dims, int64_t
                              double* vals, int64_t* off, uint32_t* k0, uint32_t* k1, uint32_t* p0,
                              uint32_t* p1, void* temp, size_t temp_bytes, int64_t* nu);
 hipError_t launch_norm2(hipStream_t st, const double* vals, int64_t n, double* out);
+// U_j = mat(T, j) S (range finder), accumulated in float64 Y (I x R) and
+// stored to U in the factor type.
+hipError_t launch_range_finder(hipStream_t st, krps_precision p, const int32_t* cols,
+                               const double* vals, int64_t nu, int N, int j, int R, uint64_t seed,
+                               int64_t I, double* Y, void* U);
 size_t hot_temp_bytes(int64_t dim);
 hipError_t build_hot_rows(hipStream_t st, const int32_t* col, int64_t n, int64_t dim, int nhot,
                           uint32_t* c0, uint32_t* c1, uint32_t* i0, uint32_t* i1, void* temp,

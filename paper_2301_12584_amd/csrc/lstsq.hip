@@ -1008,3 +1008,81 @@ hipError_t launch_ls_solve(hipStream_t st, const double* SA, const double* SBw, 
 }
 
 }  // namespace krps
+
+// ------------------------------------------------- range-finder initialisation
+//
+// U_j = mat(T, j) S with a Gaussian sketch S that is generated, never
+// stored, for the fibers that hold entries (the initialisation the paper
+// uses for its sparsest tensor, Section 4.3).  Row of S for a fiber with
+// other-mode indices (i_a, i_b, i_c, i_d) (increasing mode order, missing
+// ones 0), column pair q: Philox4x64-10 (Salmon et al., SC'11) of counter
+// (i_a | i_b << 32, i_c | i_d << 32, q, 0) under key (seed, j); the first
+// two output words give open-interval uniforms ((x >> 11) + 0.5) 2^-53 and
+// Box-Muller gives columns 2q (cosine) and 2q + 1 (sine).
+
+namespace krps {
+
+namespace {
+
+// Entry z of column r of the sketch row (w0, w1).
+__device__ __forceinline__ double sketch_entry(uint64_t w0, uint64_t w1, int r, uint64_t seed,
+                                               int j) {
+  uint64_t c[4] = {w0, w1, (uint64_t)(r >> 1), 0};
+  philox4x64_10(c, seed, (uint64_t)j);
+  const double u1 = u01_of_word(c[0]);
+  const double u2 = u01_of_word(c[1]);
+  const double rad = sqrt(-2.0 * log(u1));
+  const double ang = 2.0 * M_PI * u2;
+  return (r & 1) ? rad * sin(ang) : rad * cos(ang);
+}
+
+// Y[i_j(e), r] += x_e S[fiber(e), r]: one wavefront per stored entry at a
+// time, lanes over the columns (r and r + 64).
+__global__ __launch_bounds__(256) void range_finder_kernel(const int32_t* __restrict__ cols,
+                                                           const double* __restrict__ vals,
+                                                           int64_t nu, int N, int j, int R,
+                                                           uint64_t seed, double* __restrict__ Y) {
+  const int lane = threadIdx.x & 63;
+  const int64_t nw = ((int64_t)gridDim.x * blockDim.x) >> 6;
+  for (int64_t e = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6; e < nu; e += nw) {
+    uint64_t w[4] = {0, 0, 0, 0};
+    int m = 0;
+    for (int k = 0; k < N; ++k)
+      if (k != j) w[m++] = (uint64_t)(uint32_t)cols[(int64_t)k * nu + e];
+    const uint64_t w0 = w[0] | (w[1] << 32), w1 = w[2] | (w[3] << 32);
+    const int64_t i = cols[(int64_t)j * nu + e];
+    const double x = vals[e];
+    if (lane < R) atomicAdd(&Y[i * R + lane], x * sketch_entry(w0, w1, lane, seed, j));
+    if (lane + 64 < R)
+      atomicAdd(&Y[i * R + lane + 64], x * sketch_entry(w0, w1, lane + 64, seed, j));
+  }
+}
+
+template <typename T>
+__global__ void store_factor_kernel(const double* __restrict__ Y, T* __restrict__ U, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    U[i] = (T)Y[i];
+}
+
+}  // namespace
+
+hipError_t launch_range_finder(hipStream_t st, krps_precision p, const int32_t* cols,
+                               const double* vals, int64_t nu, int N, int j, int R, uint64_t seed,
+                               int64_t I, double* Y, void* U) {
+  hipError_t e = launch_fill_f64(st, Y, I * R);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(range_finder_kernel, dim3(4096), dim3(256), 0, st, cols, vals, nu, N, j, R,
+                     seed, Y);
+  int64_t blocks = (I * R + 255) / 256;
+  if (blocks > 8192) blocks = 8192;
+  if (p == KRPS_FP64)
+    hipLaunchKernelGGL(store_factor_kernel<double>, dim3((unsigned)blocks), dim3(256), 0, st, Y,
+                       (double*)U, I * R);
+  else
+    hipLaunchKernelGGL(store_factor_kernel<float>, dim3((unsigned)blocks), dim3(256), 0, st, Y,
+                       (float*)U, I * R);
+  return hipGetLastError();
+}
+
+}  // namespace krps

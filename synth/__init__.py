@@ -122,17 +122,20 @@ def zipf_indices(rng, n, dim, alpha, chunk=1 << 24):
     return out
 
 
-def sparse_tensor(dims, nnz, alpha, seed, sigma=1.0):
+def sparse_tensor(dims, nnz, alpha, seed, sigma=1.0, progress=None):
     """Synthetic sparse tensor: COO ``(idx int32 [nnz][N], val float32 [nnz])``.
 
     Indices per mode are truncated Zipf(alpha) (see :func:`zipf_indices`),
-    values lognormal(0, sigma).  Duplicates are kept.
+    values lognormal(0, sigma).  Duplicates are kept.  ``progress(j)`` is
+    called after each mode's indices (the draws do not depend on it).
     """
     rng = np.random.Generator(np.random.PCG64(seed))
     N = len(dims)
     idx = np.empty((int(nnz), N), dtype=np.int32)
     for j, d in enumerate(dims):
         idx[:, j] = zipf_indices(rng, nnz, d, alpha)
+        if progress is not None:
+            progress(j)
     val = rng.lognormal(0.0, sigma, size=int(nnz)).astype(np.float32)
     return idx, val
 
@@ -172,7 +175,7 @@ CONFIGS = {
 }
 
 
-def als_problem(config_no, nnz=None):
+def als_problem(config_no, nnz=None, progress=None):
     """Inputs of a sketched CP-ALS workload: ``(dims, idx, val, U0, R, J,
     sweeps, useed)`` with the COO tensor, the N(0,1) initial factors and
     the uniform seed (pass it to :func:`sweep_uniforms`).  ``nnz`` overrides
@@ -180,7 +183,7 @@ def als_problem(config_no, nnz=None):
     cfg = CONFIGS[int(config_no)]
     dims = cfg["dims"]
     n = cfg["nnz"] if nnz is None else int(nnz)
-    idx, val = sparse_tensor(dims, n, cfg["alpha"], config_seed(config_no))
+    idx, val = sparse_tensor(dims, n, cfg["alpha"], config_seed(config_no), progress=progress)
     U0 = gaussian_factors(dims, cfg["R"], config_seed(config_no) + 100)
     return dims, idx, val, U0, cfg["R"], cfg["J"], cfg["sweeps"], uniform_seed(config_no)
 

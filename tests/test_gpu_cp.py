@@ -289,3 +289,29 @@ def test_generic_sketched_lstsq_matches_oracle(env, prec):
     exact = np.linalg.lstsq(A.astype(np.float64), B.astype(np.float64), rcond=None)[0]
     res = np.linalg.norm(A @ X - B) / np.linalg.norm(A @ exact - B)
     assert res < 1.05, res
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("R", [8, 70])
+def test_range_finder_init_matches_oracle(env, prec, R):
+    """U_j = mat(T, j) S with the generated sketch, normalised: against the
+    oracle's sketch (same Philox counters) on a Zipf tensor with duplicates."""
+    from oracle import sketch as osk
+    krps, torch, ctx = env
+    dims = (300, 200, 100)
+    idx, val = synth.sparse_tensor(dims, 20_000, 1.2, seed=71)
+    Us = synth.gaussian_factors(dims, R, seed=72)
+    S, T, A = make(krps, torch, ctx, dims, idx, val, Us, prec, 256)
+    Tor = ocp.SparseTensor(dims, idx, val)
+    for j in range(3):
+        A.init_range_finder(j, seed=12345)
+        torch.cuda.synchronize()
+        got = S.factors[j].cpu().numpy().astype(np.float64)
+        sig = A.sigma.cpu().numpy()
+        ref, rsig = ocp.normalize_columns(osk.range_finder(Tor, j, R, 12345))
+        # float32 storage: the factor is rounded before its norms are taken
+        tol = 1e-10 if prec == "fp64" else 1e-6
+        np.testing.assert_allclose(sig, rsig, rtol=tol)
+        np.testing.assert_allclose(got, ref, rtol=tol, atol=tol * np.abs(ref).max())
+        # the tree was rebuilt: its root is the Gram of the new factor
+        np.testing.assert_allclose(S.gram(j).cpu().numpy(), got.T @ got, rtol=1e-6, atol=1e-6)

@@ -249,3 +249,37 @@ def test_autotune_measures_then_reads_the_cache(tmp_path):
     same = (i0 == i1).all(dim=1).cpu().numpy()
     assert same.mean() >= 0.999, same.mean()
     np.testing.assert_allclose(p1.cpu().numpy()[same], p0.cpu().numpy()[same], rtol=1e-5)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_in_kernel_uniforms_match_the_oracle(prec):
+    """Uniforms generated in the walk from (seed, ctr_base) equal the
+    oracle's Philox4x64-10 uniforms: the draws match index for index
+    (margin rule), and a disjoint counter range gives other draws."""
+    import torch
+    import paper_2301_12584_amd as krps
+    from oracle import sketch as osk
+    ctx = krps.Context(0)
+    dims, R, J = (5000, 3000, 2000), 16, 4096
+    Us = synth.gaussian_factors(dims, R, seed=81, heavy_rows_frac=0.01)
+    dt = torch.float64 if prec == "fp64" else torch.float32
+    S = krps.Sampler(ctx, [torch.from_numpy(U).to(ctx.device).to(dt).contiguous() for U in Us],
+                     precision=prec)
+    first = None
+    for exclude in (-1, 1):
+        idx, p = S.sample_seeded(exclude, J, seed=2026, ctr_base=1000)
+        if first is None:
+            first = idx
+        torch.cuda.synchronize()
+        u = osk.philox_uniforms(J, 3, 2026, 1000)
+        dr = osmp.KRPSampler(Us, store=None if prec == "fp64" else np.float32).draw(exclude, u)
+        got = idx.cpu().numpy().astype(np.int64)
+        same = (got == dr.idx).all(axis=1)
+        assert np.all(same | (dr.margin <= 1e-6)), np.sum(~same)
+        # the same uniforms through the buffer path give the same draws
+        i2, p2, _ = S.sample(exclude, torch.from_numpy(u).to(ctx.device))
+        torch.cuda.synchronize()
+        assert torch.equal(i2, idx) and torch.equal(p2, p)
+    other, _ = S.sample_seeded(-1, J, seed=2026, ctr_base=1000 + J)
+    torch.cuda.synchronize()
+    assert (other != first).any(dim=1).float().mean().item() > 0.5
