@@ -293,7 +293,13 @@ def run_als(torch, krps, ctx, precs, nnz, sweeps_arg, seeds, config=3, init="gau
                "samples_per_s_in_sweep": N * J / (float(np.mean(ms)) / 1e3)}
         if ref is not None and len(ref) == len(fits):
             rec["oracle_fits"] = ref
-            rec["max_abs_fit_diff"] = float(np.max(np.abs(np.array(fits) - np.array(ref))))
+            diff = np.abs(np.array(fits) - np.array(ref))
+            rec["max_abs_fit_diff"] = float(diff.max())
+            # the first sweeps from a random start are ill-conditioned: the
+            # split path and the float32-stored oracle take different early
+            # paths to the same fit
+            rec["max_abs_fit_diff_from_sweep2"] = float(diff[2:].max()) if len(diff) > 2 else None
+            rec["fit_diff_last"] = float(diff[-1])
         out[prec] = rec
         print(f"# als {prec}: sweep {rec['sweep_ms_mean']:.3f} ms, fits {np.round(fits, 6)}",
               file=sys.stderr, flush=True)

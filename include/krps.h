@@ -238,6 +238,11 @@ krps_status krps_tensor_destroy(krps_tensor t);
 krps_status krps_tensor_norm2(krps_tensor t, double* out);
 /* Number of stored entries: distinct coordinates after merging duplicates. */
 krps_status krps_tensor_stored_entries(krps_tensor t, int64_t* out);
+/* The rows of mode j that the SpMM accumulates per workgroup: the
+ * min(32, dims[j]) rows with the most stored entries (ties broken either
+ * way), written to rows (host, room for 32 values), their number to *n.
+ * Copies from the device on the context's stream and waits for it. */
+krps_status krps_tensor_hot_rows(krps_tensor t, int j, int32_t* rows, int* n);
 
 /* Bytes of scratch for one sketched solve / sweep / fit with J samples. */
 krps_status krps_solve_workspace_bytes(krps_sampler s, krps_tensor t, int64_t J, size_t* bytes);
@@ -354,8 +359,13 @@ typedef struct {
   size_t rows;     /* [J][R] w_d a_d (rows of S A): float64, float32 for KRPS_BF16X2 */
   size_t M;        /* float64 [R][R] (S A)^T S A */
   size_t Mp;       /* float64 [R][R] its pseudo-inverse */
-  size_t Y;        /* float64 [I_j][R] (S B)^T S A */
+  size_t Y;        /* float64 [I_j][R] (S B)^T S A: only the rows listed at
+                      yrows are written by the solve; every other row of
+                      (S B)^T S A is zero and its slot in Y is left as it was */
   size_t draw;     /* per-draw scratch (krps_draw_layout offsets are relative to this) */
+  size_t yrows;    /* int32 [*nyrows] rows of mode j that the sampled fibers'
+                      entries reach, increasing */
+  size_t nyrows;   /* int64: their count */
 } krps_solve_layout;
 
 krps_status krps_solve_layout_query(krps_sampler s, krps_tensor t, int64_t J,

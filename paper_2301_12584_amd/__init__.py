@@ -48,7 +48,8 @@ class Tune(ctypes.Structure):
 
 
 class SolveLayout(ctypes.Structure):
-    _fields_ = [(n, ctypes.c_size_t) for n in ("idx", "prob", "w", "rows", "M", "Mp", "Y", "draw")]
+    _fields_ = [(n, ctypes.c_size_t) for n in ("idx", "prob", "w", "rows", "M", "Mp", "Y", "draw",
+                                               "yrows", "nyrows")]
 
 
 def declared_symbols():
@@ -109,6 +110,7 @@ def lib():
         "krps_sketched_lstsq": (c.c_int, [P, c.c_int, c.c_int64, P, P, c.c_int64, P, P, c.c_int,
                                           P, c.c_size_t]),
         "krps_tensor_stored_entries": (c.c_int, [P, c.POINTER(c.c_int64)]),
+        "krps_tensor_hot_rows": (c.c_int, [P, c.c_int, c.POINTER(c.c_int32), c.POINTER(c.c_int)]),
         "krps_solve_workspace_bytes": (c.c_int, [P, P, c.c_int64, c.POINTER(c.c_size_t)]),
         "krps_solve_layout_query": (c.c_int, [P, P, c.c_int64, c.POINTER(SolveLayout)]),
         "krps_normalize_factor": (c.c_int, [P, c.c_int, P, P, c.c_size_t]),
@@ -443,6 +445,13 @@ class Tensor:
         check(lib().krps_tensor_stored_entries(self.handle, ctypes.byref(v)))
         return v.value
 
+    def hot_rows(self, j):
+        """Rows of mode ``j`` with the most stored entries (host int list)."""
+        buf = (ctypes.c_int32 * 32)()
+        n = ctypes.c_int()
+        check(lib().krps_tensor_hot_rows(self.handle, int(j), buf, ctypes.byref(n)))
+        return [int(buf[i]) for i in range(n.value)]
+
     def __del__(self):
         if getattr(self, "handle", None) is not None and _lib is not None:
             _lib.krps_tensor_destroy(self.handle)
@@ -512,5 +521,23 @@ class CPALS:
                      else view(l.rows, J * R, torch.float64, 8)).view(J, R).clone(),
             "M": view(l.M, R * R, torch.float64, 8).view(R, R).clone(),
             "Mp": view(l.Mp, R * R, torch.float64, 8).view(R, R).clone(),
-            "Y": view(l.Y, self.S.dims[j] * R, torch.float64, 8).view(self.S.dims[j], R).clone(),
+            "Y": self._y(j),
+            "yrows": self._yrows(),
         }
+
+    def _yrows(self):
+        l, ws = self.layout, self.ws
+        n = int(ws[l.nyrows:l.nyrows + 8].view(self.S.ctx.torch.int64).item())
+        return ws[l.yrows:l.yrows + 4 * n].view(self.S.ctx.torch.int32).clone()
+
+    def _y(self, j):
+        """(S B)^T S A of the last solve: the listed rows from the workspace,
+        zero elsewhere."""
+        torch = self.S.ctx.torch
+        l, R, ws = self.layout, self.S.R, self.ws
+        I = self.S.dims[j]
+        full = ws[l.Y:l.Y + I * R * 8].view(torch.float64).view(I, R)
+        rows = self._yrows().long()
+        Y = torch.zeros_like(full)
+        Y[rows] = full[rows]
+        return Y

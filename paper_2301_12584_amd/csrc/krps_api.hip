@@ -323,7 +323,7 @@ TensorPlan plan_tensor(int N, const int64_t* dims, int64_t nnz) {
 struct SolvePlan {
   krps_solve_layout lay;
   size_t lo, hi, cnt, start, rank, partial, gscratch, gscratch_bytes, fitp, fitout, sig;
-  size_t coef, slot, hkey, hW, hrep, rflag, rpos, rep, rstart, bsum;
+  size_t coef, slot, hkey, hW, hrep, rflag, rpos, rep, rstart, bsum, ymark, ybsum;
   int64_t H;
   int hbits;
   size_t total;
@@ -389,6 +389,14 @@ SolvePlan plan_solve(krps_sampler s, int64_t J) {
   off += 256;
   l.Y = off;
   off += align_up((size_t)Imax * R * 8);
+  l.yrows = off;
+  off += align_up((size_t)Imax * 4);
+  l.nyrows = off;
+  off += 256;
+  pl.ymark = off;
+  off += align_up((size_t)Imax * 4);
+  pl.ybsum = off;
+  off += align_up(row_bsum_bytes(Imax));
   pl.partial = off;
   off += align_up(solve_partial_bytes(R));
   TreeShape tm;
@@ -447,8 +455,6 @@ krps_status enqueue_solve(krps_sampler s, krps_tensor t, int j, int64_t J, const
   if (e != hipSuccess) return hip_fail(e, "Gram of sampled rows");
   e = launch_pinv(st, R, (double*)(w + l.M), (double*)(w + l.Mp), (int32_t*)(w + pl.rank));
   if (e != hipSuccess) return hip_fail(e, "pseudo-inverse");
-  e = launch_fill_f64(st, (double*)(w + l.Y), s->I[j] * R);
-  if (e != hipSuccess) return hip_fail(e, "Y clear");
   FiberArgs fa;
   fa.N = N;
   fa.j = j;
@@ -482,10 +488,17 @@ krps_status enqueue_solve(krps_sampler s, krps_tensor t, int j, int64_t J, const
   fa.nhot = (int)std::min<int64_t>(t->nhot, t->dims[j]);
   e = launch_lookup(st, fa);
   if (e != hipSuccess) return hip_fail(e, "fiber lookup");
+  // only the rows of Y that the entries reach are cleared, summed into and
+  // multiplied by M^+
+  int32_t* yrows = (int32_t*)(w + l.yrows);
+  int64_t* nyrows = (int64_t*)(w + l.nyrows);
+  e = launch_rows(st, fa, s->I[j], (int32_t*)(w + pl.ymark), (int64_t*)(w + pl.ybsum), yrows,
+                  nyrows, (double*)(w + l.Y));
+  if (e != hipSuccess) return hip_fail(e, "rows of Y");
   e = launch_spmm(st, split ? KRPS_BF16X2 : KRPS_FP64, fa, w + l.rows, w + l.Y);
   if (e != hipSuccess) return hip_fail(e, "SpMM");
-  e = launch_solve_gemm(st, s->prec, w + l.Y, (const double*)(w + l.Mp), s->U[j], s->I[j], R,
-                        (double*)(w + pl.partial), sigma);
+  e = launch_solve_gemm(st, s->prec, w + l.Y, (const double*)(w + l.Mp), s->U[j], s->I[j], yrows,
+                        nyrows, R, (double*)(w + pl.partial), sigma);
   if (e != hipSuccess) return hip_fail(e, "solve GEMM");
   return build_tree(s, j);
 }
@@ -1112,6 +1125,18 @@ krps_status krps_tensor_stored_entries(krps_tensor t, int64_t* out) {
   return KRPS_OK;
 }
 
+krps_status krps_tensor_hot_rows(krps_tensor t, int j, int32_t* rows, int* n) {
+  if (t == nullptr || rows == nullptr || n == nullptr) return fail(KRPS_EINVAL, "NULL argument");
+  if (j < 0 || j >= t->N) return fail(KRPS_EINVAL, "j out of range");
+  const int nh = (int)std::min<int64_t>(t->nhot, t->dims[j]);
+  KRPS_HIP(hipSetDevice(t->ctx->device));
+  KRPS_HIP(hipMemcpyAsync(rows, t->hot_rows[j], (size_t)nh * 4, hipMemcpyDeviceToHost,
+                          t->ctx->stream));
+  KRPS_HIP(hipStreamSynchronize(t->ctx->stream));
+  *n = nh;
+  return KRPS_OK;
+}
+
 krps_status krps_tensor_norm2(krps_tensor t, double* out) {
   if (t == nullptr || out == nullptr) return fail(KRPS_EINVAL, "tensor/out is NULL");
   *out = t->norm2;
@@ -1228,6 +1253,8 @@ krps_status krps_als_sweep(krps_sampler s, krps_tensor t, int64_t J, const doubl
   return KRPS_OK;
 }
 
+}  // extern "C"
+
 namespace {
 
 struct LsPlan {
@@ -1261,6 +1288,8 @@ LsPlan plan_lstsq(int R, int64_t J, int64_t n) {
 }
 
 }  // namespace
+
+extern "C" {
 
 krps_status krps_lstsq_workspace_bytes(int R, int64_t J, int64_t n, size_t* bytes) {
   if (R < 1 || R > KRPS_MAX_R) return fail(KRPS_EINVAL, "R outside [1, 128]");
@@ -1300,6 +1329,8 @@ krps_status krps_sketched_lstsq(krps_ctx ctx, int R, int64_t J, const void* rows
   if (e != hipSuccess) return hip_fail(e, "solve");
   return KRPS_OK;
 }
+
+}  // extern "C"
 
 namespace {
 
@@ -1374,6 +1405,8 @@ void tune_store(const char* path, const std::string& key, const krps_tune& t) {
 }
 
 }  // namespace
+
+extern "C" {
 
 krps_status krps_autotune_workspace_bytes(int N, const int64_t* I, int R, krps_precision p,
                                           int64_t J, size_t* bytes) {

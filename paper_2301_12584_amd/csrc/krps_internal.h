@@ -216,6 +216,12 @@ hipError_t build_hot_rows(hipStream_t st, const int32_t* col, int64_t n, int64_t
 hipError_t launch_lookup(hipStream_t st, const FiberArgs& a);
 hipError_t launch_spmm(hipStream_t st, krps_precision p, const FiberArgs& a, const void* rows,
                        void* Y);
+// Rows of Y that the sampled fibers reach: cleared marks over I rows, then
+// mark, count per tile, scan, compacted increasing list, *count, and those
+// rows of Y set to zero (the rest of Y is left as it was).
+size_t row_bsum_bytes(int64_t I);
+hipError_t launch_rows(hipStream_t st, const FiberArgs& a, int64_t I, int32_t* mark, int64_t* bsum,
+                       int32_t* list, int64_t* count, double* Y);
 size_t solve_partial_bytes(int R);
 // Generic sketched least squares (scaled rows, Z = (SA)^T S B, X = M^+ Z).
 size_t lstsq_partial_bytes(int R, int64_t n);
@@ -227,7 +233,8 @@ hipError_t launch_ls_solve(hipStream_t st, const double* SA, const double* SBw, 
 hipError_t launch_fill(hipStream_t st, krps_precision p, void* ptr, int64_t n);
 hipError_t launch_fill_f64(hipStream_t st, double* ptr, int64_t n);
 hipError_t launch_solve_gemm(hipStream_t st, krps_precision p, const void* Y, const double* Mp,
-                             void* U, int64_t I, int R, double* partial, double* sigma);
+                             void* U, int64_t I, const int32_t* list, const int64_t* count, int R,
+                             double* partial, double* sigma);
 hipError_t launch_colnorm(hipStream_t st, krps_precision p, const void* U, int64_t I, int R,
                           double* partial, double* sigma);
 hipError_t launch_normalize(hipStream_t st, krps_precision p, void* U, int64_t I, int R,

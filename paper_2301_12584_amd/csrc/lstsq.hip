@@ -41,6 +41,12 @@ namespace {
 
 constexpr int CH = 64;  // fiber entries per SpMM work item (one per lane)
 
+__global__ void fill_u32_kernel(uint32_t* __restrict__ p, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = 0u;
+}
+
 __global__ void iota_kernel(uint32_t* __restrict__ p, int64_t n) {
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
        i += (int64_t)gridDim.x * blockDim.x)
@@ -215,11 +221,44 @@ hipError_t launch_norm2(hipStream_t st, const double* vals, int64_t n, double* o
 
 namespace {
 
-__global__ void hot_count_kernel(const int32_t* __restrict__ col, int64_t n,
-                                 uint32_t* __restrict__ count) {
+// Entries per row.  A power-law mode sends a large share of all entries to
+// a handful of rows, so each workgroup first counts in a small LDS hash
+// table (the popular rows arrive early and take its slots) and falls back to
+// global atomics for rows it finds no slot for; the table is added to the
+// global counts at the end.
+constexpr int HC_SLOTS = 2048, HC_PROBES = 8;
+
+__global__ __launch_bounds__(256) void hot_count_kernel(const int32_t* __restrict__ col, int64_t n,
+                                                        uint32_t* __restrict__ count) {
+  __shared__ int32_t key[HC_SLOTS];
+  __shared__ uint32_t cnt[HC_SLOTS];
+  for (int q = threadIdx.x; q < HC_SLOTS; q += blockDim.x) {
+    key[q] = -1;
+    cnt[q] = 0;
+  }
+  __syncthreads();
   for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n;
-       e += (int64_t)gridDim.x * blockDim.x)
-    atomicAdd(&count[col[e]], 1u);
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int32_t v = col[e];
+    uint32_t h = (uint32_t)v * 2654435761u;
+    bool done = false;
+    for (int p = 0; p < HC_PROBES && !done; ++p) {
+      const int q = (int)((h >> 21) + p) & (HC_SLOTS - 1);
+      int32_t k = key[q];
+      if (k == -1) {
+        const int32_t old = atomicCAS(&key[q], -1, v);
+        k = old == -1 ? v : old;
+      }
+      if (k == v) {
+        atomicAdd(&cnt[q], 1u);
+        done = true;
+      }
+    }
+    if (!done) atomicAdd(&count[v], 1u);
+  }
+  __syncthreads();
+  for (int q = threadIdx.x; q < HC_SLOTS; q += blockDim.x)
+    if (cnt[q] != 0) atomicAdd(&count[key[q]], cnt[q]);
 }
 
 __global__ void hot_clear_kernel(uint32_t* __restrict__ count, uint32_t* __restrict__ index,
@@ -555,6 +594,78 @@ __global__ __launch_bounds__(256) void spmm_kernel(FiberArgs a, const T* __restr
   }
 }
 
+// The rows of mode j that the sampled fibers' entries reach: mark[i] = 1.
+// Traverses the compacted work items as the SpMM does, one item per
+// wavefront (lane t takes the item's entry t).
+constexpr int MARK_IPW = 8;
+
+__global__ __launch_bounds__(256) void mark_rows_kernel(FiberArgs a, int32_t* __restrict__ mark) {
+  const int lane = threadIdx.x & 63;
+  const int64_t nrep = a.rpos[a.J];
+  const int64_t total = a.rstart[nrep];
+  const int64_t nw = (int64_t)gridDim.x * (blockDim.x >> 6);
+  const int32_t* __restrict__ ij = a.cols + (int64_t)a.j * a.nnz;
+  for (int64_t c0 = ((int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6)) * MARK_IPW;
+       c0 < total; c0 += nw * MARK_IPW) {
+    int64_t l = 0, r = nrep;  // last k with rstart[k] <= c0
+    while (r - l > 1) {
+      const int64_t m = (l + r) >> 1;
+      if (a.rstart[m] <= c0) l = m; else r = m;
+    }
+    int64_t k = l;
+    const int64_t c1 = c0 + MARK_IPW < total ? c0 + MARK_IPW : total;
+    for (int64_t c = c0; c < c1; ++c) {
+      while (k + 1 < nrep && a.rstart[k + 1] <= c) ++k;
+      const int64_t d = a.rep[k];
+      const int64_t e = a.lo[d] + (c - a.rstart[k]) * CH + lane;
+      if (e < a.hi[d] && lane < CH) mark[ij[e]] = 1;
+    }
+  }
+}
+
+// Marked rows per tile of SCAN_TILE rows.
+__global__ __launch_bounds__(SCAN_TILE) void mark_count_kernel(const int32_t* __restrict__ mark,
+                                                               int64_t n,
+                                                               int64_t* __restrict__ bsum) {
+  const int64_t i = (int64_t)blockIdx.x * SCAN_TILE + threadIdx.x;
+  const int c = __syncthreads_count(i < n && mark[i] != 0);
+  if (threadIdx.x == 0) bsum[blockIdx.x] = c;
+}
+
+// list[bsum[tile] + rank within the tile] = i for every marked row i (rows
+// in increasing order); block 0 also copies the total to *count.
+__global__ __launch_bounds__(SCAN_TILE) void mark_compact_kernel(const int32_t* __restrict__ mark,
+                                                                 int64_t n, int64_t nb,
+                                                                 const int64_t* __restrict__ bsum,
+                                                                 int32_t* __restrict__ list,
+                                                                 int64_t* __restrict__ count) {
+  __shared__ int wsum[SCAN_TILE / 64];
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  const int64_t i = (int64_t)blockIdx.x * SCAN_TILE + t;
+  const bool f = i < n && mark[i] != 0;
+  const uint64_t b = __ballot(f);
+  const int pre = __popcll(b & ((uint64_t(1) << lane) - 1));
+  if (lane == 0) wsum[wave] = __popcll(b);
+  __syncthreads();
+  int off = 0;
+  for (int q = 0; q < wave; ++q) off += wsum[q];
+  if (f) list[bsum[blockIdx.x] + off + pre] = (int32_t)i;
+  if (blockIdx.x == 0 && t == 0) *count = bsum[nb];
+}
+
+// Y[list[p], :] = 0 for p < *count; a wavefront per row.
+__global__ __launch_bounds__(256) void zero_rows_kernel(double* __restrict__ Y, int R,
+                                                        const int32_t* __restrict__ list,
+                                                        const int64_t* __restrict__ count) {
+  const int lane = threadIdx.x & 63;
+  const int64_t n = *count;
+  const int64_t nw = (int64_t)gridDim.x * (blockDim.x >> 6);
+  for (int64_t p = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); p < n; p += nw) {
+    double* y = Y + (int64_t)list[p] * R;
+    for (int c = lane; c < R; c += 64) y[c] = 0.0;
+  }
+}
+
 }  // namespace
 
 hipError_t launch_lookup(hipStream_t st, const FiberArgs& a) {
@@ -572,6 +683,22 @@ hipError_t launch_lookup(hipStream_t st, const FiberArgs& a) {
   int64_t cb = (a.J + 1 + 255) / 256;
   if (cb > 4096) cb = 4096;
   hipLaunchKernelGGL(compact_kernel, dim3((unsigned)cb), dim3(256), 0, st, a);
+  return hipGetLastError();
+}
+
+size_t row_bsum_bytes(int64_t I) { return (size_t)((I + SCAN_TILE - 1) / SCAN_TILE + 2) * 8; }
+
+hipError_t launch_rows(hipStream_t st, const FiberArgs& a, int64_t I, int32_t* mark, int64_t* bsum,
+                       int32_t* list, int64_t* count, double* Y) {
+  const int64_t nb = I > 0 ? (I + SCAN_TILE - 1) / SCAN_TILE : 1;
+  hipLaunchKernelGGL(fill_u32_kernel, dim3((unsigned)std::min<int64_t>(nb * 4, 8192)), dim3(256), 0,
+                     st, (uint32_t*)mark, I);
+  hipLaunchKernelGGL(mark_rows_kernel, dim3(2048), dim3(256), 0, st, a, mark);
+  hipLaunchKernelGGL(mark_count_kernel, dim3((unsigned)nb), dim3(SCAN_TILE), 0, st, mark, I, bsum);
+  hipLaunchKernelGGL(scan_bsum_kernel, dim3(1), dim3(1024), 0, st, bsum, nb);
+  hipLaunchKernelGGL(mark_compact_kernel, dim3((unsigned)nb), dim3(SCAN_TILE), 0, st, mark, I, nb,
+                     bsum, list, count);
+  hipLaunchKernelGGL(zero_rows_kernel, dim3(2048), dim3(256), 0, st, Y, a.R, list, count);
   return hipGetLastError();
 }
 
@@ -598,7 +725,9 @@ __global__ void fill_kernel(T* __restrict__ p, int64_t n, T v) {
     p[i] = v;
 }
 
-// Y M^+ for a persistent sweep of 64-row tiles.  The block's 256 threads
+// Y M^+ over the rows list[0 .. *count) (the rows of Y that the SpMM can
+// reach; every other row of Y M^+ is zero), a persistent sweep of 64-row
+// tiles.  The block's 256 threads
 // are 16 row groups x 16 column groups; a thread accumulates 4 rows x
 // RC/16 columns (columns tc + 16 j) in float64 registers, with K taken in
 // chunks of 32 through LDS (Y tile [64][33], M^+ chunk [32][RC]).
@@ -611,10 +740,13 @@ constexpr int GT_ROWS = 64, GT_KC = 32;
 template <typename T, int RC>
 __global__ __launch_bounds__(256) void gemm_colsum_kernel(const double* __restrict__ Y,
                                                           const double* __restrict__ Mp,
-                                                          T* __restrict__ out, int64_t I, int R,
+                                                          T* __restrict__ out,
+                                                          const int32_t* __restrict__ list,
+                                                          const int64_t* __restrict__ count, int R,
                                                           double* __restrict__ partial,
                                                           const double* __restrict__ sigma) {
   constexpr int TCW = RC / 16;
+  __shared__ int64_t rix[GT_ROWS];  // row of Y per tile row, -1 past the end
   __shared__ double Ys[GT_ROWS][GT_KC + 1];
   __shared__ double Ms[GT_KC][RC];
   __shared__ double red[16][RC];
@@ -627,9 +759,14 @@ __global__ __launch_bounds__(256) void gemm_colsum_kernel(const double* __restri
     inv[j] = (sigma != nullptr && c < R && sigma[c] > 0) ? 1.0 / sigma[c] : 0.0;
     sq[j] = 0.0;
   }
-  const int64_t ntile = (I + GT_ROWS - 1) / GT_ROWS;
+  const int64_t nrow = *count;
+  const int64_t ntile = (nrow + GT_ROWS - 1) / GT_ROWS;
   for (int64_t tile = blockIdx.x; tile < ntile; tile += gridDim.x) {
-    const int64_t r0 = tile * GT_ROWS;
+    __syncthreads();
+    if (threadIdx.x < GT_ROWS) {
+      const int64_t p = tile * GT_ROWS + threadIdx.x;
+      rix[threadIdx.x] = p < nrow ? (int64_t)list[p] : -1;
+    }
     double acc[4][TCW];
 #pragma unroll
     for (int i = 0; i < 4; ++i)
@@ -639,8 +776,8 @@ __global__ __launch_bounds__(256) void gemm_colsum_kernel(const double* __restri
       __syncthreads();
       for (int e = threadIdx.x; e < GT_ROWS * GT_KC; e += 256) {
         const int i = e / GT_KC, kk = e % GT_KC;
-        const int64_t r = r0 + i;
-        Ys[i][kk] = (r < I && k0 + kk < R) ? Y[r * R + k0 + kk] : 0.0;
+        const int64_t r = rix[i];
+        Ys[i][kk] = (r >= 0 && k0 + kk < R) ? Y[r * R + k0 + kk] : 0.0;
       }
       for (int e = threadIdx.x; e < GT_KC * RC; e += 256) {
         const int kk = e / RC, c = e % RC;
@@ -662,8 +799,8 @@ __global__ __launch_bounds__(256) void gemm_colsum_kernel(const double* __restri
     }
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
-      const int64_t r = r0 + tr * 4 + i;
-      if (r >= I) continue;
+      const int64_t r = rix[tr * 4 + i];
+      if (r < 0) continue;
 #pragma unroll
       for (int j = 0; j < TCW; ++j) {
         const int c = tc + 16 * j;
@@ -763,29 +900,34 @@ hipError_t launch_fill_f64(hipStream_t st, double* ptr, int64_t n) {
 }
 
 template <typename T, int RC>
-static hipError_t run_gemm(hipStream_t st, const double* Y, const double* Mp, void* out, int64_t I,
-                           int R, double* partial, double* sigma) {
+static hipError_t run_gemm(hipStream_t st, const double* Y, const double* Mp, void* out,
+                           const int32_t* list, const int64_t* count, int R, double* partial,
+                           double* sigma) {
   hipLaunchKernelGGL((gemm_colsum_kernel<T, RC>), dim3(SOLVE_BLOCKS), dim3(256), 0, st, Y, Mp,
-                     (T*)out, I, R, partial, (const double*)nullptr);
+                     (T*)out, list, count, R, partial, (const double*)nullptr);
   hipLaunchKernelGGL(sigma_kernel, dim3(R), dim3(256), 0, st, partial, SOLVE_BLOCKS, R, sigma);
   hipLaunchKernelGGL((gemm_colsum_kernel<T, RC>), dim3(SOLVE_BLOCKS), dim3(256), 0, st, Y, Mp,
-                     (T*)out, I, R, partial, (const double*)sigma);
+                     (T*)out, list, count, R, partial, (const double*)sigma);
   return hipGetLastError();
 }
 
-// U = Y M^+ with its column norms sigma taken out: two passes over Y (norms,
-// then the normalised write) so that U is rounded once.
+// U = Y M^+ with its column norms sigma taken out: two passes over the
+// listed rows of Y (norms, then the normalised write) so that U is rounded
+// once; U is cleared first, since its other rows are zero.
 hipError_t launch_solve_gemm(hipStream_t st, krps_precision p, const void* Y, const double* Mp,
-                             void* U, int64_t I, int R, double* partial, double* sigma) {
+                             void* U, int64_t I, const int32_t* list, const int64_t* count, int R,
+                             double* partial, double* sigma) {
+  hipError_t e = launch_fill(st, p, U, I * R);
+  if (e != hipSuccess) return e;
   const double* Yd = (const double*)Y;
   if (p == KRPS_FP64) {
-    if (R <= 32) return run_gemm<double, 32>(st, Yd, Mp, U, I, R, partial, sigma);
-    if (R <= 64) return run_gemm<double, 64>(st, Yd, Mp, U, I, R, partial, sigma);
-    return run_gemm<double, 128>(st, Yd, Mp, U, I, R, partial, sigma);
+    if (R <= 32) return run_gemm<double, 32>(st, Yd, Mp, U, list, count, R, partial, sigma);
+    if (R <= 64) return run_gemm<double, 64>(st, Yd, Mp, U, list, count, R, partial, sigma);
+    return run_gemm<double, 128>(st, Yd, Mp, U, list, count, R, partial, sigma);
   }
-  if (R <= 32) return run_gemm<float, 32>(st, Yd, Mp, U, I, R, partial, sigma);
-  if (R <= 64) return run_gemm<float, 64>(st, Yd, Mp, U, I, R, partial, sigma);
-  return run_gemm<float, 128>(st, Yd, Mp, U, I, R, partial, sigma);
+  if (R <= 32) return run_gemm<float, 32>(st, Yd, Mp, U, list, count, R, partial, sigma);
+  if (R <= 64) return run_gemm<float, 64>(st, Yd, Mp, U, list, count, R, partial, sigma);
+  return run_gemm<float, 128>(st, Yd, Mp, U, list, count, R, partial, sigma);
 }
 
 hipError_t launch_colnorm(hipStream_t st, krps_precision p, const void* U, int64_t I, int R,
@@ -826,29 +968,33 @@ hipError_t launch_normalize(hipStream_t st, krps_precision p, void* U, int64_t I
 
 namespace {
 
-// <T, T~> partial sums: thread per stored entry, sum_r sigma_r prod_k U_k[i_k, r].
-template <typename T>
+// <T, T~> partial sums, sum_e v_e sum_r sigma_r prod_k U_k[i_k(e), r]: a team
+// of L lanes per stored entry, lane l taking columns l, l + L, ... so that each
+// factor row is read as contiguous runs across the team.  The sum over r is
+// linear, so every lane accumulates its own columns over all of its entries
+// and the block reduces once at the end.
+template <typename T, int L>
 __global__ __launch_bounds__(256) void fit_inner_kernel(FitArgs a, double* __restrict__ partial) {
   __shared__ double red[256];
   double acc = 0;
   const int R = a.R;
-  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < a.nnz;
-       e += (int64_t)gridDim.x * blockDim.x) {
-    double rowsum = 0;
-    for (int r0 = 0; r0 < R; r0 += 16) {
-      double pr[16];
+  const int lane = threadIdx.x % L;
+  const int64_t team = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / L;
+  const int64_t nteam = (int64_t)gridDim.x * blockDim.x / L;
+  for (int64_t e = team; e < a.nnz; e += nteam) {
+    int64_t row[KRPS_MAX_MODES];
 #pragma unroll
-      for (int q = 0; q < 16; ++q) pr[q] = r0 + q < R ? a.sigma[r0 + q] : 0.0;
-      for (int k = 0; k < a.N; ++k) {
-        const T* __restrict__ u = (const T*)a.U[k] + (int64_t)a.cols[(int64_t)k * a.nnz + e] * R + r0;
+    for (int k = 0; k < KRPS_MAX_MODES; ++k)
+      row[k] = k < a.N ? (int64_t)a.cols[(int64_t)k * a.nnz + e] * R : 0;
+    double part = 0;
+    for (int c = lane; c < R; c += L) {
+      double pr = a.sigma[c];
 #pragma unroll
-        for (int q = 0; q < 16; ++q)
-          if (r0 + q < R) pr[q] *= (double)u[q];
-      }
-#pragma unroll
-      for (int q = 0; q < 16; ++q) rowsum += pr[q];
+      for (int k = 0; k < KRPS_MAX_MODES; ++k)
+        if (k < a.N) pr *= (double)((const T*)a.U[k])[row[k] + c];
+      part += pr;
     }
-    acc += a.vals[e] * rowsum;
+    acc += a.vals[e] * part;
   }
   red[threadIdx.x] = acc;
   __syncthreads();
@@ -899,10 +1045,20 @@ size_t fit_partial_bytes() { return FIT_BLOCKS * 8; }
 
 hipError_t launch_fit(hipStream_t st, krps_precision p, const FitArgs& a, double* partial,
                       double* out) {
-  if (p == KRPS_FP64)
-    hipLaunchKernelGGL(fit_inner_kernel<double>, dim3(FIT_BLOCKS), dim3(256), 0, st, a, partial);
-  else
-    hipLaunchKernelGGL(fit_inner_kernel<float>, dim3(FIT_BLOCKS), dim3(256), 0, st, a, partial);
+  // team width: the power of two >= R, between 8 and a wavefront
+  const int L = a.R > 32 ? 64 : a.R > 16 ? 32 : a.R > 8 ? 16 : 8;
+  const dim3 g(FIT_BLOCKS), b(256);
+  if (p == KRPS_FP64) {
+    if (L == 64) hipLaunchKernelGGL((fit_inner_kernel<double, 64>), g, b, 0, st, a, partial);
+    else if (L == 32) hipLaunchKernelGGL((fit_inner_kernel<double, 32>), g, b, 0, st, a, partial);
+    else if (L == 16) hipLaunchKernelGGL((fit_inner_kernel<double, 16>), g, b, 0, st, a, partial);
+    else hipLaunchKernelGGL((fit_inner_kernel<double, 8>), g, b, 0, st, a, partial);
+  } else {
+    if (L == 64) hipLaunchKernelGGL((fit_inner_kernel<float, 64>), g, b, 0, st, a, partial);
+    else if (L == 32) hipLaunchKernelGGL((fit_inner_kernel<float, 32>), g, b, 0, st, a, partial);
+    else if (L == 16) hipLaunchKernelGGL((fit_inner_kernel<float, 16>), g, b, 0, st, a, partial);
+    else hipLaunchKernelGGL((fit_inner_kernel<float, 8>), g, b, 0, st, a, partial);
+  }
   hipLaunchKernelGGL(fit_final_kernel, dim3(1), dim3(256), 0, st, a, partial, FIT_BLOCKS, out);
   return hipGetLastError();
 }

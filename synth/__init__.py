@@ -21,6 +21,8 @@ Conventions
 from __future__ import annotations
 
 import math
+import os
+from concurrent.futures import ThreadPoolExecutor
 
 import numpy as np
 
@@ -113,12 +115,20 @@ def zipf_indices(rng, n, dim, alpha, chunk=1 << 24):
     cdf /= run
     perm = rng.permutation(dim).astype(np.int32)
     out = np.empty(int(n), dtype=np.int32)
-    for s in range(0, int(n), chunk):
-        m = min(chunk, int(n) - s)
-        u = rng.random(m)
+
+    def invert(s, u):
         r = np.searchsorted(cdf, u, side="right")
         np.minimum(r, dim - 1, out=r)
-        out[s:s + m] = perm[r]
+        out[s:s + len(u)] = perm[r]
+
+    # the uniforms are drawn in order; the searches (which release the GIL)
+    # run on a few threads, so the result does not depend on the thread count
+    nthr = max(1, min(8, os.cpu_count() or 1))
+    starts = list(range(0, int(n), chunk))
+    with ThreadPoolExecutor(nthr) as ex:
+        for b0 in range(0, len(starts), nthr):
+            batch = [(s, rng.random(min(chunk, int(n) - s))) for s in starts[b0:b0 + nthr]]
+            list(ex.map(lambda su: invert(*su), batch))
     return out
 
 

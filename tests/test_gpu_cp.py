@@ -74,6 +74,28 @@ def test_duplicates_are_merged_into_stored_entries(env):
     assert T2.stored_entries == len(np.unique(zidx, axis=0))
 
 
+def test_hot_rows_hold_the_most_entries(env):
+    """The rows the SpMM keeps per workgroup are the min(32, I_j) rows with
+    the most stored entries (enough entries per workgroup that the counting
+    table fills and the global fallback is taken too)."""
+    krps, torch, ctx = env
+    dims = (200_000, 100_000, 20)
+    idx, val = synth.sparse_tensor(dims, 20_000_000, 1.2, seed=12)
+    T = krps.Tensor(ctx, dims, torch.from_numpy(idx).to(ctx.device),
+                    torch.from_numpy(val).to(ctx.device))
+    key = (idx[:, 0].astype(np.int64) * dims[1] + idx[:, 1]) * dims[2] + idx[:, 2]
+    key = np.unique(key)
+    cols = [key // (dims[1] * dims[2]), (key // dims[2]) % dims[1], key % dims[2]]
+    assert T.stored_entries == len(key)
+    for j, d in enumerate(dims):
+        cnt = np.bincount(cols[j], minlength=d)
+        hot = T.hot_rows(j)
+        k = min(32, d)
+        assert len(hot) == k and len(set(hot)) == k
+        kth = np.sort(cnt)[::-1][k - 1]
+        assert min(cnt[h] for h in hot) >= kth, (j, sorted(cnt[hot]), kth)
+
+
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
 def test_repeated_samples_share_one_fiber(env, prec):
     """A factor with one dominant row makes most samples repeat a few
