@@ -63,9 +63,9 @@ struct Packed {
 // Branch-free: entries past the triangle read entry tri-1 and get weight 0.
 // The LDS reads go in batches of 8 entries (a compiler barrier between
 // batches) so that at most 8 entries' operands are in flight in registers.
-template <int LPS, int NP, typename TabP>
-__device__ __forceinline__ void build_packed(Packed<LPS, NP>& P, const double* hb, TabP tab, int TR,
-                                             int sl) {
+template <int LPS, int NP>
+__device__ __forceinline__ void build_packed(Packed<LPS, NP>& P, const double* hb,
+                                             const uint16_t* __restrict__ tab, int TR, int sl) {
 #pragma unroll
   for (int m = 0; m < NP; ++m) {
     if (m % 8 == 0) asm volatile("" ::: "memory");
@@ -80,23 +80,22 @@ __device__ __forceinline__ void build_packed(Packed<LPS, NP>& P, const double* h
 // Node mass <h h^T, G^v> = h^T G^v h in float64 whatever the storage type:
 // the stored packed triangle (tri(R) entries, read by the group's lanes in
 // coalesced strides) dotted with the packed outer product in registers.
-template <typename T, int LPS, int NP, typename TabP>
+template <typename T, int LPS, int NP>
 __device__ __forceinline__ double node_mass(const Packed<LPS, NP>& P, const double*,
                                             const T* __restrict__ node, int R, int TR, int sl,
-                                            TabP) {
+                                            const uint16_t* __restrict__ = nullptr) {
   // all loads first, then the float64 products.  Only the npr strides
   // that reach into the triangle are read (npr is uniform); the last may
   // run up to LPS - 1 entries past the node, into the next node or the
   // zero padding that follows every node array, with packed weight 0.
   const int npr = (TR + LPS - 1) / LPS;
-  const auto* gn = gmem(node);
   T g[NP];
   if (npr >= NP) {
 #pragma unroll
-    for (int m = 0; m < NP; ++m) g[m] = gn[sl + LPS * m];
+    for (int m = 0; m < NP; ++m) g[m] = node[sl + LPS * m];
   } else {
 #pragma unroll
-    for (int m = 0; m < NP; ++m) g[m] = m < npr ? gn[sl + LPS * m] : T(0);
+    for (int m = 0; m < NP; ++m) g[m] = m < npr ? node[sl + LPS * m] : T(0);
   }
   double acc = 0;
 #pragma unroll
@@ -108,13 +107,12 @@ __device__ __forceinline__ double node_mass(const Packed<LPS, NP>& P, const doub
 // not held in registers; each lane forms w h_a h_b for its packed entries
 // (lane + 64 m) from the (a, b) table and h in LDS, eight entries at a
 // time with their loads issued together.
-template <typename T, typename TabP>
+template <typename T>
 __device__ __forceinline__ double node_mass(const Packed<64, 0>&, const double* hb,
                                             const T* __restrict__ node, int R, int TR, int lane,
-                                            TabP tab) {
+                                            const uint16_t* __restrict__ tab) {
   double acc = 0;
   const int npr = (TR + 63) / 64;
-  const auto* gn = gmem(node);
   for (int m0 = 0; m0 < npr; m0 += 8) {
     T g[8];
     uint16_t ab[8];
@@ -122,7 +120,7 @@ __device__ __forceinline__ double node_mass(const Packed<64, 0>&, const double* 
     for (int q = 0; q < 8; ++q) {
       const int p = lane + 64 * (m0 + q);
       const int pc = p < TR ? p : TR - 1;
-      g[q] = gn[pc];
+      g[q] = node[pc];
       ab[q] = tab[pc];
     }
 #pragma unroll
@@ -141,10 +139,11 @@ __device__ __forceinline__ double node_mass(const Packed<64, 0>&, const double* 
 // sample: returns the leaf position and the offset `low` of its segment.
 // All groups of a wavefront walk the same tree, so the loop is uniform and
 // only the positions differ.
-template <typename T, int LPS, int NP, typename TabP>
+template <typename T, int LPS, int NP>
 __device__ __forceinline__ int64_t walk(const T* __restrict__ nodes, int64_t L, int D,
                                         const Packed<LPS, NP>& P, const double* hb, int R, int TR,
-                                        int sl, double x, double C, double& low_out, TabP tab) {
+                                        int sl, double x, double C, double& low_out,
+                                        const uint16_t* __restrict__ tab) {
   double low = 0.0, high = C;
   int64_t pos = 0;
   int64_t off = 1;
@@ -177,7 +176,7 @@ __device__ __forceinline__ double row_dot(const T* __restrict__ ur, const double
   if constexpr (std::is_same_v<T, float>) {
     if ((R & 3) == 0) {
       for (int c0 = 0; c0 < R; c0 += CH) {
-        const auto* u4 = gmem((const float4*)(ur + c0));
+        const float4* __restrict__ u4 = (const float4*)(ur + c0);
         float4 v[CH / 4];
 #pragma unroll
         for (int q = 0; q < CH / 4; ++q)
@@ -195,7 +194,7 @@ __device__ __forceinline__ double row_dot(const T* __restrict__ ur, const double
   } else {
     if ((R & 1) == 0) {
       for (int c0 = 0; c0 < R; c0 += CH) {
-        const auto* u2 = gmem((const double2*)(ur + c0));
+        const double2* __restrict__ u2 = (const double2*)(ur + c0);
         double2 v[CH / 2];
 #pragma unroll
         for (int q = 0; q < CH / 2; ++q)
@@ -247,9 +246,9 @@ __device__ __forceinline__ int64_t leaf_scan(const T* __restrict__ U, int R, int
 // (a, b) pair (LDS or global); `hb` is this group's RMAX doubles of LDS.
 // NP == 0 selects the masses formed entry by entry from h in LDS (R > 64,
 // LPS == 64).
-template <typename T, int LPS, int NP, int RMAX, typename TabP>
-__device__ __forceinline__ void descend(const DescentArgs& a, int64_t base, TabP tab, double* hb,
-                                        int lane) {
+template <typename T, int LPS, int NP, int RMAX>
+__device__ __forceinline__ void descend(const DescentArgs& a, int64_t base,
+                                        const uint16_t* __restrict__ tab, double* hb, int lane) {
   constexpr int HE = (RMAX + LPS - 1) / LPS;  // history entries per lane
   const int R = a.R;
   const int TR = R * (R + 1) / 2;
@@ -301,7 +300,7 @@ __device__ __forceinline__ void descend(const DescentArgs& a, int64_t base, TabP
 #pragma unroll
     for (int i = 0; i < HE; ++i) {
       const int e = sl + LPS * i;
-      ht[i] = e < R ? h[i] * (double)gmem(V)[e] : 0.0;
+      ht[i] = e < R ? h[i] * (double)V[e] : 0.0;
     }
     wave_lds_sync();
 #pragma unroll
@@ -324,7 +323,7 @@ __device__ __forceinline__ void descend(const DescentArgs& a, int64_t base, TabP
 #pragma unroll
     for (int i = 0; i < HE; ++i) {
       const int e = sl + LPS * i;
-      if (e < R) h[i] *= (double)gmem(U)[t * R + e];
+      if (e < R) h[i] *= (double)U[t * R + e];
     }
     if (active && (!(C1 > 0.0) || !(C2 > 0.0))) {
       if (sl == 0) atomicOr(a.status, ST_NUMERIC);
@@ -439,7 +438,7 @@ __global__ __launch_bounds__(64 * DESC_WAVES, KRPS_DESC_MIN_WAVES) void descent_
     }
     const BatchProblem& b = probs[lo];
     const int64_t base = (t - b.task0) * (int64_t)(64 / C::LPS);
-    descend<T, C::LPS, C::NP, C::RMAX>(b.a, base, gmem(b.tab), hb, lane);
+    descend<T, C::LPS, C::NP, C::RMAX>(b.a, base, b.tab, hb, lane);
     next = __builtin_amdgcn_readfirstlane(claim);
   }
 }

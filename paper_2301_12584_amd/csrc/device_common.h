@@ -97,14 +97,6 @@ __device__ __forceinline__ double u01_of_word(uint64_t x) {
   return ((double)(x >> 11) + 0.5) * 0x1.0p-53;
 }
 
-// Device-memory (address space 1) view of a generic pointer to global
-// memory: loads through it are global loads, which, unlike flat loads, do
-// not hold up the wave's next LDS access while they are in flight.
-template <typename T>
-__device__ __forceinline__ const __attribute__((address_space(1))) T* gmem(const T* p) {
-  return (const __attribute__((address_space(1))) T*)p;
-}
-
 // Orders the LDS traffic of one wave (all lanes see the others' writes).
 __device__ __forceinline__ void wave_lds_sync() {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");

@@ -131,6 +131,41 @@ def test_repeated_samples_share_one_fiber(env, prec):
     assert np.abs(got["Y"] - Y2).max() <= tol * np.abs(Y2).max()
 
 
+@pytest.mark.parametrize("prec", ["fp64", "bf16x2"])
+def test_solve_touches_exactly_the_reached_rows(env, prec):
+    """On a sparse tensor the solve lists exactly the rows of mode j that
+    the sampled fibers' entries reach (increasing, each once); Y matches the
+    oracle's normal equations on them and every other row of U_j is 0."""
+    krps, torch, ctx = env
+    dims, R, J, j = (5000, 40, 30), 8, 50, 0
+    idx, val = synth.sparse_tensor(dims, 20_000, 1.2, seed=31)
+    Us = synth.gaussian_factors(dims, R, seed=32)
+    S, T, A = make(krps, torch, ctx, dims, idx, val, Us, prec, J)
+    for k in range(3):
+        A.normalize(k)
+    A.solve(j, torch.from_numpy(synth.uniforms(J, 3, 33)).to(ctx.device))
+    torch.cuda.synchronize()
+    got = {k: v.cpu().numpy() for k, v in A.parts(j).items()}
+    rows_got = got["yrows"].astype(np.int64)
+    fibers = {}
+    for e in np.unique(idx, axis=0):
+        fibers.setdefault((int(e[1]), int(e[2])), set()).add(int(e[0]))
+    want = set()
+    for d in range(J):
+        want |= fibers.get((int(got["idx"][d, 1]), int(got["idx"][d, 2])), set())
+    assert 0 < len(want) < dims[j] // 2
+    assert np.all(np.diff(rows_got) > 0)
+    assert set(rows_got.tolist()) == want
+    Un = [ocp.normalize_columns(U)[0] for U in Us]
+    rows = Un[1][got["idx"][:, 1]] * Un[2][got["idx"][:, 2]]
+    M2, Y2 = ocp.normal_equations(ocp.SparseTensor(dims, idx, val), j,
+                                  got["idx"].astype(np.int64), rows, 1.0 / (J * got["prob"]))
+    assert np.abs(got["Y"] - Y2).max() <= 1e-5 * np.abs(Y2).max()
+    U = S.factors[j].cpu().numpy()
+    off = np.setdiff1d(np.arange(dims[j]), rows_got)
+    assert np.all(U[off] == 0) and np.abs(U[rows_got]).max() > 0
+
+
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
 @pytest.mark.parametrize("j", [0, 1, 2])
 def test_one_solve_matches_oracle(env, prec, j):
