@@ -1,7 +1,8 @@
 """Benchmark of the exact Khatri-Rao leverage sampler and the sketched
 CP-ALS sweep on one MI355X.
 
-Headline number (``value``, samples/s): N = 3 factors of 2^20 x 32
+Headline number (``value``, samples/s, BF16 hi/lo split trees; float32 and
+float64 beside it): N = 3 factors of 2^20 x 32
 (float32, N(0,1) with 1% of the rows scaled by 100), J = 65,536 samples
 drawn from the Khatri-Rao product of the other two factors for each
 excluded mode k in {0, 1, 2}.  One step = rebuild the three segment trees +
@@ -58,6 +59,9 @@ def parse():
                     help="also run the large 4-mode CP-ALS workload (2e7^3 x 1e6, 5e8 Zipf(1.1) "
                          "entries, R=128, J=131072; several minutes)")
     ap.add_argument("--large-sweeps", type=int, default=None)
+    ap.add_argument("--paper-point", action="store_true",
+                    help="also time the paper's own sampling point (N=3 N(0,1) factors of "
+                         "2^25 x 32, J=50,000 draws, no exclusion), next to its 0.31 s")
     ap.add_argument("--batched", default="fp32",
                     help="precision of the batched-samplers leg ('' skips it)")
     ap.add_argument("--batched-reps", type=int, default=3)
@@ -166,6 +170,66 @@ def run_sampler(torch, krps, ctx, Us, u01_dev, prec, steps, warmup, J):
     return out
 
 
+PAPER_POINT_S = 0.31  # sampling time the paper reports for this point (CPU node, 128 threads)
+
+
+def run_paper_point(torch, krps, ctx, precs, reps=5):
+    """The sampling-time point of the paper's runtime experiment (Section
+    4.1): N = 3 i.i.d. N(0,1) factors of 2^25 x 32, J = 50,000 draws from
+    the full Khatri-Rao product (no exclusion).  Tree build of the three
+    factors and the draw (preparation + walk) are timed separately with HIP
+    events on the context stream, mean of ``reps`` after a warm-up."""
+    import numpy as np
+    import synth
+    dims, R, J = (1 << 25,) * 3, 32, 50_000
+    t0 = time.perf_counter()
+    Us = synth.gaussian_factors(dims, R, synth.config_seed(6))
+    print(f"# paper point: factors generated in {time.perf_counter() - t0:.1f} s",
+          file=sys.stderr, flush=True)
+    u = torch.from_numpy(synth.uniforms(J, 3, synth.uniform_seed(6))).to(ctx.device)
+    stream = ctx.stream
+    out = {"workload": "N=3, I=2^25, R=32, i.i.d. N(0,1), J=50,000 draws, no exclusion",
+           "paper_sampling_s": PAPER_POINT_S,
+           "paper_hardware": "one CPU node, 2x 64-core EPYC 7763, 128 threads",
+           "precisions": {}}
+    for prec in precs:
+        dt = torch.float64 if prec == "fp64" else torch.float32
+        Ud = [torch.from_numpy(U).to(ctx.device).to(dt).contiguous() for U in Us]
+        S = krps.Sampler(ctx, Ud, precision=prec)
+        bms, dms = [], []
+        for rep in range(reps + 1):
+            e = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+            e[0].record(stream)
+            for k in range(3):
+                S.refresh(k)
+            e[1].record(stream)
+            S.sample(-1, u)
+            e[2].record(stream)
+            torch.cuda.synchronize()
+            if rep > 0:
+                bms.append(e[0].elapsed_time(e[1]))
+                dms.append(e[1].elapsed_time(e[2]))
+        rec = {"build_ms": float(np.mean(bms)), "draw_ms": float(np.mean(dms)),
+               "samples_per_s": J / (float(np.mean(dms)) / 1e3),
+               "paper_over_draw": PAPER_POINT_S / (float(np.mean(dms)) / 1e3)}
+        out["precisions"][prec] = rec
+        print(f"# paper point {prec}: build {rec['build_ms']:.2f} ms, draw {rec['draw_ms']:.3f} ms",
+              file=sys.stderr, flush=True)
+        del S, Ud
+        torch.cuda.synchronize()
+        torch.cuda.empty_cache()
+    return out
+
+
+def blas_threads():
+    """Threads of the BLAS pools NumPy uses (its element-wise work runs on one)."""
+    try:
+        from threadpoolctl import threadpool_info
+        return max((int(d.get("num_threads", 1)) for d in threadpool_info()), default=1)
+    except Exception:
+        return 1
+
+
 def cpu_baseline(Us, u01, J_full, budget_s=20.0):
     """The oracle (float64 NumPy) on the host: tree build of the three
     factors plus a bounded number of draws per exclusion, scaled to one
@@ -176,21 +240,25 @@ def cpu_baseline(Us, u01, J_full, budget_s=20.0):
     t0 = time.perf_counter()
     S = osmp.KRPSampler(Us)
     t_build = time.perf_counter() - t0
-    Jc = 2048
+    print(f"# cpu baseline: oracle trees built in {t_build:.1f} s", file=sys.stderr, flush=True)
+    Jc = 16384
     t0 = time.perf_counter()
     done = 0
     for k in range(N):
         S.draw(k, u01[k][:Jc])
         done += Jc
+        print(f"# cpu baseline: {done} draws in {time.perf_counter() - t0:.1f} s", file=sys.stderr,
+              flush=True)
         if time.perf_counter() - t0 > budget_s:
             break
     t_draw = (time.perf_counter() - t0) / done
     step_s = t_build + N * J_full * t_draw
     return {"value": N * J_full / step_s, "unit": "samples/s",
-            "cores": len(os.sched_getaffinity(0)), "kind": "oracle",
+            "cores": blas_threads(), "kind": "oracle",
             "sample": f"float64 NumPy oracle on the full factors: tree build of the 3 factors "
                       f"({t_build:.2f} s) + {done} draws ({Jc} per exclusion, "
-                      f"{t_draw * 1e6:.1f} us/draw), scaled to one step of 3 x {J_full} draws"}
+                      f"{t_draw * 1e6:.1f} us/draw), scaled to one step of 3 x {J_full} draws; "
+                      f"BLAS on {blas_threads()} threads, element-wise NumPy on one"}
 
 
 GOLDEN = os.path.join(ROOT, "tests", "golden")
@@ -425,7 +493,9 @@ def main():
               f"step {results[prec]['ms_per_step']:.3f} ms, build {results[prec]['build_ms']:.3f} ms, "
               f"walk {results[prec]['walk_ms']:.3f} ms", file=sys.stderr, flush=True)
 
-    head = "fp32" if "fp32" in results else list(results)[0]
+    # headline: the bf16 hi/lo split path (float32 storage, split-MFMA tree
+    # build, float64 walk); fp32 and fp64 are reported beside it
+    head = next((p for p in ("bf16x2", "fp32") if p in results), list(results)[0])
     r = results[head]
     elem = 8 if head == "fp64" else 4
     # roofline of the dominant kernel: the batched walk of the N exclusions
@@ -447,11 +517,15 @@ def main():
         "metric": METRIC, "value": r["samples_per_s"], "unit": "samples/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": r["ms_per_step"],
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "f32" if head != "fp64" else "f64",
+        "dtype": {"bf16x2": "bf16x2", "fp32": "f32", "fp64": "f64"}[head],
         "data": "synthetic (seeded N(0,1) factors, 1% rows x100; host uniforms)",
         "config": {"workload": "sampler N=3, I=2^20, R=32, J=65536 per excluded mode k=0,1,2",
                    "N": N, "I": dims[0], "R": R, "J": J, "leaf_size": R,
-                   "precision": head, "arith": "f64 walk over f32-stored trees"},
+                   "precision": head,
+                   "arith": {"bf16x2": "tree build: bf16 hi/lo split on MFMA (f32 accumulate); "
+                                       "walk: f64 over f32-stored trees",
+                             "fp32": "tree build: f64 MFMA; walk: f64 over f32-stored trees",
+                             "fp64": "f64 throughout"}[head]},
         "roofline": roof,
         "precisions": {p: {"samples_per_s": v["samples_per_s"], "ms_per_step": v["ms_per_step"],
                            "build_ms": v["build_ms"], "walk_ms": v["walk_ms"]}
@@ -470,6 +544,8 @@ def main():
         # finder (the paper's start for its sparsest tensor) is used instead
         line["als_large"] = run_als(torch, krps, ctx, ["bf16x2", "fp64"], None, args.large_sweeps,
                                     1, config=5, init="range_finder")
+    if args.paper_point:
+        line["paper_point"] = run_paper_point(torch, krps, ctx, ["bf16x2", "fp64"])
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(Us, u01, J)
     else:

@@ -108,7 +108,7 @@ __device__ int jacobi_columns_t(double* A, int R, int* flag) {
       al = team_sum<TEAM>(al);
       be = team_sum<TEAM>(be);
       ga = team_sum<TEAM>(ga);
-      if (act && al > 0 && be > 0 && fabs(ga) > tol * sqrt(al * be)) {
+      if (act && al > 0 && be > 0 && ga * ga > (tol * tol) * (al * be)) {
         // tangent of the rotation angle, the root of t^2 + 2 zeta t - 1 = 0
         // of smaller magnitude (zeta = (be - al) / (2 ga))
         const double dd = be - al, g2 = 2.0 * ga;
