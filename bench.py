@@ -241,7 +241,7 @@ def cpu_baseline(Us, u01, J_full, budget_s=20.0):
     S = osmp.KRPSampler(Us)
     t_build = time.perf_counter() - t0
     print(f"# cpu baseline: oracle trees built in {t_build:.1f} s", file=sys.stderr, flush=True)
-    Jc = 16384
+    Jc = J_full  # the whole step when it fits the budget
     t0 = time.perf_counter()
     done = 0
     for k in range(N):
