@@ -1005,6 +1005,52 @@ __global__ __launch_bounds__(256) void fit_inner_kernel(FitArgs a, double* __res
   if (threadIdx.x == 0) partial[blockIdx.x] = red[0];
 }
 
+// The same sum when R is a multiple of the 16-byte vector width VW (4
+// floats or 2 doubles): lane l of an entry's team of L lanes reads columns
+// VW l .. VW l + VW - 1 (then + VW L ...) of every row with one 16-byte
+// load, and a wavefront serves 64 / L entries at once.
+template <typename T, int L>
+__global__ __launch_bounds__(256) void fit_inner_vec_kernel(FitArgs a,
+                                                            double* __restrict__ partial) {
+  constexpr int VW = 16 / (int)sizeof(T);
+  typedef T vec __attribute__((ext_vector_type(VW)));
+  __shared__ double red[256];
+  double acc = 0;
+  const int R = a.R;
+  const int lane = threadIdx.x % L;
+  const int64_t team = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / L;
+  const int64_t nteam = (int64_t)gridDim.x * blockDim.x / L;
+  for (int64_t e = team; e < a.nnz; e += nteam) {
+    int64_t row[KRPS_MAX_MODES];
+#pragma unroll
+    for (int k = 0; k < KRPS_MAX_MODES; ++k)
+      row[k] = k < a.N ? (int64_t)a.cols[(int64_t)k * a.nnz + e] * R : 0;
+    double part = 0;
+    for (int c = lane * VW; c < R; c += L * VW) {
+      double pr[VW];
+#pragma unroll
+      for (int v = 0; v < VW; ++v) pr[v] = a.sigma[c + v];
+#pragma unroll
+      for (int k = 0; k < KRPS_MAX_MODES; ++k)
+        if (k < a.N) {
+          const vec u = *(const vec*)((const T*)a.U[k] + row[k] + c);
+#pragma unroll
+          for (int v = 0; v < VW; ++v) pr[v] *= (double)u[v];
+        }
+#pragma unroll
+      for (int v = 0; v < VW; ++v) part += pr[v];
+    }
+    acc += a.vals[e] * part;
+  }
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int o = blockDim.x / 2; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) partial[blockIdx.x] = red[0];
+}
+
 // out[0] = sum of partials (<T, T~>), out[1] = sigma^T ((*)_k G_k) sigma.
 __global__ __launch_bounds__(256) void fit_final_kernel(FitArgs a, const double* __restrict__ partial,
                                                         int nb, double* __restrict__ out) {
@@ -1043,8 +1089,39 @@ __global__ __launch_bounds__(256) void fit_final_kernel(FitArgs a, const double*
 constexpr int FIT_BLOCKS = 2048;
 size_t fit_partial_bytes() { return FIT_BLOCKS * 8; }
 
+template <typename T>
+static void launch_fit_vec(hipStream_t st, const FitArgs& a, double* partial) {
+  constexpr int VW = 16 / (int)sizeof(T);
+  // team width: the power of two >= R / VW, between 2 and a wavefront
+  const int n = a.R / VW;
+  const int L = n > 32 ? 64 : n > 16 ? 32 : n > 8 ? 16 : n > 4 ? 8 : n > 2 ? 4 : 2;
+  const dim3 g(FIT_BLOCKS), b(256);
+  switch (L) {
+    case 64: hipLaunchKernelGGL((fit_inner_vec_kernel<T, 64>), g, b, 0, st, a, partial); break;
+    case 32: hipLaunchKernelGGL((fit_inner_vec_kernel<T, 32>), g, b, 0, st, a, partial); break;
+    case 16: hipLaunchKernelGGL((fit_inner_vec_kernel<T, 16>), g, b, 0, st, a, partial); break;
+    case 8: hipLaunchKernelGGL((fit_inner_vec_kernel<T, 8>), g, b, 0, st, a, partial); break;
+    case 4: hipLaunchKernelGGL((fit_inner_vec_kernel<T, 4>), g, b, 0, st, a, partial); break;
+    default: hipLaunchKernelGGL((fit_inner_vec_kernel<T, 2>), g, b, 0, st, a, partial); break;
+  }
+}
+
 hipError_t launch_fit(hipStream_t st, krps_precision p, const FitArgs& a, double* partial,
                       double* out) {
+  // 16-byte row loads when every row starts on a 16-byte boundary (the
+  // factors are allocated so; R a multiple of the vector width)
+  bool vec_ok = true;
+  for (int k = 0; k < a.N; ++k) vec_ok = vec_ok && ((uintptr_t)a.U[k] % 16 == 0);
+  if (vec_ok && p == KRPS_FP64 && a.R % 2 == 0) {
+    launch_fit_vec<double>(st, a, partial);
+    hipLaunchKernelGGL(fit_final_kernel, dim3(1), dim3(256), 0, st, a, partial, FIT_BLOCKS, out);
+    return hipGetLastError();
+  }
+  if (vec_ok && p != KRPS_FP64 && a.R % 4 == 0) {
+    launch_fit_vec<float>(st, a, partial);
+    hipLaunchKernelGGL(fit_final_kernel, dim3(1), dim3(256), 0, st, a, partial, FIT_BLOCKS, out);
+    return hipGetLastError();
+  }
   // team width: the power of two >= R, between 8 and a wavefront
   const int L = a.R > 32 ? 64 : a.R > 16 ? 32 : a.R > 8 ? 16 : 8;
   const dim3 g(FIT_BLOCKS), b(256);

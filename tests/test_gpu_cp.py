@@ -210,18 +210,22 @@ def test_one_solve_matches_oracle(env, prec, j):
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
-def test_fit_matches_oracle(env, prec):
+@pytest.mark.parametrize("R", [3, 8, 12, 128])
+def test_fit_matches_oracle(env, prec, R):
+    """R = 3: lane-per-column teams; R = 8, 12, 128: 16-byte row loads
+    (R = 12 leaves a partial last vector team pass for float64)."""
     krps, torch, ctx = env
-    dims, R = (12, 10, 8), 3
+    dims = (12, 10, 8)
     idx, val = dense_coo(dims, 9)
     Us = synth.gaussian_factors(dims, R, seed=22)
     S, T, A = make(krps, torch, ctx, dims, idx, val, Us, prec, 64)
     for k in range(3):
         A.normalize(k)
-    A.sigma.copy_(torch.tensor([2.0, 0.5, 1.25], dtype=torch.float64))
+    sig = np.linspace(0.5, 2.0, R)
+    A.sigma.copy_(torch.from_numpy(sig))
     f = A.fit()
     Un = [ocp.normalize_columns(U)[0] for U in Us]
-    ref = ocp.fit(ocp.SparseTensor(dims, idx, val), Un, np.array([2.0, 0.5, 1.25]))
+    ref = ocp.fit(ocp.SparseTensor(dims, idx, val), Un, sig)
     assert abs(f - ref) <= (1e-12 if prec == "fp64" else 1e-6)
 
 
