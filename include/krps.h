@@ -398,7 +398,8 @@ krps_status krps_sampler_tree_info(krps_sampler s, int j, krps_tree_info* out);
 typedef struct {
   size_t gplus;       /* float64 R x R, G^+ of G = (*)_{k != exclude} G_k */
   size_t rank;        /* int32 [2 + N]: rank of G, then the Jacobi sweep count of
-                         G and of each drawn mode's G_{>k} (diagnostics) */
+                         G (0 when G^+ = G^{-1} came from the certified Cholesky
+                         route) and of each drawn mode's G_{>k} (diagnostics) */
   size_t ggt;         /* float64 [N][R][R]: G_{>k} */
   size_t lam;         /* float64 [N][R]: eigenvalues of G_{>k}, ascending */
   size_t vecs;        /* factor type [N][R][R]: eigenvector u of mode k at [k][u][:] */

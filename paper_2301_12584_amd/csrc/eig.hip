@@ -159,8 +159,94 @@ __device__ void norms_and_normalise(double* A, int R, double* lam) {
   __syncthreads();
 }
 
+// In place in the lower triangle of A (column c at A + c*RS, G in full on
+// entry): the Cholesky factor L of G = L L^T, then L^{-1} in place of L
+// (right-looking factorisation, right-to-left triangular inverse; two
+// barriers per column).  False if a pivot is not positive (every thread
+// reads the same pivot after a barrier, so all return together).  `tmp`
+// holds R doubles of LDS.
+__device__ bool cholesky_inverse_lower(double* A, int R, double* tmp) {
+  const int RS = R + 1, tid = threadIdx.x, nt = blockDim.x;
+  for (int j = 0; j < R; ++j) {
+    const double d = A[j * RS + j];
+    if (!(d > 0.0) || !(d < INFINITY)) return false;
+    const double ljj = sqrt(d), inv = 1.0 / ljj;
+    for (int i = j + 1 + tid; i < R; i += nt) A[j * RS + i] *= inv;
+    __syncthreads();
+    // trailing lower triangle: (i, k), j < k <= i
+    const int m = R - j - 1;
+    for (int t = tid; t < m * m; t += nt) {
+      const int kk = t / m, ii = t % m;
+      if (ii >= kk) A[(j + 1 + kk) * RS + j + 1 + ii] -= A[j * RS + j + 1 + ii] * A[j * RS + j + 1 + kk];
+    }
+    if (tid == 0) A[j * RS + j] = ljj;
+    __syncthreads();
+  }
+  for (int j = R - 1; j >= 0; --j) {
+    for (int i = j + 1 + tid; i < R; i += nt) tmp[i] = A[j * RS + i];
+    __syncthreads();
+    const double xjj = 1.0 / A[j * RS + j];
+    // column j of L^{-1} below the diagonal: -x_jj (L^{-1})_{22} l_j, with
+    // the columns right of j already inverted
+    for (int i = j + 1 + tid; i < R; i += nt) {
+      double acc = 0;
+      for (int k = j + 1; k <= i; ++k) acc += A[k * RS + i] * tmp[k];
+      A[j * RS + i] = -xjj * acc;
+    }
+    __syncthreads();
+    if (tid == 0) A[j * RS + j] = xjj;
+  }
+  __syncthreads();
+  return true;
+}
+
+// (G^{-1})_{ab} = sum_{i >= max(a, b)} X_{ia} X_{ib} from X = L^{-1} (lower
+// triangle of A).
+__device__ __forceinline__ double inverse_entry(const double* A, int R, int a, int b) {
+  const int RS = R + 1;
+  double v = 0;
+  for (int i = a > b ? a : b; i < R; ++i) v += A[a * RS + i] * A[b * RS + i];
+  return v;
+}
+
+// A (column c at A + c*RS) = (*) of the nmat listed Grams; then a barrier.
+__device__ void load_hadamard(const GList& gl, int nmat, int R, double* A) {
+  const int RS = R + 1;
+  for (int i = threadIdx.x; i < R * R; i += blockDim.x) {
+    double v = 1.0;
+    for (int m = 0; m < nmat; ++m) v *= gl.G[m][i];
+    A[(i / R) * RS + i % R] = v;
+  }
+  __syncthreads();
+}
+
+// G^+ entry v at flat index i = a R + b -> full, packed (a <= b) and the
+// G_{>k} products.
+__device__ __forceinline__ void store_gplus(const GList& gl, int R, int nsteps, int i, double v,
+                                            double* __restrict__ gplus_full,
+                                            double* __restrict__ gplus_packed,
+                                            double* __restrict__ ggt) {
+  const int a = i / R, b = i % R;
+  gplus_full[i] = v;
+  if (gplus_packed != nullptr && a <= b) gplus_packed[packed_index(a, b, R)] = v;
+  for (int st = 0; st < nsteps; ++st) {
+    double w = v;
+    for (int s2 = st + 1; s2 < nsteps; ++s2) w *= gl.G[s2][i];
+    ggt[(int64_t)gl.order[st] * R * R + i] = w;
+  }
+}
+
 // G = (*) of the listed Grams -> G^+ (full and packed), rank, and G_{>k}
 // for the drawn modes order[0..nsteps-1] (nsteps may be 0).  One block.
+//
+// G^+ is the eigendecomposition pseudo-inverse (eigenvalues at most
+// R eps lambda_max dropped).  When G is far from that threshold it equals
+// G^{-1}, which the Cholesky factorisation gives in a few hundred light
+// steps instead of the Jacobi sweeps: it is used when every pivot is
+// positive and ||G||_inf ||G^{-1}||_inf R eps < 1e-4, which implies
+// lambda_min >= 1 / ||G^{-1}||_inf > 1e4 R eps ||G||_inf >= 1e4 R eps
+// lambda_max, so that the eigen route would keep all R eigenvalues (rank R,
+// Jacobi sweep count reported as 0).  Otherwise the Jacobi route runs.
 __device__ void prep_gplus_body(const GList& gl, int nmat, int R, int nsteps,
                                 double* __restrict__ gplus_full, double* __restrict__ gplus_packed,
                                 int32_t* __restrict__ rank, double* __restrict__ ggt,
@@ -171,12 +257,53 @@ __device__ void prep_gplus_body(const GList& gl, int nmat, int R, int nsteps,
   int* flag = (int*)(red + 2);
   const int RS = R + 1;
   const int tid = threadIdx.x;
-  for (int i = tid; i < R * R; i += blockDim.x) {
-    double v = 1.0;
-    for (int m = 0; m < nmat; ++m) v *= gl.G[m][i];
-    A[(i / R) * RS + i % R] = v;
+  if (gplus_packed != nullptr)
+    for (int i = tid; i < NODE_SLACK; i += blockDim.x)
+      gplus_packed[(int64_t)R * (R + 1) / 2 + i] = 0.0;
+  load_hadamard(gl, nmat, R, A);
+  // ---- Cholesky route
+  for (int a = tid; a < R; a += blockDim.x) {
+    double rs = 0;
+    for (int b = 0; b < R; ++b) rs += fabs(A[b * RS + a]);
+    lam[a] = rs;
   }
   __syncthreads();
+  if (tid == 0) {
+    double g = 0;
+    for (int a = 0; a < R; ++a) g = fmax(g, lam[a]);
+    red[0] = g;                     // ||G||_inf
+  }
+  __syncthreads();
+  bool ok = cholesky_inverse_lower(A, R, lam);
+  if (ok) {
+    for (int a = tid; a < R; a += blockDim.x) {
+      double rs = 0;
+      for (int b = 0; b < R; ++b) rs += fabs(inverse_entry(A, R, a, b));
+      lam[a] = rs;
+    }
+    __syncthreads();
+    if (tid == 0) {
+      double h = 0;
+      for (int a = 0; a < R; ++a) h = fmax(h, lam[a]);
+      const double cert = red[0] * h * (double)R * DBL_EPSILON;
+      *flag = (cert < 1e-4) ? 1 : 0;
+    }
+    __syncthreads();
+    ok = *flag == 1;
+  }
+  if (ok) {
+    if (tid == 0) {
+      rank[0] = R;
+      rank[1] = 0;
+    }
+    for (int i = tid; i < R * R; i += blockDim.x)
+      store_gplus(gl, R, nsteps, i, inverse_entry(A, R, i / R, i % R), gplus_full, gplus_packed,
+                  ggt);
+    return;
+  }
+  // ---- eigen route (one-sided Jacobi)
+  __syncthreads();
+  load_hadamard(gl, nmat, R, A);
   const int sweeps = jacobi_columns(A, R, flag);
   if (tid == 0) rank[1] = sweeps;
   norms_and_normalise(A, R, lam);
@@ -195,21 +322,11 @@ __device__ void prep_gplus_body(const GList& gl, int nmat, int R, int nsteps,
   const double tau = red[0];
   for (int c = tid; c < R; c += blockDim.x) lam[c] = lam[c] > tau ? 1.0 / lam[c] : 0.0;
   __syncthreads();
-  if (gplus_packed != nullptr)
-    for (int i = tid; i < NODE_SLACK; i += blockDim.x)
-      gplus_packed[(int64_t)R * (R + 1) / 2 + i] = 0.0;
   for (int i = tid; i < R * R; i += blockDim.x) {
     const int a = i / R, b = i % R;
     double v = 0;
     for (int c = 0; c < R; ++c) v += A[c * RS + a] * A[c * RS + b] * lam[c];
-    gplus_full[i] = v;
-    if (gplus_packed != nullptr && a <= b) gplus_packed[packed_index(a, b, R)] = v;
-    // G_{>k}: later drawn modes' Grams multiplied in
-    for (int st = 0; st < nsteps; ++st) {
-      double w = v;
-      for (int s2 = st + 1; s2 < nsteps; ++s2) w *= gl.G[s2][i];
-      ggt[(int64_t)gl.order[st] * R * R + i] = w;
-    }
+    store_gplus(gl, R, nsteps, i, v, gplus_full, gplus_packed, ggt);
   }
 }
 

@@ -108,6 +108,29 @@ def test_prep_matches_oracle(env, prec, exclude):
         assert np.abs(Eg - Eref).max() <= rtol * 10 * np.abs(Eref).max()
 
 
+def test_pseudo_inverse_routes(env):
+    """Full-rank G takes the Cholesky route (Jacobi sweep count 0, rank R);
+    a column repeated in every factor makes G singular, which must take the
+    eigen route (rank R - 1); both match the oracle's eigendecomposition
+    pseudo-inverse."""
+    krps, torch, ctx = env
+    R = 8
+    base = synth.gaussian_factors((64, 50, 70), R, seed=41)
+    rep = [U.copy() for U in base]
+    for U in rep:
+        U[:, 1] = U[:, 0]
+    for Us, want_rank, cholesky in ((base, R, True), (rep, R - 1, False)):
+        S = krps.Sampler(ctx, to_dev(torch, ctx, Us, "fp64"), precision="fp64")
+        S.sample(-1, torch.from_numpy(synth.uniforms(16, 3, 2)).to(ctx.device))
+        torch.cuda.synchronize()
+        parts = S.draw_parts()
+        Gp, rank, _, _, _ = osmp.KRPSampler(Us).prepare(-1)
+        assert parts["rank"] == rank == want_rank
+        assert (parts["sweeps"][0] == 0) == cholesky
+        Gg = parts["gplus"].cpu().numpy()
+        assert np.abs(Gg - Gp).max() <= 1e-9 * np.abs(Gp).max()
+
+
 def _compare_draw(krps, torch, ctx, Us, prec, exclude, J, useed, F=0):
     S = krps.Sampler(ctx, to_dev(torch, ctx, Us, prec), precision=prec, F=F)
     u01 = synth.uniforms(J, len(Us), useed)
