@@ -53,7 +53,6 @@ __device__ __forceinline__ double team_sum(double v) {
 
 // Team of lanes per column pair for a given R (RPL rows per lane at most).
 constexpr int jacobi_team(int R) { return R <= 32 ? 4 : 16; }
-constexpr int JACOBI_RPL = 8;
 
 // One-sided Jacobi on the columns of A (column c at A + c*RS, RS = R + 1 so
 // that the columns of a step fall in different LDS banks).  Each step
@@ -61,9 +60,8 @@ constexpr int JACOBI_RPL = 8;
 // schedule in parallel, one team of TEAM lanes per pair; a lane keeps its
 // <= RPL rows of both columns in registers between the dot products and
 // the rotation.  `flag` is an int in LDS.  Returns the number of sweeps.
-template <int TEAM>
+template <int TEAM, int RPL>
 __device__ int jacobi_columns_t(double* A, int R, int* flag) {
-  constexpr int RPL = JACOBI_RPL;
   const int RS = R + 1;
   const int tid = threadIdx.x;
   const int n = R + (R & 1);
@@ -135,9 +133,10 @@ __device__ int jacobi_columns_t(double* A, int R, int* flag) {
 }
 
 __device__ int jacobi_columns(double* A, int R, int* flag) {
-  if (R <= 32) return jacobi_columns_t<jacobi_team(32)>(A, R, flag);
-  if (R <= 64) return jacobi_columns_t<jacobi_team(64)>(A, R, flag);
-  return jacobi_columns_t<jacobi_team(128)>(A, R, flag);
+  // rows per lane: just enough for the largest R of each branch
+  if (R <= 32) return jacobi_columns_t<jacobi_team(32), 32 / jacobi_team(32)>(A, R, flag);
+  if (R <= 64) return jacobi_columns_t<jacobi_team(64), 64 / jacobi_team(64)>(A, R, flag);
+  return jacobi_columns_t<jacobi_team(128), 128 / jacobi_team(128)>(A, R, flag);
 }
 
 // Column norms into lam[], columns normalised in place (zero columns stay).
