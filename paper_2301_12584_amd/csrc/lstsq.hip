@@ -567,15 +567,17 @@ __global__ __launch_bounds__(256) void spmm_kernel(FiberArgs a, const T* __restr
       const double cd = a.coef[d];
       const T r0 = lane < R ? rows[d * R + lane] : T(0);
       const T r1 = lane + 64 < R ? rows[d * R + lane + 64] : T(0);
-      // lane t holds entry e0 + t (CH == 64)
+      // lane t holds entry e0 + t (CH == 64) and its row's hot slot, so
+      // the loop below does no dependent loads
       const int64_t et = e0 + lane < e1 ? e0 + lane : e1 - 1;
       const double xv = cd * a.vals[et];
       const int iv = ij[et];
+      const int hv = a.hot_slot[iv];
       const int n = (int)(e1 - e0);
       for (int t = 0; t < n; ++t) {
         const double coef = __shfl(xv, t);
         const int64_t i = __builtin_amdgcn_readfirstlane(__shfl(iv, t));
-        const int hs = a.hot_slot[i];
+        const int hs = __builtin_amdgcn_readfirstlane(__shfl(hv, t));
         if (hs >= 0) {
           double* acc = hot_acc + hs * R;
           if (lane < R) atomicAdd(&acc[lane], coef * (double)r0);
