@@ -359,8 +359,9 @@ typedef struct {
   size_t rows;     /* [J][R] w_d a_d (rows of S A): float64, float32 for KRPS_BF16X2 */
   size_t M;        /* float64 [R][R] (S A)^T S A */
   size_t Mp;       /* float64 [R][R] its pseudo-inverse */
-  size_t Y;        /* float64 [I_j][R] (S B)^T S A: only the rows listed at
-                      yrows are written by the solve; every other row of
+  size_t Y;        /* [I_j][R] (S B)^T S A, float64 (float32 for KRPS_BF16X2,
+                      whose rows of S A are float32 too): only the rows listed
+                      at yrows are written by the solve; every other row of
                       (S B)^T S A is zero and its slot in Y is left as it was */
   size_t draw;     /* per-draw scratch (krps_draw_layout offsets are relative to this) */
   size_t yrows;    /* int32 [*nyrows] rows of mode j that the sampled fibers'

@@ -536,8 +536,11 @@ class CPALS:
         torch = self.S.ctx.torch
         l, R, ws = self.layout, self.S.R, self.ws
         I = self.S.dims[j]
-        full = ws[l.Y:l.Y + I * R * 8].view(torch.float64).view(I, R)
+        if self.S.precision == "bf16x2":
+            full = ws[l.Y:l.Y + I * R * 4].view(torch.float32).view(I, R)
+        else:
+            full = ws[l.Y:l.Y + I * R * 8].view(torch.float64).view(I, R)
         rows = self._yrows().long()
-        Y = torch.zeros_like(full)
-        Y[rows] = full[rows]
+        Y = torch.zeros(I, R, dtype=torch.float64, device=full.device)
+        Y[rows] = full[rows].double()
         return Y

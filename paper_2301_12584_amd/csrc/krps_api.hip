@@ -493,7 +493,7 @@ krps_status enqueue_solve(krps_sampler s, krps_tensor t, int j, int64_t J, const
   int32_t* yrows = (int32_t*)(w + l.yrows);
   int64_t* nyrows = (int64_t*)(w + l.nyrows);
   e = launch_rows(st, fa, s->I[j], (int32_t*)(w + pl.ymark), (int64_t*)(w + pl.ybsum), yrows,
-                  nyrows, (double*)(w + l.Y));
+                  nyrows, w + l.Y, split);
   if (e != hipSuccess) return hip_fail(e, "rows of Y");
   e = launch_spmm(st, split ? KRPS_BF16X2 : KRPS_FP64, fa, w + l.rows, w + l.Y);
   if (e != hipSuccess) return hip_fail(e, "SpMM");

@@ -221,7 +221,7 @@ hipError_t launch_spmm(hipStream_t st, krps_precision p, const FiberArgs& a, con
 // rows of Y set to zero (the rest of Y is left as it was).
 size_t row_bsum_bytes(int64_t I);
 hipError_t launch_rows(hipStream_t st, const FiberArgs& a, int64_t I, int32_t* mark, int64_t* bsum,
-                       int32_t* list, int64_t* count, double* Y);
+                       int32_t* list, int64_t* count, void* Y, bool y32);
 size_t solve_partial_bytes(int R);
 // Generic sketched least squares (scaled rows, Z = (SA)^T S B, X = M^+ Z).
 size_t lstsq_partial_bytes(int R, int64_t n);

@@ -538,9 +538,9 @@ void launch_scan(hipStream_t st, const int64_t* cnt, int64_t* start, int64_t* bs
 // go and broadcast one by one; lanes run over the R columns.
 constexpr int SPMM_IPW = 4;
 
-template <typename T>
+template <typename T, typename YT>
 __global__ __launch_bounds__(256) void spmm_kernel(FiberArgs a, const T* __restrict__ rows,
-                                                   double* __restrict__ Y) {
+                                                   YT* __restrict__ Y) {
   extern __shared__ double hot_acc[];  // [nhot][R]
   const int lane = threadIdx.x & 63;
   const int R = a.R;
@@ -583,8 +583,8 @@ __global__ __launch_bounds__(256) void spmm_kernel(FiberArgs a, const T* __restr
           if (lane < R) atomicAdd(&acc[lane], coef * (double)r0);
           if (lane + 64 < R) atomicAdd(&acc[lane + 64], coef * (double)r1);
         } else {
-          if (lane < R) atomicAdd(&Y[i * R + lane], coef * (double)r0);
-          if (lane + 64 < R) atomicAdd(&Y[i * R + lane + 64], coef * (double)r1);
+          if (lane < R) atomicAdd(&Y[i * R + lane], (YT)(coef * (double)r0));
+          if (lane + 64 < R) atomicAdd(&Y[i * R + lane + 64], (YT)(coef * (double)r1));
         }
       }
     }
@@ -592,7 +592,7 @@ __global__ __launch_bounds__(256) void spmm_kernel(FiberArgs a, const T* __restr
   __syncthreads();
   for (int q = threadIdx.x; q < a.nhot * R; q += blockDim.x) {
     const double v = hot_acc[q];
-    if (v != 0.0) atomicAdd(&Y[(int64_t)a.hot_rows[q / R] * R + q % R], v);
+    if (v != 0.0) atomicAdd(&Y[(int64_t)a.hot_rows[q / R] * R + q % R], (YT)v);
   }
 }
 
@@ -656,15 +656,16 @@ __global__ __launch_bounds__(SCAN_TILE) void mark_compact_kernel(const int32_t* 
 }
 
 // Y[list[p], :] = 0 for p < *count; a wavefront per row.
-__global__ __launch_bounds__(256) void zero_rows_kernel(double* __restrict__ Y, int R,
+template <typename YT>
+__global__ __launch_bounds__(256) void zero_rows_kernel(YT* __restrict__ Y, int R,
                                                         const int32_t* __restrict__ list,
                                                         const int64_t* __restrict__ count) {
   const int lane = threadIdx.x & 63;
   const int64_t n = *count;
   const int64_t nw = (int64_t)gridDim.x * (blockDim.x >> 6);
   for (int64_t p = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); p < n; p += nw) {
-    double* y = Y + (int64_t)list[p] * R;
-    for (int c = lane; c < R; c += 64) y[c] = 0.0;
+    YT* y = Y + (int64_t)list[p] * R;
+    for (int c = lane; c < R; c += 64) y[c] = YT(0);
   }
 }
 
@@ -691,7 +692,7 @@ hipError_t launch_lookup(hipStream_t st, const FiberArgs& a) {
 size_t row_bsum_bytes(int64_t I) { return (size_t)((I + SCAN_TILE - 1) / SCAN_TILE + 2) * 8; }
 
 hipError_t launch_rows(hipStream_t st, const FiberArgs& a, int64_t I, int32_t* mark, int64_t* bsum,
-                       int32_t* list, int64_t* count, double* Y) {
+                       int32_t* list, int64_t* count, void* Y, bool y32) {
   const int64_t nb = I > 0 ? (I + SCAN_TILE - 1) / SCAN_TILE : 1;
   hipLaunchKernelGGL(fill_u32_kernel, dim3((unsigned)std::min<int64_t>(nb * 4, 8192)), dim3(256), 0,
                      st, (uint32_t*)mark, I);
@@ -700,19 +701,26 @@ hipError_t launch_rows(hipStream_t st, const FiberArgs& a, int64_t I, int32_t* m
   hipLaunchKernelGGL(scan_bsum_kernel, dim3(1), dim3(1024), 0, st, bsum, nb);
   hipLaunchKernelGGL(mark_compact_kernel, dim3((unsigned)nb), dim3(SCAN_TILE), 0, st, mark, I, nb,
                      bsum, list, count);
-  hipLaunchKernelGGL(zero_rows_kernel, dim3(2048), dim3(256), 0, st, Y, a.R, list, count);
+  if (y32)
+    hipLaunchKernelGGL(zero_rows_kernel<float>, dim3(2048), dim3(256), 0, st, (float*)Y, a.R, list,
+                       count);
+  else
+    hipLaunchKernelGGL(zero_rows_kernel<double>, dim3(2048), dim3(256), 0, st, (double*)Y, a.R,
+                       list, count);
   return hipGetLastError();
 }
 
 hipError_t launch_spmm(hipStream_t st, krps_precision p, const FiberArgs& a, const void* rows,
                        void* Y) {
   const size_t lds = (size_t)a.nhot * a.R * 8;
+  // the split path's rows are float32 and its Y is float32 (half the
+  // atomic traffic); the float64 and float32 paths form Y in float64
   if (p == KRPS_FP64)
-    hipLaunchKernelGGL(spmm_kernel<double>, dim3(2048), dim3(256), lds, st, a,
+    hipLaunchKernelGGL((spmm_kernel<double, double>), dim3(2048), dim3(256), lds, st, a,
                        (const double*)rows, (double*)Y);
   else
-    hipLaunchKernelGGL(spmm_kernel<float>, dim3(2048), dim3(256), lds, st, a, (const float*)rows,
-                       (double*)Y);
+    hipLaunchKernelGGL((spmm_kernel<float, float>), dim3(2048), dim3(256), lds, st, a,
+                       (const float*)rows, (float*)Y);
   return hipGetLastError();
 }
 
@@ -739,8 +747,8 @@ __global__ void fill_kernel(T* __restrict__ p, int64_t n, T v) {
 // rounded once to the factor type.
 constexpr int GT_ROWS = 64, GT_KC = 32;
 
-template <typename T, int RC>
-__global__ __launch_bounds__(256) void gemm_colsum_kernel(const double* __restrict__ Y,
+template <typename T, int RC, typename YT>
+__global__ __launch_bounds__(256) void gemm_colsum_kernel(const YT* __restrict__ Y,
                                                           const double* __restrict__ Mp,
                                                           T* __restrict__ out,
                                                           const int32_t* __restrict__ list,
@@ -779,7 +787,7 @@ __global__ __launch_bounds__(256) void gemm_colsum_kernel(const double* __restri
       for (int e = threadIdx.x; e < GT_ROWS * GT_KC; e += 256) {
         const int i = e / GT_KC, kk = e % GT_KC;
         const int64_t r = rix[i];
-        Ys[i][kk] = (r >= 0 && k0 + kk < R) ? Y[r * R + k0 + kk] : 0.0;
+        Ys[i][kk] = (r >= 0 && k0 + kk < R) ? (double)Y[r * R + k0 + kk] : 0.0;
       }
       for (int e = threadIdx.x; e < GT_KC * RC; e += 256) {
         const int kk = e / RC, c = e % RC;
@@ -901,14 +909,14 @@ hipError_t launch_fill_f64(hipStream_t st, double* ptr, int64_t n) {
   return hipGetLastError();
 }
 
-template <typename T, int RC>
-static hipError_t run_gemm(hipStream_t st, const double* Y, const double* Mp, void* out,
+template <typename T, int RC, typename YT>
+static hipError_t run_gemm(hipStream_t st, const YT* Y, const double* Mp, void* out,
                            const int32_t* list, const int64_t* count, int R, double* partial,
                            double* sigma) {
-  hipLaunchKernelGGL((gemm_colsum_kernel<T, RC>), dim3(SOLVE_BLOCKS), dim3(256), 0, st, Y, Mp,
+  hipLaunchKernelGGL((gemm_colsum_kernel<T, RC, YT>), dim3(SOLVE_BLOCKS), dim3(256), 0, st, Y, Mp,
                      (T*)out, list, count, R, partial, (const double*)nullptr);
   hipLaunchKernelGGL(sigma_kernel, dim3(R), dim3(256), 0, st, partial, SOLVE_BLOCKS, R, sigma);
-  hipLaunchKernelGGL((gemm_colsum_kernel<T, RC>), dim3(SOLVE_BLOCKS), dim3(256), 0, st, Y, Mp,
+  hipLaunchKernelGGL((gemm_colsum_kernel<T, RC, YT>), dim3(SOLVE_BLOCKS), dim3(256), 0, st, Y, Mp,
                      (T*)out, list, count, R, partial, (const double*)sigma);
   return hipGetLastError();
 }
@@ -922,10 +930,16 @@ hipError_t launch_solve_gemm(hipStream_t st, krps_precision p, const void* Y, co
   hipError_t e = launch_fill(st, p, U, I * R);
   if (e != hipSuccess) return e;
   const double* Yd = (const double*)Y;
+  const float* Yf = (const float*)Y;  // the split path's Y
   if (p == KRPS_FP64) {
     if (R <= 32) return run_gemm<double, 32>(st, Yd, Mp, U, list, count, R, partial, sigma);
     if (R <= 64) return run_gemm<double, 64>(st, Yd, Mp, U, list, count, R, partial, sigma);
     return run_gemm<double, 128>(st, Yd, Mp, U, list, count, R, partial, sigma);
+  }
+  if (p == KRPS_BF16X2) {
+    if (R <= 32) return run_gemm<float, 32>(st, Yf, Mp, U, list, count, R, partial, sigma);
+    if (R <= 64) return run_gemm<float, 64>(st, Yf, Mp, U, list, count, R, partial, sigma);
+    return run_gemm<float, 128>(st, Yf, Mp, U, list, count, R, partial, sigma);
   }
   if (R <= 32) return run_gemm<float, 32>(st, Yd, Mp, U, list, count, R, partial, sigma);
   if (R <= 64) return run_gemm<float, 64>(st, Yd, Mp, U, list, count, R, partial, sigma);
