@@ -276,7 +276,10 @@ krps_status krps_als_sweep(krps_sampler s, krps_tensor t, int64_t J, const doubl
 
 /* fit = 1 - ||T~ - T||_F / ||T||_F for T~ = [sigma; U_1..U_N] (Sec. 4.3),
  * with ||T~||^2 = sigma^T ((*)_k G_k) sigma and <T, T~> over the stored
- * entries.  sigma: device float64 [R].  fit: host out (synchronises). */
+ * entries.  sigma: device float64 [R].  fit: host out (synchronises).
+ * ws: scratch (a solve workspace for any J is large enough); for
+ * KRPS_BF16X2 the G_k are recomputed in float64 from the factors there,
+ * since the split trees' Grams are only ~2^-16 accurate. */
 krps_status krps_fit(krps_sampler s, krps_tensor t, const double* sigma, double* fit, void* ws,
                      size_t ws_bytes);
 

@@ -1516,32 +1516,57 @@ krps_status krps_fit(krps_sampler s, krps_tensor t, const double* sigma, double*
   if (st != KRPS_OK) return st;
   if (sigma == nullptr || fit == nullptr || ws == nullptr)
     return fail(KRPS_EINVAL, "sigma/fit/workspace is NULL");
-  SolvePlan pl = plan_solve(s, 1);
-  const size_t need = align_up(fit_partial_bytes()) + 256;
+  const int R = s->R, N = s->N;
+  // The split path's tree roots carry its bf16 rounding (~2^-16 relative),
+  // which ||T~||^2 - 2 <T, T~> would amplify by ~1 / (1 - fit)^2; the fit
+  // takes float64 Grams of the float32 factors instead (float64 MFMA, the
+  // tree builder without stored nodes over at most 2048 leaves).
+  const bool exact_gram = s->prec == KRPS_BF16X2;
+  size_t need = align_up(fit_partial_bytes()) + 256;
+  const size_t goff = need;
+  TreeShape gts[KRPS_MAX_MODES];
+  size_t scr_off = 0, scr_bytes = 0;
+  if (exact_gram) {
+    need += align_up((size_t)N * R * R * 8);
+    scr_off = need;
+    for (int k = 0; k < N; ++k) {
+      const int64_t Lt = std::min<int64_t>(ceil_div(s->I[k], (int64_t)R), 2048);
+      gts[k].init(s->I[k], (int)ceil_div(s->I[k], Lt));
+      scr_bytes = std::max(scr_bytes, tree_build_scratch_bytes(gts[k].L, R));
+    }
+    need += align_up(scr_bytes);
+  }
   if (ws_bytes < need) return fail(KRPS_EWORKSPACE, "workspace too small for the fit");
   char* w = (char*)ws;
+  hipStream_t stream = s->ctx->stream;
   FitArgs fa;
   memset(&fa, 0, sizeof(fa));
-  fa.N = s->N;
-  fa.R = s->R;
+  fa.N = N;
+  fa.R = R;
   fa.nnz = t->nu;
   fa.cols = t->cols[0];
   fa.vals = t->vals[0];
-  for (int k = 0; k < s->N; ++k) {
+  for (int k = 0; k < N; ++k) {
     fa.U[k] = s->U[k];
     fa.G[k] = s->gram[k];
+    if (exact_gram) {
+      double* gk = (double*)(w + goff) + (size_t)k * R * R;
+      hipError_t e = launch_tree_build(stream, KRPS_FP32, s->U[k], s->I[k], R, gts[k], nullptr, gk,
+                                       (double*)(w + scr_off), scr_bytes, 2);
+      if (e != hipSuccess) return hip_fail(e, "float64 Gram for the fit");
+      fa.G[k] = gk;
+    }
   }
   fa.sigma = sigma;
   double* partial = (double*)w;
   double* out = (double*)(w + align_up(fit_partial_bytes()));
-  hipError_t e = launch_fit(s->ctx->stream, s->prec, fa, partial, out);
+  hipError_t e = launch_fit(stream, s->prec, fa, partial, out);
   if (e != hipSuccess) return hip_fail(e, "fit");
   double h[2];
   KRPS_HIP(hipMemcpyAsync(h, out, 16, hipMemcpyDeviceToHost, s->ctx->stream));
   KRPS_HIP(hipStreamSynchronize(s->ctx->stream));
   const double r2 = t->norm2 + h[1] - 2.0 * h[0];
   *fit = 1.0 - sqrt(r2 > 0 ? r2 : 0.0) / sqrt(t->norm2);
-  (void)pl;
   return KRPS_OK;
 }
 

@@ -209,7 +209,7 @@ def test_one_solve_matches_oracle(env, prec, j):
         np.testing.assert_allclose(sig, sref, rtol=1e-3)
 
 
-@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x2"])
 @pytest.mark.parametrize("R", [3, 8, 12, 128])
 def test_fit_matches_oracle(env, prec, R):
     """R = 3: lane-per-column teams; R = 8, 12, 128: 16-byte row loads
