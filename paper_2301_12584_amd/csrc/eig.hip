@@ -172,11 +172,11 @@ __device__ bool cholesky_inverse_lower(double* A, int R, double* tmp) {
     const double ljj = sqrt(d), inv = 1.0 / ljj;
     for (int i = j + 1 + tid; i < R; i += nt) A[j * RS + i] *= inv;
     __syncthreads();
-    // trailing lower triangle: (i, k), j < k <= i
-    const int m = R - j - 1;
-    for (int t = tid; t < m * m; t += nt) {
-      const int kk = t / m, ii = t % m;
-      if (ii >= kk) A[(j + 1 + kk) * RS + j + 1 + ii] -= A[j * RS + j + 1 + ii] * A[j * RS + j + 1 + kk];
+    // trailing lower triangle: (i, k), j < k <= i; a wavefront per column,
+    // its lanes over the rows
+    for (int k = j + 1 + (tid >> 6); k < R; k += nt >> 6) {
+      const double lk = A[j * RS + k];
+      for (int i = k + (tid & 63); i < R; i += 64) A[k * RS + i] -= A[j * RS + i] * lk;
     }
     if (tid == 0) A[j * RS + j] = ljj;
     __syncthreads();

@@ -575,9 +575,12 @@ __global__ __launch_bounds__(256) void spmm_kernel(FiberArgs a, const T* __restr
       const int hv = a.hot_slot[iv];
       const int n = (int)(e1 - e0);
       for (int t = 0; t < n; ++t) {
-        const double coef = __shfl(xv, t);
-        const int64_t i = __builtin_amdgcn_readfirstlane(__shfl(iv, t));
-        const int hs = __builtin_amdgcn_readfirstlane(__shfl(hv, t));
+        // t is wave-uniform: read lane t's values straight into scalar
+        // registers (no LDS permute on the loop's critical path)
+        const double coef = __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(xv), t),
+                                             __builtin_amdgcn_readlane(__double2loint(xv), t));
+        const int64_t i = __builtin_amdgcn_readlane(iv, t);
+        const int hs = __builtin_amdgcn_readlane(hv, t);
         if (hs >= 0) {
           double* acc = hot_acc + hs * R;
           if (lane < R) atomicAdd(&acc[lane], coef * (double)r0);
