@@ -50,11 +50,14 @@ __device__ __forceinline__ void write_tile(OUT* dst, const ACC& v, int ta, int t
   }
 }
 
-template <int MODE, int NT, int TW, int S>
-__global__ __launch_bounds__(64 * TW) void leaf_run_kernel(const void* __restrict__ Uv, int64_t I,
-                                                           int R, int F, int64_t L, int D,
-                                                           int s_eff, void* __restrict__ nodes_v,
-                                                           double* __restrict__ tops) {
+// The run of wave W of the team; W is a compile-time constant so that each
+// wave's code names only its own tile pairs (and loads and converts only
+// the column tiles those pairs use).
+template <int MODE, int NT, int TW, int S, int W>
+__device__ __forceinline__ void leaf_run_body(const void* __restrict__ Uv, int64_t I, int R, int F,
+                                              int64_t L, int D, int s_eff,
+                                              void* __restrict__ nodes_v,
+                                              double* __restrict__ tops) {
   // storage type of the factor and the nodes; float64 accumulation on the
   // matrix cores except for the bf16 split
   using T = std::conditional_t<MODE == M_F64, double, float>;
@@ -65,7 +68,6 @@ __global__ __launch_bounds__(64 * TW) void leaf_run_kernel(const void* __restric
   const T* __restrict__ U = (const T*)Uv;
   T* __restrict__ nodes = (T*)nodes_v;
   const int lane = threadIdx.x & 63;
-  const int wave = threadIdx.x >> 6;
   const int64_t TR = (int64_t)R * (R + 1) / 2;
   const int64_t run = blockIdx.x;
   const int nrun = 1 << s_eff;
@@ -112,7 +114,7 @@ __global__ __launch_bounds__(64 * TW) void leaf_run_kernel(const void* __restric
               constexpr int pr = decltype(pp)::value;
               constexpr int ta = pair_ta(NT, pr);
               constexpr int tb = pair_tb(NT, pr);
-              if (pr % TW == wave)
+              if constexpr (pr % TW == W)
                 node[pr / TW] = mfma_f64((double)raw[ks][ta], (double)raw[ks][tb], node[pr / TW]);
             });
           }
@@ -154,7 +156,7 @@ __global__ __launch_bounds__(64 * TW) void leaf_run_kernel(const void* __restric
             constexpr int pr = decltype(pp)::value;
             constexpr int ta = pair_ta(NT, pr);
             constexpr int tb = pair_tb(NT, pr);
-            if (pr % TW == wave) {
+            if constexpr (pr % TW == W) {
               ACC a = node[pr / TW];
               if constexpr (MODE == M_SPLIT3) {
                 // smallest terms first
@@ -191,14 +193,14 @@ __global__ __launch_bounds__(64 * TW) void leaf_run_kernel(const void* __restric
       double* dst = tops + run * TR;
       static_for<0, NPAIRS>([&](auto pp) {
         constexpr int pr = decltype(pp)::value;
-        if (pr % TW == wave) write_tile(dst, node[pr / TW], pair_ta(NT, pr), pair_tb(NT, pr), R, lane);
+        if constexpr (pr % TW == W) write_tile(dst, node[pr / TW], pair_ta(NT, pr), pair_tb(NT, pr), R, lane);
       });
     } else {
       if (nodes != nullptr && pos < ((L - 1) >> (D - lev)) + 1) {
         T* dst = nodes + (level_offset(L, D, lev) + (pos >> 1)) * TR;
         static_for<0, NPAIRS>([&](auto pp) {
           constexpr int pr = decltype(pp)::value;
-          if (pr % TW == wave) write_tile(dst, node[pr / TW], pair_ta(NT, pr), pair_tb(NT, pr), R, lane);
+          if constexpr (pr % TW == W) write_tile(dst, node[pr / TW], pair_ta(NT, pr), pair_tb(NT, pr), R, lane);
         });
       }
       static_for<0, S>([&](auto mm) {
@@ -210,6 +212,18 @@ __global__ __launch_bounds__(64 * TW) void leaf_run_kernel(const void* __restric
       });
     }
   }
+}
+
+template <int MODE, int NT, int TW, int S>
+__global__ __launch_bounds__(64 * TW) void leaf_run_kernel(const void* __restrict__ Uv, int64_t I,
+                                                           int R, int F, int64_t L, int D,
+                                                           int s_eff, void* __restrict__ nodes_v,
+                                                           double* __restrict__ tops) {
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  static_for<0, TW>([&](auto ww) {
+    constexpr int W = decltype(ww)::value;
+    if (wave == W) leaf_run_body<MODE, NT, TW, S, W>(Uv, I, R, F, L, D, s_eff, nodes_v, tops);
+  });
 }
 
 __device__ __forceinline__ void unpack_index(int64_t p, int R, int& a, int& b) {
