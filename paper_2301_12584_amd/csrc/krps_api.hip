@@ -588,7 +588,6 @@ krps_status krps_sampler_create(krps_ctx ctx, int N, const int64_t* I, int R, in
   s->scratch = (double*)(w + pl.scratch_off);
   s->scratch_bytes = pl.scratch_bytes;
   s->status = (int32_t*)(w + pl.status_off);
-  if (const char* e = getenv("KRPS_DESCENT_LPS")) s->lps = atoi(e);
   plan_draw(s);
   hipError_t e = hipSetDevice(ctx->device);
   if (e != hipSuccess) {
