@@ -379,7 +379,15 @@ def run_als(torch, krps, ctx, precs, nnz, sweeps_arg, seeds, config=3, init="gau
                        f"Zipf({synth.CONFIGS[config]['alpha']}), R={R}, J={J}, {sweeps} sweeps, "
                        "graph replay",
            "dims": list(dims), "nnz": len_nnz, "R": R, "J": J, "sweeps": sweeps, "init": init}
-    return {"config": cfg, "precisions": out}
+    res = {"config": cfg, "precisions": out}
+    if "bf16x2" in out and "fp64" in out:
+        # the metric's comparison: split path against plain float64 at equal fit
+        a, b = out["bf16x2"], out["fp64"]
+        res["bf16x2_vs_fp64"] = {
+            "sweep_speedup": b["sweep_ms_mean"] / a["sweep_ms_mean"],
+            "final_fit_gap": a["final_fit_mean"] - b["final_fit_mean"],
+            "within_1e-4": abs(a["final_fit_mean"] - b["final_fit_mean"]) <= 1e-4}
+    return res
 
 
 def run_batched(torch, krps, ctx, prec, reps):
