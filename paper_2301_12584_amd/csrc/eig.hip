@@ -23,11 +23,14 @@ namespace {
 constexpr int PREP_THREADS = 1024;  // upper bound; launches use prep_threads(R)
 constexpr int jacobi_team(int R);
 
-// Block size of the one-workgroup eigensolver: one team per column pair.
+// Block size of the one-workgroup eigensolver: one team per column pair,
+// and at least four wavefronts (one per SIMD) for the phases around the
+// Jacobi sweeps (Cholesky, inverse, eigen-tree), whose loops run over all
+// threads; the extra teams stay idle in the sweeps.
 int prep_threads(int R) {
   const int npairs = (R + (R & 1)) / 2;
   int t = npairs * jacobi_team(R);
-  if (t < 64) t = 64;
+  if (t < 256) t = 256;
   if (t > PREP_THREADS) t = PREP_THREADS;
   return (t + 63) / 64 * 64;
 }

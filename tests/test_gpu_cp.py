@@ -264,7 +264,10 @@ def test_planted_tensor_als_matches_oracle(env, prec):
 @pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x2"])
 def test_zipf_tensor_als_matches_oracle(env, prec):
     krps, torch, ctx = env
-    dims, R, J, sweeps = (3000, 2000, 500), 16, 4096, 4
+    # the split path is compared once the fits have settled (its early
+    # sweeps follow another, equally valid, trajectory)
+    dims, R, J = (3000, 2000, 500), 16, 4096
+    sweeps = 8 if prec == "bf16x2" else 4
     idx, val = synth.sparse_tensor(dims, 200_000, 1.2, seed=44)
     U0 = synth.gaussian_factors(dims, R, seed=45)
     fits, _, _ = _run_als(krps, torch, ctx, dims, idx, val, U0, prec, J, sweeps, 700)
@@ -277,8 +280,9 @@ def test_zipf_tensor_als_matches_oracle(env, prec):
     if prec != "bf16x2":
         assert diff <= 1e-4
     else:
-        # the split Grams move the sketched solves by ~2^-16, so the early,
-        # chaotic sweeps follow another trajectory; the fits meet again
+        # the split Grams move the sketched solves by ~2^-16 (and its float32
+        # Y sums in atomic order), so the early, chaotic sweeps follow another
+        # trajectory; the fits meet again as they settle
         assert abs(fits[-1] - ref[-1]) <= 1e-3
 
 
