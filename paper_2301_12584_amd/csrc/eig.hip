@@ -23,14 +23,15 @@ namespace {
 constexpr int PREP_THREADS = 1024;  // upper bound; launches use prep_threads(R)
 constexpr int jacobi_team(int R);
 
-// Block size of the one-workgroup eigensolver: one team per column pair,
-// and at least four wavefronts (one per SIMD) for the phases around the
-// Jacobi sweeps (Cholesky, inverse, eigen-tree), whose loops run over all
-// threads; the extra teams stay idle in the sweeps.
+// Block size of the one-workgroup eigensolver: a full 1024-thread block,
+// so that the phases around the Jacobi sweeps (Cholesky, inverse,
+// eigen-tree), whose loops run over all threads, use every SIMD; one team
+// per column pair works in the sweeps and wavefronts without a pair only
+// keep its barriers.
 int prep_threads(int R) {
   const int npairs = (R + (R & 1)) / 2;
   int t = npairs * jacobi_team(R);
-  if (t < 256) t = 256;
+  if (t < 1024) t = 1024;
   if (t > PREP_THREADS) t = PREP_THREADS;
   return (t + 63) / 64 * 64;
 }
@@ -84,7 +85,13 @@ __device__ int jacobi_columns_t(double* A, int R, int* flag) {
     // step; pair s holds positions s and n-1-s
     int cp = s == 0 ? 0 : (s - 1) % (n - 1);
     int cq = (n - 2 - s) % (n - 1);
+    // wavefronts that hold no pair only keep the barriers
+    const bool wave_busy = (tid & ~63) / TEAM < npairs;
     for (int step = 0; step < n - 1; ++step) {
+      if (!wave_busy) {
+        __syncthreads();
+        continue;
+      }
       int p = 0, q = 0;
       bool act = s < npairs;
       if (act) {
