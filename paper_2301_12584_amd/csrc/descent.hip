@@ -35,22 +35,80 @@ constexpr int DESC_WAVES = 4;  // waves per block
 #endif
 
 // Sum over the LPS lanes of one lane group (groups are aligned, LPS a
-// power of two <= 64); every lane of the group gets the result.
-template <int LPS>
-__device__ __forceinline__ double group_sum(double v) {
-#pragma unroll
-  for (int o = LPS / 2; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
-  return v;
+// power of two <= 64); every lane of the group gets the result.  Within a
+// row of 16 lanes the partners come from DPP (quad swaps, half-row and row
+// mirrors), across rows from the gfx950 row-swap instructions: VALU
+// latency, no LDS round trip.  Every step adds the same two values in both
+// partner lanes, so all lanes of the group end with the same bits and take
+// the same branch.
+__device__ __forceinline__ double swap16_sum(double v) {
+  // permlane16_swap(x, x) returns the even rows of x in both rows of each
+  // pair, and the odd rows in both rows of each pair
+  const int lo = __double2loint(v), hi = __double2hiint(v);
+  const auto l = __builtin_amdgcn_permlane16_swap(lo, lo, false, false);
+  const auto h = __builtin_amdgcn_permlane16_swap(hi, hi, false, false);
+  return __hiloint2double((int)h[0], (int)l[0]) + __hiloint2double((int)h[1], (int)l[1]);
+}
+__device__ __forceinline__ double swap32_sum(double v) {
+  // the same for the two halves of 32 lanes
+  const int lo = __double2loint(v), hi = __double2hiint(v);
+  const auto l = __builtin_amdgcn_permlane32_swap(lo, lo, false, false);
+  const auto h = __builtin_amdgcn_permlane32_swap(hi, hi, false, false);
+  return __hiloint2double((int)h[0], (int)l[0]) + __hiloint2double((int)h[1], (int)l[1]);
 }
 
 template <int LPS>
-__device__ __forceinline__ double group_inclusive_scan(double v, int sl) {
-#pragma unroll
-  for (int o = 1; o < LPS; o <<= 1) {
-    const double t = __shfl_up(v, o, LPS);
-    if (sl >= o) v += t;
-  }
+__device__ __forceinline__ double group_sum(double v) {
+  if constexpr (LPS >= 2) v += dpp_d<0xB1>(v);   // quad_perm [1,0,3,2]
+  if constexpr (LPS >= 4) v += dpp_d<0x4E>(v);   // quad_perm [2,3,0,1]
+  if constexpr (LPS >= 8) v += dpp_d<0x141>(v);  // row_half_mirror
+  if constexpr (LPS >= 16) v += dpp_d<0x140>(v); // row_mirror
+  if constexpr (LPS >= 32) v = swap16_sum(v);
+  if constexpr (LPS >= 64) v = swap32_sum(v);
   return v;
+}
+
+// Lane exchange through DPP where lanes without a source lane (outside the
+// row, or in a row that ROWMASK leaves out) read 0.
+template <int CTRL, int ROWMASK>
+__device__ __forceinline__ double dpp_or0(double v) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, ROWMASK, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, ROWMASK, 0xF, false);
+  return __hiloint2double(hi, lo);
+}
+
+// Inclusive prefix sum over the LPS lanes of each group: shifts within a
+// row of 16 lanes, then the last lane of a row added to the following
+// row(s) of the group.
+template <int LPS>
+__device__ __forceinline__ double group_inclusive_scan(double v, int sl) {
+  constexpr int W = LPS < 16 ? LPS : 16;
+  if constexpr (W > 1) {
+    const double t = dpp_or0<0x111, 0xF>(v);  // row_shr:1
+    if (sl >= 1) v += t;
+  }
+  if constexpr (W > 2) {
+    const double t = dpp_or0<0x112, 0xF>(v);  // row_shr:2
+    if (sl >= 2) v += t;
+  }
+  if constexpr (W > 4) {
+    const double t = dpp_or0<0x114, 0xF>(v);  // row_shr:4
+    if (sl >= 4) v += t;
+  }
+  if constexpr (W > 8) {
+    const double t = dpp_or0<0x118, 0xF>(v);  // row_shr:8
+    if (sl >= 8) v += t;
+  }
+  if constexpr (LPS >= 32) v += dpp_or0<0x142, 0xA>(v);  // row_bcast:15 into rows 1, 3
+  if constexpr (LPS >= 64) v += dpp_or0<0x143, 0xC>(v);  // row_bcast:31 into rows 2, 3
+  return v;
+}
+
+// Value of lane L (a compile-time lane) in every lane.
+template <int L>
+__device__ __forceinline__ double lane_value(double v) {
+  return __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(v), L),
+                          __builtin_amdgcn_readlane(__double2loint(v), L));
 }
 
 // Packed outer product h h^T of the group's float64 vector in hb (LDS),
@@ -97,10 +155,11 @@ __device__ __forceinline__ double node_mass(const Packed<LPS, NP>& P, const doub
 #pragma unroll
     for (int m = 0; m < NP; ++m) g[m] = m < npr ? node[sl + LPS * m] : T(0);
   }
-  double acc = 0;
+  // four partial sums: the dependent chain of FMAs is a quarter as long
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-  for (int m = 0; m < NP; ++m) acc += P.v[m] * (double)g[m];
-  return group_sum<LPS>(acc);
+  for (int m = 0; m < NP; ++m) acc[m & 3] += P.v[m] * (double)g[m];
+  return group_sum<LPS>((acc[0] + acc[1]) + (acc[2] + acc[3]));
 }
 
 // R > 64 (one sample per wavefront, NP == 0): the packed outer product is
@@ -235,7 +294,14 @@ __device__ __forceinline__ int64_t leaf_scan(const T* __restrict__ U, int R, int
     if (found < 0 && m != 0ull) found = base + (__ffsll((long long)m) - 1);
     const unsigned long long pm = (__ballot(valid && r > 0.0) >> (sub * LPS)) & gmask;
     if (pm != 0ull) last_pos = base + (63 - __clzll((long long)pm));
-    low += __shfl(incl, LPS - 1, LPS);
+    if constexpr (LPS == 64) {
+      low += lane_value<63>(incl);
+    } else if constexpr (LPS == 32) {
+      const double t0 = lane_value<31>(incl), t1 = lane_value<63>(incl);
+      low += sub ? t1 : t0;
+    } else {
+      low += __shfl(incl, LPS - 1, LPS);
+    }
   }
   if (found >= 0) return found;
   return last_pos >= 0 ? last_pos : s1 - 1;

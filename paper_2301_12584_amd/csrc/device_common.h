@@ -51,6 +51,14 @@ __device__ __forceinline__ int64_t level_offset(int64_t L, int D, int lev) {
   return off;
 }
 
+// Lane-exchange of a double through the data-parallel primitives (DPP).
+template <int CTRL>
+__device__ __forceinline__ double dpp_d(double v) {
+  const int lo = __builtin_amdgcn_mov_dpp(__double2loint(v), CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(v), CTRL, 0xF, 0xF, false);
+  return __hiloint2double(hi, lo);
+}
+
 // Sum over the 64 lanes of a wave; every lane gets the result.
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll

@@ -36,14 +36,6 @@ int prep_threads(int R) {
   return (t + 63) / 64 * 64;
 }
 
-// Lane-exchange of a double through the data-parallel primitives (DPP).
-template <int CTRL>
-__device__ __forceinline__ double dpp_d(double v) {
-  const int lo = __builtin_amdgcn_mov_dpp(__double2loint(v), CTRL, 0xF, 0xF, false);
-  const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(v), CTRL, 0xF, 0xF, false);
-  return __hiloint2double(hi, lo);
-}
-
 // Sum over an aligned team of TEAM (1, 2, 4, 8 or 16) lanes: quad swaps,
 // then half-row and row mirrors.
 template <int TEAM>
