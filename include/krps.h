@@ -358,7 +358,8 @@ krps_status krps_init_range_finder(krps_sampler s, krps_tensor t, int j, uint64_
 typedef struct {
   size_t idx;      /* int32 [J][N] sampled multi-indices */
   size_t prob;     /* float64 [J] q_d */
-  size_t w;        /* float64 [J] 1/sqrt(J q_d) */
+  size_t w;        /* float64 [J] 1/sqrt(J q_d); 0 where the computed q_d is
+                      not positive (rounding), so that sample adds nothing */
   size_t rows;     /* [J][R] w_d a_d (rows of S A): float64, float32 for KRPS_BF16X2 */
   size_t M;        /* float64 [R][R] (S A)^T S A */
   size_t Mp;       /* float64 [R][R] its pseudo-inverse */

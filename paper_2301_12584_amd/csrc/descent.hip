@@ -407,7 +407,11 @@ __device__ __forceinline__ void descend(const DescentArgs& a, int64_t base,
     const double q = node_mass<double>(P, hb, a.gplus, R, TR, sl, tab) * inv_rank;
     if (active) {
       if (sl == 0 && a.prob != nullptr) a.prob[d] = q;
-      const double w = 1.0 / sqrt((double)J * q);
+      // q > 0 in exact arithmetic; where rounding leaves it at or below zero
+      // (a row almost in the null space of G^+, with split-path Grams at
+      // an ill-conditioned start) the sample gets weight 0 and adds nothing
+      // to the sketched system, rather than an infinite or NaN row
+      const double w = q > 0.0 ? 1.0 / sqrt((double)J * q) : 0.0;
       if (sl == 0 && a.wout != nullptr) a.wout[d] = w;
       const double sc = a.scale_rows ? w : 1.0;
       if (a.rows != nullptr) {

@@ -383,8 +383,9 @@ __global__ __launch_bounds__(256) void merge_insert_kernel(FiberArgs a) {
     double w2 = 0.0;
     if (d < a.J) {
       key = a.lo[d];
-      active = a.hi[d] > key;
       const double wd = a.w[d];
+      // a sample of weight 0 (see the walk) expands nothing
+      active = a.hi[d] > key && wd > 0.0;
       w2 = wd * wd;
     }
     int myslot = -1;
