@@ -226,6 +226,33 @@ __device__ __forceinline__ int64_t walk(const T* __restrict__ nodes, int64_t L, 
   return pos;
 }
 
+// The same walk with the node masses read from a table (LDS) instead of
+// formed from stored nodes: `tm[n]` is the mass of stored node n.
+__device__ __forceinline__ int64_t walk_table(const double* tm, int64_t L, int D, double x,
+                                              double C, double& low_out) {
+  double low = 0.0, high = C;
+  int64_t pos = 0;
+  int64_t off = 1;
+  for (int lev = 1; lev <= D; ++lev) {
+    const int64_t cnt_left = ((L - 1) >> (D - lev + 1)) + 1;
+    const int64_t real = ((L - 1) >> (D - lev)) + 1;
+    double mL = tm[off + pos];
+    mL = mL > 0.0 ? mL : 0.0;
+    const double cut = low + mL;
+    const bool right_exists = 2 * pos + 1 < real;
+    if (cut >= x || !right_exists || high - cut <= 0.0) {
+      high = cut;
+      pos = 2 * pos;
+    } else {
+      low = cut;
+      pos = 2 * pos + 1;
+    }
+    off += cnt_left;
+  }
+  low_out = low;
+  return pos;
+}
+
 // Dot product of the factor row `ur` (R contiguous values) with hb.  The
 // loads of each chunk of up to 32 values are issued together.
 template <int RMAX, typename T>
@@ -350,15 +377,26 @@ __device__ __forceinline__ void descend(const DescentArgs& a, int64_t base,
       }
     }
     // ---- stage 1: eigen-component u from E_k
+    double C1, low;
+    int u;
+    if (st == 0 && md.em != nullptr) {
+      // first drawn mode: h = 1, so E_k's node masses are the same for
+      // every sample; the group walks a copy of them in its LDS slot
+      // (ne <= 2^DE <= RMAX stored nodes)
+      for (int n = sl; n < md.ne; n += LPS) hb[n] = md.em[n];
+      wave_lds_sync();
+      C1 = hb[0];
+      u = (int)walk_table(hb, (int64_t)R, md.DE, d1 * C1, C1, low);
+    } else {
 #pragma unroll
-    for (int i = 0; i < HE; ++i)
-      if (sl + LPS * i < R) hb[sl + LPS * i] = h[i];
-    wave_lds_sync();
-    if constexpr (NP > 0) build_packed(P, hb, tab, TR, sl);
-    const T* __restrict__ E = (const T*)md.E;
-    const double C1 = node_mass<T>(P, hb, E, R, TR, sl, tab);
-    double low;
-    int u = (int)walk(E, (int64_t)R, md.DE, P, hb, R, TR, sl, d1 * C1, C1, low, tab);
+      for (int i = 0; i < HE; ++i)
+        if (sl + LPS * i < R) hb[sl + LPS * i] = h[i];
+      wave_lds_sync();
+      if constexpr (NP > 0) build_packed(P, hb, tab, TR, sl);
+      const T* __restrict__ E = (const T*)md.E;
+      C1 = node_mass<T>(P, hb, E, R, TR, sl, tab);
+      u = (int)walk(E, (int64_t)R, md.DE, P, hb, R, TR, sl, d1 * C1, C1, low, tab);
+    }
     if (u >= R) u = R - 1;
     // ---- stage 2: row t from Z_k with h~ = h (*) V[:, u]
     const T* __restrict__ V = (const T*)md.V + (int64_t)u * R;

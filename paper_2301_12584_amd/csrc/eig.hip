@@ -354,7 +354,8 @@ template <typename T>
 __device__ void prep_eig_body(const GList& gk, int st, int R, const double* __restrict__ ggt,
                               double* __restrict__ lam_out, T* __restrict__ vecs,
                               T* __restrict__ etree, int64_t estride,
-                              int32_t* __restrict__ sweep_out, double* smem) {
+                              int32_t* __restrict__ sweep_out, double* __restrict__ emass,
+                              int64_t enodes, double* smem) {
   const int RS = R + 1;
   double* A = smem;
   double* lam = A + R * RS;
@@ -416,15 +417,32 @@ __device__ void prep_eig_body(const GList& gk, int st, int R, const double* __re
       }
     }
   }
+  // The first drawn mode walks E_k with h = 1, where every stored node's
+  // mass <w, E^v> (w = 1 on the diagonal, 2 off it) is the same for all
+  // samples: one wavefront per node sums it from the stored values.
+  if (st == 0 && emass != nullptr) {
+    __syncthreads();
+    const int lane = tid & 63;
+    const int nw = blockDim.x >> 6;
+    for (int64_t v = tid >> 6; v < enodes; v += nw) {
+      double acc = 0.0;
+      // twice every packed entry, less the diagonal once
+      for (int64_t p = lane; p < TR; p += 64) acc += 2.0 * (double)E[v * TR + p];
+      for (int a = lane; a < R; a += 64) acc -= (double)E[v * TR + packed_index(a, a, R)];
+      acc = wave_sum(acc);
+      if (lane == 0) emass[(int64_t)k * enodes + v] = acc;
+    }
+  }
 }
 
 template <typename T>
 __global__ __launch_bounds__(PREP_THREADS) void prep_eig_kernel(
     GList gk, int R, const double* __restrict__ ggt,
     double* __restrict__ lam_out, T* __restrict__ vecs, T* __restrict__ etree, int64_t estride,
-    int32_t* __restrict__ sweep_out) {
+    int32_t* __restrict__ sweep_out, double* __restrict__ emass, int64_t enodes) {
   extern __shared__ double smem[];
-  prep_eig_body<T>(gk, blockIdx.x, R, ggt, lam_out, vecs, etree, estride, sweep_out, smem);
+  prep_eig_body<T>(gk, blockIdx.x, R, ggt, lam_out, vecs, etree, estride, sweep_out, emass,
+                   enodes, smem);
 }
 
 template <typename T>
@@ -433,7 +451,7 @@ __global__ __launch_bounds__(PREP_THREADS) void prep_eig_batched_kernel(
   extern __shared__ double smem[];
   const EigJob& j = jobs[blockIdx.x];
   prep_eig_body<T>(j.gl, j.st, j.R, j.ggt, j.lam, (T*)j.vecs, (T*)j.etree, j.estride,
-                   j.sweep_out, smem);
+                   j.sweep_out, j.emass, j.enodes, smem);
 }
 
 hipError_t set_lds(const void* fn, size_t bytes) {
@@ -463,7 +481,7 @@ hipError_t launch_prep_gplus2(hipStream_t st, int R, int nmat, const double* con
 hipError_t launch_prep_eig2(hipStream_t st, krps_precision p, int R, int nsteps,
                             const double* const* Gsteps, const int* order, const double* ggt,
                             double* lam, void* vecs, void* etree, int64_t estride,
-                            int32_t* sweep_out) {
+                            int32_t* sweep_out, double* emass, int64_t enodes) {
   GList gl{};
   for (int m = 0; m < nsteps; ++m) {
     gl.G[m] = Gsteps[m];
@@ -475,12 +493,14 @@ hipError_t launch_prep_eig2(hipStream_t st, krps_precision p, int R, int nsteps,
     e = set_lds((const void*)prep_eig_kernel<double>, lds);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(prep_eig_kernel<double>, dim3(nsteps), dim3(prep_threads(R)), lds, st, gl,
-                       R, ggt, lam, (double*)vecs, (double*)etree, estride, sweep_out);
+                       R, ggt, lam, (double*)vecs, (double*)etree, estride, sweep_out,
+                       emass, enodes);
   } else {
     e = set_lds((const void*)prep_eig_kernel<float>, lds);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(prep_eig_kernel<float>, dim3(nsteps), dim3(prep_threads(R)), lds, st, gl,
-                       R, ggt, lam, (float*)vecs, (float*)etree, estride, sweep_out);
+                       R, ggt, lam, (float*)vecs, (float*)etree, estride, sweep_out,
+                       emass, enodes);
   }
   return hipGetLastError();
 }

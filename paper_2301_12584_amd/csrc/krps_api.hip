@@ -69,6 +69,7 @@ struct krps_sampler_s {
   int64_t enodes;
   int64_t estride;  // elements per mode of the eigen-tree region (nodes + zero padding)
   int DE;
+  size_t emass_off;  // per-draw float64 [N][enodes]: E masses at h = 1 (internal)
 };
 
 struct krps_tensor_s {
@@ -171,6 +172,8 @@ void plan_draw(krps_sampler s) {
   off += align_up((size_t)N * R * R * s->elem);
   l.etree = off;
   off += align_up((size_t)N * s->estride * s->elem);
+  s->emass_off = off;
+  off += align_up((size_t)N * s->enodes * 8);
   l.n_enodes = s->enodes;
   l.etree_stride = s->estride;
   s->draw_bytes = off;
@@ -214,7 +217,7 @@ krps_status prepare_draw(krps_sampler s, int exclude, void* ws, DescentArgs& a) 
                                     rank, ggt, s->status);
   if (e != hipSuccess) return hip_fail(e, "prep G+ launch");
   e = launch_prep_eig2(st, s->prec, R, nsteps, mats, order, ggt, lam, vecs, etree, s->estride,
-                       rank);
+                       rank, (double*)(w + s->emass_off), s->enodes);
   if (e != hipSuccess) return hip_fail(e, "prep eig launch");
   fill_descent_args(s, exclude, ws, a);
   return KRPS_OK;
@@ -243,11 +246,13 @@ void fill_descent_args(krps_sampler s, int exclude, void* ws, DescentArgs& a) {
     m.Z = s->nodes[k];
     m.E = w + s->lay.etree + (size_t)k * s->estride * s->elem;
     m.V = w + s->lay.vecs + (size_t)k * R * R * s->elem;
+    m.em = (const double*)(w + s->emass_off) + (size_t)k * s->enodes;
     m.I = s->I[k];
     m.L = s->shape[k].L;
     m.F = s->shape[k].F;
     m.D = s->shape[k].D;
     m.DE = s->DE;
+    m.ne = (int32_t)s->enodes;
   }
   a.gplus = gplus_packed;
   a.rank = rank;
@@ -860,6 +865,8 @@ krps_status krps_sample_batched_prepare(krps_ctx ctx, int P, const krps_sampler*
       ej.etree = dw + sp->lay.etree;
       ej.estride = sp->estride;
       ej.sweep_out = pj.rank;
+      ej.emass = (double*)(dw + sp->emass_off);
+      ej.enodes = sp->enodes;
       eig.push_back(ej);
       eprob.push_back(p);
     }

@@ -56,9 +56,11 @@ struct ModeDesc {
   const void* Z;      // factor tree nodes
   const void* E;      // eigen tree nodes (per draw)
   const void* V;      // eigenvectors, [u][R] (per draw)
+  const double* em;   // masses of E's stored nodes at h = 1 (per draw; written
+                      // for the first drawn mode only) or null
   int64_t I, L;
   int32_t F, D;
-  int32_t DE, pad;
+  int32_t DE, ne;     // eigen-tree depth and stored nodes
 };
 
 struct DescentArgs {
@@ -113,6 +115,8 @@ struct EigJob {
   void* etree;
   int64_t estride;  // elements from one mode's eigen-tree to the next
   int32_t* sweep_out;
+  double* emass;    // [N][enodes]: the first drawn mode's E masses at h = 1
+  int64_t enodes;
 };
 
 // One problem of a batched draw: its walk arguments, its packed-index
@@ -190,7 +194,7 @@ hipError_t launch_prep_gplus2(hipStream_t st, int R, int nmat, const double* con
 hipError_t launch_prep_eig2(hipStream_t st, krps_precision p, int R, int nsteps,
                             const double* const* Gsteps, const int* order, const double* ggt,
                             double* lam, void* vecs, void* etree, int64_t estride,
-                            int32_t* sweep_out);
+                            int32_t* sweep_out, double* emass, int64_t enodes);
 // rank points at two int32: the rank and the Jacobi sweep count.
 hipError_t launch_pinv(hipStream_t st, int R, const double* M, double* Mp_full, int32_t* rank);
 
