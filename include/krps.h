@@ -23,7 +23,17 @@
  *     references where stated and never frees them.
  *   - All device memory the library needs beyond its inputs and outputs
  *     comes from caller-provided workspaces (size queries below); the
- *     library itself does not allocate device memory.
+ *     library itself does not allocate device memory.  Host-side it
+ *     allocates its handles, the pinned staging buffers of the batched
+ *     draw (owned by the context, grown on demand, freed by
+ *     krps_ctx_destroy) and the HIP graph of a captured sweep (owned by
+ *     the sampler).
+ *   - Uniform streams generated in the kernels (the *_seeded calls) are
+ *     Philox4x64-10 (Salmon et al., SC'11) under key (seed, 0): sample d,
+ *     mode k of a draw uses counter (ctr_base + d, k, c2, 0), c2 = 0 for a
+ *     plain draw and c2 = sweep * N + j for the solve of mode j in ALS sweep
+ *     `sweep`; output words x0, x1 give the two uniforms ((x >> 11) + 0.5)
+ *     2^-53 of the first and second stage.
  *   - All work is enqueued on the context's HIP stream and is asynchronous;
  *     results are valid after the stream is synchronised.  Host-side
  *     validation happens before anything is enqueued.
@@ -40,7 +50,7 @@
 extern "C" {
 #endif
 
-#define KRPS_MAX_MODES 8
+#define KRPS_MAX_MODES 10
 #define KRPS_MAX_R 128
 
 typedef enum {
@@ -74,7 +84,8 @@ typedef struct krps_tensor_s* krps_tensor;
  * owned.  Does not initialise the GPU beyond selecting the device. */
 krps_status krps_ctx_create(int device, void* hip_stream, krps_ctx* out);
 krps_status krps_ctx_destroy(krps_ctx ctx);
-/* Synchronises the context stream and reports device-side errors. */
+/* Synchronises the context stream (device-side errors of a sampler are
+ * read by krps_sampler_check). */
 krps_status krps_ctx_sync(krps_ctx ctx);
 /* Thread-local message of the last error (never NULL). */
 const char* krps_last_error(void);
@@ -109,6 +120,15 @@ krps_status krps_sampler_create(krps_ctx ctx, int N, const int64_t* I, int R, in
 /* U[j] changed in place: rebuild Z_j and G_j (O(I_j R^2), Thm 1.1 part 1). */
 krps_status krps_sampler_refresh(krps_sampler s, int j);
 krps_status krps_sampler_destroy(krps_sampler s);
+
+/* Synchronises the context stream, reads and clears the sampler's device
+ * status.  Returns KRPS_EZERO if a preparation met a zero product
+ * (C = 0), KRPS_ENUMERIC if a kernel met a non-finite value, since the
+ * last check.  *zero_weight (may be NULL) receives the number of sampled
+ * rows since the last check whose computed probability q_d was not
+ * positive: q_d > 0 in exact arithmetic (Sec. 2.1), so only rounding can
+ * do that; such a row was given weight 0 in its solve. */
+krps_status krps_sampler_check(krps_sampler s, int64_t* zero_weight);
 
 /* ------------------------------------------------------------------ */
 /* Sampling: Algorithm 2 (KRPSample)                                   */
@@ -202,6 +222,15 @@ krps_status krps_sample_batched_draw(krps_ctx ctx, int P, const krps_sampler* s,
                                      const double* const* uniforms, int32_t* const* idx,
                                      double* const* prob, void* ws, size_t ws_bytes);
 
+/* krps_sample_batched with in-kernel uniforms: problem p's walk generates
+ * them from seed[p] and ctr_base[p] (host arrays) as krps_sample_seeded
+ * does (counter word 2 = 0).  Other arguments as for krps_sample_batched. */
+krps_status krps_sample_batched_seeded(krps_ctx ctx, int P, const krps_sampler* s,
+                                       const int* exclude, const int64_t* J,
+                                       const uint64_t* seed, const uint64_t* ctr_base,
+                                       int32_t* const* idx, double* const* prob, void* ws,
+                                       size_t ws_bytes);
+
 /* Probability q of M given multi-indices (idx [M][N], the excluded column
  * is ignored) under the leverage distribution of the (excluded) product. */
 krps_status krps_row_prob(krps_sampler s, int exclude, int64_t M, const int32_t* idx,
@@ -249,7 +278,8 @@ krps_status krps_solve_workspace_bytes(krps_sampler s, krps_tensor t, int64_t J,
 
 /* The initial normalisation of Algorithm 6 for factor j: sigma = column norms of U_j, then
  * U_j[:, i] /= sigma[i] (zero columns stay zero) and Z_j, G_j are rebuilt.
- * sigma: device float64 [R] out (may be NULL). */
+ * sigma: device float64 [R] out (may be NULL).  ws: a solve workspace (any
+ * J); only its head below krps_solve_layout's pieces is written. */
 krps_status krps_normalize_factor(krps_sampler s, int j, double* sigma, void* ws, size_t ws_bytes);
 
 /* One STS-CP solve (Sec. 3.3; the factor update of Algorithm 6 with the sampled
@@ -265,6 +295,13 @@ krps_status krps_normalize_factor(krps_sampler s, int j, double* sigma, void* ws
 krps_status krps_sketched_solve(krps_sampler s, krps_tensor t, int j, int64_t J,
                                 const double* uniforms, double* sigma, void* ws, size_t ws_bytes);
 
+/* krps_sketched_solve with uniforms generated in the walk: Philox4x64-10 of
+ * counter (ctr_base + d, k, sweep * N + j, 0) under key (seed, 0) for
+ * sample d and mode k (general conventions above). */
+krps_status krps_sketched_solve_seeded(krps_sampler s, krps_tensor t, int j, int64_t J,
+                                       uint64_t seed, uint64_t ctr_base, uint64_t sweep,
+                                       double* sigma, void* ws, size_t ws_bytes);
+
 /* One ALS sweep: krps_sketched_solve for j = 0..N-1 in order (the inner
  * loop of Algorithm 6).  uniforms: device float64 [N][J][N][2], block j for solve j.
  * With use_graph != 0 the sweep is captured once into a HIP graph (keyed by
@@ -274,12 +311,23 @@ krps_status krps_sketched_solve(krps_sampler s, krps_tensor t, int j, int64_t J,
 krps_status krps_als_sweep(krps_sampler s, krps_tensor t, int64_t J, const double* uniforms,
                            double* sigma, void* ws, size_t ws_bytes, int use_graph);
 
+/* krps_als_sweep with uniforms generated in the walks: solve j of sweep
+ * `sweep` uses counter word 2 = sweep * N + j (as
+ * krps_sketched_solve_seeded).  The sweep's offset sweep * N is written to
+ * a word of the workspace by a one-thread kernel enqueued before the sweep,
+ * so with use_graph != 0 one captured graph (keyed by t, sigma, ws, J, the
+ * walk shape, seed and ctr_base) is replayed for every sweep. */
+krps_status krps_als_sweep_seeded(krps_sampler s, krps_tensor t, int64_t J, uint64_t seed,
+                                  uint64_t ctr_base, uint64_t sweep, double* sigma, void* ws,
+                                  size_t ws_bytes, int use_graph);
+
 /* fit = 1 - ||T~ - T||_F / ||T||_F for T~ = [sigma; U_1..U_N] (Sec. 4.3),
  * with ||T~||^2 = sigma^T ((*)_k G_k) sigma and <T, T~> over the stored
  * entries.  sigma: device float64 [R].  fit: host out (synchronises).
- * ws: scratch (a solve workspace for any J is large enough); for
- * KRPS_BF16X2 the G_k are recomputed in float64 from the factors there,
- * since the split trees' Grams are only ~2^-16 accurate. */
+ * ws: a solve workspace (any J); only its head, below every piece of
+ * krps_solve_layout, is written, so the last solve's pieces stay valid.
+ * For KRPS_BF16X2 the G_k are recomputed in float64 from the factors
+ * there, since the split trees' Grams are only ~2^-16 accurate. */
 krps_status krps_fit(krps_sampler s, krps_tensor t, const double* sigma, double* fit, void* ws,
                      size_t ws_bytes);
 
@@ -350,7 +398,9 @@ krps_status krps_autotune(krps_ctx ctx, int N, const int64_t* I, int R, krps_pre
  * the Box-Muller pair (cosine, sine) gives columns 2q and 2q + 1.  Then
  * the columns are normalised as krps_normalize_factor does (sigma out,
  * may be NULL) and Z_j is rebuilt.  U[j] is overwritten.  N <= 5
- * (KRPS_EUNSUPPORTED otherwise).  ws: a solve workspace (any J). */
+ * (KRPS_EUNSUPPORTED otherwise).  ws: a solve workspace (any J); the
+ * float64 accumulation of mat(T, j) S overwrites the pieces of
+ * krps_solve_layout. */
 krps_status krps_init_range_finder(krps_sampler s, krps_tensor t, int j, uint64_t seed,
                                    double* sigma, void* ws, size_t ws_bytes);
 
@@ -415,6 +465,26 @@ typedef struct {
 } krps_draw_layout;
 
 krps_status krps_draw_layout_query(krps_sampler s, krps_draw_layout* out);
+
+/* One region of a workspace, as planned by the library. */
+typedef struct {
+  int32_t workspace;  /* 0 sampler, 1 per-draw, 2 solve, 3 tensor, 4 batched
+                         (the sampler once per exclusion), 5 least squares (n = 1) */
+  char name[28];
+  uint64_t offset;    /* bytes from the workspace start */
+  uint64_t bytes;     /* up to the next region */
+  uint64_t need;      /* the largest extent a kernel writes or reads in it,
+                         from the launch geometry (tree-build ping-pong
+                         buffers, reads past a node's end) */
+} krps_region;
+
+/* The regions of every workspace the library plans for N factors of heights
+ * I (also the tensor's dims), R columns, leaf size F (0 = R), precision p,
+ * a tensor of nnz entries and solves of J samples.  Host only: touches no
+ * device.  Writes min(cap, count) regions to out (may be NULL) and the
+ * number of regions to *count.  For tests of the workspace planning. */
+krps_status krps_workspace_regions(int N, const int64_t* I, int R, int F, krps_precision p,
+                                   int64_t nnz, int64_t J, krps_region* out, int cap, int* count);
 
 #ifdef __cplusplus
 }

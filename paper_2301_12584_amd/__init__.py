@@ -47,6 +47,11 @@ class Tune(ctypes.Structure):
                 ("draw_ms", ctypes.c_double), ("from_cache", ctypes.c_int32)]
 
 
+class Region(ctypes.Structure):
+    _fields_ = [("workspace", ctypes.c_int32), ("name", ctypes.c_char * 28),
+                ("offset", ctypes.c_uint64), ("bytes", ctypes.c_uint64), ("need", ctypes.c_uint64)]
+
+
 class SolveLayout(ctypes.Structure):
     _fields_ = [(n, ctypes.c_size_t) for n in ("idx", "prob", "w", "rows", "M", "Mp", "Y", "draw",
                                                "yrows", "nyrows")]
@@ -118,6 +123,16 @@ def lib():
         "krps_als_sweep": (c.c_int, [P, P, c.c_int64, P, P, P, c.c_size_t, c.c_int]),
         "krps_fit": (c.c_int, [P, P, P, c.POINTER(c.c_double), P, c.c_size_t]),
         "krps_sampler_tree_info": (c.c_int, [P, c.c_int, c.POINTER(TreeInfo)]),
+        "krps_sampler_check": (c.c_int, [P, c.POINTER(c.c_int64)]),
+        "krps_sketched_solve_seeded": (c.c_int, [P, P, c.c_int, c.c_int64, c.c_uint64,
+                                                 c.c_uint64, c.c_uint64, P, P, c.c_size_t]),
+        "krps_als_sweep_seeded": (c.c_int, [P, P, c.c_int64, c.c_uint64, c.c_uint64, c.c_uint64,
+                                            P, P, c.c_size_t, c.c_int]),
+        "krps_sample_batched_seeded": (c.c_int, [P, c.c_int, P, P, P, P, P, P, P, P,
+                                                 c.c_size_t]),
+        "krps_workspace_regions": (c.c_int, [c.c_int, c.POINTER(c.c_int64), c.c_int, c.c_int,
+                                             c.c_int, c.c_int64, c.c_int64, c.POINTER(Region),
+                                             c.c_int, c.POINTER(c.c_int)]),
         "krps_draw_layout_query": (c.c_int, [P, c.POINTER(DrawLayout)]),
     }
     for name, (res, args) in sig.items():
@@ -158,6 +173,21 @@ class Context:
         if getattr(self, "handle", None) is not None and _lib is not None:
             _lib.krps_ctx_destroy(self.handle)
             self.handle = None
+
+
+def workspace_regions(dims, R, F=0, precision="fp32", nnz=1, J=1):
+    """Regions of every workspace the library plans (host only): a list of
+    dicts with workspace, name, offset, bytes and need."""
+    n = len(dims)
+    arr = (ctypes.c_int64 * n)(*[int(d) for d in dims])
+    cnt = ctypes.c_int()
+    check(lib().krps_workspace_regions(n, arr, int(R), int(F), PRECISION[precision], int(nnz),
+                                       int(J), None, 0, ctypes.byref(cnt)))
+    buf = (Region * cnt.value)()
+    check(lib().krps_workspace_regions(n, arr, int(R), int(F), PRECISION[precision], int(nnz),
+                                       int(J), buf, cnt.value, ctypes.byref(cnt)))
+    return [{"workspace": r.workspace, "name": r.name.decode(), "offset": r.offset,
+             "bytes": r.bytes, "need": r.need} for r in buf]
 
 
 def sampler_workspace_bytes(dims, R, F=0, precision="fp32"):
@@ -203,6 +233,14 @@ class Sampler:
 
     def refresh(self, j):
         check(lib().krps_sampler_refresh(self.handle, int(j)))
+
+    def check_status(self):
+        """Reads and clears the device status (raises on a zero product or a
+        non-finite value); returns the number of sampled rows since the last
+        check whose computed probability was not positive."""
+        n = ctypes.c_int64()
+        check(lib().krps_sampler_check(self.handle, ctypes.byref(n)))
+        return n.value
 
     def sample(self, exclude, uniforms, prob=True, rows=False, check_status=False):
         """Draws ``J = uniforms.shape[0]`` samples; returns ``(idx, prob, rows)``."""
@@ -359,6 +397,27 @@ class Batch:
         return idx, prob
 
 
+    def sample_seeded(self, J, seeds, ctr_bases, with_prob=True):
+        """krps_sample_batched_seeded: problem p draws ``J[p]`` samples with
+        uniforms generated in the walk from ``seeds[p]``, ``ctr_bases[p]``."""
+        torch = self.ctx.torch
+        dev = self.ctx.device
+        P = self.P
+        idx = [torch.empty((int(J[p]), sp.N), dtype=torch.int32, device=dev)
+               for p, sp in enumerate(self.samplers)]
+        prob = [torch.empty(int(J[p]), dtype=torch.float64, device=dev) if with_prob else None
+                for p in range(P)]
+        Ja = (ctypes.c_int64 * P)(*[int(j) for j in J])
+        sa = (ctypes.c_uint64 * P)(*[int(x) for x in seeds])
+        ca = (ctypes.c_uint64 * P)(*[int(x) for x in ctr_bases])
+        ia = (ctypes.c_void_p * P)(*[i.data_ptr() for i in idx])
+        pa = (ctypes.c_void_p * P)(*[(q.data_ptr() if q is not None else 0) for q in prob])
+        check(lib().krps_sample_batched_seeded(self.ctx.handle, P, self._h, self._ex, Ja, sa, ca,
+                                               ia, pa if with_prob else None, _ptr(self.ws),
+                                               self.ws.numel()))
+        return idx, prob
+
+
 def sample_batched(ctx: "Context", samplers, excludes, uniforms, with_prob=True):
     """Algorithm 2 for many samplers in one batched call.  ``uniforms[p]``:
     CUDA float64 ``[J_p, N_p, 2]``.  Returns ``(idx_list, prob_list)``."""
@@ -495,6 +554,23 @@ class CPALS:
         check(lib().krps_als_sweep(self.S.handle, self.T.handle, self.J, _ptr(uniforms),
                                    _ptr(self.sigma), _ptr(self.ws), self.ws.numel(),
                                    1 if use_graph else 0))
+
+    def solve_seeded(self, j, seed, ctr_base, sweep):
+        """One solve with in-kernel uniforms (counter word 2 = sweep * N + j)."""
+        check(lib().krps_sketched_solve_seeded(self.S.handle, self.T.handle, int(j), self.J,
+                                               ctypes.c_uint64(int(seed)),
+                                               ctypes.c_uint64(int(ctr_base)),
+                                               ctypes.c_uint64(int(sweep)), _ptr(self.sigma),
+                                               _ptr(self.ws), self.ws.numel()))
+
+    def sweep_seeded(self, seed, ctr_base, sweep, use_graph=False):
+        """One sweep with in-kernel uniforms; a captured graph is replayed for
+        every sweep number."""
+        check(lib().krps_als_sweep_seeded(self.S.handle, self.T.handle, self.J,
+                                          ctypes.c_uint64(int(seed)),
+                                          ctypes.c_uint64(int(ctr_base)),
+                                          ctypes.c_uint64(int(sweep)), _ptr(self.sigma),
+                                          _ptr(self.ws), self.ws.numel(), 1 if use_graph else 0))
 
     def fit(self):
         v = ctypes.c_double()

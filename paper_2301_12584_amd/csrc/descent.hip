@@ -367,9 +367,12 @@ __device__ __forceinline__ void descend(const DescentArgs& a, int64_t base,
         d2 = a.u01[(d * N + k) * 2 + 1];
       }
     } else {
-      // in-kernel uniforms: Philox4x64-10 of (ctr_base + d, k, 0, 0) under
-      // (seed, 0); word 0 drives stage 1, word 1 stage 2
-      uint64_t c[4] = {a.ctr_base + (uint64_t)d, (uint64_t)k, 0, 0};
+      // in-kernel uniforms: Philox4x64-10 of (ctr_base + d, k, c2, 0) under
+      // (seed, 0), c2 = ctr2 (+ the device word ctr2_dev when given: the
+      // sweep's offset, set outside a captured sweep); word 0 drives stage 1,
+      // word 1 stage 2
+      const uint64_t c2 = a.ctr2 + (a.ctr2_dev != nullptr ? *a.ctr2_dev : 0ull);
+      uint64_t c[4] = {a.ctr_base + (uint64_t)d, (uint64_t)k, c2, 0};
       philox4x64_10(c, a.seed, 0);
       if (active) {
         d1 = u01_of_word(c[0]);
@@ -448,8 +451,17 @@ __device__ __forceinline__ void descend(const DescentArgs& a, int64_t base,
       // q > 0 in exact arithmetic; where rounding leaves it at or below zero
       // (a row almost in the null space of G^+, with split-path Grams at
       // an ill-conditioned start) the sample gets weight 0 and adds nothing
-      // to the sketched system, rather than an infinite or NaN row
-      const double w = q > 0.0 ? 1.0 / sqrt((double)J * q) : 0.0;
+      // to the sketched system, rather than an infinite or NaN row.  Such
+      // samples are counted in the second status word; a non-finite q sets
+      // the numeric-error flag.
+      const bool qok = q > 0.0 && q <= __DBL_MAX__;
+      const double w = qok ? 1.0 / sqrt((double)J * q) : 0.0;
+      if (sl == 0 && !qok) {
+        if (q <= 0.0)
+          atomicAdd(a.status + 1, 1);
+        else
+          atomicOr(a.status, ST_NUMERIC);
+      }
       if (sl == 0 && a.wout != nullptr) a.wout[d] = w;
       const double sc = a.scale_rows ? w : 1.0;
       if (a.rows != nullptr) {

@@ -43,6 +43,20 @@ struct krps_ctx_s {
   bool staged_pending[2] = {false, false};
 };
 
+struct GraphKey {
+  const void* t = nullptr;
+  const void* uniforms = nullptr;
+  const void* sigma = nullptr;
+  const void* ws = nullptr;
+  int64_t J = -1;
+  int lps = -1;
+  uint64_t seed = 0, ctr_base = 0;
+  bool operator==(const GraphKey& o) const {
+    return t == o.t && uniforms == o.uniforms && sigma == o.sigma && ws == o.ws && J == o.J &&
+           lps == o.lps && seed == o.seed && ctr_base == o.ctr_base;
+  }
+};
+
 struct krps_sampler_s {
   krps_ctx ctx;
   int N, R, F;
@@ -61,10 +75,9 @@ struct krps_sampler_s {
   const void* prepared_ws = nullptr;  // ws of the last preparation
   int prepared_exclude = -2;
   int lps = 0;                         // descent lanes per sample (0 = default)
-  // captured ALS sweep
+  // captured ALS sweep and what its kernels' arguments were made from
   hipGraphExec_t sweep_exec = nullptr;
-  const void* g_key[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
-  int64_t g_J = -1;
+  GraphKey gkey;
   size_t draw_bytes;
   int64_t enodes;
   int64_t estride;  // elements per mode of the eigen-tree region (nodes + zero padding)
@@ -109,7 +122,7 @@ std::vector<int> lps_choices(int R) {
 }
 
 krps_status check_dims(int N, const int64_t* I, int R) {
-  if (N < 1 || N > KRPS_MAX_MODES) return fail(KRPS_EINVAL, "N must be in [1, 8]");
+  if (N < 1 || N > KRPS_MAX_MODES) return fail(KRPS_EINVAL, "N must be in [1, KRPS_MAX_MODES]");
   if (R < 1 || R > KRPS_MAX_R) return fail(KRPS_EINVAL, "R must be in [1, 128]");
   if (I == nullptr) return fail(KRPS_EINVAL, "I is NULL");
   for (int j = 0; j < N; ++j)
@@ -325,9 +338,55 @@ TensorPlan plan_tensor(int N, const int64_t* dims, int64_t nnz) {
 
 // ------------------------------------------------------------- solve plan
 
+// The head of a solve workspace: scratch of the calls that do not depend on
+// J (the fit, the normalisation of a factor), below every piece of
+// krps_solve_layout, so that those calls leave the last solve's pieces intact.
+struct SolveHead {
+  size_t fitp, fitout, fitg, fitscr, fitscr_bytes, npart, nsig, ctrw, total;
+  TreeShape gts[KRPS_MAX_MODES];  // float64 Grams of the fit on the split path
+};
+
+// Leaf shape of the fit's float64 Gram of factor k: at most 2048 leaves.
+TreeShape fit_gram_shape(int64_t I, int R) {
+  const int64_t Lt = std::min<int64_t>(ceil_div(I, (int64_t)R), 2048);
+  TreeShape ts;
+  ts.init(I, (int)ceil_div(I, Lt));
+  return ts;
+}
+
+SolveHead plan_head(const krps_sampler_s* s) {
+  SolveHead h;
+  const int R = s->R, N = s->N;
+  size_t off = 0;
+  h.fitp = off;
+  off += align_up(fit_partial_bytes());
+  h.fitout = off;
+  off += 256;
+  h.fitg = off;
+  h.fitscr_bytes = 0;
+  if (s->prec == KRPS_BF16X2) {
+    off += align_up((size_t)N * R * R * 8);
+    for (int k = 0; k < N; ++k) {
+      h.gts[k] = fit_gram_shape(s->I[k], R);
+      h.fitscr_bytes = std::max(h.fitscr_bytes, tree_build_scratch_bytes(h.gts[k].L, R));
+    }
+  }
+  h.fitscr = off;
+  off += align_up(h.fitscr_bytes);
+  h.npart = off;
+  off += align_up(solve_partial_bytes(R));
+  h.nsig = off;
+  off += align_up((size_t)R * 8);
+  h.ctrw = off;
+  off += 256;
+  h.total = off;
+  return h;
+}
+
 struct SolvePlan {
   krps_solve_layout lay;
-  size_t lo, hi, cnt, start, rank, partial, gscratch, gscratch_bytes, fitp, fitout, sig;
+  SolveHead head;
+  size_t lo, hi, cnt, start, rank, partial, gscratch, gscratch_bytes;
   size_t coef, slot, hkey, hW, hrep, rflag, rpos, rep, rstart, bsum, ymark, ybsum;
   int64_t H;
   int hbits;
@@ -335,14 +394,14 @@ struct SolvePlan {
   int64_t Imax;
 };
 
-SolvePlan plan_solve(krps_sampler s, int64_t J) {
+SolvePlan plan_solve(const krps_sampler_s* s, int64_t J) {
   SolvePlan pl;
   const int R = s->R, N = s->N;
-  const int es = s->elem;
   int64_t Imax = 0;
   for (int j = 0; j < N; ++j) Imax = s->I[j] > Imax ? s->I[j] : Imax;
   pl.Imax = Imax;
-  size_t off = 0;
+  pl.head = plan_head(s);
+  size_t off = pl.head.total;
   krps_solve_layout& l = pl.lay;
   l.draw = off;
   off += align_up(s->draw_bytes);
@@ -409,12 +468,6 @@ SolvePlan plan_solve(krps_sampler s, int64_t J) {
   pl.gscratch = off;
   pl.gscratch_bytes = tree_build_scratch_bytes(tm.L, R);
   off += align_up(pl.gscratch_bytes);
-  pl.fitp = off;
-  off += align_up(fit_partial_bytes());
-  pl.fitout = off;
-  off += 256;
-  pl.sig = off;
-  off += align_up((size_t)R * 8);
   pl.total = off;
   return pl;
 }
@@ -427,8 +480,17 @@ krps_status check_pair(krps_sampler s, krps_tensor t) {
   return KRPS_OK;
 }
 
+// Where the walk of a solve takes its uniforms: the device array u01
+// ([J][N][2]), or, when u01 is null, Philox4x64-10 of counter
+// (ctr_base + d, k, ctr2 + *ctr2_dev, 0) under key (seed, 0).
+struct UniformSrc {
+  const double* u01 = nullptr;
+  uint64_t seed = 0, ctr_base = 0, ctr2 = 0;
+  const uint64_t* ctr2_dev = nullptr;
+};
+
 // Enqueues one sketched solve of mode j.
-krps_status enqueue_solve(krps_sampler s, krps_tensor t, int j, int64_t J, const double* uniforms,
+krps_status enqueue_solve(krps_sampler s, krps_tensor t, int j, int64_t J, const UniformSrc& us,
                           double* sigma, char* w, const SolvePlan& pl) {
   const int R = s->R, N = s->N;
   hipStream_t st = s->ctx->stream;
@@ -440,7 +502,11 @@ krps_status enqueue_solve(krps_sampler s, krps_tensor t, int j, int64_t J, const
   // Gram M and Y are then formed in float64), float32 for the bf16 split
   const bool split = s->prec == KRPS_BF16X2;
   a.J = J;
-  a.u01 = uniforms;
+  a.u01 = us.u01;
+  a.seed = us.seed;
+  a.ctr_base = us.ctr_base;
+  a.ctr2 = us.ctr2;
+  a.ctr2_dev = us.ctr2_dev;
   a.idx = (int32_t*)(w + l.idx);
   a.prob = (double*)(w + l.prob);
   if (split)
@@ -506,6 +572,105 @@ krps_status enqueue_solve(krps_sampler s, krps_tensor t, int j, int64_t J, const
                         nyrows, R, (double*)(w + pl.partial), sigma);
   if (e != hipSuccess) return hip_fail(e, "solve GEMM");
   return build_tree(s, j);
+}
+
+// Validation and enqueue of one solve (krps_sketched_solve[_seeded]).
+krps_status solve_entry(krps_sampler s, krps_tensor t, int j, int64_t J, const UniformSrc& us,
+                        double* sigma, void* ws, size_t ws_bytes) {
+  krps_status st = check_pair(s, t);
+  if (st != KRPS_OK) return st;
+  if (s->N < 2) return fail(KRPS_EINVAL, "a solve needs N >= 2");
+  if (j < 0 || j >= s->N) return fail(KRPS_EINVAL, "j out of range");
+  if (J < 1) return fail(KRPS_EINVAL, "J must be >= 1");
+  if (sigma == nullptr || ws == nullptr) return fail(KRPS_EINVAL, "sigma/workspace is NULL");
+  SolvePlan pl = plan_solve(s, J);
+  if (ws_bytes < pl.total) return fail(KRPS_EWORKSPACE, "solve workspace too small");
+  KRPS_HIP(hipSetDevice(s->ctx->device));
+  st = enqueue_solve(s, t, j, J, us, sigma, (char*)ws, pl);
+  s->prepared_ws = nullptr;
+  return st;
+}
+
+// One sweep, from a uniform buffer [N][J][N][2] (uniforms != null) or from
+// in-kernel Philox with counter word 2 = sweep * N + j.  The seeded form
+// reads sweep * N from a word of the workspace head, written by a one-thread
+// kernel enqueued before the sweep (outside any captured graph), so one
+// captured graph serves every sweep.
+krps_status sweep_entry(krps_sampler s, krps_tensor t, int64_t J, const double* uniforms,
+                        uint64_t seed, uint64_t ctr_base, uint64_t sweep, double* sigma, void* ws,
+                        size_t ws_bytes, int use_graph) {
+  krps_status st = check_pair(s, t);
+  if (st != KRPS_OK) return st;
+  if (s->N < 2) return fail(KRPS_EINVAL, "a sweep needs N >= 2");
+  if (J < 1) return fail(KRPS_EINVAL, "J must be >= 1");
+  if (sigma == nullptr || ws == nullptr) return fail(KRPS_EINVAL, "sigma/workspace is NULL");
+  SolvePlan pl = plan_solve(s, J);
+  if (ws_bytes < pl.total) return fail(KRPS_EWORKSPACE, "solve workspace too small");
+  KRPS_HIP(hipSetDevice(s->ctx->device));
+  hipStream_t stream = s->ctx->stream;
+  const bool seeded = uniforms == nullptr;
+  uint64_t* ctrw = (uint64_t*)((char*)ws + pl.head.ctrw);
+  if (seeded) {
+    hipError_t e = launch_set_u64(stream, ctrw, sweep * (uint64_t)s->N);
+    if (e != hipSuccess) return hip_fail(e, "sweep counter");
+  }
+  const size_t ublock = (size_t)J * s->N * 2;
+  auto enqueue_all = [&]() -> krps_status {
+    for (int j = 0; j < s->N; ++j) {
+      UniformSrc us;
+      if (seeded) {
+        us.seed = seed;
+        us.ctr_base = ctr_base;
+        us.ctr2 = (uint64_t)j;
+        us.ctr2_dev = ctrw;
+      } else {
+        us.u01 = uniforms + j * ublock;
+      }
+      krps_status r = enqueue_solve(s, t, j, J, us, sigma, (char*)ws, pl);
+      if (r != KRPS_OK) return r;
+    }
+    return KRPS_OK;
+  };
+  if (!use_graph) {
+    st = enqueue_all();
+    s->prepared_ws = nullptr;
+    return st;
+  }
+  // the captured graph is keyed by everything its kernels' arguments hold
+  const GraphKey key{t, uniforms, sigma, ws, J, s->lps, seeded ? seed : 0,
+                     seeded ? ctr_base : 0};
+  if (s->sweep_exec == nullptr || !(s->gkey == key)) {
+    if (s->sweep_exec != nullptr) {
+      (void)hipGraphExecDestroy(s->sweep_exec);
+      s->sweep_exec = nullptr;
+    }
+    // the null stream cannot be captured: capture on the context's own
+    // stream, replay on the caller's
+    hipStream_t cap = stream;
+    if (cap == nullptr) {
+      if (s->ctx->capture == nullptr)
+        KRPS_HIP(hipStreamCreateWithFlags(&s->ctx->capture, hipStreamNonBlocking));
+      cap = s->ctx->capture;
+    }
+    KRPS_HIP(hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal));
+    s->ctx->stream = cap;
+    st = enqueue_all();
+    s->ctx->stream = stream;
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamEndCapture(cap, &g);
+    if (st != KRPS_OK) {
+      if (g) (void)hipGraphDestroy(g);
+      return st;
+    }
+    if (e != hipSuccess) return hip_fail(e, "end capture");
+    e = hipGraphInstantiate(&s->sweep_exec, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) return hip_fail(e, "graph instantiate");
+    s->gkey = key;
+  }
+  KRPS_HIP(hipGraphLaunch(s->sweep_exec, stream));
+  s->prepared_ws = nullptr;
+  return KRPS_OK;
 }
 
 }  // namespace
@@ -599,7 +764,7 @@ krps_status krps_sampler_create(krps_ctx ctx, int N, const int64_t* I, int R, in
     delete s;
     return hip_fail(e, "hipSetDevice");
   }
-  e = hipMemsetAsync(s->status, 0, 4, ctx->stream);
+  e = hipMemsetAsync(s->status, 0, 8, ctx->stream);
   for (int j = 0; j < N && e == hipSuccess; ++j)
     e = launch_fill(ctx->stream, p, (char*)s->nodes[j] + (size_t)pl.shape[j].n_nodes * tri(R) * s->elem,
                     NODE_SLACK);
@@ -627,6 +792,19 @@ krps_status krps_sampler_refresh(krps_sampler s, int j) {
 krps_status krps_sampler_destroy(krps_sampler s) {
   if (s != nullptr && s->sweep_exec != nullptr) (void)hipGraphExecDestroy(s->sweep_exec);
   delete s;
+  return KRPS_OK;
+}
+
+krps_status krps_sampler_check(krps_sampler s, int64_t* zero_weight) {
+  if (s == nullptr) return fail(KRPS_EINVAL, "sampler is NULL");
+  KRPS_HIP(hipSetDevice(s->ctx->device));
+  int32_t words[2] = {0, 0};
+  KRPS_HIP(hipMemcpyAsync(words, s->status, 8, hipMemcpyDeviceToHost, s->ctx->stream));
+  KRPS_HIP(hipStreamSynchronize(s->ctx->stream));
+  KRPS_HIP(hipMemsetAsync(s->status, 0, 8, s->ctx->stream));
+  if (zero_weight != nullptr) *zero_weight = words[1];
+  if (words[0] & ST_ZERO) return fail(KRPS_EZERO, "the Khatri-Rao product is zero");
+  if (words[0] & ST_NUMERIC) return fail(KRPS_ENUMERIC, "non-finite or non-positive mass met");
   return KRPS_OK;
 }
 
@@ -925,17 +1103,21 @@ krps_status krps_sample_batched_prepare(krps_ctx ctx, int P, const krps_sampler*
   return KRPS_OK;
 }
 
-krps_status krps_sample_batched_draw(krps_ctx ctx, int P, const krps_sampler* s,
-                                     const int* exclude, const int64_t* J,
-                                     const double* const* uniforms, int32_t* const* idx,
-                                     double* const* prob, void* ws, size_t ws_bytes) {
+// The walks of a batched draw, from uniform buffers (uniforms != null) or
+// from in-kernel Philox under per-problem seed[p] and ctr_base[p].
+static krps_status batched_draw(krps_ctx ctx, int P, const krps_sampler* s, const int* exclude,
+                                const int64_t* J, const double* const* uniforms,
+                                const uint64_t* seed, const uint64_t* ctr_base,
+                                int32_t* const* idx, double* const* prob, void* ws,
+                                size_t ws_bytes) {
   krps_status st = check_batch(ctx, P, s, exclude);
   if (st != KRPS_OK) return st;
-  if (J == nullptr || uniforms == nullptr || idx == nullptr)
-    return fail(KRPS_EINVAL, "J/uniforms/idx is NULL");
+  if (J == nullptr || idx == nullptr) return fail(KRPS_EINVAL, "J/idx is NULL");
+  if (uniforms == nullptr && (seed == nullptr || ctr_base == nullptr))
+    return fail(KRPS_EINVAL, "neither uniforms nor seed/ctr_base given");
   for (int p = 0; p < P; ++p) {
     if (J[p] < 0) return fail(KRPS_EINVAL, "J < 0");
-    if (J[p] > 0 && (uniforms[p] == nullptr || idx[p] == nullptr))
+    if (J[p] > 0 && ((uniforms != nullptr && uniforms[p] == nullptr) || idx[p] == nullptr))
       return fail(KRPS_EINVAL, "uniforms/idx of a problem is NULL");
   }
   if (ws == nullptr) return fail(KRPS_EINVAL, "workspace is NULL");
@@ -967,7 +1149,13 @@ krps_status krps_sample_batched_draw(krps_ctx ctx, int P, const krps_sampler* s,
     memset(&b, 0, sizeof(b));
     fill_descent_args(sp, exclude[p], w + pl.draw_off[p], b.a);
     b.a.J = J[p];
-    b.a.u01 = uniforms[p];
+    if (uniforms != nullptr) {
+      b.a.u01 = uniforms[p];
+    } else {
+      b.a.u01 = nullptr;
+      b.a.seed = seed[p];
+      b.a.ctr_base = ctr_base[p];
+    }
     b.a.idx = idx[p];
     b.a.prob = prob != nullptr ? prob[p] : nullptr;
     b.tab = (const uint16_t*)(w + pl.tab_off[p]);
@@ -993,6 +1181,25 @@ krps_status krps_sample_batched_draw(krps_ctx ctx, int P, const krps_sampler* s,
     first += nprob[g];
   }
   return KRPS_OK;
+}
+
+krps_status krps_sample_batched_draw(krps_ctx ctx, int P, const krps_sampler* s,
+                                     const int* exclude, const int64_t* J,
+                                     const double* const* uniforms, int32_t* const* idx,
+                                     double* const* prob, void* ws, size_t ws_bytes) {
+  if (uniforms == nullptr) return fail(KRPS_EINVAL, "uniforms is NULL");
+  return batched_draw(ctx, P, s, exclude, J, uniforms, nullptr, nullptr, idx, prob, ws, ws_bytes);
+}
+
+krps_status krps_sample_batched_seeded(krps_ctx ctx, int P, const krps_sampler* s,
+                                       const int* exclude, const int64_t* J,
+                                       const uint64_t* seed, const uint64_t* ctr_base,
+                                       int32_t* const* idx, double* const* prob, void* ws,
+                                       size_t ws_bytes) {
+  if (seed == nullptr || ctr_base == nullptr) return fail(KRPS_EINVAL, "seed/ctr_base is NULL");
+  krps_status st = krps_sample_batched_prepare(ctx, P, s, exclude, ws, ws_bytes);
+  if (st != KRPS_OK) return st;
+  return batched_draw(ctx, P, s, exclude, J, nullptr, seed, ctr_base, idx, prob, ws, ws_bytes);
 }
 
 krps_status krps_sample_batched(krps_ctx ctx, int P, const krps_sampler* s, const int* exclude,
@@ -1170,10 +1377,10 @@ krps_status krps_solve_layout_query(krps_sampler s, krps_tensor t, int64_t J,
 krps_status krps_normalize_factor(krps_sampler s, int j, double* sigma, void* ws, size_t ws_bytes) {
   if (s == nullptr) return fail(KRPS_EINVAL, "sampler is NULL");
   if (j < 0 || j >= s->N) return fail(KRPS_EINVAL, "j out of range");
-  if (ws == nullptr || ws_bytes < solve_partial_bytes(s->R) + align_up((size_t)s->R * 8))
-    return fail(KRPS_EWORKSPACE, "workspace too small");
-  double* partial = (double*)ws;
-  double* sg = sigma != nullptr ? sigma : (double*)((char*)ws + align_up(solve_partial_bytes(s->R)));
+  const SolveHead h = plan_head(s);
+  if (ws == nullptr || ws_bytes < h.total) return fail(KRPS_EWORKSPACE, "workspace too small");
+  double* partial = (double*)((char*)ws + h.npart);
+  double* sg = sigma != nullptr ? sigma : (double*)((char*)ws + h.nsig);
   hipStream_t st = s->ctx->stream;
   hipError_t e = launch_colnorm(st, s->prec, s->U[j], s->I[j], s->R, partial, sg);
   if (e == hipSuccess) e = launch_normalize(st, s->prec, s->U[j], s->I[j], s->R, sg);
@@ -1183,80 +1390,33 @@ krps_status krps_normalize_factor(krps_sampler s, int j, double* sigma, void* ws
 
 krps_status krps_sketched_solve(krps_sampler s, krps_tensor t, int j, int64_t J,
                                 const double* uniforms, double* sigma, void* ws, size_t ws_bytes) {
-  krps_status st = check_pair(s, t);
-  if (st != KRPS_OK) return st;
-  if (s->N < 2) return fail(KRPS_EINVAL, "a solve needs N >= 2");
-  if (j < 0 || j >= s->N) return fail(KRPS_EINVAL, "j out of range");
-  if (J < 1) return fail(KRPS_EINVAL, "J must be >= 1");
-  if (uniforms == nullptr || sigma == nullptr || ws == nullptr)
-    return fail(KRPS_EINVAL, "uniforms/sigma/workspace is NULL");
-  SolvePlan pl = plan_solve(s, J);
-  if (ws_bytes < pl.total) return fail(KRPS_EWORKSPACE, "solve workspace too small");
-  st = enqueue_solve(s, t, j, J, uniforms, sigma, (char*)ws, pl);
-  s->prepared_ws = nullptr;
-  return st;
+  if (uniforms == nullptr) return fail(KRPS_EINVAL, "uniforms is NULL");
+  UniformSrc us;
+  us.u01 = uniforms;
+  return solve_entry(s, t, j, J, us, sigma, ws, ws_bytes);
+}
+
+krps_status krps_sketched_solve_seeded(krps_sampler s, krps_tensor t, int j, int64_t J,
+                                       uint64_t seed, uint64_t ctr_base, uint64_t sweep,
+                                       double* sigma, void* ws, size_t ws_bytes) {
+  if (s == nullptr) return fail(KRPS_EINVAL, "sampler is NULL");
+  UniformSrc us;
+  us.seed = seed;
+  us.ctr_base = ctr_base;
+  us.ctr2 = sweep * (uint64_t)s->N + (uint64_t)j;
+  return solve_entry(s, t, j, J, us, sigma, ws, ws_bytes);
 }
 
 krps_status krps_als_sweep(krps_sampler s, krps_tensor t, int64_t J, const double* uniforms,
                            double* sigma, void* ws, size_t ws_bytes, int use_graph) {
-  krps_status st = check_pair(s, t);
-  if (st != KRPS_OK) return st;
-  if (s->N < 2) return fail(KRPS_EINVAL, "a sweep needs N >= 2");
-  if (J < 1) return fail(KRPS_EINVAL, "J must be >= 1");
-  if (uniforms == nullptr || sigma == nullptr || ws == nullptr)
-    return fail(KRPS_EINVAL, "uniforms/sigma/workspace is NULL");
-  SolvePlan pl = plan_solve(s, J);
-  if (ws_bytes < pl.total) return fail(KRPS_EWORKSPACE, "solve workspace too small");
-  hipStream_t stream = s->ctx->stream;
-  const size_t ublock = (size_t)J * s->N * 2;
-  auto enqueue_all = [&]() -> krps_status {
-    for (int j = 0; j < s->N; ++j) {
-      krps_status r = enqueue_solve(s, t, j, J, uniforms + j * ublock, sigma, (char*)ws, pl);
-      if (r != KRPS_OK) return r;
-    }
-    return KRPS_OK;
-  };
-  if (!use_graph) {
-    st = enqueue_all();
-    s->prepared_ws = nullptr;
-    return st;
-  }
-  const void* key[5] = {t, uniforms, sigma, ws, (const void*)(intptr_t)J};
-  bool same = s->sweep_exec != nullptr && s->g_J == J;
-  for (int i = 0; i < 5 && same; ++i) same = s->g_key[i] == key[i];
-  if (!same) {
-    if (s->sweep_exec != nullptr) {
-      (void)hipGraphExecDestroy(s->sweep_exec);
-      s->sweep_exec = nullptr;
-    }
-    // the null stream cannot be captured: capture on the context's own
-    // stream, replay on the caller's
-    hipStream_t cap = stream;
-    if (cap == nullptr) {
-      if (s->ctx->capture == nullptr)
-        KRPS_HIP(hipStreamCreateWithFlags(&s->ctx->capture, hipStreamNonBlocking));
-      cap = s->ctx->capture;
-    }
-    KRPS_HIP(hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal));
-    s->ctx->stream = cap;
-    st = enqueue_all();
-    s->ctx->stream = stream;
-    hipGraph_t g = nullptr;
-    hipError_t e = hipStreamEndCapture(cap, &g);
-    if (st != KRPS_OK) {
-      if (g) (void)hipGraphDestroy(g);
-      return st;
-    }
-    if (e != hipSuccess) return hip_fail(e, "end capture");
-    e = hipGraphInstantiate(&s->sweep_exec, g, nullptr, nullptr, 0);
-    (void)hipGraphDestroy(g);
-    if (e != hipSuccess) return hip_fail(e, "graph instantiate");
-    for (int i = 0; i < 5; ++i) s->g_key[i] = key[i];
-    s->g_J = J;
-  }
-  KRPS_HIP(hipGraphLaunch(s->sweep_exec, stream));
-  s->prepared_ws = nullptr;
-  return KRPS_OK;
+  if (uniforms == nullptr) return fail(KRPS_EINVAL, "uniforms is NULL");
+  return sweep_entry(s, t, J, uniforms, 0, 0, 0, sigma, ws, ws_bytes, use_graph);
+}
+
+krps_status krps_als_sweep_seeded(krps_sampler s, krps_tensor t, int64_t J, uint64_t seed,
+                                  uint64_t ctr_base, uint64_t sweep, double* sigma, void* ws,
+                                  size_t ws_bytes, int use_graph) {
+  return sweep_entry(s, t, J, nullptr, seed, ctr_base, sweep, sigma, ws, ws_bytes, use_graph);
 }
 
 }  // extern "C"
@@ -1526,23 +1686,12 @@ krps_status krps_fit(krps_sampler s, krps_tensor t, const double* sigma, double*
   // The split path's tree roots carry its bf16 rounding (~2^-16 relative),
   // which ||T~||^2 - 2 <T, T~> would amplify by ~1 / (1 - fit)^2; the fit
   // takes float64 Grams of the float32 factors instead (float64 MFMA, the
-  // tree builder without stored nodes over at most 2048 leaves).
+  // tree builder without stored nodes over at most 2048 leaves).  All its
+  // scratch lies in the head of the solve workspace, below the pieces of
+  // krps_solve_layout.
   const bool exact_gram = s->prec == KRPS_BF16X2;
-  size_t need = align_up(fit_partial_bytes()) + 256;
-  const size_t goff = need;
-  TreeShape gts[KRPS_MAX_MODES];
-  size_t scr_off = 0, scr_bytes = 0;
-  if (exact_gram) {
-    need += align_up((size_t)N * R * R * 8);
-    scr_off = need;
-    for (int k = 0; k < N; ++k) {
-      const int64_t Lt = std::min<int64_t>(ceil_div(s->I[k], (int64_t)R), 2048);
-      gts[k].init(s->I[k], (int)ceil_div(s->I[k], Lt));
-      scr_bytes = std::max(scr_bytes, tree_build_scratch_bytes(gts[k].L, R));
-    }
-    need += align_up(scr_bytes);
-  }
-  if (ws_bytes < need) return fail(KRPS_EWORKSPACE, "workspace too small for the fit");
+  const SolveHead h = plan_head(s);
+  if (ws_bytes < h.total) return fail(KRPS_EWORKSPACE, "workspace too small for the fit");
   char* w = (char*)ws;
   hipStream_t stream = s->ctx->stream;
   FitArgs fa;
@@ -1556,23 +1705,226 @@ krps_status krps_fit(krps_sampler s, krps_tensor t, const double* sigma, double*
     fa.U[k] = s->U[k];
     fa.G[k] = s->gram[k];
     if (exact_gram) {
-      double* gk = (double*)(w + goff) + (size_t)k * R * R;
-      hipError_t e = launch_tree_build(stream, KRPS_FP32, s->U[k], s->I[k], R, gts[k], nullptr, gk,
-                                       (double*)(w + scr_off), scr_bytes, 2);
+      double* gk = (double*)(w + h.fitg) + (size_t)k * R * R;
+      hipError_t e = launch_tree_build(stream, KRPS_FP32, s->U[k], s->I[k], R, h.gts[k], nullptr,
+                                       gk, (double*)(w + h.fitscr), h.fitscr_bytes, 2);
       if (e != hipSuccess) return hip_fail(e, "float64 Gram for the fit");
       fa.G[k] = gk;
     }
   }
   fa.sigma = sigma;
-  double* partial = (double*)w;
-  double* out = (double*)(w + align_up(fit_partial_bytes()));
+  double* partial = (double*)(w + h.fitp);
+  double* out = (double*)(w + h.fitout);
   hipError_t e = launch_fit(stream, s->prec, fa, partial, out);
   if (e != hipSuccess) return hip_fail(e, "fit");
-  double h[2];
-  KRPS_HIP(hipMemcpyAsync(h, out, 16, hipMemcpyDeviceToHost, s->ctx->stream));
+  double res[2];
+  KRPS_HIP(hipMemcpyAsync(res, out, 16, hipMemcpyDeviceToHost, s->ctx->stream));
   KRPS_HIP(hipStreamSynchronize(s->ctx->stream));
-  const double r2 = t->norm2 + h[1] - 2.0 * h[0];
+  const double r2 = t->norm2 + res[1] - 2.0 * res[0];
   *fit = 1.0 - sqrt(r2 > 0 ? r2 : 0.0) / sqrt(t->norm2);
+  return KRPS_OK;
+}
+
+}  // extern "C"
+
+// ------------------------------------------------------ workspace regions
+
+namespace {
+
+struct RegionList {
+  krps_region* out;
+  int cap, n = 0;
+  void add(int ws, const char* name, size_t off, size_t bytes, size_t need) {
+    if (n < cap && out != nullptr) {
+      krps_region& r = out[n];
+      memset(&r, 0, sizeof(r));
+      r.workspace = ws;
+      snprintf(r.name, sizeof(r.name), "%s", name);
+      r.offset = off;
+      r.bytes = bytes;
+      r.need = need;
+    }
+    ++n;
+  }
+};
+
+// Bytes from `off` to the next region's start in an ordered list of offsets.
+size_t span(size_t off, size_t next) { return next - off; }
+
+}  // namespace
+
+extern "C" {
+
+krps_status krps_workspace_regions(int N, const int64_t* I, int R, int F, krps_precision p,
+                                   int64_t nnz, int64_t J, krps_region* out, int cap, int* count) {
+  krps_status st = check_dims(N, I, R);
+  if (st != KRPS_OK) return st;
+  if (!valid_prec(p)) return fail(KRPS_EINVAL, "unknown precision");
+  if (F < 0 || nnz < 1 || J < 1 || count == nullptr || cap < 0)
+    return fail(KRPS_EINVAL, "F < 0, nnz < 1, J < 1, cap < 0 or count NULL");
+  const int Fe = F == 0 ? R : F;
+  const int64_t TR = tri(R);
+  const size_t es = (size_t)elem_bytes(p);
+  // the longest read past a node's end: a lane group of at most 64 lanes
+  // reading a node in strides of its width
+  const size_t overread = 63;
+  RegionList rl{out, cap};
+  // --- sampler workspace
+  const SamplerPlan sp = plan_sampler(N, I, R, Fe, p);
+  for (int j = 0; j < N; ++j) {
+    char nm[32];
+    snprintf(nm, sizeof(nm), "tree %d", j);
+    rl.add(0, nm, sp.node_off[j], span(sp.node_off[j], sp.gram_off[j]),
+           (size_t)(sp.shape[j].n_nodes * TR + overread) * es);
+    snprintf(nm, sizeof(nm), "gram %d", j);
+    const size_t gnext = j + 1 < N ? sp.node_off[j + 1] : sp.scratch_off;
+    rl.add(0, nm, sp.gram_off[j], span(sp.gram_off[j], gnext), (size_t)R * R * 8);
+  }
+  size_t bext = 0;
+  for (int j = 0; j < N; ++j) bext = std::max(bext, tree_build_scratch_extent(sp.shape[j], R));
+  rl.add(0, "build scratch", sp.scratch_off, span(sp.scratch_off, sp.status_off), bext);
+  rl.add(0, "status", sp.status_off, span(sp.status_off, sp.total), 8);
+  // --- per-draw workspace (a host-side sampler with the same shape)
+  krps_sampler_s tmp;
+  tmp.N = N;
+  tmp.R = R;
+  tmp.F = Fe;
+  tmp.prec = p;
+  tmp.elem = (int)es;
+  for (int j = 0; j < N; ++j) {
+    tmp.I.push_back(I[j]);
+    tmp.shape.push_back(sp.shape[j]);
+  }
+  plan_draw(&tmp);
+  const krps_draw_layout& dl = tmp.lay;
+  const size_t gpk = gpacked_off(&tmp);
+  rl.add(1, "G+", dl.gplus, span(dl.gplus, gpk), (size_t)R * R * 8);
+  rl.add(1, "G+ packed", gpk, span(gpk, dl.rank), (size_t)(TR + overread) * 8);
+  rl.add(1, "rank, sweeps", dl.rank, span(dl.rank, dl.ggt), (size_t)(2 + N) * 4);
+  rl.add(1, "G>k", dl.ggt, span(dl.ggt, dl.lam), (size_t)N * R * R * 8);
+  rl.add(1, "eigenvalues", dl.lam, span(dl.lam, dl.vecs), (size_t)N * R * 8);
+  rl.add(1, "eigenvectors", dl.vecs, span(dl.vecs, dl.etree), (size_t)N * R * R * es);
+  rl.add(1, "eigen-trees", dl.etree, span(dl.etree, tmp.emass_off),
+         (size_t)((N - 1) * tmp.estride + tmp.enodes * TR + overread) * es);
+  rl.add(1, "eigen masses", tmp.emass_off, span(tmp.emass_off, tmp.draw_bytes),
+         (size_t)N * tmp.enodes * 8);
+  // --- solve workspace
+  const SolvePlan pl = plan_solve(&tmp, J);
+  const SolveHead& h = pl.head;
+  const krps_solve_layout& l = pl.lay;
+  size_t fext = 0;
+  if (p == KRPS_BF16X2)
+    for (int k = 0; k < N; ++k) fext = std::max(fext, tree_build_scratch_extent(h.gts[k], R));
+  rl.add(2, "fit partials", h.fitp, span(h.fitp, h.fitout), fit_partial_bytes());
+  rl.add(2, "fit result", h.fitout, span(h.fitout, h.fitg), 16);
+  rl.add(2, "fit Grams", h.fitg, span(h.fitg, h.fitscr),
+         p == KRPS_BF16X2 ? (size_t)N * R * R * 8 : 0);
+  rl.add(2, "fit Gram scratch", h.fitscr, span(h.fitscr, h.npart), fext);
+  rl.add(2, "norm partials", h.npart, span(h.npart, h.nsig), solve_partial_bytes(R));
+  rl.add(2, "norm sigma", h.nsig, span(h.nsig, h.ctrw), (size_t)R * 8);
+  rl.add(2, "sweep counter", h.ctrw, span(h.ctrw, l.draw), 8);
+  rl.add(2, "draw", l.draw, span(l.draw, l.idx), tmp.draw_bytes);
+  rl.add(2, "idx", l.idx, span(l.idx, l.prob), (size_t)J * N * 4);
+  rl.add(2, "prob", l.prob, span(l.prob, l.w), (size_t)J * 8);
+  rl.add(2, "w", l.w, span(l.w, l.rows), (size_t)J * 8);
+  rl.add(2, "rows", l.rows, span(l.rows, pl.lo), (size_t)J * R * (p == KRPS_BF16X2 ? 4 : 8));
+  rl.add(2, "fiber lo", pl.lo, span(pl.lo, pl.hi), (size_t)J * 8);
+  rl.add(2, "fiber hi", pl.hi, span(pl.hi, pl.cnt), (size_t)J * 8);
+  rl.add(2, "items", pl.cnt, span(pl.cnt, pl.start), (size_t)J * 8);
+  rl.add(2, "item starts", pl.start, span(pl.start, pl.coef), (size_t)(J + 1) * 8);
+  rl.add(2, "coef", pl.coef, span(pl.coef, pl.slot), (size_t)J * 8);
+  rl.add(2, "slot", pl.slot, span(pl.slot, pl.hkey), (size_t)J * 4);
+  rl.add(2, "hash keys", pl.hkey, span(pl.hkey, pl.hW), (size_t)pl.H * 8);
+  rl.add(2, "hash weights", pl.hW, span(pl.hW, pl.hrep), (size_t)pl.H * 8);
+  rl.add(2, "hash reps", pl.hrep, span(pl.hrep, pl.rflag), (size_t)pl.H * 4);
+  rl.add(2, "expand flags", pl.rflag, span(pl.rflag, pl.rpos), (size_t)J * 8);
+  rl.add(2, "expand pos", pl.rpos, span(pl.rpos, pl.rep), (size_t)(J + 1) * 8);
+  rl.add(2, "expanding", pl.rep, span(pl.rep, pl.rstart), (size_t)J * 4);
+  rl.add(2, "expand starts", pl.rstart, span(pl.rstart, pl.bsum), (size_t)(J + 1) * 8);
+  rl.add(2, "scan tiles", pl.bsum, span(pl.bsum, l.M), (size_t)((J + 1023) / 1024 + 2) * 8);
+  rl.add(2, "M", l.M, span(l.M, l.Mp), (size_t)R * R * 8);
+  rl.add(2, "M+", l.Mp, span(l.Mp, pl.rank), (size_t)R * R * 8);
+  rl.add(2, "M rank", pl.rank, span(pl.rank, l.Y), 8);
+  rl.add(2, "Y", l.Y, span(l.Y, l.yrows), (size_t)pl.Imax * R * (p == KRPS_BF16X2 ? 4 : 8));
+  rl.add(2, "Y rows", l.yrows, span(l.yrows, l.nyrows), (size_t)pl.Imax * 4);
+  rl.add(2, "Y row count", l.nyrows, span(l.nyrows, pl.ymark), 8);
+  rl.add(2, "row marks", pl.ymark, span(pl.ymark, pl.ybsum), (size_t)pl.Imax * 4);
+  rl.add(2, "row scan", pl.ybsum, span(pl.ybsum, pl.partial), row_bsum_bytes(pl.Imax));
+  rl.add(2, "solve partials", pl.partial, span(pl.partial, pl.gscratch), solve_partial_bytes(R));
+  TreeShape tm;
+  tm.init(J, R);
+  rl.add(2, "M scratch", pl.gscratch, span(pl.gscratch, pl.total),
+         tree_build_scratch_extent(tm, R));
+  // --- tensor workspace (dims = I)
+  if (nnz <= (int64_t)UINT32_MAX) {
+    const TensorPlan tp = plan_tensor(N, I, nnz);
+    for (int j = 0; j < N; ++j) {
+      char nm[32];
+      snprintf(nm, sizeof(nm), "cols %d", j);
+      rl.add(3, nm, tp.cols_off[j], span(tp.cols_off[j], tp.vals_off[j]), (size_t)N * nnz * 4);
+      snprintf(nm, sizeof(nm), "vals %d", j);
+      rl.add(3, nm, tp.vals_off[j], span(tp.vals_off[j], tp.off_off[j]), (size_t)nnz * 8);
+      snprintf(nm, sizeof(nm), "offsets %d", j);
+      const size_t onext = j + 1 < N ? tp.cols_off[j + 1] : tp.k0;
+      rl.add(3, nm, tp.off_off[j], span(tp.off_off[j], onext), (size_t)(I[tp.lead[j]] + 1) * 8);
+    }
+    rl.add(3, "keys 0", tp.k0, span(tp.k0, tp.k1), (size_t)nnz * 4);
+    rl.add(3, "keys 1", tp.k1, span(tp.k1, tp.p0), (size_t)nnz * 4);
+    rl.add(3, "perm 0", tp.p0, span(tp.p0, tp.p1), (size_t)nnz * 4);
+    rl.add(3, "perm 1", tp.p1, span(tp.p1, tp.hslot_off[0]), (size_t)nnz * 4);
+    int64_t dmax = 1;
+    for (int j = 0; j < N; ++j) {
+      dmax = std::max<int64_t>(dmax, I[j]);
+      char nm[32];
+      snprintf(nm, sizeof(nm), "hot slots %d", j);
+      rl.add(3, nm, tp.hslot_off[j], span(tp.hslot_off[j], tp.hrows_off[j]), (size_t)I[j]);
+      snprintf(nm, sizeof(nm), "hot rows %d", j);
+      const size_t hnext = j + 1 < N ? tp.hslot_off[j + 1] : tp.hc0;
+      rl.add(3, nm, tp.hrows_off[j], span(tp.hrows_off[j], hnext), (size_t)HOT_ROWS * 4);
+    }
+    rl.add(3, "hot counts 0", tp.hc0, span(tp.hc0, tp.hc1), (size_t)dmax * 4);
+    rl.add(3, "hot counts 1", tp.hc1, span(tp.hc1, tp.hi0), (size_t)dmax * 4);
+    rl.add(3, "hot index 0", tp.hi0, span(tp.hi0, tp.hi1), (size_t)dmax * 4);
+    rl.add(3, "hot index 1", tp.hi1, span(tp.hi1, tp.temp), (size_t)dmax * 4);
+    rl.add(3, "sort temp", tp.temp, span(tp.temp, tp.acc),
+           std::max(sort_temp_bytes(nnz), hot_temp_bytes(dmax)));
+    rl.add(3, "norm", tp.acc, span(tp.acc, tp.total), 8);
+  }
+  // --- batched workspace: this sampler once per exclusion
+  {
+    std::vector<krps_sampler> ss(N, &tmp);
+    std::vector<int> ex(N);
+    for (int j = 0; j < N; ++j) ex[j] = N > 1 ? j : -1;
+    const BatchPlan bp = plan_batch(N, ss.data(), ex.data());
+    for (int q = 0; q < N; ++q) {
+      char nm[32];
+      snprintf(nm, sizeof(nm), "draw %d", q);
+      rl.add(4, nm, bp.draw_off[q], span(bp.draw_off[q], bp.tab_off[q]), tmp.draw_bytes);
+      snprintf(nm, sizeof(nm), "index table %d", q);
+      const size_t tnext = q + 1 < N ? bp.draw_off[q + 1] : bp.prep;
+      rl.add(4, nm, bp.tab_off[q], span(bp.tab_off[q], tnext), (size_t)TR * 2);
+    }
+    rl.add(4, "prep jobs", bp.prep, span(bp.prep, bp.eig), (size_t)N * sizeof(PrepJob));
+    rl.add(4, "eigen jobs", bp.eig, span(bp.eig, bp.probs), (size_t)bp.n_eig * sizeof(EigJob));
+    rl.add(4, "problems", bp.probs, span(bp.probs, bp.counters),
+           (size_t)N * sizeof(BatchProblem));
+    rl.add(4, "task counters", bp.counters, span(bp.counters, bp.total), 10 * 8);
+  }
+  // --- generic least squares with one right-hand side
+  {
+    const LsPlan lp = plan_lstsq(R, J, 1);
+    TreeShape lm;
+    lm.init(J, R);
+    rl.add(5, "SA", lp.SA, span(lp.SA, lp.SBw), (size_t)J * R * 8);
+    rl.add(5, "SB", lp.SBw, span(lp.SBw, lp.M), (size_t)J * 8);
+    rl.add(5, "M", lp.M, span(lp.M, lp.Mp), (size_t)R * R * 8);
+    rl.add(5, "M+", lp.Mp, span(lp.Mp, lp.rank), (size_t)R * R * 8);
+    rl.add(5, "rank", lp.rank, span(lp.rank, lp.partial), 8);
+    rl.add(5, "partials", lp.partial, span(lp.partial, lp.Z), lstsq_partial_bytes(R, 1));
+    rl.add(5, "Z", lp.Z, span(lp.Z, lp.scratch), (size_t)R * 8);
+    rl.add(5, "M scratch", lp.scratch, span(lp.scratch, lp.total), tree_build_scratch_extent(lm, R));
+  }
+  *count = rl.n;
   return KRPS_OK;
 }
 

@@ -70,6 +70,8 @@ struct DescentArgs {
   int64_t J;
   const double* u01;              // [J][N][2], or null: generated from seed / ctr_base
   uint64_t seed, ctr_base;        // in-kernel uniforms (Philox4x64-10)
+  uint64_t ctr2;                  // third counter word of the in-kernel uniforms
+  const uint64_t* ctr2_dev;       // device word added to ctr2, or null
   int32_t* idx;                   // [J][N]
   double* prob;                   // [J] or null
   void* rows;                     // [J][R] or null (factor type)
@@ -173,12 +175,16 @@ struct FitArgs {
   const double* sigma;
 };
 
-// Status word bits set by kernels.
+// Status words of a sampler (int32 [2], cleared at creation): word 0 holds
+// flag bits set by kernels, word 1 counts sampled rows whose computed
+// probability was not positive (rounding; they were given weight 0).
 enum : int32_t { ST_ZERO = 1, ST_NUMERIC = 2 };
 
 // ------------------------------------------------------------- launchers
 // tree_build.hip
 size_t tree_build_scratch_bytes(int64_t L, int R);
+// Largest extent of the scratch that a build of this shape touches.
+size_t tree_build_scratch_extent(const TreeShape& ts, int R);
 hipError_t launch_tree_build(hipStream_t st, krps_precision p, const void* U, int64_t I, int R,
                              const TreeShape& ts, void* nodes, double* gram_full,
                              double* scratch, size_t scratch_bytes, int split_terms = 2);
@@ -236,6 +242,8 @@ hipError_t launch_ls_solve(hipStream_t st, const double* SA, const double* SBw, 
                            int64_t n, const double* Mp, double* partial, double* Z, double* X);
 hipError_t launch_fill(hipStream_t st, krps_precision p, void* ptr, int64_t n);
 hipError_t launch_fill_f64(hipStream_t st, double* ptr, int64_t n);
+// *ptr = v (one thread)
+hipError_t launch_set_u64(hipStream_t st, uint64_t* ptr, uint64_t v);
 hipError_t launch_solve_gemm(hipStream_t st, krps_precision p, const void* Y, const double* Mp,
                              void* U, int64_t I, const int32_t* list, const int64_t* count, int R,
                              double* partial, double* sigma);

@@ -907,6 +907,13 @@ hipError_t launch_fill(hipStream_t st, krps_precision p, void* ptr, int64_t n) {
   return hipGetLastError();
 }
 
+__global__ void set_u64_kernel(uint64_t* __restrict__ p, uint64_t v) { *p = v; }
+
+hipError_t launch_set_u64(hipStream_t st, uint64_t* ptr, uint64_t v) {
+  hipLaunchKernelGGL(set_u64_kernel, dim3(1), dim3(1), 0, st, ptr, v);
+  return hipGetLastError();
+}
+
 hipError_t launch_fill_f64(hipStream_t st, double* ptr, int64_t n) {
   if (n <= 0) return hipSuccess;
   hipLaunchKernelGGL(fill_kernel<double>, dim3(64), dim3(256), 0, st, ptr, n, 0.0);

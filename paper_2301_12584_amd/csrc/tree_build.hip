@@ -17,6 +17,8 @@
 // packed entry, the same binary counter over groups of 2^s2 nodes in float64,
 // down to the root (also written as the full float64 R x R Gram G_j).
 #include "device_common.h"
+#include <algorithm>
+
 #include "krps_internal.h"
 
 namespace krps {
@@ -293,9 +295,14 @@ struct LeafCfg {
   int NT, TW, S;
 };
 
+// Register-run depth (levels summed in registers by the leaf pass) for R;
+// dispatch_leaf below instantiates exactly these depths.
+int leaf_run_depth(int R) { return R <= 32 ? 4 : R <= 64 ? 3 : 2; }
+
 template <int MODE, int NT, int TW, int S>
 hipError_t run_leaf(hipStream_t st, const void* U, int64_t I, int R, int F, int64_t L, int D,
                     void* nodes, double* tops, int& s_eff) {
+  if (S != leaf_run_depth(R)) return hipErrorInvalidValue;
   s_eff = S < D ? S : D;
   const int64_t nrun = ceil_div(L, int64_t(1) << s_eff);
   hipLaunchKernelGGL((leaf_run_kernel<MODE, NT, TW, S>), dim3((unsigned)nrun), dim3(64 * TW), 0,
@@ -330,6 +337,33 @@ size_t tree_build_scratch_bytes(int64_t L, int R) {
   const int64_t a = ceil_div(L, int64_t(1) << MIN_S);
   const int64_t b = ceil_div(a, 2);
   return align_up((size_t)a * tri(R) * 8) + align_up((size_t)b * tri(R) * 8);
+}
+
+// Replays the launch geometry of launch_tree_build (the leaf pass's run
+// tops into buffer A, then each up-sweep pass into the other ping-pong
+// buffer) and returns the largest byte extent, from the start of the
+// scratch, that any pass writes or reads.
+size_t tree_build_scratch_extent(const TreeShape& ts, int R) {
+  const int64_t TR = tri(R);
+  const int64_t a_nodes = ceil_div(ts.L, int64_t(1) << MIN_S);
+  const size_t offB = align_up((size_t)a_nodes * TR * 8);
+  const int S = leaf_run_depth(R);
+  const int s_eff = S < ts.D ? S : ts.D;
+  int64_t n = ceil_div(ts.L, int64_t(1) << s_eff);
+  size_t ext = (size_t)n * TR * 8;  // run tops in A
+  size_t cur = 0, nxt = offB;
+  int lev = ts.D - s_eff;
+  for (;;) {
+    const int s2 = lev < S2 ? lev : S2;
+    const int64_t ng = ceil_div(n, int64_t(1) << s2);
+    ext = std::max(ext, cur + (size_t)n * TR * 8);           // reads
+    if (lev - s2 == 0) break;                                  // the root goes to the tree
+    ext = std::max(ext, nxt + (size_t)ng * TR * 8);          // writes
+    lev -= s2;
+    n = ng;
+    std::swap(cur, nxt);
+  }
+  return ext;
 }
 
 hipError_t launch_tree_build(hipStream_t st, krps_precision p, const void* U, int64_t I, int R,

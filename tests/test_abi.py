@@ -45,7 +45,8 @@ def test_workspace_query_validates_on_the_host(L):
     assert _ws([1000], 0)[0] == -1                 # R < 1
     assert _ws([1000], 129)[0] == -1               # R > 128
     assert _ws([0, 5], 8)[0] == -1                 # empty factor
-    assert _ws([5] * 9, 8)[0] == -1                # N > 8
+    assert _ws([5] * 10, 8)[0] == 0                # N = 10 is the largest
+    assert _ws([5] * 11, 8)[0] == -1               # N > 10
     assert _ws([5, 5], 8, F=-1)[0] == -1
     assert _ws([5, 5], 8, p=7)[0] == -1            # unknown precision
     assert b"R must be" in L.krps_last_error() or b"precision" in L.krps_last_error()
