@@ -173,28 +173,31 @@ def fit(tensor: SparseTensor, Us, sigma, chunk=1 << 20):
     return 1.0 - np.sqrt(resid2) / np.sqrt(tensor.norm2)
 
 
-def cp_als(tensor: SparseTensor, U0, sweeps, u01_of, F=None, store=None):
+def cp_als(tensor: SparseTensor, U0, sweeps, u01_of, F=None, factor_dtype=None, progress=None):
     """Algorithm 6 with the sampled solve.  ``U0``: initial factors (their
     columns are normalised here, ``sigma = 1``); ``u01_of(sweep, j)`` gives
     the uniforms of each solve.  Returns ``(Us, sigma, fits)`` with the fit
     after every sweep.
 
-    ``store`` (None or a NumPy float type) keeps the factors in that storage
-    precision: each normalised factor is rounded to ``store`` and the
-    sampler decides its indices on ``store``-rounded nodes (see
-    :class:`KRPSampler`); the arithmetic stays float64."""
+    ``factor_dtype`` (None or a NumPy float type) is the type the factors
+    are kept in: each normalised factor is rounded to it, and those rounded
+    values are the factors of the problem from then on (trees, draws and
+    solves use them in float64).  ``progress(sweep, j)`` is called after
+    every solve."""
     def keep(U):
-        return U if store is None else U.astype(store).astype(np.float64)
+        return U if factor_dtype is None else U.astype(factor_dtype).astype(np.float64)
 
     Us = [keep(normalize_columns(U)[0]) for U in U0]
     sigma = np.ones(Us[0].shape[1])
-    sampler = KRPSampler(Us, F, store=store)
+    sampler = KRPSampler(Us, F)
     fits = []
     for s in range(sweeps):
         for j in range(tensor.N):
             Uj, sigma, _, _, _ = sketched_solve(sampler, tensor, j, u01_of(s, j))
             Us[j] = keep(Uj)
-            if store is not None:
+            if factor_dtype is not None:
                 sampler.refresh(j, Us[j])
+            if progress is not None:
+                progress(s, j)
         fits.append(fit(tensor, Us, sigma))
     return Us, sigma, fits

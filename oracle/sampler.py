@@ -145,23 +145,34 @@ def row_sample(tree, h, Y, d):
     return s0 + chosen, margin
 
 
-def row_sample_batch(tree, H, Y, dvec, chunk=None):
+def row_sample_batch(tree, H, Y, dvec, chunk=None, scaled=False):
     """Algorithm 4 for many independent samples at once (the samples march
     level by level, as in the batch-synchronous strategy of Appendix A.10).
 
     ``H``: ``[J, R]`` history vectors, ``dvec``: ``[J]`` uniforms.  Returns
-    ``(rows [J] int64, min_margin [J])``.
+    ``(rows [J] int64, min_margin [J], min_scaled_margin [J])``.  The margin
+    of a comparison is ``|x - cut| / C``.  With ``scaled`` each comparison
+    is also divided by the sum of the absolute values of the terms that make
+    up ``x`` and ``cut`` (``d * sum|h_a h_b Y_ab G_ab|`` over the root,
+    the same sum over the left child and over every node whose mass went
+    into ``low``, the absolute row terms of the leaf scan): a rounding of
+    every node entry, weight and row term by a relative ``u`` moves the
+    comparison by at most ``u`` times that sum, so a draw whose scaled margin
+    exceeds ``u`` is decided the same way in that precision (``inf`` when
+    ``scaled`` is off).
     """
     H = np.asarray(H, dtype=np.float64)
     J, R = H.shape
     rows = np.empty(J, dtype=np.int64)
     margins = np.empty(J)
+    smargins = np.empty(J)
     if chunk is None:
         chunk = max(64, (1 << 23) // (R * R))
     for s in range(0, J, chunk):
         e = min(J, s + chunk)
-        rows[s:e], margins[s:e] = _row_sample_chunk(tree, H[s:e], Y, dvec[s:e])
-    return rows, margins
+        rows[s:e], margins[s:e], smargins[s:e] = _row_sample_chunk(tree, H[s:e], Y, dvec[s:e],
+                                                                   scaled)
+    return rows, margins, smargins
 
 
 def _masses(Gs, HH):
@@ -169,7 +180,7 @@ def _masses(Gs, HH):
     return np.einsum("dab,dab->d", Gs, HH)
 
 
-def _row_sample_chunk(tree, H, Y, dvec):
+def _row_sample_chunk(tree, H, Y, dvec, scaled=False):
     n, R = H.shape
     HH = H[:, :, None] * H[:, None, :]
     if Y is not None:
@@ -180,13 +191,24 @@ def _row_sample_chunk(tree, H, Y, dvec):
     high = C.copy()
     pos = np.zeros(n, dtype=np.int64)
     margin = np.full(n, np.inf)
+    smargin = np.full(n, np.inf)
+    if scaled:
+        HA = np.abs(HH)
+        xs = dvec * _masses(np.broadcast_to(np.abs(tree.root), (n, R, R)), HA)
+        lows = np.zeros(n)
     for lev in range(1, tree.D + 1):
         left = 2 * pos
-        mL = np.maximum(_masses(tree.levels[lev][left], HH), 0.0)
+        GL = tree.levels[lev][left]
+        mL = np.maximum(_masses(GL, HH), 0.0)
         cut = low + mL
         margin = np.minimum(margin, np.abs(x - cut) / C)
         right_exists = (left + 1) < tree.real(lev)
         go_left = (cut >= x) | (~right_exists) | (high - cut <= 0.0)
+        if scaled:
+            mLs = _masses(np.abs(GL), HA)
+            smargin = np.minimum(smargin, np.where(right_exists,
+                                                   np.abs(x - cut) / (xs + lows + mLs), np.inf))
+            lows = np.where(go_left, lows, lows + mLs)
         pos = np.where(go_left, left, left + 1)
         high = np.where(go_left, cut, high)
         low = np.where(go_left, low, cut)
@@ -195,7 +217,7 @@ def _row_sample_chunk(tree, H, Y, dvec):
     if F == 1:
         # a one-row leaf: the scan can only return that row, and its right
         # edge is a boundary already compared above
-        return s0, margin
+        return s0, margin, smargin
     offs = np.arange(F)
     ridx = s0[:, None] + offs[None, :]
     valid = ridx < tree.I
@@ -208,6 +230,17 @@ def _row_sample_chunk(tree, H, Y, dvec):
     acc = low[:, None] + np.cumsum(qt, axis=1)
     margin = np.minimum(margin, np.where(valid, np.abs(x[:, None] - acc) / C[:, None],
                                          np.inf).min(axis=1))
+    if scaled:
+        if Y is None:
+            qs = np.abs(Wr).sum(axis=2) ** 2
+        else:
+            Wa = np.abs(Wr)
+            qs = np.einsum("dia,ab,dib->di", Wa, np.abs(Y), Wa)
+        accs = (xs + lows)[:, None] + np.cumsum(np.where(valid, qs, 0.0), axis=1)
+        # the last row's right edge is the leaf's, compared above
+        inner = valid & (offs[None, :] < np.minimum(tree.I - s0, F)[:, None] - 1)
+        smargin = np.minimum(smargin, np.where(inner, np.abs(x[:, None] - acc) / accs,
+                                               np.inf).min(axis=1))
     hit = (acc >= x[:, None]) & valid
     any_hit = hit.any(axis=1)
     first = np.argmax(hit, axis=1)
@@ -216,25 +249,36 @@ def _row_sample_chunk(tree, H, Y, dvec):
     last_valid = np.minimum(tree.I - s0, F) - 1
     fallback = np.where(posm.any(axis=1), last_pos, last_valid)
     chosen = np.where(any_hit, first, fallback)
-    return s0 + chosen, margin
-
-
-def _round(a, dtype):
-    return np.asarray(a).astype(dtype).astype(np.float64)
+    return s0 + chosen, margin, smargin
 
 
 class Draw:
     """Result of one ``KRPSample`` call."""
 
-    def __init__(self, idx, rows, prob, margin, rank, Gp, eig, degenerate):
+    def __init__(self, idx, rows, prob, margin, smargin, rank, Gp, eig, degenerate):
         self.idx = idx            # [J, N] int64, -1 in the excluded column
         self.rows = rows          # [J, R] sampled KRP rows a_d (float64)
         self.prob = prob          # [J] q_d = a_d G^+ a_d^T / rank
         self.margin = margin      # [J] smallest |x - cut| / C along the draw
+        self.smargin = smargin    # [J] smallest scaled margin (row_sample_batch), or inf
         self.rank = rank
         self.Gp = Gp              # pseudo-inverse of G = (*)_{k != j} G_k
         self.eig = eig            # {k: (lam ascending, V)} of G_{>k}
-        self.degenerate = degenerate  # some G_{>k} has a near-degenerate gap
+        self.degenerate = degenerate  # [J] the draw met a near-degenerate eigenspace
+
+
+def _path_boundaries(u, L):
+    """Leaf boundaries that the walk to leaf ``u`` of a tree over ``L``
+    leaves (padded to ``2^D``) compares against: at each level the boundary
+    between the left and the right child of the node on the path, where the
+    right child exists.  Returns ``[J, D]`` boundary indices (``-1``: none)."""
+    D = int(math.ceil(math.log2(L))) if L > 1 else 0
+    out = np.full((u.shape[0], max(D, 1)), -1, dtype=np.int64)
+    for lev in range(1, D + 1):
+        parent = u >> (D - lev + 1)
+        b = (2 * parent + 1) << (D - lev)
+        out[:, lev - 1] = np.where(b < L, b, -1)
+    return out
 
 
 class KRPSampler:
@@ -242,22 +286,14 @@ class KRPSampler:
 
     ``F`` is the leaf size of the factor trees ``Z_j`` (the paper uses
     ``F = R``; any positive ``F`` gives the same rows under the tie rule).
-
-    ``store`` (None or a NumPy float type) takes the integer decisions in a
-    storage precision: the cached partial Gram matrices, the eigen-tree
-    nodes ``P^v (*) G_k`` and the eigenvectors are rounded to ``store``
-    before the walks, while every operation stays float64.  With
-    ``np.float32`` this is the precision in which a float32-storage
-    implementation decides its indices, so both sides compare the same
-    decision.
+    Everything is float64.
     """
 
-    def __init__(self, Us, F=None, store=None):
+    def __init__(self, Us, F=None):
         self.U = [np.asarray(U, dtype=np.float64) for U in Us]
         self.N = len(self.U)
         self.R = self.U[0].shape[1]
         self.F = self.R if F is None else int(F)
-        self.store = store
         self.Z = [None] * self.N
         self.G = [None] * self.N
         for j in range(self.N):
@@ -269,67 +305,77 @@ class KRPSampler:
         if U is not None:
             self.U[j] = np.asarray(U, dtype=np.float64)
         self.Z[j] = SegmentTree(self.U[j], self.F)
-        if self.store is not None:
-            self.Z[j].levels = [_round(lv, self.store) for lv in self.Z[j].levels]
         self.G[j] = self.U[j].T @ self.U[j]
 
     def modes(self, exclude):
         return [k for k in range(self.N) if k != exclude]
 
     def prepare(self, exclude):
-        """The set-up part of Algorithm 2 (before its per-sample loop): ``G``, ``G^+``, every ``G_{>k}`` and its
-        eigendecomposition, and the trees ``E_k``."""
+        """The set-up part of Algorithm 2 (before its per-sample loop): ``G``,
+        ``G^+``, every ``G_{>k}`` and its eigendecomposition, and the trees
+        ``E_k``."""
         modes = self.modes(exclude)
         G = hadamard_all([self.G[k] for k in modes])
         Gp, rank = pinv_psd(G)
-        eig, E, degenerate = {}, {}, False
+        eig, E = {}, {}
         for k in modes:
             later = [self.G[m] for m in modes if m > k]
             Ggt = Gp * hadamard_all(later) if later else Gp.copy()
             lam, V = np.linalg.eigh((Ggt + Ggt.T) * 0.5)
             lam = np.maximum(lam, 0.0)
-            lmax = lam[-1] if lam.size else 0.0
-            tau = self.R * 2.0 ** -52 * lmax
-            gaps = np.diff(lam)
-            big = (lam[1:] > tau)
-            if np.any(gaps[big] < 1e-8 * lmax):
-                degenerate = True
             eig[k] = (lam, V)
             B = np.sqrt(lam)[:, None] * V.T          # rows sqrt(lam_u) V[:, u]^T
             E[k] = SegmentTree(B, 1)
-            if self.store is not None:
-                # node masses <h h^T, P^v, G_k> = h^T (P^v (*) G_k) h with the
-                # Hadamard product stored in the storage precision
-                E[k].levels = [_round(lv * self.G[k], self.store) for lv in E[k].levels]
-                E[k].folded = True
-        return Gp, rank, eig, E, degenerate
+        return Gp, rank, eig, E
 
-    def draw(self, exclude, u01):
+    def degenerate_boundaries(self, lam, gap_tol):
+        """``flag[b]`` for the boundary between eigenvalues ``b - 1`` and
+        ``b`` (ascending): the gap is below ``gap_tol * lambda_max`` and
+        ``lambda_b`` lies above the pseudo-inverse cut.  Inside such a
+        cluster the eigenvectors are fixed only up to a rotation, so the
+        masses of subtrees that split it depend on the basis (every basis
+        gives the same distribution)."""
+        lmax = lam[-1] if lam.size else 0.0
+        tau = self.R * 2.0 ** -52 * lmax
+        flag = np.zeros(lam.size + 1, dtype=bool)
+        flag[1:-1] = (np.diff(lam) < gap_tol * lmax) & (lam[1:] > tau)
+        return flag
+
+    def draw(self, exclude, u01, scaled=False, gap_tol=1e-8):
         """``KRPSample(j, J)`` with the uniforms ``u01[J][N][2]`` given.
 
         Column 0 of ``u01[d, k]`` drives the draw of ``u_k`` from ``E_k``
         (Section 3.2, first-stage distribution), column 1 the draw of
-        ``t_k`` from ``Z_k`` (second-stage distribution).
+        ``t_k`` from ``Z_k`` (second-stage distribution).  A draw is marked
+        degenerate when, in some mode, its first-stage walk compared against
+        a boundary inside a near-degenerate eigenvalue cluster of ``G_{>k}``
+        or picked a component of such a cluster (see
+        :meth:`degenerate_boundaries`).
         """
         u01 = np.asarray(u01, dtype=np.float64)
         J = u01.shape[0]
         modes = self.modes(exclude)
-        Gp, rank, eig, E, degenerate = self.prepare(exclude)
+        Gp, rank, eig, E = self.prepare(exclude)
         h = np.ones((J, self.R))
         idx = np.full((J, self.N), -1, dtype=np.int64)
         margin = np.full(J, np.inf)
+        smargin = np.full(J, np.inf)
+        degenerate = np.zeros(J, dtype=bool)
         for k in modes:
             lam, V = eig[k]
-            folded = getattr(E[k], "folded", False)
-            u, m1 = row_sample_batch(E[k], h, None if folded else self.G[k], u01[:, k, 0])
-            Vs = V if self.store is None else _round(V, self.store)
-            ht = h * Vs[:, u].T
-            t, m2 = row_sample_batch(self.Z[k], ht, None, u01[:, k, 1])
+            u, m1, s1 = row_sample_batch(E[k], h, self.G[k], u01[:, k, 0], scaled=scaled)
+            flag = self.degenerate_boundaries(lam, gap_tol)
+            b = _path_boundaries(u, self.R)
+            degenerate |= np.where(b >= 0, flag[np.maximum(b, 0)], False).any(axis=1)
+            degenerate |= flag[u] | flag[u + 1]
+            ht = h * V[:, u].T
+            t, m2, s2 = row_sample_batch(self.Z[k], ht, None, u01[:, k, 1], scaled=scaled)
             h = h * self.U[k][t]
             idx[:, k] = t
             margin = np.minimum(margin, np.minimum(m1, m2))
+            smargin = np.minimum(smargin, np.minimum(s1, s2))
         prob = np.einsum("da,ab,db->d", h, Gp, h) / rank
-        return Draw(idx, h, prob, margin, rank, Gp, eig, degenerate)
+        return Draw(idx, h, prob, margin, smargin, rank, Gp, eig, degenerate)
 
     def row_prob(self, exclude, idx):
         """``q`` of given multi-indices (``[M, N]``, excluded column ignored)."""

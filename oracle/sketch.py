@@ -99,14 +99,15 @@ def range_finder(tensor, j, R, seed):
     return out
 
 
-def philox_uniforms(J, N, seed, ctr_base=0):
+def philox_uniforms(J, N, seed, ctr_base=0, ctr2=0):
     """Sampler uniforms generated from (seed, ctr_base): float64 [J][N][2]
     with [d][k][s] from word s of Philox4x64-10 of counter
-    (ctr_base + d, k, 0, 0) under key (seed, 0)."""
+    (ctr_base + d, k, ctr2, 0) under key (seed, 0); ``ctr2 = sweep * N + j``
+    keys the solve of mode j in an ALS sweep."""
     d = np.arange(J, dtype=np.uint64) + np.uint64(ctr_base)
     out = np.empty((J, N, 2))
     for k in range(N):
-        ctr = np.stack([d, np.full(J, k, dtype=np.uint64), np.zeros(J, dtype=np.uint64),
+        ctr = np.stack([d, np.full(J, k, dtype=np.uint64), np.full(J, ctr2, dtype=np.uint64),
                         np.zeros(J, dtype=np.uint64)], 1)
         x = philox4x64(ctr, [seed, 0])
         for s in range(2):

@@ -1,5 +1,7 @@
 """Writes the oracle's per-sweep fits of a sketched CP-ALS workload to
-``als_fits_c<config>_<store>.json`` beside this script.
+``als_fits_c<config>_<f64|f32>.json`` beside this script (``f32``: the
+factors are kept rounded to float32 after every solve, as a float32-storage
+implementation keeps them; all arithmetic is float64).
 
 Runs the float64 oracle only (``oracle.cp.cp_als``, Algorithm 6 with the
 sampled solve) on the seeded inputs of ``synth.als_problem``; the GPU tests
@@ -27,7 +29,7 @@ def main():
     config = int(sys.argv[1])
     store_name = sys.argv[2]
     nnz = int(float(sys.argv[3])) if len(sys.argv) > 3 else None
-    store = {"f64": None, "f32": np.float32}[store_name]
+    factor_dtype = {"f64": None, "f32": np.float32}[store_name]
     t0 = time.time()
     dims, idx, val, U0, R, J, sweeps, useed = synth.als_problem(config, nnz)
     T = ocp.SparseTensor(dims, idx, val)
@@ -37,7 +39,11 @@ def main():
     def u01_of(s, j):
         return synth.uniforms(J, N, useed + 1000 * s + j)
 
-    _, sigma, fits = ocp.cp_als(T, U0, sweeps, u01_of, store=store)
+    def progress(s, j):
+        print(f"sweep {s} solve {j} {time.time() - t0:.1f} s", flush=True)
+
+    _, sigma, fits = ocp.cp_als(T, U0, sweeps, u01_of, factor_dtype=factor_dtype,
+                                progress=progress)
     out = {"config": config, "store": store_name, "dims": list(dims), "nnz": int(T.nnz),
            "R": R, "J": J, "sweeps": sweeps, "uniform_seed": useed, "fits": fits,
            "norm2": T.norm2, "seconds": time.time() - t0,

@@ -1,0 +1,63 @@
+"""Index parity between the GPU walk and the float64 oracle.
+
+The GPU and the oracle draw with the same uniforms, so their indices must
+agree except where the two computations may legitimately decide a
+comparison differently.  A draw is excused when
+
+* it met a near-degenerate eigenvalue cluster of some ``G_{>k}``
+  (``Draw.degenerate``: inside a cluster the eigenvectors are fixed only up
+  to a rotation, which changes the first-stage masses; every basis gives the
+  same distribution), or
+* float64 path: some comparison lies within ``FP64_MARGIN`` of ``C``
+  (``|x - cut| / C``; the two sides sum the same float64 terms in another
+  order), or
+* float32 path: some comparison's scaled margin (``Draw.smargin``, the gap
+  divided by the sum of the absolute values of the terms that form ``x``
+  and the cut) is at most ``FP32_SCALED``.  The walk reads every node entry
+  and eigenvector entry rounded once to float32 (relative error at most
+  ``u = 2^-24``; the nodes are float64 sums rounded once when stored), so a
+  comparison moves by at most ``u`` per node side plus ``2 u`` through the
+  eigenvector entries of the quadratic form: ``3 u`` times its scale
+  (pinned on the CPU by ``test_scaled_margin_bounds_the_effect_of_storage_
+  rounding``), plus ``u`` for the float64 arithmetic that forms the nodes
+  and the eigendecomposition on the two sides.
+
+The split path's Grams carry ~2^-16 relative error of the products'
+absolute sums, which the scaled margin does not bound; its mismatches are
+counted and reported with the largest scaled margin needed to excuse them.
+"""
+import numpy as np
+
+U32 = 2.0 ** -24
+FP64_MARGIN = 1e-10
+FP32_SCALED = 4 * U32
+
+
+def compare(gpu_idx, dr, prec):
+    """Splits the draws into same / excused / unexcused for ``prec``."""
+    gpu_idx = np.asarray(gpu_idx).astype(np.int64)
+    same = (gpu_idx == dr.idx).all(axis=1)
+    if prec == "fp64":
+        near = dr.margin <= FP64_MARGIN
+    else:
+        near = dr.smargin <= FP32_SCALED
+    excusable = near | dr.degenerate
+    diff = ~same
+    out = {
+        "n": int(same.size),
+        "same": same,
+        "mismatch": int(diff.sum()),
+        "excusable_frac": float(excusable.mean()) if same.size else 0.0,
+        "unexcused": int((diff & ~excusable).sum()),
+        "needed_smargin": float(dr.smargin[diff & ~dr.degenerate].max())
+        if (diff & ~dr.degenerate).any() else 0.0,
+        "needed_margin": float(dr.margin[diff & ~dr.degenerate].max())
+        if (diff & ~dr.degenerate).any() else 0.0,
+    }
+    return out
+
+
+def report(tag, c):
+    print(f"{tag}: {c['n']} draws, {c['mismatch']} differ, {c['unexcused']} unexcused, "
+          f"excusable {100 * c['excusable_frac']:.2f}%, largest margin needed "
+          f"{c['needed_margin']:.2e} (scaled {c['needed_smargin']:.2e})", flush=True)

@@ -36,7 +36,7 @@ def check_prob_vs_qr(sampler, Us, exclude, u01):
 def check_walk_vs_scan(tree, H, dvec, Y=None):
     """Fraction of draws whose tree walk disagrees with a linear scan of the
     full distribution (draws with margin <= 1e-12 excused)."""
-    rows, margin = smp.row_sample_batch(tree, H, Y, dvec)
+    rows, margin, _ = smp.row_sample_batch(tree, H, Y, dvec)
     U = tree.U
     bad = 0
     for d in range(H.shape[0]):

@@ -1,6 +1,7 @@
 """Parity at the full workload sizes, in the launch configuration the
-benchmark times, on sampled outputs the oracle computes one by one and on
-properties that hold at any size.  Run with ``-m gpu``."""
+benchmark times, on sampled outputs the oracle computes one by one, on every
+deterministic step of every solve (recomputed by the oracle on the GPU's own
+draw) and on properties that hold at any size.  Run with ``-m gpu``."""
 import json
 import os
 
@@ -8,12 +9,20 @@ import numpy as np
 import pytest
 
 import synth
+from chain import check_solve
+from oracle import cp as ocp
 from oracle import sampler as osmp
+from parity import compare, report
 
 pytestmark = pytest.mark.gpu
 
-MARGIN = 1e-6
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+TOL_PROB = {"fp64": 1e-10, "fp32": 1e-9, "bf16x2": 1e-3}
+BF16_MISMATCH = 0.05
+BF16_SCALED = 2.0 ** -8
+# share of draws whose comparison may legitimately go either way (margin
+# within the precision's rounding, or a near-degenerate eigenspace)
+EXCUSABLE = {"fp64": 0.02, "fp32": 0.10}
 
 
 @pytest.fixture(scope="module")
@@ -24,10 +33,11 @@ def env():
     return krps, torch, krps.Context(0)
 
 
-@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+@pytest.mark.parametrize("prec", ["fp32", "fp64", "bf16x2"])
 def test_sampler_at_scale_sampled_against_oracle(env, prec):
     """N = 3 factors of 2^20 x 32 (1% rows x100), J = 65,536 per excluded
-    mode, the three exclusions prepared and walked as one batch."""
+    mode, the three exclusions prepared and walked as one batch (the
+    benchmark's step), against the plain float64 oracle."""
     krps, torch, ctx = env
     cfg = synth.CONFIGS[2]
     dims, R, J, N = cfg["dims"], cfg["R"], cfg["J"], cfg["N"]
@@ -43,7 +53,8 @@ def test_sampler_at_scale_sampled_against_oracle(env, prec):
     ud = [torch.from_numpy(u).to(ctx.device) for u in u01]
     idx_l, prob_l = batch.sample(ud)
     torch.cuda.synchronize()
-    orc = osmp.KRPSampler(Us, store=None if prec == "fp64" else np.float32)
+    assert S.check_status() == 0
+    orc = osmp.KRPSampler(Us)
     rng = np.random.default_rng(5)
     for k in range(N):
         idx = idx_l[k].cpu().numpy().astype(np.int64)
@@ -57,12 +68,20 @@ def test_sampler_at_scale_sampled_against_oracle(env, prec):
         rp = S.row_prob(k, idx_l[k]).cpu().numpy()
         np.testing.assert_allclose(prob, rp, rtol=1e-12)
         # sampled draws against the oracle
-        sel = np.sort(rng.choice(J, 192, replace=False))
-        dr = orc.draw(k, u01[k][sel])
-        same = (idx[sel] == dr.idx).all(axis=1)
-        assert np.all(same | (dr.margin <= MARGIN)), (k, np.sum(~same))
-        tol = 1e-10 if prec == "fp64" else 1e-5
-        np.testing.assert_allclose(prob[sel][same], dr.prob[same], rtol=tol)
+        sel = np.sort(rng.choice(J, 256, replace=False))
+        dr = orc.draw(k, u01[k][sel], scaled=prec != "fp64")
+        c = compare(idx[sel], dr, prec)
+        report(f"sampler at scale {prec} exclude={k}", c)
+        same = c["same"]
+        rel = np.abs(prob[sel][same] - dr.prob[same]) / dr.prob[same]
+        print(f"  q_d rel err max {rel.max():.2e}", flush=True)
+        assert rel.max() <= TOL_PROB[prec]
+        if prec == "bf16x2":
+            assert c["mismatch"] <= BF16_MISMATCH * c["n"]
+            assert c["needed_smargin"] <= BF16_SCALED
+        else:
+            assert c["unexcused"] == 0
+            assert c["excusable_frac"] <= EXCUSABLE[prec]
 
 
 def test_batched_samplers_at_scale(env):
@@ -96,16 +115,88 @@ def test_batched_samplers_at_scale(env):
     rng = np.random.default_rng(6)
     for p in small:
         Us = [U.cpu().numpy() for U in facs[p]]
-        orc = osmp.KRPSampler(Us, store=np.float32)
         sel = np.sort(rng.choice(J, 128, replace=False))
-        u = unis[p].cpu().numpy()[sel]
-        dr = orc.draw(-1, u)
-        got = idx_b[p].cpu().numpy().astype(np.int64)[sel]
-        same = (got == dr.idx).all(axis=1)
-        assert np.all(same | (dr.margin <= MARGIN)), (p, np.sum(~same))
-        np.testing.assert_allclose(prob_b[p].cpu().numpy()[sel][same], dr.prob[same], rtol=1e-5)
+        dr = osmp.KRPSampler(Us).draw(-1, unis[p].cpu().numpy()[sel], scaled=True)
+        c = compare(idx_b[p].cpu().numpy()[sel], dr, "fp32")
+        report(f"batched at scale problem {p} {probs[p]}", c)
+        assert c["unexcused"] == 0
+        same = c["same"]
+        np.testing.assert_allclose(prob_b[p].cpu().numpy()[sel][same], dr.prob[same],
+                                   rtol=TOL_PROB["fp32"])
     del samplers, facs, batch
     torch.cuda.empty_cache()
+
+
+@pytest.fixture(scope="module")
+def c3():
+    """The sketched CP-ALS workload's inputs and the oracle's tensor."""
+    dims, idx, val, U0, R, J, sweeps, useed = synth.als_problem(3)
+    print("sketched CP-ALS inputs generated", flush=True)
+    T = ocp.SparseTensor(dims, idx, val)
+    for j in range(len(dims)):
+        T.fibers(j)
+    print("oracle fibers sorted", flush=True)
+    return dims, idx, val, U0, R, J, sweeps, useed, T
+
+
+def _als_state(krps, torch, ctx, c3, prec):
+    dims, idx, val, U0, R, J, sweeps, useed, _ = c3
+    Tg = krps.Tensor(ctx, dims, torch.from_numpy(idx).to(ctx.device),
+                     torch.from_numpy(val).to(ctx.device))
+    dt = torch.float64 if prec == "fp64" else torch.float32
+    S = krps.Sampler(ctx, [torch.from_numpy(U).to(ctx.device).to(dt).contiguous() for U in U0],
+                     precision=prec)
+    A = krps.CPALS(S, Tg, J)
+    for k in range(3):
+        A.normalize(k)
+    A.sigma.fill_(1.0)
+    return S, Tg, A
+
+
+@pytest.mark.timeout(1800)
+@pytest.mark.parametrize("prec", ["fp64", "bf16x2"])
+def test_sketched_cp_als_chain_at_scale(env, c3, prec):
+    """Every solve of 10 sweeps on the 1e8-entry tensor (R = 64,
+    J = 65,536), checked on the GPU's own draw: q_d, M, Y, M^+, U_j and
+    sigma against the oracle step by step (the same kernels a captured sweep
+    replays), sampled indices against the oracle's draw from the factors
+    the solve started from, and the fit against the oracle's fit of the
+    GPU's factors."""
+    krps, torch, ctx = env
+    dims, idx, val, U0, R, J, sweeps, useed, T = c3
+    S, Tg, A = _als_state(krps, torch, ctx, c3, prec)
+    rng = np.random.default_rng(7)
+    worst = {}
+    mism = 0
+    for s in range(sweeps):
+        u_sweep = synth.sweep_uniforms(useed, s, 3, J)
+        for j in range(3):
+            before = [U.cpu().numpy().astype(np.float64) for U in S.factors]
+            A.solve(j, torch.from_numpy(u_sweep[j]).to(ctx.device))
+            torch.cuda.synchronize()
+            parts = {k: v.cpu().numpy() for k, v in A.parts(j).items()}
+            errs = check_solve(T, before, j, parts, S.factors[j].cpu().numpy(),
+                               A.sigma.cpu().numpy(), prec)
+            for k, v in errs.items():
+                worst[k] = max(worst.get(k, 0.0), v)
+            sel = np.sort(rng.choice(J, 48, replace=False))
+            dr = osmp.KRPSampler(before).draw(j, u_sweep[j][sel], scaled=prec != "fp64")
+            c = compare(parts["idx"][sel], dr, prec)
+            mism += c["mismatch"]
+            if prec == "fp64":
+                assert c["unexcused"] == 0, (s, j)
+            else:
+                assert c["needed_smargin"] <= BF16_SCALED, (s, j)
+            print(f"sweep {s} solve {j}: " +
+                  " ".join(f"{k} {v:.1e}" for k, v in errs.items()) +
+                  f"; sampled draws differing {c['mismatch']}/48", flush=True)
+        if s in (0, sweeps // 2, sweeps - 1):
+            f = A.fit()
+            ref = ocp.fit(T, [U.cpu().numpy() for U in S.factors], A.sigma.cpu().numpy())
+            print(f"sweep {s}: fit {f:.8f} oracle on the same factors {ref:.8f}", flush=True)
+            assert abs(f - ref) <= 1e-9
+    print(f"{prec}: worst step errors {worst}; sampled draws differing {mism}", flush=True)
+    assert S.check_status() == 0
 
 
 def _golden(store):
@@ -113,49 +204,85 @@ def _golden(store):
     return json.load(open(path)) if os.path.exists(path) else None
 
 
+@pytest.mark.timeout(900)
 @pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x2"])
-def test_sketched_cp_als_at_scale_against_oracle_fits(env, prec):
-    """The sketched CP-ALS workload (1e6 x 1e6 x 1e5, 1e8 Zipf(1.2)
-    entries, R = 64, J = 65,536, 10 sweeps, graph replay) against the
-    fits the float64 oracle stored for the same inputs and uniforms."""
+def test_sketched_cp_als_at_scale_against_oracle_fits(env, c3, prec):
+    """The graph-replayed 10-sweep run against the fits of the oracle's own
+    run with the same inputs and uniforms.  The two runs draw the same
+    samples except where a comparison lies within rounding of its cut (or
+    in a near-degenerate eigenspace); such a draw gives another, equally
+    valid sketch, and from then on the trajectories differ by sketch noise.
+    Every step of every solve is checked deterministically by
+    test_sketched_cp_als_chain_at_scale; here the final fits must agree to
+    1e-4 (the sketch-noise spread of the final fit over uniform seeds is
+    ~3e-5)."""
     krps, torch, ctx = env
     ref = _golden("f64" if prec == "fp64" else "f32")
     if ref is None:
         pytest.skip("oracle fits of the 1e8-entry workload not stored")
-    dims, idx, val, U0, R, J, sweeps, useed = synth.als_problem(3)
+    dims, idx, val, U0, R, J, sweeps, useed, _ = c3
     assert ref["nnz"] == len(val) and ref["sweeps"] == sweeps
-    T = krps.Tensor(ctx, dims, torch.from_numpy(idx).to(ctx.device),
-                    torch.from_numpy(val).to(ctx.device))
-    del idx, val
-    dt = torch.float64 if prec == "fp64" else torch.float32
-    S = krps.Sampler(ctx, [torch.from_numpy(U).to(ctx.device).to(dt).contiguous() for U in U0],
-                     precision=prec)
-    A = krps.CPALS(S, T, J)
-    for k in range(3):
-        A.normalize(k)
-    A.sigma.fill_(1.0)
+    S, Tg, A = _als_state(krps, torch, ctx, c3, prec)
     ubuf = torch.empty((3, J, 3, 2), dtype=torch.float64, device=ctx.device)
     fits = []
     for s in range(sweeps):
         ubuf.copy_(torch.from_numpy(synth.sweep_uniforms(useed, s, 3, J)))
         A.sweep(ubuf, use_graph=True)
         fits.append(A.fit())
+    zero_w = S.check_status()
     diff = np.abs(np.array(fits) - np.array(ref["fits"]))
     print(f"{prec}: fits {np.round(fits, 6)} oracle {np.round(ref['fits'], 6)} "
-          f"max diff {diff.max():.2e}", flush=True)
-    # The early sweeps are sensitive.  At the random start G and every
-    # G_{>k} are close to the identity (eigenvalue gaps ~1e-5 relative), so
-    # their eigenvectors inside near-degenerate clusters are fixed only up to
-    # a rotation that any rounding difference changes.  The first stage of
-    # the draw picks an eigencomponent (Section 3.2), so two correct
-    # implementations draw from the same distribution but realise different
-    # sketches from the same uniforms (measured: 152 of 65,536 draws of the
-    # very first solve differ between two GPU pseudo-inverse routes whose
-    # G^+ agree to 1e-13).  The fits then differ by sketch noise, large at
-    # the first sweeps (the fit after one sweep ranges over 0.63-0.78
-    # between sketches) and damped by the later ones: the last sweep is held
-    # to 1e-4 (1e-3 for the split Grams) and every sweep from the third on to
-    # 3e-4 (2e-3).
-    last, every = (1e-3, 2e-3) if prec == "bf16x2" else (1e-4, 3e-4)
-    assert diff[-1] <= last
-    assert diff[2:].max() <= every
+          f"diffs {np.array2string(diff, precision=1)}; zero-weight samples {zero_w}",
+          flush=True)
+    assert diff[-1] <= 1e-4
+
+
+@pytest.mark.timeout(1200)
+@pytest.mark.parametrize("prec", ["fp64", "bf16x2"])
+def test_large_cp_als_one_solve_at_reduced_nnz(env, prec):
+    """The large 4-mode workload's shapes (2e7 x 2e7 x 2e7 x 1e6, R = 128,
+    J = 131,072, Zipf(1.1) indices) with 2e6 entries: range-finder start,
+    then one solve of mode 3 (the 1e6-row mode; its draws walk the three
+    2e7-row factors) checked step by step on the GPU's own draw
+    (the factors are too large to hand to the oracle whole: the sampled rows
+    are gathered on the device and the Grams summed on the host in
+    chunks)."""
+    krps, torch, ctx = env
+    cfg = synth.CONFIGS[5]
+    dims, R, J = cfg["dims"], cfg["R"], cfg["J"]
+    dims_, idx, val, U0, R_, J_, _, useed = synth.als_problem(5, nnz=2_000_000)
+    T = ocp.SparseTensor(dims, idx, val)
+    Tg = krps.Tensor(ctx, dims, torch.from_numpy(idx).to(ctx.device),
+                     torch.from_numpy(val).to(ctx.device))
+    dt = torch.float64 if prec == "fp64" else torch.float32
+    Ud = [torch.zeros((d, R), dtype=dt, device=ctx.device) for d in dims]
+    S = krps.Sampler(ctx, Ud, precision=prec)
+    A = krps.CPALS(S, Tg, J)
+    for k in range(4):
+        A.init_range_finder(k, seed=12345 + k)
+    A.sigma.fill_(1.0)
+    torch.cuda.synchronize()
+    print(f"large one solve {prec}: range finder done", flush=True)
+    j = 3
+    grams = {}
+    for k in range(3):
+        G = np.zeros((R, R))
+        for s0 in range(0, dims[k], 1 << 22):
+            X = S.factors[k][s0:s0 + (1 << 22)].cpu().numpy().astype(np.float64)
+            G += X.T @ X
+        grams[k] = G
+    u01 = synth.uniforms(J, 4, useed)
+    A.solve(j, torch.from_numpy(u01).to(ctx.device))
+    torch.cuda.synchronize()
+    parts = {k: v.cpu().numpy() for k, v in A.parts(j).items()}
+    gi = A.parts(j)["idx"].long()
+    rows = torch.ones((J, R), dtype=torch.float64, device=ctx.device)
+    for k in range(3):
+        rows *= S.factors[k][gi[:, k]].double()
+    errs = check_solve(T, [None] * 4, j, parts, S.factors[j].cpu().numpy(),
+                       A.sigma.cpu().numpy(), prec, grams=grams, rows=rows.cpu().numpy())
+    print(f"large one solve {prec}: " + " ".join(f"{k} {v:.1e}" for k, v in errs.items()) +
+          f"; rows of Y reached {len(parts['yrows'])}", flush=True)
+    assert len(parts["yrows"]) > 0
+    del A, S, Ud, Tg
+    torch.cuda.empty_cache()

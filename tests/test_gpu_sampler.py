@@ -6,13 +6,22 @@ import pytest
 import synth
 from oracle import definition as dfn
 from oracle import sampler as osmp
+from parity import compare, report
 
 pytestmark = pytest.mark.gpu
 
 TOL_NODE = {"fp64": 1e-12, "fp32": 1e-5, "bf16x2": 1e-4}
-TOL_PROB = {"fp64": 1e-10, "fp32": 1e-5, "bf16x2": 1e-3}
-MARGIN = 1e-6
-STORE = {"fp64": None, "fp32": np.float32, "bf16x2": np.float32}
+# q_d = a G^+ a^T / rank in float64 from the stored factor rows and the
+# float64 Grams (exact products of float32 factors for FP32): only the
+# summation order differs from the oracle; the split path's Grams carry
+# ~2^-16 relative error
+TOL_PROB = {"fp64": 1e-10, "fp32": 1e-9, "bf16x2": 1e-3}
+# bounds on the split path's draws against the float64 oracle: the share of
+# draws that differ and the largest scaled margin among them (node entries
+# off by ~2^-15 of the products' absolute sums, times R / 4 for the
+# quadratic form over R columns)
+BF16_MISMATCH = 0.05
+BF16_SCALED = 2.0 ** -8
 
 
 @pytest.fixture(scope="module")
@@ -74,38 +83,55 @@ def test_tree_nodes_match_oracle(env, prec, dims, R, F):
         assert np.abs(G - Gref).max() <= TOL_NODE[prec] * np.abs(np.diag(Gref)).max()
 
 
+PREP = [((64, 50, 70), 8), ((3000, 2500, 2000), 64), ((900, 700, 500), 128)]
+
+
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("dims,R", PREP)
 @pytest.mark.parametrize("exclude", [-1, 0, 2])
-def test_prep_matches_oracle(env, prec, exclude):
+def test_prep_matches_oracle(env, prec, dims, R, exclude):
+    """G^+, rank, eigenvalues, eigenvectors (isolated eigenvalues; the
+    projector onto a cluster otherwise) and the eigen-trees with G_k folded
+    in, against the oracle's preparation."""
     krps, torch, ctx = env
-    print(f"prep {prec} exclude={exclude}", flush=True)
-    cfg = synth.CONFIGS[1]
-    Us = synth.gaussian_factors((64, 50, 70), 8, synth.config_seed(1))
+    print(f"prep {prec} dims={dims} R={R} exclude={exclude}", flush=True)
+    Us = synth.gaussian_factors(dims, R, synth.config_seed(1) + R)
     S = krps.Sampler(ctx, to_dev(torch, ctx, Us, prec), precision=prec)
     u = torch.from_numpy(synth.uniforms(16, 3, 1)).to(ctx.device)
     S.sample(exclude, u)
     torch.cuda.synchronize()
     parts = {k: (v.cpu() if hasattr(v, "cpu") else v) for k, v in S.draw_parts().items()}
     ref = osmp.KRPSampler(Us)
-    Gp, rank, eig, E, _ = ref.prepare(exclude)
-    rtol = 1e-10 if prec == "fp64" else 1e-4
+    Gp, rank, eig, E = ref.prepare(exclude)
+    # float32 storage only rounds the eigenvectors and the eigen-tree nodes
+    rtol = 1e-10 if prec == "fp64" else 1e-6
     assert parts["rank"] == rank
-    assert np.abs(parts["gplus"].numpy() - Gp).max() <= rtol * np.abs(Gp).max()
+    assert np.abs(parts["gplus"].numpy() - Gp).max() <= 1e-10 * np.abs(Gp).max()
+    iu = np.triu_indices(R)
     for k in ref.modes(exclude):
         lam, V = eig[k]
-        assert np.abs(parts["lam"][k].numpy() - lam).max() <= rtol * lam.max()
-        Vg = parts["vecs"][k].numpy().astype(np.float64)     # [u][:]
-        # sign-insensitive: |<v_gpu, v_ref>| = 1
-        dots = np.abs(np.einsum("ue,eu->u", Vg, V))
-        assert np.abs(dots - 1).max() <= (1e-9 if prec == "fp64" else 1e-4)
-        iu = np.triu_indices(8)
+        assert np.abs(parts["lam"][k].numpy() - lam).max() <= 1e-10 * lam.max()
+        Vg = parts["vecs"][k].numpy().astype(np.float64).T     # columns = eigenvectors
+        gaps = np.diff(lam)
+        iso = np.ones(R, dtype=bool)
+        iso[1:] &= gaps > 1e-6 * lam.max()
+        iso[:-1] &= gaps > 1e-6 * lam.max()
+        dots = np.abs(np.einsum("eu,eu->u", Vg, V))
+        assert np.abs(dots[iso] - 1).max() <= (1e-9 if prec == "fp64" else 1e-6)
+        # the whole decomposition: sum_u lam_u v_u v_u^T = G_{>k}
+        rec = (Vg * lam) @ Vg.T
+        ggt = (V * lam) @ V.T
+        assert np.abs(rec - ggt).max() <= rtol * 10 * np.abs(ggt).max()
         Eref = [E[k].root * ref.G[k]]
         for lev in range(1, E[k].D + 1):
             for p in range(0, E[k].real(lev), 2):
                 Eref.append(E[k].levels[lev][p] * ref.G[k])
         Eref = np.array([m[iu] for m in Eref])
         Eg = parts["etree"][k].numpy().astype(np.float64)
-        assert np.abs(Eg - Eref).max() <= rtol * 10 * np.abs(Eref).max()
+        if iso.all():
+            assert np.abs(Eg - Eref).max() <= rtol * 10 * np.abs(Eref).max()
+        else:
+            assert np.abs(Eg[0] - Eref[0]).max() <= rtol * 10 * np.abs(Eref).max()
 
 
 def test_pseudo_inverse_routes(env):
@@ -124,7 +150,7 @@ def test_pseudo_inverse_routes(env):
         S.sample(-1, torch.from_numpy(synth.uniforms(16, 3, 2)).to(ctx.device))
         torch.cuda.synchronize()
         parts = S.draw_parts()
-        Gp, rank, _, _, _ = osmp.KRPSampler(Us).prepare(-1)
+        Gp, rank, _, _ = osmp.KRPSampler(Us).prepare(-1)
         assert parts["rank"] == rank == want_rank
         assert (parts["sweeps"][0] == 0) == cholesky
         Gg = parts["gplus"].cpu().numpy()
@@ -137,15 +163,14 @@ def _compare_draw(krps, torch, ctx, Us, prec, exclude, J, useed, F=0):
     idx, prob, rows = S.sample(exclude, torch.from_numpy(u01).to(ctx.device), rows=True,
                                check_status=True)
     torch.cuda.synchronize()
-    # the float32-storage path decides its indices on float32-rounded nodes
-    ref = osmp.KRPSampler(Us, F=F or None, store=STORE[prec])
-    dr = ref.draw(exclude, u01)
+    # the plain float64 oracle over the same (float32) factors
+    ref = osmp.KRPSampler(Us, F=F or None)
+    dr = ref.draw(exclude, u01, scaled=prec != "fp64")
     idx = idx.cpu().numpy().astype(np.int64)
-    same = (idx == dr.idx).all(axis=1)
-    excused = (dr.margin <= MARGIN) | dr.degenerate
-    bad = ~(same | excused)
+    c = compare(idx, dr, prec)
+    same = c["same"]
     rel = np.abs(prob.cpu().numpy()[same] - dr.prob[same]) / dr.prob[same]
-    return S, idx, prob, rows, dr, same, bad, rel
+    return S, idx, prob, rows, dr, c, rel
 
 
 CASES = [((64, 64, 64), 8, 4096), ((1000, 333, 77), 16, 2048), ((5000, 2049, 700), 32, 2048),
@@ -158,14 +183,15 @@ def test_draw_matches_oracle(env, prec, dims, R, J):
     krps, torch, ctx = env
     Us = synth.gaussian_factors(dims, R, seed=3 * R + len(dims), heavy_rows_frac=0.01)
     for exclude in [-1] + list(range(len(dims))) if len(dims) > 1 else [-1]:
-        print(f"draw {prec} dims={dims} R={R} J={J} exclude={exclude}", flush=True)
-        S, idx, prob, rows, dr, same, bad, rel = _compare_draw(krps, torch, ctx, Us, prec,
-                                                               exclude, J, 100 + exclude)
-        assert bad.sum() == 0, (bad.sum(), J)
-        assert same.mean() > 0.9
+        S, idx, prob, rows, dr, c, rel = _compare_draw(krps, torch, ctx, Us, prec,
+                                                       exclude, J, 100 + exclude)
+        report(f"draw {prec} dims={dims} R={R} exclude={exclude}", c)
+        assert c["unexcused"] == 0
+        assert c["excusable_frac"] <= 0.02
         assert rel.max() <= TOL_PROB[prec], rel.max()
+        same = c["same"]
         r = rows.cpu().numpy().astype(np.float64)
-        np.testing.assert_allclose(r[same], dr.rows[same], rtol=1e-12 if prec == "fp64" else 1e-5,
+        np.testing.assert_allclose(r[same], dr.rows[same], rtol=1e-12 if prec == "fp64" else 1e-7,
                                    atol=1e-300)
         if exclude >= 0:
             assert np.all(idx[:, exclude] == -1)
@@ -178,13 +204,12 @@ def test_leaf_size_does_not_change_indices(env, prec):
     u01 = synth.uniforms(2048, 3, 9)
     ud = torch.from_numpy(u01).to(ctx.device)
     for F in (1, 5, 16, 64, 200):
-        ref = osmp.KRPSampler(Us, F=F, store=STORE[prec]).draw(1, u01)
-        print(f"leaf size {prec} F={F}", flush=True)
+        ref = osmp.KRPSampler(Us, F=F).draw(1, u01, scaled=prec != "fp64")
         S = krps.Sampler(ctx, to_dev(torch, ctx, Us, prec), precision=prec, F=F)
         idx, _, _ = S.sample(1, ud)
-        idx = idx.cpu().numpy().astype(np.int64)
-        ok = (idx == ref.idx).all(axis=1) | (ref.margin <= MARGIN)
-        assert ok.all(), (F, (~ok).sum())
+        c = compare(idx.cpu().numpy(), ref, prec)
+        report(f"leaf size {prec} F={F}", c)
+        assert c["unexcused"] == 0, F
 
 
 def test_row_prob_matches_oracle(env):
@@ -220,11 +245,11 @@ def test_probabilities_equal_exact_leverage_c1(env):
 def test_single_factor_and_rank_one(env):
     krps, torch, ctx = env
     U = synth.gaussian_factors((300,), 6, seed=3)
-    _, idx, prob, _, dr, same, bad, rel = _compare_draw(krps, torch, ctx, U, "fp64", -1, 512, 4)
-    assert bad.sum() == 0 and rel.max() <= 1e-10
+    _, idx, prob, _, dr, c, rel = _compare_draw(krps, torch, ctx, U, "fp64", -1, 512, 4)
+    assert c["unexcused"] == 0 and rel.max() <= 1e-10
     Us = synth.gaussian_factors((40, 30, 20), 1, seed=4)
-    _, idx, prob, _, dr, same, bad, rel = _compare_draw(krps, torch, ctx, Us, "fp64", 2, 512, 5)
-    assert bad.sum() == 0 and rel.max() <= 1e-10
+    _, idx, prob, _, dr, c, rel = _compare_draw(krps, torch, ctx, Us, "fp64", 2, 512, 5)
+    assert c["unexcused"] == 0 and rel.max() <= 1e-10
 
 
 def test_zero_product_is_reported(env):
@@ -241,14 +266,22 @@ def test_zero_product_is_reported(env):
     S2.sample(1, u, check_status=True)
 
 
-def test_split_precision_reports_mismatch_rate(env):
+@pytest.mark.parametrize("dims,R", [((5000, 2049, 700), 32), ((3001, 1500, 800), 64),
+                                    ((900, 777, 500), 128)])
+def test_split_precision_reports_mismatch_rate(env, dims, R):
+    """BF16 hi/lo split Grams against the plain float64 oracle: the share of
+    differing draws and the largest scaled margin among them stay below the
+    stated bounds, and q_d of the agreeing draws within 1e-3."""
     krps, torch, ctx = env
-    Us = synth.gaussian_factors((5000, 2049, 700), 32, seed=99, heavy_rows_frac=0.01)
-    _, idx, prob, _, dr, same, bad, rel = _compare_draw(krps, torch, ctx, Us, "bf16x2", 0, 4096, 7)
-    print(f"bf16x2: mismatch {1 - same.mean():.4f}, unexcused {bad.mean():.4f}, "
-          f"prob rel err max {rel.max():.2e}", flush=True)
-    assert same.mean() > 0.9
-    assert rel.max() <= TOL_PROB["bf16x2"]
+    Us = synth.gaussian_factors(dims, R, seed=99 + R, heavy_rows_frac=0.01)
+    for exclude in (-1, 0):
+        _, idx, prob, _, dr, c, rel = _compare_draw(krps, torch, ctx, Us, "bf16x2", exclude,
+                                                    4096, 7)
+        report(f"bf16x2 dims={dims} R={R} exclude={exclude}", c)
+        print(f"  q_d rel err max {rel.max():.2e}", flush=True)
+        assert c["mismatch"] <= BF16_MISMATCH * c["n"]
+        assert c["needed_smargin"] <= BF16_SCALED
+        assert rel.max() <= TOL_PROB["bf16x2"]
 
 
 def test_autotune_measures_then_reads_the_cache(tmp_path):
@@ -263,15 +296,16 @@ def test_autotune_measures_then_reads_the_cache(tmp_path):
     assert not t1["from_cache"] and t1["F"] in (8, 16, 32, 64) and t1["lps"] in (8, 16)
     t2 = krps.autotune(ctx, Ud, u, "fp32", cache_path=cache)
     assert t2["from_cache"] and (t2["F"], t2["lps"]) == (t1["F"], t1["lps"])
-    # the tuned shape draws the same indices as the default one
-    S0 = krps.Sampler(ctx, Ud, precision="fp32")
+    # the tuned shape's draws against the float64 oracle
     S1 = krps.Sampler(ctx, Ud, precision="fp32", F=t1["F"], lps=t1["lps"])
-    i0, p0, _ = S0.sample(-1, u)
     i1, p1, _ = S1.sample(-1, u)
     torch.cuda.synchronize()
-    same = (i0 == i1).all(dim=1).cpu().numpy()
-    assert same.mean() >= 0.999, same.mean()
-    np.testing.assert_allclose(p1.cpu().numpy()[same], p0.cpu().numpy()[same], rtol=1e-5)
+    dr = osmp.KRPSampler(Us, F=t1["F"]).draw(-1, u.cpu().numpy(), scaled=True)
+    c = compare(i1.cpu().numpy(), dr, "fp32")
+    report(f"autotuned F={t1['F']} lps={t1['lps']}", c)
+    assert c["unexcused"] == 0
+    same = c["same"]
+    np.testing.assert_allclose(p1.cpu().numpy()[same], dr.prob[same], rtol=TOL_PROB["fp32"])
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
@@ -295,10 +329,10 @@ def test_in_kernel_uniforms_match_the_oracle(prec):
             first = idx
         torch.cuda.synchronize()
         u = osk.philox_uniforms(J, 3, 2026, 1000)
-        dr = osmp.KRPSampler(Us, store=None if prec == "fp64" else np.float32).draw(exclude, u)
-        got = idx.cpu().numpy().astype(np.int64)
-        same = (got == dr.idx).all(axis=1)
-        assert np.all(same | (dr.margin <= 1e-6)), np.sum(~same)
+        dr = osmp.KRPSampler(Us).draw(exclude, u, scaled=prec != "fp64")
+        c = compare(idx.cpu().numpy(), dr, prec)
+        report(f"in-kernel uniforms {prec} exclude={exclude}", c)
+        assert c["unexcused"] == 0
         # the same uniforms through the buffer path give the same draws
         i2, p2, _ = S.sample(exclude, torch.from_numpy(u).to(ctx.device))
         torch.cuda.synchronize()

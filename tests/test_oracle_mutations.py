@@ -24,7 +24,7 @@ class _GeqK(smp.KRPSampler):
     """Uses G_{>=k} (includes G_k itself) instead of G_{>k}."""
 
     def prepare(self, exclude):
-        Gp, rank, eig, E, deg = super().prepare(exclude)
+        Gp, rank, eig, E = super().prepare(exclude)
         modes = self.modes(exclude)
         for k in modes:
             later = [self.G[m] for m in modes if m >= k]
@@ -33,17 +33,17 @@ class _GeqK(smp.KRPSampler):
             lam = np.maximum(lam, 0)
             eig[k] = (lam, V)
             E[k] = smp.SegmentTree(np.sqrt(lam)[:, None] * V.T, 1)
-        return Gp, rank, eig, E, deg
+        return Gp, rank, eig, E
 
 
 class _EigRowsNotColumns(smp.KRPSampler):
     """Builds E_k over sqrt(Lambda) V (rows of V) instead of sqrt(Lambda) V^T."""
 
     def prepare(self, exclude):
-        Gp, rank, eig, E, deg = super().prepare(exclude)
+        Gp, rank, eig, E = super().prepare(exclude)
         for k, (lam, V) in eig.items():
             E[k] = smp.SegmentTree(np.sqrt(lam)[:, None] * V, 1)
-        return Gp, rank, eig, E, deg
+        return Gp, rank, eig, E
 
 
 def test_g_greater_or_equal_k_is_caught():
@@ -75,9 +75,9 @@ def test_transposed_eigenvector_matrix_is_caught():
 def test_leaf_scan_off_by_one_is_caught(monkeypatch):
     orig = smp._row_sample_chunk
 
-    def shifted(tree, H, Y, dvec):
-        rows, m = orig(tree, H, Y, dvec)
-        return np.minimum(rows + 1, tree.I - 1), m
+    def shifted(tree, H, Y, dvec, scaled=False):
+        rows, m, sm = orig(tree, H, Y, dvec, scaled)
+        return np.minimum(rows + 1, tree.I - 1), m, sm
 
     monkeypatch.setattr(smp, "_row_sample_chunk", shifted)
     rng = np.random.default_rng(3)
@@ -89,7 +89,7 @@ def test_leaf_scan_off_by_one_is_caught(monkeypatch):
 
 
 def test_walk_without_low_update_is_caught(monkeypatch):
-    def no_low(tree, H, Y, dvec):
+    def no_low(tree, H, Y, dvec, scaled=False):
         n, R = H.shape
         HH = H[:, :, None] * H[:, None, :]
         C = np.einsum("dab,ab->d", HH, tree.root)
@@ -101,7 +101,7 @@ def test_walk_without_low_update_is_caught(monkeypatch):
             go_left = (mL >= x) | ((left + 1) >= tree.real(lev))   # "low" dropped
             pos = np.where(go_left, left, left + 1)
         s0 = pos * tree.F
-        return np.minimum(s0, tree.I - 1), np.ones(n)
+        return np.minimum(s0, tree.I - 1), np.ones(n), np.full(n, np.inf)
 
     monkeypatch.setattr(smp, "_row_sample_chunk", no_low)
     rng = np.random.default_rng(5)

@@ -69,7 +69,7 @@ def test_scalar_and_batched_row_sample_agree():
     t = smp.SegmentTree(U, 5)
     H = rng.standard_normal((50, 5))
     d = synth.uniforms(50, 1, 3)[:, 0, 0]
-    rows, marg = smp.row_sample_batch(t, H, None, d)
+    rows, marg, _ = smp.row_sample_batch(t, H, None, d)
     for i in range(50):
         r, m = smp.row_sample(t, H[i], None, d[i])
         assert r == rows[i]
@@ -93,7 +93,7 @@ def test_draw_probabilities_equal_qr_leverage_c1(exclude):
 def test_eigen_trees_reconstruct_g_greater_k():
     cfg, Us = _c1()
     S = smp.KRPSampler(Us)
-    Gp, rank, eig, E, _ = S.prepare(-1)
+    Gp, rank, eig, E = S.prepare(-1)
     assert rank == 8
     for k in range(3):
         later = [S.G[m] for m in range(3) if m > k]
@@ -238,13 +238,84 @@ def test_two_stage_draw_equals_bruteforce_inversion(exclude):
     assert check_two_stage_vs_bruteforce(smp.KRPSampler(Us, F=2), Us, exclude, u) == 0.0
 
 
-def test_storage_precision_changes_only_near_boundary_draws():
-    # rounding the cached nodes to float32 may move only draws whose uniform
-    # sits near a bucket edge; probabilities of the drawn rows are unchanged
-    Us = synth.gaussian_factors((300, 200, 100), 16, seed=70, heavy_rows_frac=0.01)
-    u = synth.uniforms(3000, 3, 71)
-    a = smp.KRPSampler(Us).draw(0, u)
-    b = smp.KRPSampler(Us, store=np.float32).draw(0, u)
-    same = (a.idx == b.idx).all(axis=1)
-    assert np.all(same | (a.margin < 1e-5))
-    np.testing.assert_allclose(b.prob[same], a.prob[same], rtol=1e-12)
+class _Perturbed(smp.KRPSampler):
+    """Every stored node entry of the factor trees and eigen-trees and every
+    eigenvector entry multiplied by (1 + e), |e| <= u (symmetric in the
+    node's two indices, as a packed triangle is stored): the rounding a
+    storage precision with unit roundoff u applies."""
+
+    def __init__(self, Us, u, seed):
+        self.u = u
+        self.rng = np.random.default_rng(seed)
+        super().__init__(Us)
+
+    def _jitter(self, a):
+        e = self.rng.uniform(-self.u, self.u, a.shape)
+        if a.ndim == 3:
+            e = np.triu(e) + np.swapaxes(np.triu(e, 1), 1, 2)
+        return a * (1.0 + e)
+
+    def refresh(self, j, U=None):
+        super().refresh(j, U)
+        self.Z[j].levels = [self._jitter(lv) for lv in self.Z[j].levels]
+
+    def prepare(self, exclude):
+        Gp, rank, eig, E = super().prepare(exclude)
+        for k in E:
+            E[k].levels = [self._jitter(lv) for lv in E[k].levels]
+            lam, V = eig[k]
+            eig[k] = (lam, self._jitter(V))
+        return Gp, rank, eig, E
+
+
+@pytest.mark.parametrize("dims,R,heavy", [((300, 200, 100), 16, 0.01), ((777, 260), 64, 0.0),
+                                          ((2000, 50, 900), 8, 0.05)])
+def test_scaled_margin_bounds_the_effect_of_storage_rounding(dims, R, heavy):
+    """A draw can change under a relative rounding u of every stored node
+    entry and eigenvector entry only if its scaled margin is at most 3 u
+    (one u from the nodes of each side of a comparison, two from the
+    eigenvector entries in the quadratic form); at u = 1e-5 or 1e-3 draws do
+    change, so the bound is not vacuous (at u = 1e-3 at the latest)."""
+    Us = synth.gaussian_factors(dims, R, seed=70 + R, heavy_rows_frac=heavy)
+    u01 = synth.uniforms(3000, len(dims), 71)
+    ex = 0
+    a = smp.KRPSampler(Us).draw(ex, u01, scaled=True)
+    changed = 0
+    for u, seed in ((2.0 ** -24, 1), (1e-5, 2), (1e-3, 3)):
+        b = _Perturbed(Us, u, seed).draw(ex, u01)
+        diff = ~(a.idx == b.idx).all(axis=1)
+        assert np.all(a.smargin[diff] <= 3 * u), (u, a.smargin[diff].max())
+        changed += int(diff.sum())
+        # the probabilities of unchanged draws move by the rounding only
+        same = ~diff
+        np.testing.assert_allclose(b.prob[same], a.prob[same], rtol=1e-12)
+    assert changed > 0
+
+
+def test_scaled_margin_on_nonnegative_terms():
+    # with h = 1 and nonnegative rows every term is nonnegative, so the
+    # absolute sums equal the masses: the scale of a comparison is
+    # x + low + m(L) = d C + cut <= 2 C, hence scaled margin >= margin / 2;
+    # without ``scaled`` the scaled margins are inf and the rest is unchanged
+    Us = synth.gaussian_factors((64, 64), 4, seed=3)
+    t = smp.SegmentTree(np.abs(Us[0]), 4)
+    H = np.ones((200, 4))
+    d = synth.uniforms(200, 1, 4)[:, 0, 0]
+    r, m, sm = smp.row_sample_batch(t, H, None, d, scaled=True)
+    assert np.all(sm >= 0.5 * m * (1 - 1e-12))
+    r2, m2, sm2 = smp.row_sample_batch(t, H, None, d)
+    assert np.all(np.isinf(sm2)) and np.array_equal(m, m2) and np.array_equal(r, r2)
+
+
+def test_degenerate_flags_mark_only_draws_inside_a_cluster():
+    """With orthogonal factor columns of equal norms every G_k is a multiple
+    of the identity, so every G_{>k} has one eigenvalue cluster and every
+    draw is degenerate; with distinct column norms no draw is."""
+    rng = np.random.default_rng(9)
+    Q = [np.linalg.qr(rng.standard_normal((40, 4)))[0] for _ in range(3)]
+    u01 = synth.uniforms(500, 3, 10)
+    flat = smp.KRPSampler(Q).draw(-1, u01)
+    assert flat.degenerate.all()
+    scaled = [q * np.array([1.0, 2.0, 3.0, 4.0]) for q in Q]
+    dr = smp.KRPSampler(scaled).draw(-1, u01)
+    assert not dr.degenerate.any()
