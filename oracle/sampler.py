@@ -145,21 +145,32 @@ def row_sample(tree, h, Y, d):
     return s0 + chosen, margin
 
 
-def row_sample_batch(tree, H, Y, dvec, chunk=None, scaled=False):
+def row_sample_batch(tree, H, Y, dvec, chunk=None, scaled=False, vround=False):
     """Algorithm 4 for many independent samples at once (the samples march
     level by level, as in the batch-synchronous strategy of Appendix A.10).
 
     ``H``: ``[J, R]`` history vectors, ``dvec``: ``[J]`` uniforms.  Returns
-    ``(rows [J] int64, min_margin [J], min_scaled_margin [J])``.  The margin
-    of a comparison is ``|x - cut| / C``.  With ``scaled`` each comparison
-    is also divided by the sum of the absolute values of the terms that make
-    up ``x`` and ``cut`` (``d * sum|h_a h_b Y_ab G_ab|`` over the root,
-    the same sum over the left child and over every node whose mass went
-    into ``low``, the absolute row terms of the leaf scan): a rounding of
-    every node entry, weight and row term by a relative ``u`` moves the
-    comparison by at most ``u`` times that sum, so a draw whose scaled margin
-    exceeds ``u`` is decided the same way in that precision (``inf`` when
-    ``scaled`` is off).
+    ``(rows [J] int64, min_margin [J], min_scaled_margin [J])``.
+
+    The margin of a comparison is ``|x - cut| / C``.  The scaled margin
+    (``scaled=True``; ``inf`` otherwise) is ``|x - cut| / E`` with ``E`` the
+    effect on ``x - cut`` of storing every node entry, and, with ``vround``,
+    every entry of the eigenvector that multiplies the history, with a
+    relative rounding of at most 1 (so a rounding ``u`` moves the comparison
+    by about ``u E``):
+
+    * node entries: the packed terms ``t = h_a h_b Y_ab G_ab`` of every node
+      whose mass enters ``x = d C`` (the root, times ``d``) or the cut (the
+      nodes summed into ``low`` and the left child) are rounded
+      independently, so their effect is a sum of independent terms of
+      standard deviation ``|t| / sqrt(3)``; ``E`` takes 4 times the square
+      root of the sum of squares (about seven standard deviations);
+    * eigenvector entries (``vround``): one rounding per entry ``a`` of the
+      history moves every mass ``h^T G h`` by ``2 sum_a e_a h_a (G h)_a``,
+      so ``E`` adds ``2 sum_a |h_a (d G_root h - sum_{nodes in the cut} G h)_a|``
+      (the same rounding of ``h`` moves ``x`` and the cut together); the
+      rows scanned in a leaf are exact, so the leaf scan adds its rows' terms
+      here only.
     """
     H = np.asarray(H, dtype=np.float64)
     J, R = H.shape
@@ -171,7 +182,7 @@ def row_sample_batch(tree, H, Y, dvec, chunk=None, scaled=False):
     for s in range(0, J, chunk):
         e = min(J, s + chunk)
         rows[s:e], margins[s:e], smargins[s:e] = _row_sample_chunk(tree, H[s:e], Y, dvec[s:e],
-                                                                   scaled)
+                                                                   scaled, vround)
     return rows, margins, smargins
 
 
@@ -180,7 +191,14 @@ def _masses(Gs, HH):
     return np.einsum("dab,dab->d", Gs, HH)
 
 
-def _row_sample_chunk(tree, H, Y, dvec, scaled=False):
+def _node_ss(Gs, HH):
+    """Sum of squares of the packed terms of each node: the upper triangle
+    stores (a, b) once, so an off-diagonal pair counts as one term 2 t_ab."""
+    T2 = (Gs * HH) ** 2
+    return 2.0 * T2.sum(axis=(1, 2)) - np.einsum("daa->d", T2)
+
+
+def _row_sample_chunk(tree, H, Y, dvec, scaled=False, vround=False):
     n, R = H.shape
     HH = H[:, :, None] * H[:, None, :]
     if Y is not None:
@@ -193,9 +211,18 @@ def _row_sample_chunk(tree, H, Y, dvec, scaled=False):
     margin = np.full(n, np.inf)
     smargin = np.full(n, np.inf)
     if scaled:
-        HA = np.abs(HH)
-        xs = dvec * _masses(np.broadcast_to(np.abs(tree.root), (n, R, R)), HA)
-        lows = np.zeros(n)
+        root = np.broadcast_to(tree.root, (n, R, R))
+        ss_x = dvec ** 2 * _node_ss(root, HH)
+        ss_low = np.zeros(n)
+        g_x = dvec[:, None] * (root @ H[:, :, None])[:, :, 0]   # d G_root h
+        g_low = np.zeros((n, R))
+
+    def effect(ss, g):
+        e = 4.0 * np.sqrt(ss)
+        if vround:
+            e = e + 2.0 * np.abs(H * g).sum(axis=1)
+        return e
+
     for lev in range(1, tree.D + 1):
         left = 2 * pos
         GL = tree.levels[lev][left]
@@ -205,10 +232,12 @@ def _row_sample_chunk(tree, H, Y, dvec, scaled=False):
         right_exists = (left + 1) < tree.real(lev)
         go_left = (cut >= x) | (~right_exists) | (high - cut <= 0.0)
         if scaled:
-            mLs = _masses(np.abs(GL), HA)
-            smargin = np.minimum(smargin, np.where(right_exists,
-                                                   np.abs(x - cut) / (xs + lows + mLs), np.inf))
-            lows = np.where(go_left, lows, lows + mLs)
+            ss_L = _node_ss(GL, HH)
+            g_L = (GL @ H[:, :, None])[:, :, 0]
+            E = effect(ss_x + ss_low + ss_L, g_x - g_low - g_L)
+            smargin = np.minimum(smargin, np.where(right_exists, np.abs(x - cut) / E, np.inf))
+            ss_low = np.where(go_left, ss_low, ss_low + ss_L)
+            g_low = np.where(go_left[:, None], g_low, g_low + g_L)
         pos = np.where(go_left, left, left + 1)
         high = np.where(go_left, cut, high)
         low = np.where(go_left, low, cut)
@@ -221,7 +250,8 @@ def _row_sample_chunk(tree, H, Y, dvec, scaled=False):
     offs = np.arange(F)
     ridx = s0[:, None] + offs[None, :]
     valid = ridx < tree.I
-    Wr = tree.U[np.minimum(ridx, tree.I - 1)] * H[:, None, :]
+    Ur = tree.U[np.minimum(ridx, tree.I - 1)]
+    Wr = Ur * H[:, None, :]
     if Y is None:
         qt = Wr.sum(axis=2) ** 2
     else:
@@ -232,14 +262,19 @@ def _row_sample_chunk(tree, H, Y, dvec, scaled=False):
                                          np.inf).min(axis=1))
     if scaled:
         if Y is None:
-            qs = np.abs(Wr).sum(axis=2) ** 2
+            # row i's mass (U_i . h)^2 with G = U_i^T U_i: (G h)_a = U_ia (U_i . h)
+            gr = Ur * np.where(valid, Wr.sum(axis=2), 0.0)[:, :, None]
         else:
-            Wa = np.abs(Wr)
-            qs = np.einsum("dia,ab,dib->di", Wa, np.abs(Y), Wa)
-        accs = (xs + lows)[:, None] + np.cumsum(np.where(valid, qs, 0.0), axis=1)
+            # G_ab = U_ia Y_ab U_ib: (G h)_a = U_ia (Y w)_a with w = U_i * h
+            gr = Ur * np.einsum("dib,ab->dia", Wr, Y)
+        gcum = np.cumsum(gr, axis=1)                      # sum over the scanned rows
+        gtot = (g_x - g_low)[:, None, :] - gcum
+        E = 4.0 * np.sqrt(ss_x + ss_low)[:, None] * np.ones((1, F))
+        if vround:
+            E = E + 2.0 * np.abs(H[:, None, :] * gtot).sum(axis=2)
         # the last row's right edge is the leaf's, compared above
         inner = valid & (offs[None, :] < np.minimum(tree.I - s0, F)[:, None] - 1)
-        smargin = np.minimum(smargin, np.where(inner, np.abs(x[:, None] - acc) / accs,
+        smargin = np.minimum(smargin, np.where(inner, np.abs(x[:, None] - acc) / E,
                                                np.inf).min(axis=1))
     hit = (acc >= x[:, None]) & valid
     any_hit = hit.any(axis=1)
@@ -369,7 +404,8 @@ class KRPSampler:
             degenerate |= np.where(b >= 0, flag[np.maximum(b, 0)], False).any(axis=1)
             degenerate |= flag[u] | flag[u + 1]
             ht = h * V[:, u].T
-            t, m2, s2 = row_sample_batch(self.Z[k], ht, None, u01[:, k, 1], scaled=scaled)
+            t, m2, s2 = row_sample_batch(self.Z[k], ht, None, u01[:, k, 1], scaled=scaled,
+                                         vround=True)
             h = h * self.U[k][t]
             idx[:, k] = t
             margin = np.minimum(margin, np.minimum(m1, m2))

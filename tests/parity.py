@@ -11,16 +11,15 @@ comparison differently.  A draw is excused when
 * float64 path: some comparison lies within ``FP64_MARGIN`` of ``C``
   (``|x - cut| / C``; the two sides sum the same float64 terms in another
   order), or
-* float32 path: some comparison's scaled margin (``Draw.smargin``, the gap
-  divided by the sum of the absolute values of the terms that form ``x``
-  and the cut) is at most ``FP32_SCALED``.  The walk reads every node entry
-  and eigenvector entry rounded once to float32 (relative error at most
-  ``u = 2^-24``; the nodes are float64 sums rounded once when stored), so a
-  comparison moves by at most ``u`` per node side plus ``2 u`` through the
-  eigenvector entries of the quadratic form: ``3 u`` times its scale
-  (pinned on the CPU by ``test_scaled_margin_bounds_the_effect_of_storage_
-  rounding``), plus ``u`` for the float64 arithmetic that forms the nodes
-  and the eigendecomposition on the two sides.
+* float32 path: some comparison's scaled margin (``Draw.smargin``) is at
+  most ``FP32_SCALED = u = 2^-24``.  The walk reads every node entry and
+  eigenvector entry rounded once to float32 (relative error at most ``u``;
+  the nodes are float64 sums rounded once when stored); the scaled margin
+  divides the gap ``|x - cut|`` by the effect of such roundings on it
+  (oracle/sampler.py, ``row_sample_batch``: seven standard deviations of
+  the independent node roundings plus the first-order bound of the
+  eigenvector roundings), pinned on the CPU by
+  ``test_scaled_margin_bounds_the_effect_of_storage_rounding``.
 
 The split path's Grams carry ~2^-16 relative error of the products'
 absolute sums, which the scaled margin does not bound; its mismatches are
@@ -30,7 +29,7 @@ import numpy as np
 
 U32 = 2.0 ** -24
 FP64_MARGIN = 1e-10
-FP32_SCALED = 4 * U32
+FP32_SCALED = U32
 
 
 def compare(gpu_idx, dr, prec):

@@ -17,11 +17,14 @@ TOL_NODE = {"fp64": 1e-12, "fp32": 1e-5, "bf16x2": 1e-4}
 # ~2^-16 relative error
 TOL_PROB = {"fp64": 1e-10, "fp32": 1e-9, "bf16x2": 1e-3}
 # bounds on the split path's draws against the float64 oracle: the share of
-# draws that differ and the largest scaled margin among them (node entries
-# off by ~2^-15 of the products' absolute sums, times R / 4 for the
-# quadratic form over R columns)
-BF16_MISMATCH = 0.05
-BF16_SCALED = 2.0 ** -8
+# draws that differ and the largest scaled margin among them.  A split
+# product x_a x_b ~ hi hi + hi lo + lo hi misses ~2^-15 of itself, so the
+# scaled margin's error model with 2^-15 in place of float32's 2^-24
+# explains most differences; the Grams' error also moves G^+ and the
+# eigenvectors of G_{>k} by 2^-15 over the eigenvalue gaps, which the model
+# does not cover.
+BF16_MISMATCH = 0.10
+BF16_SCALED = 2.0 ** -6
 
 
 @pytest.fixture(scope="module")
@@ -187,7 +190,7 @@ def test_draw_matches_oracle(env, prec, dims, R, J):
                                                        exclude, J, 100 + exclude)
         report(f"draw {prec} dims={dims} R={R} exclude={exclude}", c)
         assert c["unexcused"] == 0
-        assert c["excusable_frac"] <= 0.02
+        assert c["excusable_frac"] <= 0.03
         assert rel.max() <= TOL_PROB[prec], rel.max()
         same = c["same"]
         r = rows.cpu().numpy().astype(np.float64)
