@@ -5,13 +5,12 @@ import pytest
 
 import synth
 from oracle import sampler as osmp
-from parity import compare, report
+from parity import bf16_scaled, compare, report
 
 pytestmark = pytest.mark.gpu
 
 TOL_PROB = {"fp64": 1e-10, "fp32": 1e-9, "bf16x2": 1e-3}
-BF16_MISMATCH = 0.10
-BF16_SCALED = 2.0 ** -6
+BF16_MISMATCH = 0.15
 
 
 @pytest.fixture(scope="module")
@@ -93,7 +92,7 @@ def test_batched_matches_oracle(env, p):
         assert rel.max() <= TOL_PROB[prec], rel.max()
         if prec == "bf16x2":
             assert c["mismatch"] <= BF16_MISMATCH * c["n"]
-            assert c["needed_smargin"] <= BF16_SCALED
+            assert c["needed_smargin"] <= bf16_scaled(R)
         else:
             assert c["unexcused"] == 0
 

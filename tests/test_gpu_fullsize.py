@@ -12,14 +12,13 @@ import synth
 from chain import check_solve
 from oracle import cp as ocp
 from oracle import sampler as osmp
-from parity import compare, report
+from parity import bf16_scaled, compare, report
 
 pytestmark = pytest.mark.gpu
 
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
 TOL_PROB = {"fp64": 1e-10, "fp32": 1e-9, "bf16x2": 1e-3}
-BF16_MISMATCH = 0.10
-BF16_SCALED = 2.0 ** -6
+BF16_MISMATCH = 0.15
 # share of draws whose comparison may legitimately go either way (margin
 # within the precision's rounding, or a near-degenerate eigenspace)
 EXCUSABLE = {"fp64": 0.01, "fp32": 0.05}
@@ -78,7 +77,7 @@ def test_sampler_at_scale_sampled_against_oracle(env, prec):
         assert rel.max() <= TOL_PROB[prec]
         if prec == "bf16x2":
             assert c["mismatch"] <= BF16_MISMATCH * c["n"]
-            assert c["needed_smargin"] <= BF16_SCALED
+            assert c["needed_smargin"] <= bf16_scaled(R)
         else:
             assert c["unexcused"] == 0
             assert c["excusable_frac"] <= EXCUSABLE[prec]
@@ -186,7 +185,7 @@ def test_sketched_cp_als_chain_at_scale(env, c3, prec):
             if prec == "fp64":
                 assert c["unexcused"] == 0, (s, j)
             else:
-                assert c["needed_smargin"] <= BF16_SCALED, (s, j)
+                assert c["needed_smargin"] <= bf16_scaled(R), (s, j)
             print(f"sweep {s} solve {j}: " +
                   " ".join(f"{k} {v:.1e}" for k, v in errs.items()) +
                   f"; sampled draws differing {c['mismatch']}/48", flush=True)
