@@ -75,8 +75,8 @@ def test_transposed_eigenvector_matrix_is_caught():
 def test_leaf_scan_off_by_one_is_caught(monkeypatch):
     orig = smp._row_sample_chunk
 
-    def shifted(tree, H, Y, dvec, scaled=False):
-        rows, m, sm = orig(tree, H, Y, dvec, scaled)
+    def shifted(tree, H, Y, dvec, scaled=False, vround=False):
+        rows, m, sm = orig(tree, H, Y, dvec, scaled, vround)
         return np.minimum(rows + 1, tree.I - 1), m, sm
 
     monkeypatch.setattr(smp, "_row_sample_chunk", shifted)
@@ -89,7 +89,7 @@ def test_leaf_scan_off_by_one_is_caught(monkeypatch):
 
 
 def test_walk_without_low_update_is_caught(monkeypatch):
-    def no_low(tree, H, Y, dvec, scaled=False):
+    def no_low(tree, H, Y, dvec, scaled=False, vround=False):
         n, R = H.shape
         HH = H[:, :, None] * H[:, None, :]
         C = np.einsum("dab,ab->d", HH, tree.root)
