@@ -124,6 +124,7 @@ def lib():
         "krps_fit": (c.c_int, [P, P, P, c.POINTER(c.c_double), P, c.c_size_t]),
         "krps_sampler_tree_info": (c.c_int, [P, c.c_int, c.POINTER(TreeInfo)]),
         "krps_sampler_check": (c.c_int, [P, c.POINTER(c.c_int64)]),
+        "krps_sample_static": (c.c_int, [P, c.c_int, c.c_int64, P, P, P, P]),
         "krps_sketched_solve_seeded": (c.c_int, [P, P, c.c_int, c.c_int64, c.c_uint64,
                                                  c.c_uint64, c.c_uint64, P, P, c.c_size_t]),
         "krps_als_sweep_seeded": (c.c_int, [P, P, c.c_int64, c.c_uint64, c.c_uint64, c.c_uint64,
@@ -255,6 +256,12 @@ class Sampler:
                                 _ptr(r), _ptr(self.draw_ws), self.draw_ws.numel(),
                                 1 if check_status else 0))
         return idx, p, r
+
+    def sample_static(self, exclude, uniforms, idx, prob=None, rows=None):
+        """krps_sample into caller tensors with the library's static per-GPU
+        scratch instead of a workspace (no allocation in the call)."""
+        check(lib().krps_sample_static(self.handle, int(exclude), int(uniforms.shape[0]),
+                                       _ptr(uniforms), _ptr(idx), _ptr(prob), _ptr(rows)))
 
     def sample_seeded(self, exclude, J, seed, ctr_base=0, prob=True):
         """Draws J samples with uniforms generated in the walk (Philox4x64-10

@@ -6,6 +6,7 @@
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -898,6 +899,56 @@ krps_status krps_sample(krps_sampler s, int exclude, int64_t J, const double* un
     if (flag & ST_NUMERIC) return fail(KRPS_ENUMERIC, "non-finite or non-positive mass met");
   }
   return KRPS_OK;
+}
+
+}  // extern "C"
+
+// ------------------------------------------------ allocation-free draws
+
+// Per-draw scratch of krps_sample_static: one array per GPU the library
+// runs on, held until the process ends.  In host code the name is only a
+// stand-in; the device address of each GPU's copy is looked up once per
+// device (with that device current) and used everywhere instead.
+static __device__ __align__(256) unsigned char scratch[KRPS_STATIC_SCRATCH_BYTES];
+
+namespace {
+
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[256] = {nullptr};
+
+// Device address of this GPU's scratch array (looked up on first use).
+krps_status static_scratch(int device, void** out) {
+  if (device < 0 || device >= 256) return fail(KRPS_EINVAL, "device out of range");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (g_scratch_ptr[device] == nullptr) {
+    void* ptr = nullptr;
+    KRPS_HIP(hipSetDevice(device));
+    KRPS_HIP(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+    if (ptr == nullptr) return fail(KRPS_EDEVICE, "scratch array has no device address");
+    g_scratch_ptr[device] = ptr;
+  }
+  *out = g_scratch_ptr[device];
+  return KRPS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+krps_status krps_sample_static(krps_sampler s, int exclude, int64_t J, const double* uniforms,
+                               int32_t* idx, double* prob, void* rows) {
+  if (s == nullptr) return fail(KRPS_EINVAL, "sampler is NULL");
+  if (s->draw_bytes > (size_t)KRPS_STATIC_SCRATCH_BYTES)
+    return fail(KRPS_EWORKSPACE, "per-draw scratch of this sampler (" +
+                                     std::to_string(s->draw_bytes) + " bytes) exceeds the " +
+                                     std::to_string(KRPS_STATIC_SCRATCH_BYTES) +
+                                     "-byte static scratch");
+  void* ws = nullptr;
+  krps_status st = static_scratch(s->ctx->device, &ws);
+  if (st != KRPS_OK) return st;
+  st = krps_sample_prepare(s, exclude, ws, s->draw_bytes);
+  if (st != KRPS_OK) return st;
+  return krps_sample_draw(s, exclude, J, uniforms, idx, prob, rows, ws, s->draw_bytes);
 }
 
 }  // extern "C"

@@ -1,0 +1,53 @@
+"""The allocation-free draw (krps_sample_static: the per-draw scratch is the
+library's static per-GPU array) against krps_sample with a workspace, on
+two calls in a row, the second with a smaller problem and fewer samples.
+Run with ``-m gpu``."""
+import numpy as np
+import pytest
+
+import synth
+
+pytestmark = pytest.mark.gpu
+
+
+def test_static_scratch_draws_equal_workspace_draws():
+    import torch
+    import paper_2301_12584_amd as krps
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    ctx = krps.Context(0)
+    dev = ctx.device
+    cases = [((20000, 15000, 9000), 64, "fp32", 0, 8192),
+             ((700, 500), 16, "fp64", -1, 1000)]
+    for dims, R, prec, exclude, J in cases:
+        print(f"static scratch {prec} dims={dims} R={R} exclude={exclude} J={J}", flush=True)
+        Us = synth.gaussian_factors(dims, R, seed=R + len(dims), heavy_rows_frac=0.01)
+        dt = torch.float64 if prec == "fp64" else torch.float32
+        S = krps.Sampler(ctx, [torch.from_numpy(U).to(dev).to(dt).contiguous() for U in Us],
+                         precision=prec)
+        assert S.draw_ws.numel() <= 8 << 20
+        u = torch.from_numpy(synth.uniforms(J, len(dims), 31 + J)).to(dev)
+        idx = torch.full((J, len(dims)), -7, dtype=torch.int32, device=dev)
+        prob = torch.zeros(J, dtype=torch.float64, device=dev)
+        rows = torch.zeros((J, R), dtype=dt, device=dev)
+        S.sample_static(exclude, u, idx, prob, rows)
+        ref_i, ref_p, ref_r = S.sample(exclude, u, rows=True)
+        torch.cuda.synchronize()
+        assert torch.equal(idx, ref_i)
+        assert torch.equal(prob, ref_p)
+        assert torch.equal(rows, ref_r)
+        assert S.check_status() == 0
+
+
+def test_static_scratch_rejects_a_sampler_too_large():
+    import torch
+    import paper_2301_12584_amd as krps
+    ctx = krps.Context(0)
+    Us = synth.gaussian_factors((400, 300, 200), 128, seed=3)
+    S = krps.Sampler(ctx, [torch.from_numpy(U).to(ctx.device).contiguous() for U in Us],
+                     precision="fp32")
+    assert S.draw_ws.numel() > 8 << 20
+    u = torch.from_numpy(synth.uniforms(16, 3, 1)).to(ctx.device)
+    idx = torch.empty((16, 3), dtype=torch.int32, device=ctx.device)
+    with pytest.raises(krps.KrpsError) as e:
+        S.sample_static(-1, u, idx)
+    assert e.value.code == -2
