@@ -337,6 +337,18 @@ krps_status krps_als_sweep_seeded(krps_sampler s, krps_tensor t, int64_t J, uint
                                   uint64_t ctr_base, uint64_t sweep, double* sigma, void* ws,
                                   size_t ws_bytes, int use_graph);
 
+/* The exact ALS step of mode j (Algorithm 6 with the full least-squares
+ * problem, the reference the sampled solves are measured against): U_j =
+ * mat(T, j) (U_N (.) ... (.) U_1 without U_j) ((*)_{k != j} G_k)^+ over
+ * every stored entry of T (the sparse MTTKRP), sigma = its column norms,
+ * U_j renormalised in place, Z_j and G_j rebuilt.  Float64 arithmetic in
+ * every precision (for KRPS_BF16X2 the G_k are recomputed in float64); the
+ * factor is stored in its type.  ws: a solve workspace (any J); the
+ * pieces of krps_solve_layout are overwritten (M^+ at Mp, the MTTKRP in
+ * float64 at Y for the rows listed at yrows, their count at nyrows). */
+krps_status krps_exact_solve(krps_sampler s, krps_tensor t, int j, double* sigma, void* ws,
+                             size_t ws_bytes);
+
 /* fit = 1 - ||T~ - T||_F / ||T||_F for T~ = [sigma; U_1..U_N] (Sec. 4.3),
  * with ||T~||^2 = sigma^T ((*)_k G_k) sigma and <T, T~> over the stored
  * entries.  sigma: device float64 [R].  fit: host out (synchronises).

@@ -14,6 +14,12 @@
 * :func:`fit` -- ``1 - ||T~ - T||_F / ||T||_F`` (Section 4.3) through
   ``||T~||^2 = sigma^T ((*)_k G_k) sigma`` and ``<T, T~>`` over the nonzeros.
 * :func:`cp_als` -- Algorithm 6 with the sampled solve.
+* :func:`mttkrp` / :func:`exact_solve` / :func:`exact_als` -- the exact
+  least-squares step of Algorithm 6 (no sampling): ``U_j = mat(T, j)
+  U_{!=j} ((*)_{k != j} G_k)^+`` with the Khatri-Rao product never formed
+  (the sparse MTTKRP over the stored entries), the reference the sampled
+  solves approach (Appendix A.13, the exact-ALS column of the accuracy
+  table).
 
 The solve method is not fixed by the paper; the reading used is the normal
 equations with a float64 eigen-pseudo-inverse (no regularisation).  A column
@@ -28,7 +34,8 @@ from .definition import pinv_psd, hadamard_all
 from .sampler import KRPSampler
 
 __all__ = ["SparseTensor", "normal_equations", "sketched_solve", "fit",
-           "cp_als", "normalize_columns", "sketched_lstsq"]
+           "cp_als", "normalize_columns", "sketched_lstsq", "mttkrp", "exact_solve",
+           "exact_als"]
 
 
 class SparseTensor:
@@ -197,6 +204,56 @@ def cp_als(tensor: SparseTensor, U0, sweeps, u01_of, F=None, factor_dtype=None, 
             Us[j] = keep(Uj)
             if factor_dtype is not None:
                 sampler.refresh(j, Us[j])
+            if progress is not None:
+                progress(s, j)
+        fits.append(fit(tensor, Us, sigma))
+    return Us, sigma, fits
+
+
+def mttkrp(tensor: SparseTensor, Us, j, chunk=1 << 20):
+    """``mat(T, j) U_{!=j}``: ``Y[i_j(e), :] += x_e prod_{k != j} U_k[i_k(e), :]``
+    over every stored entry (duplicates add)."""
+    R = next(np.asarray(U).shape[1] for k, U in enumerate(Us) if k != j)
+    Y = np.zeros((tensor.dims[j], R))
+    for s in range(0, tensor.nnz, chunk):
+        e = min(tensor.nnz, s + chunk)
+        p = np.ones((e - s, R))
+        for k, U in enumerate(Us):
+            if k != j:
+                p *= np.asarray(U, dtype=np.float64)[tensor.idx[s:e, k]]
+        # the sum over entries as a sparse (I_j x chunk) matrix of values
+        X = sparse.coo_matrix((tensor.val[s:e], (tensor.idx[s:e, j], np.arange(e - s))),
+                              shape=(tensor.dims[j], e - s)).tocsr()
+        Y += X @ p
+    return Y
+
+
+def exact_solve(tensor: SparseTensor, Us, j):
+    """The exact least-squares update of factor ``j`` (Algorithm 6 without
+    sampling): ``U_j = mat(T, j) U_{!=j} M^+`` with ``M = (*)_{k != j}
+    U_k^T U_k``; returns ``(U_j normalised, sigma, Y, M)``."""
+    G = hadamard_all([np.asarray(U, dtype=np.float64).T @ np.asarray(U, dtype=np.float64)
+                      for k, U in enumerate(Us) if k != j])
+    Y = mttkrp(tensor, Us, j)
+    Mp, _ = pinv_psd(G)
+    Unew, sigma = normalize_columns(Y @ Mp)
+    return Unew, sigma, Y, G
+
+
+def exact_als(tensor: SparseTensor, U0, sweeps, factor_dtype=None, progress=None):
+    """Algorithm 6 with the exact solve: columns normalised first, factors
+    kept in ``factor_dtype`` (as :func:`cp_als`); returns ``(Us, sigma,
+    fits)`` with the fit after every sweep."""
+    def keep(U):
+        return U if factor_dtype is None else U.astype(factor_dtype).astype(np.float64)
+
+    Us = [keep(normalize_columns(U)[0]) for U in U0]
+    sigma = np.ones(Us[0].shape[1])
+    fits = []
+    for s in range(sweeps):
+        for j in range(tensor.N):
+            Uj, sigma, _, _ = exact_solve(tensor, Us, j)
+            Us[j] = keep(Uj)
             if progress is not None:
                 progress(s, j)
         fits.append(fit(tensor, Us, sigma))

@@ -125,6 +125,7 @@ def lib():
         "krps_sampler_tree_info": (c.c_int, [P, c.c_int, c.POINTER(TreeInfo)]),
         "krps_sampler_check": (c.c_int, [P, c.POINTER(c.c_int64)]),
         "krps_sample_static": (c.c_int, [P, c.c_int, c.c_int64, P, P, P, P]),
+        "krps_exact_solve": (c.c_int, [P, P, c.c_int, P, P, c.c_size_t]),
         "krps_sketched_solve_seeded": (c.c_int, [P, P, c.c_int, c.c_int64, c.c_uint64,
                                                  c.c_uint64, c.c_uint64, P, P, c.c_size_t]),
         "krps_als_sweep_seeded": (c.c_int, [P, P, c.c_int64, c.c_uint64, c.c_uint64, c.c_uint64,
@@ -561,6 +562,26 @@ class CPALS:
         check(lib().krps_als_sweep(self.S.handle, self.T.handle, self.J, _ptr(uniforms),
                                    _ptr(self.sigma), _ptr(self.ws), self.ws.numel(),
                                    1 if use_graph else 0))
+
+    def exact_solve(self, j):
+        """The exact ALS step of mode j (full sparse MTTKRP, no sampling)."""
+        check(lib().krps_exact_solve(self.S.handle, self.T.handle, int(j), _ptr(self.sigma),
+                                     _ptr(self.ws), self.ws.numel()))
+
+    def exact_parts(self, j):
+        """M^+ and the MTTKRP (listed rows, float64) of the last exact solve."""
+        torch = self.S.ctx.torch
+        lay = SolveLayout()
+        check(lib().krps_solve_layout_query(self.S.handle, self.T.handle, 1, ctypes.byref(lay)))
+        R, ws = self.S.R, self.ws
+        n = int(ws[lay.nyrows:lay.nyrows + 8].view(torch.int64).item())
+        rows = ws[lay.yrows:lay.yrows + 4 * n].view(torch.int32).clone()
+        I = self.S.dims[j]
+        full = ws[lay.Y:lay.Y + I * R * 8].view(torch.float64).view(I, R)
+        Y = torch.zeros(I, R, dtype=torch.float64, device=full.device)
+        Y[rows.long()] = full[rows.long()]
+        return {"Mp": ws[lay.Mp:lay.Mp + R * R * 8].view(torch.float64).view(R, R).clone(),
+                "Y": Y, "yrows": rows}
 
     def solve_seeded(self, j, seed, ctr_base, sweep):
         """One solve with in-kernel uniforms (counter word 2 = sweep * N + j)."""

@@ -1727,6 +1727,64 @@ krps_status krps_init_range_finder(krps_sampler s, krps_tensor t, int j, uint64_
   return krps_normalize_factor(s, j, sigma, ws, ws_bytes);
 }
 
+krps_status krps_exact_solve(krps_sampler s, krps_tensor t, int j, double* sigma, void* ws,
+                             size_t ws_bytes) {
+  krps_status st = check_pair(s, t);
+  if (st != KRPS_OK) return st;
+  if (s->N < 2) return fail(KRPS_EINVAL, "a solve needs N >= 2");
+  if (j < 0 || j >= s->N) return fail(KRPS_EINVAL, "j out of range");
+  if (sigma == nullptr || ws == nullptr) return fail(KRPS_EINVAL, "sigma/workspace is NULL");
+  const SolvePlan pl = plan_solve(s, 1);
+  if (ws_bytes < pl.total) return fail(KRPS_EWORKSPACE, "solve workspace too small");
+  KRPS_HIP(hipSetDevice(s->ctx->device));
+  const int R = s->R, N = s->N;
+  char* w = (char*)ws;
+  hipStream_t stream = s->ctx->stream;
+  const krps_solve_layout& l = pl.lay;
+  const SolveHead& h = pl.head;
+  // M = (*)_{k != j} G_k in float64 (the split path's tree roots carry
+  // ~2^-16 error: its Grams are recomputed with float64 products) and M^+
+  const double* mats[KRPS_MAX_MODES];
+  int nm = 0;
+  for (int k = 0; k < N; ++k) {
+    if (k == j) continue;
+    const double* g = s->gram[k];
+    if (s->prec == KRPS_BF16X2) {
+      double* gk = (double*)(w + h.fitg) + (size_t)k * R * R;
+      hipError_t e = launch_tree_build(stream, KRPS_FP32, s->U[k], s->I[k], R, h.gts[k], nullptr,
+                                       gk, (double*)(w + h.fitscr), h.fitscr_bytes, 2);
+      if (e != hipSuccess) return hip_fail(e, "float64 Gram");
+      g = gk;
+    }
+    mats[nm++] = g;
+  }
+  hipError_t e = launch_prep_gplus2(stream, R, nm, mats, 0, nullptr, (double*)(w + l.Mp), nullptr,
+                                    (int32_t*)(w + pl.rank), nullptr, s->status);
+  if (e != hipSuccess) return hip_fail(e, "pseudo-inverse of the Hadamard product of Grams");
+  MttkrpArgs a;
+  memset(&a, 0, sizeof(a));
+  a.N = N;
+  a.j = j;
+  a.R = R;
+  a.nnz = t->nu;
+  a.cols = t->cols[j];
+  a.vals = t->vals[j];
+  for (int k = 0; k < N; ++k) a.U[k] = s->U[k];
+  a.hot_slot = t->hot_slot[j];
+  a.hot_rows = t->hot_rows[j];
+  a.nhot = (int)std::min<int64_t>(t->nhot, t->dims[j]);
+  int32_t* list = (int32_t*)(w + l.yrows);
+  int64_t* count = (int64_t*)(w + l.nyrows);
+  e = launch_mttkrp(stream, s->prec, a, s->I[j], (int32_t*)(w + pl.ymark),
+                    (int64_t*)(w + pl.ybsum), list, count, (double*)(w + l.Y));
+  if (e != hipSuccess) return hip_fail(e, "MTTKRP");
+  e = launch_solve_gemm(stream, s->prec == KRPS_FP64 ? KRPS_FP64 : KRPS_FP32, w + l.Y,
+                        (const double*)(w + l.Mp), s->U[j], s->I[j], list, count, R,
+                        (double*)(w + pl.partial), sigma);
+  if (e != hipSuccess) return hip_fail(e, "solve GEMM");
+  return build_tree(s, j);
+}
+
 krps_status krps_fit(krps_sampler s, krps_tensor t, const double* sigma, double* fit, void* ws,
                      size_t ws_bytes) {
   krps_status st = check_pair(s, t);

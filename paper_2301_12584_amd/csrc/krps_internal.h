@@ -165,6 +165,18 @@ struct FiberArgs {
 // the SpMM).
 constexpr int HOT_ROWS = 32;
 
+// Exact MTTKRP of mode j over a tensor's stored entries (mode j's copy).
+struct MttkrpArgs {
+  int N, j, R;
+  int64_t nnz;
+  const int32_t* cols;        // [N][nnz] mode j's sorted, merged entries
+  const double* vals;         // [nnz]
+  const void* U[KRPS_MAX_MODES];
+  const int8_t* hot_slot;     // [dims[j]] slot of a hot row of mode j, -1 otherwise
+  const int32_t* hot_rows;    // [nhot]
+  int nhot;
+};
+
 struct FitArgs {
   int N, R;
   int64_t nnz;
@@ -251,6 +263,10 @@ hipError_t launch_colnorm(hipStream_t st, krps_precision p, const void* U, int64
                           double* partial, double* sigma);
 hipError_t launch_normalize(hipStream_t st, krps_precision p, void* U, int64_t I, int R,
                             const double* sigma);
+// Rows of Y that mode j's entries reach (marked, listed increasing, zeroed),
+// then Y[i_j(e)] += x_e (*)_{k != j} U_k[i_k(e)] over every stored entry.
+hipError_t launch_mttkrp(hipStream_t st, krps_precision p, const MttkrpArgs& a, int64_t I,
+                         int32_t* mark, int64_t* bsum, int32_t* list, int64_t* count, double* Y);
 size_t fit_partial_bytes();
 hipError_t launch_fit(hipStream_t st, krps_precision p, const FitArgs& a, double* partial,
                       double* out);

@@ -1346,3 +1346,108 @@ hipError_t launch_range_finder(hipStream_t st, krps_precision p, const int32_t* 
 }
 
 }  // namespace krps
+
+// ------------------------------------------------------ exact MTTKRP
+//
+// The exact ALS step of mode j (Algorithm 6 with the full least-squares
+// problem): Y = mat(T, j) (U_N (.) ... (.) U_1 without U_j), i.e.
+// Y[i_j(e), :] += x_e (*)_{k != j} U_k[i_k(e), :] over every stored entry.
+
+namespace krps {
+namespace {
+
+// mark[i_j(e)] = 1 for every stored entry.
+__global__ __launch_bounds__(256) void mark_all_kernel(const int32_t* __restrict__ ij, int64_t n,
+                                                       int32_t* __restrict__ mark) {
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n;
+       e += (int64_t)gridDim.x * blockDim.x)
+    mark[ij[e]] = 1;
+}
+
+// A wavefront takes MTTKRP_CHUNK consecutive entries of mode j's copy
+// (sorted by the other modes' indices, so the entries of a fiber are
+// consecutive and share their Khatri-Rao row, formed once per fiber);
+// lanes run over the R columns (two per lane above 64).  The rows of mode
+// j with the most entries are accumulated per workgroup in LDS, as in the
+// sampled SpMM.
+constexpr int MTTKRP_CHUNK = 256;
+
+template <typename T>
+__global__ __launch_bounds__(256) void mttkrp_kernel(MttkrpArgs a, double* __restrict__ Y) {
+  extern __shared__ double hot_acc[];  // [nhot][R]
+  const int lane = threadIdx.x & 63;
+  const int R = a.R;
+  for (int q = threadIdx.x; q < a.nhot * R; q += blockDim.x) hot_acc[q] = 0.0;
+  __syncthreads();
+  const int32_t* __restrict__ ij = a.cols + (int64_t)a.j * a.nnz;
+  const int64_t nw = (int64_t)gridDim.x * (blockDim.x >> 6);
+  for (int64_t e0 = ((int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6)) * MTTKRP_CHUNK;
+       e0 < a.nnz; e0 += nw * MTTKRP_CHUNK) {
+    const int64_t e1 = e0 + MTTKRP_CHUNK < a.nnz ? e0 + MTTKRP_CHUNK : a.nnz;
+    double k0 = 0.0, k1 = 0.0;  // the current fiber's Khatri-Rao row (columns lane, lane + 64)
+    int32_t prev[KRPS_MAX_MODES];
+#pragma unroll
+    for (int k = 0; k < KRPS_MAX_MODES; ++k) prev[k] = -1;
+    for (int64_t e = e0; e < e1; ++e) {
+      bool same = true;
+#pragma unroll
+      for (int k = 0; k < KRPS_MAX_MODES; ++k)
+        if (k < a.N && k != a.j) {
+          const int32_t c = a.cols[(int64_t)k * a.nnz + e];
+          same = same && c == prev[k];
+          prev[k] = c;
+        }
+      if (!same) {
+        k0 = 1.0;
+        k1 = 1.0;
+#pragma unroll
+        for (int k = 0; k < KRPS_MAX_MODES; ++k)
+          if (k < a.N && k != a.j) {
+            const T* u = (const T*)a.U[k] + (int64_t)prev[k] * R;
+            if (lane < R) k0 *= (double)u[lane];
+            if (lane + 64 < R) k1 *= (double)u[lane + 64];
+          }
+      }
+      const double x = a.vals[e];
+      const int32_t i = ij[e];
+      const int hs = a.hot_slot[i];
+      if (hs >= 0) {
+        double* acc = hot_acc + hs * R;
+        if (lane < R) atomicAdd(&acc[lane], x * k0);
+        if (lane + 64 < R) atomicAdd(&acc[lane + 64], x * k1);
+      } else {
+        if (lane < R) atomicAdd(&Y[(int64_t)i * R + lane], x * k0);
+        if (lane + 64 < R) atomicAdd(&Y[(int64_t)i * R + lane + 64], x * k1);
+      }
+    }
+  }
+  __syncthreads();
+  for (int q = threadIdx.x; q < a.nhot * R; q += blockDim.x) {
+    const double v = hot_acc[q];
+    if (v != 0.0) atomicAdd(&Y[(int64_t)a.hot_rows[q / R] * R + q % R], v);
+  }
+}
+
+}  // namespace
+
+hipError_t launch_mttkrp(hipStream_t st, krps_precision p, const MttkrpArgs& a, int64_t I,
+                         int32_t* mark, int64_t* bsum, int32_t* list, int64_t* count, double* Y) {
+  const int64_t nb = I > 0 ? (I + SCAN_TILE - 1) / SCAN_TILE : 1;
+  const int32_t* ij = a.cols + (int64_t)a.j * a.nnz;
+  hipLaunchKernelGGL(fill_u32_kernel, dim3((unsigned)std::min<int64_t>(nb * 4, 8192)), dim3(256), 0,
+                     st, (uint32_t*)mark, I);
+  hipLaunchKernelGGL(mark_all_kernel, dim3(4096), dim3(256), 0, st, ij, a.nnz, mark);
+  hipLaunchKernelGGL(mark_count_kernel, dim3((unsigned)nb), dim3(SCAN_TILE), 0, st, mark, I, bsum);
+  hipLaunchKernelGGL(scan_bsum_kernel, dim3(1), dim3(1024), 0, st, bsum, nb);
+  hipLaunchKernelGGL(mark_compact_kernel, dim3((unsigned)nb), dim3(SCAN_TILE), 0, st, mark, I, nb,
+                     bsum, list, count);
+  hipLaunchKernelGGL(zero_rows_kernel<double>, dim3(2048), dim3(256), 0, st, Y, a.R, list, count);
+  const size_t lds = (size_t)a.nhot * a.R * 8;
+  if (p == KRPS_FP64)
+    hipLaunchKernelGGL(mttkrp_kernel<double>, dim3(2048), dim3(256), lds, st, a, Y);
+  else
+    hipLaunchKernelGGL(mttkrp_kernel<float>, dim3(2048), dim3(256), lds, st, a, Y);
+  return hipGetLastError();
+}
+
+}  // namespace krps

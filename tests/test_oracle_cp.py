@@ -159,3 +159,32 @@ def test_sketched_lstsq_weights_follow_the_probabilities():
     w = np.sqrt(1.0 / (40 * q))
     ref = np.linalg.lstsq(A * w[:, None], B * w[:, None], rcond=None)[0]
     np.testing.assert_allclose(X, ref, rtol=1e-10, atol=1e-12)
+
+
+@pytest.mark.parametrize("j", [0, 1, 2])
+def test_exact_solve_equals_dense_least_squares(j):
+    """The exact step without the Khatri-Rao product formed equals the
+    dense least-squares solution on the materialised matricisation
+    (min_X ||U_{!=j} X^T - mat(T, j)^T||, the definition), normalised."""
+    T = _tiny_tensor(4)
+    Us = synth.gaussian_factors(T.dims, 4, seed=25 + j)
+    Unew, sigma, Y, M = cp.exact_solve(T, Us, j)
+    A = _u_neq_j(Us, j)
+    B = _mat_t(_dense(T), j)
+    Xref = np.linalg.lstsq(A, B, rcond=None)[0].T
+    ref, sref = cp.normalize_columns(Xref)
+    np.testing.assert_allclose(sigma, sref, rtol=1e-9)
+    np.testing.assert_allclose(Unew, ref, rtol=1e-9, atol=1e-11)
+    # and the MTTKRP is mat(T, j) times the materialised Khatri-Rao product
+    np.testing.assert_allclose(Y, B.T @ A, rtol=1e-12, atol=1e-12 * np.abs(Y).max())
+
+
+def test_exact_als_recovers_a_planted_tensor_monotonically():
+    idx, val, _ = synth.planted_cp_tensor((14, 12, 10), 3, seed=31)
+    T = cp.SparseTensor((14, 12, 10), idx, val)
+    U0 = synth.gaussian_factors((14, 12, 10), 3, seed=32)
+    _, _, fits = cp.exact_als(T, U0, 40)
+    assert fits[-1] >= 0.9999
+    # an exact step never increases the residual of the problem it solves:
+    # the fit after each sweep does not fall
+    assert np.all(np.diff(fits) >= -1e-12)
