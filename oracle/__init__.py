@@ -18,6 +18,11 @@ Two levels:
   partial Gram matrices, Algorithms 1-4 with the two-stage draw of
   Section 3.2), batched over independent samples.
 * :mod:`oracle.cp` -- the sketched least-squares solve, CP-ALS
-  (Algorithm 6 with the sampled solve of Section 3.3) and the fit.
+  (Algorithm 6 with the sampled solve of Section 3.3), the exact ALS step
+  (sparse MTTKRP) and the fit.
+* :mod:`oracle.sketch` -- the counter-based generator (Philox4x64-10) of
+  in-kernel uniforms and of the range finder's Gaussian sketch.
+* :mod:`oracle.accuracy` -- residual error and distortion of a sketch of a
+  Khatri-Rao least-squares problem (Section 4.2, Appendix A.12).
 """
-from . import definition, sampler, cp  # noqa: F401
+from . import definition, sampler, cp, sketch, accuracy  # noqa: F401
