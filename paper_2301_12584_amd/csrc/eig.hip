@@ -535,9 +535,10 @@ hipError_t launch_eig_batched(hipStream_t st, bool f64, const EigJob* jobs, int 
   return hipGetLastError();
 }
 
-hipError_t launch_pinv(hipStream_t st, int R, const double* M, double* Mp_full, int32_t* rank) {
+hipError_t launch_pinv(hipStream_t st, int R, const double* M, double* Mp_full, int32_t* rank,
+                       int32_t* status) {
   const double* mats[1] = {M};
-  return launch_prep_gplus2(st, R, 1, mats, 0, nullptr, Mp_full, nullptr, rank, nullptr, nullptr);
+  return launch_prep_gplus2(st, R, 1, mats, 0, nullptr, Mp_full, nullptr, rank, nullptr, status);
 }
 
 }  // namespace krps

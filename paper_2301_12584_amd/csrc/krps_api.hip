@@ -525,7 +525,10 @@ krps_status enqueue_solve(krps_sampler s, krps_tensor t, int j, int64_t J, const
   e = launch_tree_build(st, split ? KRPS_BF16X2 : KRPS_FP64, w + l.rows, J, R, tm, nullptr,
                         (double*)(w + l.M), (double*)(w + pl.gscratch), pl.gscratch_bytes, 3);
   if (e != hipSuccess) return hip_fail(e, "Gram of sampled rows");
-  e = launch_pinv(st, R, (double*)(w + l.M), (double*)(w + l.Mp), (int32_t*)(w + pl.rank));
+  // a non-finite M (a non-finite sampled row) would give M^+ = 0 and a zero
+  // factor: it is flagged in the sampler's status
+  e = launch_pinv(st, R, (double*)(w + l.M), (double*)(w + l.Mp), (int32_t*)(w + pl.rank),
+                  s->status);
   if (e != hipSuccess) return hip_fail(e, "pseudo-inverse");
   FiberArgs fa;
   fa.N = N;
@@ -805,7 +808,9 @@ krps_status krps_sampler_check(krps_sampler s, int64_t* zero_weight) {
   KRPS_HIP(hipMemsetAsync(s->status, 0, 8, s->ctx->stream));
   if (zero_weight != nullptr) *zero_weight = words[1];
   if (words[0] & ST_ZERO) return fail(KRPS_EZERO, "the Khatri-Rao product is zero");
-  if (words[0] & ST_NUMERIC) return fail(KRPS_ENUMERIC, "non-finite or non-positive mass met");
+  if (words[0] & ST_NUMERIC)
+    return fail(KRPS_ENUMERIC, "a non-finite value or a non-positive mass was met (a draw's "
+                               "masses, or a solve's sampled Gram)");
   return KRPS_OK;
 }
 

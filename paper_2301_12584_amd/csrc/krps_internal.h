@@ -213,8 +213,11 @@ hipError_t launch_prep_eig2(hipStream_t st, krps_precision p, int R, int nsteps,
                             const double* const* Gsteps, const int* order, const double* ggt,
                             double* lam, void* vecs, void* etree, int64_t estride,
                             int32_t* sweep_out, double* emass, int64_t enodes);
-// rank points at two int32: the rank and the Jacobi sweep count.
-hipError_t launch_pinv(hipStream_t st, int R, const double* M, double* Mp_full, int32_t* rank);
+// rank points at two int32: the rank and the Jacobi sweep count.  A zero or
+// non-finite M sets ST_ZERO / ST_NUMERIC in *status (if not null): the
+// pseudo-inverse of such an M is returned as 0.
+hipError_t launch_pinv(hipStream_t st, int R, const double* M, double* Mp_full, int32_t* rank,
+                       int32_t* status = nullptr);
 
 // lstsq.hip
 size_t sort_temp_bytes(int64_t nnz);
