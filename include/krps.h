@@ -92,6 +92,19 @@ const char* krps_last_error(void);
 /* Library version string. */
 const char* krps_version(void);
 
+/* Measured peaks of the units the rooflines are priced against. */
+typedef struct {
+  double hbm_copy_gbs;        /* device copy: bytes read + written per second */
+  double f64_vector_tflops;   /* float64 FMA loops */
+  double f32_vector_tflops;   /* float32 FMA loops (no packed instructions) */
+  double f64_matrix_tflops;   /* float64 16x16x4 MFMA loops */
+  double bf16_matrix_tflops;  /* bf16 16x16x32 MFMA loops (float32 accumulate) */
+} krps_peaks;
+
+/* Runs the probe loops on the context's stream (synchronises; the copy uses
+ * the device workspace ws, at least 64 MiB, half read and half written). */
+krps_status krps_measure_peaks(krps_ctx ctx, void* ws, size_t ws_bytes, krps_peaks* out);
+
 /* ------------------------------------------------------------------ */
 /* Sampler: Algorithm 1 (ConstructKRPSampler) and Theorem 1.1 part 1   */
 /* ------------------------------------------------------------------ */
@@ -449,6 +462,8 @@ typedef struct {
   size_t yrows;    /* int32 [*nyrows] rows of mode j that the sampled fibers'
                       entries reach, increasing */
   size_t nyrows;   /* int64: their count */
+  size_t expanded; /* int64: fiber entries the SpMM expanded (the sizes of
+                      the distinct sampled fibers summed) */
 } krps_solve_layout;
 
 krps_status krps_solve_layout_query(krps_sampler s, krps_tensor t, int64_t J,

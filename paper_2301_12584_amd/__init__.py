@@ -54,7 +54,13 @@ class Region(ctypes.Structure):
 
 class SolveLayout(ctypes.Structure):
     _fields_ = [(n, ctypes.c_size_t) for n in ("idx", "prob", "w", "rows", "M", "Mp", "Y", "draw",
-                                               "yrows", "nyrows")]
+                                               "yrows", "nyrows", "expanded")]
+
+
+class Peaks(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_double) for n in ("hbm_copy_gbs", "f64_vector_tflops",
+                                               "f32_vector_tflops", "f64_matrix_tflops",
+                                               "bf16_matrix_tflops")]
 
 
 def declared_symbols():
@@ -126,6 +132,7 @@ def lib():
         "krps_sampler_check": (c.c_int, [P, c.POINTER(c.c_int64)]),
         "krps_sample_static": (c.c_int, [P, c.c_int, c.c_int64, P, P, P, P]),
         "krps_exact_solve": (c.c_int, [P, P, c.c_int, P, P, c.c_size_t]),
+        "krps_measure_peaks": (c.c_int, [P, P, c.c_size_t, c.POINTER(Peaks)]),
         "krps_sketched_solve_seeded": (c.c_int, [P, P, c.c_int, c.c_int64, c.c_uint64,
                                                  c.c_uint64, c.c_uint64, P, P, c.c_size_t]),
         "krps_als_sweep_seeded": (c.c_int, [P, P, c.c_int64, c.c_uint64, c.c_uint64, c.c_uint64,
@@ -175,6 +182,15 @@ class Context:
         if getattr(self, "handle", None) is not None and _lib is not None:
             _lib.krps_ctx_destroy(self.handle)
             self.handle = None
+
+
+def measure_peaks(ctx: "Context", nbytes=1 << 30):
+    """Measured HBM copy bandwidth and vector / matrix-core peaks (dict)."""
+    torch = ctx.torch
+    ws = torch.empty(int(nbytes), dtype=torch.uint8, device=ctx.device)
+    out = Peaks()
+    check(lib().krps_measure_peaks(ctx.handle, _ptr(ws), ws.numel(), ctypes.byref(out)))
+    return {n: getattr(out, n) for n, _ in Peaks._fields_}
 
 
 def workspace_regions(dims, R, F=0, precision="fp32", nnz=1, J=1):
@@ -627,6 +643,7 @@ class CPALS:
             "Mp": view(l.Mp, R * R, torch.float64, 8).view(R, R).clone(),
             "Y": self._y(j),
             "yrows": self._yrows(),
+            "expanded": view(l.expanded, 1, torch.int64, 8).clone(),
         }
 
     def _yrows(self):

@@ -457,7 +457,9 @@ SolvePlan plan_solve(const krps_sampler_s* s, int64_t J) {
   l.yrows = off;
   off += align_up((size_t)Imax * 4);
   l.nyrows = off;
-  off += 256;
+  off += 128;
+  l.expanded = off;
+  off += 128;
   pl.ymark = off;
   off += align_up((size_t)Imax * 4);
   pl.ybsum = off;
@@ -561,6 +563,7 @@ krps_status enqueue_solve(krps_sampler s, krps_tensor t, int j, int64_t J, const
   fa.hot_slot = t->hot_slot[j];
   fa.hot_rows = t->hot_rows[j];
   fa.nhot = (int)std::min<int64_t>(t->nhot, t->dims[j]);
+  fa.expanded = (int64_t*)(w + l.expanded);
   e = launch_lookup(st, fa);
   if (e != hipSuccess) return hip_fail(e, "fiber lookup");
   // only the rows of Y that the entries reach are cleared, summed into and
@@ -709,6 +712,11 @@ krps_status krps_ctx_destroy(krps_ctx ctx) {
   if (ctx != nullptr && ctx->capture != nullptr) (void)hipStreamDestroy(ctx->capture);
   delete ctx;
   return KRPS_OK;
+}
+
+krps_status krps_measure_peaks(krps_ctx ctx, void* ws, size_t ws_bytes, krps_peaks* out) {
+  if (ctx == nullptr) return fail(KRPS_EINVAL, "ctx is NULL");
+  return measure_peaks(ctx->device, ctx->stream, ws, ws_bytes, out);
 }
 
 krps_status krps_ctx_sync(krps_ctx ctx) {
@@ -1961,7 +1969,8 @@ krps_status krps_workspace_regions(int N, const int64_t* I, int R, int F, krps_p
   rl.add(2, "M rank", pl.rank, span(pl.rank, l.Y), 8);
   rl.add(2, "Y", l.Y, span(l.Y, l.yrows), (size_t)pl.Imax * R * (p == KRPS_BF16X2 ? 4 : 8));
   rl.add(2, "Y rows", l.yrows, span(l.yrows, l.nyrows), (size_t)pl.Imax * 4);
-  rl.add(2, "Y row count", l.nyrows, span(l.nyrows, pl.ymark), 8);
+  rl.add(2, "Y row count", l.nyrows, span(l.nyrows, l.expanded), 8);
+  rl.add(2, "expanded entries", l.expanded, span(l.expanded, pl.ymark), 8);
   rl.add(2, "row marks", pl.ymark, span(pl.ymark, pl.ybsum), (size_t)pl.Imax * 4);
   rl.add(2, "row scan", pl.ybsum, span(pl.ybsum, pl.partial), row_bsum_bytes(pl.Imax));
   rl.add(2, "solve partials", pl.partial, span(pl.partial, pl.gscratch), solve_partial_bytes(R));

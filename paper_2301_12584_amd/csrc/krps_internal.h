@@ -159,6 +159,7 @@ struct FiberArgs {
   const int8_t* hot_slot;     // [dims[j]] slot of a hot row of mode j, -1 otherwise
   const int32_t* hot_rows;    // [nhot] the hot rows
   int nhot;
+  int64_t* expanded;          // out: entries the SpMM expands, or null
 };
 
 // Rows of a mode with the most stored entries (kept per workgroup in LDS by
@@ -273,6 +274,10 @@ hipError_t launch_mttkrp(hipStream_t st, krps_precision p, const MttkrpArgs& a, 
 size_t fit_partial_bytes();
 hipError_t launch_fit(hipStream_t st, krps_precision p, const FitArgs& a, double* partial,
                       double* out);
+
+// probes.hip: copy, FMA and MFMA loops timed on the stream (ws >= 64 MiB)
+krps_status measure_peaks(int device, hipStream_t st, void* ws, size_t ws_bytes,
+                          krps_peaks* out);
 
 // descent.hip
 hipError_t launch_descent(hipStream_t st, krps_precision p, const DescentArgs& a);

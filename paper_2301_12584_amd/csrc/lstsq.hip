@@ -454,6 +454,23 @@ __global__ void compact_kernel(FiberArgs a) {
   }
 }
 
+// Entries the SpMM expands: the sizes of the distinct sampled fibers,
+// summed by one block in a fixed order (a measurement, read by callers).
+__global__ __launch_bounds__(1024) void expanded_kernel(FiberArgs a) {
+  __shared__ int64_t red[16];
+  int64_t sum = 0;
+  for (int64_t d = threadIdx.x; d < a.J; d += blockDim.x)
+    if (a.cnt[d] > 0) sum += a.hi[d] - a.lo[d];
+  for (int o = 32; o > 0; o >>= 1) sum += __shfl_down(sum, o, 64);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = sum;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int64_t t = 0;
+    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) t += red[w];
+    *a.expanded = t;
+  }
+}
+
 // Exclusive scan of cnt[0..J) into start[0..J] (start[J] = the total) in
 // three launches: tiles of 1024 (wave scans, then the 16 wave totals),
 // the tile totals, and the tile offsets added back.
@@ -690,6 +707,8 @@ hipError_t launch_lookup(hipStream_t st, const FiberArgs& a) {
   int64_t cb = (a.J + 1 + 255) / 256;
   if (cb > 4096) cb = 4096;
   hipLaunchKernelGGL(compact_kernel, dim3((unsigned)cb), dim3(256), 0, st, a);
+  if (a.expanded != nullptr)
+    hipLaunchKernelGGL(expanded_kernel, dim3(1), dim3(1024), 0, st, a);
   return hipGetLastError();
 }
 
