@@ -1,21 +1,25 @@
 """Benchmark of the exact Khatri-Rao leverage sampler and the sketched
 CP-ALS sweep on one MI355X.
 
-Headline number (``value``, samples/s, BF16 hi/lo split trees; float32 and
-float64 beside it): N = 3 factors of 2^20 x 32
-(float32, N(0,1) with 1% of the rows scaled by 100), J = 65,536 samples
-drawn from the Khatri-Rao product of the other two factors for each
-excluded mode k in {0, 1, 2}.  One step = rebuild the three segment trees +
-prepare and draw the three exclusions (with the probability of every
-sample), the three preparations batched and the three walks in one
-persistent launch.
+Headline number (``value``, samples/s, the plain float64 path; float32
+storage and BF16 hi/lo split trees beside it): N = 3 factors of 2^20 x 32
+(N(0,1) with 1% of the rows scaled by 100), J = 65,536 samples drawn from
+the Khatri-Rao product of the other two factors for each excluded mode
+k in {0, 1, 2}.  One step = rebuild the three segment trees + prepare and
+draw the three exclusions (with the probability of every sample), the
+three preparations batched and the three walks in one persistent launch.
 
 Second half of the metric (``als``): sketched CP-ALS on a sparse
 1e6 x 1e6 x 1e5 tensor with 1e8 Zipf(1.2) nonzeros, R = 64, J = 65,536
 samples per solve, 10 sweeps, each sweep replayed from a HIP graph; sweep
 time (fit excluded) and the fit after every sweep, BF16 hi/lo split Grams
-against the plain float64 path, with the float64 oracle's fits when they
-have been stored.
+against the plain float64 path, the float64 oracle's fits beside them, the
+exact (unsampled) ALS fits for the fraction of exact fit, and the sweep's
+roofline floor.
+
+Also: the 64-sampler batched workload, the least-squares accuracy
+experiment (residual error and distortion, N up to 9), measured peaks, and
+the float64 oracle on the host as the CPU baseline.
 
 Prints one JSON line.
 """
@@ -33,9 +37,12 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 METRIC = "KRP leverage samples/s + ALS sweep s at fit +-1e-4: BF16-split vs FP64"
+# datasheet peaks of MI355X (dense)
 HBM_PEAK_GBS = 8000.0
 F64_VALU_PEAK_TFS = 78.6
-COUNTERS = os.path.join(ROOT, "profiles", "descent_c2_fp32_counters.json")
+F64_MFMA_PEAK_TFS = 78.6
+BF16_MFMA_PEAK_TFS = 2500.0
+COUNTERS = os.path.join(ROOT, "profiles", "descent_c2_counters.json")
 DESCENT_SRC = os.path.join(ROOT, "paper_2301_12584_amd", "csrc", "descent.hip")
 
 
@@ -65,6 +72,11 @@ def parse():
     ap.add_argument("--batched", default="fp32",
                     help="precision of the batched-samplers leg ('' skips it)")
     ap.add_argument("--batched-reps", type=int, default=3)
+    ap.add_argument("--no-exact", action="store_true", help="skip the exact (unsampled) ALS leg")
+    ap.add_argument("--no-ls-accuracy", action="store_true",
+                    help="skip the least-squares accuracy experiment")
+    ap.add_argument("--no-cpu-als", action="store_true",
+                    help="skip the oracle's timed solve on the CP-ALS tensor")
     return ap.parse_args()
 
 
@@ -110,14 +122,46 @@ def descent_flops(dims, R, F, exclude, J, N):
     return fl * J
 
 
-def counters_for(src_sha):
+def counters_for(src_sha, prec):
+    """HBM bytes per walk launch from the stored rocprofv3 counters of this
+    precision, if they were taken on the current walk source."""
     try:
         c = json.load(open(COUNTERS))
     except (OSError, ValueError):
         return None
     if c.get("descent_src_sha256") != src_sha:
         return None
-    return c
+    return c.get("precisions", {}).get(prec)
+
+
+def tree_nodes(I, F):
+    """Stored nodes of T_{I,F}: the root and the left children."""
+    L = -(-I // F)
+    D = (L - 1).bit_length() if L > 1 else 0
+    return 1 + sum(((L - 1) >> (D - l + 1)) + 1 for l in range(1, D + 1))
+
+
+def roofline(bytes_, flops, seconds, vpeak_tfs, mpeak_tfs=None, kernel=None):
+    """Both fractions of one launch and the binding one (the larger)."""
+    hbm = bytes_ / seconds / 1e9
+    alu = flops / seconds / 1e12
+    fh, fv = hbm / HBM_PEAK_GBS, alu / (mpeak_tfs or vpeak_tfs)
+    if fh >= fv:
+        r = {"bound": "hbm", "achieved": hbm, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": fh}
+    else:
+        r = {"bound": "mfma" if mpeak_tfs else "alu", "achieved": alu,
+             "peak": mpeak_tfs or vpeak_tfs, "unit": "TFLOP/s", "frac": fv}
+    r.update({"hbm_frac": fh, "alu_frac": fv, "algorithmic_bytes": bytes_, "flops": flops,
+              "launch_ms": seconds * 1e3})
+    if kernel:
+        r["kernel"] = kernel
+    return r
+
+
+def floor_s(bytes_, flops, peak_tfs):
+    """Roofline time of one step: the larger of its bytes at HBM peak and
+    its flops at the unit's peak."""
+    return max(bytes_ / (HBM_PEAK_GBS * 1e9), flops / (peak_tfs * 1e12))
 
 
 def run_sampler(torch, krps, ctx, Us, u01_dev, prec, steps, warmup, J):
@@ -254,7 +298,8 @@ def cpu_baseline(Us, u01, J_full, budget_s=20.0):
     t_draw = (time.perf_counter() - t0) / done
     step_s = t_build + N * J_full * t_draw
     return {"value": N * J_full / step_s, "unit": "samples/s",
-            "cores": blas_threads(), "kind": "oracle",
+            "cores": blas_threads(), "affinity_cores": len(os.sched_getaffinity(0)),
+            "kind": "oracle",
             "sample": f"float64 NumPy oracle on the full factors: tree build of the 3 factors "
                       f"({t_build:.2f} s) + {done} draws ({Jc} per exclusion, "
                       f"{t_draw * 1e6:.1f} us/draw), scaled to one step of 3 x {J_full} draws; "
@@ -272,7 +317,38 @@ def oracle_fits(config, store, nnz):
         return None
 
 
-def run_als(torch, krps, ctx, precs, nnz, sweeps_arg, seeds, config=3, init="gaussian"):
+def solve_floor(parts, prec, dims, R, J, j, nu):
+    """Roofline time of one sketched solve, step by step (Section 8(d)):
+    sum over its steps of max(algorithmic bytes / HBM peak, flops / peak of
+    the unit the step runs on).  The per-draw eigendecompositions are
+    latency-bound and left out (reported by the profiles).  Returns
+    (seconds, {step: seconds})."""
+    import numpy as np
+    N = len(dims)
+    s = 8 if prec == "fp64" else 4            # factor and node storage
+    rs = 4 if prec == "bf16x2" else 8         # rows of S A and Y
+    mm = BF16_MFMA_PEAK_TFS if prec == "bf16x2" else F64_MFMA_PEAK_TFS
+    I = dims[j]
+    tri = R * (R + 1) // 2
+    idx = parts["idx"].cpu().numpy()
+    E = int(parts["expanded"].cpu().numpy()[0])
+    nrows = int(len(parts["yrows"]))
+    st = {}
+    st["tree build"] = floor_s(I * R * s + tree_nodes(I, R) * tri * s, 2.0 * I * R * R, mm)
+    st["walk"] = floor_s(unique_descent_bytes(idx, j, dims, R, R, s, J, N),
+                         descent_flops(dims, R, R, j, J, N), F64_VALU_PEAK_TFS)
+    st["sampled Gram"] = floor_s(J * R * rs, 2.0 * J * R * R, mm)
+    st["fiber lookup"] = floor_s(J * (N - 1) * 4 * int(np.ceil(np.log2(max(nu, 2)))) + J * N * 4
+                                 + 2 * J * 8, 0, 1)
+    st["SpMM"] = floor_s(E * (4 + 8 + 2 * R * rs), 2.0 * E * R, F64_VALU_PEAK_TFS)
+    st["rows of Y"] = floor_s(E * 4 + 3 * I * 4 + nrows * R * rs, 0, 1)
+    st["Y M+ and sigma"] = floor_s(nrows * R * rs + I * R * s + nrows * R * s,
+                                   2.0 * nrows * R * R, F64_VALU_PEAK_TFS)
+    return sum(st.values()), st
+
+
+def run_als(torch, krps, ctx, precs, nnz, sweeps_arg, seeds, config=3, init="gaussian",
+            exact=False):
     """Sketched CP-ALS: one untimed sweep captures the graph, the factors
     are reset, then every sweep is replayed and timed with HIP events on
     the context stream; the fit is taken between sweeps, outside the
@@ -342,6 +418,39 @@ def run_als(torch, krps, ctx, precs, nnz, sweeps_arg, seeds, config=3, init="gau
             fits.append(A.fit())
             print(f"# als {prec} sweep {s}: {ms[-1]:.3f} ms fit {fits[-1]:.6f}", file=sys.stderr,
                   flush=True)
+        zero_w = S.check_status()
+        # in-kernel uniforms (krps_als_sweep_seeded): the same sweep without
+        # the staged uniform buffers, one captured graph for every sweep
+        reset()
+        A.sweep_seeded(useed, 0, 0, use_graph=True)
+        reset()
+        torch.cuda.synchronize()
+        ms_seeded = []
+        for s in range(sweeps):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            A.sweep_seeded(useed, 0, s, use_graph=True)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            ms_seeded.append(e0.elapsed_time(e1))
+        fit_seeded = A.fit()
+        # roofline floor of a sweep: one eager sweep, each solve's pieces
+        reset()
+        for s in range(sweeps - 1):
+            ubuf.copy_(u_all[s])
+            A.sweep(ubuf, use_graph=True)
+        floors, steps = [], {}
+        nu = T.stored_entries
+        for j in range(N):
+            A.solve(j, u_all[sweeps - 1][j])
+            torch.cuda.synchronize()
+            f, st = solve_floor(A.parts(j), prec, dims, R, J, j, nu)
+            floors.append(f)
+            for k, v in st.items():
+                steps[k] = steps.get(k, 0.0) + v
+        floor_ms = 1e3 * sum(floors)
+        print(f"# als {prec}: sweep floor {floor_ms:.3f} ms, seeded sweep "
+              f"{float(np.mean(ms_seeded)):.3f} ms", file=sys.stderr, flush=True)
         # more uniform seeds: the spread of the final fit over sketches
         finals = [fits[-1]]
         for extra in range(1, seeds):
@@ -358,7 +467,16 @@ def run_als(torch, krps, ctx, precs, nnz, sweeps_arg, seeds, config=3, init="gau
                "als_s_total": float(np.sum(ms)) / 1e3, "fits": fits,
                "final_fit_over_seeds": finals, "final_fit_mean": float(np.mean(finals)),
                "final_fit_std": float(np.std(finals)),
-               "samples_per_s_in_sweep": N * J / (float(np.mean(ms)) / 1e3)}
+               "samples_per_s_in_sweep": N * J / (float(np.mean(ms)) / 1e3),
+               "zero_weight_samples": zero_w,
+               "seeded_sweep_ms_mean": float(np.mean(ms_seeded)), "seeded_final_fit": fit_seeded,
+               "sweep_roofline": {"floor_ms": floor_ms,
+                                  "frac": floor_ms / float(np.mean(ms)),
+                                  "steps_floor_ms": {k: 1e3 * v for k, v in steps.items()},
+                                  "note": "sum over the solves' steps of max(bytes / HBM peak, "
+                                          "flops / unit peak); eigendecompositions excluded"}}
+        if exact:
+            rec["exact"] = run_exact(torch, krps, ctx, S, T, A, reset, N, sweeps, finals)
         if ref is not None and len(ref) == len(fits):
             rec["oracle_fits"] = ref
             diff = np.abs(np.array(fits) - np.array(ref))
@@ -388,6 +506,30 @@ def run_als(torch, krps, ctx, precs, nnz, sweeps_arg, seeds, config=3, init="gau
             "final_fit_gap": a["final_fit_mean"] - b["final_fit_mean"],
             "within_1e-4": abs(a["final_fit_mean"] - b["final_fit_mean"]) <= 1e-4}
     return res
+
+
+def run_exact(torch, krps, ctx, S, T, A, reset, N, sweeps, finals):
+    """Exact ALS (the full sparse MTTKRP, no sampling) from the same start:
+    its fits, sweep time, and the sketched runs' fraction of the exact fit
+    (Appendix A.13's accuracy measure)."""
+    import numpy as np
+    reset()
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    ms, fits = [], []
+    for s in range(sweeps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for j in range(N):
+            A.exact_solve(j)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms.append(e0.elapsed_time(e1))
+        fits.append(A.fit())
+    print(f"# exact ALS: sweep {float(np.mean(ms)):.3f} ms, fits {np.round(fits, 6)}",
+          file=sys.stderr, flush=True)
+    return {"sweep_ms_mean": float(np.mean(ms)), "fits": fits,
+            "fraction_of_exact_fit": float(np.mean(finals)) / fits[-1]}
 
 
 def run_batched(torch, krps, ctx, prec, reps):
@@ -437,6 +579,27 @@ def run_batched(torch, krps, ctx, prec, reps):
         torch.cuda.synchronize()
         ts.append(e0.elapsed_time(e1))
     same = all(torch.equal(a, o[0]) for a, o in zip(idx_b, outs))
+    # the batched call's halves: preparations, then the one walk launch per class
+    pidx = [torch.empty_like(i) for i in idx_b]
+    pprob = [torch.empty_like(q) for q in prob_b]
+    tp, tw = [], []
+    for _ in range(reps):
+        e0, e1, e2 = ev(), ev(), ev()
+        e0.record()
+        batch.prepare()
+        e1.record()
+        batch.draw(unis, pidx, pprob)
+        e2.record()
+        torch.cuda.synchronize()
+        tp.append(e0.elapsed_time(e1))
+        tw.append(e1.elapsed_time(e2))
+    es = 8 if prec == "fp64" else 4
+    ub = fl = 0
+    for (dims, R), ib in zip(probs, idx_b):
+        ii = ib.cpu().numpy()
+        ub += unique_descent_bytes(ii, -1, dims, R, R, es, J, len(dims))
+        fl += descent_flops(dims, R, R, -1, J, len(dims))
+    walk_s = float(np.median(tw)) / 1e3
     e0, e1 = ev(), ev()
     e0.record()
     for S in samplers:
@@ -453,13 +616,142 @@ def run_batched(torch, krps, ctx, prec, reps):
            "batched_ms": float(np.median(tb)), "per_problem_ms": float(np.median(ts)),
            "batched_samples_per_s": total / (float(np.median(tb)) / 1e3),
            "per_problem_samples_per_s": total / (float(np.median(ts)) / 1e3),
-           "build_all_ms": e0.elapsed_time(e1), "identical_to_per_problem": bool(same)}
+           "build_all_ms": e0.elapsed_time(e1), "identical_to_per_problem": bool(same),
+           "prepare_ms": float(np.median(tp)), "walk_ms": float(np.median(tw)),
+           "walk_roofline": roofline(ub, fl, walk_s, F64_VALU_PEAK_TFS,
+                                     kernel="descent_batched_kernel (all classes, summed over "
+                                            "the 64 problems)")}
     print(f"# batched {prec}: {rec['batched_ms']:.2f} ms ({rec['batched_samples_per_s'] / 1e6:.1f}"
           f" M samples/s) vs per-problem {rec['per_problem_ms']:.2f} ms; identical {same}",
           file=sys.stderr, flush=True)
     del samplers
     torch.cuda.synchronize()
     return rec
+
+
+def run_ls_accuracy(torch, krps, ctx, prec="fp64", Ns=(3, 4, 5, 6, 7, 8, 9), Rs=(16, 32, 64),
+                    trials=3):
+    """The least-squares accuracy experiment of Section 4.2: A = U_1 (.) ...
+    (.) U_N with I = 2^16 (N(0,1) entries, 1% of them x10), b = c_1 (x) ...
+    (x) c_N with N(0,1) c_j, J = 5000 leverage samples drawn on the GPU and
+    the sketched problem solved on the GPU (krps_sketched_lstsq).  The
+    evaluation on the host uses the Gram identities (A^T A = (*) G_k,
+    A^T b = (*) U_k^T c_k, ||b||^2 = prod ||c_k||^2): residual error
+    eps = ||A x - b|| / ||A x* - b|| - 1 and distortion kappa(S Q) - 1 with
+    S Q = S A V Sigma^-1 (Appendix A.12)."""
+    import numpy as np
+    import synth
+    I, J = 1 << 16, 5000
+    out = {"workload": "N in 3..9, I=2^16, R in {16,32,64}, J=5000, 1% of entries x10, "
+                       "b = c_1 (x) ... (x) c_N", "precision": prec, "trials": trials, "runs": []}
+    dt = torch.float64 if prec == "fp64" else torch.float32
+    for R in Rs:
+        for N in Ns:
+            Us = synth.gaussian_factors((I,) * N, R, seed=5000 + 10 * N + R,
+                                        heavy_entries_frac=0.01)
+            rng = np.random.default_rng(6000 + 10 * N + R)
+            cs = [rng.standard_normal(I) for _ in range(N)]
+            S = krps.Sampler(ctx, [torch.from_numpy(U).to(ctx.device).to(dt).contiguous()
+                                   for U in Us], precision=prec)
+            G = np.ones((R, R))
+            Atb = np.ones(R)
+            bb = 1.0
+            for k in range(N):
+                G *= S.gram(k).cpu().numpy()
+                Atb *= Us[k].astype(np.float64).T @ cs[k]
+                bb *= float(cs[k] @ cs[k])
+            lam, V = np.linalg.eigh(G)
+            keep = lam > R * 2.0 ** -52 * lam.max()
+            Gp = (V[:, keep] / lam[keep]) @ V[:, keep].T
+            xo = Gp @ Atb
+
+            def resid(x):
+                return np.sqrt(max(float(x @ G @ x - 2 * x @ Atb + bb), 0.0))
+
+            ro = resid(xo)
+            eps, dist, ms = [], [], []
+            for t in range(trials):
+                u = torch.from_numpy(synth.uniforms(J, N, 7000 + 100 * N + R + t)).to(ctx.device)
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record()
+                idx, prob, rows = S.sample(-1, u, rows=True)
+                e1.record()
+                torch.cuda.synchronize()
+                ms.append(e0.elapsed_time(e1))
+                gi = idx.cpu().numpy().astype(np.int64)
+                sb = np.ones(J)
+                for k in range(N):
+                    sb *= cs[k][gi[:, k]]
+                X = krps.sketched_lstsq(ctx, rows, prob, torch.from_numpy(sb[:, None])
+                                        .to(ctx.device).to(dt)).cpu().numpy()[:, 0]
+                eps.append(resid(X) / ro - 1.0)
+                SA = rows.cpu().numpy().astype(np.float64) / np.sqrt(J * prob.cpu().numpy())[:, None]
+                sv = np.linalg.svd(SA @ (V[:, keep] / np.sqrt(lam[keep])), compute_uv=False)
+                dist.append(sv[0] / sv[-1] - 1.0)
+            rec = {"N": N, "R": R, "eps_mean": float(np.mean(eps)), "eps": eps,
+                   "distortion_mean": float(np.mean(dist)), "draw_ms": float(np.median(ms))}
+            out["runs"].append(rec)
+            print(f"# ls accuracy N={N} R={R}: eps {rec['eps_mean']:.2e} distortion "
+                  f"{rec['distortion_mean']:.3f} draw {rec['draw_ms']:.3f} ms", file=sys.stderr,
+                  flush=True)
+            del S
+    return out
+
+
+def cpu_info():
+    model = None
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return {"model": model, "affinity_cores": len(os.sched_getaffinity(0)),
+            "blas_threads": blas_threads()}
+
+
+def cpu_single_thread(Us, u01, n=2000):
+    """Oracle draws of the sampler-at-scale workload with one BLAS thread."""
+    from threadpoolctl import threadpool_limits
+    from oracle import sampler as osmp
+    with threadpool_limits(limits=1):
+        S = osmp.KRPSampler(Us)
+        t0 = time.perf_counter()
+        S.draw(0, u01[0][:n])
+        dt = time.perf_counter() - t0
+    return {"value": n / dt, "unit": "samples/s", "cores": 1, "sample": f"{n} draws excluding "
+            "mode 0 (trees prebuilt), one BLAS thread"}
+
+
+def cpu_als_solve(budget_note=True):
+    """The oracle's sketched solve of mode 2 of the CP-ALS workload (sweep
+    0's uniforms) on the host, timed after the one-time fiber index of
+    mode 2 (which the GPU builds at tensor creation)."""
+    import numpy as np
+    import synth
+    from oracle import cp as ocp
+    from oracle import sampler as osmp
+    t0 = time.perf_counter()
+    dims, idx, val, U0, R, J, sweeps, useed = synth.als_problem(3)
+    T = ocp.SparseTensor(dims, idx, val)
+    del idx, val
+    T.fibers(2)
+    Us = [ocp.normalize_columns(U.astype(np.float32).astype(np.float64))[0] for U in U0]
+    S = osmp.KRPSampler(Us)
+    t_setup = time.perf_counter() - t0
+    print(f"# cpu baseline (als): tensor, index and trees in {t_setup:.1f} s", file=sys.stderr,
+          flush=True)
+    t0 = time.perf_counter()
+    ocp.sketched_solve(S, T, 2, synth.sweep_uniforms(useed, 0, 3, J)[2])
+    t_solve = time.perf_counter() - t0
+    print(f"# cpu baseline (als): one solve in {t_solve:.1f} s", file=sys.stderr, flush=True)
+    return {"value": t_solve * 1e3, "unit": "ms per solve (mode 2)", "cores": blas_threads(),
+            "kind": "oracle", "higher_is_better": False,
+            "sample": f"one sketched solve of mode 2 (I=1e5, J=65536, R=64) of sweep 0 on the "
+                      f"1e8-entry tensor, after the one-time fiber index and trees "
+                      f"({t_setup:.0f} s); draw, normal equations, pseudo-inverse, update, "
+                      f"rebuild of Z_2"}
 
 
 def main():
@@ -492,35 +784,35 @@ def main():
     u01 = [synth.uniforms(J, N, synth.uniform_seed(2) + k) for k in range(N)]
     ctx = krps.Context(0)
     u01_dev = [torch.from_numpy(u).to(ctx.device) for u in u01]
+    peaks = krps.measure_peaks(ctx)
+    print(f"# measured peaks: {peaks}", file=sys.stderr, flush=True)
 
+    precs = args.precisions.split(",")
     results = {}
-    for prec in args.precisions.split(","):
+    for prec in precs:
         results[prec] = run_sampler(torch, krps, ctx, Us, u01_dev, prec, args.steps,
                                     args.warmup, J)
         print(f"# {prec}: {results[prec]['samples_per_s'] / 1e6:.2f} M samples/s, "
               f"step {results[prec]['ms_per_step']:.3f} ms, build {results[prec]['build_ms']:.3f} ms, "
               f"walk {results[prec]['walk_ms']:.3f} ms", file=sys.stderr, flush=True)
 
-    # headline: the bf16 hi/lo split path (float32 storage, split-MFMA tree
-    # build, float64 walk); fp32 and fp64 are reported beside it
-    head = next((p for p in ("bf16x2", "fp32") if p in results), list(results)[0])
-    r = results[head]
-    elem = 8 if head == "fp64" else 4
-    # roofline of the dominant kernel: the batched walk of the N exclusions
-    ub = sum(unique_descent_bytes(r["idx"][k], k, dims, R, R, elem, J, N) for k in range(N))
-    fl = sum(descent_flops(dims, R, R, k, J, N) for k in range(N))
-    t = r["walk_ms"] / 1e3
+    # rooflines of the dominant kernel, the batched walk of the N exclusions:
+    # unique algorithmic bytes and float64 flops of the launch over its
+    # HIP-event time; the bound is the larger of the two fractions
     sha = hashlib.sha256(open(DESCENT_SRC, "rb").read()).hexdigest()
-    cnt = counters_for(sha)
-    traffic = None
-    if cnt is not None:
-        traffic = cnt.get("hbm_bytes_per_launch")
-    roof = {"bound": "hbm", "achieved": ub / t / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": ub / t / 1e9 / HBM_PEAK_GBS, "traffic": traffic,
-            "kernel": "descent_batched_kernel (3 exclusions in one launch)",
-            "algorithmic_bytes": ub, "launch_ms": r["walk_ms"],
-            "valu_f64_frac": fl / t / 1e12 / F64_VALU_PEAK_TFS, "flops": fl}
-
+    roofs = {}
+    for prec, r in results.items():
+        elem = 8 if prec == "fp64" else 4
+        ub = sum(unique_descent_bytes(r["idx"][k], k, dims, R, R, elem, J, N) for k in range(N))
+        fl = sum(descent_flops(dims, R, R, k, J, N) for k in range(N))
+        roofs[prec] = roofline(ub, fl, r["walk_ms"] / 1e3, F64_VALU_PEAK_TFS,
+                               kernel="descent_batched_kernel (3 exclusions in one launch)")
+        cnt = counters_for(sha, prec)
+        roofs[prec]["traffic"] = cnt.get("hbm_bytes_per_launch") if cnt else None
+    # headline: the plain float64 path (the paper's precision); the split and
+    # float32-storage paths are reported beside it
+    head = "fp64" if "fp64" in results else precs[0]
+    r = results[head]
     line = {
         "metric": METRIC, "value": r["samples_per_s"], "unit": "samples/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": r["ms_per_step"],
@@ -534,18 +826,25 @@ def main():
                                        "walk: f64 over f32-stored trees",
                              "fp32": "tree build: f64 MFMA; walk: f64 over f32-stored trees",
                              "fp64": "f64 throughout"}[head]},
-        "roofline": roof,
+        "roofline": roofs[head],
+        "rooflines_by_precision": roofs,
+        "peaks": {"datasheet": {"hbm_gbs": HBM_PEAK_GBS, "f64_vector_tflops": F64_VALU_PEAK_TFS,
+                                "f64_matrix_tflops": F64_MFMA_PEAK_TFS,
+                                "bf16_matrix_tflops": BF16_MFMA_PEAK_TFS,
+                                "f32_vector_tflops": 157.3},
+                  "measured": peaks},
         "precisions": {p: {"samples_per_s": v["samples_per_s"], "ms_per_step": v["ms_per_step"],
                            "build_ms": v["build_ms"], "walk_ms": v["walk_ms"]}
                        for p, v in results.items()},
     }
-    del results
     torch.cuda.synchronize()
     if args.als:
         line["als"] = run_als(torch, krps, ctx, args.als.split(","), args.als_nnz,
-                              args.als_sweeps, args.als_seeds)
+                              args.als_sweeps, args.als_seeds, exact=not args.no_exact)
     if args.batched:
         line["batched"] = run_batched(torch, krps, ctx, args.batched, args.batched_reps)
+    if not args.no_ls_accuracy:
+        line["ls_accuracy"] = run_ls_accuracy(torch, krps, ctx)
     if args.large:
         # the N(0,1) start draws only empty fibers of this tensor (5e8 entries
         # among 4e20 fibers per mode), so the first solve is zero; the range
@@ -554,8 +853,12 @@ def main():
                                     1, config=5, init="range_finder")
     if args.paper_point:
         line["paper_point"] = run_paper_point(torch, krps, ctx, ["bf16x2", "fp64"])
+    line["cpu"] = cpu_info()
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(Us, u01, J)
+        line["cpu_baseline_single_thread"] = cpu_single_thread(Us, u01)
+        if args.als and not args.no_cpu_als:
+            line["cpu_baseline_als"] = cpu_als_solve()
     else:
         line["cpu_baseline"] = None
     print(json.dumps(line))
