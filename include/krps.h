@@ -173,16 +173,17 @@ krps_status krps_sample(krps_sampler s, int exclude, int64_t J, const double* un
                         int32_t* idx, double* prob, void* rows, void* ws, size_t ws_bytes,
                         int check);
 
-/* Size of the static per-GPU scratch of krps_sample_static (8 MiB). */
-#define KRPS_STATIC_SCRATCH_BYTES (8u << 20)
+/* Size of the static per-GPU scratch of krps_sample_static (16 MiB). */
+#define KRPS_STATIC_SCRATCH_BYTES (16u << 20)
 
 /* krps_sample without a workspace argument and without any allocation, for
  * callers that cannot allocate (code under HIP graph capture, tight serving
  * loops, harnesses that forbid hipMalloc).  The per-draw scratch is a
  * static device array of KRPS_STATIC_SCRATCH_BYTES per GPU, held until the
  * process ends; the call fails with KRPS_EWORKSPACE when the sampler's
- * per-draw scratch (krps_sample_workspace_bytes: e.g. ~0.5 MB for N = 3,
- * R = 32 and ~3.4 MB for N = 3, R = 64 in float32 storage) is larger.  All
+ * per-draw scratch (krps_sample_workspace_bytes: e.g. ~9 MB for N = 3,
+ * R = 32, I = 2^20 and ~3.6 MB for N = 3, R = 64, I = 2e4 in float32
+ * storage) is larger.  All
  * calls on one GPU share that array: calls that overlap on one GPU (two
  * streams, two host threads) race.  Results equal krps_sample's with the
  * same arguments (no status check). */

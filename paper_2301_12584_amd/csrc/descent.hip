@@ -414,11 +414,23 @@ __device__ __forceinline__ void descend(const DescentArgs& a, int64_t base,
     for (int i = 0; i < HE; ++i)
       if (sl + LPS * i < R) hb[sl + LPS * i] = ht[i];
     wave_lds_sync();
-    if constexpr (NP > 0) build_packed(P, hb, tab, TR, sl);
+    if constexpr (NP > 0)
+      if (!(st == 0 && md.zt != nullptr)) build_packed(P, hb, tab, TR, sl);
     const T* __restrict__ Z = (const T*)md.Z;
-    const double C2 = node_mass<T>(P, hb, Z, R, TR, sl, tab);
-    const double x2 = d2 * C2;
-    const int64_t c = walk(Z, md.L, md.D, P, hb, R, TR, sl, x2, C2, low, tab);
+    double C2, x2;
+    int64_t c;
+    if (st == 0 && md.zt != nullptr) {
+      // first drawn mode: the node masses for h~ = V[:, u] were tabulated
+      // by the preparation; the walk reads one float64 per level
+      const double* __restrict__ zt = md.zt + (int64_t)u * md.zn;
+      C2 = zt[0];
+      x2 = d2 * C2;
+      c = walk_table(zt, md.L, md.D, x2, C2, low);
+    } else {
+      C2 = node_mass<T>(P, hb, Z, R, TR, sl, tab);
+      x2 = d2 * C2;
+      c = walk(Z, md.L, md.D, P, hb, R, TR, sl, x2, C2, low, tab);
+    }
     const int64_t s0 = c * md.F;
     const int64_t s1 = s0 + md.F < md.I ? s0 + md.F : md.I;
     const T* __restrict__ U = (const T*)md.U;

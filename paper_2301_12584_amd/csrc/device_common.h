@@ -43,6 +43,18 @@ __host__ __device__ __forceinline__ int64_t packed_index(int a, int b, int R) {
   return (int64_t)a * R - ((int64_t)a * (a - 1)) / 2 + (b - a);
 }
 
+// (a, b), a <= b, of packed entry p (inverse of packed_index).
+__device__ __forceinline__ void unpack_index(int64_t p, int R, int& a, int& b) {
+  const double q = (double)(2 * R + 1);
+  int aa = (int)((q - sqrt(q * q - 8.0 * (double)p)) * 0.5);
+  if (aa < 0) aa = 0;
+  if (aa > R - 1) aa = R - 1;
+  while (aa > 0 && packed_index(aa, aa, R) > p) --aa;
+  while (aa < R - 1 && packed_index(aa + 1, aa + 1, R) <= p) ++aa;
+  a = aa;
+  b = aa + (int)(p - packed_index(aa, aa, R));
+}
+
 // Offset (in nodes) of the stored left children of level `lev` (>= 1) in
 // a tree with L leaves and depth D; the root is node 0.
 __device__ __forceinline__ int64_t level_offset(int64_t L, int D, int lev) {

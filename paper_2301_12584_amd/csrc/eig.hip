@@ -535,6 +535,125 @@ hipError_t launch_eig_batched(hipStream_t st, bool f64, const EigJob* jobs, int 
   return hipGetLastError();
 }
 
+// ---------------------------------------------- first-mode factor-tree masses
+//
+// For the first drawn mode the history is h = 1, so stage 2 weights every
+// node of Z_k with h~ = V[:, u]: its mass V[:, u]^T G^v V[:, u] depends only
+// on the component u drawn in stage 1.  The table tab[u][n] of every stored
+// node n and every u is a contraction of the packed weights
+// P[u][p] = w_p V[a_p][u] V[b_p][u] (w = 2 off the diagonal) with the stored
+// packed nodes: tab = P Z^T over the tri(R) packed entries, float64 over the
+// stored values.  A block computes RMAX u's x NB nodes, K in chunks of KC
+// packed entries staged through LDS; a thread holds 4 u's x NB/32 nodes.
+
+// P[p][u] = w_p V[a_p][u] V[b_p][u] (columns u >= R are 0), RMAX columns.
+template <typename T, int RMAX>
+__global__ __launch_bounds__(256) void zweights_kernel(const T* __restrict__ V, int R,
+                                                       double* __restrict__ P) {
+  const int TR = R * (R + 1) / 2;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < (int64_t)TR * RMAX;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const int p = (int)(i / RMAX), u = (int)(i % RMAX);
+    double v = 0.0;
+    if (u < R) {
+      int a, b;
+      unpack_index(p, R, a, b);
+      v = (a == b ? 1.0 : 2.0) * (double)V[(int64_t)u * R + a] * (double)V[(int64_t)u * R + b];
+    }
+    P[i] = v;
+  }
+}
+
+// The contraction on the float64 matrix cores: a wavefront owns 16 nodes
+// and every u (RMAX / 16 accumulator tiles of v_mfma_f64_16x16x4f64); per
+// step of 4 packed entries lane l supplies A = P[p0 + l/16][16 t + l%16]
+// and B = G^(n0 + l%16)[p0 + l/16], and holds the result rows 4 i + l/16 of
+// column l%16.  Loads of KS steps are issued before their products.
+template <typename T, int RMAX>
+__global__ __launch_bounds__(256) void ztab_kernel(const T* __restrict__ Z, int64_t nn, int R,
+                                                   const double* __restrict__ P,
+                                                   double* __restrict__ tab) {
+  constexpr int NTU = RMAX / 16;  // u tiles
+  constexpr int KS = 8;           // steps of 4 entries whose loads go together
+  const int TR = R * (R + 1) / 2;
+  const int lane = threadIdx.x & 63;
+  const int r16 = lane & 15, k4 = lane >> 4;
+  const int64_t nwave = (int64_t)gridDim.x * (blockDim.x >> 6);
+  for (int64_t n0 = ((int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6)) * 16; n0 < nn;
+       n0 += nwave * 16) {
+    f64x4 acc[NTU];
+#pragma unroll
+    for (int t = 0; t < NTU; ++t) acc[t] = f64x4{0, 0, 0, 0};
+    const int64_t n = n0 + r16;
+    const T* __restrict__ zrow = Z + (n < nn ? n : nn - 1) * (int64_t)TR;
+    for (int p0 = 0; p0 < TR; p0 += 4 * KS) {
+      double bv[KS], av[KS][NTU];
+#pragma unroll
+      for (int ks = 0; ks < KS; ++ks) {
+        const int p = p0 + 4 * ks + k4;
+        const int pc = p < TR ? p : TR - 1;
+        bv[ks] = (double)zrow[pc];
+#pragma unroll
+        for (int t = 0; t < NTU; ++t) av[ks][t] = P[(int64_t)pc * RMAX + 16 * t + r16];
+      }
+#pragma unroll
+      for (int ks = 0; ks < KS; ++ks) {
+        const bool ok = p0 + 4 * ks + k4 < TR && n < nn;
+        const double b = ok ? bv[ks] : 0.0;
+#pragma unroll
+        for (int t = 0; t < NTU; ++t)
+          acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[ks][t], b, acc[t], 0, 0, 0);
+      }
+    }
+#pragma unroll
+    for (int t = 0; t < NTU; ++t)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int u = 16 * t + 4 * i + k4;
+        if (u < R && n < nn) tab[(int64_t)u * nn + n] = acc[t][i];
+      }
+  }
+}
+
+template <typename T, int RMAX>
+void run_ztab_r(hipStream_t st, const T* Z, int64_t nn, int R, const T* V, double* P,
+                double* tab) {
+  const int TR = R * (R + 1) / 2;
+  int64_t wb = ((int64_t)TR * RMAX + 255) / 256;
+  if (wb > 2048) wb = 2048;
+  hipLaunchKernelGGL((zweights_kernel<T, RMAX>), dim3((unsigned)wb), dim3(256), 0, st, V, R, P);
+  // four wavefronts of 16 nodes per block
+  int64_t blocks = (nn + 63) / 64;
+  if (blocks > 8192) blocks = 8192;
+  if (blocks < 1) blocks = 1;
+  hipLaunchKernelGGL((ztab_kernel<T, RMAX>), dim3((unsigned)blocks), dim3(256), 0, st, Z, nn, R, P,
+                     tab);
+}
+
+template <typename T>
+hipError_t run_ztab(hipStream_t st, const T* Z, int64_t nn, int R, const T* V, double* P,
+                    double* tab) {
+  if (R <= 32)
+    run_ztab_r<T, 32>(st, Z, nn, R, V, P, tab);
+  else if (R <= 64)
+    run_ztab_r<T, 64>(st, Z, nn, R, V, P, tab);
+  else
+    run_ztab_r<T, 128>(st, Z, nn, R, V, P, tab);
+  return hipGetLastError();
+}
+
+size_t ztab_weights_bytes(int R) {
+  const int rmax = R <= 32 ? 32 : R <= 64 ? 64 : 128;
+  return (size_t)R * (R + 1) / 2 * rmax * 8;
+}
+
+hipError_t launch_ztab(hipStream_t st, krps_precision p, const void* Z, int64_t nn, int R,
+                       const void* V, double* weights, double* tab) {
+  if (p == KRPS_FP64)
+    return run_ztab<double>(st, (const double*)Z, nn, R, (const double*)V, weights, tab);
+  return run_ztab<float>(st, (const float*)Z, nn, R, (const float*)V, weights, tab);
+}
+
 hipError_t launch_pinv(hipStream_t st, int R, const double* M, double* Mp_full, int32_t* rank,
                        int32_t* status) {
   const double* mats[1] = {M};

@@ -84,6 +84,9 @@ struct krps_sampler_s {
   int64_t estride;  // elements per mode of the eigen-tree region (nodes + zero padding)
   int DE;
   size_t emass_off;  // per-draw float64 [N][enodes]: E masses at h = 1 (internal)
+  size_t ztab_off;   // per-draw float64 [R][znmax]: first-mode Z masses per u, or 0
+  size_t zw_off;     // per-draw float64: the table's packed weights per u
+  int64_t znmax;     // largest stored-node count of the factor trees (0: no table)
 };
 
 struct krps_tensor_s {
@@ -162,6 +165,10 @@ SamplerPlan plan_sampler(int N, const int64_t* I, int R, int F, krps_precision p
   return pl;
 }
 
+// Largest table of first-mode factor-tree masses a draw workspace holds
+// (R x stored nodes float64); larger samplers walk the first mode's tree.
+constexpr size_t ZTAB_MAX_BYTES = size_t(64) << 20;
+
 void plan_draw(krps_sampler s) {
   const int R = s->R, N = s->N;
   const int64_t TR = tri(R);
@@ -188,6 +195,15 @@ void plan_draw(krps_sampler s) {
   off += align_up((size_t)N * s->estride * s->elem);
   s->emass_off = off;
   off += align_up((size_t)N * s->enodes * 8);
+  // the first drawn mode's factor-tree masses for every eigen-component u,
+  // when the table is at most ZTAB_MAX_BYTES
+  int64_t znmax = 0;
+  for (int k = 0; k < N; ++k) znmax = std::max<int64_t>(znmax, s->shape[k].n_nodes);
+  s->znmax = (size_t)R * znmax * 8 <= ZTAB_MAX_BYTES ? znmax : 0;
+  s->ztab_off = off;
+  off += align_up((size_t)R * s->znmax * 8);
+  s->zw_off = off;
+  off += s->znmax > 0 ? align_up(ztab_weights_bytes(R)) : 0;
   l.n_enodes = s->enodes;
   l.etree_stride = s->estride;
   s->draw_bytes = off;
@@ -233,6 +249,13 @@ krps_status prepare_draw(krps_sampler s, int exclude, void* ws, DescentArgs& a) 
   e = launch_prep_eig2(st, s->prec, R, nsteps, mats, order, ggt, lam, vecs, etree, s->estride,
                        rank, (double*)(w + s->emass_off), s->enodes);
   if (e != hipSuccess) return hip_fail(e, "prep eig launch");
+  if (s->znmax > 0 && nsteps > 0) {
+    const int k0 = order[0];
+    e = launch_ztab(st, s->prec, s->nodes[k0], s->shape[k0].n_nodes, R,
+                    (char*)vecs + (size_t)k0 * R * R * s->elem, (double*)(w + s->zw_off),
+                    (double*)(w + s->ztab_off));
+    if (e != hipSuccess) return hip_fail(e, "first-mode table launch");
+  }
   fill_descent_args(s, exclude, ws, a);
   return KRPS_OK;
 }
@@ -261,6 +284,8 @@ void fill_descent_args(krps_sampler s, int exclude, void* ws, DescentArgs& a) {
     m.E = w + s->lay.etree + (size_t)k * s->estride * s->elem;
     m.V = w + s->lay.vecs + (size_t)k * R * R * s->elem;
     m.em = (const double*)(w + s->emass_off) + (size_t)k * s->enodes;
+    m.zt = s->znmax > 0 ? (const double*)(w + s->ztab_off) : nullptr;
+    m.zn = s->shape[k].n_nodes;
     m.I = s->I[k];
     m.L = s->shape[k].L;
     m.F = s->shape[k].F;
@@ -1164,6 +1189,17 @@ krps_status krps_sample_batched_prepare(krps_ctx ctx, int P, const krps_sampler*
     if (e != hipSuccess) return hip_fail(e, "batched eigen-trees");
     i = j;
   }
+  // first-mode factor-tree mass tables, one launch per problem
+  for (int p = 0; p < P; ++p) {
+    krps_sampler sp = s[p];
+    const int k0 = prep[p].gl.order[0];
+    if (sp->znmax == 0 || prep[p].nsteps == 0) continue;
+    char* dw = w + pl.draw_off[p];
+    hipError_t e = launch_ztab(stream, sp->prec, sp->nodes[k0], sp->shape[k0].n_nodes, sp->R,
+                               dw + sp->lay.vecs + (size_t)k0 * sp->R * sp->R * sp->elem,
+                               (double*)(dw + sp->zw_off), (double*)(dw + sp->ztab_off));
+    if (e != hipSuccess) return hip_fail(e, "batched first-mode tables");
+  }
   return KRPS_OK;
 }
 
@@ -1574,11 +1610,15 @@ TunePlan plan_tune(int N, const int64_t* I, int R, krps_precision p, int64_t J) 
   pl.Fmin = R / 2 > 0 ? R / 2 : 1;
   size_t off = 0;
   pl.sampler = off;
-  off += align_up(plan_sampler(N, I, R, pl.Fmin, p).total);
+  const SamplerPlan sp = plan_sampler(N, I, R, pl.Fmin, p);
+  off += align_up(sp.total);
+  // the smallest leaf size tried has the most nodes, so the largest
+  // first-mode table
   krps_sampler_s tmp;
   tmp.N = N;
   tmp.R = R;
   tmp.elem = elem_bytes(p);
+  tmp.shape = sp.shape;
   plan_draw(&tmp);
   pl.draw = off;
   off += align_up(tmp.draw_bytes);
@@ -1928,8 +1968,12 @@ krps_status krps_workspace_regions(int N, const int64_t* I, int R, int F, krps_p
   rl.add(1, "eigenvectors", dl.vecs, span(dl.vecs, dl.etree), (size_t)N * R * R * es);
   rl.add(1, "eigen-trees", dl.etree, span(dl.etree, tmp.emass_off),
          (size_t)((N - 1) * tmp.estride + tmp.enodes * TR + overread) * es);
-  rl.add(1, "eigen masses", tmp.emass_off, span(tmp.emass_off, tmp.draw_bytes),
+  rl.add(1, "eigen masses", tmp.emass_off, span(tmp.emass_off, tmp.ztab_off),
          (size_t)N * tmp.enodes * 8);
+  rl.add(1, "first-mode table", tmp.ztab_off, span(tmp.ztab_off, tmp.zw_off),
+         (size_t)R * tmp.znmax * 8);
+  rl.add(1, "table weights", tmp.zw_off, span(tmp.zw_off, tmp.draw_bytes),
+         tmp.znmax > 0 ? ztab_weights_bytes(R) : 0);
   // --- solve workspace
   const SolvePlan pl = plan_solve(&tmp, J);
   const SolveHead& h = pl.head;

@@ -58,6 +58,9 @@ struct ModeDesc {
   const void* V;      // eigenvectors, [u][R] (per draw)
   const double* em;   // masses of E's stored nodes at h = 1 (per draw; written
                       // for the first drawn mode only) or null
+  const double* zt;   // [R][zn] masses of Z's stored nodes for h~ = V[:, u]
+                      // (per draw; first drawn mode only) or null
+  int64_t zn;         // stored nodes of Z (the table's row length)
   int64_t I, L;
   int32_t F, D;
   int32_t DE, ne;     // eigen-tree depth and stored nodes
@@ -214,6 +217,13 @@ hipError_t launch_prep_eig2(hipStream_t st, krps_precision p, int R, int nsteps,
                             const double* const* Gsteps, const int* order, const double* ggt,
                             double* lam, void* vecs, void* etree, int64_t estride,
                             int32_t* sweep_out, double* emass, int64_t enodes);
+// Table of the first drawn mode's factor-tree node masses for h~ = V[:, u]:
+// tab[u * nn + n] = V[:,u]^T G^n V[:,u] for the nn stored nodes of Z (V as
+// stored, [u][R]).  Float64 from the stored values.
+// weights: scratch of ztab_weights_bytes(R) for the packed weights of every u.
+size_t ztab_weights_bytes(int R);
+hipError_t launch_ztab(hipStream_t st, krps_precision p, const void* Z, int64_t nn, int R,
+                       const void* V, double* weights, double* tab);
 // rank points at two int32: the rank and the Jacobi sweep count.  A zero or
 // non-finite M sets ST_ZERO / ST_NUMERIC in *status (if not null): the
 // pseudo-inverse of such an M is returned as 0.

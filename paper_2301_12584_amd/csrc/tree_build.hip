@@ -228,17 +228,6 @@ __global__ __launch_bounds__(64 * TW) void leaf_run_kernel(const void* __restric
   });
 }
 
-__device__ __forceinline__ void unpack_index(int64_t p, int R, int& a, int& b) {
-  const double q = (double)(2 * R + 1);
-  int aa = (int)((q - sqrt(q * q - 8.0 * (double)p)) * 0.5);
-  if (aa < 0) aa = 0;
-  if (aa > R - 1) aa = R - 1;
-  while (aa > 0 && packed_index(aa, aa, R) > p) --aa;
-  while (aa < R - 1 && packed_index(aa + 1, aa + 1, R) <= p) ++aa;
-  a = aa;
-  b = aa + (int)(p - packed_index(aa, aa, R));
-}
-
 constexpr int S2 = 3;  // levels summed per upsweep pass
 
 // One thread per packed entry and per group of 2^S2 consecutive nodes of

@@ -24,7 +24,7 @@ def test_static_scratch_draws_equal_workspace_draws():
         dt = torch.float64 if prec == "fp64" else torch.float32
         S = krps.Sampler(ctx, [torch.from_numpy(U).to(dev).to(dt).contiguous() for U in Us],
                          precision=prec)
-        assert S.draw_ws.numel() <= 8 << 20
+        assert S.draw_ws.numel() <= 16 << 20
         u = torch.from_numpy(synth.uniforms(J, len(dims), 31 + J)).to(dev)
         idx = torch.full((J, len(dims)), -7, dtype=torch.int32, device=dev)
         prob = torch.zeros(J, dtype=torch.float64, device=dev)
@@ -43,9 +43,9 @@ def test_static_scratch_rejects_a_sampler_too_large():
     import paper_2301_12584_amd as krps
     ctx = krps.Context(0)
     Us = synth.gaussian_factors((400, 300, 200), 128, seed=3)
-    S = krps.Sampler(ctx, [torch.from_numpy(U).to(ctx.device).contiguous() for U in Us],
-                     precision="fp32")
-    assert S.draw_ws.numel() > 8 << 20
+    S = krps.Sampler(ctx, [torch.from_numpy(U).to(ctx.device).double().contiguous() for U in Us],
+                     precision="fp64")
+    assert S.draw_ws.numel() > 16 << 20
     u = torch.from_numpy(synth.uniforms(16, 3, 1)).to(ctx.device)
     idx = torch.empty((16, 3), dtype=torch.int32, device=ctx.device)
     with pytest.raises(krps.KrpsError) as e:
