@@ -340,7 +340,12 @@ def solve_floor(parts, prec, dims, R, J, j, nu):
     st["sampled Gram"] = floor_s(J * R * rs, 2.0 * J * R * R, mm)
     st["fiber lookup"] = floor_s(J * (N - 1) * 4 * int(np.ceil(np.log2(max(nu, 2)))) + J * N * 4
                                  + 2 * J * 8, 0, 1)
-    st["SpMM"] = floor_s(E * (4 + 8 + 2 * R * rs), 2.0 * E * R, F64_VALU_PEAK_TFS)
+    # each fiber entry's mode-j index and value once, every sampled row
+    # once, every touched row of Y written once: a read-modify-write of R
+    # values per entry is how a scatter-add spends traffic, not what the
+    # product needs
+    st["SpMM"] = floor_s(E * (4 + 4) + J * R * rs + nrows * R * rs, 2.0 * E * R,
+                         F64_VALU_PEAK_TFS)
     st["rows of Y"] = floor_s(E * 4 + 3 * I * 4 + nrows * R * rs, 0, 1)
     st["Y M+ and sigma"] = floor_s(nrows * R * rs + I * R * s + nrows * R * s,
                                    2.0 * nrows * R * R, F64_VALU_PEAK_TFS)

@@ -140,8 +140,11 @@ krps_status krps_sampler_destroy(krps_sampler s);
  * last check.  *zero_weight (may be NULL) receives the number of sampled
  * rows since the last check whose computed probability q_d was not
  * positive: q_d > 0 in exact arithmetic (Sec. 2.1), so only rounding can
- * do that; such a row was given weight 0 in its solve. */
-krps_status krps_sampler_check(krps_sampler s, int64_t* zero_weight);
+ * do that; such a row was given weight 0 in its solve.  *rewalked (may be
+ * NULL) receives the number of float64 walks (a sample and a drawn mode)
+ * since the last check that the float32 node copies could not decide and
+ * that were walked again from the float64 tree (krps_sampler_set_filter). */
+krps_status krps_sampler_check(krps_sampler s, int64_t* zero_weight, int64_t* rewalked);
 
 /* ------------------------------------------------------------------ */
 /* Sampling: Algorithm 2 (KRPSample)                                   */
@@ -411,6 +414,20 @@ typedef struct {
  * 4 or 8 for R <= 8, 8 or 16 for R <= 16, 16, 32 or 64 for R <= 32, 64
  * above).  The index and probability of every draw do not depend on it. */
 krps_status krps_sampler_set_lps(krps_sampler s, int lps);
+
+/* Float64 samplers keep a float32 copy of every factor-tree node (each
+ * entry rounded to nearest; it is built with the tree and held in the
+ * sampler workspace).  Below the top `top` levels of a tree, the walk of
+ * Algorithm 4 reads the copy -- half the bytes -- and takes a branch only
+ * when the float64 walk would take it for every value within the copy's
+ * rounding bound (the node mass's bound, 2^-24 relative per entry, and the
+ * running offset's, accumulated over the filtered levels); a sample whose
+ * branch or leaf row that bound cannot decide is walked again from the
+ * float64 nodes.  Every drawn index is therefore the float64 walk's.
+ * top = -1 selects the default (all but the ten deepest levels read the
+ * float64 nodes); top >= the tree depth turns the copy off.  No effect
+ * on float32 and split samplers.  Returns KRPS_EINVAL for top < -1. */
+krps_status krps_sampler_set_filter(krps_sampler s, int top);
 
 /* Bytes of workspace for krps_autotune (a sampler with the smallest leaf
  * size tried, its draw scratch and J outputs). */

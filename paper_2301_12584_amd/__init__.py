@@ -129,7 +129,8 @@ def lib():
         "krps_als_sweep": (c.c_int, [P, P, c.c_int64, P, P, P, c.c_size_t, c.c_int]),
         "krps_fit": (c.c_int, [P, P, P, c.POINTER(c.c_double), P, c.c_size_t]),
         "krps_sampler_tree_info": (c.c_int, [P, c.c_int, c.POINTER(TreeInfo)]),
-        "krps_sampler_check": (c.c_int, [P, c.POINTER(c.c_int64)]),
+        "krps_sampler_check": (c.c_int, [P, c.POINTER(c.c_int64), c.POINTER(c.c_int64)]),
+        "krps_sampler_set_filter": (c.c_int, [P, c.c_int]),
         "krps_sample_static": (c.c_int, [P, c.c_int, c.c_int64, P, P, P, P]),
         "krps_exact_solve": (c.c_int, [P, P, c.c_int, P, P, c.c_size_t]),
         "krps_measure_peaks": (c.c_int, [P, P, c.c_size_t, c.POINTER(Peaks)]),
@@ -255,10 +256,19 @@ class Sampler:
     def check_status(self):
         """Reads and clears the device status (raises on a zero product or a
         non-finite value); returns the number of sampled rows since the last
-        check whose computed probability was not positive."""
-        n = ctypes.c_int64()
-        check(lib().krps_sampler_check(self.handle, ctypes.byref(n)))
+        check whose computed probability was not positive.  The number of
+        float64 walks re-walked from the float64 tree since the last check
+        is left in ``self.rewalked``."""
+        n, r = ctypes.c_int64(), ctypes.c_int64()
+        check(lib().krps_sampler_check(self.handle, ctypes.byref(n), ctypes.byref(r)))
+        self.rewalked = r.value
         return n.value
+
+    def set_filter(self, top):
+        """Levels of each factor tree the float64 walk reads from the
+        float64 nodes before it decides from their float32 copy (-1: the
+        default; >= the depth: the copy is not used)."""
+        check(lib().krps_sampler_set_filter(self.handle, int(top)))
 
     def sample(self, exclude, uniforms, prob=True, rows=False, check_status=False):
         """Draws ``J = uniforms.shape[0]`` samples; returns ``(idx, prob, rows)``."""

@@ -194,6 +194,71 @@ __device__ __forceinline__ double node_mass(const Packed<64, 0>&, const double* 
   return group_sum<64>(acc);
 }
 
+// The same mass from the float32 copy g32 of a float64 node g64, with
+// s = sum_p |P_p g32_p|.  Rounding to nearest gives |g64 - g32| <=
+// 2^-24 |g64| (plus 2^-126 where the copy lost range), so the float64 node's
+// exact mass is within 2^-24 / (1 - 2^-24) s + 2^-125 sum_p |P_p| of m; the
+// float64 sums on either side add a few ulps of s, which the margin below
+// (6.0e-8 > 5.9605e-8) covers.
+struct MassB {
+  double m, s;
+};
+
+template <int LPS, int NP>
+__device__ __forceinline__ MassB node_mass32(const Packed<LPS, NP>& P, const double*,
+                                             const float* __restrict__ node, int TR, int sl,
+                                             const uint16_t* __restrict__ = nullptr) {
+  const int npr = (TR + LPS - 1) / LPS;
+  float g[NP];
+  if (npr >= NP) {
+#pragma unroll
+    for (int m = 0; m < NP; ++m) g[m] = node[sl + LPS * m];
+  } else {
+#pragma unroll
+    for (int m = 0; m < NP; ++m) g[m] = m < npr ? node[sl + LPS * m] : 0.f;
+  }
+  double acc[4] = {0.0, 0.0, 0.0, 0.0}, sab[2] = {0.0, 0.0};
+#pragma unroll
+  for (int m = 0; m < NP; ++m) {
+    const double t = P.v[m] * (double)g[m];
+    acc[m & 3] += t;
+    sab[m & 1] += fabs(t);
+  }
+  return {group_sum<LPS>((acc[0] + acc[1]) + (acc[2] + acc[3])), group_sum<LPS>(sab[0] + sab[1])};
+}
+
+__device__ __forceinline__ MassB node_mass32(const Packed<64, 0>&, const double* hb,
+                                             const float* __restrict__ node, int TR, int lane,
+                                             const uint16_t* __restrict__ tab) {
+  double acc = 0, sab = 0;
+  const int npr = (TR + 63) / 64;
+  for (int m0 = 0; m0 < npr; m0 += 8) {
+    float g[8];
+    uint16_t ab[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const int p = lane + 64 * (m0 + q);
+      const int pc = p < TR ? p : TR - 1;
+      g[q] = node[pc];
+      ab[q] = tab[pc];
+    }
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const int p = lane + 64 * (m0 + q);
+      const int a = ab[q] & 0xff, b = ab[q] >> 8;
+      const double w = p < TR ? (a != b ? 2.0 : 1.0) : 0.0;
+      const double t = w * hb[a] * hb[b] * (double)g[q];
+      acc += t;
+      sab += fabs(t);
+    }
+  }
+  return {group_sum<64>(acc), group_sum<64>(sab)};
+}
+
+constexpr double F32_COPY_REL = 6.0e-8;  // >= 2^-24 / (1 - 2^-24) + float64 sums
+constexpr double F32_COPY_ABS = 0x1p-124;  // per unit of sum_p |P_p| (range loss)
+constexpr double ADD_SLACK = 1e-15;       // float64 additions of the offsets, relative
+
 // Inversion walk down a stored tree (root + left children) for each group's
 // sample: returns the leaf position and the offset `low` of its segment.
 // All groups of a wavefront walk the same tree, so the loop is uniform and
@@ -223,6 +288,73 @@ __device__ __forceinline__ int64_t walk(const T* __restrict__ nodes, int64_t L, 
     off += cnt_left;
   }
   low_out = low;
+  return pos;
+}
+
+// The walk of `walk` over a float64 tree whose levels below `top` are
+// decided from its float32 copy.  It tracks approximations lowA, highA of
+// the offsets the float64 walk would hold, with |low - lowA| and
+// |high - highA| <= B; a level is decided only if the float64 walk's
+// comparison has the same outcome for every mass and offset within the
+// bounds (left: x <= cut - E; right: x > cut + E and high - cut > 0 for
+// sure), else the walk is marked undecided (`amb`) and goes on left, and
+// the caller walks that sample again from the float64 tree.  Levels up to
+// `top` read the float64 nodes, with the float64 walk's own arithmetic, so
+// that B stays 0 there.  sP = sum_p |P_p| = (sum_a |h_a|)^2.
+template <int LPS, int NP>
+__device__ __forceinline__ int64_t walk_filtered(const double* __restrict__ nodes,
+                                                 const float* __restrict__ nodes32, int64_t L,
+                                                 int D, int top, const Packed<LPS, NP>& P,
+                                                 const double* hb, int R, int TR, int sl, double x,
+                                                 double C, double sP, double& low_out,
+                                                 double& bound_out, bool& amb,
+                                                 const uint16_t* __restrict__ tab) {
+  double low = 0.0, high = C, B = 0.0;
+  int64_t pos = 0;
+  int64_t off = 1;
+  amb = false;
+  for (int lev = 1; lev <= D; ++lev) {
+    const int64_t cnt_left = ((L - 1) >> (D - lev + 1)) + 1;
+    const int64_t real = ((L - 1) >> (D - lev)) + 1;
+    const bool right_exists = 2 * pos + 1 < real;
+    const int64_t at = (off + pos) * (int64_t)TR;
+    bool left;
+    double cut;
+    if (lev <= top) {
+      double mL = node_mass<double>(P, hb, nodes + at, R, TR, sl, tab);
+      mL = mL > 0.0 ? mL : 0.0;
+      cut = low + mL;
+      left = cut >= x || !right_exists || high - cut <= 0.0;
+    } else {
+      const MassB mb = node_mass32(P, hb, nodes32 + at, TR, sl, tab);
+      const double mL = mb.m > 0.0 ? mb.m : 0.0;
+      cut = low + mL;
+      // bound on |cut64 - cut|: the offset's, the mass's (the clamp at 0 is
+      // monotone, so it only shrinks it) and the two additions' rounding
+      const double beta = F32_COPY_REL * mb.s + F32_COPY_ABS * sP;
+      const double E = (B + beta) * (1.0 + 1e-12) + ADD_SLACK * (fabs(cut) + fabs(x));
+      if (!(E <= __DBL_MAX__)) amb = true;  // non-finite copy or bound
+      if (!right_exists || x <= cut - E) {
+        left = true;
+      } else if (x > cut + E && (high - B) - (cut + E) > ADD_SLACK * fabs(high)) {
+        left = false;
+      } else {
+        amb = true;
+        left = true;
+      }
+      B = E;
+    }
+    if (left) {
+      high = cut;
+      pos = 2 * pos;
+    } else {
+      low = cut;
+      pos = 2 * pos + 1;
+    }
+    off += cnt_left;
+  }
+  low_out = low;
+  bound_out = B;
   return pos;
 }
 
@@ -334,6 +466,64 @@ __device__ __forceinline__ int64_t leaf_scan(const T* __restrict__ U, int R, int
   return last_pos >= 0 ? last_pos : s1 - 1;
 }
 
+// `leaf_scan` with the offset known only as lowA, |low - lowA| <= B (from
+// walk_filtered): row i is a sure hit if lowA + incl_i - E >= x, a sure
+// miss if lowA + incl_i + E < x; the scan's answer is decided if a sure hit
+// comes before every unsure row, or if every row is a sure miss (then the
+// float64 scan's fallback rule, which does not read the offset, applies).
+// Otherwise `amb` is set.
+template <int LPS, int RMAX, typename T>
+__device__ __forceinline__ int64_t leaf_scan_filtered(const T* __restrict__ U, int R, int64_t s0,
+                                                      int64_t s1, int nchunk, const double* hb,
+                                                      double low, double B, double x, int sl,
+                                                      int sub, bool& amb) {
+  const unsigned long long gmask = LPS == 64 ? ~0ull : ((1ull << LPS) - 1ull);
+  int64_t found = -1, last_pos = -1;
+  bool undecided = false;
+  for (int ch = 0; ch < nchunk; ++ch) {
+    asm volatile("" ::: "memory");
+    const int64_t base = s0 + (int64_t)ch * LPS;
+    const int64_t row = base + sl;
+    const bool valid = row < s1;
+    const double acc = row_dot<RMAX>(U + (valid ? row : s1 - 1) * R, hb, R);
+    const double r = valid ? acc * acc : 0.0;
+    const double incl = group_inclusive_scan<LPS>(r, sl);
+    const double v = low + incl;
+    const double E = B * (1.0 + 1e-12) + ADD_SLACK * (fabs(v) + fabs(x));
+    const bool sure = valid && v - E >= x;
+    const bool unsure = valid && !sure && v + E >= x;
+    const unsigned long long ms = (__ballot(sure) >> (sub * LPS)) & gmask;
+    const unsigned long long mu = (__ballot(unsure) >> (sub * LPS)) & gmask;
+    if (found < 0 && !undecided) {
+      // the first row that may hit decides: a sure hit, or an unsure row
+      const unsigned long long any = ms | mu;
+      if (any != 0ull) {
+        const int f = __ffsll((long long)any) - 1;
+        if ((ms >> f) & 1ull)
+          found = base + f;
+        else
+          undecided = true;
+      }
+    }
+    const unsigned long long pm = (__ballot(valid && r > 0.0) >> (sub * LPS)) & gmask;
+    if (pm != 0ull) last_pos = base + (63 - __clzll((long long)pm));
+    double tot;
+    if constexpr (LPS == 64) {
+      tot = lane_value<63>(incl);
+    } else if constexpr (LPS == 32) {
+      const double t0 = lane_value<31>(incl), t1 = lane_value<63>(incl);
+      tot = sub ? t1 : t0;
+    } else {
+      tot = __shfl(incl, LPS - 1, LPS);
+    }
+    low += tot;
+    B = B * (1.0 + 1e-12) + ADD_SLACK * fabs(low);
+  }
+  amb = undecided;
+  if (found >= 0) return found;
+  return last_pos >= 0 ? last_pos : s1 - 1;
+}
+
 // The walk of the samples base + (lane group) of one wavefront: 64 / LPS
 // samples at once, LPS lanes per sample.  `tab` maps packed entry p to its
 // (a, b) pair (LDS or global); `hb` is this group's RMAX doubles of LDS.
@@ -417,25 +607,60 @@ __device__ __forceinline__ void descend(const DescentArgs& a, int64_t base,
     if constexpr (NP > 0)
       if (!(st == 0 && md.zt != nullptr)) build_packed(P, hb, tab, TR, sl);
     const T* __restrict__ Z = (const T*)md.Z;
+    const T* __restrict__ U = (const T*)md.U;
+    const int nchunk = (md.F + LPS - 1) / LPS;
     double C2, x2;
-    int64_t c;
+    int64_t t;
     if (st == 0 && md.zt != nullptr) {
       // first drawn mode: the node masses for h~ = V[:, u] were tabulated
       // by the preparation; the walk reads one float64 per level
       const double* __restrict__ zt = md.zt + (int64_t)u * md.zn;
       C2 = zt[0];
       x2 = d2 * C2;
-      c = walk_table(zt, md.L, md.D, x2, C2, low);
+      const int64_t c = walk_table(zt, md.L, md.D, x2, C2, low);
+      const int64_t s0 = c * md.F;
+      t = leaf_scan<LPS, RMAX>(U, R, s0, s0 + md.F < md.I ? s0 + md.F : md.I, nchunk, hb, low, x2,
+                               sl, sub);
     } else {
       C2 = node_mass<T>(P, hb, Z, R, TR, sl, tab);
       x2 = d2 * C2;
-      c = walk(Z, md.L, md.D, P, hb, R, TR, sl, x2, C2, low, tab);
+      bool plain = true;
+      if constexpr (std::is_same_v<T, double>) {
+        if (md.z32 != nullptr) {
+          // deep levels from the float32 copy; undecided samples (rare:
+          // a target within the copy's error of a cut) walk again below
+          double sh = 0.0;
+#pragma unroll
+          for (int i = 0; i < HE; ++i)
+            if (sl + LPS * i < R) sh += fabs(ht[i]);
+          sh = group_sum<LPS>(sh);
+          const double sP = 2.0 * sh * sh;
+          double B;
+          bool amb_w, amb_l;
+          const int64_t c = walk_filtered(Z, md.z32, md.L, md.D, md.ztop, P, hb, R, TR, sl, x2,
+                                          C2, sP, low, B, amb_w, tab);
+          const int64_t s0 = c * md.F;
+          t = leaf_scan_filtered<LPS, RMAX>(U, R, s0, s0 + md.F < md.I ? s0 + md.F : md.I, nchunk,
+                                            hb, low, B, x2, sl, sub, amb_l);
+          const bool amb = active && (amb_w || amb_l);
+          plain = false;
+          if (__ballot(amb) != 0ull) {
+            const int64_t c2 = walk(Z, md.L, md.D, P, hb, R, TR, sl, x2, C2, low, tab);
+            const int64_t s2 = c2 * md.F;
+            const int64_t t2 = leaf_scan<LPS, RMAX>(
+                U, R, s2, s2 + md.F < md.I ? s2 + md.F : md.I, nchunk, hb, low, x2, sl, sub);
+            if (amb) t = t2;
+            if (amb && sl == 0) atomicAdd(a.status + 2, 1);
+          }
+        }
+      }
+      if (plain) {
+        const int64_t c = walk(Z, md.L, md.D, P, hb, R, TR, sl, x2, C2, low, tab);
+        const int64_t s0 = c * md.F;
+        t = leaf_scan<LPS, RMAX>(U, R, s0, s0 + md.F < md.I ? s0 + md.F : md.I, nchunk, hb, low,
+                                 x2, sl, sub);
+      }
     }
-    const int64_t s0 = c * md.F;
-    const int64_t s1 = s0 + md.F < md.I ? s0 + md.F : md.I;
-    const T* __restrict__ U = (const T*)md.U;
-    const int nchunk = (md.F + LPS - 1) / LPS;
-    int64_t t = leaf_scan<LPS, RMAX>(U, R, s0, s1, nchunk, hb, low, x2, sl, sub);
     if (t < 0) t = 0;
     if (t >= md.I) t = md.I - 1;
     if (sl == 0 && active) a.idx[d * N + k] = (int32_t)t;

@@ -50,11 +50,11 @@ struct GraphKey {
   const void* sigma = nullptr;
   const void* ws = nullptr;
   int64_t J = -1;
-  int lps = -1;
+  int lps = -1, filter = -2;
   uint64_t seed = 0, ctr_base = 0;
   bool operator==(const GraphKey& o) const {
     return t == o.t && uniforms == o.uniforms && sigma == o.sigma && ws == o.ws && J == o.J &&
-           lps == o.lps && seed == o.seed && ctr_base == o.ctr_base;
+           lps == o.lps && filter == o.filter && seed == o.seed && ctr_base == o.ctr_base;
   }
 };
 
@@ -67,6 +67,8 @@ struct krps_sampler_s {
   std::vector<void*> U;
   std::vector<TreeShape> shape;
   std::vector<void*> nodes;
+  std::vector<float*> nodes32;         // float32 copies of float64 trees (else null)
+  int filter_top = -1;                 // levels read from the float64 tree (-1: default)
   std::vector<double*> gram;
   double* scratch;
   size_t scratch_bytes;
@@ -136,7 +138,7 @@ krps_status check_dims(int N, const int64_t* I, int R) {
 
 struct SamplerPlan {
   std::vector<TreeShape> shape;
-  std::vector<size_t> node_off, gram_off;
+  std::vector<size_t> node_off, node32_off, gram_off;
   size_t scratch_off = 0, scratch_bytes = 0, status_off = 0, total = 0;
 };
 
@@ -151,6 +153,9 @@ SamplerPlan plan_sampler(int N, const int64_t* I, int R, int F, krps_precision p
     pl.shape.push_back(ts);
     pl.node_off.push_back(off);
     off += align_up((size_t)(ts.n_nodes * TR + NODE_SLACK) * elem_bytes(p));
+    // float64 trees: a float32 copy of the nodes for the walk's deep levels
+    pl.node32_off.push_back(p == KRPS_FP64 ? off : 0);
+    if (p == KRPS_FP64) off += align_up((size_t)(ts.n_nodes * TR + NODE_SLACK) * 4);
     pl.gram_off.push_back(off);
     off += align_up((size_t)R * R * 8);
     const size_t sb = tree_build_scratch_bytes(ts.L, R);
@@ -214,12 +219,26 @@ size_t gpacked_off(krps_sampler s) { return s->lay.gplus + align_up((size_t)s->R
 
 krps_status build_tree(krps_sampler s, int j) {
   hipError_t e = launch_tree_build(s->ctx->stream, s->prec, s->U[j], s->I[j], s->R, s->shape[j],
-                                   s->nodes[j], s->gram[j], s->scratch, s->scratch_bytes);
+                                   s->nodes[j], s->gram[j], s->scratch, s->scratch_bytes, 2,
+                                   s->nodes32[j]);
   if (e != hipSuccess) return hip_fail(e, "tree build launch");
   return KRPS_OK;
 }
 
 void fill_descent_args(krps_sampler s, int exclude, void* ws, DescentArgs& a);
+
+// Levels of factor k's tree that the walk decides from the float64 nodes
+// before it turns to their float32 copy (>= D: the copy is not used).  The
+// default keeps the top D - 10 levels, which the caches hold anyway, and
+// filters the ten deepest, where the bytes are; each filtered level adds
+// its float32 error to the running offset, so that deeper filtering makes
+// undecided (re-walked) samples more frequent.
+int walk_filter_top(krps_sampler s, int k) {
+  const int D = s->shape[k].D;
+  if (s->nodes32[k] == nullptr) return D;
+  if (s->filter_top >= 0) return std::min(s->filter_top, D);
+  return std::max(D - 10, 0);
+}
 
 // Enqueues the set-up part of Algorithm 2 (before its per-sample loop) for exclusion `exclude` into ws and
 // fills the descent arguments.
@@ -286,6 +305,9 @@ void fill_descent_args(krps_sampler s, int exclude, void* ws, DescentArgs& a) {
     m.em = (const double*)(w + s->emass_off) + (size_t)k * s->enodes;
     m.zt = s->znmax > 0 ? (const double*)(w + s->ztab_off) : nullptr;
     m.zn = s->shape[k].n_nodes;
+    const int top = walk_filter_top(s, k);
+    m.z32 = top < s->shape[k].D ? s->nodes32[k] : nullptr;
+    m.ztop = top;
     m.I = s->I[k];
     m.L = s->shape[k].L;
     m.F = s->shape[k].F;
@@ -669,8 +691,8 @@ krps_status sweep_entry(krps_sampler s, krps_tensor t, int64_t J, const double* 
     return st;
   }
   // the captured graph is keyed by everything its kernels' arguments hold
-  const GraphKey key{t, uniforms, sigma, ws, J, s->lps, seeded ? seed : 0,
-                     seeded ? ctr_base : 0};
+  const GraphKey key{t,         uniforms,          sigma, ws, J, s->lps, s->filter_top,
+                     seeded ? seed : 0, seeded ? ctr_base : 0};
   if (s->sweep_exec == nullptr || !(s->gkey == key)) {
     if (s->sweep_exec != nullptr) {
       (void)hipGraphExecDestroy(s->sweep_exec);
@@ -790,6 +812,7 @@ krps_status krps_sampler_create(krps_ctx ctx, int N, const int64_t* I, int R, in
     s->U.push_back(U[j]);
     s->shape.push_back(pl.shape[j]);
     s->nodes.push_back(w + pl.node_off[j]);
+    s->nodes32.push_back(p == KRPS_FP64 ? (float*)(w + pl.node32_off[j]) : nullptr);
     s->gram.push_back((double*)(w + pl.gram_off[j]));
   }
   s->scratch = (double*)(w + pl.scratch_off);
@@ -801,10 +824,14 @@ krps_status krps_sampler_create(krps_ctx ctx, int N, const int64_t* I, int R, in
     delete s;
     return hip_fail(e, "hipSetDevice");
   }
-  e = hipMemsetAsync(s->status, 0, 8, ctx->stream);
-  for (int j = 0; j < N && e == hipSuccess; ++j)
+  e = hipMemsetAsync(s->status, 0, 12, ctx->stream);
+  for (int j = 0; j < N && e == hipSuccess; ++j) {
     e = launch_fill(ctx->stream, p, (char*)s->nodes[j] + (size_t)pl.shape[j].n_nodes * tri(R) * s->elem,
                     NODE_SLACK);
+    if (e == hipSuccess && s->nodes32[j] != nullptr)
+      e = launch_fill(ctx->stream, KRPS_FP32, s->nodes32[j] + pl.shape[j].n_nodes * tri(R),
+                      NODE_SLACK);
+  }
   if (e != hipSuccess) {
     delete s;
     return hip_fail(e, "status and padding clear");
@@ -832,18 +859,26 @@ krps_status krps_sampler_destroy(krps_sampler s) {
   return KRPS_OK;
 }
 
-krps_status krps_sampler_check(krps_sampler s, int64_t* zero_weight) {
+krps_status krps_sampler_check(krps_sampler s, int64_t* zero_weight, int64_t* rewalked) {
   if (s == nullptr) return fail(KRPS_EINVAL, "sampler is NULL");
   KRPS_HIP(hipSetDevice(s->ctx->device));
-  int32_t words[2] = {0, 0};
-  KRPS_HIP(hipMemcpyAsync(words, s->status, 8, hipMemcpyDeviceToHost, s->ctx->stream));
+  int32_t words[3] = {0, 0, 0};
+  KRPS_HIP(hipMemcpyAsync(words, s->status, 12, hipMemcpyDeviceToHost, s->ctx->stream));
   KRPS_HIP(hipStreamSynchronize(s->ctx->stream));
-  KRPS_HIP(hipMemsetAsync(s->status, 0, 8, s->ctx->stream));
+  KRPS_HIP(hipMemsetAsync(s->status, 0, 12, s->ctx->stream));
   if (zero_weight != nullptr) *zero_weight = words[1];
+  if (rewalked != nullptr) *rewalked = words[2];
   if (words[0] & ST_ZERO) return fail(KRPS_EZERO, "the Khatri-Rao product is zero");
   if (words[0] & ST_NUMERIC)
     return fail(KRPS_ENUMERIC, "a non-finite value or a non-positive mass was met (a draw's "
                                "masses, or a solve's sampled Gram)");
+  return KRPS_OK;
+}
+
+krps_status krps_sampler_set_filter(krps_sampler s, int top) {
+  if (s == nullptr) return fail(KRPS_EINVAL, "sampler is NULL");
+  if (top < -1) return fail(KRPS_EINVAL, "top must be >= -1");
+  s->filter_top = top;
   return KRPS_OK;
 }
 
@@ -1936,8 +1971,14 @@ krps_status krps_workspace_regions(int N, const int64_t* I, int R, int F, krps_p
   for (int j = 0; j < N; ++j) {
     char nm[32];
     snprintf(nm, sizeof(nm), "tree %d", j);
-    rl.add(0, nm, sp.node_off[j], span(sp.node_off[j], sp.gram_off[j]),
+    const size_t nend = p == KRPS_FP64 ? sp.node32_off[j] : sp.gram_off[j];
+    rl.add(0, nm, sp.node_off[j], span(sp.node_off[j], nend),
            (size_t)(sp.shape[j].n_nodes * TR + overread) * es);
+    if (p == KRPS_FP64) {
+      snprintf(nm, sizeof(nm), "tree %d float32 copy", j);
+      rl.add(0, nm, sp.node32_off[j], span(sp.node32_off[j], sp.gram_off[j]),
+             (size_t)(sp.shape[j].n_nodes * TR + overread) * 4);
+    }
     snprintf(nm, sizeof(nm), "gram %d", j);
     const size_t gnext = j + 1 < N ? sp.node_off[j + 1] : sp.scratch_off;
     rl.add(0, nm, sp.gram_off[j], span(sp.gram_off[j], gnext), (size_t)R * R * 8);
@@ -1945,7 +1986,7 @@ krps_status krps_workspace_regions(int N, const int64_t* I, int R, int F, krps_p
   size_t bext = 0;
   for (int j = 0; j < N; ++j) bext = std::max(bext, tree_build_scratch_extent(sp.shape[j], R));
   rl.add(0, "build scratch", sp.scratch_off, span(sp.scratch_off, sp.status_off), bext);
-  rl.add(0, "status", sp.status_off, span(sp.status_off, sp.total), 8);
+  rl.add(0, "status", sp.status_off, span(sp.status_off, sp.total), 12);
   // --- per-draw workspace (a host-side sampler with the same shape)
   krps_sampler_s tmp;
   tmp.N = N;

@@ -61,6 +61,8 @@ struct ModeDesc {
   const double* zt;   // [R][zn] masses of Z's stored nodes for h~ = V[:, u]
                       // (per draw; first drawn mode only) or null
   int64_t zn;         // stored nodes of Z (the table's row length)
+  const float* z32;   // float32 copy of a float64 Z (same layout), or null
+  int32_t ztop;       // with z32: levels 1..ztop are decided from Z itself
   int64_t I, L;
   int32_t F, D;
   int32_t DE, ne;     // eigen-tree depth and stored nodes
@@ -191,9 +193,11 @@ struct FitArgs {
   const double* sigma;
 };
 
-// Status words of a sampler (int32 [2], cleared at creation): word 0 holds
+// Status words of a sampler (int32 [3], cleared at creation): word 0 holds
 // flag bits set by kernels, word 1 counts sampled rows whose computed
-// probability was not positive (rounding; they were given weight 0).
+// probability was not positive (rounding; they were given weight 0), word 2
+// counts walks whose float32-copy decisions were not certain and that were
+// walked again from the float64 tree.
 enum : int32_t { ST_ZERO = 1, ST_NUMERIC = 2 };
 
 // ------------------------------------------------------------- launchers
@@ -203,7 +207,8 @@ size_t tree_build_scratch_bytes(int64_t L, int R);
 size_t tree_build_scratch_extent(const TreeShape& ts, int R);
 hipError_t launch_tree_build(hipStream_t st, krps_precision p, const void* U, int64_t I, int R,
                              const TreeShape& ts, void* nodes, double* gram_full,
-                             double* scratch, size_t scratch_bytes, int split_terms = 2);
+                             double* scratch, size_t scratch_bytes, int split_terms = 2,
+                             float* nodes32 = nullptr);
 
 // eig.hip
 size_t prep_lds_bytes(int R);

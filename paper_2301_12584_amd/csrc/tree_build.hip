@@ -16,6 +16,9 @@
 // Kernel 2 (node_upsweep_kernel): the levels above the runs, one thread per
 // packed entry, the same binary counter over groups of 2^s2 nodes in float64,
 // down to the root (also written as the full float64 R x R Gram G_j).
+// A float64 tree may also get a float32 copy of every stored node (each
+// entry rounded to nearest), written by both kernels beside the float64
+// node: the walk decides its deep levels from the copy.
 #include "device_common.h"
 #include <algorithm>
 
@@ -59,7 +62,8 @@ template <int MODE, int NT, int TW, int S, int W>
 __device__ __forceinline__ void leaf_run_body(const void* __restrict__ Uv, int64_t I, int R, int F,
                                               int64_t L, int D, int s_eff,
                                               void* __restrict__ nodes_v,
-                                              double* __restrict__ tops) {
+                                              double* __restrict__ tops,
+                                              float* __restrict__ nodes32) {
   // storage type of the factor and the nodes; float64 accumulation on the
   // matrix cores except for the bf16 split
   using T = std::conditional_t<MODE == M_F64, double, float>;
@@ -199,11 +203,19 @@ __device__ __forceinline__ void leaf_run_body(const void* __restrict__ Uv, int64
       });
     } else {
       if (nodes != nullptr && pos < ((L - 1) >> (D - lev)) + 1) {
-        T* dst = nodes + (level_offset(L, D, lev) + (pos >> 1)) * TR;
+        const int64_t at = (level_offset(L, D, lev) + (pos >> 1)) * TR;
         static_for<0, NPAIRS>([&](auto pp) {
           constexpr int pr = decltype(pp)::value;
-          if constexpr (pr % TW == W) write_tile(dst, node[pr / TW], pair_ta(NT, pr), pair_tb(NT, pr), R, lane);
+          if constexpr (pr % TW == W) write_tile(nodes + at, node[pr / TW], pair_ta(NT, pr), pair_tb(NT, pr), R, lane);
         });
+        if constexpr (MODE == M_F64) {
+          if (nodes32 != nullptr) {
+            static_for<0, NPAIRS>([&](auto pp) {
+              constexpr int pr = decltype(pp)::value;
+              if constexpr (pr % TW == W) write_tile(nodes32 + at, node[pr / TW], pair_ta(NT, pr), pair_tb(NT, pr), R, lane);
+            });
+          }
+        }
       }
       static_for<0, S>([&](auto mm) {
         constexpr int m = decltype(mm)::value;
@@ -220,11 +232,13 @@ template <int MODE, int NT, int TW, int S>
 __global__ __launch_bounds__(64 * TW) void leaf_run_kernel(const void* __restrict__ Uv, int64_t I,
                                                            int R, int F, int64_t L, int D,
                                                            int s_eff, void* __restrict__ nodes_v,
-                                                           double* __restrict__ tops) {
+                                                           double* __restrict__ tops,
+                                                           float* __restrict__ nodes32) {
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   static_for<0, TW>([&](auto ww) {
     constexpr int W = decltype(ww)::value;
-    if (wave == W) leaf_run_body<MODE, NT, TW, S, W>(Uv, I, R, F, L, D, s_eff, nodes_v, tops);
+    if (wave == W)
+      leaf_run_body<MODE, NT, TW, S, W>(Uv, I, R, F, L, D, s_eff, nodes_v, tops, nodes32);
   });
 }
 
@@ -238,7 +252,8 @@ __global__ __launch_bounds__(256) void node_upsweep_kernel(const double* __restr
                                                            int64_t n_in, int lev_in, int s2, int R,
                                                            int64_t L, int D, T* __restrict__ nodes,
                                                            double* __restrict__ out,
-                                                           double* __restrict__ gram_full) {
+                                                           double* __restrict__ gram_full,
+                                                           float* __restrict__ nodes32) {
   const int64_t TR = (int64_t)R * (R + 1) / 2;
   const int64_t ng = (n_in + (int64_t(1) << s2) - 1) >> s2;
   const int64_t total = ng * TR;
@@ -262,6 +277,7 @@ __global__ __launch_bounds__(256) void node_upsweep_kernel(const double* __restr
       if (t == s2) {
         if (lev == 0) {
           if (nodes != nullptr) nodes[p] = (T)v;
+          if (nodes32 != nullptr) nodes32[p] = (float)v;
           int a, b;
           unpack_index(p, R, a, b);
           gram_full[(int64_t)a * R + b] = v;
@@ -270,8 +286,11 @@ __global__ __launch_bounds__(256) void node_upsweep_kernel(const double* __restr
           out[g * TR + p] = v;
         }
       } else {
-        if (nodes != nullptr && pos < ((L - 1) >> (D - lev)) + 1)
-          nodes[(level_offset(L, D, lev) + (pos >> 1)) * TR + p] = (T)v;
+        if (nodes != nullptr && pos < ((L - 1) >> (D - lev)) + 1) {
+          const int64_t at = (level_offset(L, D, lev) + (pos >> 1)) * TR + p;
+          nodes[at] = (T)v;
+          if (nodes32 != nullptr) nodes32[at] = (float)v;
+        }
 #pragma unroll
         for (int m = 0; m < S2; ++m)
           if (m == t) stack[m] = v;
@@ -290,31 +309,31 @@ int leaf_run_depth(int R) { return R <= 32 ? 4 : R <= 64 ? 3 : 2; }
 
 template <int MODE, int NT, int TW, int S>
 hipError_t run_leaf(hipStream_t st, const void* U, int64_t I, int R, int F, int64_t L, int D,
-                    void* nodes, double* tops, int& s_eff) {
+                    void* nodes, double* tops, float* nodes32, int& s_eff) {
   if (S != leaf_run_depth(R)) return hipErrorInvalidValue;
   s_eff = S < D ? S : D;
   const int64_t nrun = ceil_div(L, int64_t(1) << s_eff);
   hipLaunchKernelGGL((leaf_run_kernel<MODE, NT, TW, S>), dim3((unsigned)nrun), dim3(64 * TW), 0,
-                     st, U, I, R, F, L, D, s_eff, nodes, tops);
+                     st, U, I, R, F, L, D, s_eff, nodes, tops, nodes32);
   return hipGetLastError();
 }
 
 // Team shape and register-run depth per precision and tile count.
 template <int MODE>
 hipError_t dispatch_leaf(hipStream_t st, const void* U, int64_t I, int R, int F, int64_t L, int D,
-                         void* nodes, double* tops, int& s_eff) {
+                         void* nodes, double* tops, float* nodes32, int& s_eff) {
   if constexpr (MODE == M_SPLIT || MODE == M_SPLIT3) {
-    if (R <= 16) return run_leaf<MODE, 1, 1, 4>(st, U, I, R, F, L, D, nodes, tops, s_eff);
-    if (R <= 32) return run_leaf<MODE, 2, 1, 4>(st, U, I, R, F, L, D, nodes, tops, s_eff);
-    if (R <= 64) return run_leaf<MODE, 4, 2, 3>(st, U, I, R, F, L, D, nodes, tops, s_eff);
-    return run_leaf<MODE, 8, 4, 2>(st, U, I, R, F, L, D, nodes, tops, s_eff);
+    if (R <= 16) return run_leaf<MODE, 1, 1, 4>(st, U, I, R, F, L, D, nodes, tops, nodes32, s_eff);
+    if (R <= 32) return run_leaf<MODE, 2, 1, 4>(st, U, I, R, F, L, D, nodes, tops, nodes32, s_eff);
+    if (R <= 64) return run_leaf<MODE, 4, 2, 3>(st, U, I, R, F, L, D, nodes, tops, nodes32, s_eff);
+    return run_leaf<MODE, 8, 4, 2>(st, U, I, R, F, L, D, nodes, tops, nodes32, s_eff);
   } else {
     // one or two float64 accumulator tiles per wave keep the register run
     // (binary-counter stack) small enough for several waves per SIMD
-    if (R <= 16) return run_leaf<MODE, 1, 1, 4>(st, U, I, R, F, L, D, nodes, tops, s_eff);
-    if (R <= 32) return run_leaf<MODE, 2, 3, 4>(st, U, I, R, F, L, D, nodes, tops, s_eff);
-    if (R <= 64) return run_leaf<MODE, 4, 5, 3>(st, U, I, R, F, L, D, nodes, tops, s_eff);
-    return run_leaf<MODE, 8, 12, 2>(st, U, I, R, F, L, D, nodes, tops, s_eff);
+    if (R <= 16) return run_leaf<MODE, 1, 1, 4>(st, U, I, R, F, L, D, nodes, tops, nodes32, s_eff);
+    if (R <= 32) return run_leaf<MODE, 2, 3, 4>(st, U, I, R, F, L, D, nodes, tops, nodes32, s_eff);
+    if (R <= 64) return run_leaf<MODE, 4, 5, 3>(st, U, I, R, F, L, D, nodes, tops, nodes32, s_eff);
+    return run_leaf<MODE, 8, 12, 2>(st, U, I, R, F, L, D, nodes, tops, nodes32, s_eff);
   }
 }
 
@@ -357,8 +376,9 @@ size_t tree_build_scratch_extent(const TreeShape& ts, int R) {
 
 hipError_t launch_tree_build(hipStream_t st, krps_precision p, const void* U, int64_t I, int R,
                              const TreeShape& ts, void* nodes, double* gram_full, double* scratch,
-                             size_t scratch_bytes, int split_terms) {
+                             size_t scratch_bytes, int split_terms, float* nodes32) {
   const int64_t TR = tri(R);
+  if (p != KRPS_FP64) nodes32 = nullptr;  // only float64 trees carry a float32 copy
   const int64_t a_nodes = ceil_div(ts.L, int64_t(1) << MIN_S);
   double* bufA = scratch;
   double* bufB = (double*)((char*)scratch + align_up((size_t)a_nodes * TR * 8));
@@ -366,13 +386,13 @@ hipError_t launch_tree_build(hipStream_t st, krps_precision p, const void* U, in
   int s_eff = 0;
   hipError_t e;
   if (p == KRPS_FP64)
-    e = dispatch_leaf<M_F64>(st, U, I, R, ts.F, ts.L, ts.D, nodes, bufA, s_eff);
+    e = dispatch_leaf<M_F64>(st, U, I, R, ts.F, ts.L, ts.D, nodes, bufA, nodes32, s_eff);
   else if (p == KRPS_FP32)
-    e = dispatch_leaf<M_F32>(st, U, I, R, ts.F, ts.L, ts.D, nodes, bufA, s_eff);
+    e = dispatch_leaf<M_F32>(st, U, I, R, ts.F, ts.L, ts.D, nodes, bufA, nodes32, s_eff);
   else if (split_terms == 3)
-    e = dispatch_leaf<M_SPLIT3>(st, U, I, R, ts.F, ts.L, ts.D, nodes, bufA, s_eff);
+    e = dispatch_leaf<M_SPLIT3>(st, U, I, R, ts.F, ts.L, ts.D, nodes, bufA, nodes32, s_eff);
   else
-    e = dispatch_leaf<M_SPLIT>(st, U, I, R, ts.F, ts.L, ts.D, nodes, bufA, s_eff);
+    e = dispatch_leaf<M_SPLIT>(st, U, I, R, ts.F, ts.L, ts.D, nodes, bufA, nodes32, s_eff);
   if (e != hipSuccess) return e;
   int lev = ts.D - s_eff;
   int64_t n = ceil_div(ts.L, int64_t(1) << s_eff);
@@ -385,10 +405,10 @@ hipError_t launch_tree_build(hipStream_t st, krps_precision p, const void* U, in
     if (blocks > 4096) blocks = 4096;
     if (p == KRPS_FP64)
       hipLaunchKernelGGL(node_upsweep_kernel<double>, dim3((unsigned)blocks), dim3(256), 0, st, cur,
-                         n, lev, s2, R, ts.L, ts.D, (double*)nodes, nxt, gram_full);
+                         n, lev, s2, R, ts.L, ts.D, (double*)nodes, nxt, gram_full, nodes32);
     else
       hipLaunchKernelGGL(node_upsweep_kernel<float>, dim3((unsigned)blocks), dim3(256), 0, st, cur,
-                         n, lev, s2, R, ts.L, ts.D, (float*)nodes, nxt, gram_full);
+                         n, lev, s2, R, ts.L, ts.D, (float*)nodes, nxt, gram_full, nullptr);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
     if (lev - s2 == 0) break;

@@ -337,3 +337,40 @@ def test_in_kernel_uniforms_match_the_oracle(prec):
     other, _ = S.sample_seeded(-1, J, seed=2026, ctr_base=1000 + J)
     torch.cuda.synchronize()
     assert (other != first).any(dim=1).float().mean().item() > 0.5
+
+
+FILTER_CASES = [((200000, 150000, 9000), 8, 8192), ((60000, 40000, 3000), 16, 8192),
+                ((100000, 70000, 5000), 32, 8192), ((30000, 20000), 64, 4096),
+                ((12000, 9000), 128, 2048)]
+
+
+@pytest.mark.parametrize("dims,R,J", FILTER_CASES)
+def test_float32_node_copy_gives_the_float64_walk(env, dims, R, J):
+    """The float64 walk deciding its deep levels from the float32 node
+    copies draws exactly the indices (and so the probabilities) of the walk
+    that reads only the float64 nodes, whichever levels are filtered; the
+    undecided share that is walked again stays small by default."""
+    krps, torch, ctx = env
+    Us = synth.gaussian_factors(dims, R, seed=7 * R + 1, heavy_rows_frac=0.01)
+    S = krps.Sampler(ctx, to_dev(torch, ctx, Us, "fp64"), precision="fp64")
+    D = max(S.tree_info(j).D for j in range(len(dims)))
+    u = torch.from_numpy(synth.uniforms(J, len(dims), 4242 + R)).to(ctx.device)
+    out = {}
+    for top in (100, -1, 0, D // 2):
+        S.set_filter(top)
+        for exclude in (-1, 0):
+            idx, prob, rows = S.sample(exclude, u, rows=True)
+            torch.cuda.synchronize()
+            assert S.check_status() == 0
+            out[top, exclude] = (idx.cpu(), prob.cpu(), rows.cpu(), S.rewalked)
+    walks = J * len(dims)
+    for exclude in (-1, 0):
+        i0, p0, r0, w0 = out[100, exclude]
+        assert w0 == 0  # the copy is off
+        for top in (-1, 0, D // 2):
+            i1, p1, r1, w1 = out[top, exclude]
+            print(f"filter R={R} D={D} top={top} exclude={exclude}: re-walked {w1} of "
+                  f"{walks} walks", flush=True)
+            assert torch.equal(i0, i1), (top, exclude)
+            assert torch.equal(p0, p1) and torch.equal(r0, r1)
+        assert out[-1, exclude][3] <= 0.02 * walks
