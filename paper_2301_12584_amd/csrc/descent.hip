@@ -385,6 +385,59 @@ __device__ __forceinline__ int64_t walk_table(const double* tm, int64_t L, int D
   return pos;
 }
 
+// walk_table over a table in global memory for one lane group, K levels
+// per memory round trip: lane m < 2^K - 1 of the group reads the mass of
+// stored node (level lev + i, position pos 2^i + j), m = 2^i - 1 + j, i.e.
+// every left child the next K levels can reach from the current node;
+// the K decisions are then taken from those lanes' values (lane exchange)
+// with the arithmetic of walk_table, so the outcome is the same.
+// Candidates past a level's stored nodes are clamped into it and never
+// chosen (the walk only goes where a right sibling exists).
+template <int LPS>
+__device__ __forceinline__ int64_t walk_table_group(const double* __restrict__ tm, int64_t L, int D,
+                                                    double x, double C, double& low_out, int sl) {
+  constexpr int K = LPS >= 64 ? 6 : LPS >= 32 ? 5 : LPS >= 16 ? 4 : LPS >= 8 ? 3 : 2;
+  const int li = 31 - __clz(sl + 1);  // this lane's level within a round
+  const int lj = sl + 1 - (1 << li);  // and position within that level
+  double low = 0.0, high = C;
+  int64_t pos = 0;
+  int64_t off = 1;
+  for (int lev = 1; lev <= D; lev += K) {
+    const int nk = K < D - lev + 1 ? K : D - lev + 1;
+    double v = 0.0;
+    if (li < nk) {
+      int64_t o = off;
+      for (int i = 0; i < li; ++i) o += ((L - 1) >> (D - (lev + i) + 1)) + 1;
+      const int64_t cnt = ((L - 1) >> (D - (lev + li) + 1)) + 1;
+      int64_t q = (pos << li) + lj;
+      if (q > cnt - 1) q = cnt - 1;
+      v = tm[o + q];
+    }
+    int jb = 0;
+    for (int i = 0; i < nk; ++i) {
+      const int l = lev + i;
+      const int64_t cnt_left = ((L - 1) >> (D - l + 1)) + 1;
+      const int64_t real = ((L - 1) >> (D - l)) + 1;
+      double mL = __shfl(v, (1 << i) - 1 + jb, LPS);
+      mL = mL > 0.0 ? mL : 0.0;
+      const double cut = low + mL;
+      const bool right_exists = 2 * pos + 1 < real;
+      if (cut >= x || !right_exists || high - cut <= 0.0) {
+        high = cut;
+        pos = 2 * pos;
+        jb = 2 * jb;
+      } else {
+        low = cut;
+        pos = 2 * pos + 1;
+        jb = 2 * jb + 1;
+      }
+      off += cnt_left;
+    }
+  }
+  low_out = low;
+  return pos;
+}
+
 // Dot product of the factor row `ur` (R contiguous values) with hb.  The
 // loads of each chunk of up to 32 values are issued together.
 template <int RMAX, typename T>
@@ -617,7 +670,7 @@ __device__ __forceinline__ void descend(const DescentArgs& a, int64_t base,
       const double* __restrict__ zt = md.zt + (int64_t)u * md.zn;
       C2 = zt[0];
       x2 = d2 * C2;
-      const int64_t c = walk_table(zt, md.L, md.D, x2, C2, low);
+      const int64_t c = walk_table_group<LPS>(zt, md.L, md.D, x2, C2, low, sl);
       const int64_t s0 = c * md.F;
       t = leaf_scan<LPS, RMAX>(U, R, s0, s0 + md.F < md.I ? s0 + md.F : md.I, nchunk, hb, low, x2,
                                sl, sub);
