@@ -132,6 +132,25 @@ krps_status krps_sampler_create(krps_ctx ctx, int N, const int64_t* I, int R, in
 
 /* U[j] changed in place: rebuild Z_j and G_j (O(I_j R^2), Thm 1.1 part 1). */
 krps_status krps_sampler_refresh(krps_sampler s, int j);
+
+/* UpdateSampler (Appendix A.7, Algorithm 5; Thm 1.1 part 1's single-entry
+ * update) for M entries, applied in order: U_j[rows[m], cols[m]] :=
+ * values[m].  The library writes each new value into the caller's U[j]
+ * (rounded to float32 for FP32 / BF16X2 factors) and adds the change to
+ * every stored node on the path from the row's leaf to the root (the root
+ * and the left children; a right child's mass is implied), to the float32
+ * node copy of an FP64 sampler and to G_j: O(R log(I_j / F)) per entry,
+ * in one workgroup.  rows, cols, values are HOST arrays of length M (they
+ * are validated on the host and passed to the kernels by value, 32 per
+ * launch).  Asynchronous on the context stream.  A preparation made before
+ * the update is invalidated (krps_sample_draw then needs a new
+ * krps_sample_prepare).  On float32 storage each update is added in
+ * float32, so after many updates the nodes drift from a rebuild by float32
+ * rounding; krps_sampler_refresh rebuilds exactly.
+ * Errors: KRPS_EINVAL for j, a row or column out of range, a non-finite
+ * value, M < 0 or NULL arrays with M > 0. */
+krps_status krps_sampler_update_entries(krps_sampler s, int j, int64_t M, const int64_t* rows,
+                                        const int32_t* cols, const double* values);
 krps_status krps_sampler_destroy(krps_sampler s);
 
 /* Synchronises the context stream, reads and clears the sampler's device

@@ -97,6 +97,32 @@ class SegmentTree:
         s0 = c * self.F
         return s0, min(s0 + self.F, self.I)
 
+    def update_entry(self, r, c, value):
+        """``UpdateSampler`` (Appendix A.7, Algorithm 5): ``U[r, c] := value``.
+
+        With ``u`` the old row ``U[r, :]`` and ``delta = value - u[c]``, the
+        leaf holding row ``r`` gets ``delta u`` added to its row ``c`` and to
+        its column ``c``, and ``delta^2`` more at ``(c, c)``; then each
+        ancestor, up to the root, is set to the sum of its two children."""
+        if not getattr(self, "_own_u", False):
+            self.U = self.U.copy()
+            self._own_u = True
+        u = self.U[r].copy()
+        delta = float(value) - u[c]
+        pos = r // self.F
+        G = self.levels[self.D][pos]
+        G[c, :] += delta * u
+        G[:, c] += delta * u
+        G[c, c] += delta * delta
+        self.U[r, c] = value
+        for lev in range(self.D - 1, -1, -1):
+            pos //= 2
+            child = self.levels[lev + 1]
+            s = child[2 * pos].copy()
+            if 2 * pos + 1 < child.shape[0]:
+                s += child[2 * pos + 1]
+            self.levels[lev][pos] = s
+
 
 def _gen_inner(h, G, Y):
     """``<h h^T, G, Y>`` for one vector ``h`` (``Y`` None means all ones)."""
@@ -341,6 +367,14 @@ class KRPSampler:
             self.U[j] = np.asarray(U, dtype=np.float64)
         self.Z[j] = SegmentTree(self.U[j], self.F)
         self.G[j] = self.U[j].T @ self.U[j]
+
+    def update_entry(self, j, r, c, value):
+        """``UpdateSampler(j, r, c, value)`` (Appendix A.7, Algorithm 5):
+        ``U_j[r, c] := value`` with the path of ``Z_j`` from the leaf of row
+        ``r`` to the root updated; ``G_j`` is that root."""
+        self.Z[j].update_entry(r, c, value)
+        self.U[j] = self.Z[j].U
+        self.G[j] = self.Z[j].root.copy()
 
     def modes(self, exclude):
         return [k for k in range(self.N) if k != exclude]

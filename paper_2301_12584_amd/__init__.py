@@ -131,6 +131,9 @@ def lib():
         "krps_sampler_tree_info": (c.c_int, [P, c.c_int, c.POINTER(TreeInfo)]),
         "krps_sampler_check": (c.c_int, [P, c.POINTER(c.c_int64), c.POINTER(c.c_int64)]),
         "krps_sampler_set_filter": (c.c_int, [P, c.c_int]),
+        "krps_sampler_update_entries": (c.c_int, [P, c.c_int, c.c_int64, c.POINTER(c.c_int64),
+                                                  c.POINTER(c.c_int32),
+                                                  c.POINTER(c.c_double)]),
         "krps_sample_static": (c.c_int, [P, c.c_int, c.c_int64, P, P, P, P]),
         "krps_exact_solve": (c.c_int, [P, P, c.c_int, P, P, c.c_size_t]),
         "krps_measure_peaks": (c.c_int, [P, P, c.c_size_t, c.POINTER(Peaks)]),
@@ -252,6 +255,16 @@ class Sampler:
 
     def refresh(self, j):
         check(lib().krps_sampler_refresh(self.handle, int(j)))
+
+    def update_entries(self, j, rows, cols, values):
+        """krps_sampler_update_entries: ``U_j[rows[m], cols[m]] := values[m]``
+        in order, with the factor tree updated along each row's path
+        (host sequences)."""
+        M = len(rows)
+        ra = (ctypes.c_int64 * M)(*[int(x) for x in rows])
+        ca = (ctypes.c_int32 * M)(*[int(x) for x in cols])
+        va = (ctypes.c_double * M)(*[float(x) for x in values])
+        check(lib().krps_sampler_update_entries(self.handle, int(j), M, ra, ca, va))
 
     def check_status(self):
         """Reads and clears the device status (raises on a zero product or a

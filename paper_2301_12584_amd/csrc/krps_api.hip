@@ -847,6 +847,36 @@ krps_status krps_sampler_create(krps_ctx ctx, int N, const int64_t* I, int R, in
   return KRPS_OK;
 }
 
+krps_status krps_sampler_update_entries(krps_sampler s, int j, int64_t M, const int64_t* rows,
+                                        const int32_t* cols, const double* values) {
+  if (s == nullptr) return fail(KRPS_EINVAL, "sampler is NULL");
+  if (j < 0 || j >= s->N) return fail(KRPS_EINVAL, "j out of range");
+  if (M < 0) return fail(KRPS_EINVAL, "M < 0");
+  if (M > 0 && (rows == nullptr || cols == nullptr || values == nullptr))
+    return fail(KRPS_EINVAL, "rows/cols/values is NULL");
+  for (int64_t m = 0; m < M; ++m) {
+    if (rows[m] < 0 || rows[m] >= s->I[j]) return fail(KRPS_EINVAL, "row out of range");
+    if (cols[m] < 0 || cols[m] >= s->R) return fail(KRPS_EINVAL, "column out of range");
+    if (!std::isfinite(values[m])) return fail(KRPS_EINVAL, "value is not finite");
+  }
+  KRPS_HIP(hipSetDevice(s->ctx->device));
+  for (int64_t m0 = 0; m0 < M; m0 += UPDATE_CHUNK) {
+    UpdateList ul;
+    ul.n = (int)std::min<int64_t>(UPDATE_CHUNK, M - m0);
+    for (int q = 0; q < ul.n; ++q) {
+      ul.row[q] = rows[m0 + q];
+      ul.col[q] = cols[m0 + q];
+      ul.val[q] = values[m0 + q];
+    }
+    hipError_t e = launch_update_entries(s->ctx->stream, s->prec, ul, s->U[j], s->nodes[j],
+                                         s->nodes32[j], s->gram[j], s->I[j], s->R, s->shape[j]);
+    if (e != hipSuccess) return hip_fail(e, "entry update launch");
+  }
+  // a preparation made before the update no longer describes the trees
+  s->prepared_ws = nullptr;
+  return KRPS_OK;
+}
+
 krps_status krps_sampler_refresh(krps_sampler s, int j) {
   if (s == nullptr) return fail(KRPS_EINVAL, "sampler is NULL");
   if (j < 0 || j >= s->N) return fail(KRPS_EINVAL, "j out of range");

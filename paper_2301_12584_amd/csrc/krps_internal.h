@@ -210,6 +210,21 @@ hipError_t launch_tree_build(hipStream_t st, krps_precision p, const void* U, in
                              double* scratch, size_t scratch_bytes, int split_terms = 2,
                              float* nodes32 = nullptr);
 
+// Up to UPDATE_CHUNK single-entry updates (row, column, new value), passed
+// by value to one launch.
+constexpr int UPDATE_CHUNK = 32;
+struct UpdateList {
+  int64_t row[UPDATE_CHUNK];
+  int32_t col[UPDATE_CHUNK];
+  double val[UPDATE_CHUNK];
+  int n;
+};
+// Algorithm 5 for the entries of ul, in order (the factor, its stored
+// nodes, the float32 copy if any, and G_j).
+hipError_t launch_update_entries(hipStream_t st, krps_precision p, const UpdateList& ul, void* U,
+                                 void* nodes, float* nodes32, double* gram, int64_t I, int R,
+                                 const TreeShape& ts);
+
 // eig.hip
 size_t prep_lds_bytes(int R);
 // G = (*) mats[0..nmat-1] -> G^+ (full, and packed if non-null), rank;

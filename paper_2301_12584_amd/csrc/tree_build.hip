@@ -422,3 +422,78 @@ hipError_t launch_tree_build(hipStream_t st, krps_precision p, const void* U, in
 }
 
 }  // namespace krps
+
+// ------------------------------------------------ single-entry updates
+
+namespace krps {
+
+namespace {
+
+// UpdateSampler (Appendix A.7, Algorithm 5) for a list of entries, in order:
+// U[r, c] := v.  With u the old row and delta = v - u[c] (v as stored), the
+// Gram of every node whose segment holds row r gains delta u in its row c
+// and column c and delta^2 more at (c, c); of those nodes the root and the
+// left children are stored (a right child's mass is its parent's minus its
+// sibling's, so it follows), and so is G_j.  One workgroup: thread a
+// updates entry (min(a, c), max(a, c)) of each stored path node.
+template <typename T>
+__global__ __launch_bounds__(128) void update_entries_kernel(UpdateList ul, T* __restrict__ U,
+                                                             T* __restrict__ nodes,
+                                                             float* __restrict__ nodes32,
+                                                             double* __restrict__ gram, int64_t I,
+                                                             int R, int F, int64_t L, int D) {
+  __shared__ double urow[128];
+  const int a = threadIdx.x;
+  for (int m = 0; m < ul.n; ++m) {
+    const int64_t r = ul.row[m];
+    const int c = ul.col[m];
+    if (a < R) urow[a] = (double)U[r * R + a];
+    __syncthreads();
+    const double vs = (double)(T)ul.val[m];
+    const double delta = vs - urow[c];
+    if (a < R) {
+      const double add = a == c ? 2.0 * delta * urow[c] + delta * delta : delta * urow[a];
+      const int lo = a < c ? a : c, hi = a < c ? c : a;
+      const int64_t p = packed_index(lo, hi, R);
+      // the root, then the left children on the path down to the leaf
+      int64_t pos = r / F;  // leaf position at level D
+      for (int lev = D; lev >= 0; --lev) {
+        int64_t node = -1;
+        if (lev == 0)
+          node = 0;
+        else if ((pos & 1) == 0)
+          node = level_offset(L, D, lev) + (pos >> 1);
+        if (node >= 0) {
+          const int64_t at = node * (int64_t)(R * (R + 1) / 2) + p;
+          const double nv = (double)nodes[at] + add;
+          nodes[at] = (T)nv;
+          if (nodes32 != nullptr) nodes32[at] = (float)nv;
+        }
+        pos >>= 1;
+      }
+      gram[(int64_t)lo * R + hi] += add;
+      if (lo != hi) gram[(int64_t)hi * R + lo] += add;
+    }
+    __syncthreads();
+    if (a == 0) U[r * R + c] = (T)ul.val[m];
+    __syncthreads();
+  }
+  (void)I;
+}
+
+}  // namespace
+
+hipError_t launch_update_entries(hipStream_t st, krps_precision p, const UpdateList& ul, void* U,
+                                 void* nodes, float* nodes32, double* gram, int64_t I, int R,
+                                 const TreeShape& ts) {
+  if (ul.n <= 0) return hipSuccess;
+  if (p == KRPS_FP64)
+    hipLaunchKernelGGL(update_entries_kernel<double>, dim3(1), dim3(128), 0, st, ul, (double*)U,
+                       (double*)nodes, nodes32, gram, I, R, ts.F, ts.L, ts.D);
+  else
+    hipLaunchKernelGGL(update_entries_kernel<float>, dim3(1), dim3(128), 0, st, ul, (float*)U,
+                       (float*)nodes, nullptr, gram, I, R, ts.F, ts.L, ts.D);
+  return hipGetLastError();
+}
+
+}  // namespace krps

@@ -374,3 +374,109 @@ def test_float32_node_copy_gives_the_float64_walk(env, dims, R, J):
             assert torch.equal(i0, i1), (top, exclude)
             assert torch.equal(p0, p1) and torch.equal(r0, r1)
         assert out[-1, exclude][3] <= 0.02 * walks
+
+
+def _chi2_equal_mass_groups(counts, p, groups):
+    """Chi-square p-value over ``groups`` equal-mass groups of rows sorted
+    by their probability (so that every group expects many draws)."""
+    from scipy.stats import chisquare
+    order = np.argsort(p)
+    cum = np.cumsum(p[order])
+    g = np.minimum((cum * groups / cum[-1]).astype(int), groups - 1)
+    obs = np.bincount(g, weights=counts[order], minlength=groups)
+    exp = np.bincount(g, weights=p[order], minlength=groups) * counts.sum()
+    return chisquare(obs, exp).pvalue
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x2"])
+def test_gpu_histograms_match_exact_leverage(env, prec):
+    """Large-J histograms of the GPU's own draws (in-kernel uniforms)
+    against the exact leverage distribution of the materialised
+    Khatri-Rao product (QR leverage, the definition): the exact tiny
+    workload over all modes (4,096 equal-mass groups of its 262,144 rows)
+    and excluding mode 0 (all 4,096 rows), and the Appendix A.13 check
+    (three 8 x 8 factors with 1% of entries x10, all 512 rows)."""
+    from scipy.stats import chisquare
+    krps, torch, ctx = env
+    cfg = synth.CONFIGS[1]
+    cases = [(synth.gaussian_factors(cfg["dims"], cfg["R"], synth.config_seed(1)), -1, 4096),
+             (synth.gaussian_factors(cfg["dims"], cfg["R"], synth.config_seed(1)), 0, 0),
+             (synth.gaussian_factors((8, 8, 8), 8, seed=2023, heavy_entries_frac=0.01), -1, 0)]
+    J = 1 << 22
+    pvals = []
+    for t, (Us, exclude, groups) in enumerate(cases):
+        S = krps.Sampler(ctx, to_dev(torch, ctx, Us, prec), precision=prec)
+        modes = [k for k in range(len(Us)) if k != exclude]
+        A = dfn.khatri_rao([Us[k] for k in modes])
+        lev = dfn.leverage_qr(A)
+        p = lev / lev.sum()
+        idx, _ = S.sample_seeded(exclude, J, seed=777 + t)
+        torch.cuda.synchronize()
+        idx = idx.cpu().numpy().astype(np.int64)
+        flat = np.zeros(J, dtype=np.int64)
+        for k in modes:            # C order over the drawn modes, last fastest
+            flat = flat * len(Us[k]) + idx[:, k]
+        cnt = np.bincount(flat, minlength=len(p)).astype(np.float64)
+        assert cnt.sum() == J
+        pv = (_chi2_equal_mass_groups(cnt, p, groups) if groups
+              else chisquare(cnt, p * J).pvalue)
+        print(f"chi-square {prec} case {t}: p = {pv:.3g}", flush=True)
+        pvals.append(pv)
+    # fixed seeds; Bonferroni over the three tests
+    assert min(pvals) > 1e-3 / len(pvals), pvals
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x2"])
+def test_entry_updates_match_a_rebuilt_oracle(env, prec):
+    """krps_sampler_update_entries (Algorithm 5): after single-entry updates
+    (first row, the ragged last leaf, repeated rows and entries, a zero)
+    the factor holds the new values, every stored node and G_j match the
+    oracle tree rebuilt from the updated factor, and the draws match the
+    oracle's over the updated factors; for float64 the float32 node copy
+    follows (walks with and without it agree)."""
+    krps, torch, ctx = env
+    dims, R = (5003, 1200, 700), 16
+    Us = synth.gaussian_factors(dims, R, seed=44, heavy_rows_frac=0.01)
+    S = krps.Sampler(ctx, to_dev(torch, ctx, Us, prec), precision=prec)
+    Us2 = [U.astype(np.float64).copy() for U in Us]
+    rng = np.random.default_rng(45)
+    for j in (0, 2):
+        I = dims[j]
+        rows = list(rng.integers(0, I, 60)) + [0, I - 1, I - 1, 7, 7]
+        cols = list(rng.integers(0, R, 60)) + [0, R - 1, 3, 5, 5]
+        vals = list((rng.standard_normal(60) * 20).astype(np.float32)) + [0.0, 1.5, -2.0, 0.25,
+                                                                         -0.5]
+        S.update_entries(j, rows, cols, vals)
+        for r, c, v in zip(rows, cols, vals):
+            Us2[j][r, c] = v
+    torch.cuda.synchronize()
+    for j in range(3):
+        got = S.factors[j].cpu().numpy().astype(np.float64)
+        assert np.array_equal(got, Us2[j]), j
+        t = osmp.SegmentTree(Us2[j], R)
+        ref = stored_nodes(t)
+        nodes = S.tree_nodes(j).cpu().numpy().astype(np.float64)
+        scale = node_scale(ref, R)[:, None] + 1e-300
+        err = float((np.abs(nodes - ref) / scale).max())
+        print(f"update {prec} factor {j}: node error {err:.2e}", flush=True)
+        assert err <= TOL_NODE[prec] * (1 if prec == "fp64" else 4), (j, err)
+        G = S.gram(j).cpu().numpy()
+        Gref = Us2[j].T @ Us2[j]
+        assert np.abs(G - Gref).max() <= TOL_NODE[prec] * np.abs(np.diag(Gref)).max()
+    u01 = synth.uniforms(2048, 3, 46)
+    ud = torch.from_numpy(u01).to(ctx.device)
+    for exclude in (-1, 1):
+        idx, prob, _ = S.sample(exclude, ud, check_status=True)
+        dr = osmp.KRPSampler(Us2).draw(exclude, u01, scaled=prec != "fp64")
+        c = compare(idx.cpu().numpy(), dr, prec)
+        report(f"after updates {prec} exclude={exclude}", c)
+        if prec == "bf16x2":
+            assert c["mismatch"] <= BF16_MISMATCH * c["n"]
+            assert c["needed_smargin"] <= bf16_scaled(R)
+        else:
+            assert c["unexcused"] == 0
+        if prec == "fp64":
+            S.set_filter(100)
+            i2, p2, _ = S.sample(exclude, ud)
+            S.set_filter(-1)
+            assert torch.equal(idx, i2) and torch.equal(prob, p2)

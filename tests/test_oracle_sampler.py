@@ -330,3 +330,93 @@ def test_degenerate_flags_mark_only_draws_inside_a_cluster():
     scaled = [q * np.array([1.0, 2.0, 3.0, 4.0]) for q in Q]
     dr = smp.KRPSampler(scaled).draw(-1, u01)
     assert not dr.degenerate.any()
+
+
+def _tree_err(t, ref):
+    """Largest |node - rebuilt node| over every level, relative to the
+    largest diagonal of the rebuilt node."""
+    worst = 0.0
+    for lev in range(ref.D + 1):
+        a, b = t.levels[lev], ref.levels[lev]
+        assert a.shape == b.shape
+        scale = np.abs(np.diagonal(b, axis1=1, axis2=2)).max(axis=1)[:, None, None] + 1e-300
+        worst = max(worst, float((np.abs(a - b) / scale).max()))
+    return worst
+
+
+def _updates(I, R, n, seed):
+    rng = np.random.default_rng(seed)
+    rows = rng.integers(0, I, n)
+    rows[: 3] = [0, I - 1, I - 1]          # first row, the ragged last leaf, twice
+    cols = rng.integers(0, R, n)
+    vals = rng.standard_normal(n) * 3.0
+    vals[5] = 0.0                          # an entry set to zero
+    return rows, cols, vals
+
+
+@pytest.mark.parametrize("I,R,F", [(103, 5, 5), (64, 8, 1), (1000, 16, 7), (1, 3, 4)])
+def test_entry_update_equals_rebuild(I, R, F):
+    """Algorithm 5 (Appendix A.7): after single-entry updates every node of
+    the tree equals the Gram of its rows recomputed from the updated factor,
+    and nodes whose segment does not hold an updated row are untouched."""
+    U = synth.gaussian_factors((I,), R, seed=I + R)[0].astype(np.float64)
+    t = smp.SegmentTree(U, F)
+    before = [lv.copy() for lv in t.levels]
+    rows, cols, vals = _updates(I, R, 40, seed=I)
+    U2 = U.copy()
+    for r, c, v in zip(rows, cols, vals):
+        t.update_entry(int(r), int(c), float(v))
+        U2[r, c] = v
+    assert np.array_equal(t.U, U2)
+    assert np.array_equal(U, synth.gaussian_factors((I,), R, seed=I + R)[0])  # caller's copy kept
+    ref = smp.SegmentTree(U2, F)
+    assert _tree_err(t, ref) <= 1e-12
+    touched = set()
+    for r in rows:
+        pos = int(r) // F
+        for lev in range(t.D, -1, -1):
+            touched.add((lev, pos))
+            pos //= 2
+    for lev in range(t.D + 1):
+        for p in range(t.real(lev)):
+            if (lev, p) not in touched:
+                assert np.array_equal(t.levels[lev][p], before[lev][p])
+
+
+def test_entry_update_draws_equal_a_fresh_sampler():
+    Us = synth.gaussian_factors((300, 200, 100), 8, seed=91, heavy_rows_frac=0.01)
+    S = smp.KRPSampler(Us)
+    Us2 = [U.astype(np.float64).copy() for U in Us]
+    for j in range(3):
+        rows, cols, vals = _updates(len(Us[j]), 8, 25, seed=92 + j)
+        for r, c, v in zip(rows, cols, vals):
+            S.update_entry(j, int(r), int(c), float(v))
+            Us2[j][r, c] = v
+    fresh = smp.KRPSampler(Us2)
+    u = synth.uniforms(2000, 3, 93)
+    for exclude in (-1, 1):
+        a, b = S.draw(exclude, u), fresh.draw(exclude, u)
+        diff = ~(a.idx == b.idx).all(axis=1)
+        assert np.all(b.margin[diff] <= 1e-10)
+        np.testing.assert_allclose(a.prob[~diff], b.prob[~diff], rtol=1e-10)
+
+
+def test_entry_update_without_the_square_term_is_caught():
+    """Planted mistake: dropping Algorithm 5's delta^2 on the diagonal (or
+    using the new row for the cross terms) is seen by the rebuild pin."""
+    U = synth.gaussian_factors((50,), 6, seed=5)[0].astype(np.float64)
+
+    class NoSquare(smp.SegmentTree):
+        def update_entry(self, r, c, value):
+            d = float(value) - self.U[r, c]
+            super().update_entry(r, c, value)
+            pos = r // self.F
+            for lev in range(self.D, -1, -1):
+                self.levels[lev][pos][c, c] -= d * d
+                pos //= 2
+
+    t = NoSquare(U, 6)
+    for r, c, v in zip(*_updates(50, 6, 10, seed=6)):
+        t.update_entry(int(r), int(c), float(v))
+    U2 = t.U
+    assert _tree_err(t, smp.SegmentTree(U2, 6)) > 1e-3
