@@ -629,7 +629,63 @@ def run_batched(torch, krps, ctx, prec, reps):
     print(f"# batched {prec}: {rec['batched_ms']:.2f} ms ({rec['batched_samples_per_s'] / 1e6:.1f}"
           f" M samples/s) vs per-problem {rec['per_problem_ms']:.2f} ms; identical {same}",
           file=sys.stderr, flush=True)
+    # autotuned shapes: for each R the tuner times every leaf size, walk
+    # shape and build team on that R's largest problem (outside the timed
+    # region); every problem of that R is then rebuilt with the winner
+    t0 = time.perf_counter()
+    factors = [S.factors for S in samplers]
+    del batch, outs
+    tuned = {}
+    for R in sorted({R for _, R in probs}):
+        p = max((i for i, (_, r) in enumerate(probs) if r == R), key=lambda i: sum(probs[i][0]))
+        tuned[R] = krps.autotune(ctx, factors[p], unis[p], precision=prec)
+        tuned[R]["tuned_on_problem"] = p
+        print(f"# batched tune R={R}: {tuned[R]}", file=sys.stderr, flush=True)
+    tune_s = time.perf_counter() - t0
     del samplers
+    torch.cuda.synchronize()
+    tsamplers = []
+    for (dims, R), Ud in zip(probs, factors):
+        t = tuned[R]
+        S = krps.Sampler(ctx, Ud, precision=prec, F=t["F"], lps=t["lps"], team=t["team"])
+        for j in range(S.N):
+            S.refresh(j)
+        tsamplers.append(S)
+    tbatch = krps.Batch(ctx, tsamplers, excl)
+    idx_t, _ = tbatch.sample(unis)
+    torch.cuda.synchronize()
+    tt, ttp, ttw = [], [], []
+    for _ in range(reps):
+        e0, e1 = ev(), ev()
+        e0.record()
+        idx_t, prob_t = tbatch.sample(unis)
+        e1.record()
+        torch.cuda.synchronize()
+        tt.append(e0.elapsed_time(e1))
+    for _ in range(reps):
+        e0, e1, e2 = ev(), ev(), ev()
+        e0.record()
+        tbatch.prepare()
+        e1.record()
+        tbatch.draw(unis, pidx, pprob)
+        e2.record()
+        torch.cuda.synchronize()
+        ttp.append(e0.elapsed_time(e1))
+        ttw.append(e1.elapsed_time(e2))
+    agree = float(np.mean([(a == b).all(dim=1).float().mean().item()
+                           for a, b in zip(idx_t, idx_b)]))
+    rec["tuned"] = {"per_R": {str(R): v for R, v in tuned.items()}, "tune_s": tune_s,
+                    "batched_ms": float(np.median(tt)),
+                    "batched_samples_per_s": total / (float(np.median(tt)) / 1e3),
+                    "prepare_ms": float(np.median(ttp)), "walk_ms": float(np.median(ttw)),
+                    "draws_equal_to_default_shape": agree,
+                    "walk_roofline": roofline(ub, fl, float(np.median(ttw)) / 1e3,
+                                              F64_VALU_PEAK_TFS,
+                                              kernel="descent_batched_kernel, tuned shapes")}
+    print(f"# batched {prec} tuned: {rec['tuned']['batched_ms']:.2f} ms "
+          f"({rec['tuned']['batched_samples_per_s'] / 1e6:.1f} M samples/s), draws equal to the "
+          f"default shape's {agree:.4f}", file=sys.stderr, flush=True)
+    del tbatch, tsamplers, factors
     torch.cuda.synchronize()
     return rec
 

@@ -424,6 +424,7 @@ krps_status krps_sketched_lstsq(krps_ctx ctx, int R, int64_t J, const void* rows
 typedef struct {
   int32_t F;          /* leaf size of the factor trees (krps_sampler_create's F) */
   int32_t lps;        /* lanes per sample of the walk (krps_sampler_set_lps) */
+  int32_t team;       /* waves per leaf team of the tree build (krps_sampler_set_build) */
   double build_ms;    /* measured: rebuild of all N trees */
   double draw_ms;     /* measured: prepare + draw of J samples over all modes */
   int32_t from_cache; /* 1 if read from the cache file, 0 if measured now */
@@ -433,6 +434,13 @@ typedef struct {
  * 4 or 8 for R <= 8, 8 or 16 for R <= 16, 16, 32 or 64 for R <= 32, 64
  * above).  The index and probability of every draw do not depend on it. */
 krps_status krps_sampler_set_lps(krps_sampler s, int lps);
+
+/* Selects the tree build's team width: waves that share one leaf's
+ * 16 x 16 accumulator tiles (0 = default; R <= 16: 1; R <= 32: 1 or 3;
+ * R <= 64: 2 or 5; above: 4 or 8 for KRPS_BF16X2, 6 or 12 otherwise).
+ * Fewer waves hold more tiles each (more registers, fewer loads shared).
+ * The stored nodes do not depend on it.  KRPS_EINVAL for another value. */
+krps_status krps_sampler_set_build(krps_sampler s, int team);
 
 /* Float64 samplers keep a float32 copy of every factor-tree node (each
  * entry rounded to nearest; it is built with the tree and held in the
@@ -455,8 +463,8 @@ krps_status krps_autotune_workspace_bytes(int N, const int64_t* I, int R, krps_p
 
 /* Times a rebuild of the N trees plus a draw of J samples (no exclusion,
  * uniforms device float64 [J][N][2]) over the caller's factors U for leaf
- * sizes F in {R/2, R, 2R, 4R} and every lanes-per-sample choice of R, and
- * returns the fastest.  Results are keyed by (gfx950, precision, R, J, I_1..I_N)
+ * sizes F in {R/2, R, 2R, 4R}, every lanes-per-sample choice of R and
+ * every tree-build team width of R and p, and returns the fastest.  Results are keyed by (gfx950, precision, R, J, I_1..I_N)
  * in the JSON-lines file cache_path (NULL: no cache): a key present there
  * is returned without timing; a new result is appended.  The leaf size
  * does not change any drawn index (ties go to the lower row, so the index

@@ -43,8 +43,9 @@ class DrawLayout(ctypes.Structure):
 
 
 class Tune(ctypes.Structure):
-    _fields_ = [("F", ctypes.c_int32), ("lps", ctypes.c_int32), ("build_ms", ctypes.c_double),
-                ("draw_ms", ctypes.c_double), ("from_cache", ctypes.c_int32)]
+    _fields_ = [("F", ctypes.c_int32), ("lps", ctypes.c_int32), ("team", ctypes.c_int32),
+                ("build_ms", ctypes.c_double), ("draw_ms", ctypes.c_double),
+                ("from_cache", ctypes.c_int32)]
 
 
 class Region(ctypes.Structure):
@@ -131,6 +132,7 @@ def lib():
         "krps_sampler_tree_info": (c.c_int, [P, c.c_int, c.POINTER(TreeInfo)]),
         "krps_sampler_check": (c.c_int, [P, c.POINTER(c.c_int64), c.POINTER(c.c_int64)]),
         "krps_sampler_set_filter": (c.c_int, [P, c.c_int]),
+        "krps_sampler_set_build": (c.c_int, [P, c.c_int]),
         "krps_sampler_update_entries": (c.c_int, [P, c.c_int, c.c_int64, c.POINTER(c.c_int64),
                                                   c.POINTER(c.c_int32),
                                                   c.POINTER(c.c_double)]),
@@ -226,7 +228,7 @@ class Sampler:
     contiguous CUDA tensors ``[I_j, R]`` (float64 for ``fp64``, float32
     otherwise).  The tensors are referenced, not copied."""
 
-    def __init__(self, ctx: Context, factors, precision="fp32", F=0, lps=0):
+    def __init__(self, ctx: Context, factors, precision="fp32", F=0, lps=0, team=0):
         torch = ctx.torch
         self.ctx = ctx
         self.precision = precision
@@ -249,6 +251,10 @@ class Sampler:
         self.handle = h
         if lps:
             check(lib().krps_sampler_set_lps(self.handle, int(lps)))
+        if team:
+            # the trees were built with the default team at creation; the
+            # nodes do not depend on it, later rebuilds use this one
+            check(lib().krps_sampler_set_build(self.handle, int(team)))
         sz = ctypes.c_size_t()
         check(lib().krps_sample_workspace_bytes(self.handle, ctypes.byref(sz)))
         self.draw_ws = torch.empty(sz.value, dtype=torch.uint8, device=ctx.device)
@@ -472,10 +478,11 @@ def sample_batched(ctx: "Context", samplers, excludes, uniforms, with_prob=True)
 
 
 def autotune(ctx: "Context", factors, uniforms, precision="fp32", cache_path=None):
-    """Leaf size F and walk lanes per sample for these factors: measured
-    (rebuild + draw of J = uniforms.shape[0] samples; uniforms float64
-    ``[J, N, 2]`` on the device) or read from the JSON-lines cache.
-    Returns a dict with F, lps, build_ms, draw_ms, from_cache."""
+    """Leaf size F, walk lanes per sample and tree-build team width for
+    these factors: measured (rebuild + draw of J = uniforms.shape[0]
+    samples; uniforms float64 ``[J, N, 2]`` on the device) or read from the
+    JSON-lines cache.  Returns a dict with F, lps, team, build_ms, draw_ms,
+    from_cache."""
     torch = ctx.torch
     N = len(factors)
     R = int(factors[0].shape[1])
@@ -492,8 +499,8 @@ def autotune(ctx: "Context", factors, uniforms, precision="fp32", cache_path=Non
                               _ptr(uniforms), _ptr(ws), ws.numel(),
                               None if cache_path is None else str(cache_path).encode(),
                               ctypes.byref(t)))
-    return {"F": t.F, "lps": t.lps, "build_ms": t.build_ms, "draw_ms": t.draw_ms,
-            "from_cache": bool(t.from_cache)}
+    return {"F": t.F, "lps": t.lps, "team": t.team, "build_ms": t.build_ms,
+            "draw_ms": t.draw_ms, "from_cache": bool(t.from_cache)}
 
 
 def sketched_lstsq(ctx: "Context", rows, prob, sb_rows, precision=None):

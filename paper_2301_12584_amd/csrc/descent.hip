@@ -807,13 +807,18 @@ __global__ __launch_bounds__(64 * DESC_WAVES, KRPS_DESC_MIN_WAVES) void descent_
 }
 
 // Shape classes of the batched walk (lanes per sample, packed entries per
-// lane, largest R): R <= 8, 16, 32, 64, 128.
+// lane, largest R): the default shape of R <= 8, 16, 32, 64, 128, then the
+// other lanes-per-sample choices of R <= 8, 16, 32 (krps_sampler_set_lps).
 template <int CLS> struct Cls;
 template <> struct Cls<0> { static constexpr int LPS = 4, NP = 9, RMAX = 8; };
 template <> struct Cls<1> { static constexpr int LPS = 8, NP = 17, RMAX = 16; };
 template <> struct Cls<2> { static constexpr int LPS = 32, NP = 17, RMAX = 32; };
 template <> struct Cls<3> { static constexpr int LPS = 64, NP = 33, RMAX = 64; };
 template <> struct Cls<4> { static constexpr int LPS = 64, NP = 0, RMAX = 128; };
+template <> struct Cls<5> { static constexpr int LPS = 8, NP = 5, RMAX = 8; };
+template <> struct Cls<6> { static constexpr int LPS = 16, NP = 9, RMAX = 16; };
+template <> struct Cls<7> { static constexpr int LPS = 16, NP = 33, RMAX = 32; };
+template <> struct Cls<8> { static constexpr int LPS = 64, NP = 9, RMAX = 32; };
 
 // Many problems of one shape class in one persistent launch (Appendix
 // A.10 batching): every wavefront takes the next task -- (problem, group
@@ -943,8 +948,16 @@ hipError_t launch_descent(hipStream_t st, krps_precision p, const DescentArgs& a
   return dispatch_descent<float>(st, a, a.lps);
 }
 
-int batch_class(int R) { return R <= 8 ? 0 : R <= 16 ? 1 : R <= 32 ? 2 : R <= 64 ? 3 : 4; }
-int batch_group(int cls) { return cls == 0 ? 16 : cls == 1 ? 8 : cls == 2 ? 2 : 1; }
+int batch_class(int R, int lps) {
+  if (R <= 8) return lps == 8 ? 5 : 0;
+  if (R <= 16) return lps == 16 ? 6 : 1;
+  if (R <= 32) return lps == 16 ? 7 : lps == 64 ? 8 : 2;
+  return R <= 64 ? 3 : 4;
+}
+int batch_group(int cls) {
+  static const int lps[NBATCH_CLASSES] = {4, 8, 32, 64, 64, 8, 16, 16, 64};
+  return 64 / lps[cls];
+}
 
 template <typename T, int CLS>
 void launch_cls(hipStream_t st, int64_t blocks, const BatchProblem* probs, int P, int64_t ntask,
@@ -961,7 +974,11 @@ void launch_batched_t(hipStream_t st, int cls, int64_t blocks, const BatchProble
     case 1: launch_cls<T, 1>(st, blocks, probs, P, ntask, counter); break;
     case 2: launch_cls<T, 2>(st, blocks, probs, P, ntask, counter); break;
     case 3: launch_cls<T, 3>(st, blocks, probs, P, ntask, counter); break;
-    default: launch_cls<T, 4>(st, blocks, probs, P, ntask, counter); break;
+    case 4: launch_cls<T, 4>(st, blocks, probs, P, ntask, counter); break;
+    case 5: launch_cls<T, 5>(st, blocks, probs, P, ntask, counter); break;
+    case 6: launch_cls<T, 6>(st, blocks, probs, P, ntask, counter); break;
+    case 7: launch_cls<T, 7>(st, blocks, probs, P, ntask, counter); break;
+    default: launch_cls<T, 8>(st, blocks, probs, P, ntask, counter); break;
   }
 }
 

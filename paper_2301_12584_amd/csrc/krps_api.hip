@@ -50,11 +50,12 @@ struct GraphKey {
   const void* sigma = nullptr;
   const void* ws = nullptr;
   int64_t J = -1;
-  int lps = -1, filter = -2;
+  int lps = -1, filter = -2, team = -1;
   uint64_t seed = 0, ctr_base = 0;
   bool operator==(const GraphKey& o) const {
     return t == o.t && uniforms == o.uniforms && sigma == o.sigma && ws == o.ws && J == o.J &&
-           lps == o.lps && filter == o.filter && seed == o.seed && ctr_base == o.ctr_base;
+           lps == o.lps && filter == o.filter && team == o.team && seed == o.seed &&
+           ctr_base == o.ctr_base;
   }
 };
 
@@ -78,6 +79,7 @@ struct krps_sampler_s {
   const void* prepared_ws = nullptr;  // ws of the last preparation
   int prepared_exclude = -2;
   int lps = 0;                         // descent lanes per sample (0 = default)
+  int team = 0;                        // waves per leaf team of the tree build (0 = default)
   // captured ALS sweep and what its kernels' arguments were made from
   hipGraphExec_t sweep_exec = nullptr;
   GraphKey gkey;
@@ -220,7 +222,7 @@ size_t gpacked_off(krps_sampler s) { return s->lay.gplus + align_up((size_t)s->R
 krps_status build_tree(krps_sampler s, int j) {
   hipError_t e = launch_tree_build(s->ctx->stream, s->prec, s->U[j], s->I[j], s->R, s->shape[j],
                                    s->nodes[j], s->gram[j], s->scratch, s->scratch_bytes, 2,
-                                   s->nodes32[j]);
+                                   s->nodes32[j], s->team);
   if (e != hipSuccess) return hip_fail(e, "tree build launch");
   return KRPS_OK;
 }
@@ -692,7 +694,7 @@ krps_status sweep_entry(krps_sampler s, krps_tensor t, int64_t J, const double* 
   }
   // the captured graph is keyed by everything its kernels' arguments hold
   const GraphKey key{t,         uniforms,          sigma, ws, J, s->lps, s->filter_top,
-                     seeded ? seed : 0, seeded ? ctr_base : 0};
+                     s->team,   seeded ? seed : 0, seeded ? ctr_base : 0};
   if (s->sweep_exec == nullptr || !(s->gkey == key)) {
     if (s->sweep_exec != nullptr) {
       (void)hipGraphExecDestroy(s->sweep_exec);
@@ -909,6 +911,15 @@ krps_status krps_sampler_set_filter(krps_sampler s, int top) {
   if (s == nullptr) return fail(KRPS_EINVAL, "sampler is NULL");
   if (top < -1) return fail(KRPS_EINVAL, "top must be >= -1");
   s->filter_top = top;
+  return KRPS_OK;
+}
+
+krps_status krps_sampler_set_build(krps_sampler s, int team) {
+  if (s == nullptr) return fail(KRPS_EINVAL, "sampler is NULL");
+  const std::vector<int> ch = build_team_choices(s->R, s->prec);
+  if (team != 0 && std::find(ch.begin(), ch.end(), team) == ch.end())
+    return fail(KRPS_EINVAL, "team width not available for R and precision");
+  s->team = team;
   return KRPS_OK;
 }
 
@@ -1295,7 +1306,9 @@ static krps_status batched_draw(krps_ctx ctx, int P, const krps_sampler* s, cons
   // problems in a group by falling cost
   std::vector<double> cost(P);
   for (int p = 0; p < P; ++p) cost[p] = sample_cost(s[p], exclude[p]) * (double)J[p];
-  auto group_of = [&](int p) { return (s[p]->prec == KRPS_FP64 ? 0 : 5) + batch_class(s[p]->R); };
+  auto group_of = [&](int p) {
+    return (s[p]->prec == KRPS_FP64 ? 0 : NBATCH_CLASSES) + batch_class(s[p]->R, s[p]->lps);
+  };
   std::vector<int> ord(P);
   for (int p = 0; p < P; ++p) ord[p] = p;
   std::sort(ord.begin(), ord.end(), [&](int x, int y) {
@@ -1304,8 +1317,9 @@ static krps_status batched_draw(krps_ctx ctx, int P, const krps_sampler* s, cons
     return cost[x] > cost[y];
   });
   std::vector<BatchProblem> probs(P);
-  int64_t task[10] = {0};
-  int nprob[10] = {0};
+  constexpr int NG = 2 * NBATCH_CLASSES;
+  int64_t task[NG] = {0};
+  int nprob[NG] = {0};
   for (int i = 0; i < P; ++i) {
     const int p = ord[i];
     krps_sampler sp = s[p];
@@ -1324,7 +1338,7 @@ static krps_status batched_draw(krps_ctx ctx, int P, const krps_sampler* s, cons
     b.a.idx = idx[p];
     b.a.prob = prob != nullptr ? prob[p] : nullptr;
     b.tab = (const uint16_t*)(w + pl.tab_off[p]);
-    b.cls = batch_class(sp->R);
+    b.cls = batch_class(sp->R, sp->lps);
     b.G = batch_group(b.cls);
     b.task0 = task[g];
     task[g] += (J[p] + b.G - 1) / b.G;
@@ -1333,14 +1347,14 @@ static krps_status batched_draw(krps_ctx ctx, int P, const krps_sampler* s, cons
   st = stage_copy(ctx, 1, probs.data(), (size_t)P * sizeof(BatchProblem), w + pl.probs);
   if (st != KRPS_OK) return st;
   unsigned long long* counters = (unsigned long long*)(w + pl.counters);
-  hipError_t e = launch_fill_f64(stream, (double*)counters, 10);
+  hipError_t e = launch_fill_f64(stream, (double*)counters, NG);
   if (e != hipSuccess) return hip_fail(e, "counter clear");
   const BatchProblem* dprobs = (const BatchProblem*)(w + pl.probs);
   int first = 0;
-  for (int g = 0; g < 10; ++g) {
+  for (int g = 0; g < NG; ++g) {
     if (nprob[g] > 0) {
-      e = launch_descent_batched(stream, g < 5, g % 5, dprobs + first, nprob[g], task[g],
-                                 counters + g);
+      e = launch_descent_batched(stream, g < NBATCH_CLASSES, g % NBATCH_CLASSES, dprobs + first,
+                                 nprob[g], task[g], counters + g);
       if (e != hipSuccess) return hip_fail(e, "batched walk");
     }
     first += nprob[g];
@@ -1702,7 +1716,8 @@ std::string tune_key(int N, const int64_t* I, int R, krps_precision p, int64_t J
   return k;
 }
 
-// One line per entry: {"key": "...", "F": f, "lps": l, "build_ms": b, "draw_ms": d}
+// One line per entry: {"key": "...", "F": f, "lps": l, "team": w, "build_ms": b,
+// "draw_ms": d} (entries without "team" used the default team)
 bool tune_lookup(const char* path, const std::string& key, krps_tune* out) {
   if (path == nullptr) return false;
   FILE* f = fopen(path, "r");
@@ -1715,11 +1730,13 @@ bool tune_lookup(const char* path, const std::string& key, krps_tune* out) {
     if (at == nullptr) continue;
     const char* q = strstr(line, "\"F\": ");
     const char* l = strstr(line, "\"lps\": ");
+    const char* tw = strstr(line, "\"team\": ");
     const char* b = strstr(line, "\"build_ms\": ");
     const char* d = strstr(line, "\"draw_ms\": ");
     if (q && l && b && d) {
       out->F = atoi(q + 5);
       out->lps = atoi(l + 7);
+      out->team = tw ? atoi(tw + 8) : 0;
       out->build_ms = atof(b + 12);
       out->draw_ms = atof(d + 11);
       out->from_cache = 1;
@@ -1734,8 +1751,10 @@ void tune_store(const char* path, const std::string& key, const krps_tune& t) {
   if (path == nullptr) return;
   FILE* f = fopen(path, "a");
   if (f == nullptr) return;
-  fprintf(f, "{\"key\": \"%s\", \"F\": %d, \"lps\": %d, \"build_ms\": %.6f, \"draw_ms\": %.6f}\n",
-          key.c_str(), t.F, t.lps, t.build_ms, t.draw_ms);
+  fprintf(f,
+          "{\"key\": \"%s\", \"F\": %d, \"lps\": %d, \"team\": %d, \"build_ms\": %.6f, "
+          "\"draw_ms\": %.6f}\n",
+          key.c_str(), t.F, t.lps, t.team, t.build_ms, t.draw_ms);
   fclose(f);
 }
 
@@ -1781,8 +1800,10 @@ krps_status krps_autotune(krps_ctx ctx, int N, const int64_t* I, int R, krps_pre
     krps_sampler s = nullptr;
     result = krps_sampler_create(ctx, N, I, R, F, U, p, w + pl.sampler, pl.draw - pl.sampler, &s);
     if (result != KRPS_OK) break;
-    for (int lps : lps_choices(R)) {
+    for (int lps : lps_choices(R))
+    for (int team : build_team_choices(R, p)) {
       s->lps = lps;
+      s->team = team;
       float bmin = 1e30f, dmin = 1e30f;
       for (int rep = 0; rep < 4 && result == KRPS_OK; ++rep) {
         hipError_t e = hipEventRecord(ev[0], ctx->stream);
@@ -1815,6 +1836,7 @@ krps_status krps_autotune(krps_ctx ctx, int N, const int64_t* I, int R, krps_pre
         best = bmin + dmin;
         out->F = F;
         out->lps = lps;
+        out->team = team;
         out->build_ms = bmin;
         out->draw_ms = dmin;
       }
@@ -2146,7 +2168,8 @@ krps_status krps_workspace_regions(int N, const int64_t* I, int R, int F, krps_p
     rl.add(4, "eigen jobs", bp.eig, span(bp.eig, bp.probs), (size_t)bp.n_eig * sizeof(EigJob));
     rl.add(4, "problems", bp.probs, span(bp.probs, bp.counters),
            (size_t)N * sizeof(BatchProblem));
-    rl.add(4, "task counters", bp.counters, span(bp.counters, bp.total), 10 * 8);
+    rl.add(4, "task counters", bp.counters, span(bp.counters, bp.total),
+           2 * NBATCH_CLASSES * 8);
   }
   // --- generic least squares with one right-hand side
   {

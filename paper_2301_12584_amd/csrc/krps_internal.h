@@ -6,6 +6,7 @@
 #include <cstddef>
 #include <cstdint>
 #include <string>
+#include <vector>
 
 #include "../../include/krps.h"
 
@@ -208,7 +209,10 @@ size_t tree_build_scratch_extent(const TreeShape& ts, int R);
 hipError_t launch_tree_build(hipStream_t st, krps_precision p, const void* U, int64_t I, int R,
                              const TreeShape& ts, void* nodes, double* gram_full,
                              double* scratch, size_t scratch_bytes, int split_terms = 2,
-                             float* nodes32 = nullptr);
+                             float* nodes32 = nullptr, int team = 0);
+// Waves per team of the leaf pass available for R and a precision (the
+// default first; 0 also selects the default).
+std::vector<int> build_team_choices(int R, krps_precision p);
 
 // Up to UPDATE_CHUNK single-entry updates (row, column, new value), passed
 // by value to one launch.
@@ -315,7 +319,10 @@ hipError_t launch_descent(hipStream_t st, krps_precision p, const DescentArgs& a
 int prep_block_threads(int R);
 hipError_t launch_prep_batched(hipStream_t st, const PrepJob* jobs, int njobs, int Rmax);
 hipError_t launch_eig_batched(hipStream_t st, bool f64, const EigJob* jobs, int njobs, int Rmax);
-int batch_class(int R);
+// Shape class of the batched walk for R and a lanes-per-sample choice
+// (0 = default), and the samples one wavefront serves in that class.
+constexpr int NBATCH_CLASSES = 9;
+int batch_class(int R, int lps);
 int batch_group(int cls);
 hipError_t launch_descent_batched(hipStream_t st, bool f64, int cls, const BatchProblem* probs,
                                   int P, int64_t ntask, unsigned long long* counter);

@@ -21,6 +21,7 @@
 // node: the walk decides its deep levels from the copy.
 #include "device_common.h"
 #include <algorithm>
+#include <vector>
 
 #include "krps_internal.h"
 
@@ -318,28 +319,40 @@ hipError_t run_leaf(hipStream_t st, const void* U, int64_t I, int R, int F, int6
   return hipGetLastError();
 }
 
-// Team shape and register-run depth per precision and tile count.
+// Team width (waves per leaf team) and register-run depth per precision
+// and tile count, the default width first; build_team_choices lists the
+// same widths.
 template <int MODE>
 hipError_t dispatch_leaf(hipStream_t st, const void* U, int64_t I, int R, int F, int64_t L, int D,
-                         void* nodes, double* tops, float* nodes32, int& s_eff) {
+                         void* nodes, double* tops, float* nodes32, int team, int& s_eff) {
+#define KRPS_LEAF(NT, TW, S) run_leaf<MODE, NT, TW, S>(st, U, I, R, F, L, D, nodes, tops, nodes32, s_eff)
   if constexpr (MODE == M_SPLIT || MODE == M_SPLIT3) {
-    if (R <= 16) return run_leaf<MODE, 1, 1, 4>(st, U, I, R, F, L, D, nodes, tops, nodes32, s_eff);
-    if (R <= 32) return run_leaf<MODE, 2, 1, 4>(st, U, I, R, F, L, D, nodes, tops, nodes32, s_eff);
-    if (R <= 64) return run_leaf<MODE, 4, 2, 3>(st, U, I, R, F, L, D, nodes, tops, nodes32, s_eff);
-    return run_leaf<MODE, 8, 4, 2>(st, U, I, R, F, L, D, nodes, tops, nodes32, s_eff);
+    if (R <= 16) return KRPS_LEAF(1, 1, 4);
+    if (R <= 32) return team == 3 ? KRPS_LEAF(2, 3, 4) : KRPS_LEAF(2, 1, 4);
+    if (R <= 64) return team == 5 ? KRPS_LEAF(4, 5, 3) : KRPS_LEAF(4, 2, 3);
+    return team == 8 ? KRPS_LEAF(8, 8, 2) : KRPS_LEAF(8, 4, 2);
   } else {
     // one or two float64 accumulator tiles per wave keep the register run
     // (binary-counter stack) small enough for several waves per SIMD
-    if (R <= 16) return run_leaf<MODE, 1, 1, 4>(st, U, I, R, F, L, D, nodes, tops, nodes32, s_eff);
-    if (R <= 32) return run_leaf<MODE, 2, 3, 4>(st, U, I, R, F, L, D, nodes, tops, nodes32, s_eff);
-    if (R <= 64) return run_leaf<MODE, 4, 5, 3>(st, U, I, R, F, L, D, nodes, tops, nodes32, s_eff);
-    return run_leaf<MODE, 8, 12, 2>(st, U, I, R, F, L, D, nodes, tops, nodes32, s_eff);
+    if (R <= 16) return KRPS_LEAF(1, 1, 4);
+    if (R <= 32) return team == 1 ? KRPS_LEAF(2, 1, 4) : KRPS_LEAF(2, 3, 4);
+    if (R <= 64) return team == 2 ? KRPS_LEAF(4, 2, 3) : KRPS_LEAF(4, 5, 3);
+    return team == 6 ? KRPS_LEAF(8, 6, 2) : KRPS_LEAF(8, 12, 2);
   }
+#undef KRPS_LEAF
 }
 
 constexpr int MIN_S = 2;  // smallest register-run depth used above
 
 }  // namespace
+
+std::vector<int> build_team_choices(int R, krps_precision p) {
+  const bool split = p == KRPS_BF16X2;
+  if (R <= 16) return {1};
+  if (R <= 32) return split ? std::vector<int>{1, 3} : std::vector<int>{3, 1};
+  if (R <= 64) return split ? std::vector<int>{2, 5} : std::vector<int>{5, 2};
+  return split ? std::vector<int>{4, 8} : std::vector<int>{12, 6};
+}
 
 size_t tree_build_scratch_bytes(int64_t L, int R) {
   const int64_t a = ceil_div(L, int64_t(1) << MIN_S);
@@ -376,7 +389,7 @@ size_t tree_build_scratch_extent(const TreeShape& ts, int R) {
 
 hipError_t launch_tree_build(hipStream_t st, krps_precision p, const void* U, int64_t I, int R,
                              const TreeShape& ts, void* nodes, double* gram_full, double* scratch,
-                             size_t scratch_bytes, int split_terms, float* nodes32) {
+                             size_t scratch_bytes, int split_terms, float* nodes32, int team) {
   const int64_t TR = tri(R);
   if (p != KRPS_FP64) nodes32 = nullptr;  // only float64 trees carry a float32 copy
   const int64_t a_nodes = ceil_div(ts.L, int64_t(1) << MIN_S);
@@ -386,13 +399,13 @@ hipError_t launch_tree_build(hipStream_t st, krps_precision p, const void* U, in
   int s_eff = 0;
   hipError_t e;
   if (p == KRPS_FP64)
-    e = dispatch_leaf<M_F64>(st, U, I, R, ts.F, ts.L, ts.D, nodes, bufA, nodes32, s_eff);
+    e = dispatch_leaf<M_F64>(st, U, I, R, ts.F, ts.L, ts.D, nodes, bufA, nodes32, team, s_eff);
   else if (p == KRPS_FP32)
-    e = dispatch_leaf<M_F32>(st, U, I, R, ts.F, ts.L, ts.D, nodes, bufA, nodes32, s_eff);
+    e = dispatch_leaf<M_F32>(st, U, I, R, ts.F, ts.L, ts.D, nodes, bufA, nodes32, team, s_eff);
   else if (split_terms == 3)
-    e = dispatch_leaf<M_SPLIT3>(st, U, I, R, ts.F, ts.L, ts.D, nodes, bufA, nodes32, s_eff);
+    e = dispatch_leaf<M_SPLIT3>(st, U, I, R, ts.F, ts.L, ts.D, nodes, bufA, nodes32, team, s_eff);
   else
-    e = dispatch_leaf<M_SPLIT>(st, U, I, R, ts.F, ts.L, ts.D, nodes, bufA, nodes32, s_eff);
+    e = dispatch_leaf<M_SPLIT>(st, U, I, R, ts.F, ts.L, ts.D, nodes, bufA, nodes32, team, s_eff);
   if (e != hipSuccess) return e;
   int lev = ts.D - s_eff;
   int64_t n = ceil_div(ts.L, int64_t(1) << s_eff);

@@ -291,10 +291,14 @@ def test_autotune_measures_then_reads_the_cache(tmp_path):
     cache = tmp_path / "tune.jsonl"
     t1 = krps.autotune(ctx, Ud, u, "fp32", cache_path=cache)
     assert not t1["from_cache"] and t1["F"] in (8, 16, 32, 64) and t1["lps"] in (8, 16)
+    assert t1["team"] == 1
     t2 = krps.autotune(ctx, Ud, u, "fp32", cache_path=cache)
-    assert t2["from_cache"] and (t2["F"], t2["lps"]) == (t1["F"], t1["lps"])
+    assert t2["from_cache"]
+    assert (t2["F"], t2["lps"], t2["team"]) == (t1["F"], t1["lps"], t1["team"])
     # the tuned shape's draws against the float64 oracle
-    S1 = krps.Sampler(ctx, Ud, precision="fp32", F=t1["F"], lps=t1["lps"])
+    S1 = krps.Sampler(ctx, Ud, precision="fp32", F=t1["F"], lps=t1["lps"], team=t1["team"])
+    for j in range(3):
+        S1.refresh(j)       # rebuilt with the tuned team
     i1, p1, _ = S1.sample(-1, u)
     torch.cuda.synchronize()
     dr = osmp.KRPSampler(Us, F=t1["F"]).draw(-1, u.cpu().numpy(), scaled=True)
@@ -480,3 +484,53 @@ def test_entry_updates_match_a_rebuilt_oracle(env, prec):
             i2, p2, _ = S.sample(exclude, ud)
             S.set_filter(-1)
             assert torch.equal(idx, i2) and torch.equal(prob, p2)
+
+
+TUNE_R = [(16, (3000, 2500, 900)), (32, (4000, 1800, 700)), (64, (3000, 1500)),
+          (128, (900, 700))]
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x2"])
+@pytest.mark.parametrize("R,dims", TUNE_R)
+def test_every_tunable_shape_matches_the_oracle(env, prec, R, dims):
+    """Every shape the autotuner can pick -- leaf size, lanes per sample of
+    the walk, team width of the tree build -- draws, against the float64
+    oracle, under the same parity rules as the default shape, through the
+    single-problem walk and through the batched walk (whose shape classes
+    follow the samplers' lanes-per-sample choice)."""
+    krps, torch, ctx = env
+    lib = krps.lib()
+    Us = synth.gaussian_factors(dims, R, seed=600 + R, heavy_rows_frac=0.01)
+    J = 1024
+    u01 = synth.uniforms(J, len(dims), 601 + R)
+    ud = torch.from_numpy(u01).to(ctx.device)
+    lps_all = {16: (8, 16), 32: (16, 32, 64), 64: (64,), 128: (64,)}[R]
+    teams = {16: (1,), 32: (1, 3), 64: (2, 5), 128: (4, 8) if prec == "bf16x2" else (6, 12)}[R]
+    samplers, refs = [], []
+    for F in (R // 2, 2 * R):
+        ref = osmp.KRPSampler(Us, F=F).draw(-1, u01, scaled=prec != "fp64")
+        for lps in lps_all:
+            for team in teams:
+                S = krps.Sampler(ctx, to_dev(torch, ctx, Us, prec), precision=prec, F=F,
+                                 lps=lps, team=team)
+                for j in range(len(dims)):
+                    S.refresh(j)
+                idx, prob, _ = S.sample(-1, ud)
+                c = compare(idx.cpu().numpy(), ref, prec)
+                report(f"shape {prec} R={R} F={F} lps={lps} team={team}", c)
+                if prec == "bf16x2":
+                    assert c["mismatch"] <= BF16_MISMATCH * c["n"]
+                    assert c["needed_smargin"] <= bf16_scaled(R)
+                else:
+                    assert c["unexcused"] == 0
+                samplers.append(S)
+                refs.append((ref, idx))
+    # one batch over all of them: the batched walk of each class gives the
+    # single-problem walk's indices
+    B = krps.Batch(ctx, samplers, [-1] * len(samplers))
+    ib, _ = B.sample([ud] * len(samplers))
+    torch.cuda.synchronize()
+    for (ref, idx), got in zip(refs, ib):
+        assert torch.equal(got, idx)
+    # a team width the tree build does not have is refused
+    assert lib.krps_sampler_set_build(samplers[0].handle, 7) != 0
