@@ -435,6 +435,18 @@ typedef struct {
  * above).  The index and probability of every draw do not depend on it. */
 krps_status krps_sampler_set_lps(krps_sampler s, int lps);
 
+/* Deterministic sketched solves (on != 0) for runs that must repeat bit
+ * for bit: the SpMM forming Y (Appendix A.13) rounds every term
+ * coef x_e a_d[c] to a multiple of 2^-s and sums with int64 atomics, whose
+ * result does not depend on their order; s is the largest exponent with
+ * B 2^s <= 2^62 for B = the sum over all terms of |coef x_e| max_c |a_d[c]|
+ * (a bound on every row's sum of |terms|, itself reduced in a fixed
+ * order), so each term carries at most B 2^-63 of rounding and no sum
+ * overflows.  Y is then float64 on every path.  Default 0: float atomics,
+ * whose order varies the last bits of Y between runs.  Applies to
+ * krps_sketched_solve*, krps_als_sweep*; a captured sweep is re-captured. */
+krps_status krps_sampler_set_deterministic(krps_sampler s, int on);
+
 /* Selects the tree build's team width: waves that share one leaf's
  * 16 x 16 accumulator tiles (0 = default; R <= 16: 1; R <= 32: 1 or 3;
  * R <= 64: 2 or 5; above: 4 or 8 for KRPS_BF16X2, 6 or 12 otherwise).

@@ -133,6 +133,7 @@ def lib():
         "krps_sampler_check": (c.c_int, [P, c.POINTER(c.c_int64), c.POINTER(c.c_int64)]),
         "krps_sampler_set_filter": (c.c_int, [P, c.c_int]),
         "krps_sampler_set_build": (c.c_int, [P, c.c_int]),
+        "krps_sampler_set_deterministic": (c.c_int, [P, c.c_int]),
         "krps_sampler_update_entries": (c.c_int, [P, c.c_int, c.c_int64, c.POINTER(c.c_int64),
                                                   c.POINTER(c.c_int32),
                                                   c.POINTER(c.c_double)]),
@@ -249,6 +250,7 @@ class Sampler:
                                         PRECISION[precision], _ptr(self.ws), nbytes,
                                         ctypes.byref(h)))
         self.handle = h
+        self.deterministic = False
         if lps:
             check(lib().krps_sampler_set_lps(self.handle, int(lps)))
         if team:
@@ -282,6 +284,13 @@ class Sampler:
         check(lib().krps_sampler_check(self.handle, ctypes.byref(n), ctypes.byref(r)))
         self.rewalked = r.value
         return n.value
+
+    def set_deterministic(self, on=True):
+        """Sketched solves sum Y in fixed point (order-independent, so runs
+        repeat bit for bit) instead of with float atomics; Y is then float64
+        on every path."""
+        check(lib().krps_sampler_set_deterministic(self.handle, 1 if on else 0))
+        self.deterministic = bool(on)
 
     def set_filter(self, top):
         """Levels of each factor tree the float64 walk reads from the
@@ -687,7 +696,7 @@ class CPALS:
         torch = self.S.ctx.torch
         l, R, ws = self.layout, self.S.R, self.ws
         I = self.S.dims[j]
-        if self.S.precision == "bf16x2":
+        if self.S.precision == "bf16x2" and not self.S.deterministic:
             full = ws[l.Y:l.Y + I * R * 4].view(torch.float32).view(I, R)
         else:
             full = ws[l.Y:l.Y + I * R * 8].view(torch.float64).view(I, R)

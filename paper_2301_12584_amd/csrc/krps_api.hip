@@ -50,11 +50,12 @@ struct GraphKey {
   const void* sigma = nullptr;
   const void* ws = nullptr;
   int64_t J = -1;
-  int lps = -1, filter = -2, team = -1;
+  int lps = -1, filter = -2, team = -1, det = -1;
   uint64_t seed = 0, ctr_base = 0;
   bool operator==(const GraphKey& o) const {
     return t == o.t && uniforms == o.uniforms && sigma == o.sigma && ws == o.ws && J == o.J &&
-           lps == o.lps && filter == o.filter && team == o.team && seed == o.seed &&
+           lps == o.lps && filter == o.filter && team == o.team && det == o.det &&
+           seed == o.seed &&
            ctr_base == o.ctr_base;
   }
 };
@@ -80,6 +81,7 @@ struct krps_sampler_s {
   int prepared_exclude = -2;
   int lps = 0;                         // descent lanes per sample (0 = default)
   int team = 0;                        // waves per leaf team of the tree build (0 = default)
+  int det = 0;                         // solves: fixed-point (order-independent) SpMM
   // captured ALS sweep and what its kernels' arguments were made from
   hipGraphExec_t sweep_exec = nullptr;
   GraphKey gkey;
@@ -381,7 +383,7 @@ TensorPlan plan_tensor(int N, const int64_t* dims, int64_t nnz) {
   pl.temp = off;
   off += align_up(pl.temp_bytes);
   pl.acc = off;
-  off += 256;
+  off += align_up(norm2_bytes());
   pl.total = off;
   return pl;
 }
@@ -437,7 +439,7 @@ struct SolvePlan {
   krps_solve_layout lay;
   SolveHead head;
   size_t lo, hi, cnt, start, rank, partial, gscratch, gscratch_bytes;
-  size_t coef, slot, hkey, hW, hrep, rflag, rpos, rep, rstart, bsum, ymark, ybsum;
+  size_t coef, slot, hkey, hW, hWlo, hrep, rflag, rpos, rep, rstart, bsum, ymark, ybsum, det;
   int64_t H;
   int hbits;
   size_t total;
@@ -483,6 +485,8 @@ SolvePlan plan_solve(const krps_sampler_s* s, int64_t J) {
   off += align_up((size_t)pl.H * 8);
   pl.hW = off;
   off += align_up((size_t)pl.H * 8);
+  pl.hWlo = off;
+  off += align_up((size_t)pl.H * 8);
   pl.hrep = off;
   off += align_up((size_t)pl.H * 4);
   pl.rflag = off;
@@ -515,6 +519,8 @@ SolvePlan plan_solve(const krps_sampler_s* s, int64_t J) {
   off += align_up(row_bsum_bytes(Imax));
   pl.partial = off;
   off += align_up(solve_partial_bytes(R));
+  pl.det = off;
+  off += align_up(spmm_det_bytes());
   TreeShape tm;
   tm.init(J > 0 ? J : 1, R);
   pl.gscratch = off;
@@ -581,7 +587,7 @@ krps_status enqueue_solve(krps_sampler s, krps_tensor t, int j, int64_t J, const
   e = launch_pinv(st, R, (double*)(w + l.M), (double*)(w + l.Mp), (int32_t*)(w + pl.rank),
                   s->status);
   if (e != hipSuccess) return hip_fail(e, "pseudo-inverse");
-  FiberArgs fa;
+  FiberArgs fa{};
   fa.N = N;
   fa.j = j;
   fa.lead = t->lead[j];
@@ -613,18 +619,29 @@ krps_status enqueue_solve(krps_sampler s, krps_tensor t, int j, int64_t J, const
   fa.hot_rows = t->hot_rows[j];
   fa.nhot = (int)std::min<int64_t>(t->nhot, t->dims[j]);
   fa.expanded = (int64_t*)(w + l.expanded);
+  fa.hWlo = s->det ? (long long*)(w + pl.hWlo) : nullptr;
+  fa.wscale = s->det ? (double*)(w + pl.det + spmm_det_bytes() - 16) : nullptr;
   e = launch_lookup(st, fa);
   if (e != hipSuccess) return hip_fail(e, "fiber lookup");
   // only the rows of Y that the entries reach are cleared, summed into and
   // multiplied by M^+
   int32_t* yrows = (int32_t*)(w + l.yrows);
   int64_t* nyrows = (int64_t*)(w + l.nyrows);
+  // the deterministic mode sums Y in fixed point and converts it to float64
+  // (also on the split path, whose Y is otherwise float32)
+  const bool ydouble = !split || s->det;
   e = launch_rows(st, fa, s->I[j], (int32_t*)(w + pl.ymark), (int64_t*)(w + pl.ybsum), yrows,
-                  nyrows, w + l.Y, split);
+                  nyrows, w + l.Y, !ydouble);
   if (e != hipSuccess) return hip_fail(e, "rows of Y");
-  e = launch_spmm(st, split ? KRPS_BF16X2 : KRPS_FP64, fa, w + l.rows, w + l.Y);
+  if (s->det)
+    e = launch_spmm_det(st, split ? KRPS_BF16X2 : KRPS_FP64, fa, w + l.rows, w + l.Y, yrows, nyrows,
+                        (double*)(w + pl.det));
+  else
+    e = launch_spmm(st, split ? KRPS_BF16X2 : KRPS_FP64, fa, w + l.rows, w + l.Y);
   if (e != hipSuccess) return hip_fail(e, "SpMM");
-  e = launch_solve_gemm(st, s->prec, w + l.Y, (const double*)(w + l.Mp), s->U[j], s->I[j], yrows,
+  // the split path's factor is float32, like the float32 path's
+  const krps_precision gp = split && s->det ? KRPS_FP32 : s->prec;
+  e = launch_solve_gemm(st, gp, w + l.Y, (const double*)(w + l.Mp), s->U[j], s->I[j], yrows,
                         nyrows, R, (double*)(w + pl.partial), sigma);
   if (e != hipSuccess) return hip_fail(e, "solve GEMM");
   return build_tree(s, j);
@@ -694,7 +711,7 @@ krps_status sweep_entry(krps_sampler s, krps_tensor t, int64_t J, const double* 
   }
   // the captured graph is keyed by everything its kernels' arguments hold
   const GraphKey key{t,         uniforms,          sigma, ws, J, s->lps, s->filter_top,
-                     s->team,   seeded ? seed : 0, seeded ? ctr_base : 0};
+                     s->team,   s->det,            seeded ? seed : 0, seeded ? ctr_base : 0};
   if (s->sweep_exec == nullptr || !(s->gkey == key)) {
     if (s->sweep_exec != nullptr) {
       (void)hipGraphExecDestroy(s->sweep_exec);
@@ -911,6 +928,12 @@ krps_status krps_sampler_set_filter(krps_sampler s, int top) {
   if (s == nullptr) return fail(KRPS_EINVAL, "sampler is NULL");
   if (top < -1) return fail(KRPS_EINVAL, "top must be >= -1");
   s->filter_top = top;
+  return KRPS_OK;
+}
+
+krps_status krps_sampler_set_deterministic(krps_sampler s, int on) {
+  if (s == nullptr) return fail(KRPS_EINVAL, "sampler is NULL");
+  s->det = on ? 1 : 0;
   return KRPS_OK;
 }
 
@@ -1494,8 +1517,7 @@ krps_status krps_tensor_create(krps_ctx ctx, int N, const int64_t* dims, int64_t
     }
   }
   double* acc = (double*)(w + pl.acc);
-  hipError_t e = launch_fill_f64(s, acc, 1);
-  if (e == hipSuccess) e = launch_norm2(s, t->vals[0], t->nu, acc);
+  hipError_t e = launch_norm2(s, t->vals[0], t->nu, acc);
   if (e == hipSuccess) e = hipMemcpyAsync(&t->norm2, acc, 8, hipMemcpyDeviceToHost, s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);
   if (e != hipSuccess) {
@@ -2094,7 +2116,8 @@ krps_status krps_workspace_regions(int N, const int64_t* I, int R, int F, krps_p
   rl.add(2, "coef", pl.coef, span(pl.coef, pl.slot), (size_t)J * 8);
   rl.add(2, "slot", pl.slot, span(pl.slot, pl.hkey), (size_t)J * 4);
   rl.add(2, "hash keys", pl.hkey, span(pl.hkey, pl.hW), (size_t)pl.H * 8);
-  rl.add(2, "hash weights", pl.hW, span(pl.hW, pl.hrep), (size_t)pl.H * 8);
+  rl.add(2, "hash weights", pl.hW, span(pl.hW, pl.hWlo), (size_t)pl.H * 8);
+  rl.add(2, "hash weights, low words", pl.hWlo, span(pl.hWlo, pl.hrep), (size_t)pl.H * 8);
   rl.add(2, "hash reps", pl.hrep, span(pl.hrep, pl.rflag), (size_t)pl.H * 4);
   rl.add(2, "expand flags", pl.rflag, span(pl.rflag, pl.rpos), (size_t)J * 8);
   rl.add(2, "expand pos", pl.rpos, span(pl.rpos, pl.rep), (size_t)(J + 1) * 8);
@@ -2110,7 +2133,8 @@ krps_status krps_workspace_regions(int N, const int64_t* I, int R, int F, krps_p
   rl.add(2, "expanded entries", l.expanded, span(l.expanded, pl.ymark), 8);
   rl.add(2, "row marks", pl.ymark, span(pl.ymark, pl.ybsum), (size_t)pl.Imax * 4);
   rl.add(2, "row scan", pl.ybsum, span(pl.ybsum, pl.partial), row_bsum_bytes(pl.Imax));
-  rl.add(2, "solve partials", pl.partial, span(pl.partial, pl.gscratch), solve_partial_bytes(R));
+  rl.add(2, "solve partials", pl.partial, span(pl.partial, pl.det), solve_partial_bytes(R));
+  rl.add(2, "fixed-point bound", pl.det, span(pl.det, pl.gscratch), spmm_det_bytes());
   TreeShape tm;
   tm.init(J, R);
   rl.add(2, "M scratch", pl.gscratch, span(pl.gscratch, pl.total),
@@ -2148,7 +2172,7 @@ krps_status krps_workspace_regions(int N, const int64_t* I, int R, int F, krps_p
     rl.add(3, "hot index 1", tp.hi1, span(tp.hi1, tp.temp), (size_t)dmax * 4);
     rl.add(3, "sort temp", tp.temp, span(tp.temp, tp.acc),
            std::max(sort_temp_bytes(nnz), hot_temp_bytes(dmax)));
-    rl.add(3, "norm", tp.acc, span(tp.acc, tp.total), 8);
+    rl.add(3, "norm", tp.acc, span(tp.acc, tp.total), norm2_bytes());
   }
   // --- batched workspace: this sampler once per exclusion
   {

@@ -166,6 +166,10 @@ struct FiberArgs {
   const int32_t* hot_rows;    // [nhot] the hot rows
   int nhot;
   int64_t* expanded;          // out: entries the SpMM expands, or null
+  // deterministic mode (else null): hW holds the int64 high words of the
+  // fixed-point sums of w^2, hWlo the low words; wscale = {2^S, 2^-S}
+  long long* hWlo;            // [H]
+  double* wscale;             // [2]
 };
 
 // Rows of a mode with the most stored entries (kept per workgroup in LDS by
@@ -264,6 +268,7 @@ hipError_t build_fiber_index(hipStream_t st, int N, const int64_t* dims, int64_t
                              double* vals, int64_t* off, uint32_t* k0, uint32_t* k1, uint32_t* p0,
                              uint32_t* p1, void* temp, size_t temp_bytes, int64_t* nu);
 hipError_t launch_norm2(hipStream_t st, const double* vals, int64_t n, double* out);
+size_t norm2_bytes();  // out of launch_norm2: ||T||^2, then block partials
 // U_j = mat(T, j) S (range finder), accumulated in float64 Y (I x R) and
 // stored to U in the factor type.
 hipError_t launch_range_finder(hipStream_t st, krps_precision p, const int32_t* cols,
@@ -274,6 +279,13 @@ hipError_t build_hot_rows(hipStream_t st, const int32_t* col, int64_t n, int64_t
                           uint32_t* c0, uint32_t* c1, uint32_t* i0, uint32_t* i1, void* temp,
                           size_t temp_bytes, int32_t* rows, int8_t* slot);
 hipError_t launch_lookup(hipStream_t st, const FiberArgs& a);
+// The SpMM in fixed point (int64 atomics, order-independent), then the
+// listed rows of Y converted to float64 in place; p = KRPS_BF16X2 reads
+// float32 rows, otherwise float64.  det: spmm_det_bytes() of scratch (its
+// last two words are the fiber merge's scale, FiberArgs::wscale).
+hipError_t launch_spmm_det(hipStream_t st, krps_precision p, const FiberArgs& a, const void* rows,
+                           void* Y, const int32_t* list, const int64_t* count, double* det);
+size_t spmm_det_bytes();
 hipError_t launch_spmm(hipStream_t st, krps_precision p, const FiberArgs& a, const void* rows,
                        void* Y);
 // Rows of Y that the sampled fibers reach: cleared marks over I rows, then

@@ -109,7 +109,11 @@ __global__ void offsets_kernel(int64_t* __restrict__ off, const int32_t* __restr
   }
 }
 
-// ||T||^2 over the merged entries (each coordinate stored once).
+// ||T||^2 over the merged entries (each coordinate stored once): block
+// partials out[1 + b], then their sum in a fixed order into out[0], so the
+// norm repeats bit for bit.
+constexpr int NORM_BLOCKS = 1024;
+
 __global__ void norm2_kernel(const double* __restrict__ vals, int64_t n,
                              double* __restrict__ out) {
   __shared__ double red[256];
@@ -123,7 +127,14 @@ __global__ void norm2_kernel(const double* __restrict__ vals, int64_t n,
     if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
     __syncthreads();
   }
-  if (threadIdx.x == 0) atomicAdd(out, red[0]);
+  if (threadIdx.x == 0) out[1 + blockIdx.x] = red[0];
+}
+
+__global__ void norm2_final_kernel(double* __restrict__ out) {
+  if (threadIdx.x != 0) return;
+  double sum = 0.0;
+  for (int b = 0; b < NORM_BLOCKS; ++b) sum += out[1 + b];
+  out[0] = sum;
 }
 
 }  // namespace
@@ -208,9 +219,12 @@ hipError_t build_fiber_index(hipStream_t st, int N, const int64_t* dims, int64_t
 }
 
 hipError_t launch_norm2(hipStream_t st, const double* vals, int64_t n, double* out) {
-  hipLaunchKernelGGL(norm2_kernel, dim3(1024), dim3(256), 0, st, vals, n, out);
+  hipLaunchKernelGGL(norm2_kernel, dim3(NORM_BLOCKS), dim3(256), 0, st, vals, n, out);
+  hipLaunchKernelGGL(norm2_final_kernel, dim3(1), dim3(64), 0, st, out);
   return hipGetLastError();
 }
+
+size_t norm2_bytes() { return (size_t)(NORM_BLOCKS + 1) * 8; }
 
 // ---------------------------------------------------------------- hot rows
 //
@@ -353,8 +367,35 @@ __global__ void merge_clear_kernel(FiberArgs a) {
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < a.H;
        i += (int64_t)gridDim.x * blockDim.x) {
     a.hkey[i] = EMPTY_KEY;
-    a.hW[i] = 0.0;
+    a.hW[i] = 0.0;  // also the int64 zero of the fixed-point high words
+    if (a.hWlo != nullptr) a.hWlo[i] = 0;
     a.hrep[i] = INT32_MAX;
+  }
+}
+
+// Deterministic mode: the per-fiber sums of w_d^2 are fixed point with
+// 2^-S units, S = 93 - ceil(log2 B) for B = sum_d w_d^2 (>= every fiber's
+// sum; reduced here in a fixed order), kept as two int64 words (the high
+// word counts 2^32 units): about 93 significant bits, with every partial
+// sum exact, so their order does not matter.
+__global__ __launch_bounds__(1024) void w2_scale_kernel(FiberArgs a) {
+  __shared__ double red[1024];
+  double acc = 0.0;
+  for (int64_t d = threadIdx.x; d < a.J; d += blockDim.x) {
+    const double wd = a.w[d];
+    acc += wd * wd;
+  }
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int h = 512; h > 0; h >>= 1) {
+    if ((int)threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    const double B = red[0] * (1.0 + 1e-9);
+    const int S = B > 0.0 ? 93 - (ilogb(B) + 1) : 0;
+    a.wscale[0] = ldexp(1.0, S);
+    a.wscale[1] = ldexp(1.0, -S);
   }
 }
 
@@ -407,7 +448,16 @@ __global__ __launch_bounds__(256) void merge_insert_kernel(FiberArgs a) {
           h = (h + 1) & (uint64_t)(a.H - 1);
         }
         slot = (int)h;
-        atomicAdd(&a.hW[slot], v);
+        if (a.hWlo != nullptr) {
+          // t = v 2^S < 2^93 split exactly into 2^32 units and the rest
+          const double t = v * a.wscale[0];
+          const double hi = floor(t * 0x1p-32);
+          const double lo = floor(t - hi * 0x1p32);
+          atomicAdd((unsigned long long*)&a.hW[slot], (unsigned long long)(long long)hi);
+          atomicAdd((unsigned long long*)&a.hWlo[slot], (unsigned long long)(long long)lo);
+        } else {
+          atomicAdd(&a.hW[slot], v);
+        }
         atomicMin(&a.hrep[slot], dmin);
       }
       slot = __shfl(slot, leader);
@@ -431,7 +481,12 @@ __global__ void merge_finish_kernel(FiberArgs a) {
     double coef = 0.0;
     if (s >= 0 && a.hrep[s] == (int)d) {
       c = (a.hi[d] - a.lo[d] + CH - 1) / CH;
-      coef = a.hW[s] / a.w[d];
+      double W = a.hW[s];
+      if (a.hWlo != nullptr) {
+        const long long hi = __double_as_longlong(a.hW[s]);
+        W = ((double)hi * 0x1p32 + (double)a.hWlo[s]) * a.wscale[1];
+      }
+      coef = W / a.w[d];
     }
     a.cnt[d] = c;
     a.coef[d] = coef;
@@ -617,6 +672,150 @@ __global__ __launch_bounds__(256) void spmm_kernel(FiberArgs a, const T* __restr
   }
 }
 
+// Deterministic SpMM (fixed point).  Every term coef x_e rows[d][c] is
+// rounded to an integer multiple of 2^-s and summed with int64 atomics,
+// whose result does not depend on their order.  s is the largest exponent
+// with B 2^s <= 2^62 for a bound B >= every row's sum of |terms| (the sum
+// over all terms of |coef_d x_e| max_c |rows[d][c]|), so no partial sum
+// overflows; each term then carries at most 2^-(s+1) <= B 2^-63 of
+// rounding.  B is reduced in a fixed order: each wavefront walks the same
+// work items in every run, each block sums its waves in order, and one
+// thread sums the blocks in order.
+constexpr int DET_BLOCKS = 1024;
+constexpr int DET_IPW = 8;
+
+template <typename T>
+__global__ __launch_bounds__(256) void spmm_bound_kernel(FiberArgs a, const T* __restrict__ rows,
+                                                         double* __restrict__ partial) {
+  __shared__ double wsum[4];
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int R = a.R;
+  const int64_t nrep = a.rpos[a.J];
+  const int64_t total = a.rstart[nrep];
+  const int64_t nw = (int64_t)gridDim.x * (blockDim.x >> 6);
+  double acc = 0.0;
+  for (int64_t c0 = ((int64_t)blockIdx.x * (blockDim.x >> 6) + wave) * DET_IPW; c0 < total;
+       c0 += nw * DET_IPW) {
+    int64_t l = 0, r = nrep;  // last k with rstart[k] <= c0
+    while (r - l > 1) {
+      const int64_t m = (l + r) >> 1;
+      if (a.rstart[m] <= c0) l = m; else r = m;
+    }
+    int64_t k = l;
+    const int64_t c1 = c0 + DET_IPW < total ? c0 + DET_IPW : total;
+    for (int64_t c = c0; c < c1; ++c) {
+      while (k + 1 < nrep && a.rstart[k + 1] <= c) ++k;
+      const int64_t d = a.rep[k];
+      const int64_t e = a.lo[d] + (c - a.rstart[k]) * CH + lane;
+      double x = e < a.hi[d] ? fabs(a.vals[e]) : 0.0;
+      double m = 0.0;
+      for (int q = lane; q < R; q += 64) m = fmax(m, fabs((double)rows[d * R + q]));
+#pragma unroll
+      for (int o = 32; o > 0; o >>= 1) {
+        x += __shfl_xor(x, o, 64);
+        m = fmax(m, __shfl_xor(m, o, 64));
+      }
+      acc += fabs(a.coef[d]) * m * x;  // the same value in every lane
+    }
+  }
+  if (lane == 0) wsum[wave] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) partial[blockIdx.x] = ((wsum[0] + wsum[1]) + wsum[2]) + wsum[3];
+}
+
+// scale[0] = 2^s, scale[1] = 2^-s from the block bounds.
+__global__ void spmm_scale_kernel(const double* __restrict__ partial, int n,
+                                  double* __restrict__ scale) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  double B = 0.0;
+  for (int i = 0; i < n; ++i) B += partial[i];
+  B *= 1.0 + 1e-9;  // the bound's own rounding
+  int s = 0;
+  if (B > 0.0) s = 62 - (ilogb(B) + 1);  // 2^(ilogb + 1) > B
+  scale[0] = ldexp(1.0, s);
+  scale[1] = ldexp(1.0, -s);
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void spmm_det_kernel(FiberArgs a, const T* __restrict__ rows,
+                                                       const double* __restrict__ scale,
+                                                       unsigned long long* __restrict__ Y) {
+  extern __shared__ unsigned long long hot_q[];  // [nhot][R]
+  const int lane = threadIdx.x & 63;
+  const int R = a.R;
+  const double sc = scale[0];
+  for (int q = threadIdx.x; q < a.nhot * R; q += blockDim.x) hot_q[q] = 0ull;
+  __syncthreads();
+  const int64_t nrep = a.rpos[a.J];
+  const int64_t total = a.rstart[nrep];
+  const int64_t nw = (int64_t)gridDim.x * (blockDim.x >> 6);
+  const int32_t* __restrict__ ij = a.cols + (int64_t)a.j * a.nnz;
+  for (int64_t c0 = ((int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6)) * SPMM_IPW;
+       c0 < total; c0 += nw * SPMM_IPW) {
+    int64_t l = 0, r = nrep;  // last k with rstart[k] <= c0
+    while (r - l > 1) {
+      const int64_t m = (l + r) >> 1;
+      if (a.rstart[m] <= c0) l = m; else r = m;
+    }
+    int64_t k = l;
+    const int64_t c1 = c0 + SPMM_IPW < total ? c0 + SPMM_IPW : total;
+    for (int64_t c = c0; c < c1; ++c) {
+      while (k + 1 < nrep && a.rstart[k + 1] <= c) ++k;
+      const int64_t d = a.rep[k];
+      const int64_t e0 = a.lo[d] + (c - a.rstart[k]) * CH;
+      const int64_t e1 = e0 + CH < a.hi[d] ? e0 + CH : a.hi[d];
+      const double cd = a.coef[d];
+      const double r0 = lane < R ? (double)rows[d * R + lane] : 0.0;
+      const double r1 = lane + 64 < R ? (double)rows[d * R + lane + 64] : 0.0;
+      const int64_t et = e0 + lane < e1 ? e0 + lane : e1 - 1;
+      const double xv = cd * a.vals[et];
+      const int iv = ij[et];
+      const int hv = a.hot_slot[iv];
+      const int n = (int)(e1 - e0);
+      for (int t = 0; t < n; ++t) {
+        const double coef = __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(xv), t),
+                                             __builtin_amdgcn_readlane(__double2loint(xv), t));
+        const int64_t i = __builtin_amdgcn_readlane(iv, t);
+        const int hs = __builtin_amdgcn_readlane(hv, t);
+        const unsigned long long q0 = (unsigned long long)(long long)rint(coef * r0 * sc);
+        const unsigned long long q1 = (unsigned long long)(long long)rint(coef * r1 * sc);
+        if (hs >= 0) {
+          unsigned long long* acc = hot_q + hs * R;
+          if (lane < R) atomicAdd(&acc[lane], q0);
+          if (lane + 64 < R) atomicAdd(&acc[lane + 64], q1);
+        } else {
+          if (lane < R) atomicAdd(&Y[i * R + lane], q0);
+          if (lane + 64 < R) atomicAdd(&Y[i * R + lane + 64], q1);
+        }
+      }
+    }
+  }
+  __syncthreads();
+  for (int q = threadIdx.x; q < a.nhot * R; q += blockDim.x) {
+    const unsigned long long v = hot_q[q];
+    if (v != 0ull) atomicAdd(&Y[(int64_t)a.hot_rows[q / R] * R + q % R], v);
+  }
+}
+
+// The listed rows of Y from fixed point to float64, in place.
+__global__ __launch_bounds__(256) void fix_to_double_kernel(double* __restrict__ Y, int R,
+                                                            const int32_t* __restrict__ list,
+                                                            const int64_t* __restrict__ count,
+                                                            const double* __restrict__ scale) {
+  const int lane = threadIdx.x & 63;
+  const int64_t n = *count;
+  const double inv = scale[1];
+  const int64_t nw = (int64_t)gridDim.x * (blockDim.x >> 6);
+  for (int64_t p = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); p < n; p += nw) {
+    double* y = Y + (int64_t)list[p] * R;
+    for (int c = lane; c < R; c += 64) {
+      const long long v = (long long)__double_as_longlong(y[c]);
+      y[c] = (double)v * inv;
+    }
+  }
+}
+
 // The rows of mode j that the sampled fibers' entries reach: mark[i] = 1.
 // Traverses the compacted work items as the SpMM does, one item per
 // wavefront (lane t takes the item's entry t).
@@ -700,6 +899,7 @@ hipError_t launch_lookup(hipStream_t st, const FiberArgs& a) {
   int64_t hb = (a.H + 255) / 256;
   if (hb > 4096) hb = 4096;
   hipLaunchKernelGGL(merge_clear_kernel, dim3((unsigned)hb), dim3(256), 0, st, a);
+  if (a.hWlo != nullptr) hipLaunchKernelGGL(w2_scale_kernel, dim3(1), dim3(1024), 0, st, a);
   hipLaunchKernelGGL(merge_insert_kernel, dim3((unsigned)blocks), dim3(256), 0, st, a);
   hipLaunchKernelGGL(merge_finish_kernel, dim3((unsigned)blocks), dim3(256), 0, st, a);
   launch_scan(st, a.cnt, a.start, a.bsum, a.J);
@@ -732,6 +932,31 @@ hipError_t launch_rows(hipStream_t st, const FiberArgs& a, int64_t I, int32_t* m
                        list, count);
   return hipGetLastError();
 }
+
+hipError_t launch_spmm_det(hipStream_t st, krps_precision p, const FiberArgs& a, const void* rows,
+                           void* Y, const int32_t* list, const int64_t* count, double* det) {
+  // det: DET_BLOCKS block bounds, then the scale pair
+  double* scale = det + DET_BLOCKS;
+  const size_t lds = (size_t)a.nhot * a.R * 8;
+  if (p == KRPS_BF16X2) {
+    hipLaunchKernelGGL(spmm_bound_kernel<float>, dim3(DET_BLOCKS), dim3(256), 0, st, a,
+                       (const float*)rows, det);
+    hipLaunchKernelGGL(spmm_scale_kernel, dim3(1), dim3(64), 0, st, det, DET_BLOCKS, scale);
+    hipLaunchKernelGGL(spmm_det_kernel<float>, dim3(2048), dim3(256), lds, st, a,
+                       (const float*)rows, scale, (unsigned long long*)Y);
+  } else {
+    hipLaunchKernelGGL(spmm_bound_kernel<double>, dim3(DET_BLOCKS), dim3(256), 0, st, a,
+                       (const double*)rows, det);
+    hipLaunchKernelGGL(spmm_scale_kernel, dim3(1), dim3(64), 0, st, det, DET_BLOCKS, scale);
+    hipLaunchKernelGGL(spmm_det_kernel<double>, dim3(2048), dim3(256), lds, st, a,
+                       (const double*)rows, scale, (unsigned long long*)Y);
+  }
+  hipLaunchKernelGGL(fix_to_double_kernel, dim3(2048), dim3(256), 0, st, (double*)Y, a.R, list,
+                     count, scale);
+  return hipGetLastError();
+}
+
+size_t spmm_det_bytes() { return (size_t)(DET_BLOCKS + 4) * 8; }
 
 hipError_t launch_spmm(hipStream_t st, krps_precision p, const FiberArgs& a, const void* rows,
                        void* Y) {

@@ -469,3 +469,48 @@ def test_range_finder_init_matches_oracle(env, prec, R):
         np.testing.assert_allclose(got, ref, rtol=tol, atol=tol * np.abs(ref).max())
         # the tree was rebuilt: its root is the Gram of the new factor
         np.testing.assert_allclose(S.gram(j).cpu().numpy(), got.T @ got, rtol=1e-6, atol=1e-6)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x2"])
+def test_deterministic_solves_repeat_bit_for_bit(env, prec):
+    """krps_sampler_set_deterministic: two independent runs of three sweeps
+    (eager and replayed from a graph) on a 2e5-entry Zipf tensor give
+    bit-identical factors, sigma and fits, and every solve still matches
+    the oracle step by step on the GPU's own draw (the fixed-point Y is as
+    accurate as the float64 one)."""
+    krps, torch, ctx = env
+    dims, R, J = (3000, 2000, 500), 16, 4096
+    # the workload of test_zipf_tensor_als_matches_oracle, same uniforms
+    idx, val = synth.sparse_tensor(dims, 200_000, 1.2, seed=44)
+    U0 = synth.gaussian_factors(dims, R, seed=45)
+    Tor = ocp.SparseTensor(dims, idx, val)
+    runs = []
+    for use_graph in (False, True):
+        S, T, A = make(krps, torch, ctx, dims, idx, val, U0, prec, J)
+        S.set_deterministic(True)
+        for k in range(3):
+            A.normalize(k)
+        A.sigma.fill_(1.0)
+        fits = []
+        for s in range(3):
+            u = _sweep_uniforms(700, s, 3, J)
+            if use_graph:
+                A.sweep(torch.from_numpy(u).to(ctx.device), use_graph=True)
+            else:
+                for j in range(3):
+                    before = [U.cpu().numpy().astype(np.float64) for U in S.factors]
+                    A.solve(j, torch.from_numpy(u[j]).to(ctx.device))
+                    torch.cuda.synchronize()
+                    got = {k: v.cpu().numpy() for k, v in A.parts(j).items()}
+                    errs = check_solve(Tor, before, j, got, S.factors[j].cpu().numpy(),
+                                       A.sigma.cpu().numpy(), prec)
+                    print(f"deterministic {prec} sweep {s} solve {j}: " +
+                          " ".join(f"{k} {v:.1e}" for k, v in errs.items()), flush=True)
+            fits.append(A.fit())
+        torch.cuda.synchronize()
+        runs.append(([U.cpu().clone() for U in S.factors], A.sigma.cpu().clone(), fits))
+        assert S.check_status() == 0
+    (f0, s0, fit0), (f1, s1, fit1) = runs
+    for a, b in zip(f0, f1):
+        assert torch.equal(a, b)
+    assert torch.equal(s0, s1) and fit0 == fit1
