@@ -27,12 +27,16 @@ namespace krps {
 namespace {
 
 constexpr int DESC_WAVES = 4;  // waves per block
-// Waves per SIMD the register allocation of the walk kernels must allow
-// (the walk is bound by the latency of its dependent node reads, so
-// occupancy matters more than registers).
-#ifndef KRPS_DESC_MIN_WAVES
-#define KRPS_DESC_MIN_WAVES 1
-#endif
+// Waves per SIMD the register allocation of a walk shape must allow: the
+// walk is bound by the latency of its dependent reads, so samples in
+// flight matter more than registers.  With the packed weights in LDS the
+// shapes with 17 entries per lane fit three waves (<= 168 VGPRs) and those
+// with 33 two (<= 256, no AGPR overflow); the LDS of a block (4 waves of
+// packed weights, h and the index table) allows that many blocks per CU.
+template <int NP>
+constexpr int desc_min_waves() {
+  return NP >= 33 ? 2 : NP >= 17 ? 3 : 1;
+}
 
 // Sum over the LPS lanes of one lane group (groups are aligned, LPS a
 // power of two <= 64); every lane of the group gets the result.  Within a
@@ -112,10 +116,13 @@ __device__ __forceinline__ double lane_value(double v) {
 }
 
 // Packed outer product h h^T of the group's float64 vector in hb (LDS),
-// off-diagonal terms doubled; lane sl of the group holds entries sl + LPS m.
+// off-diagonal terms doubled, held in LDS: entry sl + LPS m at v[LPS m] of
+// lane sl's pointer (the group's slot of NP LPS doubles, offset by sl), so
+// that each lane reads back only what it wrote (no barrier) and a wave's
+// reads of one m are consecutive doubles (no bank conflicts).
 template <int LPS, int NP>
 struct Packed {
-  double v[NP];
+  double* v;
 };
 
 // Branch-free: entries past the triangle read entry tri-1 and get weight 0.
@@ -131,7 +138,7 @@ __device__ __forceinline__ void build_packed(Packed<LPS, NP>& P, const double* h
     const uint16_t ab = tab[p < TR ? p : TR - 1];
     const int a = ab & 0xff, b = ab >> 8;
     const double w = p < TR ? (a != b ? 2.0 : 1.0) : 0.0;
-    P.v[m] = w * hb[a] * hb[b];
+    P.v[LPS * m] = w * hb[a] * hb[b];
   }
 }
 
@@ -158,7 +165,7 @@ __device__ __forceinline__ double node_mass(const Packed<LPS, NP>& P, const doub
   // four partial sums: the dependent chain of FMAs is a quarter as long
   double acc[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-  for (int m = 0; m < NP; ++m) acc[m & 3] += P.v[m] * (double)g[m];
+  for (int m = 0; m < NP; ++m) acc[m & 3] += P.v[LPS * m] * (double)g[m];
   return group_sum<LPS>((acc[0] + acc[1]) + (acc[2] + acc[3]));
 }
 
@@ -220,7 +227,7 @@ __device__ __forceinline__ MassB node_mass32(const Packed<LPS, NP>& P, const dou
   double acc[4] = {0.0, 0.0, 0.0, 0.0}, sab[2] = {0.0, 0.0};
 #pragma unroll
   for (int m = 0; m < NP; ++m) {
-    const double t = P.v[m] * (double)g[m];
+    const double t = P.v[LPS * m] * (double)g[m];
     acc[m & 3] += t;
     sab[m & 1] += fabs(t);
   }
@@ -442,7 +449,7 @@ __device__ __forceinline__ int64_t walk_table_group(const double* __restrict__ t
 // loads of each chunk of up to 32 values are issued together.
 template <int RMAX, typename T>
 __device__ __forceinline__ double row_dot(const T* __restrict__ ur, const double* hb, int R) {
-  constexpr int CH = RMAX < 32 ? RMAX : 32;
+  constexpr int CH = RMAX < 32 ? RMAX : (sizeof(T) == 8 ? 16 : 32);
   double acc = 0;
   if constexpr (std::is_same_v<T, float>) {
     if ((R & 3) == 0) {
@@ -584,7 +591,8 @@ __device__ __forceinline__ int64_t leaf_scan_filtered(const T* __restrict__ U, i
 // LPS == 64).
 template <typename T, int LPS, int NP, int RMAX>
 __device__ __forceinline__ void descend(const DescentArgs& a, int64_t base,
-                                        const uint16_t* __restrict__ tab, double* hb, int lane) {
+                                        const uint16_t* __restrict__ tab, double* hb, int lane,
+                                        double* pslot) {
   constexpr int HE = (RMAX + LPS - 1) / LPS;  // history entries per lane
   const int R = a.R;
   const int TR = R * (R + 1) / 2;
@@ -599,7 +607,7 @@ __device__ __forceinline__ void descend(const DescentArgs& a, int64_t base,
   double h[HE];
 #pragma unroll
   for (int i = 0; i < HE; ++i) h[i] = 1.0;
-  Packed<LPS, NP> P;
+  Packed<LPS, NP> P{pslot + sl};
   for (int st = 0; st < a.nsteps; ++st) {
     const int k = a.order[st];
     const ModeDesc& md = a.mode[k];
@@ -789,21 +797,24 @@ __device__ __forceinline__ void fill_tab(uint16_t* tab, int R, int t0, int nt) {
 // One problem: persistent grid-stride loop of the wavefronts over groups
 // of 64 / LPS samples.
 template <typename T, int LPS, int NP, int RMAX>
-__global__ __launch_bounds__(64 * DESC_WAVES, KRPS_DESC_MIN_WAVES) void descent_kernel(DescentArgs a) {
+__global__ __launch_bounds__(64 * DESC_WAVES, desc_min_waves<NP>()) void descent_kernel(
+    DescentArgs a) {
   constexpr int G = 64 / LPS;
   extern __shared__ unsigned char smem_raw[];
   const int R = a.R;
   const int TR = R * (R + 1) / 2;
   uint16_t* tab = (uint16_t*)smem_raw;
   double* hb_all = (double*)(smem_raw + ((TR * 2 + 15) / 16) * 16);
+  double* p_all = hb_all + DESC_WAVES * 128;
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
   double* hb = hb_all + wave * 128 + (lane / LPS) * RMAX;
+  double* pslot = p_all + (wave * 64 + (lane / LPS) * LPS) * NP;
   fill_tab(tab, R, threadIdx.x, blockDim.x);
   __syncthreads();
   const int64_t stride = (int64_t)gridDim.x * DESC_WAVES * G;
   for (int64_t base = ((int64_t)blockIdx.x * DESC_WAVES + wave) * G; base < a.J; base += stride)
-    descend<T, LPS, NP, RMAX>(a, base, tab, hb, lane);
+    descend<T, LPS, NP, RMAX>(a, base, tab, hb, lane, pslot);
 }
 
 // Shape classes of the batched walk (lanes per sample, packed entries per
@@ -827,14 +838,16 @@ template <> struct Cls<8> { static constexpr int LPS = 64, NP = 9, RMAX = 32; };
 // start first.  One kernel per class keeps each class's register budget
 // (and so its occupancy) instead of the largest class's.
 template <typename T, int CLS>
-__global__ __launch_bounds__(64 * DESC_WAVES, KRPS_DESC_MIN_WAVES) void descent_batched_kernel(
+__global__ __launch_bounds__(64 * DESC_WAVES, desc_min_waves<Cls<CLS>::NP>()) void descent_batched_kernel(
     const BatchProblem* __restrict__ probs, int P, int64_t ntask,
     unsigned long long* __restrict__ counter) {
   using C = Cls<CLS>;
   __shared__ double hb_all[DESC_WAVES * 128];
+  __shared__ double p_all[DESC_WAVES * 64 * (C::NP > 0 ? C::NP : 1)];
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
   double* hb = hb_all + wave * 128 + (lane / C::LPS) * C::RMAX;
+  double* pslot = p_all + (wave * 64 + (lane / C::LPS) * C::LPS) * C::NP;
   // task numbers are wave-uniform (scalar registers), so the problem's
   // descriptor is read with scalar loads; the next task is claimed before
   // the current one is walked, which hides the counter's latency
@@ -853,7 +866,7 @@ __global__ __launch_bounds__(64 * DESC_WAVES, KRPS_DESC_MIN_WAVES) void descent_
     }
     const BatchProblem& b = probs[lo];
     const int64_t base = (t - b.task0) * (int64_t)(64 / C::LPS);
-    descend<T, C::LPS, C::NP, C::RMAX>(b.a, base, b.tab, hb, lane);
+    descend<T, C::LPS, C::NP, C::RMAX>(b.a, base, b.tab, hb, lane, pslot);
     next = __builtin_amdgcn_readfirstlane(claim);
   }
 }
@@ -915,7 +928,8 @@ template <typename T, int LPS, int NP, int RMAX>
 hipError_t run_descent(hipStream_t st, const DescentArgs& a) {
   constexpr int G = 64 / LPS;
   const int TR = a.R * (a.R + 1) / 2;
-  const size_t lds = ((TR * 2 + 15) / 16) * 16 + DESC_WAVES * 128 * sizeof(double);
+  const size_t lds = ((TR * 2 + 15) / 16) * 16 + DESC_WAVES * 128 * sizeof(double) +
+                     (size_t)DESC_WAVES * 64 * NP * sizeof(double);
   int64_t blocks = (a.J + DESC_WAVES * G - 1) / (DESC_WAVES * G);
   if (blocks > 256 * 8) blocks = 256 * 8;
   if (blocks < 1) blocks = 1;
