@@ -319,10 +319,13 @@ krps_status krps_tensor_destroy(krps_tensor t);
 krps_status krps_tensor_norm2(krps_tensor t, double* out);
 /* Number of stored entries: distinct coordinates after merging duplicates. */
 krps_status krps_tensor_stored_entries(krps_tensor t, int64_t* out);
-/* The rows of mode j that the SpMM accumulates per workgroup: the
- * min(32, dims[j]) rows with the most stored entries (ties broken either
- * way), written to rows (host, room for 32 values), their number to *n.
- * Copies from the device on the context's stream and waits for it. */
+/* The rows of mode j with the most stored entries, in decreasing count:
+ * min(KRPS_HOT_ROWS, dims[j]) of them (ties broken either way), written to
+ * rows (host, room for KRPS_HOT_ROWS values), their number to *n.  The
+ * SpMM and the exact MTTKRP accumulate the first min(n, 131072 / (8 R)) of
+ * them per workgroup in LDS.  Copies from the device on the context's
+ * stream and waits for it. */
+#define KRPS_HOT_ROWS 512
 krps_status krps_tensor_hot_rows(krps_tensor t, int j, int32_t* rows, int* n);
 
 /* Bytes of scratch for one sketched solve / sweep / fit with J samples. */

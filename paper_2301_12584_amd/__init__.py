@@ -568,8 +568,9 @@ class Tensor:
         return v.value
 
     def hot_rows(self, j):
-        """Rows of mode ``j`` with the most stored entries (host int list)."""
-        buf = (ctypes.c_int32 * 32)()
+        """Rows of mode ``j`` with the most stored entries, in decreasing
+        count (host int list of at most 512)."""
+        buf = (ctypes.c_int32 * 512)()
         n = ctypes.c_int()
         check(lib().krps_tensor_hot_rows(self.handle, int(j), buf, ctypes.byref(n)))
         return [int(buf[i]) for i in range(n.value)]

@@ -105,7 +105,7 @@ struct krps_tensor_s {
   std::vector<double*> vals;   // per mode: [nu], duplicates summed
   std::vector<int64_t*> off;   // per mode: [dims[lead] + 1]
   std::vector<int> lead;
-  std::vector<int8_t*> hot_slot;   // per mode: [dims[j]]
+  std::vector<int16_t*> hot_slot;  // per mode: [dims[j]]
   std::vector<int32_t*> hot_rows;  // per mode: [nhot]
   int nhot = 0;
   double norm2 = 0;
@@ -356,13 +356,13 @@ TensorPlan plan_tensor(int N, const int64_t* dims, int64_t nnz) {
   off += align_up((size_t)nnz * 4);
   pl.p1 = off;
   off += align_up((size_t)nnz * 4);
-  // hot rows: per mode a slot byte per row and the rows; temporaries sized
+  // hot rows: per mode a 16-bit slot per row and the rows; temporaries sized
   // for the largest mode
   int64_t dmax = 1;
   for (int j = 0; j < N; ++j) {
     dmax = dims[j] > dmax ? dims[j] : dmax;
     pl.hslot_off.push_back(off);
-    off += align_up((size_t)dims[j]);
+    off += align_up((size_t)dims[j] * 2);
     pl.hrows_off.push_back(off);
     off += align_up((size_t)HOT_ROWS * 4);
   }
@@ -1504,7 +1504,7 @@ krps_status krps_tensor_create(krps_ctx ctx, int N, const int64_t* dims, int64_t
   const int nhot = (int)std::min<int64_t>(pl.nhot, 1 << 20);
   t->nhot = nhot;
   for (int j = 0; j < N; ++j) {
-    t->hot_slot.push_back((int8_t*)(w + pl.hslot_off[j]));
+    t->hot_slot.push_back((int16_t*)(w + pl.hslot_off[j]));
     t->hot_rows.push_back((int32_t*)(w + pl.hrows_off[j]));
     const int nh = (int)std::min<int64_t>(nhot, dims[j]);
     hipError_t e = build_hot_rows(s, t->cols[j] + (int64_t)j * t->nu, t->nu, dims[j], nh,
@@ -2161,7 +2161,7 @@ krps_status krps_workspace_regions(int N, const int64_t* I, int R, int F, krps_p
       dmax = std::max<int64_t>(dmax, I[j]);
       char nm[32];
       snprintf(nm, sizeof(nm), "hot slots %d", j);
-      rl.add(3, nm, tp.hslot_off[j], span(tp.hslot_off[j], tp.hrows_off[j]), (size_t)I[j]);
+      rl.add(3, nm, tp.hslot_off[j], span(tp.hslot_off[j], tp.hrows_off[j]), (size_t)I[j] * 2);
       snprintf(nm, sizeof(nm), "hot rows %d", j);
       const size_t hnext = j + 1 < N ? tp.hslot_off[j + 1] : tp.hc0;
       rl.add(3, nm, tp.hrows_off[j], span(tp.hrows_off[j], hnext), (size_t)HOT_ROWS * 4);

@@ -162,7 +162,7 @@ struct FiberArgs {
   int32_t* rep;               // [J] expanding samples in sample order
   int64_t* rstart;            // [J + 1] first work item of each of them, then the total
   int64_t* bsum;              // [ceil(J / 1024) + 1] scan tile totals
-  const int8_t* hot_slot;     // [dims[j]] slot of a hot row of mode j, -1 otherwise
+  const int16_t* hot_slot;    // [dims[j]] slot of a hot row of mode j, -1 otherwise
   const int32_t* hot_rows;    // [nhot] the hot rows
   int nhot;
   int64_t* expanded;          // out: entries the SpMM expands, or null
@@ -174,7 +174,15 @@ struct FiberArgs {
 
 // Rows of a mode with the most stored entries (kept per workgroup in LDS by
 // the SpMM).
-constexpr int HOT_ROWS = 32;
+constexpr int HOT_ROWS = KRPS_HOT_ROWS;
+// LDS a workgroup of the SpMM-like kernels gives to hot-row accumulators
+// (8 bytes per entry): the hot rows it accumulates are the first
+// hot_rows_used() of the mode's list (slots in decreasing entry count).
+constexpr size_t HOT_LDS_BYTES = size_t(128) << 10;
+inline int hot_rows_used(int nhot, int R) {
+  const int cap = (int)(HOT_LDS_BYTES / ((size_t)R * 8));
+  return nhot < cap ? nhot : cap;
+}
 
 // Exact MTTKRP of mode j over a tensor's stored entries (mode j's copy).
 struct MttkrpArgs {
@@ -183,7 +191,7 @@ struct MttkrpArgs {
   const int32_t* cols;        // [N][nnz] mode j's sorted, merged entries
   const double* vals;         // [nnz]
   const void* U[KRPS_MAX_MODES];
-  const int8_t* hot_slot;     // [dims[j]] slot of a hot row of mode j, -1 otherwise
+  const int16_t* hot_slot;    // [dims[j]] slot of a hot row of mode j, -1 otherwise
   const int32_t* hot_rows;    // [nhot]
   int nhot;
 };
@@ -277,7 +285,7 @@ hipError_t launch_range_finder(hipStream_t st, krps_precision p, const int32_t* 
 size_t hot_temp_bytes(int64_t dim);
 hipError_t build_hot_rows(hipStream_t st, const int32_t* col, int64_t n, int64_t dim, int nhot,
                           uint32_t* c0, uint32_t* c1, uint32_t* i0, uint32_t* i1, void* temp,
-                          size_t temp_bytes, int32_t* rows, int8_t* slot);
+                          size_t temp_bytes, int32_t* rows, int16_t* slot);
 hipError_t launch_lookup(hipStream_t st, const FiberArgs& a);
 // The SpMM in fixed point (int64 atomics, order-independent), then the
 // listed rows of Y converted to float64 in place; p = KRPS_BF16X2 reads

@@ -276,7 +276,7 @@ __global__ __launch_bounds__(256) void hot_count_kernel(const int32_t* __restric
 }
 
 __global__ void hot_clear_kernel(uint32_t* __restrict__ count, uint32_t* __restrict__ index,
-                                 int8_t* __restrict__ slot, int64_t dim) {
+                                 int16_t* __restrict__ slot, int64_t dim) {
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < dim;
        i += (int64_t)gridDim.x * blockDim.x) {
     count[i] = 0;
@@ -286,12 +286,11 @@ __global__ void hot_clear_kernel(uint32_t* __restrict__ count, uint32_t* __restr
 }
 
 __global__ void hot_pick_kernel(const uint32_t* __restrict__ sorted_index, int nhot,
-                                int32_t* __restrict__ rows, int8_t* __restrict__ slot) {
-  const int s = threadIdx.x;
-  if (s < nhot) {
+                                int32_t* __restrict__ rows, int16_t* __restrict__ slot) {
+  for (int s = threadIdx.x; s < nhot; s += blockDim.x) {
     const uint32_t i = sorted_index[s];
     rows[s] = (int32_t)i;
-    slot[i] = (int8_t)s;
+    slot[i] = (int16_t)s;
   }
 }
 
@@ -307,14 +306,14 @@ size_t hot_temp_bytes(int64_t dim) {
 
 hipError_t build_hot_rows(hipStream_t st, const int32_t* col, int64_t n, int64_t dim, int nhot,
                           uint32_t* c0, uint32_t* c1, uint32_t* i0, uint32_t* i1, void* temp,
-                          size_t temp_bytes, int32_t* rows, int8_t* slot) {
+                          size_t temp_bytes, int32_t* rows, int16_t* slot) {
   hipLaunchKernelGGL(hot_clear_kernel, dim3(1024), dim3(256), 0, st, c0, i0, slot, dim);
   hipLaunchKernelGGL(hot_count_kernel, dim3(4096), dim3(256), 0, st, col, n, c0);
   size_t tb = temp_bytes;
   hipError_t e = rocprim::radix_sort_pairs_desc(temp, tb, c0, c1, i0, i1, (uint32_t)dim, 0, 32,
                                                 st);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(hot_pick_kernel, dim3(1), dim3(64), 0, st, i1, nhot, rows, slot);
+  hipLaunchKernelGGL(hot_pick_kernel, dim3(1), dim3(256), 0, st, i1, nhot, rows, slot);
   return hipGetLastError();
 }
 
@@ -610,9 +609,12 @@ void launch_scan(hipStream_t st, const int64_t* cnt, int64_t* start, int64_t* bs
 // then a linear advance.  The chunk's entries are read by the lanes in one
 // go and broadcast one by one; lanes run over the R columns.
 constexpr int SPMM_IPW = 4;
+// Workgroups of 16 wavefronts, as many per CU (256 CUs, 160 KB of LDS
+// each) as their HOT_LDS_BYTES of hot-row accumulators allow.
+constexpr int SPMM_BLOCKS = 256 * (int)((size_t(160) << 10) / HOT_LDS_BYTES);
 
 template <typename T, typename YT>
-__global__ __launch_bounds__(256) void spmm_kernel(FiberArgs a, const T* __restrict__ rows,
+__global__ __launch_bounds__(1024) void spmm_kernel(FiberArgs a, const T* __restrict__ rows,
                                                    YT* __restrict__ Y) {
   extern __shared__ double hot_acc[];  // [nhot][R]
   const int lane = threadIdx.x & 63;
@@ -654,7 +656,7 @@ __global__ __launch_bounds__(256) void spmm_kernel(FiberArgs a, const T* __restr
                                              __builtin_amdgcn_readlane(__double2loint(xv), t));
         const int64_t i = __builtin_amdgcn_readlane(iv, t);
         const int hs = __builtin_amdgcn_readlane(hv, t);
-        if (hs >= 0) {
+        if (hs >= 0 && hs < a.nhot) {
           double* acc = hot_acc + hs * R;
           if (lane < R) atomicAdd(&acc[lane], coef * (double)r0);
           if (lane + 64 < R) atomicAdd(&acc[lane + 64], coef * (double)r1);
@@ -738,7 +740,7 @@ __global__ void spmm_scale_kernel(const double* __restrict__ partial, int n,
 }
 
 template <typename T>
-__global__ __launch_bounds__(256) void spmm_det_kernel(FiberArgs a, const T* __restrict__ rows,
+__global__ __launch_bounds__(1024) void spmm_det_kernel(FiberArgs a, const T* __restrict__ rows,
                                                        const double* __restrict__ scale,
                                                        unsigned long long* __restrict__ Y) {
   extern __shared__ unsigned long long hot_q[];  // [nhot][R]
@@ -780,7 +782,7 @@ __global__ __launch_bounds__(256) void spmm_det_kernel(FiberArgs a, const T* __r
         const int hs = __builtin_amdgcn_readlane(hv, t);
         const unsigned long long q0 = (unsigned long long)(long long)rint(coef * r0 * sc);
         const unsigned long long q1 = (unsigned long long)(long long)rint(coef * r1 * sc);
-        if (hs >= 0) {
+        if (hs >= 0 && hs < a.nhot) {
           unsigned long long* acc = hot_q + hs * R;
           if (lane < R) atomicAdd(&acc[lane], q0);
           if (lane + 64 < R) atomicAdd(&acc[lane + 64], q1);
@@ -937,18 +939,20 @@ hipError_t launch_spmm_det(hipStream_t st, krps_precision p, const FiberArgs& a,
                            void* Y, const int32_t* list, const int64_t* count, double* det) {
   // det: DET_BLOCKS block bounds, then the scale pair
   double* scale = det + DET_BLOCKS;
-  const size_t lds = (size_t)a.nhot * a.R * 8;
+  FiberArgs b = a;
+  b.nhot = hot_rows_used(a.nhot, a.R);
+  const size_t lds = (size_t)b.nhot * b.R * 8;
   if (p == KRPS_BF16X2) {
     hipLaunchKernelGGL(spmm_bound_kernel<float>, dim3(DET_BLOCKS), dim3(256), 0, st, a,
                        (const float*)rows, det);
     hipLaunchKernelGGL(spmm_scale_kernel, dim3(1), dim3(64), 0, st, det, DET_BLOCKS, scale);
-    hipLaunchKernelGGL(spmm_det_kernel<float>, dim3(2048), dim3(256), lds, st, a,
+    hipLaunchKernelGGL(spmm_det_kernel<float>, dim3(SPMM_BLOCKS), dim3(1024), lds, st, b,
                        (const float*)rows, scale, (unsigned long long*)Y);
   } else {
     hipLaunchKernelGGL(spmm_bound_kernel<double>, dim3(DET_BLOCKS), dim3(256), 0, st, a,
                        (const double*)rows, det);
     hipLaunchKernelGGL(spmm_scale_kernel, dim3(1), dim3(64), 0, st, det, DET_BLOCKS, scale);
-    hipLaunchKernelGGL(spmm_det_kernel<double>, dim3(2048), dim3(256), lds, st, a,
+    hipLaunchKernelGGL(spmm_det_kernel<double>, dim3(SPMM_BLOCKS), dim3(1024), lds, st, b,
                        (const double*)rows, scale, (unsigned long long*)Y);
   }
   hipLaunchKernelGGL(fix_to_double_kernel, dim3(2048), dim3(256), 0, st, (double*)Y, a.R, list,
@@ -960,14 +964,16 @@ size_t spmm_det_bytes() { return (size_t)(DET_BLOCKS + 4) * 8; }
 
 hipError_t launch_spmm(hipStream_t st, krps_precision p, const FiberArgs& a, const void* rows,
                        void* Y) {
-  const size_t lds = (size_t)a.nhot * a.R * 8;
+  FiberArgs b = a;
+  b.nhot = hot_rows_used(a.nhot, a.R);
+  const size_t lds = (size_t)b.nhot * b.R * 8;
   // the split path's rows are float32 and its Y is float32 (half the
   // atomic traffic); the float64 and float32 paths form Y in float64
   if (p == KRPS_FP64)
-    hipLaunchKernelGGL((spmm_kernel<double, double>), dim3(2048), dim3(256), lds, st, a,
+    hipLaunchKernelGGL((spmm_kernel<double, double>), dim3(SPMM_BLOCKS), dim3(1024), lds, st, b,
                        (const double*)rows, (double*)Y);
   else
-    hipLaunchKernelGGL((spmm_kernel<float, float>), dim3(2048), dim3(256), lds, st, a,
+    hipLaunchKernelGGL((spmm_kernel<float, float>), dim3(SPMM_BLOCKS), dim3(1024), lds, st, b,
                        (const float*)rows, (float*)Y);
   return hipGetLastError();
 }
@@ -1617,7 +1623,7 @@ __global__ __launch_bounds__(256) void mark_all_kernel(const int32_t* __restrict
 constexpr int MTTKRP_CHUNK = 256;
 
 template <typename T>
-__global__ __launch_bounds__(256) void mttkrp_kernel(MttkrpArgs a, double* __restrict__ Y) {
+__global__ __launch_bounds__(1024) void mttkrp_kernel(MttkrpArgs a, double* __restrict__ Y) {
   extern __shared__ double hot_acc[];  // [nhot][R]
   const int lane = threadIdx.x & 63;
   const int R = a.R;
@@ -1655,7 +1661,7 @@ __global__ __launch_bounds__(256) void mttkrp_kernel(MttkrpArgs a, double* __res
       const double x = a.vals[e];
       const int32_t i = ij[e];
       const int hs = a.hot_slot[i];
-      if (hs >= 0) {
+      if (hs >= 0 && hs < a.nhot) {
         double* acc = hot_acc + hs * R;
         if (lane < R) atomicAdd(&acc[lane], x * k0);
         if (lane + 64 < R) atomicAdd(&acc[lane + 64], x * k1);
@@ -1686,11 +1692,13 @@ hipError_t launch_mttkrp(hipStream_t st, krps_precision p, const MttkrpArgs& a, 
   hipLaunchKernelGGL(mark_compact_kernel, dim3((unsigned)nb), dim3(SCAN_TILE), 0, st, mark, I, nb,
                      bsum, list, count);
   hipLaunchKernelGGL(zero_rows_kernel<double>, dim3(2048), dim3(256), 0, st, Y, a.R, list, count);
-  const size_t lds = (size_t)a.nhot * a.R * 8;
+  MttkrpArgs b = a;
+  b.nhot = hot_rows_used(a.nhot, a.R);
+  const size_t lds = (size_t)b.nhot * b.R * 8;
   if (p == KRPS_FP64)
-    hipLaunchKernelGGL(mttkrp_kernel<double>, dim3(2048), dim3(256), lds, st, a, Y);
+    hipLaunchKernelGGL(mttkrp_kernel<double>, dim3(SPMM_BLOCKS), dim3(1024), lds, st, b, Y);
   else
-    hipLaunchKernelGGL(mttkrp_kernel<float>, dim3(2048), dim3(256), lds, st, a, Y);
+    hipLaunchKernelGGL(mttkrp_kernel<float>, dim3(SPMM_BLOCKS), dim3(1024), lds, st, b, Y);
   return hipGetLastError();
 }
 

@@ -77,8 +77,8 @@ def test_duplicates_are_merged_into_stored_entries(env):
 
 
 def test_hot_rows_hold_the_most_entries(env):
-    """The rows the SpMM keeps per workgroup are the min(32, I_j) rows with
-    the most stored entries (enough entries per workgroup that the counting
+    """The hot rows are the min(512, I_j) rows with the most stored entries,
+    in decreasing count (enough entries per workgroup that the counting
     table fills and the global fallback is taken too)."""
     krps, torch, ctx = env
     dims = (200_000, 100_000, 20)
@@ -92,10 +92,12 @@ def test_hot_rows_hold_the_most_entries(env):
     for j, d in enumerate(dims):
         cnt = np.bincount(cols[j], minlength=d)
         hot = T.hot_rows(j)
-        k = min(32, d)
+        k = min(512, d)
         assert len(hot) == k and len(set(hot)) == k
         kth = np.sort(cnt)[::-1][k - 1]
         assert min(cnt[h] for h in hot) >= kth, (j, sorted(cnt[hot]), kth)
+        c = cnt[hot]
+        assert np.all(c[:-1] >= c[1:])  # decreasing: a prefix is the hottest rows
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
