@@ -376,12 +376,13 @@ class Sampler:
         check(lib().krps_draw_layout_query(self.handle, ctypes.byref(dl)))
         return dl
 
-    def draw_parts(self):
-        """Views of what the last sample()/row_prob() prepared."""
+    def draw_parts(self, ws=None):
+        """Views of what the last sample()/row_prob() prepared (or, with
+        ``ws``, the preparation held in that per-draw workspace)."""
         torch = self.ctx.torch
         dl = self.draw_layout()
         R, N = self.R, self.N
-        ws = self.draw_ws
+        ws = self.draw_ws if ws is None else ws
         tri = R * (R + 1) // 2
         es = 8 if self.precision == "fp64" else 4
         dt = torch.float64 if es == 8 else torch.float32
@@ -685,6 +686,11 @@ class CPALS:
             "yrows": self._yrows(),
             "expanded": view(l.expanded, 1, torch.int64, 8).clone(),
         }
+
+    def draw_parts(self):
+        """The preparation of the last solve's draw (G^+, eigenpairs of
+        every G_{>k}, eigen-trees, Jacobi sweep counts)."""
+        return self.S.draw_parts(self.ws[self.layout.draw:])
 
     def _yrows(self):
         l, ws = self.layout, self.ws

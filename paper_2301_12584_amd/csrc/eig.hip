@@ -162,42 +162,43 @@ __device__ void norms_and_normalise(double* A, int R, double* lam) {
 
 // In place in the lower triangle of A (column c at A + c*RS, G in full on
 // entry): the Cholesky factor L of G = L L^T, then L^{-1} in place of L
-// (right-looking factorisation, right-to-left triangular inverse; two
-// barriers per column).  False if a pivot is not positive (every thread
-// reads the same pivot after a barrier, so all return together).  `tmp`
-// holds R doubles of LDS.
-__device__ bool cholesky_inverse_lower(double* A, int R, double* tmp) {
-  const int RS = R + 1, tid = threadIdx.x, nt = blockDim.x;
+// (right-looking factorisation, right-to-left triangular inverse).  One
+// wavefront (lane l holds rows l, l + 64): the R dependent column steps of
+// each phase are ordered by wave-level LDS waits, not workgroup barriers
+// (two barriers per column across the workgroup cost ~0.25 ms at R = 64).
+// False if a pivot is not positive (every lane reads the same pivot, so
+// all return together).  `tmp` holds R doubles of LDS.  Call from the
+// threads of one wavefront only.
+__device__ bool cholesky_inverse_lower_wave(double* A, int R, double* tmp) {
+  const int RS = R + 1, lane = threadIdx.x & 63;
   for (int j = 0; j < R; ++j) {
-    const double d = A[j * RS + j];
+    const double d = A[j * RS + j];  // the same value in every lane
     if (!(d > 0.0) || !(d < INFINITY)) return false;
     const double ljj = sqrt(d), inv = 1.0 / ljj;
-    for (int i = j + 1 + tid; i < R; i += nt) A[j * RS + i] *= inv;
-    __syncthreads();
-    // trailing lower triangle: (i, k), j < k <= i; a wavefront per column,
-    // its lanes over the rows
-    for (int k = j + 1 + (tid >> 6); k < R; k += nt >> 6) {
-      const double lk = A[j * RS + k];
-      for (int i = k + (tid & 63); i < R; i += 64) A[k * RS + i] -= A[j * RS + i] * lk;
+    for (int i = j + 1 + lane; i < R; i += 64) A[j * RS + i] *= inv;
+    wave_lds_sync();
+    // trailing lower triangle (i, k), j < k <= i: each lane its rows
+    for (int i = j + 1 + lane; i < R; i += 64) {
+      const double li = A[j * RS + i];
+      for (int k = j + 1; k <= i; ++k) A[k * RS + i] -= li * A[j * RS + k];
     }
-    if (tid == 0) A[j * RS + j] = ljj;
-    __syncthreads();
+    if (lane == 0) A[j * RS + j] = ljj;
+    wave_lds_sync();
   }
   for (int j = R - 1; j >= 0; --j) {
-    for (int i = j + 1 + tid; i < R; i += nt) tmp[i] = A[j * RS + i];
-    __syncthreads();
+    for (int i = j + 1 + lane; i < R; i += 64) tmp[i] = A[j * RS + i];
+    wave_lds_sync();
     const double xjj = 1.0 / A[j * RS + j];
-    // column j of L^{-1} below the diagonal: -x_jj (L^{-1})_{22} l_j, with
-    // the columns right of j already inverted
-    for (int i = j + 1 + tid; i < R; i += nt) {
+    // column j of L^{-1} below the diagonal from the columns right of it
+    for (int i = j + 1 + lane; i < R; i += 64) {
       double acc = 0;
       for (int k = j + 1; k <= i; ++k) acc += A[k * RS + i] * tmp[k];
       A[j * RS + i] = -xjj * acc;
     }
-    __syncthreads();
-    if (tid == 0) A[j * RS + j] = xjj;
+    wave_lds_sync();
+    if (lane == 0) A[j * RS + j] = xjj;
+    wave_lds_sync();
   }
-  __syncthreads();
   return true;
 }
 
@@ -275,7 +276,12 @@ __device__ void prep_gplus_body(const GList& gl, int nmat, int R, int nsteps,
     red[0] = g;                     // ||G||_inf
   }
   __syncthreads();
-  bool ok = cholesky_inverse_lower(A, R, lam);
+  if (tid < 64) {
+    const bool okw = cholesky_inverse_lower_wave(A, R, lam);
+    if (tid == 0) *flag = okw ? 1 : 0;
+  }
+  __syncthreads();
+  bool ok = *flag == 1;
   if (ok) {
     for (int a = tid; a < R; a += blockDim.x) {
       double rs = 0;
@@ -355,7 +361,8 @@ __device__ void prep_eig_body(const GList& gk, int st, int R, const double* __re
                               double* __restrict__ lam_out, T* __restrict__ vecs,
                               T* __restrict__ etree, int64_t estride,
                               int32_t* __restrict__ sweep_out, double* __restrict__ emass,
-                              int64_t enodes, double* smem) {
+                              int64_t enodes, double* smem, double* __restrict__ warm = nullptr,
+                              int32_t* __restrict__ warm_ok = nullptr) {
   const int RS = R + 1;
   double* A = smem;
   double* lam = A + R * RS;
@@ -366,6 +373,34 @@ __device__ void prep_eig_body(const GList& gk, int st, int R, const double* __re
   const int tid = threadIdx.x;
   for (int i = tid; i < R * R; i += blockDim.x) A[(i / R) * RS + i % R] = ggt[(int64_t)k * R * R + i];
   __syncthreads();
+  // Warm start (a caller's earlier eigenvectors V of this mode, rows
+  // v_c^T): one-sided Jacobi on A V instead of A.  Its converged columns
+  // A V Q are orthogonal with V Q orthogonal, so they are lambda_c v'_c
+  // for the eigenpairs of A as from a cold start (any orthogonal start
+  // works); near the last solve's eigenvectors few sweeps remain.
+  double* Vw = warm != nullptr ? warm + (int64_t)k * R * R : nullptr;
+  const bool use_warm = Vw != nullptr && warm_ok[k] != 0;
+  if (use_warm) {
+    constexpr int MAXO = 128 * 128 / PREP_THREADS;  // outputs per thread
+    double out[MAXO];
+#pragma unroll
+    for (int o = 0; o < MAXO; ++o) {
+      const int i = tid + o * (int)blockDim.x;
+      double acc = 0.0;
+      if (i < R * R) {
+        const int c = i / R, r = i % R;  // (A V)[r][c] = sum_m A[r][m] V[m][c]
+        for (int m = 0; m < R; ++m) acc += A[m * RS + r] * Vw[(int64_t)c * R + m];
+      }
+      out[o] = acc;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int o = 0; o < MAXO; ++o) {
+      const int i = tid + o * (int)blockDim.x;
+      if (i < R * R) A[(i / R) * RS + i % R] = out[o];
+    }
+    __syncthreads();
+  }
   const int sweeps = jacobi_columns(A, R, flag);
   if (tid == 0 && sweep_out != nullptr) sweep_out[2 + st] = sweeps;
   norms_and_normalise(A, R, lam);
@@ -380,8 +415,10 @@ __device__ void prep_eig_body(const GList& gk, int st, int R, const double* __re
   for (int i = tid; i < R * R; i += blockDim.x) {
     const int u = i / R, e = i % R;
     vecs[(int64_t)k * R * R + i] = (T)A[perm[u] * RS + e];
+    if (Vw != nullptr) Vw[i] = A[perm[u] * RS + e];
     if (e == 0) lam_out[(int64_t)k * R + u] = lam[perm[u]];
   }
+  if (Vw != nullptr && tid == 0) warm_ok[k] = 1;
   // eigen-tree over the R rows sqrt(lam_u) v_u^T with Y = G_k: node masses
   // <h h^T, P^v, G_k> with P^v = sum_{u in S(v)} lam_u v_u v_u^T; the
   // stored node is P^v (*) G_k (packed upper triangle).
@@ -439,10 +476,11 @@ template <typename T>
 __global__ __launch_bounds__(PREP_THREADS) void prep_eig_kernel(
     GList gk, int R, const double* __restrict__ ggt,
     double* __restrict__ lam_out, T* __restrict__ vecs, T* __restrict__ etree, int64_t estride,
-    int32_t* __restrict__ sweep_out, double* __restrict__ emass, int64_t enodes) {
+    int32_t* __restrict__ sweep_out, double* __restrict__ emass, int64_t enodes,
+    double* __restrict__ warm, int32_t* __restrict__ warm_ok) {
   extern __shared__ double smem[];
   prep_eig_body<T>(gk, blockIdx.x, R, ggt, lam_out, vecs, etree, estride, sweep_out, emass,
-                   enodes, smem);
+                   enodes, smem, warm, warm_ok);
 }
 
 template <typename T>
@@ -481,7 +519,8 @@ hipError_t launch_prep_gplus2(hipStream_t st, int R, int nmat, const double* con
 hipError_t launch_prep_eig2(hipStream_t st, krps_precision p, int R, int nsteps,
                             const double* const* Gsteps, const int* order, const double* ggt,
                             double* lam, void* vecs, void* etree, int64_t estride,
-                            int32_t* sweep_out, double* emass, int64_t enodes) {
+                            int32_t* sweep_out, double* emass, int64_t enodes, double* warm,
+                            int32_t* warm_ok) {
   GList gl{};
   for (int m = 0; m < nsteps; ++m) {
     gl.G[m] = Gsteps[m];
@@ -494,13 +533,13 @@ hipError_t launch_prep_eig2(hipStream_t st, krps_precision p, int R, int nsteps,
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(prep_eig_kernel<double>, dim3(nsteps), dim3(prep_threads(R)), lds, st, gl,
                        R, ggt, lam, (double*)vecs, (double*)etree, estride, sweep_out,
-                       emass, enodes);
+                       emass, enodes, warm, warm_ok);
   } else {
     e = set_lds((const void*)prep_eig_kernel<float>, lds);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(prep_eig_kernel<float>, dim3(nsteps), dim3(prep_threads(R)), lds, st, gl,
                        R, ggt, lam, (float*)vecs, (float*)etree, estride, sweep_out,
-                       emass, enodes);
+                       emass, enodes, warm, warm_ok);
   }
   return hipGetLastError();
 }

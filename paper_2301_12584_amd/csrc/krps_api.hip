@@ -75,6 +75,8 @@ struct krps_sampler_s {
   double* scratch;
   size_t scratch_bytes;
   int32_t* status;
+  double* warm;                   // [N + 1][N][R][R] eigenvectors of the last solves
+  int32_t* warm_ok;               // [N + 1][N] 1 where warm holds them
   // per-draw workspace layout
   krps_draw_layout lay;
   const void* prepared_ws = nullptr;  // ws of the last preparation
@@ -143,7 +145,8 @@ krps_status check_dims(int N, const int64_t* I, int R) {
 struct SamplerPlan {
   std::vector<TreeShape> shape;
   std::vector<size_t> node_off, node32_off, gram_off;
-  size_t scratch_off = 0, scratch_bytes = 0, status_off = 0, total = 0;
+  size_t scratch_off = 0, scratch_bytes = 0, status_off = 0, warm_off = 0, warm_ok_off = 0;
+  size_t total = 0;
 };
 
 SamplerPlan plan_sampler(int N, const int64_t* I, int R, int F, krps_precision p) {
@@ -170,6 +173,12 @@ SamplerPlan plan_sampler(int N, const int64_t* I, int R, int F, krps_precision p
   off += align_up(scratch);
   pl.status_off = off;
   off += 256;
+  // warm starts of the solves' eigendecompositions: per exclusion (-1 .. N-1)
+  // and drawn mode, the last eigenvectors (float64 R x R) and a flag
+  pl.warm_ok_off = off;
+  off += align_up((size_t)(N + 1) * N * 4);
+  pl.warm_off = off;
+  off += align_up((size_t)(N + 1) * N * R * R * 8);
   pl.total = off;
   return pl;
 }
@@ -246,7 +255,8 @@ int walk_filter_top(krps_sampler s, int k) {
 
 // Enqueues the set-up part of Algorithm 2 (before its per-sample loop) for exclusion `exclude` into ws and
 // fills the descent arguments.
-krps_status prepare_draw(krps_sampler s, int exclude, void* ws, DescentArgs& a) {
+krps_status prepare_draw(krps_sampler s, int exclude, void* ws, DescentArgs& a,
+                         bool warm = false) {
   char* w = (char*)ws;
   const int R = s->R;
   int order[KRPS_MAX_MODES];
@@ -269,8 +279,13 @@ krps_status prepare_draw(krps_sampler s, int exclude, void* ws, DescentArgs& a) 
   hipError_t e = launch_prep_gplus2(st, R, nsteps, mats, nsteps, order, gplus_full, gplus_packed,
                                     rank, ggt, s->status);
   if (e != hipSuccess) return hip_fail(e, "prep G+ launch");
+  // the sketched solves of CP-ALS start each eigendecomposition from the
+  // last solve's eigenvectors of the same exclusion and mode; plain draws
+  // start cold, so that a repeated draw repeats bit for bit
+  double* wv = warm ? s->warm + (size_t)(exclude + 1) * s->N * R * R : nullptr;
+  int32_t* wok = warm ? s->warm_ok + (size_t)(exclude + 1) * s->N : nullptr;
   e = launch_prep_eig2(st, s->prec, R, nsteps, mats, order, ggt, lam, vecs, etree, s->estride,
-                       rank, (double*)(w + s->emass_off), s->enodes);
+                       rank, (double*)(w + s->emass_off), s->enodes, wv, wok);
   if (e != hipSuccess) return hip_fail(e, "prep eig launch");
   if (s->znmax > 0 && nsteps > 0) {
     const int k0 = order[0];
@@ -554,7 +569,7 @@ krps_status enqueue_solve(krps_sampler s, krps_tensor t, int j, int64_t J, const
   hipStream_t st = s->ctx->stream;
   const krps_solve_layout& l = pl.lay;
   DescentArgs a;
-  krps_status rs = prepare_draw(s, j, w + l.draw, a);
+  krps_status rs = prepare_draw(s, j, w + l.draw, a, true);
   if (rs != KRPS_OK) return rs;
   // rows of S A = w_d a_d: float64 for the float64 and float32 paths (the
   // Gram M and Y are then formed in float64), float32 for the bf16 split
@@ -837,6 +852,8 @@ krps_status krps_sampler_create(krps_ctx ctx, int N, const int64_t* I, int R, in
   s->scratch = (double*)(w + pl.scratch_off);
   s->scratch_bytes = pl.scratch_bytes;
   s->status = (int32_t*)(w + pl.status_off);
+  s->warm = (double*)(w + pl.warm_off);
+  s->warm_ok = (int32_t*)(w + pl.warm_ok_off);
   plan_draw(s);
   hipError_t e = hipSetDevice(ctx->device);
   if (e != hipSuccess) {
@@ -844,6 +861,8 @@ krps_status krps_sampler_create(krps_ctx ctx, int N, const int64_t* I, int R, in
     return hip_fail(e, "hipSetDevice");
   }
   e = hipMemsetAsync(s->status, 0, 12, ctx->stream);
+  if (e == hipSuccess)
+    e = hipMemsetAsync(s->warm_ok, 0, (size_t)(N + 1) * N * 4, ctx->stream);
   for (int j = 0; j < N && e == hipSuccess; ++j) {
     e = launch_fill(ctx->stream, p, (char*)s->nodes[j] + (size_t)pl.shape[j].n_nodes * tri(R) * s->elem,
                     NODE_SLACK);
@@ -2060,7 +2079,11 @@ krps_status krps_workspace_regions(int N, const int64_t* I, int R, int F, krps_p
   size_t bext = 0;
   for (int j = 0; j < N; ++j) bext = std::max(bext, tree_build_scratch_extent(sp.shape[j], R));
   rl.add(0, "build scratch", sp.scratch_off, span(sp.scratch_off, sp.status_off), bext);
-  rl.add(0, "status", sp.status_off, span(sp.status_off, sp.total), 12);
+  rl.add(0, "status", sp.status_off, span(sp.status_off, sp.warm_ok_off), 12);
+  rl.add(0, "warm-start flags", sp.warm_ok_off, span(sp.warm_ok_off, sp.warm_off),
+         (size_t)(N + 1) * N * 4);
+  rl.add(0, "warm-start vectors", sp.warm_off, span(sp.warm_off, sp.total),
+         (size_t)(N + 1) * N * R * R * 8);
   // --- per-draw workspace (a host-side sampler with the same shape)
   krps_sampler_s tmp;
   tmp.N = N;

@@ -252,7 +252,8 @@ hipError_t launch_prep_gplus2(hipStream_t st, int R, int nmat, const double* con
 hipError_t launch_prep_eig2(hipStream_t st, krps_precision p, int R, int nsteps,
                             const double* const* Gsteps, const int* order, const double* ggt,
                             double* lam, void* vecs, void* etree, int64_t estride,
-                            int32_t* sweep_out, double* emass, int64_t enodes);
+                            int32_t* sweep_out, double* emass, int64_t enodes,
+                            double* warm = nullptr, int32_t* warm_ok = nullptr);
 // Table of the first drawn mode's factor-tree node masses for h~ = V[:, u]:
 // tab[u * nn + n] = V[:,u]^T G^n V[:,u] for the nn stored nodes of Z (V as
 // stored, [u][R]).  Float64 from the stored values.

@@ -516,3 +516,53 @@ def test_deterministic_solves_repeat_bit_for_bit(env, prec):
     for a, b in zip(f0, f1):
         assert torch.equal(a, b)
     assert torch.equal(s0, s1) and fit0 == fit1
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_warm_started_preparations_match_the_oracle(env, prec):
+    """The solves of a sweep start each eigendecomposition of G_{>k} from
+    the last solve's eigenvectors of the same exclusion and mode: after
+    every solve of three sweeps the preparation (eigenvalues, isolated
+    eigenvectors, the whole decomposition, G^+) matches the oracle's from
+    the factors the solve started from, and the warm-started solves need
+    fewer Jacobi sweeps than the first, cold ones."""
+    krps, torch, ctx = env
+    dims, R, J = (3000, 2000, 500), 16, 4096
+    idx, val = synth.sparse_tensor(dims, 200_000, 1.2, seed=44)
+    U0 = synth.gaussian_factors(dims, R, seed=45)
+    S, T, A = make(krps, torch, ctx, dims, idx, val, U0, prec, J)
+    for k in range(3):
+        A.normalize(k)
+    A.sigma.fill_(1.0)
+    sweeps_used = []
+    for s in range(3):
+        u = _sweep_uniforms(700, s, 3, J)
+        for j in range(3):
+            before = [U.cpu().numpy().astype(np.float64) for U in S.factors]
+            A.solve(j, torch.from_numpy(u[j]).to(ctx.device))
+            torch.cuda.synchronize()
+            parts = A.draw_parts()
+            Gp, rank, eig, _ = osmp.KRPSampler(before).prepare(j)
+            assert parts["rank"] == rank
+            gp = parts["gplus"].cpu().numpy()
+            assert np.abs(gp - Gp).max() <= 1e-9 * np.abs(Gp).max()
+            for st, k in enumerate(m for m in range(3) if m != j):
+                lam, V = eig[k]
+                lg = parts["lam"][k].cpu().numpy()
+                assert np.abs(lg - lam).max() <= 1e-10 * lam.max(), (s, j, k)
+                Vg = parts["vecs"][k].cpu().numpy().astype(np.float64).T
+                gaps = np.diff(lam)
+                iso = np.ones(R, dtype=bool)
+                iso[1:] &= gaps > 1e-6 * lam.max()
+                iso[:-1] &= gaps > 1e-6 * lam.max()
+                dots = np.abs(np.einsum("eu,eu->u", Vg, V))
+                assert np.abs(dots[iso] - 1).max() <= (1e-9 if prec == "fp64" else 1e-6)
+                rec = (Vg * lg) @ Vg.T
+                ref = (V * lam) @ V.T
+                assert np.abs(rec - ref).max() <= (1e-9 if prec == "fp64" else 1e-5) * \
+                    np.abs(ref).max()
+                sweeps_used.append((s, parts["sweeps"][1 + st]))
+    cold = [n for s, n in sweeps_used if s == 0]
+    warm = [n for s, n in sweeps_used if s > 0]
+    print(f"{prec}: Jacobi sweeps, first sweep's solves {cold}, later {warm}", flush=True)
+    assert np.mean(warm) < np.mean(cold)
