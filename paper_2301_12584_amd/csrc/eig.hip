@@ -177,10 +177,22 @@ __device__ bool cholesky_inverse_lower_wave(double* A, int R, double* tmp) {
     const double ljj = sqrt(d), inv = 1.0 / ljj;
     for (int i = j + 1 + lane; i < R; i += 64) A[j * RS + i] *= inv;
     wave_lds_sync();
-    // trailing lower triangle (i, k), j < k <= i: each lane its rows
+    // trailing lower triangle (i, k), j < k <= i: each lane its rows, eight
+    // entries at a time with every load issued before the stores
     for (int i = j + 1 + lane; i < R; i += 64) {
       const double li = A[j * RS + i];
-      for (int k = j + 1; k <= i; ++k) A[k * RS + i] -= li * A[j * RS + k];
+      for (int k0 = j + 1; k0 <= i; k0 += 8) {
+        double a[8], l[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+          const int k = k0 + q <= i ? k0 + q : i;
+          a[q] = A[k * RS + i];
+          l[q] = A[j * RS + k];
+        }
+#pragma unroll
+        for (int q = 0; q < 8; ++q)
+          if (k0 + q <= i) A[(k0 + q) * RS + i] = a[q] - li * l[q];
+      }
     }
     if (lane == 0) A[j * RS + j] = ljj;
     wave_lds_sync();
@@ -191,9 +203,19 @@ __device__ bool cholesky_inverse_lower_wave(double* A, int R, double* tmp) {
     const double xjj = 1.0 / A[j * RS + j];
     // column j of L^{-1} below the diagonal from the columns right of it
     for (int i = j + 1 + lane; i < R; i += 64) {
-      double acc = 0;
-      for (int k = j + 1; k <= i; ++k) acc += A[k * RS + i] * tmp[k];
-      A[j * RS + i] = -xjj * acc;
+      double acc[2] = {0.0, 0.0};
+      for (int k0 = j + 1; k0 <= i; k0 += 8) {
+        double a[8], t[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+          const int k = k0 + q <= i ? k0 + q : i;
+          a[q] = A[k * RS + i];
+          t[q] = k0 + q <= i ? tmp[k] : 0.0;
+        }
+#pragma unroll
+        for (int q = 0; q < 8; ++q) acc[q & 1] += a[q] * t[q];
+      }
+      A[j * RS + i] = -xjj * (acc[0] + acc[1]);
     }
     wave_lds_sync();
     if (lane == 0) A[j * RS + j] = xjj;
@@ -209,6 +231,13 @@ __device__ __forceinline__ double inverse_entry(const double* A, int R, int a, i
   double v = 0;
   for (int i = a > b ? a : b; i < R; ++i) v += A[a * RS + i] * A[b * RS + i];
   return v;
+}
+
+// Entry (a, b) of G^{-1} once stored in the upper triangle of A (column b,
+// row a < b) with the diagonal in lam.
+__device__ __forceinline__ double stored_inverse(const double* A, const double* lam, int RS, int a,
+                                                 int b) {
+  return a == b ? lam[a] : a < b ? A[b * RS + a] : A[a * RS + b];
 }
 
 // A (column c at A + c*RS) = (*) of the nmat listed Grams; then a barrier.
@@ -257,6 +286,7 @@ __device__ void prep_gplus_body(const GList& gl, int nmat, int R, int nsteps,
   double* lam = A + R * (R + 1);    // R
   double* red = lam + R;            // 2
   int* flag = (int*)(red + 2);
+  double* wmax = red + 8;           // PREP_THREADS / 64 (the space past the eigen route's perm)
   const int RS = R + 1;
   const int tid = threadIdx.x;
   if (gplus_packed != nullptr)
@@ -283,30 +313,65 @@ __device__ void prep_gplus_body(const GList& gl, int nmat, int R, int nsteps,
   __syncthreads();
   bool ok = *flag == 1;
   if (ok) {
-    for (int a = tid; a < R; a += blockDim.x) {
-      double rs = 0;
-      for (int b = 0; b < R; ++b) rs += fabs(inverse_entry(A, R, a, b));
-      lam[a] = rs;
+    // G^{-1} = X^T X (X = L^{-1} in the lower triangle): every entry a <= b
+    // formed once, by all threads, into registers, then stored in the upper
+    // triangle of A (column b, row a < b; G's copy there is no longer
+    // needed) with the diagonal in lam; ||G^{-1}||_inf from its rows, one
+    // wavefront per row
+    constexpr int MAXE = (128 * 129 / 2 + PREP_THREADS - 1) / PREP_THREADS;
+    const int ne = R * (R + 1) / 2;
+    double v[MAXE];
+#pragma unroll
+    for (int q = 0; q < MAXE; ++q) {
+      const int p = tid + q * (int)blockDim.x;
+      v[q] = 0.0;
+      if (p < ne) {
+        int a, b;
+        unpack_index(p, R, a, b);
+        v[q] = inverse_entry(A, R, a, b);
+      }
     }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < MAXE; ++q) {
+      const int p = tid + q * (int)blockDim.x;
+      if (p < ne) {
+        int a, b;
+        unpack_index(p, R, a, b);
+        if (a == b)
+          lam[a] = v[q];
+        else
+          A[b * RS + a] = v[q];
+      }
+    }
+    __syncthreads();
+    const int lane = tid & 63, wave = tid >> 6, nwave = (int)blockDim.x >> 6;
+    double hmax = 0.0;
+    for (int a = wave; a < R; a += nwave) {
+      double rs = 0.0;
+      for (int b = lane; b < R; b += 64) rs += fabs(stored_inverse(A, lam, RS, a, b));
+      hmax = fmax(hmax, wave_sum(rs));
+    }
+    if (lane == 0) wmax[wave] = hmax;
     __syncthreads();
     if (tid == 0) {
       double h = 0;
-      for (int a = 0; a < R; ++a) h = fmax(h, lam[a]);
+      for (int w = 0; w < nwave; ++w) h = fmax(h, wmax[w]);
       const double cert = red[0] * h * (double)R * DBL_EPSILON;
       *flag = (cert < 1e-4) ? 1 : 0;
     }
     __syncthreads();
     ok = *flag == 1;
-  }
-  if (ok) {
-    if (tid == 0) {
-      rank[0] = R;
-      rank[1] = 0;
+    if (ok) {
+      if (tid == 0) {
+        rank[0] = R;
+        rank[1] = 0;
+      }
+      for (int i = tid; i < R * R; i += blockDim.x)
+        store_gplus(gl, R, nsteps, i, stored_inverse(A, lam, RS, i / R, i % R), gplus_full,
+                    gplus_packed, ggt);
+      return;
     }
-    for (int i = tid; i < R * R; i += blockDim.x)
-      store_gplus(gl, R, nsteps, i, inverse_entry(A, R, i / R, i % R), gplus_full, gplus_packed,
-                  ggt);
-    return;
   }
   // ---- eigen route (one-sided Jacobi)
   __syncthreads();
@@ -499,7 +564,10 @@ hipError_t set_lds(const void* fn, size_t bytes) {
 }  // namespace
 
 size_t prep_lds_bytes(int R) {
-  return (size_t)R * (R + 1) * 8 + (size_t)R * 8 + 64 + (size_t)R * 4 + 64;
+  // A, lam, then 64 bytes (red, flag), the eigen route's perm and flag or
+  // the Cholesky route's per-wave maxima, and slack
+  return (size_t)R * (R + 1) * 8 + (size_t)R * 8 + 64 + (size_t)R * 4 + 64 +
+         (size_t)PREP_THREADS / 64 * 8;
 }
 
 hipError_t launch_prep_gplus2(hipStream_t st, int R, int nmat, const double* const* mats,

@@ -35,6 +35,10 @@ struct krps_ctx_s {
   int device;
   hipStream_t stream;
   hipStream_t capture = nullptr;  // own stream for graph capture when `stream` is null
+  // a second stream (default priority) and the fork / join events that let
+  // a solve's M^+ run beside its fiber lookup and SpMM (created at first use)
+  hipStream_t aux = nullptr;
+  hipEvent_t fork = nullptr, join = nullptr;
   // pinned host staging of batched-draw descriptors (slot 0: preparation
   // jobs, slot 1: walk problems); `staged` marks the copy out of a slot
   // that must finish before the slot is rewritten
@@ -597,11 +601,23 @@ krps_status enqueue_solve(krps_sampler s, krps_tensor t, int j, int64_t J, const
   e = launch_tree_build(st, split ? KRPS_BF16X2 : KRPS_FP64, w + l.rows, J, R, tm, nullptr,
                         (double*)(w + l.M), (double*)(w + pl.gscratch), pl.gscratch_bytes, 3);
   if (e != hipSuccess) return hip_fail(e, "Gram of sampled rows");
-  // a non-finite M (a non-finite sampled row) would give M^+ = 0 and a zero
-  // factor: it is flagged in the sampler's status
-  e = launch_pinv(st, R, (double*)(w + l.M), (double*)(w + l.Mp), (int32_t*)(w + pl.rank),
+  // M^+ depends only on M: it runs on the context's second stream beside
+  // the fiber lookup and the SpMM, and the GEMM waits for it (a captured
+  // sweep records this fork and join as graph edges).  A non-finite M (a
+  // non-finite sampled row) would give M^+ = 0 and a zero factor: it is
+  // flagged in the sampler's status.
+  krps_ctx cx = s->ctx;
+  if (cx->aux == nullptr) {
+    KRPS_HIP(hipStreamCreateWithFlags(&cx->aux, hipStreamNonBlocking));
+    KRPS_HIP(hipEventCreateWithFlags(&cx->fork, hipEventDisableTiming));
+    KRPS_HIP(hipEventCreateWithFlags(&cx->join, hipEventDisableTiming));
+  }
+  KRPS_HIP(hipEventRecord(cx->fork, st));
+  KRPS_HIP(hipStreamWaitEvent(cx->aux, cx->fork, 0));
+  e = launch_pinv(cx->aux, R, (double*)(w + l.M), (double*)(w + l.Mp), (int32_t*)(w + pl.rank),
                   s->status);
   if (e != hipSuccess) return hip_fail(e, "pseudo-inverse");
+  KRPS_HIP(hipEventRecord(cx->join, cx->aux));
   FiberArgs fa{};
   fa.N = N;
   fa.j = j;
@@ -654,6 +670,7 @@ krps_status enqueue_solve(krps_sampler s, krps_tensor t, int j, int64_t J, const
   else
     e = launch_spmm(st, split ? KRPS_BF16X2 : KRPS_FP64, fa, w + l.rows, w + l.Y);
   if (e != hipSuccess) return hip_fail(e, "SpMM");
+  KRPS_HIP(hipStreamWaitEvent(st, cx->join, 0));
   // the split path's factor is float32, like the float32 path's
   const krps_precision gp = split && s->det ? KRPS_FP32 : s->prec;
   e = launch_solve_gemm(st, gp, w + l.Y, (const double*)(w + l.Mp), s->U[j], s->I[j], yrows,
@@ -791,6 +808,12 @@ krps_status krps_ctx_destroy(krps_ctx ctx) {
     if (ctx->pinned[i] != nullptr) (void)hipHostFree(ctx->pinned[i]);
   }
   if (ctx != nullptr && ctx->capture != nullptr) (void)hipStreamDestroy(ctx->capture);
+  if (ctx != nullptr && ctx->aux != nullptr) {
+    (void)hipStreamSynchronize(ctx->aux);
+    (void)hipStreamDestroy(ctx->aux);
+  }
+  if (ctx != nullptr && ctx->fork != nullptr) (void)hipEventDestroy(ctx->fork);
+  if (ctx != nullptr && ctx->join != nullptr) (void)hipEventDestroy(ctx->join);
   delete ctx;
   return KRPS_OK;
 }
