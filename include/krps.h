@@ -63,12 +63,19 @@ typedef enum {
   KRPS_EUNSUPPORTED = -6 /* valid request this build does not implement */
 } krps_status;
 
-/* Arithmetic of the sampler.  Factor storage is float64 for KRPS_FP64 and
- * float32 for the other two.  KRPS_FP32 builds the Gram matrices with
- * float64 matrix-core products and stores them rounded to float32;
- * KRPS_BF16X2 builds them as bf16 hi/lo split products accumulated in
- * float32.  In every precision the walk's arithmetic (node masses, the
- * running offsets, probabilities) is float64 over the stored values. */
+/* Arithmetic of the sampler and of the sketched solve.  Factor storage is
+ * float64 for KRPS_FP64 and float32 for the other two.  The trees' Gram
+ * matrices are sums of float64 matrix-core products (exact for float32
+ * factors) in every precision, the nodes stored in the factor's type and
+ * G_j in float64 (G_j gives G^+, the leverage scores q_d and the
+ * eigendecompositions of G_{>k}).  In every precision the walk's
+ * arithmetic (node masses, the running offsets, probabilities) is float64
+ * over the stored values, so KRPS_FP32 and KRPS_BF16X2 draw the same
+ * samples.  The sketched solve keeps the scaled sampled rows w_d a_d and
+ * Y = (S B)^T S A in float64 for KRPS_FP64 and KRPS_FP32; KRPS_BF16X2
+ * keeps them in float32 and sums the sampled Gram M = (S A)^T S A from
+ * three-part bf16 split matrix-core products (~2^-24 relative, float32
+ * sums). */
 typedef enum { KRPS_FP64 = 0, KRPS_FP32 = 1, KRPS_BF16X2 = 2 } krps_precision;
 
 typedef struct krps_ctx_s* krps_ctx;
@@ -157,9 +164,12 @@ krps_status krps_sampler_destroy(krps_sampler s);
  * status.  Returns KRPS_EZERO if a preparation met a zero product
  * (C = 0), KRPS_ENUMERIC if a kernel met a non-finite value, since the
  * last check.  *zero_weight (may be NULL) receives the number of sampled
- * rows since the last check whose computed probability q_d was not
- * positive: q_d > 0 in exact arithmetic (Sec. 2.1), so only rounding can
- * do that; such a row was given weight 0 in its solve.  *rewalked (may be
+ * rows since the last check whose computed probability q_d, or a total
+ * mass of whose walk (stage 1 or 2 of a mode, Sec. 3.2), was not
+ * positive: both are > 0 in exact arithmetic (Sec. 2.1), so only the
+ * rounding of stored values can do that (float32 eigen-trees at a G of
+ * condition number near 2^24 / R, for example); such a row was given
+ * weight 0 in its solve.  *rewalked (may be
  * NULL) receives the number of float64 walks (a sample and a drawn mode)
  * since the last check that the float32 node copies could not decide and
  * that were walked again from the float64 tree (krps_sampler_set_filter). */
@@ -381,8 +391,8 @@ krps_status krps_als_sweep_seeded(krps_sampler s, krps_tensor t, int64_t J, uint
  * mat(T, j) (U_N (.) ... (.) U_1 without U_j) ((*)_{k != j} G_k)^+ over
  * every stored entry of T (the sparse MTTKRP), sigma = its column norms,
  * U_j renormalised in place, Z_j and G_j rebuilt.  Float64 arithmetic in
- * every precision (for KRPS_BF16X2 the G_k are recomputed in float64); the
- * factor is stored in its type.  ws: a solve workspace (any J); the
+ * every precision (the G_k are float64 in every precision); the factor is
+ * stored in its type.  ws: a solve workspace (any J); the
  * pieces of krps_solve_layout are overwritten (M^+ at Mp, the MTTKRP in
  * float64 at Y for the rows listed at yrows, their count at nyrows). */
 krps_status krps_exact_solve(krps_sampler s, krps_tensor t, int j, double* sigma, void* ws,
@@ -393,8 +403,8 @@ krps_status krps_exact_solve(krps_sampler s, krps_tensor t, int j, double* sigma
  * entries.  sigma: device float64 [R].  fit: host out (synchronises).
  * ws: a solve workspace (any J); only its head, below every piece of
  * krps_solve_layout, is written, so the last solve's pieces stay valid.
- * For KRPS_BF16X2 the G_k are recomputed in float64 from the factors
- * there, since the split trees' Grams are only ~2^-16 accurate. */
+ * The G_k are the sampler's float64 Grams (float64 products in every
+ * precision). */
 krps_status krps_fit(krps_sampler s, krps_tensor t, const double* sigma, double* fit, void* ws,
                      size_t ws_bytes);
 
@@ -452,7 +462,7 @@ krps_status krps_sampler_set_deterministic(krps_sampler s, int on);
 
 /* Selects the tree build's team width: waves that share one leaf's
  * 16 x 16 accumulator tiles (0 = default; R <= 16: 1; R <= 32: 1 or 3;
- * R <= 64: 2 or 5; above: 4 or 8 for KRPS_BF16X2, 6 or 12 otherwise).
+ * R <= 64: 2 or 5; above: 6 or 12).
  * Fewer waves hold more tiles each (more registers, fewer loads shared).
  * The stored nodes do not depend on it.  KRPS_EINVAL for another value. */
 krps_status krps_sampler_set_build(krps_sampler s, int team);

@@ -608,6 +608,10 @@ __device__ __forceinline__ void descend(const DescentArgs& a, int64_t base,
 #pragma unroll
   for (int i = 0; i < HE; ++i) h[i] = 1.0;
   Packed<LPS, NP> P{pslot + sl};
+  // false once a walk's total mass came out <= 0 (finite): rounding of the
+  // stored values has swallowed the sample's mass, so its draw is not
+  // governed by the method's probabilities and it gets weight 0
+  bool mass_ok = true;
   for (int st = 0; st < a.nsteps; ++st) {
     const int k = a.order[st];
     const ModeDesc& md = a.mode[k];
@@ -731,7 +735,16 @@ __device__ __forceinline__ void descend(const DescentArgs& a, int64_t base,
       if (e < R) h[i] *= (double)U[t * R + e];
     }
     if (active && (!(C1 > 0.0) || !(C2 > 0.0))) {
-      if (sl == 0) atomicOr(a.status, ST_NUMERIC);
+      if (!(fabs(C1) <= __DBL_MAX__) || !(fabs(C2) <= __DBL_MAX__)) {
+        if (sl == 0) atomicOr(a.status, ST_NUMERIC);
+      } else {
+        // C1 (stage 1) or C2 (stage 2) is a p.s.d. form of stored values,
+        // > 0 in exact arithmetic; at <= 0 the stored values' rounding
+        // exceeds the mass (float32 eigen-tree entries of a G_{>k} with
+        // condition number near 2^24 / R)
+        if (sl == 0 && mass_ok) atomicAdd(a.status + 1, 1);
+        mass_ok = false;
+      }
     }
     wave_lds_sync();
   }
@@ -747,14 +760,14 @@ __device__ __forceinline__ void descend(const DescentArgs& a, int64_t base,
     if (active) {
       if (sl == 0 && a.prob != nullptr) a.prob[d] = q;
       // q > 0 in exact arithmetic; where rounding leaves it at or below zero
-      // (a row almost in the null space of G^+, with split-path Grams at
-      // an ill-conditioned start) the sample gets weight 0 and adds nothing
-      // to the sketched system, rather than an infinite or NaN row.  Such
-      // samples are counted in the second status word; a non-finite q sets
-      // the numeric-error flag.
-      const bool qok = q > 0.0 && q <= __DBL_MAX__;
+      // (a row almost in the null space of G^+), or a walk mass was <= 0
+      // (above), the sample gets weight 0 and adds nothing to the sketched
+      // system, rather than an infinite, NaN or misweighted row.  Such
+      // samples are counted once in the second status word; a non-finite q
+      // sets the numeric-error flag.
+      const bool qok = mass_ok && q > 0.0 && q <= __DBL_MAX__;
       const double w = qok ? 1.0 / sqrt((double)J * q) : 0.0;
-      if (sl == 0 && !qok) {
+      if (sl == 0 && mass_ok && !qok) {
         if (q <= 0.0)
           atomicAdd(a.status + 1, 1);
         else

@@ -234,9 +234,17 @@ void plan_draw(krps_sampler s) {
 
 size_t gpacked_off(krps_sampler s) { return s->lay.gplus + align_up((size_t)s->R * s->R * 8); }
 
+// The split path's trees are the float32 path's: float64 products of the
+// float32 factor (exact) summed in float64, nodes stored in float32, and
+// G_j in float64.  bf16 split products in the trees would put ~2^-16
+// relative error into G_j, which reaches G^+ and the leverage scores
+// multiplied by the condition number of G, and, with the lo lo^T products
+// dropped, would make the root Gram indefinite at a condition number above
+// ~2^16, so that a drawn component's stage-2 mass could be <= 0.
 krps_status build_tree(krps_sampler s, int j) {
-  hipError_t e = launch_tree_build(s->ctx->stream, s->prec, s->U[j], s->I[j], s->R, s->shape[j],
-                                   s->nodes[j], s->gram[j], s->scratch, s->scratch_bytes, 2,
+  const krps_precision tp = s->prec == KRPS_BF16X2 ? KRPS_FP32 : s->prec;
+  hipError_t e = launch_tree_build(s->ctx->stream, tp, s->U[j], s->I[j], s->R, s->shape[j],
+                                   s->nodes[j], s->gram[j], s->scratch, s->scratch_bytes,
                                    s->nodes32[j], s->team);
   if (e != hipSuccess) return hip_fail(e, "tree build launch");
   return KRPS_OK;
@@ -413,37 +421,17 @@ TensorPlan plan_tensor(int N, const int64_t* dims, int64_t nnz) {
 // J (the fit, the normalisation of a factor), below every piece of
 // krps_solve_layout, so that those calls leave the last solve's pieces intact.
 struct SolveHead {
-  size_t fitp, fitout, fitg, fitscr, fitscr_bytes, npart, nsig, ctrw, total;
-  TreeShape gts[KRPS_MAX_MODES];  // float64 Grams of the fit on the split path
+  size_t fitp, fitout, npart, nsig, ctrw, total;
 };
-
-// Leaf shape of the fit's float64 Gram of factor k: at most 2048 leaves.
-TreeShape fit_gram_shape(int64_t I, int R) {
-  const int64_t Lt = std::min<int64_t>(ceil_div(I, (int64_t)R), 2048);
-  TreeShape ts;
-  ts.init(I, (int)ceil_div(I, Lt));
-  return ts;
-}
 
 SolveHead plan_head(const krps_sampler_s* s) {
   SolveHead h;
-  const int R = s->R, N = s->N;
+  const int R = s->R;
   size_t off = 0;
   h.fitp = off;
   off += align_up(fit_partial_bytes());
   h.fitout = off;
   off += 256;
-  h.fitg = off;
-  h.fitscr_bytes = 0;
-  if (s->prec == KRPS_BF16X2) {
-    off += align_up((size_t)N * R * R * 8);
-    for (int k = 0; k < N; ++k) {
-      h.gts[k] = fit_gram_shape(s->I[k], R);
-      h.fitscr_bytes = std::max(h.fitscr_bytes, tree_build_scratch_bytes(h.gts[k].L, R));
-    }
-  }
-  h.fitscr = off;
-  off += align_up(h.fitscr_bytes);
   h.npart = off;
   off += align_up(solve_partial_bytes(R));
   h.nsig = off;
@@ -599,7 +587,7 @@ krps_status enqueue_solve(krps_sampler s, krps_tensor t, int j, int64_t J, const
   TreeShape tm;
   tm.init(J, R);
   e = launch_tree_build(st, split ? KRPS_BF16X2 : KRPS_FP64, w + l.rows, J, R, tm, nullptr,
-                        (double*)(w + l.M), (double*)(w + pl.gscratch), pl.gscratch_bytes, 3);
+                        (double*)(w + l.M), (double*)(w + pl.gscratch), pl.gscratch_bytes);
   if (e != hipSuccess) return hip_fail(e, "Gram of sampled rows");
   // M^+ depends only on M: it runs on the context's second stream beside
   // the fiber lookup and the SpMM, and the GEMM waits for it (a captured
@@ -1946,22 +1934,11 @@ krps_status krps_exact_solve(krps_sampler s, krps_tensor t, int j, double* sigma
   hipStream_t stream = s->ctx->stream;
   const krps_solve_layout& l = pl.lay;
   const SolveHead& h = pl.head;
-  // M = (*)_{k != j} G_k in float64 (the split path's tree roots carry
-  // ~2^-16 error: its Grams are recomputed with float64 products) and M^+
+  // M = (*)_{k != j} G_k in float64 and M^+
   const double* mats[KRPS_MAX_MODES];
   int nm = 0;
-  for (int k = 0; k < N; ++k) {
-    if (k == j) continue;
-    const double* g = s->gram[k];
-    if (s->prec == KRPS_BF16X2) {
-      double* gk = (double*)(w + h.fitg) + (size_t)k * R * R;
-      hipError_t e = launch_tree_build(stream, KRPS_FP32, s->U[k], s->I[k], R, h.gts[k], nullptr,
-                                       gk, (double*)(w + h.fitscr), h.fitscr_bytes, 2);
-      if (e != hipSuccess) return hip_fail(e, "float64 Gram");
-      g = gk;
-    }
-    mats[nm++] = g;
-  }
+  for (int k = 0; k < N; ++k)
+    if (k != j) mats[nm++] = s->gram[k];
   hipError_t e = launch_prep_gplus2(stream, R, nm, mats, 0, nullptr, (double*)(w + l.Mp), nullptr,
                                     (int32_t*)(w + pl.rank), nullptr, s->status);
   if (e != hipSuccess) return hip_fail(e, "pseudo-inverse of the Hadamard product of Grams");
@@ -1996,13 +1973,11 @@ krps_status krps_fit(krps_sampler s, krps_tensor t, const double* sigma, double*
   if (sigma == nullptr || fit == nullptr || ws == nullptr)
     return fail(KRPS_EINVAL, "sigma/fit/workspace is NULL");
   const int R = s->R, N = s->N;
-  // The split path's tree roots carry its bf16 rounding (~2^-16 relative),
-  // which ||T~||^2 - 2 <T, T~> would amplify by ~1 / (1 - fit)^2; the fit
-  // takes float64 Grams of the float32 factors instead (float64 MFMA, the
-  // tree builder without stored nodes over at most 2048 leaves).  All its
+  // The Grams G_k are float64 in every precision (the split path's too),
+  // so ||T~||^2 = sigma^T ((*) G_k) sigma carries no bf16 rounding, which
+  // ||T~||^2 - 2 <T, T~> would amplify by ~1 / (1 - fit)^2.  The fit's
   // scratch lies in the head of the solve workspace, below the pieces of
   // krps_solve_layout.
-  const bool exact_gram = s->prec == KRPS_BF16X2;
   const SolveHead h = plan_head(s);
   if (ws_bytes < h.total) return fail(KRPS_EWORKSPACE, "workspace too small for the fit");
   char* w = (char*)ws;
@@ -2017,13 +1992,6 @@ krps_status krps_fit(krps_sampler s, krps_tensor t, const double* sigma, double*
   for (int k = 0; k < N; ++k) {
     fa.U[k] = s->U[k];
     fa.G[k] = s->gram[k];
-    if (exact_gram) {
-      double* gk = (double*)(w + h.fitg) + (size_t)k * R * R;
-      hipError_t e = launch_tree_build(stream, KRPS_FP32, s->U[k], s->I[k], R, h.gts[k], nullptr,
-                                       gk, (double*)(w + h.fitscr), h.fitscr_bytes, 2);
-      if (e != hipSuccess) return hip_fail(e, "float64 Gram for the fit");
-      fa.G[k] = gk;
-    }
   }
   fa.sigma = sigma;
   double* partial = (double*)(w + h.fitp);
@@ -2139,14 +2107,8 @@ krps_status krps_workspace_regions(int N, const int64_t* I, int R, int F, krps_p
   const SolvePlan pl = plan_solve(&tmp, J);
   const SolveHead& h = pl.head;
   const krps_solve_layout& l = pl.lay;
-  size_t fext = 0;
-  if (p == KRPS_BF16X2)
-    for (int k = 0; k < N; ++k) fext = std::max(fext, tree_build_scratch_extent(h.gts[k], R));
   rl.add(2, "fit partials", h.fitp, span(h.fitp, h.fitout), fit_partial_bytes());
-  rl.add(2, "fit result", h.fitout, span(h.fitout, h.fitg), 16);
-  rl.add(2, "fit Grams", h.fitg, span(h.fitg, h.fitscr),
-         p == KRPS_BF16X2 ? (size_t)N * R * R * 8 : 0);
-  rl.add(2, "fit Gram scratch", h.fitscr, span(h.fitscr, h.npart), fext);
+  rl.add(2, "fit result", h.fitout, span(h.fitout, h.npart), 16);
   rl.add(2, "norm partials", h.npart, span(h.npart, h.nsig), solve_partial_bytes(R));
   rl.add(2, "norm sigma", h.nsig, span(h.nsig, h.ctrw), (size_t)R * 8);
   rl.add(2, "sweep counter", h.ctrw, span(h.ctrw, l.draw), 8);

@@ -208,7 +208,8 @@ struct FitArgs {
 
 // Status words of a sampler (int32 [3], cleared at creation): word 0 holds
 // flag bits set by kernels, word 1 counts sampled rows whose computed
-// probability was not positive (rounding; they were given weight 0), word 2
+// probability, or a total mass of whose walk, was not positive (rounding;
+// they were given weight 0), word 2
 // counts walks whose float32-copy decisions were not certain and that were
 // walked again from the float64 tree.
 enum : int32_t { ST_ZERO = 1, ST_NUMERIC = 2 };
@@ -218,11 +219,14 @@ enum : int32_t { ST_ZERO = 1, ST_NUMERIC = 2 };
 size_t tree_build_scratch_bytes(int64_t L, int R);
 // Largest extent of the scratch that a build of this shape touches.
 size_t tree_build_scratch_extent(const TreeShape& ts, int R);
+// p: KRPS_FP64 (float64 U), KRPS_FP32 (float32 U, float64 products and
+// sums, float32 nodes), KRPS_BF16X2 (float32 U, three-part bf16 split
+// products summed in float32; used for the Gram of a solve's sampled rows).
 hipError_t launch_tree_build(hipStream_t st, krps_precision p, const void* U, int64_t I, int R,
                              const TreeShape& ts, void* nodes, double* gram_full,
-                             double* scratch, size_t scratch_bytes, int split_terms = 2,
-                             float* nodes32 = nullptr, int team = 0);
-// Waves per team of the leaf pass available for R and a precision (the
+                             double* scratch, size_t scratch_bytes, float* nodes32 = nullptr,
+                             int team = 0);
+// Waves per team of the sampler trees' leaf pass available for R (the
 // default first; 0 also selects the default).
 std::vector<int> build_team_choices(int R, krps_precision p);
 

@@ -29,10 +29,11 @@ namespace krps {
 
 namespace {
 
-// M_SPLIT: x = hi + lo (bf16 each), products hi hi + hi lo + lo hi (about
-// 2^-16 relative error).  M_SPLIT3: x = hi + mid + lo, the six products
-// whose parts' orders sum to at most 2 (about 2^-24, float32-like).
-enum { M_F64 = 0, M_F32 = 1, M_SPLIT = 2, M_SPLIT3 = 3 };
+// M_F64: float64 factor; M_F32: float32 factor, float64 products (exact)
+// and sums.  M_SPLIT3 (the Gram of a solve's sampled rows on the split
+// path): x = hi + mid + lo (bf16 each), the six products whose parts'
+// orders sum to at most 2 (about 2^-24, float32-like), float32 sums.
+enum { M_F64 = 0, M_F32 = 1, M_SPLIT3 = 3 };
 
 __device__ __forceinline__ f64x4 mfma_f64(double a, double b, f64x4 c) {
   return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
@@ -68,7 +69,7 @@ __device__ __forceinline__ void leaf_run_body(const void* __restrict__ Uv, int64
   // storage type of the factor and the nodes; float64 accumulation on the
   // matrix cores except for the bf16 split
   using T = std::conditional_t<MODE == M_F64, double, float>;
-  constexpr bool SPLIT = MODE == M_SPLIT || MODE == M_SPLIT3;
+  constexpr bool SPLIT = MODE == M_SPLIT3;
   using ACC = std::conditional_t<SPLIT, f32x4, f64x4>;
   constexpr int NPAIRS = NT * (NT + 1) / 2;
   constexpr int NPW = (NPAIRS + TW - 1) / TW;
@@ -149,14 +150,10 @@ __device__ __forceinline__ void leaf_run_body(const void* __restrict__ Uv, int64
               const float x = (cv && row < r1) ? xs[t][j] : 0.f;
               const __bf16 h = (__bf16)x;
               hi[t][j] = h;
-              if constexpr (MODE == M_SPLIT3) {
-                const float r = x - (float)h;
-                const __bf16 m = (__bf16)r;
-                mid[t][j] = m;
-                lo[t][j] = (__bf16)(r - (float)m);
-              } else {
-                lo[t][j] = (__bf16)(x - (float)h);
-              }
+              const float r = x - (float)h;
+              const __bf16 m = (__bf16)r;
+              mid[t][j] = m;
+              lo[t][j] = (__bf16)(r - (float)m);
             }
           });
           static_for<0, NPAIRS>([&](auto pp) {
@@ -165,19 +162,13 @@ __device__ __forceinline__ void leaf_run_body(const void* __restrict__ Uv, int64
             constexpr int tb = pair_tb(NT, pr);
             if constexpr (pr % TW == W) {
               ACC a = node[pr / TW];
-              if constexpr (MODE == M_SPLIT3) {
-                // smallest terms first
-                a = mfma_bf16(mid[ta], mid[tb], a);
-                a = mfma_bf16(hi[ta], lo[tb], a);
-                a = mfma_bf16(lo[ta], hi[tb], a);
-                a = mfma_bf16(hi[ta], mid[tb], a);
-                a = mfma_bf16(mid[ta], hi[tb], a);
-                a = mfma_bf16(hi[ta], hi[tb], a);
-              } else {
-                a = mfma_bf16(hi[ta], hi[tb], a);
-                a = mfma_bf16(hi[ta], lo[tb], a);
-                a = mfma_bf16(lo[ta], hi[tb], a);
-              }
+              // smallest terms first
+              a = mfma_bf16(mid[ta], mid[tb], a);
+              a = mfma_bf16(hi[ta], lo[tb], a);
+              a = mfma_bf16(lo[ta], hi[tb], a);
+              a = mfma_bf16(hi[ta], mid[tb], a);
+              a = mfma_bf16(mid[ta], hi[tb], a);
+              a = mfma_bf16(hi[ta], hi[tb], a);
               node[pr / TW] = a;
             }
           });
@@ -326,7 +317,7 @@ template <int MODE>
 hipError_t dispatch_leaf(hipStream_t st, const void* U, int64_t I, int R, int F, int64_t L, int D,
                          void* nodes, double* tops, float* nodes32, int team, int& s_eff) {
 #define KRPS_LEAF(NT, TW, S) run_leaf<MODE, NT, TW, S>(st, U, I, R, F, L, D, nodes, tops, nodes32, s_eff)
-  if constexpr (MODE == M_SPLIT || MODE == M_SPLIT3) {
+  if constexpr (MODE == M_SPLIT3) {
     if (R <= 16) return KRPS_LEAF(1, 1, 4);
     if (R <= 32) return team == 3 ? KRPS_LEAF(2, 3, 4) : KRPS_LEAF(2, 1, 4);
     if (R <= 64) return team == 5 ? KRPS_LEAF(4, 5, 3) : KRPS_LEAF(4, 2, 3);
@@ -346,12 +337,12 @@ constexpr int MIN_S = 2;  // smallest register-run depth used above
 
 }  // namespace
 
-std::vector<int> build_team_choices(int R, krps_precision p) {
-  const bool split = p == KRPS_BF16X2;
+std::vector<int> build_team_choices(int R, krps_precision) {
+  // the sampler's trees are built with float64 products in every precision
   if (R <= 16) return {1};
-  if (R <= 32) return split ? std::vector<int>{1, 3} : std::vector<int>{3, 1};
-  if (R <= 64) return split ? std::vector<int>{2, 5} : std::vector<int>{5, 2};
-  return split ? std::vector<int>{4, 8} : std::vector<int>{12, 6};
+  if (R <= 32) return {3, 1};
+  if (R <= 64) return {5, 2};
+  return {12, 6};
 }
 
 size_t tree_build_scratch_bytes(int64_t L, int R) {
@@ -389,7 +380,7 @@ size_t tree_build_scratch_extent(const TreeShape& ts, int R) {
 
 hipError_t launch_tree_build(hipStream_t st, krps_precision p, const void* U, int64_t I, int R,
                              const TreeShape& ts, void* nodes, double* gram_full, double* scratch,
-                             size_t scratch_bytes, int split_terms, float* nodes32, int team) {
+                             size_t scratch_bytes, float* nodes32, int team) {
   const int64_t TR = tri(R);
   if (p != KRPS_FP64) nodes32 = nullptr;  // only float64 trees carry a float32 copy
   const int64_t a_nodes = ceil_div(ts.L, int64_t(1) << MIN_S);
@@ -402,10 +393,8 @@ hipError_t launch_tree_build(hipStream_t st, krps_precision p, const void* U, in
     e = dispatch_leaf<M_F64>(st, U, I, R, ts.F, ts.L, ts.D, nodes, bufA, nodes32, team, s_eff);
   else if (p == KRPS_FP32)
     e = dispatch_leaf<M_F32>(st, U, I, R, ts.F, ts.L, ts.D, nodes, bufA, nodes32, team, s_eff);
-  else if (split_terms == 3)
-    e = dispatch_leaf<M_SPLIT3>(st, U, I, R, ts.F, ts.L, ts.D, nodes, bufA, nodes32, team, s_eff);
   else
-    e = dispatch_leaf<M_SPLIT>(st, U, I, R, ts.F, ts.L, ts.D, nodes, bufA, nodes32, team, s_eff);
+    e = dispatch_leaf<M_SPLIT3>(st, U, I, R, ts.F, ts.L, ts.D, nodes, bufA, nodes32, team, s_eff);
   if (e != hipSuccess) return e;
   int lev = ts.D - s_eff;
   int64_t n = ceil_div(ts.L, int64_t(1) << s_eff);

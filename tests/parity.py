@@ -21,24 +21,14 @@ comparison differently.  A draw is excused when
   eigenvector roundings), pinned on the CPU by
   ``test_scaled_margin_bounds_the_effect_of_storage_rounding``.
 
-The split path's Grams carry ~2^-16 relative error per product (the split
-x = hi + lo into two bf16 values keeps 16 significant bits, and the three
-products drop lo lo); they reach the walk through the nodes and, amplified
-by the conditioning of G and of the eigenvalue gaps of G_{>k}, through G^+
-and the eigenvectors.  Its mismatches are counted and reported with the
-largest scaled margin needed to excuse them; the tests hold that margin to
-``bf16_scaled(R) = R 2^-16`` (R split errors adding coherently in a node's
-quadratic form) and the share of differing draws to a stated bound.
+The split path samples from the float32 path's trees (float64 products of
+the float32 factors, float32 nodes), so it is held to the float32 rule.
 """
 import numpy as np
 
 U32 = 2.0 ** -24
 FP64_MARGIN = 1e-10
 FP32_SCALED = U32
-
-
-def bf16_scaled(R):
-    return R * 2.0 ** -16
 
 
 def compare(gpu_idx, dr, prec):

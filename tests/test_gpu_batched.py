@@ -5,12 +5,11 @@ import pytest
 
 import synth
 from oracle import sampler as osmp
-from parity import bf16_scaled, compare, report
+from parity import compare, report
 
 pytestmark = pytest.mark.gpu
 
-TOL_PROB = {"fp64": 1e-10, "fp32": 1e-9, "bf16x2": 1e-3}
-BF16_MISMATCH = 0.15
+TOL_PROB = {"fp64": 1e-10, "fp32": 1e-9, "bf16x2": 1e-9}
 
 
 @pytest.fixture(scope="module")
@@ -90,11 +89,7 @@ def test_batched_matches_oracle(env, p):
         pr = prob_b[i].cpu().numpy()
         rel = np.abs(pr[same] - dr.prob[same]) / dr.prob[same]
         assert rel.max() <= TOL_PROB[prec], rel.max()
-        if prec == "bf16x2":
-            assert c["mismatch"] <= BF16_MISMATCH * c["n"]
-            assert c["needed_smargin"] <= bf16_scaled(R)
-        else:
-            assert c["unexcused"] == 0
+        assert c["unexcused"] == 0
 
 
 def test_batched_seeded_equals_per_problem_seeded_draws(env):

@@ -12,16 +12,15 @@ import synth
 from chain import check_solve
 from oracle import cp as ocp
 from oracle import sampler as osmp
-from parity import bf16_scaled, compare, report
+from parity import compare, report
 
 pytestmark = pytest.mark.gpu
 
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
-TOL_PROB = {"fp64": 1e-10, "fp32": 1e-9, "bf16x2": 1e-3}
-BF16_MISMATCH = 0.15
+TOL_PROB = {"fp64": 1e-10, "fp32": 1e-9, "bf16x2": 1e-9}
 # share of draws whose comparison may legitimately go either way (margin
 # within the precision's rounding, or a near-degenerate eigenspace)
-EXCUSABLE = {"fp64": 0.01, "fp32": 0.05}
+EXCUSABLE = {"fp64": 0.01, "fp32": 0.05, "bf16x2": 0.05}
 
 
 @pytest.fixture(scope="module")
@@ -75,12 +74,8 @@ def test_sampler_at_scale_sampled_against_oracle(env, prec):
         rel = np.abs(prob[sel][same] - dr.prob[same]) / dr.prob[same]
         print(f"  q_d rel err max {rel.max():.2e}", flush=True)
         assert rel.max() <= TOL_PROB[prec]
-        if prec == "bf16x2":
-            assert c["mismatch"] <= BF16_MISMATCH * c["n"]
-            assert c["needed_smargin"] <= bf16_scaled(R)
-        else:
-            assert c["unexcused"] == 0
-            assert c["excusable_frac"] <= EXCUSABLE[prec]
+        assert c["unexcused"] == 0
+        assert c["excusable_frac"] <= EXCUSABLE[prec]
 
 
 def test_batched_samplers_at_scale(env):
@@ -173,22 +168,26 @@ def test_sketched_cp_als_chain_at_scale(env, c3, prec):
             before = [U.cpu().numpy().astype(np.float64) for U in S.factors]
             A.solve(j, torch.from_numpy(u_sweep[j]).to(ctx.device))
             torch.cuda.synchronize()
+            # weight-0 samples (a computed mass or q_d <= 0 by rounding):
+            # none in float64; on the float32-storage path a few where
+            # G_{>k}'s condition number nears 2^24 / R
+            nonpos = S.check_status()
+            assert nonpos <= (0 if prec == "fp64" else J // 1000), (s, j, nonpos)
             parts = {k: v.cpu().numpy() for k, v in A.parts(j).items()}
             errs = check_solve(T, before, j, parts, S.factors[j].cpu().numpy(),
                                A.sigma.cpu().numpy(), prec)
+            assert errs["w0"] <= nonpos, (s, j, errs["w0"], nonpos)
             for k, v in errs.items():
                 worst[k] = max(worst.get(k, 0.0), v)
             sel = np.sort(rng.choice(J, 48, replace=False))
             dr = osmp.KRPSampler(before).draw(j, u_sweep[j][sel], scaled=prec != "fp64")
             c = compare(parts["idx"][sel], dr, prec)
             mism += c["mismatch"]
-            if prec == "fp64":
-                assert c["unexcused"] == 0, (s, j)
-            else:
-                assert c["needed_smargin"] <= bf16_scaled(R), (s, j)
+            assert c["unexcused"] == 0, (s, j)
             print(f"sweep {s} solve {j}: " +
                   " ".join(f"{k} {v:.1e}" for k, v in errs.items()) +
-                  f"; sampled draws differing {c['mismatch']}/48", flush=True)
+                  f"; sampled draws differing {c['mismatch']}/48; weight-0 samples {nonpos}",
+                  flush=True)
         if s in (0, sweeps // 2, sweeps - 1):
             f = A.fit()
             ref = ocp.fit(T, [U.cpu().numpy() for U in S.factors], A.sigma.cpu().numpy())

@@ -6,19 +6,15 @@ import pytest
 import synth
 from oracle import definition as dfn
 from oracle import sampler as osmp
-from parity import bf16_scaled, compare, report
+from parity import compare, report
 
 pytestmark = pytest.mark.gpu
 
-TOL_NODE = {"fp64": 1e-12, "fp32": 1e-5, "bf16x2": 1e-4}
+TOL_NODE = {"fp64": 1e-12, "fp32": 1e-5, "bf16x2": 1e-5}
 # q_d = a G^+ a^T / rank in float64 from the stored factor rows and the
-# float64 Grams (exact products of float32 factors for FP32): only the
-# summation order differs from the oracle; the split path's Grams carry
-# ~2^-16 relative error
-TOL_PROB = {"fp64": 1e-10, "fp32": 1e-9, "bf16x2": 1e-3}
-# the split path's draws against the float64 oracle: at most this share
-# differs, and every difference lies within bf16_scaled(R) (tests/parity.py)
-BF16_MISMATCH = 0.15
+# float64 Grams (exact products of float32 factors for FP32 and the split
+# path): only the summation order differs from the oracle
+TOL_PROB = {"fp64": 1e-10, "fp32": 1e-9, "bf16x2": 1e-9}
 
 
 @pytest.fixture(scope="module")
@@ -265,20 +261,25 @@ def test_zero_product_is_reported(env):
 
 @pytest.mark.parametrize("dims,R", [((5000, 2049, 700), 32), ((3001, 1500, 800), 64),
                                     ((900, 777, 500), 128)])
-def test_split_precision_reports_mismatch_rate(env, dims, R):
-    """BF16 hi/lo split Grams against the plain float64 oracle: the share of
-    differing draws and the largest scaled margin among them stay below the
-    stated bounds, and q_d of the agreeing draws within 1e-3."""
+def test_split_precision_draws_equal_float32_draws(env, dims, R):
+    """The split path samples from the float32 path's trees (float64
+    products of the float32 factors, float32 nodes, float64 G_j), so its
+    draws are the float32 sampler's, index for index and bit for bit in
+    q_d, and against the plain float64 oracle under the float32 rule."""
     krps, torch, ctx = env
     Us = synth.gaussian_factors(dims, R, seed=99 + R, heavy_rows_frac=0.01)
+    S32 = krps.Sampler(ctx, to_dev(torch, ctx, Us, "fp32"), precision="fp32")
+    ud = torch.from_numpy(synth.uniforms(4096, len(dims), 7)).to(ctx.device)
     for exclude in (-1, 0):
         _, idx, prob, _, dr, c, rel = _compare_draw(krps, torch, ctx, Us, "bf16x2", exclude,
                                                     4096, 7)
         report(f"bf16x2 dims={dims} R={R} exclude={exclude}", c)
         print(f"  q_d rel err max {rel.max():.2e}", flush=True)
-        assert c["mismatch"] <= BF16_MISMATCH * c["n"]
-        assert c["needed_smargin"] <= bf16_scaled(R)
+        assert c["unexcused"] == 0
         assert rel.max() <= TOL_PROB["bf16x2"]
+        i32, p32, _ = S32.sample(exclude, ud, check_status=True)
+        assert np.array_equal(idx, i32.cpu().numpy().astype(np.int64))
+        assert np.array_equal(prob.cpu().numpy(), p32.cpu().numpy())
 
 
 def test_autotune_measures_then_reads_the_cache(tmp_path):
@@ -474,11 +475,7 @@ def test_entry_updates_match_a_rebuilt_oracle(env, prec):
         dr = osmp.KRPSampler(Us2).draw(exclude, u01, scaled=prec != "fp64")
         c = compare(idx.cpu().numpy(), dr, prec)
         report(f"after updates {prec} exclude={exclude}", c)
-        if prec == "bf16x2":
-            assert c["mismatch"] <= BF16_MISMATCH * c["n"]
-            assert c["needed_smargin"] <= bf16_scaled(R)
-        else:
-            assert c["unexcused"] == 0
+        assert c["unexcused"] == 0
         if prec == "fp64":
             S.set_filter(100)
             i2, p2, _ = S.sample(exclude, ud)
@@ -505,7 +502,7 @@ def test_every_tunable_shape_matches_the_oracle(env, prec, R, dims):
     u01 = synth.uniforms(J, len(dims), 601 + R)
     ud = torch.from_numpy(u01).to(ctx.device)
     lps_all = {16: (8, 16), 32: (16, 32, 64), 64: (64,), 128: (64,)}[R]
-    teams = {16: (1,), 32: (1, 3), 64: (2, 5), 128: (4, 8) if prec == "bf16x2" else (6, 12)}[R]
+    teams = {16: (1,), 32: (1, 3), 64: (2, 5), 128: (6, 12)}[R]
     samplers, refs = [], []
     for F in (R // 2, 2 * R):
         ref = osmp.KRPSampler(Us, F=F).draw(-1, u01, scaled=prec != "fp64")
@@ -518,11 +515,7 @@ def test_every_tunable_shape_matches_the_oracle(env, prec, R, dims):
                 idx, prob, _ = S.sample(-1, ud)
                 c = compare(idx.cpu().numpy(), ref, prec)
                 report(f"shape {prec} R={R} F={F} lps={lps} team={team}", c)
-                if prec == "bf16x2":
-                    assert c["mismatch"] <= BF16_MISMATCH * c["n"]
-                    assert c["needed_smargin"] <= bf16_scaled(R)
-                else:
-                    assert c["unexcused"] == 0
+                assert c["unexcused"] == 0
                 samplers.append(S)
                 refs.append((ref, idx))
     # one batch over all of them: the batched walk of each class gives the

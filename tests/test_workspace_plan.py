@@ -60,7 +60,7 @@ def test_regions_are_ordered_and_large_enough(krps, prec, dims, R, F, nnz, J):
     assert last["offset"] + last["bytes"] == sz.value
     # fit / normalisation scratch below every piece of the solve layout
     solve = {r["name"]: r for r in by_ws[2]}
-    head = ["fit partials", "fit result", "fit Grams", "fit Gram scratch", "norm partials",
+    head = ["fit partials", "fit result", "norm partials",
             "norm sigma", "sweep counter"]
     pieces = ["draw", "idx", "prob", "w", "rows", "M", "M+", "Y", "Y rows", "Y row count"]
     top = max(solve[h]["offset"] + solve[h]["bytes"] for h in head)
