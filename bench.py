@@ -2,7 +2,8 @@
 CP-ALS sweep on one MI355X.
 
 Headline number (``value``, samples/s, the plain float64 path; float32
-storage and BF16 hi/lo split trees beside it): N = 3 factors of 2^20 x 32
+storage and the split path, whose sampler is the float32 one, beside it):
+N = 3 factors of 2^20 x 32
 (N(0,1) with 1% of the rows scaled by 100), J = 65,536 samples drawn from
 the Khatri-Rao product of the other two factors for each excluded mode
 k in {0, 1, 2}.  One step = rebuild the three segment trees + prepare and
@@ -12,8 +13,9 @@ three preparations batched and the three walks in one persistent launch.
 Second half of the metric (``als``): sketched CP-ALS on a sparse
 1e6 x 1e6 x 1e5 tensor with 1e8 Zipf(1.2) nonzeros, R = 64, J = 65,536
 samples per solve, 10 sweeps, each sweep replayed from a HIP graph; sweep
-time (fit excluded) and the fit after every sweep, BF16 hi/lo split Grams
-against the plain float64 path, the float64 oracle's fits beside them, the
+time (fit excluded) and the fit after every sweep, the split path (float32
+factors and trees, the sampled Gram from bf16 hi/mid/lo products, Y in
+float32) against the plain float64 path, the float64 oracle's fits beside them, the
 exact (unsampled) ALS fits for the fraction of exact fit, and the sweep's
 roofline floor.
 
@@ -883,8 +885,8 @@ def main():
         "config": {"workload": "sampler N=3, I=2^20, R=32, J=65536 per excluded mode k=0,1,2",
                    "N": N, "I": dims[0], "R": R, "J": J, "leaf_size": R,
                    "precision": head,
-                   "arith": {"bf16x2": "tree build: bf16 hi/lo split on MFMA (f32 accumulate); "
-                                       "walk: f64 over f32-stored trees",
+                   "arith": {"bf16x2": "tree build: f64 MFMA; walk: f64 over f32-stored trees; "
+                                       "sketched solve: bf16 hi/mid/lo split sampled Gram",
                              "fp32": "tree build: f64 MFMA; walk: f64 over f32-stored trees",
                              "fp64": "f64 throughout"}[head]},
         "roofline": roofs[head],
