@@ -655,11 +655,11 @@ hipError_t launch_eig_batched(hipStream_t st, bool f64, const EigJob* jobs, int 
 
 // P[p][u] = w_p V[a_p][u] V[b_p][u] (columns u >= R are 0), RMAX columns.
 template <typename T, int RMAX>
-__global__ __launch_bounds__(256) void zweights_kernel(const T* __restrict__ V, int R,
-                                                       double* __restrict__ P) {
+__device__ __forceinline__ void zweights_body(const T* __restrict__ V, int R,
+                                              double* __restrict__ P, int64_t i0,
+                                              int64_t stride) {
   const int TR = R * (R + 1) / 2;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < (int64_t)TR * RMAX;
-       i += (int64_t)gridDim.x * blockDim.x) {
+  for (int64_t i = i0; i < (int64_t)TR * RMAX; i += stride) {
     const int p = (int)(i / RMAX), u = (int)(i % RMAX);
     double v = 0.0;
     if (u < R) {
@@ -671,23 +671,36 @@ __global__ __launch_bounds__(256) void zweights_kernel(const T* __restrict__ V, 
   }
 }
 
+template <typename T, int RMAX>
+__global__ __launch_bounds__(256) void zweights_kernel(const T* __restrict__ V, int R,
+                                                       double* __restrict__ P) {
+  zweights_body<T, RMAX>(V, R, P, (int64_t)blockIdx.x * blockDim.x + threadIdx.x,
+                         (int64_t)gridDim.x * blockDim.x);
+}
+
+// One job per blockIdx.y.
+template <typename T, int RMAX>
+__global__ __launch_bounds__(256) void zweights_batched_kernel(const ZtabJob* __restrict__ jobs) {
+  const ZtabJob& j = jobs[blockIdx.y];
+  zweights_body<T, RMAX>((const T*)j.V, j.R, j.weights,
+                         (int64_t)blockIdx.x * blockDim.x + threadIdx.x,
+                         (int64_t)gridDim.x * blockDim.x);
+}
+
 // The contraction on the float64 matrix cores: a wavefront owns 16 nodes
 // and every u (RMAX / 16 accumulator tiles of v_mfma_f64_16x16x4f64); per
 // step of 4 packed entries lane l supplies A = P[p0 + l/16][16 t + l%16]
 // and B = G^(n0 + l%16)[p0 + l/16], and holds the result rows 4 i + l/16 of
 // column l%16.  Loads of KS steps are issued before their products.
 template <typename T, int RMAX>
-__global__ __launch_bounds__(256) void ztab_kernel(const T* __restrict__ Z, int64_t nn, int R,
-                                                   const double* __restrict__ P,
-                                                   double* __restrict__ tab) {
+__device__ __forceinline__ void ztab_unit(const T* __restrict__ Z, int64_t nn, int R,
+                                          const double* __restrict__ P, double* __restrict__ tab,
+                                          int64_t n0, int lane) {
   constexpr int NTU = RMAX / 16;  // u tiles
   constexpr int KS = 8;           // steps of 4 entries whose loads go together
   const int TR = R * (R + 1) / 2;
-  const int lane = threadIdx.x & 63;
   const int r16 = lane & 15, k4 = lane >> 4;
-  const int64_t nwave = (int64_t)gridDim.x * (blockDim.x >> 6);
-  for (int64_t n0 = ((int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6)) * 16; n0 < nn;
-       n0 += nwave * 16) {
+  {
     f64x4 acc[NTU];
 #pragma unroll
     for (int t = 0; t < NTU; ++t) acc[t] = f64x4{0, 0, 0, 0};
@@ -719,6 +732,36 @@ __global__ __launch_bounds__(256) void ztab_kernel(const T* __restrict__ Z, int6
         const int u = 16 * t + 4 * i + k4;
         if (u < R && n < nn) tab[(int64_t)u * nn + n] = acc[t][i];
       }
+  }
+}
+
+template <typename T, int RMAX>
+__global__ __launch_bounds__(256) void ztab_kernel(const T* __restrict__ Z, int64_t nn, int R,
+                                                   const double* __restrict__ P,
+                                                   double* __restrict__ tab) {
+  const int64_t nwave = (int64_t)gridDim.x * (blockDim.x >> 6);
+  for (int64_t n0 = ((int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6)) * 16; n0 < nn;
+       n0 += nwave * 16)
+    ztab_unit<T, RMAX>(Z, nn, R, P, tab, n0, threadIdx.x & 63);
+}
+
+// Several problems' tables in one launch: wavefront w takes units w,
+// w + waves, ... of the batch (a unit is 16 nodes of one job; the job is
+// found by a wave-uniform binary search over the jobs' first units).
+template <typename T, int RMAX>
+__global__ __launch_bounds__(256) void ztab_batched_kernel(const ZtabJob* __restrict__ jobs,
+                                                           int njobs, int64_t units) {
+  const int64_t nwave = (int64_t)gridDim.x * (blockDim.x >> 6);
+  for (int64_t un = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); un < units;
+       un += nwave) {
+    int lo = 0, hi = njobs;  // last job with unit0 <= un
+    while (hi - lo > 1) {
+      const int mid = (lo + hi) >> 1;
+      if (jobs[mid].unit0 <= un) lo = mid; else hi = mid;
+    }
+    const ZtabJob& j = jobs[lo];
+    ztab_unit<T, RMAX>((const T*)j.Z, j.nn, j.R, j.weights, j.tab, (un - j.unit0) * 16,
+                       threadIdx.x & 63);
   }
 }
 
@@ -759,6 +802,49 @@ hipError_t launch_ztab(hipStream_t st, krps_precision p, const void* Z, int64_t 
   if (p == KRPS_FP64)
     return run_ztab<double>(st, (const double*)Z, nn, R, (const double*)V, weights, tab);
   return run_ztab<float>(st, (const float*)Z, nn, R, (const float*)V, weights, tab);
+}
+
+int ztab_rclass(int R) { return R <= 32 ? 0 : R <= 64 ? 1 : 2; }
+
+namespace {
+
+template <typename T, int RMAX>
+void run_ztab_batched(hipStream_t st, const ZtabJob* jobs, int njobs, int64_t units) {
+  // weights: the largest job's tri(R) x RMAX entries per row of blocks
+  const int TR = RMAX * (RMAX + 1) / 2;
+  int64_t wb = ((int64_t)TR * RMAX + 255) / 256;
+  if (wb > 256) wb = 256;
+  hipLaunchKernelGGL((zweights_batched_kernel<T, RMAX>), dim3((unsigned)wb, (unsigned)njobs),
+                     dim3(256), 0, st, jobs);
+  int64_t blocks = (units + 3) / 4;
+  if (blocks > 8192) blocks = 8192;
+  if (blocks < 1) blocks = 1;
+  hipLaunchKernelGGL((ztab_batched_kernel<T, RMAX>), dim3((unsigned)blocks), dim3(256), 0, st,
+                     jobs, njobs, units);
+}
+
+template <typename T>
+void run_ztab_batched_t(hipStream_t st, int rclass, const ZtabJob* jobs, int njobs,
+                        int64_t units) {
+  if (rclass == 0)
+    run_ztab_batched<T, 32>(st, jobs, njobs, units);
+  else if (rclass == 1)
+    run_ztab_batched<T, 64>(st, jobs, njobs, units);
+  else
+    run_ztab_batched<T, 128>(st, jobs, njobs, units);
+}
+
+}  // namespace
+
+hipError_t launch_ztab_batched(hipStream_t st, bool f64, int rclass, const ZtabJob* jobs,
+                               int njobs, int64_t units) {
+  if (njobs <= 0 || units <= 0) return hipSuccess;
+  if (njobs > 65535) return hipErrorInvalidValue;
+  if (f64)
+    run_ztab_batched_t<double>(st, rclass, jobs, njobs, units);
+  else
+    run_ztab_batched_t<float>(st, rclass, jobs, njobs, units);
+  return hipGetLastError();
 }
 
 hipError_t launch_pinv(hipStream_t st, int R, const double* M, double* Mp_full, int32_t* rank,

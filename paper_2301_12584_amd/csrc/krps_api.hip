@@ -1126,7 +1126,7 @@ namespace {
 // index table, then the job and problem descriptors and two task counters.
 struct BatchPlan {
   std::vector<size_t> draw_off, tab_off;
-  size_t desc = 0, prep = 0, eig = 0, probs = 0, counters = 0, total = 0;
+  size_t desc = 0, prep = 0, eig = 0, ztab = 0, probs = 0, counters = 0, total = 0;
   int n_eig = 0;
 };
 
@@ -1147,6 +1147,8 @@ BatchPlan plan_batch(int P, const krps_sampler* s, const int* exclude) {
   off += align_up((size_t)P * sizeof(PrepJob));
   pl.eig = off;
   off += align_up((size_t)pl.n_eig * sizeof(EigJob));
+  pl.ztab = off;
+  off += align_up((size_t)P * sizeof(ZtabJob));
   pl.probs = off;
   off += align_up((size_t)P * sizeof(BatchProblem));
   pl.counters = off;
@@ -1283,12 +1285,56 @@ krps_status krps_sample_batched_prepare(krps_ctx ctx, int P, const krps_sampler*
   });
   std::vector<EigJob> eig_sorted;
   for (int i : eord) eig_sorted.push_back(eig[i]);
+  // first-mode table jobs, grouped by storage type and R class; within a
+  // group the units of 16 nodes are numbered job after job
+  std::vector<ZtabJob> zt;
+  std::vector<int> zprob;
+  for (int p = 0; p < P; ++p) {
+    krps_sampler sp = s[p];
+    if (sp->znmax == 0 || prep[p].nsteps == 0) continue;
+    const int k0 = prep[p].gl.order[0];
+    char* dw = w + pl.draw_off[p];
+    ZtabJob zj;
+    memset(&zj, 0, sizeof(zj));
+    zj.Z = sp->nodes[k0];
+    zj.V = dw + sp->lay.vecs + (size_t)k0 * sp->R * sp->R * sp->elem;
+    zj.weights = (double*)(dw + sp->zw_off);
+    zj.tab = (double*)(dw + sp->ztab_off);
+    zj.nn = sp->shape[k0].n_nodes;
+    zj.R = sp->R;
+    zt.push_back(zj);
+    zprob.push_back(p);
+  }
+  std::vector<int> zord(zt.size());
+  for (size_t i = 0; i < zt.size(); ++i) zord[i] = (int)i;
+  auto zkey = [&](int i) {
+    return (s[zprob[i]]->prec == KRPS_FP64 ? 0 : 3) + ztab_rclass(zt[i].R);
+  };
+  std::stable_sort(zord.begin(), zord.end(), [&](int x, int y) { return zkey(x) < zkey(y); });
+  std::vector<ZtabJob> zt_sorted;
+  std::vector<int64_t> zgroup_units;  // per job: its group's total units
+  for (size_t i = 0; i < zord.size();) {
+    size_t j = i;
+    int64_t u = 0;
+    while (j < zord.size() && zkey(zord[j]) == zkey(zord[i])) {
+      ZtabJob zj = zt[zord[j]];
+      zj.unit0 = u;
+      u += (zj.nn + 15) / 16;
+      zt_sorted.push_back(zj);
+      ++j;
+    }
+    for (size_t q = i; q < j; ++q) zgroup_units.push_back(u);
+    i = j;
+  }
   // stage and copy the job descriptors
   std::vector<char> host(pl.probs - pl.prep);
   memcpy(host.data(), prep_sorted.data(), (size_t)P * sizeof(PrepJob));
   if (!eig_sorted.empty())
     memcpy(host.data() + (pl.eig - pl.prep), eig_sorted.data(),
            eig_sorted.size() * sizeof(EigJob));
+  if (!zt_sorted.empty())
+    memcpy(host.data() + (pl.ztab - pl.prep), zt_sorted.data(),
+           zt_sorted.size() * sizeof(ZtabJob));
   st = stage_copy(ctx, 0, host.data(), host.size(), w + pl.prep);
   if (st != KRPS_OK) return st;
   // preparations, grouped by block size
@@ -1318,16 +1364,16 @@ krps_status krps_sample_batched_prepare(krps_ctx ctx, int P, const krps_sampler*
     if (e != hipSuccess) return hip_fail(e, "batched eigen-trees");
     i = j;
   }
-  // first-mode factor-tree mass tables, one launch per problem
-  for (int p = 0; p < P; ++p) {
-    krps_sampler sp = s[p];
-    const int k0 = prep[p].gl.order[0];
-    if (sp->znmax == 0 || prep[p].nsteps == 0) continue;
-    char* dw = w + pl.draw_off[p];
-    hipError_t e = launch_ztab(stream, sp->prec, sp->nodes[k0], sp->shape[k0].n_nodes, sp->R,
-                               dw + sp->lay.vecs + (size_t)k0 * sp->R * sp->R * sp->elem,
-                               (double*)(dw + sp->zw_off), (double*)(dw + sp->ztab_off));
+  // first-mode factor-tree mass tables, one launch pair per group
+  const ZtabJob* dzt = (const ZtabJob*)(w + pl.ztab);
+  for (size_t i = 0; i < zt_sorted.size();) {
+    size_t j = i;
+    while (j < zt_sorted.size() && zkey(zord[j]) == zkey(zord[i])) ++j;
+    const bool f64 = s[zprob[zord[i]]]->prec == KRPS_FP64;
+    hipError_t e = launch_ztab_batched(stream, f64, ztab_rclass(zt_sorted[i].R), dzt + i,
+                                       (int)(j - i), zgroup_units[i]);
     if (e != hipSuccess) return hip_fail(e, "batched first-mode tables");
+    i = j;
   }
   return KRPS_OK;
 }
@@ -2197,7 +2243,8 @@ krps_status krps_workspace_regions(int N, const int64_t* I, int R, int F, krps_p
       rl.add(4, nm, bp.tab_off[q], span(bp.tab_off[q], tnext), (size_t)TR * 2);
     }
     rl.add(4, "prep jobs", bp.prep, span(bp.prep, bp.eig), (size_t)N * sizeof(PrepJob));
-    rl.add(4, "eigen jobs", bp.eig, span(bp.eig, bp.probs), (size_t)bp.n_eig * sizeof(EigJob));
+    rl.add(4, "eigen jobs", bp.eig, span(bp.eig, bp.ztab), (size_t)bp.n_eig * sizeof(EigJob));
+    rl.add(4, "table jobs", bp.ztab, span(bp.ztab, bp.probs), (size_t)N * sizeof(ZtabJob));
     rl.add(4, "problems", bp.probs, span(bp.probs, bp.counters),
            (size_t)N * sizeof(BatchProblem));
     rl.add(4, "task counters", bp.counters, span(bp.counters, bp.total),

@@ -265,6 +265,20 @@ hipError_t launch_prep_eig2(hipStream_t st, krps_precision p, int R, int nsteps,
 size_t ztab_weights_bytes(int R);
 hipError_t launch_ztab(hipStream_t st, krps_precision p, const void* Z, int64_t nn, int R,
                        const void* V, double* weights, double* tab);
+// The same tables for several problems: one job per problem, all of one
+// storage type and R class (R <= 32, <= 64, <= 128); unit0 = the job's
+// first unit of 16 nodes in the batch's numbering, units = the total.
+struct ZtabJob {
+  const void* Z;
+  const void* V;
+  double* weights;
+  double* tab;
+  int64_t nn, unit0;
+  int R, pad;
+};
+int ztab_rclass(int R);
+hipError_t launch_ztab_batched(hipStream_t st, bool f64, int rclass, const ZtabJob* jobs,
+                               int njobs, int64_t units);
 // rank points at two int32: the rank and the Jacobi sweep count.  A zero or
 // non-finite M sets ST_ZERO / ST_NUMERIC in *status (if not null): the
 // pseudo-inverse of such an M is returned as 0.
