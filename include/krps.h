@@ -445,7 +445,9 @@ typedef struct {
 
 /* Selects the walk shape of a sampler: lanes per sample (0 = default;
  * 4 or 8 for R <= 8, 8 or 16 for R <= 16, 16, 32 or 64 for R <= 32, 64
- * above).  The index and probability of every draw do not depend on it. */
+ * above; the defaults are 4, 8, 32 for float64 and 16 for float32
+ * storage at R <= 32, and 64).  The index and probability of every draw do
+ * not depend on it. */
 krps_status krps_sampler_set_lps(krps_sampler s, int lps);
 
 /* Deterministic sketched solves (on != 0) for runs that must repeat bit
