@@ -9,5 +9,7 @@ if ROOT not in sys.path:
 
 
 def pytest_configure(config):
+    import progress
+    progress.CONFIG = config
     config.addinivalue_line("markers", "gpu: needs an MI355X (run with -m gpu)")
     config.addinivalue_line("markers", "slow: long CPU test")

@@ -13,6 +13,7 @@ from chain import check_solve
 from oracle import cp as ocp
 from oracle import sampler as osmp
 from parity import compare, report
+from progress import emit
 
 pytestmark = pytest.mark.gpu
 
@@ -39,7 +40,7 @@ def test_sampler_at_scale_sampled_against_oracle(env, prec):
     krps, torch, ctx = env
     cfg = synth.CONFIGS[2]
     dims, R, J, N = cfg["dims"], cfg["R"], cfg["J"], cfg["N"]
-    print(f"sampler at scale {prec}", flush=True)
+    emit(f"sampler at scale {prec}", flush=True)
     Us = synth.gaussian_factors(dims, R, synth.config_seed(2),
                                 heavy_rows_frac=cfg["heavy_rows_frac"],
                                 heavy_row_scale=cfg["heavy_row_scale"])
@@ -72,7 +73,7 @@ def test_sampler_at_scale_sampled_against_oracle(env, prec):
         report(f"sampler at scale {prec} exclude={k}", c)
         same = c["same"]
         rel = np.abs(prob[sel][same] - dr.prob[same]) / dr.prob[same]
-        print(f"  q_d rel err max {rel.max():.2e}", flush=True)
+        emit(f"  q_d rel err max {rel.max():.2e}", flush=True)
         assert rel.max() <= TOL_PROB[prec]
         assert c["unexcused"] == 0
         assert c["excusable_frac"] <= EXCUSABLE[prec]
@@ -96,7 +97,7 @@ def test_batched_samplers_at_scale(env):
         samplers.append(krps.Sampler(ctx, Ud, precision="fp32"))
         unis.append(torch.from_numpy(synth.uniforms(J, len(dims), synth.uniform_seed(4) + p))
                     .to(ctx.device))
-    print("batched at scale: samplers built", flush=True)
+    emit("batched at scale: samplers built", flush=True)
     batch = krps.Batch(ctx, samplers, [-1] * len(probs))
     idx_b, prob_b = batch.sample(unis)
     torch.cuda.synchronize()
@@ -125,11 +126,11 @@ def test_batched_samplers_at_scale(env):
 def c3():
     """The sketched CP-ALS workload's inputs and the oracle's tensor."""
     dims, idx, val, U0, R, J, sweeps, useed = synth.als_problem(3)
-    print("sketched CP-ALS inputs generated", flush=True)
+    emit("sketched CP-ALS inputs generated", flush=True)
     T = ocp.SparseTensor(dims, idx, val)
     for j in range(len(dims)):
         T.fibers(j)
-    print("oracle fibers sorted", flush=True)
+    emit("oracle fibers sorted", flush=True)
     return dims, idx, val, U0, R, J, sweeps, useed, T
 
 
@@ -184,16 +185,16 @@ def test_sketched_cp_als_chain_at_scale(env, c3, prec):
             c = compare(parts["idx"][sel], dr, prec)
             mism += c["mismatch"]
             assert c["unexcused"] == 0, (s, j)
-            print(f"sweep {s} solve {j}: " +
+            emit(f"sweep {s} solve {j}: " +
                   " ".join(f"{k} {v:.1e}" for k, v in errs.items()) +
                   f"; sampled draws differing {c['mismatch']}/48; weight-0 samples {nonpos}",
                   flush=True)
         if s in (0, sweeps // 2, sweeps - 1):
             f = A.fit()
             ref = ocp.fit(T, [U.cpu().numpy() for U in S.factors], A.sigma.cpu().numpy())
-            print(f"sweep {s}: fit {f:.8f} oracle on the same factors {ref:.8f}", flush=True)
+            emit(f"sweep {s}: fit {f:.8f} oracle on the same factors {ref:.8f}", flush=True)
             assert abs(f - ref) <= 1e-9
-    print(f"{prec}: worst step errors {worst}; sampled draws differing {mism}", flush=True)
+    emit(f"{prec}: worst step errors {worst}; sampled draws differing {mism}", flush=True)
     assert S.check_status() == 0
 
 
@@ -229,7 +230,7 @@ def test_sketched_cp_als_at_scale_against_oracle_fits(env, c3, prec):
         fits.append(A.fit())
     zero_w = S.check_status()
     diff = np.abs(np.array(fits) - np.array(ref["fits"]))
-    print(f"{prec}: fits {np.round(fits, 6)} oracle {np.round(ref['fits'], 6)} "
+    emit(f"{prec}: fits {np.round(fits, 6)} oracle {np.round(ref['fits'], 6)} "
           f"diffs {np.array2string(diff, precision=1)}; zero-weight samples {zero_w}",
           flush=True)
     assert diff[-1] <= 1e-4
@@ -260,7 +261,7 @@ def test_large_cp_als_one_solve_at_reduced_nnz(env, prec):
         A.init_range_finder(k, seed=12345 + k)
     A.sigma.fill_(1.0)
     torch.cuda.synchronize()
-    print(f"large one solve {prec}: range finder done", flush=True)
+    emit(f"large one solve {prec}: range finder done", flush=True)
     j = 3
     grams = {}
     for k in range(3):
@@ -279,7 +280,7 @@ def test_large_cp_als_one_solve_at_reduced_nnz(env, prec):
         rows *= S.factors[k][gi[:, k]].double()
     errs = check_solve(T, [None] * 4, j, parts, S.factors[j].cpu().numpy(),
                        A.sigma.cpu().numpy(), prec, grams=grams, rows=rows.cpu().numpy())
-    print(f"large one solve {prec}: " + " ".join(f"{k} {v:.1e}" for k, v in errs.items()) +
+    emit(f"large one solve {prec}: " + " ".join(f"{k} {v:.1e}" for k, v in errs.items()) +
           f"; rows of Y reached {len(parts['yrows'])}", flush=True)
     assert len(parts["yrows"]) > 0
     del A, S, Ud, Tg
