@@ -60,7 +60,7 @@ typedef enum {
   KRPS_EDEVICE = -3,     /* a HIP runtime call failed (message has the HIP error) */
   KRPS_EZERO = -4,       /* the Khatri-Rao product is the zero matrix (C = 0, Sec. 3) */
   KRPS_ENUMERIC = -5,    /* NaN/Inf met on the device */
-  KRPS_EUNSUPPORTED = -6 /* valid request this build does not implement */
+  KRPS_EUNSUPPORTED = -6 /* valid request the library does not implement */
 } krps_status;
 
 /* Arithmetic of the sampler and of the sketched solve.  Factor storage is
