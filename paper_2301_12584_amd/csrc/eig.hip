@@ -685,6 +685,10 @@ __global__ __launch_bounds__(256) void zweights_batched_kernel(const ZtabJob* __
   zweights_body<T, RMAX>((const T*)j.V, j.R, j.weights,
                          (int64_t)blockIdx.x * blockDim.x + threadIdx.x,
                          (int64_t)gridDim.x * blockDim.x);
+  if (j.tab2 != nullptr)
+    zweights_body<T, RMAX>((const T*)j.V2, j.R, j.weights2,
+                           (int64_t)blockIdx.x * blockDim.x + threadIdx.x,
+                           (int64_t)gridDim.x * blockDim.x);
 }
 
 // The contraction on the float64 matrix cores: a wavefront owns 16 nodes
@@ -692,46 +696,56 @@ __global__ __launch_bounds__(256) void zweights_batched_kernel(const ZtabJob* __
 // step of 4 packed entries lane l supplies A = P[p0 + l/16][16 t + l%16]
 // and B = G^(n0 + l%16)[p0 + l/16], and holds the result rows 4 i + l/16 of
 // column l%16.  Loads of KS steps are issued before their products.
-template <typename T, int RMAX>
+// NS weight sets P[0..NS) contracted with the same nodes (the tables of
+// two problems whose first drawn mode has the same tree share its reads).
+template <typename T, int RMAX, int NS>
 __device__ __forceinline__ void ztab_unit(const T* __restrict__ Z, int64_t nn, int R,
-                                          const double* __restrict__ P, double* __restrict__ tab,
+                                          const double* const* P, double* const* tab,
                                           int64_t n0, int lane) {
   constexpr int NTU = RMAX / 16;  // u tiles
-  constexpr int KS = 8;           // steps of 4 entries whose loads go together
+  constexpr int KS = NS == 1 ? 8 : 4;  // steps of 4 entries whose loads go together
   const int TR = R * (R + 1) / 2;
   const int r16 = lane & 15, k4 = lane >> 4;
   {
-    f64x4 acc[NTU];
+    f64x4 acc[NS][NTU];
 #pragma unroll
-    for (int t = 0; t < NTU; ++t) acc[t] = f64x4{0, 0, 0, 0};
+    for (int w = 0; w < NS; ++w)
+#pragma unroll
+      for (int t = 0; t < NTU; ++t) acc[w][t] = f64x4{0, 0, 0, 0};
     const int64_t n = n0 + r16;
     const T* __restrict__ zrow = Z + (n < nn ? n : nn - 1) * (int64_t)TR;
     for (int p0 = 0; p0 < TR; p0 += 4 * KS) {
-      double bv[KS], av[KS][NTU];
+      double bv[KS], av[NS][KS][NTU];
 #pragma unroll
       for (int ks = 0; ks < KS; ++ks) {
         const int p = p0 + 4 * ks + k4;
         const int pc = p < TR ? p : TR - 1;
         bv[ks] = (double)zrow[pc];
 #pragma unroll
-        for (int t = 0; t < NTU; ++t) av[ks][t] = P[(int64_t)pc * RMAX + 16 * t + r16];
+        for (int w = 0; w < NS; ++w)
+#pragma unroll
+          for (int t = 0; t < NTU; ++t) av[w][ks][t] = P[w][(int64_t)pc * RMAX + 16 * t + r16];
       }
 #pragma unroll
       for (int ks = 0; ks < KS; ++ks) {
         const bool ok = p0 + 4 * ks + k4 < TR && n < nn;
         const double b = ok ? bv[ks] : 0.0;
 #pragma unroll
-        for (int t = 0; t < NTU; ++t)
-          acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[ks][t], b, acc[t], 0, 0, 0);
+        for (int w = 0; w < NS; ++w)
+#pragma unroll
+          for (int t = 0; t < NTU; ++t)
+            acc[w][t] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[w][ks][t], b, acc[w][t], 0, 0, 0);
       }
     }
 #pragma unroll
-    for (int t = 0; t < NTU; ++t)
+    for (int w = 0; w < NS; ++w)
 #pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const int u = 16 * t + 4 * i + k4;
-        if (u < R && n < nn) tab[(int64_t)u * nn + n] = acc[t][i];
-      }
+      for (int t = 0; t < NTU; ++t)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const int u = 16 * t + 4 * i + k4;
+          if (u < R && n < nn) tab[w][(int64_t)u * nn + n] = acc[w][t][i];
+        }
   }
 }
 
@@ -741,8 +755,11 @@ __global__ __launch_bounds__(256) void ztab_kernel(const T* __restrict__ Z, int6
                                                    double* __restrict__ tab) {
   const int64_t nwave = (int64_t)gridDim.x * (blockDim.x >> 6);
   for (int64_t n0 = ((int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6)) * 16; n0 < nn;
-       n0 += nwave * 16)
-    ztab_unit<T, RMAX>(Z, nn, R, P, tab, n0, threadIdx.x & 63);
+       n0 += nwave * 16) {
+    const double* Ps[1] = {P};
+    double* tabs[1] = {tab};
+    ztab_unit<T, RMAX, 1>(Z, nn, R, Ps, tabs, n0, threadIdx.x & 63);
+  }
 }
 
 // Several problems' tables in one launch: wavefront w takes units w,
@@ -760,8 +777,19 @@ __global__ __launch_bounds__(256) void ztab_batched_kernel(const ZtabJob* __rest
       if (jobs[mid].unit0 <= un) lo = mid; else hi = mid;
     }
     const ZtabJob& j = jobs[lo];
-    ztab_unit<T, RMAX>((const T*)j.Z, j.nn, j.R, j.weights, j.tab, (un - j.unit0) * 16,
-                       threadIdx.x & 63);
+    if constexpr (RMAX <= 32) {
+      if (j.tab2 != nullptr) {
+        const double* Ps[2] = {j.weights, j.weights2};
+        double* tabs[2] = {j.tab, j.tab2};
+        ztab_unit<T, RMAX, 2>((const T*)j.Z, j.nn, j.R, Ps, tabs, (un - j.unit0) * 16,
+                              threadIdx.x & 63);
+        continue;
+      }
+    }
+    const double* Ps[1] = {j.weights};
+    double* tabs[1] = {j.tab};
+    ztab_unit<T, RMAX, 1>((const T*)j.Z, j.nn, j.R, Ps, tabs, (un - j.unit0) * 16,
+                          threadIdx.x & 63);
   }
 }
 

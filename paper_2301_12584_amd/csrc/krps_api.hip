@@ -1314,6 +1314,20 @@ krps_status krps_sample_batched_prepare(krps_ctx ctx, int P, const krps_sampler*
     zj.tab = (double*)(dw + sp->ztab_off);
     zj.nn = sp->shape[k0].n_nodes;
     zj.R = sp->R;
+    // a second problem over a tree another job already reads (the
+    // exclusions of one sampler whose first drawn mode is the same) rides
+    // on that job at R <= 32
+    bool paired = false;
+    if (zj.R <= 32)
+      for (ZtabJob& o : zt)
+        if (o.Z == zj.Z && o.tab2 == nullptr) {
+          o.V2 = zj.V;
+          o.weights2 = zj.weights;
+          o.tab2 = zj.tab;
+          paired = true;
+          break;
+        }
+    if (paired) continue;
     zt.push_back(zj);
     zprob.push_back(p);
   }

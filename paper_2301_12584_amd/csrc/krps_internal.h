@@ -267,12 +267,17 @@ hipError_t launch_ztab(hipStream_t st, krps_precision p, const void* Z, int64_t 
                        const void* V, double* weights, double* tab);
 // The same tables for several problems: one job per problem, all of one
 // storage type and R class (R <= 32, <= 64, <= 128); unit0 = the job's
-// first unit of 16 nodes in the batch's numbering, units = the total.
+// first unit of 16 nodes in the batch's numbering, units = the total.  At
+// R <= 32 a job may carry a second problem over the same tree (V2,
+// weights2, tab2; else null), whose table is formed from the same reads.
 struct ZtabJob {
   const void* Z;
   const void* V;
   double* weights;
   double* tab;
+  const void* V2;
+  double* weights2;
+  double* tab2;
   int64_t nn, unit0;
   int R, pad;
 };
