@@ -491,9 +491,11 @@ krps_status krps_autotune_workspace_bytes(int N, const int64_t* I, int R, krps_p
 /* Times a rebuild of the N trees plus a draw of J samples (no exclusion,
  * uniforms device float64 [J][N][2]) over the caller's factors U for leaf
  * sizes F in {R/2, R, 2R, 4R}, every lanes-per-sample choice of R and
- * every tree-build team width of R and p, and returns the fastest.  Results are keyed by (gfx950, precision, R, J, I_1..I_N)
- * in the JSON-lines file cache_path (NULL: no cache): a key present there
- * is returned without timing; a new result is appended.  The leaf size
+ * every tree-build team width of R and p, and returns the fastest.
+ * Results are keyed by (gfx950, precision, R, J, I_1..I_N) in the
+ * JSON-lines file cache_path (NULL: no cache): a key present there is
+ * returned without timing (the last entry whose shapes the library offers
+ * for R and p; others are skipped); a new result is appended.  The leaf size
  * does not change any drawn index (ties go to the lower row, so the index
  * depends only on the row order).  Synchronises the stream. */
 krps_status krps_autotune(krps_ctx ctx, int N, const int64_t* I, int R, krps_precision p,

@@ -1842,8 +1842,11 @@ std::string tune_key(int N, const int64_t* I, int R, krps_precision p, int64_t J
 }
 
 // One line per entry: {"key": "...", "F": f, "lps": l, "team": w, "build_ms": b,
-// "draw_ms": d} (entries without "team" used the default team)
-bool tune_lookup(const char* path, const std::string& key, krps_tune* out) {
+// "draw_ms": d} (entries without "team" used the default team).  Entries
+// whose shapes this library does not offer for R and p (a cache written
+// by another version) are skipped.
+bool tune_lookup(const char* path, const std::string& key, int R, krps_precision p,
+                 krps_tune* out) {
   if (path == nullptr) return false;
   FILE* f = fopen(path, "r");
   if (f == nullptr) return false;
@@ -1859,9 +1862,14 @@ bool tune_lookup(const char* path, const std::string& key, krps_tune* out) {
     const char* b = strstr(line, "\"build_ms\": ");
     const char* d = strstr(line, "\"draw_ms\": ");
     if (q && l && b && d) {
-      out->F = atoi(q + 5);
-      out->lps = atoi(l + 7);
-      out->team = tw ? atoi(tw + 8) : 0;
+      const int F = atoi(q + 5), lps = atoi(l + 7), team = tw ? atoi(tw + 8) : 0;
+      const std::vector<int> teams = build_team_choices(R, p);
+      const bool ok = F >= 1 && lps_supported(R, lps) &&
+                      (team == 0 || std::find(teams.begin(), teams.end(), team) != teams.end());
+      if (!ok) continue;
+      out->F = F;
+      out->lps = lps;
+      out->team = team;
       out->build_ms = atof(b + 12);
       out->draw_ms = atof(d + 11);
       out->from_cache = 1;
@@ -1909,7 +1917,7 @@ krps_status krps_autotune(krps_ctx ctx, int N, const int64_t* I, int R, krps_pre
     return fail(KRPS_EINVAL, "J/uniforms/U/workspace invalid");
   const std::string key = tune_key(N, I, R, p, J);
   memset(out, 0, sizeof(*out));
-  if (tune_lookup(cache_path, key, out)) return KRPS_OK;
+  if (tune_lookup(cache_path, key, R, p, out)) return KRPS_OK;
   const TunePlan pl = plan_tune(N, I, R, p, J);
   if (ws_bytes < pl.total) return fail(KRPS_EWORKSPACE, "autotune workspace too small");
   char* w = (char*)ws;

@@ -296,6 +296,17 @@ def test_autotune_measures_then_reads_the_cache(tmp_path):
     t2 = krps.autotune(ctx, Ud, u, "fp32", cache_path=cache)
     assert t2["from_cache"]
     assert (t2["F"], t2["lps"], t2["team"]) == (t1["F"], t1["lps"], t1["team"])
+    # a later entry of the same key with shapes the library does not offer
+    # at R = 16 (written by another version) is skipped
+    line = cache.read_text().splitlines()[-1]
+    stale = line.replace(f'"lps": {t1["lps"]}', '"lps": 64').replace(f'"team": {t1["team"]}',
+                                                                      '"team": 8')
+    assert stale != line
+    with open(cache, "a") as f:
+        f.write(stale + "\n")
+    t3 = krps.autotune(ctx, Ud, u, "fp32", cache_path=cache)
+    assert t3["from_cache"]
+    assert (t3["F"], t3["lps"], t3["team"]) == (t1["F"], t1["lps"], t1["team"])
     # the tuned shape's draws against the float64 oracle
     S1 = krps.Sampler(ctx, Ud, precision="fp32", F=t1["F"], lps=t1["lps"], team=t1["team"])
     for j in range(3):
