@@ -56,6 +56,48 @@ constexpr int jacobi_team(int R) { return R <= 32 ? 4 : 16; }
 // schedule in parallel, one team of TEAM lanes per pair; a lane keeps its
 // <= RPL rows of both columns in registers between the dot products and
 // the rotation.  `flag` is an int in LDS.  Returns the number of sweeps.
+// One rotation of columns p and q (team lane li holds rows li + TEAM i):
+// their dot products over the team, then the rotation that makes them
+// orthogonal, unless they already are within tol.  Sets *flag on a
+// rotation.
+template <int TEAM, int RPL>
+__device__ __forceinline__ void jacobi_rotate(double* A, int R, int RS, int p, int q, bool act,
+                                              int li, double tol, int* flag) {
+  double x[RPL], y[RPL];
+  double al = 0, be = 0, ga = 0;
+#pragma unroll
+  for (int i = 0; i < RPL; ++i) {
+    const int r = li + TEAM * i;
+    const bool ok = act && r < R;
+    x[i] = ok ? A[p * RS + r] : 0.0;
+    y[i] = ok ? A[q * RS + r] : 0.0;
+    al += x[i] * x[i];
+    be += y[i] * y[i];
+    ga += x[i] * y[i];
+  }
+  al = team_sum<TEAM>(al);
+  be = team_sum<TEAM>(be);
+  ga = team_sum<TEAM>(ga);
+  if (act && al > 0 && be > 0 && ga * ga > (tol * tol) * (al * be)) {
+    // tangent of the rotation angle, the root of t^2 + 2 zeta t - 1 = 0
+    // of smaller magnitude (zeta = (be - al) / (2 ga))
+    const double dd = be - al, g2 = 2.0 * ga;
+    const double rr = sqrt(dd * dd + g2 * g2);
+    const double t = g2 / (dd + (dd >= 0 ? rr : -rr));
+    const double c = rsqrt(1.0 + t * t);
+    const double sn = c * t;
+#pragma unroll
+    for (int i = 0; i < RPL; ++i) {
+      const int r = li + TEAM * i;
+      if (r < R) {
+        A[p * RS + r] = c * x[i] - sn * y[i];
+        A[q * RS + r] = sn * x[i] + c * y[i];
+      }
+    }
+    if (li == 0) *flag = 1;
+  }
+}
+
 template <int TEAM, int RPL>
 __device__ int jacobi_columns_t(double* A, int R, int* flag) {
   const int RS = R + 1;
@@ -69,6 +111,34 @@ __device__ int jacobi_columns_t(double* A, int R, int* flag) {
   // tol would only spin until the sweep cap
   const double tol = 1e-13;
   int sweep = 0;
+  if (npairs * TEAM <= 64) {
+    // every pair in wavefront 0: it runs the sweeps with wavefront-level
+    // LDS ordering between the steps, the other wavefronts wait once
+    if (tid < 64) {
+      for (; sweep < 24; ++sweep) {
+        if (tid == 0) *flag = 0;
+        wave_lds_sync();
+        int cp = s == 0 ? 0 : (s - 1) % (n - 1);
+        int cq = (n - 2 - s) % (n - 1);
+        for (int step = 0; step < n - 1; ++step) {
+          int p = 0, q = 0;
+          bool act = s < npairs;
+          if (act) {
+            p = (s == 0) ? 0 : 1 + cp;
+            q = 1 + cq;
+            act = p < R && q < R;
+          }
+          cp = cp + 1 == n - 1 ? 0 : cp + 1;
+          cq = cq + 1 == n - 1 ? 0 : cq + 1;
+          jacobi_rotate<TEAM, RPL>(A, R, RS, p, q, act, li, tol, flag);
+          wave_lds_sync();
+        }
+        if (*flag == 0) break;
+      }
+    }
+    __syncthreads();
+    return sweep + 1;
+  }
   for (; sweep < 24; ++sweep) {
     __syncthreads();
     if (tid == 0) *flag = 0;
@@ -93,39 +163,7 @@ __device__ int jacobi_columns_t(double* A, int R, int* flag) {
       }
       cp = cp + 1 == n - 1 ? 0 : cp + 1;
       cq = cq + 1 == n - 1 ? 0 : cq + 1;
-      double x[RPL], y[RPL];
-      double al = 0, be = 0, ga = 0;
-#pragma unroll
-      for (int i = 0; i < RPL; ++i) {
-        const int r = li + TEAM * i;
-        const bool ok = act && r < R;
-        x[i] = ok ? A[p * RS + r] : 0.0;
-        y[i] = ok ? A[q * RS + r] : 0.0;
-        al += x[i] * x[i];
-        be += y[i] * y[i];
-        ga += x[i] * y[i];
-      }
-      al = team_sum<TEAM>(al);
-      be = team_sum<TEAM>(be);
-      ga = team_sum<TEAM>(ga);
-      if (act && al > 0 && be > 0 && ga * ga > (tol * tol) * (al * be)) {
-        // tangent of the rotation angle, the root of t^2 + 2 zeta t - 1 = 0
-        // of smaller magnitude (zeta = (be - al) / (2 ga))
-        const double dd = be - al, g2 = 2.0 * ga;
-        const double rr = sqrt(dd * dd + g2 * g2);
-        const double t = g2 / (dd + (dd >= 0 ? rr : -rr));
-        const double c = rsqrt(1.0 + t * t);
-        const double sn = c * t;
-#pragma unroll
-        for (int i = 0; i < RPL; ++i) {
-          const int r = li + TEAM * i;
-          if (r < R) {
-            A[p * RS + r] = c * x[i] - sn * y[i];
-            A[q * RS + r] = sn * x[i] + c * y[i];
-          }
-        }
-        if (li == 0) *flag = 1;
-      }
+      jacobi_rotate<TEAM, RPL>(A, R, RS, p, q, act, li, tol, flag);
       __syncthreads();
     }
     if (*flag == 0) break;
@@ -133,7 +171,6 @@ __device__ int jacobi_columns_t(double* A, int R, int* flag) {
   __syncthreads();
   return sweep + 1;
 }
-
 __device__ int jacobi_columns(double* A, int R, int* flag) {
   // rows per lane: just enough for the largest R of each branch
   if (R <= 32) return jacobi_columns_t<jacobi_team(32), 32 / jacobi_team(32)>(A, R, flag);
